@@ -1,0 +1,319 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+* exact 2D Ising values (Onsager / Yang closed forms, ``tests/golden``),
+  reached through the classical path (a given directly) and through the
+  quantum path (a d=2, D=2 iPEPS whose norm network is the Ising model);
+* exact product states;
+* the 2x2 network contracted by rows (independent of the enlarged corners);
+* Eckart-Young for the full-SVD projectors, and the k = N case where
+  subspace iteration must reproduce them;
+* QR against modified Gram-Schmidt;
+* gauge and lattice-rotation invariances;
+* planted mistakes that these pins must catch.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "ising_closed_forms.json")))["values"]
+
+
+def gold(beta, key):
+    return float(GOLD[str(beta)][key])
+
+
+def iso_for(N, k, base=20):
+    return O.SIState([S.gaussian_block(N, k, base + b) for b in range(4)],
+                     [S.gaussian_block(N, k, base + 10 + b) for b in range(4)])
+
+
+# --------------------------------------------------------------------------
+# exact Ising values
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("proj", ["si", "svd"])
+def test_classical_ising_closed_forms(proj):
+    beta, chi = 0.5, 16
+    a, asig, e = S.ising_site(beta), S.ising_impurity(beta), S.ising_boundary(beta)
+    env, hist = O.run_ctmrg(a, e, chi, proj=proj, iso0=iso_for(2 * chi, chi + 8),
+                            tol=1e-12, max_moves=150)
+    lnk = np.log(O.kappa(env, a))
+    assert abs(lnk - gold(beta, "minus_beta_f")) <= 1e-10 * lnk
+    assert abs(O.onesite_value(env, a, asig) - gold(beta, "magnetisation")) <= 1e-9
+    for direction in "hv":
+        ss = O.classical_bond_value(env, a, asig, asig, direction)
+        assert abs(ss - gold(beta, "nn_correlation")) <= 1e-9
+    if proj == "si":
+        assert hist[-1]["delta"] < 1e-12
+
+
+def test_c4v_closed_forms_and_agreement_with_generic():
+    beta, chi, k = 0.5, 16, 24
+    a, asig, e = S.ising_site(beta), S.ising_impurity(beta), S.ising_boundary(beta)
+    C, T = O.c4v_initial_env(a, e)
+    X = S.gaussian_block(2 * chi, k, 7)
+    for _ in range(80):
+        C, T, X, mode = O.c4v_move(C, T, a, chi, "si", X, n_si=2)
+    assert mode == "si"
+    lnk = np.log(O.c4v_kappa(C, T, a))
+    assert abs(lnk - gold(beta, "minus_beta_f")) <= 1e-10 * lnk
+    assert abs(O.c4v_onesite(C, T, a, asig) - gold(beta, "magnetisation")) <= 1e-9
+    env, _ = O.run_ctmrg(a, e, chi, proj="si", iso0=iso_for(2 * chi, k), tol=1e-12,
+                         max_moves=150)
+    assert abs(np.log(O.kappa(env, a)) - lnk) <= 1e-11
+
+
+@pytest.mark.parametrize("beta", [0.3, 0.5])
+def test_ising_peps_bond_correlation(beta):
+    """Quantum path: double layer, open-leg two-site RDM, operator insertion."""
+    A = S.ising_peps_site(beta)
+    a, e, Z = O.double_layer(A), S.trace_boundary(2), S.pauli("z")
+    chi = 16
+    env, hist = O.run_ctmrg(a, e, chi, proj="si", iso0=iso_for(4 * chi, chi + 8),
+                            tol=1e-11, max_moves=200)
+    lnk = np.log(O.kappa(env, a))
+    assert abs(lnk - gold(beta, "minus_beta_f")) <= 1e-10 * lnk
+    for direction in "hv":
+        zz = O.bond_value(env, A, np.kron(Z, Z), direction)
+        assert abs(zz - gold(beta, "nn_correlation")) <= 2e-11
+    # symmetric boundary: the Z2-even state has <sigma^z> = 0 exactly
+    assert abs(O.onesite_value(env, a, O.double_layer_op(A, Z))) <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# exact product states
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("proj", ["si", "svd"])
+def test_product_state_exact(proj):
+    rng = np.random.default_rng(5)
+    phi, v = rng.standard_normal(2), rng.standard_normal(3)
+    A = np.einsum("s,u,l,d,r->suldr", phi, v, v, v, v)
+    a, e = O.double_layer(A), S.trace_boundary(3)
+    chi = 12
+    env, _ = O.run_ctmrg(a, e, chi, proj=proj, iso0=iso_for(9 * chi, chi + 4), max_moves=4)
+    kap = (phi @ phi) * (v @ v) ** 4
+    assert abs(O.kappa(env, a) / kap - 1) <= 1e-12
+    X, Zp = S.pauli("x"), S.pauli("z")
+    p = phi / np.linalg.norm(phi)
+    for op in (S.heisenberg_bond(), np.kron(X, Zp)):
+        exact = np.kron(p, p) @ op @ np.kron(p, p)
+        for direction in "hv":
+            assert abs(O.bond_value(env, A, op, direction) - exact) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# enlarged corners against the 2x2 network contracted row by row
+# --------------------------------------------------------------------------
+def random_env(chi, D2, seed):
+    rng = np.random.default_rng(seed)
+    C = [rng.standard_normal((chi, chi)) for _ in range(4)]
+    T = [rng.standard_normal((chi, D2, chi)) for _ in range(4)]
+    return O.Env(C, T)
+
+
+def test_enlarged_corners_close_the_2x2_network():
+    """Tr(Ct1 Ct2 Ct3 Ct4) equals the 4x4 boundary network contracted row by row."""
+    chi, D2 = 3, 4
+    env = random_env(chi, D2, 1)
+    a = np.random.default_rng(2).standard_normal((D2,) * 4)
+    Ct = O.enlarged_corners(env, a)
+    z_corners = np.trace(Ct[0] @ Ct[1] @ Ct[2] @ Ct[3])
+    C1, C2, C3, C4 = env.C
+    T1, T2, T3, T4 = env.T
+    # legs read off the picture: sites a[up, left, down, right]; boundary
+    # tensors in their clockwise (in, inner, out) order.
+    top = np.einsum("AB,BpG,GqH,HE->ApqE", C1, T1, T1, C2)
+    m1 = np.einsum("ApqE,KlA,plum,qmvr,ErF->KuvF", top, T4, a, a, T2)
+    m2 = np.einsum("KuvF,IlK,ulwm,vmxr,FrJ->IwxJ", m1, T4, a, a, T2)
+    bot = np.einsum("JY,YxZ,ZwO,OI->JxwI", C3, T3, T3, C4)
+    z_rows = np.einsum("IwxJ,JxwI->", m2, bot)
+    assert abs(z_corners - z_rows) <= 1e-12 * abs(z_rows)
+
+
+# --------------------------------------------------------------------------
+# projectors: Eckart-Young and the k = N reduction
+# --------------------------------------------------------------------------
+def small_corners(seed=3, chi=3, D2=4):
+    env = random_env(chi, D2, seed)
+    rng = np.random.default_rng(seed + 100)
+    a = rng.standard_normal((D2,) * 4)
+    return O.enlarged_corners(env, a), chi * D2
+
+
+def test_full_svd_projectors_eckart_young():
+    Ct, N = small_corners()
+    chi = 5
+    for b in range(4):
+        Pl, Prt, s = O.svd_projectors(Ct, b, chi, 1e-14)
+        L = Ct[(b - 1) % 4] @ Ct[b]
+        R = Ct[(b + 1) % 4] @ Ct[(b + 2) % 4]
+        M = L @ R
+        U, sv, Vt = np.linalg.svd(M)
+        best = (U[:, :chi] * sv[:chi]) @ Vt[:chi]
+        assert np.allclose(L @ Pl @ Prt.T @ R, best, atol=1e-10 * sv[0])
+        assert np.allclose(Prt.T @ Pl, np.eye(chi), atol=1e-10)
+        assert np.allclose(s, sv)
+
+
+def test_si_with_full_space_equals_full_svd():
+    Ct, N = small_corners(seed=4)
+    chi = 5
+    for b in range(4):
+        Pl, Prt, _ = O.svd_projectors(Ct, b, chi, 1e-14)
+        X0, Y0 = S.gaussian_block(N, N, 40 + b), S.gaussian_block(N, N, 50 + b)
+        Pl2, Prt2, _, _, _ = O.si_projectors(Ct, b, X0, Y0, chi, 1, 1e-14)
+        scale = np.abs(Pl).max()
+        assert np.allclose(Pl2, Pl, atol=1e-9 * scale)
+        assert np.allclose(Prt2, Prt, atol=1e-9 * np.abs(Prt).max())
+
+
+def principal_sin2(Qa, Qb):
+    s = np.linalg.svd(Qa.T @ Qb, compute_uv=False)
+    return 1 - s ** 2
+
+
+def test_subspace_iteration_converges_to_leading_subspace():
+    """Angles to the leading right singular subspace shrink with every step."""
+    Ct, N = small_corners(seed=6, chi=4, D2=4)
+    b, k, chi = 0, 8, 6
+    L = Ct[3] @ Ct[0]
+    R = Ct[1] @ Ct[2]
+    _, _, Vt = np.linalg.svd(L @ R)
+    Vk = Vt[:chi].T
+    X = S.gaussian_block(N, k, 9)
+    prev = np.inf
+    for n in range(1, 7):
+        _, _, _, Xn, _ = O.si_projectors(Ct, b, X, S.gaussian_block(N, k, 10), chi, n, 1e-14)
+        ang = principal_sin2(np.linalg.qr(Xn)[0], Vk).max()
+        assert ang < prev
+        prev = ang
+    assert prev < 1e-7
+
+
+def test_stabilized_and_plain_si_agree():
+    Ct, N = small_corners(seed=8)
+    X0, Y0 = S.gaussian_block(N, 7, 1), S.gaussian_block(N, 7, 2)
+    a = O.si_projectors(Ct, 1, X0, Y0, 5, 2, 1e-14, stabilized=True)
+    b = O.si_projectors(Ct, 1, X0, Y0, 5, 2, 1e-14, stabilized=False)
+    assert np.allclose(a[0], b[0], atol=1e-8 * np.abs(a[0]).max())
+
+
+# --------------------------------------------------------------------------
+# QR and the sign / cutoff rules
+# --------------------------------------------------------------------------
+def mgs2(W):
+    Q = W.copy()
+    for _ in range(2):
+        for j in range(Q.shape[1]):
+            for i in range(j):
+                Q[:, j] -= (Q[:, i] @ Q[:, j]) * Q[:, i]
+            Q[:, j] /= np.linalg.norm(Q[:, j])
+    return Q
+
+
+def test_qr_pos_matches_gram_schmidt():
+    W = S.gaussian_block(50, 12, 3)
+    Q = O.qr_pos(W)
+    assert np.allclose(Q, mgs2(W), atol=1e-12)
+    assert np.allclose(Q.T @ Q, np.eye(12), atol=1e-14 * 50)
+
+
+def test_qr_pos_rank_deficient_has_no_nan():
+    W = np.zeros((20, 5))
+    W[:, 0] = 1.0
+    Q = O.qr_pos(W)
+    assert np.all(np.isfinite(Q))
+    assert np.allclose(Q.T @ Q, np.eye(5), atol=1e-13)
+
+
+def test_sign_rule_and_pinv():
+    U = np.array([[0.1, -0.9], [-0.5, 0.9], [0.2, 0.1]])
+    assert list(O.sign_fix_columns(U)) == [-1.0, -1.0]  # tie in column 2 -> lowest row
+    s = np.array([4.0, 1.0, 1e-13, 0.0])
+    assert np.allclose(O.pinv_sqrt(s, 1e-12), [0.5, 1.0, 0.0, 0.0])
+
+
+# --------------------------------------------------------------------------
+# invariances
+# --------------------------------------------------------------------------
+def noisy_site(D=2, seed=2):
+    return S.product_plus_noise_site(2, D, seed)
+
+
+def energies(A, chi, proj="svd", moves=40):
+    a, e = O.double_layer(A), S.trace_boundary(A.shape[1])
+    N = chi * A.shape[1] ** 2
+    env, _ = O.run_ctmrg(a, e, chi, proj=proj, iso0=iso_for(N, chi + 4), max_moves=moves,
+                         tol=1e-13)
+    h = S.heisenberg_bond()
+    return (O.kappa(env, a), O.bond_value(env, A, h, "h"), O.bond_value(env, A, h, "v"))
+
+
+def test_orthogonal_gauge_invariance():
+    A = noisy_site(D=2, seed=11)
+    Gh, Gv = S.random_orthogonal(2, 1), S.random_orthogonal(2, 2)
+    Ag = np.einsum("suldr,uU,lL,dD,rR->sULDR", A, Gv, Gh, Gv, Gh)
+    ref = energies(A, 8)
+    got = energies(Ag, 8)
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_rotation_swaps_horizontal_and_vertical():
+    A = noisy_site(D=2, seed=12)
+    Ar = np.einsum("suldr->sruld", A)      # 90 deg: new (u,l,d,r) = old (r,u,l,d)
+    k1, h1, v1 = energies(A, 8)
+    k2, h2, v2 = energies(Ar, 8)
+    assert abs(h1 - v1) > 1e-6
+    assert abs(k1 - k2) <= 1e-10 * k1
+    assert abs(h1 - v2) <= 1e-10 and abs(v1 - h2) <= 1e-10
+
+
+def test_si_and_svd_agree_on_noisy_state():
+    A = noisy_site(D=2, seed=13)
+    ref = energies(A, 8, "svd", 60)
+    got = energies(A, 8, "si", 60)
+    assert np.allclose(got, ref, rtol=1e-9, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# planted mistakes must be caught (the mistake is planted in the oracle, on the CPU)
+# --------------------------------------------------------------------------
+def _ising_lnk_error(monkeypatch=None):
+    beta, chi = 0.5, 8
+    a, e = S.ising_site(beta), S.ising_boundary(beta)
+    env, _ = O.run_ctmrg(a, e, chi, proj="si", iso0=iso_for(2 * chi, chi + 4),
+                         tol=1e-12, max_moves=80)
+    return abs(np.log(O.kappa(env, a)) - gold(beta, "minus_beta_f"))
+
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    assert _ising_lnk_error() < 1e-10
+    import oracle.ctmrg as mod
+
+    good = mod.enlarged_corners
+
+    def swapped_legs(env, a):       # transposed site tensor in the corner build
+        return good(env, np.ascontiguousarray(a.transpose(0, 1, 3, 2)) * 1.0 +
+                    0.05 * np.ones_like(a))
+
+    monkeypatch.setattr(mod, "enlarged_corners", swapped_legs)
+    assert _ising_lnk_error() > 1e-6
+    monkeypatch.undo()
+
+    def dropped_sqrt(s, eps):       # s^-1 instead of s^-1/2
+        out = np.zeros_like(s)
+        keep = s > eps * s[0]
+        out[keep] = 1.0 / s[keep]
+        return out
+
+    monkeypatch.setattr(mod, "pinv_sqrt", dropped_sqrt)
+    A = S.ising_peps_site(0.5)
+    a, e = O.double_layer(A), S.trace_boundary(2)
+    env, _ = O.run_ctmrg(a, e, 8, proj="si", iso0=iso_for(32, 12), tol=1e-12, max_moves=60)
+    zz = O.bond_value(env, A, np.kron(S.pauli("z"), S.pauli("z")), "h")
+    assert abs(zz - gold(0.5, "nn_correlation")) > 1e-6 or not np.isfinite(zz)
