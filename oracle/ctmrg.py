@@ -33,9 +33,10 @@ reason in the design notes of the repository):
   to the squared condition number).
 * QR convention: ``R_ii >= 0``.
 * Sign rule (replaces the cited Bro-Acar-Kolda fix by a deterministic one):
-  for every singular triple, the entry of largest magnitude of the
-  N-dimensional left vector (column ``i`` of ``U``, or of ``Y^T u``) is made
-  positive; ties go to the lowest index.
+  for every singular triple, the dominant entry of the N-dimensional left
+  vector (column ``i`` of ``U``, or of ``Y^T u``) is made positive; the
+  dominant entry is the lowest-index one within a relative 1e-8 of the
+  largest magnitude (roundoff-level ties are resolved by index).
 * Pseudo-inverse: ``s_i <= eps * s_1`` gives ``s_i^-1/2 := 0``.
 * Normalisation: every new ``C`` and ``T`` is scaled to unit Frobenius norm.
 * Growth phase: while the environment dimension is below ``chi`` the move
@@ -195,9 +196,22 @@ def qr_pos(W: np.ndarray) -> np.ndarray:
     return q * sg
 
 
+SIGN_TIE_RTOL = 1e-8
+
+
 def sign_fix_columns(U: np.ndarray) -> np.ndarray:
-    """Signs that make the largest-|.| entry of every column positive (ties -> lowest row)."""
-    idx = np.argmax(np.abs(U), axis=0)
+    """Signs that make the dominant entry of every column positive.
+
+    The dominant entry is the lowest-index entry whose magnitude is within a
+    relative ``SIGN_TIE_RTOL`` of the column's largest magnitude, so that
+    entries equal up to roundoff (frequent: the double layer is symmetric
+    under exchanging ket and bra, which pairs entries of equal magnitude) are
+    resolved by index and not by rounding.
+    """
+    A = np.abs(U)
+    mx = A.max(axis=0)
+    near = A >= (1.0 - SIGN_TIE_RTOL) * mx
+    idx = np.argmax(near, axis=0)          # first True
     sg = np.sign(U[idx, np.arange(U.shape[1])])
     sg[sg == 0] = 1.0
     return sg
@@ -292,11 +306,41 @@ def si_projectors(Ct, b: int, X: np.ndarray, Yt: np.ndarray, chi: int, n_si: int
 # --------------------------------------------------------------------------
 # a6: renormalisation (Fig. 1)
 # --------------------------------------------------------------------------
-def renormalize(Ct, Tt, Pl, Prt) -> Env:
-    """``C_i' = P_r^{b(i-1)} Ct_i P_l^{b(i)}``; ``T_j' = P_r^{b(j)} Tt_j P_l^{b(j)}``."""
+def renormalize(Ct, env: Env, a: np.ndarray, Pl, Prt) -> Env:
+    """``C_i' = P_r^{b(i-1)} Ct_i P_l^{b(i)}``; ``T_j' = P_r^{b(j)} Tt_j P_l^{b(j)}``.
+
+    The enlarged edge ``Tt_j`` (see :func:`enlarged_edges`) is contracted in
+    the same expression instead of being formed, which keeps memory at
+    ``O(N^2)``; the result is the same sum.
+    """
+    x, D2 = env.chi, a.shape[0]
+    T1, T2, T3, T4 = env.T
+    C = [Prt[(i - 1) % 4].T @ Ct[i] @ Pl[i] for i in range(4)]
+    r = lambda P: P.reshape(x, D2, P.shape[1])   # noqa: E731  (chi, D^2, chi')
+    # edge j: contract the out pair with P_l, then the site, then P_r
+    z = np.einsum("bug,gry->buyr", T1, r(Pl[0]))
+    z = np.einsum("buyr,uldr->blyd", z, a)
+    T = [np.einsum("blx,blyd->xdy", r(Prt[0]), z)]
+    z = np.einsum("hre,edy->hyrd", T2, r(Pl[1]))
+    z = np.einsum("hyrd,uldr->huyl", z, a)
+    T.append(np.einsum("hux,huyl->xly", r(Prt[1]), z))
+    z = np.einsum("zdn,nly->zydl", T3, r(Pl[2]))
+    z = np.einsum("zydl,uldr->zryu", z, a)
+    T.append(np.einsum("zrx,zryu->xuy", r(Prt[2]), z))
+    z = np.einsum("tla,auy->tylu", T4, r(Pl[3]))
+    z = np.einsum("tylu,uldr->tdyr", z, a)
+    T.append(np.einsum("tdx,tdyr->xry", r(Prt[3]), z))
+    return normalize_env(Env(C, T))
+
+
+def renormalize_via_edges(Ct, Tt, Pl, Prt) -> Env:
+    """Same as :func:`renormalize`, with the enlarged edges formed explicitly."""
     C = [Prt[(i - 1) % 4].T @ Ct[i] @ Pl[i] for i in range(4)]
     T = [np.einsum("Xx,XmY,Yy->xmy", Prt[j], Tt[j], Pl[j], **_EIN) for j in range(4)]
     return normalize_env(Env(C, T))
+
+
+__all__.append("renormalize_via_edges")
 
 
 def corner_spectra(env: Env, chi: int) -> np.ndarray:
@@ -330,7 +374,6 @@ def ctm_move(env: Env, a: np.ndarray, chi: int, proj: str = "si",
     x, D2 = env.chi, a.shape[0]
     N = x * D2
     Ct = enlarged_corners(env, a)
-    Tt = enlarged_edges(env, a)
     info = {"svals": []}
     if N <= chi:
         Pl = [np.eye(N)] * 4
@@ -359,7 +402,7 @@ def ctm_move(env: Env, a: np.ndarray, chi: int, proj: str = "si",
         si = SIState(Xn, Ytn)
         info["mode"] = "si"
     info["si"] = si
-    return renormalize(Ct, Tt, Pl, Prt), info
+    return renormalize(Ct, env, a, Pl, Prt), info
 
 
 def run_ctmrg(a: np.ndarray, e: np.ndarray, chi: int, proj: str = "si", k: Optional[int] = None,

@@ -145,6 +145,22 @@ def small_corners(seed=3, chi=3, D2=4):
     return O.enlarged_corners(env, a), chi * D2
 
 
+def test_renormalize_direct_equals_via_enlarged_edges():
+    env = random_env(3, 4, 21)
+    a = np.random.default_rng(22).standard_normal((4,) * 4)
+    Ct = O.enlarged_corners(env, a)
+    Pl, Prt = [], []
+    for b in range(4):
+        pl, prt, _ = O.svd_projectors(Ct, b, 5, 1e-14)
+        Pl.append(pl)
+        Prt.append(prt)
+    e1 = O.renormalize(Ct, env, a, Pl, Prt)
+    e2 = O.renormalize_via_edges(Ct, O.enlarged_edges(env, a), Pl, Prt)
+    for i in range(4):
+        assert np.allclose(e1.C[i], e2.C[i], atol=1e-14)
+        assert np.allclose(e1.T[i], e2.T[i], atol=1e-14)
+
+
 def test_full_svd_projectors_eckart_young():
     Ct, N = small_corners()
     chi = 5
@@ -234,6 +250,11 @@ def test_qr_pos_rank_deficient_has_no_nan():
 def test_sign_rule_and_pinv():
     U = np.array([[0.1, -0.9], [-0.5, 0.9], [0.2, 0.1]])
     assert list(O.sign_fix_columns(U)) == [-1.0, -1.0]  # tie in column 2 -> lowest row
+    # a tie up to roundoff is still a tie: the lowest row decides
+    V = np.array([[0.9], [-(0.9 + 1e-13)], [0.1]])
+    assert list(O.sign_fix_columns(V)) == [1.0]
+    W = np.array([[0.5], [-0.9], [0.1]])
+    assert list(O.sign_fix_columns(W)) == [-1.0]
     s = np.array([4.0, 1.0, 1e-13, 0.0])
     assert np.allclose(O.pinv_sqrt(s, 1e-12), [0.5, 1.0, 0.0, 0.0])
 
