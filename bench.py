@@ -1,0 +1,191 @@
+"""Benchmark of one SI-CTMRG move on one MI355X (prints one JSON line).
+
+Workload (the D=6, chi=144 precision configuration): single-site real iPEPS,
+d=2, D=6 (double-layer bond 36), chi=144, p=16 (k=160), n_si=2 stabilised
+subspace steps per move, enlarged corners of 5184 x 5184.  Site tensor:
+product state (1,0) on every leg plus 0.1 * iid U[-1,1] noise (seed 3); start
+blocks iid N(0,1) (seeds 40+b and 50+b).  A "step" is one full four-direction
+SI move (enlarged corners, subspace iteration with Householder QRs, rho and
+its SVD, projectors, renormalisation, normalisation and the convergence
+measure), timed with inputs resident in HBM.
+
+Also reported, in the same JSON line:
+  * roofline of the dominant kernel (the enlarged-corner applications of the
+    subspace iteration) from HIP events recorded around every launch of it on
+    the library's stream during the timed region;
+  * the full-SVD CTMRG move on the same GPU (rocSOLVER dgesvd of the four
+    5184 x 5184 M_b), timed over --svd-moves moves;
+  * the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}    # dense MFMA TFLOP/s, MI355X
+HBM_PEAK = 8000.0                                      # GB/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(D=6, chi=144, p=16, seed=3):
+    import synth as S
+    A = S.product_plus_noise_site(2, D, seed)
+    N, k = chi * D * D, min(chi + p, chi * D * D)
+    X = np.stack([S.gaussian_block(N, k, 40 + b) for b in range(4)])
+    Y = np.stack([S.gaussian_block(N, k, 50 + b) for b in range(4)])
+    return A, X, Y
+
+
+def cpu_baseline(args, A, X, Y, state=None):
+    """Times the FP64 oracle on one SI move of the same workload (bounded sample)."""
+    import oracle as O
+    import synth as S
+    threads = len(os.sched_getaffinity(0))
+    chi, D = args.chi, args.D
+    a = O.double_layer(A)
+    env = O.initial_env(a, S.trace_boundary(D))
+    t0 = time.perf_counter()
+    if state is not None:
+        env = state
+    else:
+        env, _ = O.ctm_move(env, a, chi, "si", None, eps=args.pinv_rtol)    # growth move
+    si = O.SIState(list(X), list(Y))
+    t1 = time.perf_counter()
+    env, _ = O.ctm_move(env, a, chi, "si", si, n_si=args.n_si, eps=args.pinv_rtol)
+    t2 = time.perf_counter()
+    return {"value": 1.0 / (t2 - t1), "unit": "moves/s", "cores": threads, "kind": "oracle",
+            "sample": f"one SI move (n_si={args.n_si}) of the same D={D}, chi={chi} workload, "
+                      f"numpy/OpenBLAS float64, {t2 - t1:.1f} s (+{t1 - t0:.1f} s growth move untimed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--D", type=int, default=6)
+    ap.add_argument("--chi", type=int, default=144)
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--n-si", type=int, default=2)
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--pinv-rtol", type=float, default=1e-12)
+    ap.add_argument("--svd-moves", type=int, default=1, help="full-SVD comparator moves (0: skip)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2607_15158_amd as P
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    A, X, Y = workload(args.D, args.chi, args.p)
+    cfg = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="si",
+                   prec=args.prec, stabilized=1, pinv_rtol=args.pinv_rtol)
+    log(f"config d=2 D={args.D} chi={args.chi} k={cfg.k} N={cfg.N} prec={args.prec}; "
+        f"workspace {P.workspace_bytes(cfg) / 2**30:.2f} GiB")
+    ctx = P.Ctm(cfg, torch.from_numpy(A).to(dev))
+    ctx.set_isometries(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
+    t = time.perf_counter()
+    info = ctx.move()                      # growth move (full SVD of the first M_b)
+    log(f"growth move mode={info['mode']} chi_env={info['chi_env']} "
+        f"{time.perf_counter() - t:.2f} s")
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        info = ctx.move()
+        log(f"warmup {i}: mode={info['mode']} delta={info['delta']:.3e} "
+            f"{(time.perf_counter() - t) * 1e3:.1f} ms")
+    state_after_warmup = ctx.get_state()
+
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        info = ctx.move()                  # synchronises (reads delta)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_step = 1e3 * elapsed / args.steps
+    log(f"timed {args.steps} moves: {ms_step:.2f} ms/move, last delta {info['delta']:.3e}")
+    for e in prof:
+        log(f"  {e['name']:16s} launches {e['launches']:5d}  {e['ms']:9.2f} ms  "
+            f"{e['flops'] / max(e['ms'], 1e-9) / 1e9:8.2f} TFLOP/s")
+
+    dom = next(e for e in prof if e["name"] == "si_apply")
+    per_launch_ms = dom["ms"] / dom["launches"]
+    flops_launch = dom["flops"] / dom["launches"]
+    bytes_launch = dom["bytes"] / dom["launches"]
+    achieved = flops_launch / (per_launch_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": "si_apply (8 enlarged-corner applications per launch)",
+                "achieved": round(achieved, 2), "peak": PEAK[args.prec], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK[args.prec], 4), "traffic": None,
+                "launch_ms": round(per_launch_ms, 4), "flops_per_launch": flops_launch,
+                "algorithmic_GBps": round(bytes_launch / (per_launch_ms * 1e-3) / 1e9, 1)}
+    total_flops = sum(e["flops"] for e in prof) / args.steps
+    breakdown = {e["name"]: round(e["ms"] / args.steps, 3) for e in prof}
+
+    svd = None
+    if args.svd_moves > 0:
+        cfg_s = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="svd",
+                         prec="f64", stabilized=1, pinv_rtol=args.pinv_rtol)
+        del ctx
+        torch.cuda.empty_cache()
+        cs = P.Ctm(cfg_s, torch.from_numpy(A).to(dev))
+        cs.set_state(state_after_warmup)
+        tt = []
+        for i in range(args.svd_moves):
+            t = time.perf_counter()
+            cs.move()
+            tt.append(time.perf_counter() - t)
+            log(f"full-SVD move {i}: {tt[-1]:.2f} s")
+        svd = {"moves_per_s": round(1.0 / float(np.mean(tt)), 4), "ms_per_move": round(1e3 * float(np.mean(tt)), 1),
+               "moves": args.svd_moves, "solver": "rocsolver_dgesvd on 4 x (5184 x 5184)"}
+        del cs
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (one SI move) ...")
+        cpu = cpu_baseline(args, A, X, Y)
+        log(f"CPU oracle: {1.0 / cpu['value']:.1f} s per move on {cpu['cores']} threads")
+
+    value = args.steps / elapsed
+    out = {
+        "metric": "SI-CTMRG iters/s at D=6 chi=144 vs full-SVD on same GPU; MFMA util; p50/p99",
+        "value": round(value, 4), "unit": "moves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": f"SI-CTMRG move, single-site iPEPS d=2 D={args.D} chi={args.chi} "
+                               f"p={args.p} n_si={args.n_si}, enlarged corner {cfg.N}x{cfg.N}",
+                   "D": args.D, "chi": args.chi, "k": cfg.k, "n_si": args.n_si,
+                   "contraction_precision": args.prec, "parallelism": "1 GPU"},
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+        "tflops_per_move": round(total_flops / 1e12, 4),
+        "tflops_per_s": round(total_flops / (ms_step * 1e-3) / 1e12, 2),
+        "phase_ms_per_move": breakdown,
+        "roofline": roofline,
+        "full_svd_same_gpu": svd,
+        "speedup_vs_full_svd": None if svd is None else round(value / svd["moves_per_s"], 2),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

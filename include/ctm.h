@@ -1,0 +1,201 @@
+/*
+ * ctm.h -- C ABI of the MI355X SI-CTMRG library (libsictm.so).
+ *
+ * The library contracts an infinite square-lattice tensor network built from
+ * one site tensor with the corner transfer matrix renormalisation group, using
+ * the subspace-iteration projectors of Zhang & Corboz, "Fast two-dimensional
+ * tensor-network contraction via subspace iteration" (QR-based projector
+ * section, steps 1-4) or the standard full-SVD projectors (Standard CTMRG
+ * section).  Every step of a move runs in this library's own HIP kernels on
+ * the GPU; the full-SVD projectors additionally call rocSOLVER's dgesvd.
+ *
+ * Conventions shared by every entry point
+ *  - All tensors are real float64, C-ordered (row-major).
+ *  - Site tensor A[s,u,l,d,r] (physical, up, left, down, right) of shape
+ *    (d, D, D, D, D) (iPEPS section, eq. ipeps_ansatz).  With d == 0 the
+ *    caller passes the rank-4 network tensor a[u,l,d,r] itself (a classical
+ *    model), of leg dimension D.  Dl denotes the leg dimension of the
+ *    double layer a: Dl = D*D if d > 0, else D (eq. double_layer).
+ *  - Environment (Fig. 1): corners C1..C4 (chi x chi) clockwise from the
+ *    top-left, edges T1 (top), T2 (right), T3 (bottom), T4 (left) of shape
+ *    (chi, Dl, chi), each ordered (in, inner, out) going clockwise:
+ *    C1[a,b] T1[b,u,g] C2[g,h] T2[h,r,e] C3[e,z] T3[z,d,n] C4[n,t] T4[t,l,a].
+ *  - N = chi * Dl, k = min(chi + p, N).  Bond b = 0,1,2,3 is the top, right,
+ *    bottom, left cut between enlarged corners b and b+1.  Its isometries are
+ *    X_b (N x k) and Y_b^T (N x k), both stored N x k row-major.
+ *  - Device pointers are HIP device addresses; host pointers are ordinary
+ *    process memory.  Unless stated otherwise the library never keeps a
+ *    caller pointer beyond the call.
+ *  - A stream argument is a hipStream_t passed as void* (NULL = the default
+ *    stream).  All device work of a context is ordered on its stream.
+ *  - Errors are returned as ctm_status; no entry point aborts the process.
+ *    After an error, ctm_last_error() describes it.
+ */
+#ifndef SICTM_CTM_H
+#define SICTM_CTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ctm_ctx ctm_ctx;
+
+typedef enum {
+  CTM_OK = 0,
+  CTM_E_ARG = 1,           /* null pointer or out-of-range argument            */
+  CTM_E_SHAPE = 2,         /* inconsistent dimensions                          */
+  CTM_E_NOMEM = 3,         /* workspace too small or device allocation failed  */
+  CTM_E_DEVICE = 4,        /* a HIP / rocSOLVER call failed                    */
+  CTM_E_NUMERIC = 5,       /* NaN/Inf or zero norm; the environment is kept    */
+  CTM_E_NOT_CONVERGED = 6, /* move budget exhausted; the state stays valid     */
+  CTM_E_STATE = 7          /* call not valid in the current state              */
+} ctm_status;
+
+typedef enum { CTM_PROJ_FULLSVD = 0, CTM_PROJ_SI = 1 } ctm_proj;
+
+/* Precision of the contractions only; QR, small SVD, pseudo-inverse,
+ * projector scaling and the stored environment are always float64. */
+typedef enum { CTM_PREC_F64 = 0, CTM_PREC_F32 = 1, CTM_PREC_BF16 = 2 } ctm_prec;
+
+typedef enum {
+  CTM_OBS_NORM = 0,    /* out[0] = kappa = Z11 Z00 / (Z10 Z01), out[1..4] = Z11,Z00,Z10,Z01 */
+  CTM_OBS_ONESITE = 1, /* d > 0: op is d x d (bra, ket); d == 0: op is an impurity a_O[u,l,d,r] */
+  CTM_OBS_BOND_H = 2,  /* d > 0: op is d^2 x d^2 on (site1 site2); d == 0: two impurities     */
+  CTM_OBS_BOND_V = 3   /* as BOND_H for the vertical bond (site 1 above site 2)               */
+} ctm_obs;
+
+typedef struct {
+  int d;            /* physical dimension; 0 = the network tensor a is given directly    */
+  int D;            /* virtual bond dimension of A, or leg dimension of a when d == 0    */
+  int chi;          /* environment bond dimension (>= 1)                                 */
+  int p;            /* oversampling of the subspace (>= 0)                               */
+  int n_si;         /* subspace-iteration steps per move (>= 0)                          */
+  int proj;         /* ctm_proj                                                          */
+  int prec;         /* ctm_prec                                                          */
+  int stabilized;   /* 1: orthonormalise after M and after M^T; 0: only after M^T M      */
+  double pinv_rtol; /* s_i <= pinv_rtol * s_1 gives s_i^-1/2 := 0 (e.g. 1e-12 in f64)   */
+} ctm_config;
+
+typedef struct {
+  double delta;   /* max over corners of |s_new - s_old|_2 of unit-norm corner spectra */
+  int mode;       /* 0: growth without truncation, 1: full-SVD projectors, 2: SI       */
+  int chi_env;    /* environment dimension after the move                              */
+  double gap;     /* min over bonds of s_chi / s_(chi+1) - 1 (-1 when not truncated)   */
+} ctm_move_info;
+
+/* Human-readable name of a status code (static string). */
+const char* ctm_status_str(ctm_status s);
+
+/* Last error message recorded on ctx (static per context), or "" if none. */
+const char* ctm_last_error(const ctm_ctx* ctx);
+
+/* Exact device bytes ctm_init needs for cfg (the admission size of a solve).
+ * Returns CTM_E_ARG / CTM_E_SHAPE for invalid configurations. */
+ctm_status ctm_workspace_bytes(const ctm_config* cfg, size_t* bytes);
+
+/* Creates a context (iPEPS section: a = sum_s A A; Standard CTMRG section:
+ * initial boundary).
+ *  site_dev     device, A (d*D^4 doubles) or a (D^4) when d == 0; copied.
+ *  boundary_dev device, Dl doubles closing every outer leg of the initial
+ *               boundary site, or NULL for vec(I_D) (ket traced against bra;
+ *               only valid when d > 0); copied.
+ *  workspace    device memory of at least ctm_workspace_bytes(cfg) bytes owned
+ *               by the caller and kept until ctm_destroy, or NULL to let the
+ *               library allocate (and free) it.
+ *  stream       hipStream_t as void*.
+ * Builds a and the initial environment; returns once the stream has reached
+ * that point.  On error *out is NULL. */
+ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev,
+                    const double* boundary_dev, void* workspace, size_t ws_bytes,
+                    void* stream);
+
+/* Frees the context (and its workspace if the library allocated it). */
+void ctm_destroy(ctm_ctx* ctx);
+
+/* Sets the start blocks of the subspace iteration (QR-based projector
+ * section, step 1: random Gaussian matrices).  X_dev and Yt_dev are device
+ * arrays of 4*N*k doubles ([bond][N][k]); copied.  They take effect at the
+ * next SI move that starts from fresh blocks (the first move with
+ * chi_env == chi), or immediately if the environment already has chi_env ==
+ * chi.  Without this call the library draws its own standard normals. */
+ctm_status ctm_set_isometries(ctm_ctx* ctx, const double* X_dev, const double* Yt_dev);
+
+/* One simultaneous four-direction CTMRG move (Fig. 1).  Growth moves
+ * (chi_env < chi) use no truncation when chi_env*Dl <= chi, else full-SVD
+ * projectors; later moves use the configured projectors.  Stream-ordered;
+ * info, if non-NULL, is filled after a stream synchronisation.  On
+ * CTM_E_NUMERIC the previous environment is kept. */
+ctm_status ctm_move(ctm_ctx* ctx, ctm_move_info* info);
+
+/* Moves until delta < tol or max_moves moves were made.  Returns
+ * CTM_E_NOT_CONVERGED when the budget ran out (the state stays valid). */
+ctm_status ctm_converge(ctm_ctx* ctx, double tol, int max_moves, int* moves_done,
+                        double* last_delta);
+
+/* Observable of the current environment (iPEPS section: operator insertion
+ * into the norm network).  op_host and out_host are host arrays; see ctm_obs
+ * for their meaning.  Synchronises the stream. */
+ctm_status ctm_observable(ctm_ctx* ctx, int kind, const double* op_host, double* out_host);
+
+/* Number of doubles of the state vector: C1..C4, T1..T4, then X_0..X_3 and
+ * Yt_0..Yt_3 (each N x k), then one double holding chi_env and one holding
+ * the number of SI moves made. */
+ctm_status ctm_state_size(const ctm_ctx* ctx, size_t* n);
+
+/* Copies the state vector to / from host memory (n doubles, see
+ * ctm_state_size).  Corner and edge blocks are laid out for chi, with the
+ * leading chi_env x ... sub-block meaningful during growth.  Synchronises. */
+ctm_status ctm_get_state(ctm_ctx* ctx, double* host, size_t n);
+ctm_status ctm_set_state(ctm_ctx* ctx, const double* host, size_t n);
+
+/* Per-kernel-class timing of the context's launches, measured with HIP
+ * event pairs recorded on the context's stream around every launch.
+ * ctm_profile(ctx, 1) clears the records and starts recording; 0 stops.
+ * ctm_profile_read synchronises and returns one entry per kernel class that
+ * was launched: launches, summed device milliseconds between the event pairs,
+ * and the algorithmic flops and bytes of those launches (flops = 2 M N K per
+ * GEMM; bytes = one read of each operand and one write of the result). */
+typedef struct {
+  char name[32];
+  int launches;
+  double ms;
+  double flops;
+  double bytes;
+} ctm_prof_entry;
+
+ctm_status ctm_profile(ctm_ctx* ctx, int enable);
+ctm_status ctm_profile_read(ctm_ctx* ctx, ctm_prof_entry* out, int max_entries, int* n);
+
+/* ---------------------------------------------------------------------------
+ * Building blocks of a move, exposed for testing and for callers composing
+ * their own loops.  All operate on caller device memory on `stream`.
+ * ------------------------------------------------------------------------- */
+
+/* Batched C_i = alpha * op(A_i) * B_i (+ C_i if accumulate), float64 MFMA.
+ * A_i is M x K row-major (lda) if trans_a == 0, else stored K x M row-major
+ * (lda) and read transposed; B_i is K x N row-major (ldb); C_i is M x N
+ * row-major (ldc).  Arrays of `count` device pointers are host arrays. */
+ctm_status ctm_gemm_f64(int count, const double* const* A, const double* const* B,
+                        double* const* C, int M, int N, int K, int trans_a, long lda,
+                        long ldb, long ldc, double alpha, int accumulate, void* stream);
+
+/* Thin Householder QR of `count` N x k row-major matrices W_i (N >= k), in
+ * place: on return W_i holds Q with R_ii >= 0 (QR-based projector section,
+ * step 1).  Zero columns get tau = 0 and no division by zero. */
+ctm_status ctm_qr_f64(int count, double* const* W, int N, int k, void* stream);
+
+/* Singular value decomposition of `count` n x n row-major matrices
+ * (QR-based projector section, step 2): rho_i = u_i diag(s_i) v_i^T with
+ * s descending.  u_i and v_i are n x n row-major (columns are the singular
+ * vectors); any of them may be NULL for values only. */
+ctm_status ctm_svd_f64(int count, const double* const* rho, double* const* u,
+                       double* const* s, double* const* v, int n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SICTM_CTM_H */

@@ -1,0 +1,290 @@
+"""MI355X SI-CTMRG: Python binding of libsictm.so (include/ctm.h).
+
+The binding only marshals arguments: every step of a CTMRG move runs in the
+library's HIP kernels.  PyTorch supplies device memory (the workspace and the
+input tensors) and the stream.  Importing this package fails loudly when the
+library has not been built (``python -m paper_2607_15158_amd.build_lib``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsictm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python paper_2607_15158_amd/build_lib.py` "
+        "(the HIP library is required; there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+CTM_OK, CTM_E_ARG, CTM_E_SHAPE, CTM_E_NOMEM, CTM_E_DEVICE, CTM_E_NUMERIC, \
+    CTM_E_NOT_CONVERGED, CTM_E_STATE = range(8)
+PROJ = {"svd": 0, "fullsvd": 0, "si": 1}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+OBS_NORM, OBS_ONESITE, OBS_BOND_H, OBS_BOND_V = range(4)
+
+
+class ctm_config(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("D", ctypes.c_int), ("chi", ctypes.c_int),
+                ("p", ctypes.c_int), ("n_si", ctypes.c_int), ("proj", ctypes.c_int),
+                ("prec", ctypes.c_int), ("stabilized", ctypes.c_int),
+                ("pinv_rtol", ctypes.c_double)]
+
+
+class ctm_move_info(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("mode", ctypes.c_int), ("chi_env", ctypes.c_int),
+                ("gap", ctypes.c_double)]
+
+
+class ctm_prof_entry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+_vp, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+_sigs = {
+    "ctm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "ctm_last_error": (ctypes.c_char_p, [_vp]),
+    "ctm_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ctm_config), ctypes.POINTER(ctypes.c_size_t)]),
+    "ctm_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(ctm_config), _vp, _vp, _vp,
+                                ctypes.c_size_t, _vp]),
+    "ctm_destroy": (None, [_vp]),
+    "ctm_set_isometries": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ctm_move": (ctypes.c_int, [_vp, ctypes.POINTER(ctm_move_info)]),
+    "ctm_converge": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int), _dp]),
+    "ctm_observable": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
+    "ctm_state_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ctm_get_state": (ctypes.c_int, [_vp, _dp, ctypes.c_size_t]),
+    "ctm_set_state": (ctypes.c_int, [_vp, _dp, ctypes.c_size_t]),
+    "ctm_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ctm_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctm_prof_entry), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
+    "ctm_gemm_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long,
+                                    ctypes.c_double, ctypes.c_int, _vp]),
+    "ctm_qr_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),
+    "ctm_svd_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                   ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _vp]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class CtmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.ctm_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+def _check(status: int, ctx=None):
+    if status != CTM_OK:
+        raise CtmError(status, _lib.ctm_last_error(ctx).decode())
+    return status
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+@dataclass
+class Config:
+    d: int
+    D: int
+    chi: int
+    p: int = 8
+    n_si: int = 2
+    proj: str = "si"
+    prec: str = "f64"
+    stabilized: int = 1
+    pinv_rtol: float = 1e-12
+
+    def c(self) -> ctm_config:
+        return ctm_config(self.d, self.D, self.chi, self.p, self.n_si, PROJ[self.proj],
+                          PREC[self.prec], self.stabilized, self.pinv_rtol)
+
+    @property
+    def Dl(self) -> int:
+        return self.D * self.D if self.d > 0 else self.D
+
+    @property
+    def N(self) -> int:
+        return self.chi * self.Dl
+
+    @property
+    def k(self) -> int:
+        return min(self.chi + self.p, self.N)
+
+
+def workspace_bytes(cfg: Config) -> int:
+    n = ctypes.c_size_t(0)
+    c = cfg.c()
+    _check(_lib.ctm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)))
+    return n.value
+
+
+class Ctm:
+    """One environment solve on the GPU (owns a torch workspace tensor)."""
+
+    def __init__(self, cfg: Config, site, boundary=None, stream=None, workspace=None):
+        import torch
+        self.cfg = cfg
+        self._c = cfg.c()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self._site = site.to(dev, torch.float64).contiguous()
+        self._bnd = None if boundary is None else boundary.to(dev, torch.float64).contiguous()
+        nbytes = workspace_bytes(cfg)
+        self.workspace = (torch.empty(nbytes, dtype=torch.uint8, device=dev)
+                          if workspace is None else workspace)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(_lib.ctm_init(ctypes.byref(h), ctypes.byref(self._c), _ptr(self._site),
+                             None if self._bnd is None else _ptr(self._bnd),
+                             _ptr(self.workspace), nbytes, _stream(stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ctm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_isometries(self, X, Yt):
+        """X, Yt: device float64 tensors of shape (4, N, k)."""
+        X = X.contiguous()
+        Yt = Yt.contiguous()
+        _check(_lib.ctm_set_isometries(self._h, _ptr(X), _ptr(Yt)), self._h)
+        self._keep = (X, Yt)
+
+    def move(self) -> dict:
+        info = ctm_move_info()
+        _check(_lib.ctm_move(self._h, ctypes.byref(info)), self._h)
+        return {"delta": info.delta, "mode": info.mode, "chi_env": info.chi_env, "gap": info.gap}
+
+    def converge(self, tol: float, max_moves: int, raise_on_budget: bool = False):
+        n = ctypes.c_int(0)
+        dl = ctypes.c_double(0.0)
+        st = _lib.ctm_converge(self._h, tol, max_moves, ctypes.byref(n), ctypes.byref(dl))
+        if st not in (CTM_OK, CTM_E_NOT_CONVERGED) or (raise_on_budget and st != CTM_OK):
+            _check(st, self._h)
+        return {"converged": st == CTM_OK, "moves": n.value, "delta": dl.value}
+
+    def observable(self, kind: int, op: Optional[np.ndarray] = None) -> np.ndarray:
+        out = np.zeros(8)
+        opa = None if op is None else np.ascontiguousarray(op, dtype=np.float64)
+        _check(_lib.ctm_observable(self._h, kind,
+                                   None if opa is None else opa.ctypes.data_as(_dp),
+                                   out.ctypes.data_as(_dp)), self._h)
+        return out
+
+    def kappa(self) -> float:
+        return float(self.observable(OBS_NORM)[0])
+
+    def state_size(self) -> int:
+        n = ctypes.c_size_t(0)
+        _check(_lib.ctm_state_size(self._h, ctypes.byref(n)), self._h)
+        return n.value
+
+    def get_state(self) -> np.ndarray:
+        n = self.state_size()
+        buf = np.zeros(n)
+        _check(_lib.ctm_get_state(self._h, buf.ctypes.data_as(_dp), n), self._h)
+        return buf
+
+    def set_state(self, state: np.ndarray):
+        buf = np.ascontiguousarray(state, dtype=np.float64)
+        _check(_lib.ctm_set_state(self._h, buf.ctypes.data_as(_dp), buf.size), self._h)
+
+    def unpack_state(self, state: np.ndarray) -> dict:
+        """Splits a state vector into C, T (cut to chi_env), X, Yt, chi_env."""
+        chi, Dl, N, k = self.cfg.chi, self.cfg.Dl, self.cfg.N, self.cfg.k
+        o = 0
+        C = [state[o + i * chi * chi: o + (i + 1) * chi * chi] for i in range(4)]
+        o += 4 * chi * chi
+        T = [state[o + i * chi * Dl * chi: o + (i + 1) * chi * Dl * chi] for i in range(4)]
+        o += 4 * chi * Dl * chi
+        X = state[o: o + 4 * N * k].reshape(4, N, k)
+        o += 4 * N * k
+        Yt = state[o: o + 4 * N * k].reshape(4, N, k)
+        o += 4 * N * k
+        x = int(state[o])
+        C = [c[: x * x].reshape(x, x) for c in C]
+        T = [t[: x * Dl * x].reshape(x, Dl, x) for t in T]
+        return {"C": C, "T": T, "X": X, "Yt": Yt, "chi_env": x, "si_moves": int(state[o + 1])}
+
+    def pack_state(self, C, T, X, Yt, si_moves: int = 0) -> np.ndarray:
+        chi, Dl, N, k = self.cfg.chi, self.cfg.Dl, self.cfg.N, self.cfg.k
+        x = C[0].shape[0]
+        out = np.zeros(self.state_size())
+        o = 0
+        for c in C:
+            out[o: o + x * x] = np.asarray(c).ravel()
+            o += chi * chi
+        for t in T:
+            out[o: o + x * Dl * x] = np.asarray(t).ravel()
+            o += chi * Dl * chi
+        out[o: o + 4 * N * k] = np.asarray(X).ravel()
+        o += 4 * N * k
+        out[o: o + 4 * N * k] = np.asarray(Yt).ravel()
+        o += 4 * N * k
+        out[o] = x
+        out[o + 1] = si_moves
+        return out
+
+    # profiling ---------------------------------------------------------------
+    def profile(self, enable: bool):
+        _check(_lib.ctm_profile(self._h, int(enable)), self._h)
+
+    def profile_read(self) -> list:
+        arr = (ctm_prof_entry * 16)()
+        n = ctypes.c_int(0)
+        _check(_lib.ctm_profile_read(self._h, arr, 16, ctypes.byref(n)), self._h)
+        return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "ms": arr[i].ms,
+                 "flops": arr[i].flops, "bytes": arr[i].bytes} for i in range(n.value)]
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def gemm_f64(A: Sequence, B: Sequence, C: Sequence, M, N, K, trans_a=0, lda=None, ldb=None,
+             ldc=None, alpha=1.0, accumulate=0, stream=None):
+    lda = (M if trans_a else K) if lda is None else lda
+    ldb = N if ldb is None else ldb
+    ldc = N if ldc is None else ldc
+    _check(_lib.ctm_gemm_f64(len(A), _ptr_array(A), _ptr_array(B), _ptr_array(C), M, N, K,
+                             trans_a, lda, ldb, ldc, alpha, accumulate, _stream(stream)))
+
+
+def qr_f64(W: Sequence, stream=None):
+    """In-place thin Householder QR (R_ii >= 0) of N x k device matrices."""
+    N, k = W[0].shape
+    _check(_lib.ctm_qr_f64(len(W), _ptr_array(W), N, k, _stream(stream)))
+
+
+def svd_f64(rho: Sequence, u: Sequence, s: Sequence, v: Sequence, stream=None):
+    n = rho[0].shape[0]
+    _check(_lib.ctm_svd_f64(len(rho), _ptr_array(rho), None if u is None else _ptr_array(u),
+                            _ptr_array(s), None if v is None else _ptr_array(v), n,
+                            _stream(stream)))

@@ -1,0 +1,82 @@
+// Shared definitions of the SI-CTMRG HIP library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+#define CTM_HIP_TRY(expr)                                              \
+  do {                                                                 \
+    hipError_t _e = (expr);                                            \
+    if (_e != hipSuccess) return ::sictm::hip_fail(_e, #expr, __LINE__); \
+  } while (0)
+
+namespace sictm {
+
+// Records the failing call in a thread-local message and returns CTM_E_DEVICE.
+int hip_fail(hipError_t e, const char* what, int line);
+const std::string& thread_error();
+void set_thread_error(const std::string& s);
+
+constexpr int kWave = 64;
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// GEMM descriptor: C_p[map_c(m, n) + batch*c_bs] = alpha * sum_k A(m,k) B(k,n)
+// for up to kMaxProb problems p with identical shapes.  A(m,k) is
+// A_p[m*lda + k] (trans 0) or A_p[k*lda + m] (trans 1), per problem.  B(k,n)
+// is B_p[k*ldb + n].  The output map is two-level in m and in n:
+//   off(m) = (m / cdiv_m) * cs_m1 + (m % cdiv_m) * cs_m0, same for n.
+// ---------------------------------------------------------------------------
+constexpr int kMaxProb = 8;
+
+struct GemmBatch {
+  const void* A[kMaxProb];
+  const void* B[kMaxProb];
+  void* C[kMaxProb];
+  int transA[kMaxProb];
+  int count;          // problems
+  int M, N, K;
+  long lda, ldb;
+  int cdiv_m;
+  long cs_m1, cs_m0;
+  int cdiv_n;
+  long cs_n1, cs_n0;
+  int nbatch;         // inner batch per problem
+  long a_bs, b_bs, c_bs;
+  double alpha;
+  int accumulate;     // 1: C += alpha*AB
+};
+
+// Element types of a GEMM launch.
+enum class DT : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+// Plain row-major output helper.
+inline void gemm_set_rowmajor_c(GemmBatch& g, long ldc) {
+  g.cdiv_m = 1 << 30; g.cs_m1 = 0; g.cs_m0 = ldc;
+  g.cdiv_n = 1 << 30; g.cs_n1 = 0; g.cs_n0 = 1;
+}
+
+// Launches a batched GEMM; ta = element type of A, tb of B, tc of C.
+// Accumulation is float64 for F64 inputs and float32 otherwise.
+int launch_gemm(const GemmBatch& g, DT ta, DT tb, DT tc, hipStream_t s);
+
+// Householder QR (in place, Q returned with R_ii >= 0) of `count` N x k
+// row-major matrices.  ws must hold qr_workspace_bytes(count, N, k) bytes.
+size_t qr_workspace_bytes(int count, int N, int k);
+int launch_qr(int count, double* const* W, int N, int k, void* ws, hipStream_t s);
+
+// One-sided Jacobi SVD of `count` n x n row-major matrices (see ctm.h).
+size_t svd_workspace_bytes(int count, int n);
+int launch_svd(int count, const double* const* A, double* const* U, double* const* S,
+               double* const* V, int n, void* ws, hipStream_t s);
+
+}  // namespace sictm

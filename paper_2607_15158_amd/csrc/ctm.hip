@@ -1,0 +1,1368 @@
+// Host orchestration of the SI-CTMRG move and the C ABI of include/ctm.h.
+//
+// A move (Fig. 1 of Zhang & Corboz) on one GPU, all of it stream-ordered on
+// the context's stream:
+//   1. enlarged corners Ct_i = T_(i-1) C_i T_i a, batched over the 4 corners
+//      (three GEMMs each: C T, then T (C T), then the absorption of a);
+//   2. projectors of the 4 bonds, batched:
+//      - SI (QR-based projector section, steps 1-3): n_si subspace steps, each
+//        8 applications of enlarged corners to the N x k blocks (X side and
+//        Y side together, 8 problems per launch) and Householder QRs; then
+//        A = R X, B^T = L^T Y^T, rho = B A, SVD of rho, the sign rule,
+//        the pseudo-inverse scaling and the gauge recycle X <- X v,
+//        Y <- u^T Y (eq. xy_recycle);
+//      - full SVD (Standard CTMRG section): M_b = L_b R_b formed explicitly
+//        and decomposed with rocSOLVER dgesvd; used for the comparator and
+//        for growth moves that truncate;
+//      - growth without truncation: identity projectors;
+//   3. renormalisation C' = P_r Ct P_l and T' = P_r (T a) P_l;
+//   4. unit Frobenius normalisation, NaN / zero guard, corner spectra and
+//      the convergence measure.
+// The environment is double-buffered: a move that fails the numeric guard
+// leaves the committed corners and edges untouched.
+
+#include "../../include/ctm.h"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "elem.h"
+
+namespace sictm {
+
+thread_local std::string g_err;
+
+int hip_fail(hipError_t e, const char* what, int line) {
+  g_err = std::string("HIP error '") + hipGetErrorString(e) + "' in " + what + " (ctm.hip:" +
+          std::to_string(line) + ")";
+  return CTM_E_DEVICE;
+}
+const std::string& thread_error() { return g_err; }
+void set_thread_error(const std::string& s) { g_err = s; }
+
+}  // namespace sictm
+
+using namespace sictm;
+
+namespace {
+
+size_t dt_size(DT t) { return t == DT::F64 ? 8 : (t == DT::F32 ? 4 : 2); }
+
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  std::vector<std::pair<uintptr_t, uintptr_t>>* reg = nullptr;   // [begin, end) of each buffer
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    if (base && reg) reg->push_back({(uintptr_t)p, (uintptr_t)p + count * sizeof(T)});
+    off += count * sizeof(T);
+    return p;
+  }
+  void* take_bytes(size_t bytes) { return take<char>(bytes); }
+};
+
+enum ProfClass { PC_CORNER = 0, PC_SI_APPLY, PC_QR, PC_SVD, PC_PROJ, PC_RENORM, PC_FULLSVD, PC_MISC, PC_N };
+const char* kProfNames[PC_N] = {"corner_build", "si_apply", "householder_qr", "jacobi_svd",
+                                "projector_gemm", "renormalise", "full_svd", "misc"};
+
+}  // namespace
+
+struct ctm_ctx {
+  ctm_config cfg;
+  int d, D, Dl, chi, k, N, xmax, Nmax;
+  DT cp;
+  hipStream_t st;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  // state
+  int chi_env = 0, cur = 0, spec_cur = 0;
+  bool si_ready = false, iso_pending = false;
+  long si_moves = 0, moves = 0;
+  // buffers
+  double* A_site = nullptr;
+  double* a = nullptr;
+  void* ap[4];
+  double* imp[3];            // impurity scratch (Dl^4 each)
+  double* imps[2];           // open-leg impurities of the two bond sites (d^2 Dl^4 each)
+  double* e = nullptr;
+  double* C[2][4];
+  double* T[2][4];
+  double* X[4];
+  double* Yt[4];
+  double* X0[4];
+  double* Yt0[4];
+  double* W[2][8];
+  void* Ct[4];
+  double* S1[4];
+  double* S2[4];
+  double* CT[4];
+  double *rho[4], *u[4], *v[4], *vs[4], *s[4], *sg[4], *vsc[4], *usc[4];
+  double *Pl[4], *Prt[4], *Zc[4];
+  double* spec[2];
+  double* csv[4];
+  double* scal;              // [0..7] norms, [8] delta, [9..12] gap, [16..] observables
+  int* bad;
+  void* qr_ws;
+  void* svd_ws;
+  double *fs_s, *fs_E, *fs_sg, *fs_Us, *fs_Vs;
+  int* fs_info;
+  double* obs_y;             // [d^2][x Dl x]
+  double* obs_w;             // [d^2][x Dl x]
+  double* obs_op;            // [d^4] device copy of an operator
+  rocblas_handle rb = nullptr;
+  std::string err;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec { int cls; hipEvent_t a, b; double flops, bytes; };
+  std::vector<Rec> recs;
+  size_t ev_next = 0;
+  // carved buffers, for the host-side bounds check of every GEMM launch
+  std::vector<std::pair<uintptr_t, uintptr_t>> bufs;
+};
+
+namespace {
+
+int fail(ctm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  g_err = msg;
+  return code;
+}
+
+// Propagates a non-zero launcher code (1 = bad argument) with its message.
+#define TRY(expr)                                                    \
+  do {                                                               \
+    int _r = (expr);                                                 \
+    if (_r != 0) {                                                   \
+      c->err = g_err.empty() ? std::string(#expr) : g_err;           \
+      return _r == 1 ? (int)CTM_E_ARG : _r;                          \
+    }                                                                \
+  } while (0)
+
+int validate(const ctm_config* cfg) {
+  if (!cfg) return fail(nullptr, CTM_E_ARG, "null config");
+  if (cfg->d < 0 || cfg->D < 1 || cfg->chi < 1 || cfg->p < 0 || cfg->n_si < 0)
+    return fail(nullptr, CTM_E_SHAPE, "need d >= 0, D >= 1, chi >= 1, p >= 0, n_si >= 0");
+  if (cfg->proj != CTM_PROJ_FULLSVD && cfg->proj != CTM_PROJ_SI)
+    return fail(nullptr, CTM_E_ARG, "unknown projector kind");
+  if (cfg->prec < CTM_PREC_F64 || cfg->prec > CTM_PREC_BF16)
+    return fail(nullptr, CTM_E_ARG, "unknown precision");
+  if (!(cfg->pinv_rtol >= 0.0)) return fail(nullptr, CTM_E_ARG, "pinv_rtol must be >= 0");
+  const int Dl = cfg->d > 0 ? cfg->D * cfg->D : cfg->D;
+  const long N = (long)cfg->chi * Dl;
+  const long k = std::min<long>(cfg->chi + cfg->p, N);
+  if (k > 256) return fail(nullptr, CTM_E_SHAPE, "chi + p must be <= 256");
+  if (N > 65536) return fail(nullptr, CTM_E_SHAPE, "chi * Dl must be <= 65536");
+  return CTM_OK;
+}
+
+void set_dims(ctm_ctx* c, const ctm_config* cfg) {
+  c->cfg = *cfg;
+  c->d = cfg->d;
+  c->D = cfg->D;
+  c->Dl = cfg->d > 0 ? cfg->D * cfg->D : cfg->D;
+  c->chi = cfg->chi;
+  c->N = c->chi * c->Dl;
+  c->k = std::min(c->chi + cfg->p, c->N);
+  c->xmax = std::max(c->chi, c->Dl);
+  c->Nmax = c->xmax * c->Dl;
+  c->cp = cfg->prec == CTM_PREC_F64 ? DT::F64 : (cfg->prec == CTM_PREC_F32 ? DT::F32 : DT::BF16);
+}
+
+// Assigns every buffer of the context from base (or only sizes it).
+size_t carve(ctm_ctx* c, char* base) {
+  Carver cv;
+  cv.base = base;
+  c->bufs.clear();
+  cv.reg = &c->bufs;
+  const size_t Dl4 = (size_t)c->Dl * c->Dl * c->Dl * c->Dl;
+  const size_t xm = c->xmax, Dl = c->Dl, N = c->N, k = c->k, chi = c->chi, Nm = c->Nmax;
+  const size_t es = dt_size(c->cp);
+  const int dd = std::max(1, c->d * c->d);
+  c->A_site = cv.take<double>(c->d > 0 ? (size_t)c->d * c->D * c->D * c->D * c->D : 1);
+  c->a = cv.take<double>(Dl4);
+  for (int i = 0; i < 4; ++i) c->ap[i] = cv.take_bytes(Dl4 * es);
+  for (int i = 0; i < 3; ++i) c->imp[i] = cv.take<double>(Dl4);
+  for (int i = 0; i < 2; ++i) c->imps[i] = cv.take<double>((size_t)dd * Dl4);
+  c->e = cv.take<double>(Dl);
+  for (int b = 0; b < 2; ++b)
+    for (int i = 0; i < 4; ++i) {
+      c->C[b][i] = cv.take<double>(xm * xm);
+      c->T[b][i] = cv.take<double>(xm * Dl * xm);
+    }
+  for (int i = 0; i < 4; ++i) {
+    c->X[i] = cv.take<double>(N * k);
+    c->Yt[i] = cv.take<double>(N * k);
+    c->X0[i] = cv.take<double>(N * k);
+    c->Yt0[i] = cv.take<double>(N * k);
+  }
+  for (int s = 0; s < 2; ++s)
+    for (int i = 0; i < 8; ++i) c->W[s][i] = cv.take<double>(N * k);
+  for (int i = 0; i < 4; ++i) c->Ct[i] = cv.take_bytes(Nm * Nm * es);
+  for (int i = 0; i < 4; ++i) c->S1[i] = cv.take<double>(Nm * Nm);
+  for (int i = 0; i < 4; ++i) c->S2[i] = cv.take<double>(Nm * Nm);
+  for (int i = 0; i < 4; ++i) c->CT[i] = cv.take<double>(xm * Dl * xm);
+  for (int i = 0; i < 4; ++i) {
+    c->rho[i] = cv.take<double>(k * k);
+    c->u[i] = cv.take<double>(k * k);
+    c->v[i] = cv.take<double>(k * k);
+    c->vs[i] = cv.take<double>(k * k);
+    c->s[i] = cv.take<double>(std::max(k, xm));
+    c->sg[i] = cv.take<double>(std::max(k, xm));
+    c->vsc[i] = cv.take<double>(k * chi);
+    c->usc[i] = cv.take<double>(k * chi);
+    c->Pl[i] = cv.take<double>(Nm * std::max(Nm, chi));
+    c->Prt[i] = cv.take<double>(Nm * std::max(Nm, chi));
+    c->Zc[i] = cv.take<double>(Nm * std::max(Nm, chi));
+    c->csv[i] = cv.take<double>(xm);
+  }
+  for (int i = 0; i < 2; ++i) c->spec[i] = cv.take<double>(4 * chi);
+  c->scal = cv.take<double>(256);
+  c->bad = cv.take<int>(64);
+  c->qr_ws = cv.take_bytes(qr_workspace_bytes(8, (int)N, (int)k));
+  c->svd_ws = cv.take_bytes(svd_workspace_bytes(8, (int)std::max(k, xm)));
+  c->fs_s = cv.take<double>(Nm);
+  c->fs_E = cv.take<double>(Nm);
+  c->fs_sg = cv.take<double>(Nm);
+  c->fs_Us = cv.take<double>(Nm * chi);
+  c->fs_Vs = cv.take<double>(Nm * chi);
+  c->fs_info = cv.take<int>(64);
+  c->obs_y = cv.take<double>((size_t)dd * xm * Dl * xm);
+  c->obs_w = cv.take<double>((size_t)dd * xm * Dl * xm);
+  c->obs_op = cv.take<double>(256);
+  std::sort(c->bufs.begin(), c->bufs.end());
+  return cv.off + 256;
+}
+
+// ---------------------------------------------------------------------------
+// profiling: hipEvent pairs around launches of each class
+// ---------------------------------------------------------------------------
+struct ProfScope {
+  ctm_ctx* c;
+  int cls;
+  double flops, bytes;
+  hipEvent_t a{}, b{};
+  ProfScope(ctm_ctx* ctx, int cl, double fl = 0, double by = 0) : c(ctx), cls(cl), flops(fl), bytes(by) {
+    if (!c->prof) return;
+    a = next();
+    (void)hipEventRecord(a, c->st);
+  }
+  hipEvent_t next() {
+    if (c->ev_next >= c->ev_pool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_next++];
+  }
+  ~ProfScope() {
+    if (!c->prof) return;
+    b = next();
+    (void)hipEventRecord(b, c->st);
+    c->recs.push_back({cls, a, b, flops, bytes});
+  }
+};
+
+GemmBatch gemm_rowmajor(int count, int M, int N, int K, long lda, long ldb, long ldc) {
+  GemmBatch g{};
+  g.count = count;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  gemm_set_rowmajor_c(g, ldc);
+  g.nbatch = 1;
+  g.alpha = 1.0;
+  return g;
+}
+
+double gemm_flops(const GemmBatch& g) { return 2.0 * g.M * g.N * (double)g.K * g.count * g.nbatch; }
+
+// Largest element offset a 2-level map can address for indices < n.
+long map_extent(int n, int div, long s1, long s0) {
+  if (n <= 0) return 0;
+  return (long)((n - 1) / div) * s1 + (long)std::min(div - 1, n - 1) * s0;
+}
+
+// True if [p, p + bytes) lies inside one carved buffer of the context.
+bool inside(const ctm_ctx* c, const void* p, size_t bytes) {
+  const uintptr_t a = (uintptr_t)p;
+  auto it = std::upper_bound(c->bufs.begin(), c->bufs.end(),
+                             std::make_pair(a, std::numeric_limits<uintptr_t>::max()));
+  if (it == c->bufs.begin()) return false;
+  --it;
+  return a >= it->first && a + bytes <= it->second;
+}
+
+// Host-side bounds check of every operand of a GEMM launch against the
+// buffer that holds its base pointer; refuses to launch on a violation.
+int check_gemm(ctm_ctx* c, const GemmBatch& g, DT ta, DT tb, DT tc) {
+  if (g.M <= 0 || g.N <= 0) return 0;
+  for (int i = 0; i < g.count; ++i) {
+    const long ea = g.K <= 0 ? 0
+                    : (g.transA[i] ? (long)(g.K - 1) * g.lda + (g.M - 1)
+                                   : (long)(g.M - 1) * g.lda + (g.K - 1)) +
+                          (long)(g.nbatch - 1) * g.a_bs;
+    const long eb = g.K <= 0 ? 0 : (long)(g.K - 1) * g.ldb + (g.N - 1) + (long)(g.nbatch - 1) * g.b_bs;
+    const long ec = map_extent(g.M, g.cdiv_m, g.cs_m1, g.cs_m0) +
+                    map_extent(g.N, g.cdiv_n, g.cs_n1, g.cs_n0) + (long)(g.nbatch - 1) * g.c_bs;
+    const bool ok = (g.K <= 0 || inside(c, g.A[i], (size_t)(ea + 1) * dt_size(ta))) &&
+                    (g.K <= 0 || inside(c, g.B[i], (size_t)(eb + 1) * dt_size(tb))) &&
+                    inside(c, g.C[i], (size_t)(ec + 1) * dt_size(tc));
+    if (!ok) {
+      g_err = "GEMM operand out of its buffer (M=" + std::to_string(g.M) + " N=" +
+              std::to_string(g.N) + " K=" + std::to_string(g.K) + " problem " +
+              std::to_string(i) + "); launch refused";
+      return CTM_E_SHAPE;
+    }
+  }
+  return 0;
+}
+
+int run_gemm(ctm_ctx* c, int cls, const GemmBatch& g, DT ta, DT tb, DT tc, double bytes = 0) {
+  const int chk = check_gemm(c, g, ta, tb, tc);
+  if (chk) return chk;
+  ProfScope ps(c, cls, gemm_flops(g), bytes);
+  return launch_gemm(g, ta, tb, tc, c->st);
+}
+
+// ---------------------------------------------------------------------------
+// step 1: enlarged corners (batched over the four corners)
+// ---------------------------------------------------------------------------
+int build_corners(ctm_ctx* c) {
+  const int x = c->chi_env, Dl = c->Dl, N1 = x * Dl;
+  double* const* C = c->C[c->cur];
+  double* const* T = c->T[c->cur];
+  // CT_i[a, (q, y)] = C_i[a, b] T_i[b, q, y]
+  GemmBatch g1 = gemm_rowmajor(4, x, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
+  for (int i = 0; i < 4; ++i) {
+    g1.A[i] = C[i];
+    g1.B[i] = T[i];
+    g1.C[i] = c->CT[i];
+  }
+  TRY(run_gemm(c, PC_CORNER, g1, DT::F64, DT::F64, DT::F64));
+  // W_i[(x_in, y), (p, q)] = T_(i-1)[(x_in, p), a] CT_i[a, (q, y)]
+  GemmBatch g2 = gemm_rowmajor(4, x * Dl, Dl * x, x, x, (long)Dl * x, 0);
+  g2.cdiv_m = Dl;
+  g2.cs_m1 = (long)x * Dl * Dl;
+  g2.cs_m0 = Dl;
+  g2.cdiv_n = x;
+  g2.cs_n1 = 1;
+  g2.cs_n0 = (long)Dl * Dl;
+  for (int i = 0; i < 4; ++i) {
+    g2.A[i] = T[(i + 3) % 4];
+    g2.B[i] = c->CT[i];
+    g2.C[i] = c->S1[i];
+  }
+  TRY(run_gemm(c, PC_CORNER, g2, DT::F64, DT::F64, DT::F64));
+  // Ct_i[(x_in, o1), (y, o2)] = W_i[(x_in, y), (p, q)] ap_i[(p, q), (o1, o2)]
+  GemmBatch g3 = gemm_rowmajor(4, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
+  g3.cdiv_m = x;
+  g3.cs_m1 = (long)Dl * N1;
+  g3.cs_m0 = Dl;
+  g3.cdiv_n = Dl;
+  g3.cs_n1 = N1;
+  g3.cs_n0 = 1;
+  for (int i = 0; i < 4; ++i) {
+    g3.A[i] = c->S1[i];
+    g3.B[i] = c->ap[i];
+    g3.C[i] = c->Ct[i];
+  }
+  TRY(run_gemm(c, PC_CORNER, g3, DT::F64, c->cp, c->cp));
+  return 0;
+}
+
+// One application step: dst_i = op(Ct[ci_i]) src_i for up to 8 problems.
+int apply_step(ctm_ctx* c, int count, const int* ci, const int* trans, double* const* src,
+               double* const* dst, int N1) {
+  const int k = c->k;
+  GemmBatch g = gemm_rowmajor(count, N1, k, N1, N1, k, k);
+  for (int i = 0; i < count; ++i) {
+    g.A[i] = c->Ct[ci[i]];
+    g.transA[i] = trans[i];
+    g.B[i] = src[i];
+    g.C[i] = dst[i];
+  }
+  const double bytes = (double)count * ((double)N1 * N1 * dt_size(c->cp) + 2.0 * N1 * k * 8.0);
+  return run_gemm(c, PC_SI_APPLY, g, c->cp, DT::F64, DT::F64, bytes);
+}
+
+inline int md(int i) { return ((i % 4) + 4) % 4; }
+
+// Applies M (or M^T) of every bond to the X side and the opposite operator
+// to the Y side: the X block of bond b goes through Ct[b+2], Ct[b+1], Ct[b],
+// Ct[b-1] (M) or their transposes in reverse order (M^T).
+int half_step(ctm_ctx* c, bool x_with_M, int N1) {
+  double* in[8];
+  for (int b = 0; b < 4; ++b) {
+    in[b] = c->X[b];
+    in[4 + b] = c->Yt[b];
+  }
+  for (int t = 0; t < 4; ++t) {
+    int ci[8], tr[8];
+    double* out[8];
+    for (int b = 0; b < 4; ++b) {
+      const int mseq[4] = {md(b + 2), md(b + 1), md(b), md(b - 1)};
+      const int tseq[4] = {md(b - 1), md(b), md(b + 1), md(b + 2)};
+      ci[b] = x_with_M ? mseq[t] : tseq[t];
+      tr[b] = x_with_M ? 0 : 1;
+      ci[4 + b] = x_with_M ? tseq[t] : mseq[t];
+      tr[4 + b] = x_with_M ? 1 : 0;
+    }
+    for (int i = 0; i < 8; ++i) out[i] = c->W[t & 1][i];
+    TRY(apply_step(c, 8, ci, tr, in, out, N1));
+    for (int i = 0; i < 8; ++i) in[i] = out[i];
+  }
+  return 0;
+}
+
+// The results of a half step live in W[1]; orthonormalise them in place and
+// make them the current blocks (pointer swap, no copy).
+int qr_and_swap(ctm_ctx* c, int N1) {
+  {
+    ProfScope ps(c, PC_QR, 8.0 * 4.0 * N1 * (double)c->k * c->k);
+    TRY(launch_qr(8, c->W[1], N1, c->k, c->qr_ws, c->st));
+  }
+  for (int b = 0; b < 4; ++b) {
+    std::swap(c->X[b], c->W[1][b]);
+    std::swap(c->Yt[b], c->W[1][4 + b]);
+  }
+  return 0;
+}
+
+int ensure_si_blocks(ctm_ctx* c) {
+  const size_t nk = (size_t)c->N * c->k;
+  if (c->iso_pending) {
+    for (int b = 0; b < 4; ++b) {
+      CTM_HIP_TRY(hipMemcpyAsync(c->X[b], c->X0[b], nk * 8, hipMemcpyDeviceToDevice, c->st));
+      CTM_HIP_TRY(hipMemcpyAsync(c->Yt[b], c->Yt0[b], nk * 8, hipMemcpyDeviceToDevice, c->st));
+    }
+    c->iso_pending = false;
+    c->si_ready = true;
+  } else if (!c->si_ready) {
+    for (int b = 0; b < 4; ++b) {
+      TRY(elem_gauss(c->X[b], (long)nk, 1000 + b, c->st));
+      TRY(elem_gauss(c->Yt[b], (long)nk, 2000 + b, c->st));
+    }
+    c->si_ready = true;
+  }
+  return 0;
+}
+
+// SI projectors of the four bonds (QR-based projector section, steps 1-3).
+int si_projectors(ctm_ctx* c, int keep) {
+  const int N1 = c->N, k = c->k;
+  TRY(ensure_si_blocks(c));
+  for (int step = 0; step < c->cfg.n_si; ++step) {
+    if (c->cfg.stabilized) {
+      TRY(half_step(c, true, N1));   // X: M X      Y: M^T Y^T
+      TRY(qr_and_swap(c, N1));
+      TRY(half_step(c, false, N1));  // X: M^T (.)  Y: M (.)
+      TRY(qr_and_swap(c, N1));
+    } else {
+      TRY(half_step(c, true, N1));
+      for (int b = 0; b < 8; ++b) std::swap(b < 4 ? c->X[b] : c->Yt[b - 4], c->W[1][b]);
+      TRY(half_step(c, false, N1));
+      TRY(qr_and_swap(c, N1));
+    }
+  }
+  // A_b = R_b X = Ct[b+1] (Ct[b+2] X);  B_b^T = L_b^T Y^T = Ct[b]^T (Ct[b-1]^T Y^T)
+  {
+    int ci[8], tr[8];
+    double* in[8];
+    double* out[8];
+    for (int b = 0; b < 4; ++b) {
+      ci[b] = md(b + 2); tr[b] = 0; in[b] = c->X[b]; out[b] = c->W[0][b];
+      ci[4 + b] = md(b - 1); tr[4 + b] = 1; in[4 + b] = c->Yt[b]; out[4 + b] = c->W[0][4 + b];
+    }
+    TRY(apply_step(c, 8, ci, tr, in, out, N1));
+    for (int b = 0; b < 4; ++b) {
+      ci[b] = md(b + 1); in[b] = c->W[0][b]; out[b] = c->W[1][b];
+      ci[4 + b] = md(b); in[4 + b] = c->W[0][4 + b]; out[4 + b] = c->W[1][4 + b];
+    }
+    TRY(apply_step(c, 8, ci, tr, in, out, N1));
+  }
+  double* const* A = c->W[1];        // A_b in W[1][b], B_b^T in W[1][4+b]
+  // rho_b = B_b A_b = (B_b^T)^T A_b   (float64)
+  {
+    GemmBatch g = gemm_rowmajor(4, k, k, N1, k, k, k);
+    for (int b = 0; b < 4; ++b) {
+      g.A[b] = A[4 + b];
+      g.transA[b] = 1;
+      g.B[b] = A[b];
+      g.C[b] = c->rho[b];
+    }
+    TRY(run_gemm(c, PC_PROJ, g, DT::F64, DT::F64, DT::F64));
+  }
+  {
+    ProfScope ps(c, PC_SVD);
+    TRY(launch_svd(4, c->rho, c->u, c->s, c->v, k, c->svd_ws, c->st));
+  }
+  // Y^T u -> W[0][4+b]; signs from it
+  {
+    GemmBatch g = gemm_rowmajor(4, N1, k, k, k, k, k);
+    for (int b = 0; b < 4; ++b) {
+      g.A[b] = c->Yt[b];
+      g.B[b] = c->u[b];
+      g.C[b] = c->W[0][4 + b];
+    }
+    TRY(run_gemm(c, PC_PROJ, g, DT::F64, DT::F64, DT::F64));
+  }
+  SignArgs sa{};
+  sa.N = N1;
+  sa.k = k;
+  sa.ld = k;
+  for (int b = 0; b < 4; ++b) {
+    sa.Y[b] = c->W[0][4 + b];
+    sa.sg[b] = c->sg[b];
+  }
+  TRY(elem_col_sign(sa, 4, c->st));
+  TRY(elem_scale_cols(sa, 4, c->st));
+  ProjPrepArgs pa{};
+  pa.k = k;
+  pa.keep = keep;
+  pa.rtol = c->cfg.pinv_rtol;
+  pa.gap = c->scal + 9;
+  for (int b = 0; b < 4; ++b) {
+    pa.u[b] = c->u[b];
+    pa.v[b] = c->v[b];
+    pa.s[b] = c->s[b];
+    pa.sg[b] = c->sg[b];
+    pa.vs[b] = c->vs[b];
+    pa.vsc[b] = c->vsc[b];
+    pa.usc[b] = c->usc[b];
+  }
+  TRY(elem_proj_prep(pa, 4, c->st));
+  // X <- X v diag(sg) (into W[0][b]); P_l = A vsc; P_r^T = B^T usc
+  {
+    GemmBatch g = gemm_rowmajor(4, N1, k, k, k, k, k);
+    for (int b = 0; b < 4; ++b) {
+      g.A[b] = c->X[b];
+      g.B[b] = c->vs[b];
+      g.C[b] = c->W[0][b];
+    }
+    TRY(run_gemm(c, PC_PROJ, g, DT::F64, DT::F64, DT::F64));
+  }
+  {
+    GemmBatch g = gemm_rowmajor(8, N1, keep, k, k, keep, keep);
+    for (int b = 0; b < 4; ++b) {
+      g.A[b] = A[b];
+      g.B[b] = c->vsc[b];
+      g.C[b] = c->Pl[b];
+      g.A[4 + b] = A[4 + b];
+      g.B[4 + b] = c->usc[b];
+      g.C[4 + b] = c->Prt[b];
+    }
+    TRY(run_gemm(c, PC_PROJ, g, DT::F64, DT::F64, DT::F64));
+  }
+  for (int b = 0; b < 4; ++b) {
+    std::swap(c->X[b], c->W[0][b]);
+    std::swap(c->Yt[b], c->W[0][4 + b]);
+  }
+  return 0;
+}
+
+int ensure_rocblas(ctm_ctx* c) {
+  if (c->rb) return 0;
+  if (rocblas_create_handle(&c->rb) != rocblas_status_success)
+    return fail(c, CTM_E_DEVICE, "rocblas_create_handle failed");
+  rocblas_set_stream(c->rb, c->st);
+  return 0;
+}
+
+// Full-SVD projectors (Standard CTMRG section) for environment dimension x.
+int full_projectors(ctm_ctx* c, int keep) {
+  const int N1 = c->chi_env * c->Dl;
+  const DT cp = c->cp;
+  TRY(ensure_rocblas(c));
+  // P_i = Ct_i Ct_(i+1) in S1[i]
+  {
+    GemmBatch g = gemm_rowmajor(4, N1, N1, N1, N1, N1, N1);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = c->Ct[i];
+      g.B[i] = c->Ct[(i + 1) % 4];
+      g.C[i] = c->S1[i];
+    }
+    TRY(run_gemm(c, PC_FULLSVD, g, cp, cp, DT::F64));
+  }
+  for (int b = 0; b < 4; ++b) {
+    const double* L = c->S1[md(b - 1)];
+    const double* R = c->S1[md(b + 1)];
+    double* M = c->S2[0];
+    double* Ut = c->S2[1];   // receives V^T of M (row-major)
+    double* Uv = c->S2[2];   // receives U of M (row-major)
+    {
+      GemmBatch g = gemm_rowmajor(1, N1, N1, N1, N1, N1, N1);
+      g.A[0] = L;
+      g.B[0] = R;
+      g.C[0] = M;
+      TRY(run_gemm(c, PC_FULLSVD, g, DT::F64, DT::F64, DT::F64));
+    }
+    {
+      ProfScope ps(c, PC_FULLSVD);
+      // rocSOLVER is column-major: it sees M^T = (V) S (U^T)
+      rocblas_status st = rocsolver_dgesvd(c->rb, rocblas_svect_all, rocblas_svect_all, N1, N1, M,
+                                           N1, c->fs_s, Ut, N1, Uv, N1, c->fs_E,
+                                           rocblas_outofplace, c->fs_info);
+      if (st != rocblas_status_success)
+        return fail(c, CTM_E_DEVICE, "rocsolver_dgesvd failed: " + std::to_string((int)st));
+    }
+    SignArgs sa{};
+    sa.N = N1;
+    sa.k = keep;
+    sa.ld = N1;
+    sa.Y[0] = Uv;
+    sa.sg[0] = c->fs_sg;
+    TRY(elem_col_sign(sa, 1, c->st));
+    TRY(elem_proj_prep_full(Uv, Ut, c->fs_s, c->fs_sg, N1, keep, c->cfg.pinv_rtol, c->fs_Us,
+                            c->fs_Vs, c->scal + 9 + b, c->st));
+    // P_l = R Vs ; P_r^T = L^T Us
+    GemmBatch g = gemm_rowmajor(2, N1, keep, N1, N1, keep, keep);
+    g.A[0] = R;
+    g.B[0] = c->fs_Vs;
+    g.C[0] = c->Pl[b];
+    g.A[1] = L;
+    g.transA[1] = 1;
+    g.B[1] = c->fs_Us;
+    g.C[1] = c->Prt[b];
+    TRY(run_gemm(c, PC_FULLSVD, g, DT::F64, DT::F64, DT::F64));
+  }
+  return 0;
+}
+
+// Step 3: C_i' = P_r^(i-1) Ct_i P_l^(i);  T_j' = P_r^(j) (T_j a) P_l^(j).
+int renormalize(ctm_ctx* c, int keep) {
+  const int x = c->chi_env, Dl = c->Dl, N1 = x * Dl, xp = keep;
+  const int nxt = 1 - c->cur;
+  double* const* T = c->T[c->cur];
+  {
+    GemmBatch g = gemm_rowmajor(4, N1, xp, N1, N1, xp, xp);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = c->Ct[i];
+      g.B[i] = c->Pl[i];
+      g.C[i] = c->Zc[i];
+    }
+    TRY(run_gemm(c, PC_RENORM, g, c->cp, DT::F64, DT::F64));
+  }
+  {
+    GemmBatch g = gemm_rowmajor(4, xp, xp, N1, xp, xp, xp);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = c->Prt[md(i - 1)];
+      g.transA[i] = 1;
+      g.B[i] = c->Zc[i];
+      g.C[i] = c->C[nxt][i];
+    }
+    TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
+  }
+  // Z1[(b, g'), (u, r)] = sum_g T_j[(b, u), g] P_l[(g, r), g']   (batched over r)
+  {
+    GemmBatch g = gemm_rowmajor(4, x * Dl, xp, x, x, (long)Dl * xp, 0);
+    g.cdiv_m = Dl;
+    g.cs_m1 = (long)xp * Dl * Dl;
+    g.cs_m0 = Dl;
+    g.cdiv_n = 1 << 30;
+    g.cs_n1 = 0;
+    g.cs_n0 = (long)Dl * Dl;
+    g.nbatch = Dl;
+    g.a_bs = 0;
+    g.b_bs = xp;
+    g.c_bs = 1;
+    for (int j = 0; j < 4; ++j) {
+      g.A[j] = T[j];
+      g.B[j] = c->Pl[j];
+      g.C[j] = c->S1[j];
+    }
+    TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
+  }
+  // Z2[(b, l), d, g'] = Z1[(b, g'), (u, r)] ap_(j+1)[(u, r), (l, d)]
+  {
+    GemmBatch g = gemm_rowmajor(4, x * xp, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
+    g.cdiv_m = xp;
+    g.cs_m1 = (long)Dl * Dl * xp;
+    g.cs_m0 = 1;
+    g.cdiv_n = Dl;
+    g.cs_n1 = (long)Dl * xp;
+    g.cs_n0 = xp;
+    for (int j = 0; j < 4; ++j) {
+      g.A[j] = c->S1[j];
+      g.B[j] = c->ap[(j + 1) % 4];
+      g.C[j] = c->S2[j];
+    }
+    TRY(run_gemm(c, PC_RENORM, g, DT::F64, c->cp, DT::F64));
+  }
+  // T'[b', d, g'] = sum_(b,l) P_r^T[(b, l), b'] Z2[(b, l), d, g']   (batched over d)
+  {
+    GemmBatch g = gemm_rowmajor(4, xp, xp, x * Dl, xp, (long)Dl * xp, (long)Dl * xp);
+    g.nbatch = Dl;
+    g.a_bs = 0;
+    g.b_bs = xp;
+    g.c_bs = xp;
+    for (int j = 0; j < 4; ++j) {
+      g.A[j] = c->Prt[j];
+      g.transA[j] = 1;
+      g.B[j] = c->S2[j];
+      g.C[j] = c->T[nxt][j];
+    }
+    TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
+  }
+  return 0;
+}
+
+// Normalises the 8 tensors of buffer `buf` (environment dimension x) and
+// raises the device flag on a zero or non-finite norm.
+int normalize_env(ctm_ctx* c, int buf, int x) {
+  NormArgs na{};
+  for (int i = 0; i < 4; ++i) {
+    na.x[i] = c->C[buf][i];
+    na.n[i] = (long)x * x;
+    na.x[4 + i] = c->T[buf][i];
+    na.n[4 + i] = (long)x * c->Dl * x;
+  }
+  na.out = c->scal;
+  na.bad = c->bad;
+  return elem_normalize(na, 8, c->st);
+}
+
+// Corner spectra of buffer `buf` and delta against the committed spectra.
+int spectra(ctm_ctx* c, int buf, int x) {
+  {
+    ProfScope ps(c, PC_SVD);
+    const double* A[4] = {c->C[buf][0], c->C[buf][1], c->C[buf][2], c->C[buf][3]};
+    TRY(launch_svd(4, A, nullptr, c->csv, nullptr, x, c->svd_ws, c->st));
+  }
+  SpecArgs sp{};
+  for (int i = 0; i < 4; ++i) sp.s[i] = c->csv[i];
+  sp.old_spec = c->spec[c->spec_cur];
+  sp.new_spec = c->spec[1 - c->spec_cur];
+  sp.delta = c->scal + 8;
+  sp.x = std::min(x, c->chi);
+  sp.chi = c->chi;
+  return elem_spectra_delta(sp, c->st);
+}
+
+int do_move(ctm_ctx* c, ctm_move_info* info) {
+  const int x = c->chi_env, N1 = x * c->Dl;
+  int mode, keep;
+  if (N1 <= c->chi) {
+    mode = 0;
+    keep = N1;
+  } else if (x != c->chi || c->cfg.proj == CTM_PROJ_FULLSVD) {
+    mode = 1;
+    keep = c->chi;
+  } else {
+    mode = 2;
+    keep = c->chi;
+  }
+  CTM_HIP_TRY(hipMemsetAsync(c->bad, 0, sizeof(int), c->st));
+  TRY(build_corners(c));
+  if (mode == 0) {
+    for (int b = 0; b < 4; ++b) {
+      TRY(elem_identity(c->Pl[b], N1, N1, c->st));
+      TRY(elem_identity(c->Prt[b], N1, N1, c->st));
+    }
+  } else if (mode == 1) {
+    TRY(full_projectors(c, keep));
+  } else {
+    TRY(si_projectors(c, keep));
+    ++c->si_moves;
+  }
+  TRY(renormalize(c, keep));
+  const int nxt = 1 - c->cur;
+  TRY(normalize_env(c, nxt, keep));
+  TRY(spectra(c, nxt, keep));
+  double host[16];
+  int bad = 0;
+  CTM_HIP_TRY(hipMemcpyAsync(host, c->scal, sizeof(host), hipMemcpyDeviceToHost, c->st));
+  CTM_HIP_TRY(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  CTM_HIP_TRY(hipStreamSynchronize(c->st));
+  if (bad || !std::isfinite(host[8]))
+    return fail(c, CTM_E_NUMERIC, "move produced a zero or non-finite norm; environment kept");
+  c->cur = nxt;
+  c->chi_env = keep;
+  c->spec_cur = 1 - c->spec_cur;
+  ++c->moves;
+  if (info) {
+    info->delta = host[8];
+    info->mode = mode;
+    info->chi_env = keep;
+    double gap = -1.0;
+    if (mode != 0) {
+      gap = 1e300;
+      for (int b = 0; b < 4; ++b) gap = std::min(gap, host[9 + b]);
+    }
+    info->gap = gap;
+  }
+  return CTM_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// observables (iPEPS section: norm network and operator insertion)
+// ---------------------------------------------------------------------------
+GemmBatch gb1(int M, int N, int K, const void* A, long lda, int transA, const void* B, long ldb,
+              void* C, long ldc) {
+  GemmBatch g = gemm_rowmajor(1, M, N, K, lda, ldb, ldc);
+  g.A[0] = A;
+  g.transA[0] = transA;
+  g.B[0] = B;
+  g.C[0] = C;
+  return g;
+}
+
+void set_map(GemmBatch& g, int mdiv, long m1, long m0, int ndiv, long n1, long n0) {
+  g.cdiv_m = mdiv; g.cs_m1 = m1; g.cs_m0 = m0;
+  g.cdiv_n = ndiv; g.cs_n1 = n1; g.cs_n0 = n0;
+}
+
+int g64(ctm_ctx* c, const GemmBatch& g) { return run_gemm(c, PC_MISC, g, DT::F64, DT::F64, DT::F64); }
+
+// Permuted f64 copy of a rank-4 site tensor for absorption slot `slot`
+// (0: K=(l,u) N=(d,r); 1: K=(u,r) N=(l,d); 2: K=(r,d) N=(u,l)).
+int perm_site(ctm_ctx* c, const double* src, double* dst, int slot) {
+  const long Dl = c->Dl;
+  const long su = Dl * Dl * Dl, sl = Dl * Dl, sd = Dl, sr = 1;
+  const long perm[3][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}};
+  return elem_permute4(src, dst, DT::F64, (int)Dl, perm[slot][0], perm[slot][1], perm[slot][2],
+                       perm[slot][3], c->st);
+}
+
+// Z11 with the site tensor xp (slot-0 permuted, f64) into *out.
+int z11(ctm_ctx* c, const double* xp, double* out) {
+  const int x = c->chi_env, Dl = c->Dl;
+  double* const* C = c->C[c->cur];
+  double* const* T = c->T[c->cur];
+  TRY(g64(c, gb1(x, Dl * x, x, C[0], x, 0, T[0], (long)Dl * x, c->CT[0], (long)Dl * x)));
+  TRY(g64(c, gb1(x * Dl, x, x, c->CT[0], x, 0, C[1], x, c->CT[1], x)));          // top[(a,u),h]
+  GemmBatch g = gb1(x * Dl, Dl * x, x, T[3], x, 0, c->CT[1], (long)Dl * x, c->S1[0], 0);
+  set_map(g, Dl, (long)x * Dl * Dl, Dl, x, 1, (long)Dl * Dl);                        // x1[(t,h),(l,u)]
+  TRY(g64(c, g));
+  g = gb1(x * x, Dl * Dl, Dl * Dl, c->S1[0], (long)Dl * Dl, 0, xp, (long)Dl * Dl, c->S2[0], 0);
+  set_map(g, x, (long)Dl * Dl * x, Dl, Dl, (long)x * Dl, 1);                         // y[(t,d),(h,r)]
+  TRY(g64(c, g));
+  TRY(g64(c, gb1(x * Dl, x, x * Dl, c->S2[0], (long)x * Dl, 0, T[1], x, c->CT[2], x)));  // z[(t,d),e]
+  TRY(g64(c, gb1(x, Dl * x, x, C[2], x, 0, T[2], (long)Dl * x, c->CT[3], (long)Dl * x)));
+  TRY(g64(c, gb1(x * Dl, x, x, c->CT[3], x, 0, C[3], x, c->Zc[0], x)));              // bot[(e,d),t]
+  return elem_dot_rev(c->CT[2], c->Zc[0], x, Dl, out, c->st);
+}
+
+// Z00, Z10, Z01 into out[0..2].
+int z_rest(ctm_ctx* c, double* out) {
+  const int x = c->chi_env, Dl = c->Dl;
+  double* const* C = c->C[c->cur];
+  double* const* T = c->T[c->cur];
+  TRY(g64(c, gb1(x, x, x, C[0], x, 0, C[1], x, c->Zc[1], x)));
+  TRY(g64(c, gb1(x, x, x, c->Zc[1], x, 0, C[2], x, c->Zc[2], x)));
+  TRY(g64(c, gb1(x, x, x, c->Zc[2], x, 0, C[3], x, c->Zc[3], x)));
+  TRY(elem_trace(c->Zc[3], x, out, c->st));
+  // Z10: top[(a,u),h] C3[h,z] . T3[(z,u),n] C4[n,a]
+  TRY(g64(c, gb1(x, Dl * x, x, C[0], x, 0, T[0], (long)Dl * x, c->CT[0], (long)Dl * x)));
+  TRY(g64(c, gb1(x * Dl, x, x, c->CT[0], x, 0, C[1], x, c->CT[1], x)));
+  TRY(g64(c, gb1(x * Dl, x, x, c->CT[1], x, 0, C[2], x, c->Zc[1], x)));
+  TRY(g64(c, gb1(x * Dl, x, x, T[2], x, 0, C[3], x, c->Zc[2], x)));
+  TRY(elem_dot_rev(c->Zc[1], c->Zc[2], x, Dl, out + 1, c->st));
+  // Z01: C1[a,b] (C2 T2 C3)[b,(r,z)] . (C4 T4)[z,(r,a)]
+  TRY(g64(c, gb1(x, Dl * x, x, C[1], x, 0, T[1], (long)Dl * x, c->CT[0], (long)Dl * x)));
+  TRY(g64(c, gb1(x * Dl, x, x, c->CT[0], x, 0, C[2], x, c->CT[1], x)));
+  TRY(g64(c, gb1(x, Dl * x, x, C[3], x, 0, T[3], (long)Dl * x, c->CT[2], (long)Dl * x)));
+  TRY(g64(c, gb1(x, Dl * x, x, C[0], x, 0, c->CT[1], (long)Dl * x, c->CT[3], (long)Dl * x)));
+  return elem_dot_rev(c->CT[3], c->CT[2], x, Dl, out + 2, c->st);
+}
+
+// Two-site network values E[i*n2 + j] for site-1 tensors s1[i] (slot 0 layout)
+// and site-2 tensors s2[j] (slot 1 layout for horizontal, slot 2 for vertical).
+int two_site(ctm_ctx* c, bool horizontal, const double* const* s1, int n1,
+             const double* const* s2, int n2, double* E) {
+  const int x = c->chi_env, Dl = c->Dl;
+  const long L = (long)x * Dl * x;
+  double* const* C = c->C[c->cur];
+  double* const* T = c->T[c->cur];
+  if (horizontal) {
+    // left'[(j,l),b] = C4[j,k] T4[k,(l,a)] C1[a,b]
+    TRY(g64(c, gb1(x, Dl * x, x, C[3], x, 0, T[3], (long)Dl * x, c->CT[0], (long)Dl * x)));
+    TRY(g64(c, gb1(x * Dl, x, x, c->CT[0], x, 0, C[0], x, c->CT[1], x)));
+    GemmBatch g = gb1(x * Dl, Dl * x, x, c->CT[1], x, 0, T[0], (long)Dl * x, c->S1[0], 0);
+    set_map(g, Dl, (long)x * Dl * Dl, Dl, x, 1, (long)Dl * Dl);                    // y1'[(j,g),(l,u)]
+    TRY(g64(c, g));
+    for (int i = 0; i < n1; ++i) {
+      g = gb1(x * x, Dl * Dl, Dl * Dl, c->S1[0], (long)Dl * Dl, 0, s1[i], (long)Dl * Dl, c->S2[0], 0);
+      set_map(g, x, (long)x * Dl, Dl, Dl, (long)x * x * Dl, 1);                    // y2[(d,j),(g,m)]
+      TRY(g64(c, g));
+      g = gb1(x, x * Dl, x * Dl, T[2], (long)Dl * x, 0, c->S2[0], (long)x * Dl, c->obs_y + i * L, 0);
+      set_map(g, 1 << 30, 0, 1, Dl, (long)Dl * x, x);                               // y3[g,m,i]
+      TRY(g64(c, g));
+    }
+    // right[(h,w),f] = C2[h,c] T2[c,(w,e)] C3[e,f]
+    TRY(g64(c, gb1(x, Dl * x, x, C[1], x, 0, T[1], (long)Dl * x, c->CT[2], (long)Dl * x)));
+    TRY(g64(c, gb1(x * Dl, x, x, c->CT[2], x, 0, C[2], x, c->CT[3], x)));
+    g = gb1(x * Dl, Dl * x, x, T[0], x, 0, c->CT[3], (long)Dl * x, c->S1[1], 0);
+    set_map(g, Dl, (long)x * Dl * Dl, Dl, x, 1, (long)Dl * Dl);                    // w1'[(g,f),(v,w)]
+    TRY(g64(c, g));
+    for (int j = 0; j < n2; ++j) {
+      g = gb1(x * x, Dl * Dl, Dl * Dl, c->S1[1], (long)Dl * Dl, 0, s2[j], (long)Dl * Dl, c->S2[1], 0);
+      set_map(g, x, (long)Dl * Dl * x, Dl, Dl, (long)x * Dl, 1);                    // w2[(g,m),(f,y)]
+      TRY(g64(c, g));
+      TRY(g64(c, gb1(x * Dl, x, x * Dl, c->S2[1], (long)x * Dl, 0, T[2], x, c->obs_w + j * L, x)));
+    }
+    return elem_pair_dot(c->obs_y, c->obs_w, L, n1, n2, x, Dl, 0, E, c->st);
+  }
+  // vertical: top[(a,u),h]
+  TRY(g64(c, gb1(x, Dl * x, x, C[0], x, 0, T[0], (long)Dl * x, c->CT[0], (long)Dl * x)));
+  TRY(g64(c, gb1(x * Dl, x, x, c->CT[0], x, 0, C[1], x, c->CT[1], x)));
+  GemmBatch g = gb1(x * Dl, Dl * x, x, T[3], x, 0, c->CT[1], (long)Dl * x, c->S1[0], 0);
+  set_map(g, Dl, (long)x * Dl * Dl, Dl, x, 1, (long)Dl * Dl);                      // p1'[(n,h),(l,u)]
+  TRY(g64(c, g));
+  for (int i = 0; i < n1; ++i) {
+    g = gb1(x * x, Dl * Dl, Dl * Dl, c->S1[0], (long)Dl * Dl, 0, s1[i], (long)Dl * Dl, c->S2[0], 0);
+    set_map(g, x, (long)Dl * Dl * x, Dl, Dl, (long)x * Dl, 1);                      // p2[(n,x),(h,r)]
+    TRY(g64(c, g));
+    TRY(g64(c, gb1(x * Dl, x, x * Dl, c->S2[0], (long)x * Dl, 0, T[1], x, c->obs_y + i * L, x)));
+  }
+  // bot[(i,w),m] = C3[i,j] T3[j,(w,k)] C4[k,m]
+  TRY(g64(c, gb1(x, Dl * x, x, C[2], x, 0, T[2], (long)Dl * x, c->CT[2], (long)Dl * x)));
+  TRY(g64(c, gb1(x * Dl, x, x, c->CT[2], x, 0, C[3], x, c->CT[3], x)));
+  g = gb1(x * Dl, Dl * x, x, T[1], x, 0, c->CT[3], (long)Dl * x, c->S1[1], 0);
+  set_map(g, Dl, (long)x * Dl * Dl, Dl, x, 1, (long)Dl * Dl);                      // q1'[(c,m),(s,w)]
+  TRY(g64(c, g));
+  for (int j = 0; j < n2; ++j) {
+    g = gb1(x * x, Dl * Dl, Dl * Dl, c->S1[1], (long)Dl * Dl, 0, s2[j], (long)Dl * Dl, c->S2[1], 0);
+    set_map(g, x, (long)Dl * Dl * x, Dl, Dl, (long)x * Dl, 1);                      // q2[(c,x),(m,p)]
+    TRY(g64(c, g));
+    TRY(g64(c, gb1(x * Dl, x, x * Dl, c->S2[1], (long)x * Dl, 0, T[3], x, c->obs_w + j * L, x)));
+  }
+  return elem_pair_dot(c->obs_y, c->obs_w, L, n1, n2, x, Dl, 1, E, c->st);
+}
+
+int observable(ctm_ctx* c, int kind, const double* op_host, double* out_host) {
+  const int Dl = c->Dl, d = c->d;
+  const size_t Dl4 = (size_t)Dl * Dl * Dl * Dl;
+  double* sc = c->scal + 16;   // device scalars
+  double host[32] = {0};
+  if (kind == CTM_OBS_NORM) {
+    TRY(perm_site(c, c->a, c->imp[2], 0));
+    TRY(z11(c, c->imp[2], sc));
+    TRY(z_rest(c, sc + 1));
+    TRY(elem_kappa(sc, sc + 5, c->st));
+    CTM_HIP_TRY(hipMemcpyAsync(host, sc, 6 * 8, hipMemcpyDeviceToHost, c->st));
+    CTM_HIP_TRY(hipStreamSynchronize(c->st));
+    out_host[0] = host[5];
+    for (int i = 0; i < 4; ++i) out_host[1 + i] = host[i];
+    return 0;
+  }
+  if (!op_host) return fail(c, CTM_E_ARG, "observable needs an operator");
+  if (kind == CTM_OBS_ONESITE) {
+    if (d > 0) {
+      CTM_HIP_TRY(hipMemcpy(c->obs_op, op_host, (size_t)d * d * 8, hipMemcpyHostToDevice));
+      TRY(elem_double_layer(c->A_site, c->obs_op, c->imp[0], d, c->D, c->st));
+    } else {
+      CTM_HIP_TRY(hipMemcpy(c->imp[0], op_host, Dl4 * 8, hipMemcpyHostToDevice));
+    }
+    TRY(perm_site(c, c->imp[0], c->imp[1], 0));
+    TRY(perm_site(c, c->a, c->imp[2], 0));
+    TRY(z11(c, c->imp[1], sc));
+    TRY(z11(c, c->imp[2], sc + 1));
+    TRY(elem_ratio(sc, sc + 1, sc + 2, c->st));
+    CTM_HIP_TRY(hipMemcpyAsync(host, sc, 3 * 8, hipMemcpyDeviceToHost, c->st));
+    CTM_HIP_TRY(hipStreamSynchronize(c->st));
+    out_host[0] = host[2];
+    return 0;
+  }
+  if (kind != CTM_OBS_BOND_H && kind != CTM_OBS_BOND_V)
+    return fail(c, CTM_E_ARG, "unknown observable kind");
+  const bool hor = kind == CTM_OBS_BOND_H;
+  const int slot2 = hor ? 1 : 2;
+  if (d == 0) {
+    // two impurities (x1 then x2) against the plain network
+    CTM_HIP_TRY(hipMemcpy(c->imp[0], op_host, Dl4 * 8, hipMemcpyHostToDevice));
+    TRY(perm_site(c, c->imp[0], c->imp[1], 0));
+    CTM_HIP_TRY(hipMemcpy(c->imp[0], op_host + Dl4, Dl4 * 8, hipMemcpyHostToDevice));
+    TRY(perm_site(c, c->imp[0], c->imp[2], slot2));
+    const double* a1[1] = {c->imp[1]};
+    const double* a2[1] = {c->imp[2]};
+    TRY(two_site(c, hor, a1, 1, a2, 1, sc));
+    // plain network: permute a into both slots (imp[0], imp[1])
+    TRY(perm_site(c, c->a, c->imp[0], 0));
+    TRY(perm_site(c, c->a, c->imp[1], slot2));
+    const double* b1[1] = {c->imp[0]};
+    const double* b2[1] = {c->imp[1]};
+    TRY(two_site(c, hor, b1, 1, b2, 1, sc + 1));
+    TRY(elem_ratio(sc, sc + 1, sc + 2, c->st));
+    CTM_HIP_TRY(hipMemcpyAsync(host, sc, 3 * 8, hipMemcpyDeviceToHost, c->st));
+    CTM_HIP_TRY(hipStreamSynchronize(c->st));
+    out_host[0] = host[2];
+    return 0;
+  }
+  // open physical legs: one impurity per (ket s, bra t); d^2 x d^2 values E
+  const int d2 = d * d;
+  if (d2 > 9) return fail(c, CTM_E_SHAPE, "bond observables support d <= 3");
+  std::vector<const double*> s1(d2), s2(d2);
+  // site-1 tensors in imps[0], site-2 tensors in imps[1] (each Dl^4, d^2 of them)
+  for (int st = 0; st < d2; ++st) {
+    TRY(elem_double_layer(c->A_site, nullptr, c->imp[0], d, c->D, c->st, st / d, st % d));
+    double* p1 = c->imps[0] + st * Dl4;
+    double* p2 = c->imps[1] + st * Dl4;
+    TRY(perm_site(c, c->imp[0], p1, 0));
+    TRY(perm_site(c, c->imp[0], p2, slot2));
+    s1[st] = p1;
+    s2[st] = p2;
+  }
+  double* E = c->scal + 64;
+  TRY(two_site(c, hor, s1.data(), d2, s2.data(), d2, E));
+  CTM_HIP_TRY(hipMemcpy(c->obs_op, op_host, (size_t)d2 * d2 * 8, hipMemcpyHostToDevice));
+  TRY(elem_bond_value(E, c->obs_op, d, sc, c->st));
+  CTM_HIP_TRY(hipMemcpyAsync(host, sc, 8, hipMemcpyDeviceToHost, c->st));
+  CTM_HIP_TRY(hipStreamSynchronize(c->st));
+  out_host[0] = host[0];
+  return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* ctm_status_str(ctm_status s) {
+  switch (s) {
+    case CTM_OK: return "ok";
+    case CTM_E_ARG: return "invalid argument";
+    case CTM_E_SHAPE: return "invalid shape";
+    case CTM_E_NOMEM: return "out of memory";
+    case CTM_E_DEVICE: return "device error";
+    case CTM_E_NUMERIC: return "numerical failure";
+    case CTM_E_NOT_CONVERGED: return "not converged";
+    case CTM_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* ctm_last_error(const ctm_ctx* ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_err.c_str();
+}
+
+ctm_status ctm_workspace_bytes(const ctm_config* cfg, size_t* bytes) {
+  int r = validate(cfg);
+  if (r) return (ctm_status)r;
+  if (!bytes) return (ctm_status)fail(nullptr, CTM_E_ARG, "null bytes");
+  ctm_ctx tmp;
+  set_dims(&tmp, cfg);
+  *bytes = carve(&tmp, nullptr);
+  return CTM_OK;
+}
+
+ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev,
+                    const double* boundary_dev, void* workspace, size_t ws_bytes, void* stream) {
+  if (!out) return (ctm_status)fail(nullptr, CTM_E_ARG, "null out");
+  *out = nullptr;
+  int r = validate(cfg);
+  if (r) return (ctm_status)r;
+  if (!site_dev) return (ctm_status)fail(nullptr, CTM_E_ARG, "null site tensor");
+  if (cfg->d == 0 && !boundary_dev)
+    return (ctm_status)fail(nullptr, CTM_E_ARG, "d == 0 needs a boundary vector");
+  ctm_ctx* c = new ctm_ctx();
+  set_dims(c, cfg);
+  c->st = (hipStream_t)stream;
+  const size_t need = carve(c, nullptr);
+  if (workspace) {
+    if (ws_bytes < need) {
+      delete c;
+      return (ctm_status)fail(nullptr, CTM_E_NOMEM, "workspace smaller than ctm_workspace_bytes");
+    }
+    c->ws = workspace;
+  } else {
+    if (hipMalloc(&c->ws, need) != hipSuccess) {
+      delete c;
+      return (ctm_status)fail(nullptr, CTM_E_NOMEM, "hipMalloc of the workspace failed");
+    }
+    c->own_ws = true;
+  }
+  c->ws_bytes = need;
+  carve(c, (char*)c->ws);
+  auto bail = [&](int code) {
+    std::string m = c->err.empty() ? g_err : c->err;
+    ctm_destroy(c);
+    g_err = m;
+    return (ctm_status)code;
+  };
+  const int Dl = c->Dl;
+  const size_t Dl4 = (size_t)Dl * Dl * Dl * Dl;
+  int rc = 0;
+  if (c->d > 0) {
+    const size_t nA = (size_t)c->d * c->D * c->D * c->D * c->D;
+    if (hipMemcpyAsync(c->A_site, site_dev, nA * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+      return bail(fail(c, CTM_E_DEVICE, "copy of the site tensor failed"));
+    rc = elem_double_layer(c->A_site, nullptr, c->a, c->d, c->D, c->st);
+  } else {
+    if (hipMemcpyAsync(c->a, site_dev, Dl4 * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+      return bail(fail(c, CTM_E_DEVICE, "copy of the site tensor failed"));
+  }
+  if (rc) return bail(rc);
+  if (boundary_dev) {
+    if (hipMemcpyAsync(c->e, boundary_dev, Dl * 8, hipMemcpyDeviceToDevice, c->st) != hipSuccess)
+      return bail(fail(c, CTM_E_DEVICE, "copy of the boundary vector failed"));
+  } else {
+    std::vector<double> e(Dl, 0.0);
+    for (int i = 0; i < c->D; ++i) e[i * c->D + i] = 1.0;
+    if (hipMemcpy(c->e, e.data(), Dl * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(c, CTM_E_DEVICE, "copy of the boundary vector failed"));
+  }
+  // leg permutations of a for the four corner absorptions (a[u,l,d,r]):
+  // corner 0: (l,u),(d,r); 1: (u,r),(l,d); 2: (r,d),(u,l); 3: (d,l),(r,u)
+  const long su = (long)Dl * Dl * Dl, sl = (long)Dl * Dl, sd = Dl, sr = 1;
+  const long perm[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
+  for (int i = 0; i < 4 && !rc; ++i)
+    rc = elem_permute4(c->a, c->ap[i], c->cp, Dl, perm[i][0], perm[i][1], perm[i][2], perm[i][3],
+                       c->st);
+  if (rc) return bail(rc);
+  rc = elem_init_env(c->a, c->e, Dl, c->C[0], c->T[0], c->st);
+  if (rc) return bail(rc);
+  c->cur = 0;
+  c->chi_env = Dl;
+  if (hipMemsetAsync(c->bad, 0, sizeof(int), c->st) != hipSuccess ||
+      hipMemsetAsync(c->spec[0], 0, 4 * c->chi * 8, c->st) != hipSuccess ||
+      hipMemsetAsync(c->spec[1], 0, 4 * c->chi * 8, c->st) != hipSuccess)
+    return bail(fail(c, CTM_E_DEVICE, "memset failed"));
+  rc = normalize_env(c, 0, Dl);
+  if (!rc) rc = spectra(c, 0, Dl);
+  if (rc) return bail(rc);
+  c->spec_cur = 1;
+  int bad = 0;
+  if (hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess)
+    return bail(fail(c, CTM_E_DEVICE, "synchronisation failed"));
+  if (bad) return bail(fail(c, CTM_E_NUMERIC, "initial environment has a zero or non-finite norm"));
+  *out = c;
+  return CTM_OK;
+}
+
+void ctm_destroy(ctm_ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  else (void)hipDeviceSynchronize();
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->rb) rocblas_destroy_handle(c->rb);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  delete c;
+}
+
+ctm_status ctm_set_isometries(ctm_ctx* c, const double* X_dev, const double* Yt_dev) {
+  if (!c || !X_dev || !Yt_dev) return (ctm_status)fail(c, CTM_E_ARG, "null argument");
+  const size_t nk = (size_t)c->N * c->k;
+  for (int b = 0; b < 4; ++b) {
+    if (hipMemcpyAsync(c->X0[b], X_dev + b * nk, nk * 8, hipMemcpyDeviceToDevice, c->st) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->Yt0[b], Yt_dev + b * nk, nk * 8, hipMemcpyDeviceToDevice, c->st) !=
+            hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy of the isometries failed");
+  }
+  c->iso_pending = true;
+  c->si_ready = false;
+  return CTM_OK;
+}
+
+ctm_status ctm_move(ctm_ctx* c, ctm_move_info* info) {
+  if (!c) return (ctm_status)fail(nullptr, CTM_E_ARG, "null context");
+  c->err.clear();
+  g_err.clear();
+  return (ctm_status)do_move(c, info);
+}
+
+ctm_status ctm_converge(ctm_ctx* c, double tol, int max_moves, int* moves_done,
+                        double* last_delta) {
+  if (!c || max_moves < 0) return (ctm_status)fail(c, CTM_E_ARG, "invalid argument");
+  int n = 0;
+  double delta = INFINITY;
+  ctm_status st = CTM_E_NOT_CONVERGED;
+  while (n < max_moves) {
+    ctm_move_info info;
+    ctm_status r = ctm_move(c, &info);
+    if (r != CTM_OK) {
+      st = r;
+      break;
+    }
+    ++n;
+    delta = info.delta;
+    if (info.mode == 2 || info.mode == 1) {
+      if (delta < tol && c->chi_env == c->chi) {
+        st = CTM_OK;
+        break;
+      }
+    }
+  }
+  if (moves_done) *moves_done = n;
+  if (last_delta) *last_delta = delta;
+  return st;
+}
+
+ctm_status ctm_state_size(const ctm_ctx* c, size_t* n) {
+  if (!c || !n) return (ctm_status)fail(nullptr, CTM_E_ARG, "null argument");
+  const size_t chi = c->chi, Dl = c->Dl, N = c->N, k = c->k;
+  *n = 4 * chi * chi + 4 * chi * Dl * chi + 8 * N * k + 2;
+  return CTM_OK;
+}
+
+ctm_status ctm_get_state(ctm_ctx* c, double* host, size_t n) {
+  size_t need;
+  if (ctm_state_size(c, &need) != CTM_OK || !host || n < need)
+    return (ctm_status)fail(c, CTM_E_ARG, "state buffer too small");
+  const size_t chi = c->chi, Dl = c->Dl, N = c->N, k = c->k;
+  const size_t x = c->chi_env;
+  std::fill(host, host + need, 0.0);
+  double* p = host;
+  for (int i = 0; i < 4; ++i, p += chi * chi)
+    if (hipMemcpyAsync(p, c->C[c->cur][i], x * x * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  for (int i = 0; i < 4; ++i, p += chi * Dl * chi)
+    if (hipMemcpyAsync(p, c->T[c->cur][i], x * Dl * x * 8, hipMemcpyDeviceToHost, c->st) !=
+        hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  for (int i = 0; i < 4; ++i, p += N * k)
+    if (hipMemcpyAsync(p, c->X[i], N * k * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  for (int i = 0; i < 4; ++i, p += N * k)
+    if (hipMemcpyAsync(p, c->Yt[i], N * k * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  if (hipStreamSynchronize(c->st) != hipSuccess)
+    return (ctm_status)fail(c, CTM_E_DEVICE, "synchronisation failed");
+  p[0] = (double)c->chi_env;
+  p[1] = (double)c->si_moves;
+  return CTM_OK;
+}
+
+ctm_status ctm_set_state(ctm_ctx* c, const double* host, size_t n) {
+  size_t need;
+  if (ctm_state_size(c, &need) != CTM_OK || !host || n < need)
+    return (ctm_status)fail(c, CTM_E_ARG, "state buffer too small");
+  const size_t chi = c->chi, Dl = c->Dl, N = c->N, k = c->k;
+  const double* p = host + 4 * chi * chi + 4 * chi * Dl * chi + 8 * N * k;
+  const int x = (int)p[0];
+  if (x < 1 || x > (int)chi) return (ctm_status)fail(c, CTM_E_SHAPE, "chi_env out of range");
+  p = host;
+  for (int i = 0; i < 4; ++i, p += chi * chi)
+    if (hipMemcpy(c->C[c->cur][i], p, (size_t)x * x * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  for (int i = 0; i < 4; ++i, p += chi * Dl * chi)
+    if (hipMemcpy(c->T[c->cur][i], p, (size_t)x * Dl * x * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  for (int i = 0; i < 4; ++i, p += N * k)
+    if (hipMemcpy(c->X[i], p, N * k * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  for (int i = 0; i < 4; ++i, p += N * k)
+    if (hipMemcpy(c->Yt[i], p, N * k * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  c->chi_env = x;
+  c->si_moves = (long)p[1];
+  c->si_ready = (x == (int)chi);
+  c->iso_pending = false;
+  // spectra of the restored corners become the reference of the next delta
+  const int rs = spectra(c, c->cur, x);
+  if (rs) return (ctm_status)(rs == 1 ? CTM_E_ARG : rs);
+  c->spec_cur = 1 - c->spec_cur;
+  if (hipStreamSynchronize(c->st) != hipSuccess)
+    return (ctm_status)fail(c, CTM_E_DEVICE, "synchronisation failed");
+  return CTM_OK;
+}
+
+
+ctm_status ctm_observable(ctm_ctx* c, int kind, const double* op_host, double* out_host) {
+  if (!c || !out_host) return (ctm_status)fail(c, CTM_E_ARG, "null argument");
+  c->err.clear();
+  const bool prof = c->prof;
+  c->prof = false;
+  const int r = observable(c, kind, op_host, out_host);
+  c->prof = prof;
+  return (ctm_status)r;
+}
+
+ctm_status ctm_profile(ctm_ctx* c, int enable) {
+  if (!c) return (ctm_status)fail(nullptr, CTM_E_ARG, "null context");
+  if (hipStreamSynchronize(c->st) != hipSuccess)
+    return (ctm_status)fail(c, CTM_E_DEVICE, "synchronisation failed");
+  c->recs.clear();
+  c->ev_next = 0;
+  c->prof = enable != 0;
+  return CTM_OK;
+}
+
+ctm_status ctm_profile_read(ctm_ctx* c, ctm_prof_entry* out, int max_entries, int* n) {
+  if (!c || !out || !n) return (ctm_status)fail(c, CTM_E_ARG, "null argument");
+  if (hipStreamSynchronize(c->st) != hipSuccess)
+    return (ctm_status)fail(c, CTM_E_DEVICE, "synchronisation failed");
+  int cnt = 0;
+  for (int cls = 0; cls < PC_N && cnt < max_entries; ++cls) {
+    ctm_prof_entry e;
+    std::memset(&e, 0, sizeof(e));
+    std::strncpy(e.name, kProfNames[cls], sizeof(e.name) - 1);
+    for (const auto& r : c->recs) {
+      if (r.cls != cls) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+        return (ctm_status)fail(c, CTM_E_DEVICE, "hipEventElapsedTime failed");
+      e.launches += 1;
+      e.ms += ms;
+      e.flops += r.flops;
+      e.bytes += r.bytes;
+    }
+    if (e.launches) out[cnt++] = e;
+  }
+  *n = cnt;
+  return CTM_OK;
+}
+
+ctm_status ctm_gemm_f64(int count, const double* const* A, const double* const* B,
+                        double* const* C, int M, int N, int K, int trans_a, long lda, long ldb,
+                        long ldc, double alpha, int accumulate, void* stream) {
+  if (count < 0 || count > kMaxProb || M < 0 || N < 0 || K < 0 || !A || !B || !C)
+    return (ctm_status)fail(nullptr, CTM_E_ARG, "invalid gemm arguments");
+  GemmBatch g = gemm_rowmajor(count, M, N, K, lda, ldb, ldc);
+  g.alpha = alpha;
+  g.accumulate = accumulate;
+  for (int i = 0; i < count; ++i) {
+    g.A[i] = A[i];
+    g.B[i] = B[i];
+    g.C[i] = C[i];
+    g.transA[i] = trans_a;
+  }
+  int r = launch_gemm(g, DT::F64, DT::F64, DT::F64, (hipStream_t)stream);
+  return r ? CTM_E_DEVICE : CTM_OK;
+}
+
+ctm_status ctm_qr_f64(int count, double* const* W, int N, int k, void* stream) {
+  if (count < 0 || count > kMaxProb || !W || k < 1 || N < k)
+    return (ctm_status)fail(nullptr, CTM_E_ARG, "invalid qr arguments");
+  void* ws = nullptr;
+  if (hipMalloc(&ws, qr_workspace_bytes(count, N, k)) != hipSuccess)
+    return (ctm_status)fail(nullptr, CTM_E_NOMEM, "hipMalloc failed");
+  int r = launch_qr(count, W, N, k, ws, (hipStream_t)stream);
+  (void)hipStreamSynchronize((hipStream_t)stream);
+  (void)hipFree(ws);
+  return r ? (ctm_status)(r == 1 ? CTM_E_ARG : r) : CTM_OK;
+}
+
+ctm_status ctm_svd_f64(int count, const double* const* rho, double* const* u, double* const* s,
+                       double* const* v, int n, void* stream) {
+  if (count < 0 || count > kMaxProb || !rho || !s || n < 1)
+    return (ctm_status)fail(nullptr, CTM_E_ARG, "invalid svd arguments");
+  void* ws = nullptr;
+  if (hipMalloc(&ws, svd_workspace_bytes(count, n)) != hipSuccess)
+    return (ctm_status)fail(nullptr, CTM_E_NOMEM, "hipMalloc failed");
+  int r = launch_svd(count, rho, u, s, v, n, ws, (hipStream_t)stream);
+  (void)hipStreamSynchronize((hipStream_t)stream);
+  (void)hipFree(ws);
+  return r ? (ctm_status)(r == 1 ? CTM_E_ARG : r) : CTM_OK;
+}
+
+}  // extern "C"

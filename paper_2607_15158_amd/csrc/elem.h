@@ -1,0 +1,73 @@
+// Element-wise kernels of a CTMRG move (internal).
+#pragma once
+
+#include "common.h"
+
+namespace sictm {
+
+struct NormArgs {
+  double* x[8];
+  long n[8];
+  double* out;   // 8 norms
+  int* bad;      // set to 1 on a zero / non-finite norm
+};
+
+struct SignArgs {
+  double* Y[4];
+  double* sg[4];
+  int N, k;
+  long ld;
+};
+
+struct ProjPrepArgs {
+  const double* u[4];
+  const double* v[4];
+  const double* s[4];
+  const double* sg[4];
+  double* vs[4];
+  double* vsc[4];
+  double* usc[4];
+  double* gap;   // [4] or null
+  int k, keep;
+  double rtol;
+};
+
+struct SpecArgs {
+  const double* s[4];
+  const double* old_spec;  // [4][chi]
+  double* new_spec;        // [4][chi]
+  double* delta;
+  int x, chi;
+};
+
+// a = sum_{s,t} A[s,ket] O[t,s] A[t,bra]; O == null: identity; s_fix >= 0: the single
+// (ket s_fix, bra t_fix) term (an open physical leg).
+int elem_double_layer(const double* A, const double* O, double* a, int d, int D, hipStream_t s,
+                      int s_fix = -1, int t_fix = -1);
+int elem_pair_dot(const double* X, const double* Y, long stride, int ni, int nj, int x, int m,
+                  int rev, double* out, hipStream_t s);
+int elem_kappa(const double* z, double* out, hipStream_t s);
+int elem_bond_value(const double* E, const double* op, int d, double* out, hipStream_t s);
+int elem_ratio(const double* a, const double* b, double* out, hipStream_t s);
+int elem_permute4(const double* src, void* dst, DT t, int n, long s0, long s1, long s2, long s3,
+                  hipStream_t s);
+int elem_init_env(const double* a, const double* e, int n, double* const* C, double* const* T,
+                  hipStream_t s);
+int elem_normalize(const NormArgs& na, int count, hipStream_t s);
+int elem_norms(const NormArgs& na, int count, hipStream_t s);
+int elem_col_sign(const SignArgs& sa, int count, hipStream_t s);
+int elem_scale_cols(const SignArgs& sa, int count, hipStream_t s);
+int elem_proj_prep(const ProjPrepArgs& pa, int count, hipStream_t s);
+int elem_proj_prep_full(const double* U, const double* Vt, const double* sv, const double* sg,
+                        int N, int keep, double rtol, double* Us, double* Vs, double* gap,
+                        hipStream_t s);
+int elem_identity(double* P, int n, int m, hipStream_t s);
+int elem_spectra_delta(const SpecArgs& sp, hipStream_t s);
+int elem_gauss(double* x, long n, uint64_t seed, hipStream_t s);
+int elem_dot_rev(const double* X, const double* Y, int x, int m, double* out, hipStream_t s);
+int elem_dot_rev_batched(const double* X, long xs, const double* Y, long ys, int nb, int x, int m,
+                         double* out, hipStream_t s);
+int elem_trace(const double* A, int n, double* out, hipStream_t s);
+int elem_dot(const double* X, const double* Y, long n, double* out, hipStream_t s);
+
+}  // namespace sictm

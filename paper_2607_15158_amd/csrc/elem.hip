@@ -1,0 +1,539 @@
+// Element-wise and reduction kernels of a CTMRG move: double layer, leg
+// permutations, initial boundary, normalisation, the sign rule, projector
+// scaling with the pseudo-inverse cutoff, spectra and the convergence
+// measure.  None of these is on the FLOP-critical path; they are written for
+// clarity and coalesced access.
+
+#include "elem.h"
+
+namespace sictm {
+namespace {
+
+template <typename T> __device__ __forceinline__ T from_f64(double x) { return (T)x; }
+template <> __device__ __forceinline__ __bf16 from_f64<__bf16>(double x) { return (__bf16)(float)x; }
+
+__device__ __forceinline__ double block_sum(double x, double* sh) {
+  // 256-thread block reduction
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = x;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+// a[(uU),(lL),(dD),(rR)] = sum_{s,t} A[s,u,l,d,r] O[t,s] A[t,U,L,D,R]   (O = identity if null)
+__global__ void k_double_layer(const double* A, const double* O, double* a, int d, int D,
+                               int s_fix, int t_fix) {
+  const long D4 = (long)D * D * D * D;
+  const long total = D4 * D4;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    // a index: ((((u U) l L) d D) r R) with each pair ket-major
+    long rem = i;
+    const int R = rem % D; rem /= D;
+    const int r = rem % D; rem /= D;
+    const int Dd = rem % D; rem /= D;
+    const int dd = rem % D; rem /= D;
+    const int L = rem % D; rem /= D;
+    const int l = rem % D; rem /= D;
+    const int U = rem % D; rem /= D;
+    const int u = (int)rem;
+    const long ket = (((long)u * D + l) * D + dd) * D + r;
+    const long bra = (((long)U * D + L) * D + Dd) * D + R;
+    double acc = 0.0;
+    if (s_fix >= 0) {
+      acc = A[s_fix * D4 + ket] * A[t_fix * D4 + bra];
+    } else if (O == nullptr) {
+      for (int s = 0; s < d; ++s) acc += A[s * D4 + ket] * A[s * D4 + bra];
+    } else {
+      for (int s = 0; s < d; ++s)
+        for (int t = 0; t < d; ++t) acc += A[s * D4 + ket] * O[t * d + s] * A[t * D4 + bra];
+    }
+    a[i] = acc;
+  }
+}
+
+template <typename T>
+__global__ void k_permute4(const double* src, T* dst, int n, long s0, long s1, long s2, long s3) {
+  const long total = (long)n * n * n * n;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    long rem = i;
+    const int i3 = rem % n; rem /= n;
+    const int i2 = rem % n; rem /= n;
+    const int i1 = rem % n; rem /= n;
+    const int i0 = (int)rem;
+    dst[i] = from_f64<T>(src[i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3]);
+  }
+}
+
+// Initial environment: close outer legs with e (see ctm.h / oracle docs).
+// C1[d,r] = a[u,l,d,r] e_u e_l        T1[l,d,r] = a[u,l,d,r] e_u
+// C2[l,d] = a e_u e_r                 T2[u,l,d] = a e_r
+// C3[u,l] = a e_d e_r                 T3[r,u,l] = a e_d
+// C4[r,u] = a e_l e_d                 T4[d,r,u] = a e_l
+__global__ void k_init_env(const double* a, const double* e, int n, double* C1, double* C2,
+                           double* C3, double* C4, double* T1, double* T2, double* T3,
+                           double* T4) {
+  const long n2 = (long)n * n, n3 = n2 * n;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  auto A = [&](int u, int l, int d, int r) { return a[u * n3 + l * n2 + d * n + r]; };
+  if (tid < n2) {
+    const int x = tid / n, y = tid % n;
+    double c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) {
+        const double w = e[p] * e[q];
+        c1 += A(p, q, x, y) * w;   // C1[d=x, r=y], u=p, l=q
+        c2 += A(p, x, y, q) * w;   // C2[l=x, d=y], u=p, r=q
+        c3 += A(x, y, p, q) * w;   // C3[u=x, l=y], d=p, r=q
+        c4 += A(y, p, q, x) * w;   // C4[r=x, u=y], l=p, d=q
+      }
+    C1[tid] = c1; C2[tid] = c2; C3[tid] = c3; C4[tid] = c4;
+  }
+  if (tid < n3) {
+    const int x = tid / (int)n2, y = (tid / n) % n, z = tid % n;
+    double t1 = 0, t2 = 0, t3 = 0, t4 = 0;
+    for (int p = 0; p < n; ++p) {
+      t1 += A(p, x, y, z) * e[p];  // T1[l=x, d=y, r=z]
+      t2 += A(x, y, z, p) * e[p];  // T2[u=x, l=y, d=z]
+      t3 += A(y, z, p, x) * e[p];  // T3[r=x, u=y, l=z]
+      t4 += A(z, p, x, y) * e[p];  // T4[d=x, r=y, u=z]
+    }
+    T1[tid] = t1; T2[tid] = t2; T3[tid] = t3; T4[tid] = t4;
+  }
+}
+
+// Frobenius norms of up to 8 tensors (one block each) -> out[i]; sets *bad
+// when a norm is zero or not finite.
+__global__ void k_norms(NormArgs na) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x;
+  const double* x = na.x[t];
+  const long n = na.n[t];
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) acc += x[i] * x[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    const double nr = sqrt(acc);
+    na.out[t] = nr;
+    if (!(nr > 0.0) || !isfinite(nr)) atomicOr(na.bad, 1);
+  }
+}
+
+__global__ void k_scale(NormArgs na) {
+  const int t = blockIdx.y;
+  double* x = na.x[t];
+  const long n = na.n[t];
+  const double inv = 1.0 / na.out[t];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    x[i] *= inv;
+}
+
+// Sign rule: for every column j of the N x k block Y (ld = ld), the dominant
+// entry -- the lowest-index entry whose magnitude is within a relative 1e-8
+// of the column's largest magnitude -- is made positive; sg[j] = +-1.
+// Roundoff-level ties (the ket/bra exchange symmetry of the double layer
+// pairs entries of equal magnitude) are thereby resolved by index.
+__global__ void k_col_sign(SignArgs sa) {
+  const int b = blockIdx.y;
+  const double* Y = sa.Y[b];
+  double* sg = sa.sg[b];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = blockIdx.x * 4 + wave; j < sa.k; j += gridDim.x * 4) {
+    double best = 0.0;
+    for (int r = lane; r < sa.N; r += 64) best = fmax(best, fabs(Y[(long)r * sa.ld + j]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) best = fmax(best, __shfl_xor(best, off, 64));
+    const double thr = (1.0 - 1e-8) * best;
+    int bi = 1 << 30;
+    double val = 0.0;
+    for (int r = lane; r < sa.N; r += 64) {
+      const double v = Y[(long)r * sa.ld + j];
+      if (fabs(v) >= thr) { bi = r; val = v; break; }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const int oi = __shfl_xor(bi, off, 64);
+      const double ov = __shfl_xor(val, off, 64);
+      if (oi < bi) { bi = oi; val = ov; }
+    }
+    if (lane == 0) sg[j] = val < 0.0 ? -1.0 : 1.0;
+  }
+}
+
+// Projector factors for one bond (one block per bond):
+//   sinv_i = s_i^-1/2 if s_i > rtol * s_0 else 0    (i < keep)
+//   vs  = v diag(sg)            (k x k)   -> recycled X = X vs
+//   vsc = v[:, :keep] diag(sg * sinv)     -> P_l = A vsc
+//   usc = u[:, :keep] diag(sg * sinv)     -> P_r^T = B^T usc
+//   gap = s_keep / s_(keep+1) - 1 (or -1)
+__global__ void k_proj_prep(ProjPrepArgs pa) {
+  const int b = blockIdx.x;
+  const int k = pa.k, keep = pa.keep;
+  const double* s = pa.s[b];
+  const double* sg = pa.sg[b];
+  const double s0 = s[0];
+  for (int i = threadIdx.x; i < k * k; i += blockDim.x) {
+    const int r = i / k, c = i % k;
+    const double sgc = sg[c];
+    if (pa.vs[b]) pa.vs[b][i] = pa.v[b][i] * sgc;
+    if (c < keep) {
+      const double sc = s[c];
+      const double si = (s0 > 0.0 && sc > pa.rtol * s0) ? 1.0 / sqrt(sc) : 0.0;
+      pa.vsc[b][r * keep + c] = pa.v[b][i] * sgc * si;
+      pa.usc[b][r * keep + c] = pa.u[b][i] * sgc * si;
+    }
+  }
+  if (threadIdx.x == 0 && pa.gap) {
+    double g = -1.0;
+    if (keep < k && s[keep] > 0.0) g = s[keep - 1] / s[keep] - 1.0;
+    pa.gap[b] = g;
+  }
+}
+
+// Full-SVD variant: U (N x N row-major), Vt (N x N row-major) from the
+// dense SVD, column signs sg of U.  Writes Vs[r][c] = Vt[c][r] sg_c sinv_c
+// and Us[r][c] = U[r][c] sg_c sinv_c for c < keep (both N x keep).
+__global__ void k_proj_prep_full(const double* U, const double* Vt, const double* s,
+                                 const double* sg, int N, int keep, double rtol, double* Us,
+                                 double* Vs, double* gap) {
+  const double s0 = s[0];
+  const long total = (long)N * keep;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(i / keep), c = (int)(i % keep);
+    const double sc = s[c];
+    const double si = (s0 > 0.0 && sc > rtol * s0) ? 1.0 / sqrt(sc) : 0.0;
+    const double f = sg[c] * si;
+    Us[i] = U[(long)r * N + c] * f;
+    Vs[i] = Vt[(long)c * N + r] * f;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && gap) {
+    double g = -1.0;
+    if (keep < N && s[keep] > 0.0) g = s[keep - 1] / s[keep] - 1.0;
+    *gap = g;
+  }
+}
+
+__global__ void k_scale_cols(SignArgs sa) {
+  const int b = blockIdx.y;
+  double* Y = sa.Y[b];
+  const double* sg = sa.sg[b];
+  const long total = (long)sa.N * sa.k;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(i / sa.k), c = (int)(i % sa.k);
+    Y[(long)r * sa.ld + c] *= sg[c];
+  }
+}
+
+__global__ void k_identity(double* P, int n, int m) {
+  const long total = (long)n * m;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x)
+    P[i] = ((i / m) == (i % m)) ? 1.0 : 0.0;
+}
+
+// Unit-2-norm spectra of the four corners (values of length x, descending),
+// zero-padded to chi; delta = max_i |s_new - s_old|_2.  One block.
+__global__ void k_spectra_delta(SpecArgs sp) {
+  __shared__ double sh[4];
+  __shared__ double dmax;
+  if (threadIdx.x == 0) dmax = 0.0;
+  __syncthreads();
+  for (int c = 0; c < 4; ++c) {
+    const double* s = sp.s[c];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < sp.x; i += blockDim.x) acc += s[i] * s[i];
+    const double nrm = sqrt(block_sum(acc, sh));
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    double dd = 0.0;
+    for (int i = threadIdx.x; i < sp.chi; i += blockDim.x) {
+      const double v = i < sp.x ? s[i] * inv : 0.0;
+      const double o = sp.old_spec[c * sp.chi + i];
+      dd += (v - o) * (v - o);
+      sp.new_spec[c * sp.chi + i] = v;
+    }
+    dd = block_sum(dd, sh);
+    if (threadIdx.x == 0) dmax = fmax(dmax, sqrt(dd));
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *sp.delta = dmax;
+}
+
+// Standard normals from a counter-based generator (SplitMix64 finaliser of
+// (seed, index), Box-Muller): used only when the caller gives no start block.
+__device__ __forceinline__ uint64_t splitmix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void k_gauss(double* x, long n, uint64_t seed) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    const uint64_t h1 = splitmix(seed * 0x100000001B3ull + 2 * (uint64_t)i);
+    const uint64_t h2 = splitmix(seed * 0x100000001B3ull + 2 * (uint64_t)i + 1);
+    const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+    x[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+// sum_{t,d,e} X[t,d,e] Y[e,d,t] (X, Y of shape x, m, x) into *out.  One block.
+__global__ void k_dot_rev(const double* X, const double* Y, int x, int m, double* out) {
+  __shared__ double sh[4];
+  const long total = (long)x * m * x;
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < total; i += blockDim.x) {
+    const int t = (int)(i / ((long)m * x));
+    const int d = (int)((i / x) % m);
+    const int e = (int)(i % x);
+    acc += X[i] * Y[((long)e * m + d) * x + t];
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+// Batched variant over nb leading blocks: out[b] = sum X_b[t,d,e] Y_b'[e,d,t].
+__global__ void k_dot_rev_batched(const double* X, long xs, const double* Y, long ys, int x,
+                                  int m, double* out) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  const double* Xb = X + b * xs;
+  const double* Yb = Y + b * ys;
+  const long total = (long)x * m * x;
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < total; i += blockDim.x) {
+    const int t = (int)(i / ((long)m * x));
+    const int d = (int)((i / x) % m);
+    const int e = (int)(i % x);
+    acc += Xb[i] * Yb[((long)e * m + d) * x + t];
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[b] = acc;
+}
+
+__global__ void k_trace(const double* A, int n, double* out) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += A[(long)i * n + i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+// sum_i X[i] * Y[perm(i)] for X of shape (x, m, x) and Y[t,m?]: general
+// elementwise dot of equal-layout arrays.
+__global__ void k_dot(const double* X, const double* Y, long n, double* out) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) acc += X[i] * Y[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+// out[i * nj + j] = sum_idx X_i[idx] Y_j[idx'] over arrays of shape (x, m, x);
+// idx' = idx (rev == 0) or the reversed index (t,d,e) -> (e,d,t) (rev == 1).
+__global__ void k_pair_dot(const double* X, const double* Y, long stride, int nj, int x, int m,
+                           int rev, double* out) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x / nj, j = blockIdx.x % nj;
+  const double* Xi = X + i * stride;
+  const double* Yj = Y + j * stride;
+  const long total = (long)x * m * x;
+  double acc = 0.0;
+  for (long q = threadIdx.x; q < total; q += blockDim.x) {
+    long r = q;
+    if (rev) {
+      const int t = (int)(q / ((long)m * x));
+      const int d = (int)((q / x) % m);
+      const int e = (int)(q % x);
+      r = ((long)e * m + d) * x + t;
+    }
+    acc += Xi[q] * Yj[r];
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+// vals = [Z11, Z00, Z10, Z01] -> out = Z11 Z00 / (Z10 Z01)
+__global__ void k_kappa(const double* z, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = z[0] * z[1] / (z[2] * z[3]);
+}
+
+// <op> = sum_{s1 t1 s2 t2} op[(t1 t2),(s1 s2)] E[(s1 t1),(s2 t2)] / sum_{s1 s2} E[(s1 s1),(s2 s2)]
+__global__ void k_bond_value(const double* E, const double* op, int d, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int d2 = d * d;
+  double num = 0.0, den = 0.0;
+  for (int s1 = 0; s1 < d; ++s1)
+    for (int t1 = 0; t1 < d; ++t1)
+      for (int s2 = 0; s2 < d; ++s2)
+        for (int t2 = 0; t2 < d; ++t2) {
+          const double e = E[(s1 * d + t1) * d2 + (s2 * d + t2)];
+          num += op[(t1 * d + t2) * d2 + (s1 * d + s2)] * e;
+          if (s1 == t1 && s2 == t2) den += e;
+        }
+  out[0] = num / den;
+}
+
+__global__ void k_ratio(const double* a, const double* b, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = a[0] / b[0];
+}
+
+}  // namespace
+
+int elem_pair_dot(const double* X, const double* Y, long stride, int ni, int nj, int x, int m,
+                  int rev, double* out, hipStream_t s) {
+  k_pair_dot<<<ni * nj, 256, 0, s>>>(X, Y, stride, nj, x, m, rev, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_kappa(const double* z, double* out, hipStream_t s) {
+  k_kappa<<<1, 64, 0, s>>>(z, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_bond_value(const double* E, const double* op, int d, double* out, hipStream_t s) {
+  k_bond_value<<<1, 64, 0, s>>>(E, op, d, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_ratio(const double* a, const double* b, double* out, hipStream_t s) {
+  k_ratio<<<1, 64, 0, s>>>(a, b, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_double_layer(const double* A, const double* O, double* a, int d, int D, hipStream_t s,
+                      int s_fix, int t_fix) {
+  const long total = (long)D * D * D * D * D * D * D * D;
+  const int blocks = (int)std::min<long>(4096, (total + 255) / 256);
+  k_double_layer<<<blocks, 256, 0, s>>>(A, O, a, d, D, s_fix, t_fix);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_permute4(const double* src, void* dst, DT t, int n, long s0, long s1, long s2, long s3,
+                  hipStream_t s) {
+  const long total = (long)n * n * n * n;
+  const int blocks = (int)std::min<long>(4096, (total + 255) / 256);
+  if (t == DT::F64) k_permute4<double><<<blocks, 256, 0, s>>>(src, (double*)dst, n, s0, s1, s2, s3);
+  else if (t == DT::F32) k_permute4<float><<<blocks, 256, 0, s>>>(src, (float*)dst, n, s0, s1, s2, s3);
+  else k_permute4<__bf16><<<blocks, 256, 0, s>>>(src, (__bf16*)dst, n, s0, s1, s2, s3);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_init_env(const double* a, const double* e, int n, double* const* C, double* const* T,
+                  hipStream_t s) {
+  const long n3 = (long)n * n * n;
+  const int blocks = (int)((n3 + 255) / 256);
+  k_init_env<<<blocks, 256, 0, s>>>(a, e, n, C[0], C[1], C[2], C[3], T[0], T[1], T[2], T[3]);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_normalize(const NormArgs& na, int count, hipStream_t s) {
+  k_norms<<<count, 256, 0, s>>>(na);
+  long mx = 0;
+  for (int i = 0; i < count; ++i) mx = std::max(mx, na.n[i]);
+  const int blocks = (int)std::min<long>(1024, (mx + 255) / 256);
+  k_scale<<<dim3(blocks, count), 256, 0, s>>>(na);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_norms(const NormArgs& na, int count, hipStream_t s) {
+  k_norms<<<count, 256, 0, s>>>(na);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_col_sign(const SignArgs& sa, int count, hipStream_t s) {
+  const int blocks = std::max(1, std::min(64, (sa.k + 3) / 4));
+  k_col_sign<<<dim3(blocks, count), 256, 0, s>>>(sa);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_scale_cols(const SignArgs& sa, int count, hipStream_t s) {
+  const long total = (long)sa.N * sa.k;
+  const int blocks = (int)std::min<long>(1024, (total + 255) / 256);
+  k_scale_cols<<<dim3(blocks, count), 256, 0, s>>>(sa);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_proj_prep(const ProjPrepArgs& pa, int count, hipStream_t s) {
+  k_proj_prep<<<count, 256, 0, s>>>(pa);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_proj_prep_full(const double* U, const double* Vt, const double* sv, const double* sg,
+                        int N, int keep, double rtol, double* Us, double* Vs, double* gap,
+                        hipStream_t s) {
+  const long total = (long)N * keep;
+  const int blocks = (int)std::min<long>(2048, (total + 255) / 256);
+  k_proj_prep_full<<<blocks, 256, 0, s>>>(U, Vt, sv, sg, N, keep, rtol, Us, Vs, gap);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_identity(double* P, int n, int m, hipStream_t s) {
+  const long total = (long)n * m;
+  const int blocks = (int)std::min<long>(1024, (total + 255) / 256);
+  k_identity<<<blocks, 256, 0, s>>>(P, n, m);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_spectra_delta(const SpecArgs& sp, hipStream_t s) {
+  k_spectra_delta<<<1, 256, 0, s>>>(sp);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_gauss(double* x, long n, uint64_t seed, hipStream_t s) {
+  const int blocks = (int)std::min<long>(2048, (n + 255) / 256);
+  k_gauss<<<blocks, 256, 0, s>>>(x, n, seed);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_dot_rev(const double* X, const double* Y, int x, int m, double* out, hipStream_t s) {
+  k_dot_rev<<<1, 256, 0, s>>>(X, Y, x, m, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_dot_rev_batched(const double* X, long xs, const double* Y, long ys, int nb, int x, int m,
+                         double* out, hipStream_t s) {
+  k_dot_rev_batched<<<nb, 256, 0, s>>>(X, xs, Y, ys, x, m, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_trace(const double* A, int n, double* out, hipStream_t s) {
+  k_trace<<<1, 256, 0, s>>>(A, n, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_dot(const double* X, const double* Y, long n, double* out, hipStream_t s) {
+  k_dot<<<1, 256, 0, s>>>(X, Y, n, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace sictm

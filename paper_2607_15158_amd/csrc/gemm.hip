@@ -1,0 +1,427 @@
+// Batched, index-mapped GEMM on the gfx950 matrix cores.
+//
+// Every contraction of a CTMRG move -- the enlarged-corner build, the
+// applications of the enlarged corners to the N x k isometry blocks, the
+// reduced matrix rho, the projector products and the renormalisation of C
+// and T (Fig. 1; QR-based projector section) -- is one launch of this kernel
+// family.  Leg permutations are folded into the operand strides and into the
+// two-level output map, so no tensor is ever transposed in memory.
+//
+// Design: 256-thread workgroups (4 wavefronts of 64), one BM x BN output tile
+// per workgroup, K staged through LDS in BK slices with a register prefetch
+// of the next slice.  Wavefronts own (BM/WGM) x (BN/WGN) sub-tiles built
+// from 16x16 MFMA blocks:
+//   float64: v_mfma_f64_16x16x4_f64  (A: lane -> (row l%16, k l/16))
+//   float32: v_mfma_f32_16x16x4_f32  (same operand layout)
+//   bf16   : v_mfma_f32_16x16x32_bf16 (A: lane -> (row l%16, k 8*(l/16)..+7))
+// and accumulate in float64 (f64 inputs) or float32 (f32/bf16 inputs).
+// Result element r = 0..3 of lane l lies in column l%16 and in row
+// l/16 + 4r for the float64 instruction, row 4(l/16) + r for the others
+// (both measured on gfx950).
+// Workgroup ids are remapped so that consecutive tiles share an XCD (and its
+// L2), since the hardware deals consecutive workgroups round-robin to the 8
+// XCDs.
+
+#include "common.h"
+
+namespace sictm {
+namespace {
+
+template <typename Dst, typename Src>
+__device__ __forceinline__ Dst cvt(Src x) { return (Dst)x; }
+template <>
+__device__ __forceinline__ __bf16 cvt<__bf16, double>(double x) { return (__bf16)(float)x; }
+template <>
+__device__ __forceinline__ __bf16 cvt<__bf16, float>(float x) { return (__bf16)x; }
+template <>
+__device__ __forceinline__ float cvt<float, __bf16>(__bf16 x) { return (float)x; }
+template <>
+__device__ __forceinline__ double cvt<double, __bf16>(__bf16 x) { return (double)(float)x; }
+
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+__device__ __forceinline__ long map2(int i, int div, long s1, long s0) {
+  return (long)(i / div) * s1 + (long)(i % div) * s0;
+}
+
+// ---------------------------------------------------------------------------
+// 16x16x4 path (float64 or float32 compute type CT).
+// ---------------------------------------------------------------------------
+template <typename CT> struct Mfma4;
+template <> struct Mfma4<double> {
+  using acc_t = v4d;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mfma4<float> {
+  using acc_t = v4f;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename TA, typename TB, typename TC, typename CT, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void gemm_k4(GemmBatch g, int tiles_m, int tiles_n) {
+  constexpr int BK = 16;
+  constexpr int PAD = 2;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int MI = WTM / 16, NI = WTN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  static_assert(WGM * WGN == 4, "four wavefronts");
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile multiple of 16");
+  static_assert((BM * BK) % 256 == 0 && (BN * BK) % 256 == 0, "tile loads");
+  using Acc = typename Mfma4<CT>::acc_t;
+
+  __shared__ CT As[BK][BM + PAD];
+  __shared__ CT Bs[BK][BN + PAD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = tile % tiles_n, tm = tile / tiles_n;
+  const int prob = blockIdx.y / g.nbatch, batch = blockIdx.y % g.nbatch;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int M = g.M, N = g.N, K = g.K;
+  const int trans = g.transA[prob];
+  const TA* A = (const TA*)g.A[prob] + (long)batch * g.a_bs;
+  const TB* B = (const TB*)g.B[prob] + (long)batch * g.b_bs;
+  TC* C = (TC*)g.C[prob] + (long)batch * g.c_bs;
+  const long lda = g.lda, ldb = g.ldb;
+
+  CT ra[EA], rb[EB];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int i = tid + e * 256;
+      int m, kk;
+      if (trans) { m = i % BM; kk = i / BM; } else { m = i / BK; kk = i % BK; }
+      const int gm = m0 + m, gk = k0 + kk;
+      CT v = (CT)0;
+      if (gm < M && gk < K) v = cvt<CT>(trans ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk]);
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int i = tid + e * 256;
+      const int n = i % BN, kk = i / BN;
+      const int gn = n0 + n, gk = k0 + kk;
+      CT v = (CT)0;
+      if (gn < N && gk < K) v = cvt<CT>(B[(long)gk * ldb + gn]);
+      rb[e] = v;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int i = tid + e * 256;
+      int m, kk;
+      if (trans) { m = i % BM; kk = i / BM; } else { m = i / BK; kk = i % BK; }
+      As[kk][m] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int i = tid + e * 256;
+      Bs[i / BN][i % BN] = rb[e];
+    }
+  };
+
+  Acc acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+  const int nk = (K + BK - 1) / BK;
+  load_tiles(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    store_tiles();
+    __syncthreads();
+    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      CT a[MI], b[NI];
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < MI; ++i) a[i] = As[kr][wm * WTM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) b[j] = Bs[kr][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) acc[i][j] = Mfma4<CT>::op(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: two-level output map
+  long offn[NI];
+  bool okn[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+    okn[j] = n < N;
+    offn[j] = okn[j] ? map2(n, g.cdiv_n, g.cs_n1, g.cs_n0) : 0;
+  }
+  const double alpha = g.alpha;
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * WTM + i * 16 + Mfma4<CT>::row(lane, r);
+      if (m >= M) continue;
+      const long offm = map2(m, g.cdiv_m, g.cs_m1, g.cs_m0);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        if (!okn[j]) continue;
+        TC* p = C + offm + offn[j];
+        double v = alpha * (double)acc[i][j][r];
+        if (g.accumulate) v += (double)*p;
+        *p = cvt<TC>(v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// bf16 path: v_mfma_f32_16x16x32_bf16, float32 accumulation.
+// LDS keeps k contiguous per row so that a lane reads its 8 k-values at once.
+// ---------------------------------------------------------------------------
+template <typename TA, typename TB, typename TC, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void gemm_bf16(GemmBatch g, int tiles_m, int tiles_n) {
+  constexpr int BK = 32;
+  constexpr int PAD = 8;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int MI = WTM / 16, NI = WTN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  static_assert(WGM * WGN == 4, "four wavefronts");
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile multiple of 16");
+
+  __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][BK + PAD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = tile % tiles_n, tm = tile / tiles_n;
+  const int prob = blockIdx.y / g.nbatch, batch = blockIdx.y % g.nbatch;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int M = g.M, N = g.N, K = g.K;
+  const int trans = g.transA[prob];
+  const TA* A = (const TA*)g.A[prob] + (long)batch * g.a_bs;
+  const TB* B = (const TB*)g.B[prob] + (long)batch * g.b_bs;
+  TC* C = (TC*)g.C[prob] + (long)batch * g.c_bs;
+  const long lda = g.lda, ldb = g.ldb;
+
+  __bf16 ra[EA], rb[EB];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int i = tid + e * 256;
+      int m, kk;
+      if (trans) { m = i % BM; kk = i / BM; } else { m = i / BK; kk = i % BK; }
+      const int gm = m0 + m, gk = k0 + kk;
+      __bf16 v = (__bf16)0.0f;
+      if (gm < M && gk < K)
+        v = cvt<__bf16>(trans ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk]);
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int i = tid + e * 256;
+      const int n = i % BN, kk = i / BN;
+      const int gn = n0 + n, gk = k0 + kk;
+      __bf16 v = (__bf16)0.0f;
+      if (gn < N && gk < K) v = cvt<__bf16>(B[(long)gk * ldb + gn]);
+      rb[e] = v;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int i = tid + e * 256;
+      int m, kk;
+      if (trans) { m = i % BM; kk = i / BM; } else { m = i / BK; kk = i % BK; }
+      As[m][kk] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int i = tid + e * 256;
+      Bs[i % BN][i / BN] = rb[e];
+    }
+  };
+
+  v4f acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+  const int nk = (K + BK - 1) / BK;
+  load_tiles(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    store_tiles();
+    __syncthreads();
+    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+    const int kc = 8 * (lane >> 4);
+    v8bf a[MI], b[NI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+      a[i] = *reinterpret_cast<const v8bf*>(&As[wm * WTM + i * 16 + (lane & 15)][kc]);
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+      b[j] = *reinterpret_cast<const v8bf*>(&Bs[wn * WTN + j * 16 + (lane & 15)][kc]);
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+
+  long offn[NI];
+  bool okn[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+    okn[j] = n < N;
+    offn[j] = okn[j] ? map2(n, g.cdiv_n, g.cs_n1, g.cs_n0) : 0;
+  }
+  const float alpha = (float)g.alpha;
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
+      if (m >= M) continue;
+      const long offm = map2(m, g.cdiv_m, g.cs_m1, g.cs_m0);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        if (!okn[j]) continue;
+        TC* p = C + offm + offn[j];
+        float v = alpha * acc[i][j][r];
+        if (g.accumulate) v += (float)*p;
+        *p = cvt<TC>(v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tile selection
+// ---------------------------------------------------------------------------
+struct TileCfg {
+  int bm, bn;
+};
+
+// Available (BM, BN) shapes; each has a fixed wavefront arrangement below.
+constexpr TileCfg kTiles[] = {{128, 128}, {128, 144}, {64, 160}, {64, 80}, {64, 64}, {32, 32}};
+
+int pick_tile(const GemmBatch& g) {
+  int best = -1;
+  double best_cost = 1e300;
+  const long blocks_y = (long)g.count * g.nbatch;
+  for (int c = 0; c < (int)(sizeof(kTiles) / sizeof(kTiles[0])); ++c) {
+    const int bm = kTiles[c].bm, bn = kTiles[c].bn;
+    const long tm = ceil_div(g.M, bm), tn = ceil_div(g.N, bn);
+    const long wgs = tm * tn * blocks_y;
+    // padded work, penalised when the grid cannot fill 256 compute units, and
+    // slightly by the per-tile overhead of small tiles
+    const double work = (double)tm * bm * tn * bn * blocks_y;
+    const double fill = wgs >= 256 ? 1.0 : 256.0 / (double)wgs;
+    const double small = 1.0 + 2048.0 / (double)(bm * bn);
+    const double cost = work * fill * small;
+    if (cost < best_cost) { best_cost = cost; best = c; }
+  }
+  return best;
+}
+
+template <typename TA, typename TB, typename TC, typename CT>
+int launch_k4(const GemmBatch& g, hipStream_t s) {
+  const int c = pick_tile(g);
+  const int bm = kTiles[c].bm, bn = kTiles[c].bn;
+  const int tm = ceil_div(g.M, bm), tn = ceil_div(g.N, bn);
+  dim3 grid(tm * tn, g.count * g.nbatch), block(256);
+  switch (c) {
+    case 0: gemm_k4<TA, TB, TC, CT, 128, 128, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 1: gemm_k4<TA, TB, TC, CT, 128, 144, 4, 1><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 2: gemm_k4<TA, TB, TC, CT, 64, 160, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 3: gemm_k4<TA, TB, TC, CT, 64, 80, 4, 1><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 4: gemm_k4<TA, TB, TC, CT, 64, 64, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    default: gemm_k4<TA, TB, TC, CT, 32, 32, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+  }
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+template <typename TA, typename TB, typename TC>
+int launch_b16(const GemmBatch& g, hipStream_t s) {
+  const int c = pick_tile(g);
+  const int bm = kTiles[c].bm, bn = kTiles[c].bn;
+  const int tm = ceil_div(g.M, bm), tn = ceil_div(g.N, bn);
+  dim3 grid(tm * tn, g.count * g.nbatch), block(256);
+  switch (c) {
+    case 0: gemm_bf16<TA, TB, TC, 128, 128, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 1: gemm_bf16<TA, TB, TC, 128, 144, 4, 1><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 2: gemm_bf16<TA, TB, TC, 64, 160, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 3: gemm_bf16<TA, TB, TC, 64, 80, 4, 1><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 4: gemm_bf16<TA, TB, TC, 64, 64, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    default: gemm_bf16<TA, TB, TC, 32, 32, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+  }
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace
+
+// Compute type: float64 when any operand is float64 and the mode is f64;
+// the caller selects the mode through the operand types:
+//   (F64, F64, *)   -> float64 MFMA
+//   (F32, *, *)     -> float32 MFMA (f64 B operands are rounded to f32)
+//   (BF16, *, *)    -> bf16 MFMA with f32 accumulation
+int launch_gemm(const GemmBatch& g, DT ta, DT tb, DT tc, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch <= 0) return 0;
+  if (g.K <= 0 && !g.accumulate) {
+    // empty sum: the kernels still write zeros (load loop does not run)
+  }
+  if (ta == DT::F64 && tb == DT::F64) {
+    if (tc == DT::F64) return launch_k4<double, double, double, double>(g, s);
+    if (tc == DT::F32) return launch_k4<double, double, float, double>(g, s);
+  }
+  if (ta == DT::F32) {
+    if (tb == DT::F64 && tc == DT::F64) return launch_k4<float, double, double, float>(g, s);
+    if (tb == DT::F64 && tc == DT::F32) return launch_k4<float, double, float, float>(g, s);
+    if (tb == DT::F32 && tc == DT::F32) return launch_k4<float, float, float, float>(g, s);
+    if (tb == DT::F32 && tc == DT::F64) return launch_k4<float, float, double, float>(g, s);
+  }
+  if (ta == DT::F64 && tb == DT::F32) {
+    if (tc == DT::F32) return launch_k4<double, float, float, float>(g, s);
+    if (tc == DT::F64) return launch_k4<double, float, double, float>(g, s);
+  }
+  if (ta == DT::F64 && tb == DT::BF16) {
+    if (tc == DT::BF16) return launch_b16<double, __bf16, __bf16>(g, s);
+    if (tc == DT::F32) return launch_b16<double, __bf16, float>(g, s);
+    if (tc == DT::F64) return launch_b16<double, __bf16, double>(g, s);
+  }
+  if (ta == DT::F64 && tb == DT::F32 && tc == DT::BF16) return launch_k4<double, float, __bf16, float>(g, s);
+  if (ta == DT::BF16) {
+    if (tb == DT::BF16 && tc == DT::F64) return launch_b16<__bf16, __bf16, double>(g, s);
+    if (tb == DT::F64 && tc == DT::F64) return launch_b16<__bf16, double, double>(g, s);
+    if (tb == DT::F64 && tc == DT::F32) return launch_b16<__bf16, double, float>(g, s);
+    if (tb == DT::F32 && tc == DT::F32) return launch_b16<__bf16, float, float>(g, s);
+    if (tb == DT::F32 && tc == DT::F64) return launch_b16<__bf16, float, double>(g, s);
+  }
+  if (ta == DT::F64 && tb == DT::F64 && tc == DT::BF16)
+    return launch_k4<double, double, __bf16, double>(g, s);
+  if (ta == DT::F64 && tb == DT::F64) return launch_k4<double, double, double, double>(g, s);
+  set_thread_error("launch_gemm: unsupported type combination");
+  return 1;
+}
+
+}  // namespace sictm

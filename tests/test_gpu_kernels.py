@@ -1,0 +1,98 @@
+"""GPU parity of the building-block kernels through the C ABI.
+
+GEMM against float64 NumPy products; Householder QR against the oracle's
+QR convention (R_ii >= 0) and orthogonality; Jacobi SVD against NumPy's
+singular values and the reconstruction.  Shapes span several tiles and
+ragged tails.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import paper_2607_15158_amd as P  # noqa: E402
+import synth as S  # noqa: E402
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("M,N,K,trans", [(5, 7, 3, 0), (130, 70, 33, 0), (130, 70, 33, 1),
+                                         (257, 160, 300, 0), (300, 161, 257, 1),
+                                         (1000, 144, 520, 0), (64, 1296, 1296, 0)])
+def test_gemm_f64_matches_numpy(M, N, K, trans):
+    rng = np.random.default_rng(M * 7 + N)
+    A = [rng.standard_normal((K, M) if trans else (M, K)) for _ in range(3)]
+    B = [rng.standard_normal((K, N)) for _ in range(3)]
+    Ad, Bd = [dev(a) for a in A], [dev(b) for b in B]
+    Cd = [torch.zeros(M, N, dtype=torch.float64, device="cuda") for _ in range(3)]
+    P.gemm_f64(Ad, Bd, Cd, M, N, K, trans_a=trans)
+    torch.cuda.synchronize()
+    for a, b, c in zip(A, B, Cd):
+        ref = (a.T if trans else a) @ b
+        err = np.abs(c.cpu().numpy() - ref).max()
+        assert err <= 1e-12 * np.sqrt(K) * np.abs(ref).max()
+
+
+def test_gemm_accumulate_and_alpha():
+    rng = np.random.default_rng(1)
+    A, B, C0 = rng.standard_normal((40, 50)), rng.standard_normal((50, 30)), rng.standard_normal((40, 30))
+    Cd = dev(C0.copy())
+    P.gemm_f64([dev(A)], [dev(B)], [Cd], 40, 30, 50, alpha=-0.5, accumulate=1)
+    torch.cuda.synchronize()
+    assert np.allclose(Cd.cpu().numpy(), C0 - 0.5 * A @ B, atol=1e-12)
+
+
+@pytest.mark.parametrize("N,k", [(32, 24), (100, 100), (1024, 72), (2500, 105), (5184, 160),
+                                 (777, 33)])
+def test_householder_qr(N, k):
+    W = [S.gaussian_block(N, k, 3 + i) for i in range(4)]
+    W[1][:, 5] = 0.0                              # a zero column (tau = 0 path)
+    W[2][:, 3] = 2.0 * W[2][:, 1]                 # exactly dependent columns
+    Wd = [dev(w) for w in W]
+    P.qr_f64(Wd)
+    torch.cuda.synchronize()
+    for i, (w, q) in enumerate(zip(W, Wd)):
+        Q = q.cpu().numpy()
+        assert np.all(np.isfinite(Q))
+        assert np.abs(Q.T @ Q - np.eye(k)).max() <= 1e-13 * np.sqrt(N)
+        R = Q.T @ w
+        assert np.abs(np.tril(R, -1)).max() <= 1e-12 * np.abs(w).max() * np.sqrt(N)
+        assert np.all(np.diag(R) >= -1e-12 * np.abs(w).max())
+        if i in (0, 3):                           # full rank: unique, equals the oracle's
+            assert np.abs(Q - O.qr_pos(w)).max() <= 1e-11
+
+
+@pytest.mark.parametrize("n", [7, 24, 72, 105, 160])
+def test_jacobi_svd(n):
+    rng = np.random.default_rng(n)
+    mats = [rng.standard_normal((n, n)),
+            rng.standard_normal((n, n)) @ np.diag(np.logspace(0, -13, n)) @ rng.standard_normal((n, n)),
+            np.outer(rng.standard_normal(n), rng.standard_normal(n))]
+    rd = [dev(m) for m in mats]
+    ud = [torch.zeros(n, n, dtype=torch.float64, device="cuda") for _ in mats]
+    vd = [torch.zeros(n, n, dtype=torch.float64, device="cuda") for _ in mats]
+    sd = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in mats]
+    P.svd_f64(rd, ud, sd, vd)
+    torch.cuda.synchronize()
+    for m, u, s, v in zip(mats, ud, sd, vd):
+        U, Sv, V = u.cpu().numpy(), s.cpu().numpy(), v.cpu().numpy()
+        ref = np.linalg.svd(m, compute_uv=False)
+        assert np.all(np.diff(Sv) <= 0)
+        assert np.abs(Sv - ref).max() <= 1e-13 * ref[0] * n
+        assert np.abs(U.T @ U - np.eye(n)).max() <= 1e-12 * n
+        assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12 * n
+        assert np.abs((U * Sv) @ V.T - m).max() <= 1e-13 * ref[0] * n
+
+
+def test_jacobi_svd_values_only():
+    rng = np.random.default_rng(9)
+    m = rng.standard_normal((50, 50))
+    s = torch.zeros(50, dtype=torch.float64, device="cuda")
+    P.svd_f64([dev(m)], None, [s], None)
+    torch.cuda.synchronize()
+    assert np.allclose(s.cpu().numpy(), np.linalg.svd(m, compute_uv=False), rtol=1e-13, atol=1e-13)
