@@ -1,29 +1,27 @@
 // Tall-skinny Householder QR with explicit Q (QR-based projector section,
 // step 1: the isometries are re-orthonormalised by a QR decomposition after
-// every power update).
+// the power update).
 //
 // Communication-avoiding layout for N x k blocks with N >> k:
 //  * the rows are split into `nb` leaves of at most kLeafRows rows (leaf 0
 //    holds at least k rows); the columns are processed in panels of width
 //    kPanel;
 //  * per panel, every leaf factors its active rows of the panel with
-//    Householder reflectors held in LDS and applies them to its trailing
-//    columns (one workgroup per leaf);
-//  * the w x w triangles that the leaves leave in their top rows are then
-//    combined pairwise up a binary tree; a combine of two upper triangles has
-//    reflectors [e_j; v] whose lower part v is itself upper triangular, so it
-//    is stored in the place of the absorbed triangle; the tree node applies
-//    its reflectors to the trailing columns of its 2w rows;
+//    Householder reflectors in LDS, forms the compact-WY factor T
+//    (H_0...H_(w-1) = I - V T V^T) and updates its trailing columns with
+//    C <- C - V T^T (V^T C), three small GEMMs on the FP64 matrix cores;
+//  * the w x w triangles the leaves leave in their top rows are combined
+//    pairwise up a binary tree; combining two upper triangles gives
+//    reflectors [e_j; v] with v upper triangular, stored in the place of the
+//    absorbed triangle, and their own WY factor updates the trailing columns
+//    of the node's 2w rows;
 //  * Q = prod_p L_p T_p [I; 0] is then formed by applying the tree and leaf
-//    reflectors in reverse order to [I_k; 0], restricted to the columns that
-//    can be non-trivial, and each column c is multiplied by sign(R_cc) so
-//    that R has a non-negative diagonal.
+//    WY factors (C <- C - V T (V^T C)) in reverse order to [I_k; 0], on the
+//    columns that can be non-trivial, and each column c is multiplied by
+//    sign(R_cc) so that R has a non-negative diagonal.
 // Reflectors follow the LAPACK dlarfg convention: beta = -sign(alpha) * norm,
 // tau = (beta - alpha) / beta, and tau = 0 (H = I) when the part below the
 // diagonal is exactly zero, so rank-deficient blocks never divide by zero.
-// A wavefront owns one column at a time; rows are spread over its 64 lanes
-// and reductions use cross-lane shuffles, so no workgroup barrier is needed
-// inside the reflector application to a column.
 
 #include "common.h"
 
@@ -32,7 +30,9 @@ namespace {
 
 constexpr int kPanel = 32;
 constexpr int kLeafRows = 256;
-constexpr int kRowsPerLane = kLeafRows / 64;
+constexpr int kLR = kLeafRows + 1;   // odd row length: fragment reads hit distinct banks
+constexpr int kT = kPanel + 1;   // padded row length of the small LDS matrices
+constexpr int kTrail = 64;       // trailing columns per LDS chunk in the tree kernels
 
 struct QrPlan {
   int N, k, nb, P, depth;
@@ -48,60 +48,101 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// C(M x N) = sum_k A(m, k) B(k, n) for operands in LDS, on the FP64 matrix
+// cores (v_mfma_f64_16x16x4: operand lane l -> (row l%16, k l/16), result
+// element r -> (row l/16 + 4r, column l%16)).  16x16 blocks are dealt to the
+// four wavefronts; `store(m, n, value)` receives every result element once.
+template <typename FA, typename FB, typename FS>
+__device__ __forceinline__ void lds_mm(int M, int N, int K, FA A, FB B, FS store, int wave,
+                                       int lane) {
+  const int bm = (M + 15) >> 4, bn = (N + 15) >> 4;
+  for (int blk = wave; blk < bm * bn; blk += 4) {
+    const int i0 = (blk / bn) << 4, j0 = (blk % bn) << 4;
+    const int ar = i0 + (lane & 15), bc = j0 + (lane & 15);
+    v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    int k0 = 0;
+    for (; k0 + 8 <= K; k0 += 8) {
+      const int ka = k0 + (lane >> 4), kb = ka + 4;
+      const double a0 = ar < M ? A(ar, ka) : 0.0;
+      const double b0 = bc < N ? B(ka, bc) : 0.0;
+      const double a1 = ar < M ? A(ar, kb) : 0.0;
+      const double b1 = bc < N ? B(kb, bc) : 0.0;
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+    }
+    for (; k0 < K; k0 += 4) {
+      const int ka = k0 + (lane >> 4);
+      const double a0 = (ar < M && ka < K) ? A(ar, ka) : 0.0;
+      const double b0 = (bc < N && ka < K) ? B(ka, bc) : 0.0;
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = i0 + (lane >> 4) + 4 * r, col = j0 + (lane & 15);
+      if (row < M && col < N) store(row, col, acc0[r] + acc1[r]);
+    }
+  }
+}
+
+// Global -> LDS copy with kInFlight independent loads per thread before the
+// LDS stores: one workgroup per CU leaves nothing else to hide the latency.
+constexpr int kInFlight = 8;
+template <typename FL, typename FS>
+__device__ __forceinline__ void g2l(int count, int tid, FL load, FS store) {
+  for (int base = tid; base < count; base += 256 * kInFlight) {
+    double t[kInFlight];
+#pragma unroll
+    for (int u = 0; u < kInFlight; ++u) {
+      const int i = base + u * 256;
+      t[u] = i < count ? load(i) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kInFlight; ++u) {
+      const int i = base + u * 256;
+      if (i < count) store(i, t[u]);
+    }
+  }
+}
+
 struct QrArgs {
   double* A[kMaxProb];   // matrices being factored (in place)
   double* E[kMaxProb];   // explicit Q being formed
   double* O[kMaxProb];   // destination of Q
   double* tau;           // [count][P][nb][kPanel] leaf taus
-  double* tau_node;      // [count][P][nb][kPanel] tree taus, indexed by right child
+  double* Tl;            // [count][P][nb][kPanel*kPanel] leaf WY factors
+  double* Tn;            // [count][P][nb][kPanel*kPanel] tree WY factors (by right child)
   double* sgn;           // [count][k] signs of the diagonal of R
   int count, N, k, nb, P;
 };
 
-__device__ __forceinline__ double* tau_at(double* base, int mat, int p, int leaf, int nb, int P) {
-  return base + (((long)mat * P + p) * nb + leaf) * kPanel;
+__device__ __forceinline__ long slot(int mat, int p, int leaf, int nb, int P) {
+  return ((long)mat * P + p) * nb + leaf;
 }
 
-// Applies the w reflectors of a leaf panel (unit diagonal implicit, V[j][r]
-// for r > j) to one column x held in LDS, in order (Q^T) or reversed (Q).
-// Lane l owns rows l, l+64, ... for the whole call.
-__device__ __forceinline__ void apply_panel(const double (*V)[kLeafRows], const double* tau_s,
-                                            double* x_lds, int m, int w, int lane, bool reverse) {
-  double x[kRowsPerLane];
-#pragma unroll
-  for (int t = 0; t < kRowsPerLane; ++t) {
-    const int r = lane + 64 * t;
-    x[t] = r < m ? x_lds[r] : 0.0;
-  }
-  for (int jj = 0; jj < w; ++jj) {
-    const int j = reverse ? w - 1 - jj : jj;
-    const double tau = tau_s[j];
-    if (tau == 0.0) continue;
-    double v[kRowsPerLane];
-    double d = 0.0;
-#pragma unroll
-    for (int t = 0; t < kRowsPerLane; ++t) {
-      const int r = lane + 64 * t;
-      v[t] = (r > j && r < m) ? V[j][r] : (r == j ? 1.0 : 0.0);
-      d += v[t] * x[t];
+// T (w x w, upper) of H_0...H_(w-1) = I - V T V^T from the Gram matrix
+// G = V^T V and the taus (forward, columnwise): T_jj = tau_j,
+// T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].  One wavefront, lane i = row i.
+__device__ __forceinline__ void build_T(double (*T)[kT], double (*G)[kT], const double* tau,
+                                        int w, int lane) {
+  for (int j = 0; j < w; ++j) {
+    double t = 0.0;
+    if (lane < j) {
+      for (int l = lane; l < j; ++l) t += T[lane][l] * G[l][j];
+      t *= -tau[j];
+      T[lane][j] = t;
     }
-    const double f = tau * wave_sum(d);
-#pragma unroll
-    for (int t = 0; t < kRowsPerLane; ++t) x[t] -= f * v[t];
-  }
-#pragma unroll
-  for (int t = 0; t < kRowsPerLane; ++t) {
-    const int r = lane + 64 * t;
-    if (r < m) x_lds[r] = x[t];
+    if (lane == j) T[j][j] = tau[j];
+    if (lane > j && lane < kPanel) T[lane][j] = 0.0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// leaf factorisation of panel p + update of its trailing columns
+// leaf factorisation of panel p + WY update of its trailing columns
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void qr_leaf_factor(QrArgs q, int p) {
-  __shared__ double V[kPanel][kLeafRows];     // panel, column-major
-  __shared__ double Cc[kPanel][kLeafRows];    // trailing chunk, column-major
+  __shared__ double V[kPanel][kLR];           // panel, column-major
+  __shared__ double Cc[kPanel][kLR];          // trailing chunk, column-major
+  __shared__ double T[kPanel][kT], G[kPanel][kT], W1[kPanel][kT];
   __shared__ double tau_s[kPanel];
   const int leaf = blockIdx.x, mat = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -112,13 +153,12 @@ __global__ __launch_bounds__(256) void qr_leaf_factor(QrArgs q, int p) {
   const int m = e - a0;
   double* A = q.A[mat];
 
-  // load panel rows [a0, e) x columns [c0, c0+w)
-  for (int idx = tid; idx < kPanel * kLeafRows; idx += 256) {
-    const int r = idx / kPanel, c = idx % kPanel;
-    double v = 0.0;
-    if (r < m && c < w) v = A[(long)(a0 + r) * k + c0 + c];
-    V[c][r] = v;
-  }
+  g2l(kPanel * kLeafRows, tid,
+      [&](int idx) {
+        const int r = idx / kPanel, c = idx % kPanel;
+        return (r < m && c < w) ? A[(long)(a0 + r) * k + c0 + c] : 0.0;
+      },
+      [&](int idx, double v) { V[idx % kPanel][idx / kPanel] = v; });
   __syncthreads();
 
   for (int j = 0; j < w; ++j) {
@@ -140,35 +180,75 @@ __global__ __launch_bounds__(256) void qr_leaf_factor(QrArgs q, int p) {
     __syncthreads();
     const double tau = tau_s[j];
     if (tau != 0.0) {
-      for (int c = j + 1 + wave; c < w; c += 4) {
-        double d = 0.0;
-        for (int r = j + 1 + lane; r < m; r += 64) d += V[j][r] * V[c][r];
-        d = wave_sum(d) + V[c][j];
-        const double f = tau * d;
-        for (int r = j + 1 + lane; r < m; r += 64) V[c][r] -= f * V[j][r];
-        if (lane == 0) V[c][j] -= f;
+      // all columns of this wavefront at once: the cross-lane reductions of
+      // the (up to 8) dot products are independent and overlap
+      double d[kPanel / 4];
+#pragma unroll
+      for (int t = 0; t < kPanel / 4; ++t) {
+        const int c = j + 1 + wave + 4 * t;
+        double acc = 0.0;
+        if (c < w)
+          for (int r = j + 1 + lane; r < m; r += 64) acc += V[j][r] * V[c][r];
+        d[t] = acc;
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int t = 0; t < kPanel / 4; ++t) d[t] += __shfl_xor(d[t], off, 64);
+#pragma unroll
+      for (int t = 0; t < kPanel / 4; ++t) {
+        const int c = j + 1 + wave + 4 * t;
+        if (c < w) {
+          const double f = tau * (d[t] + V[c][j]);
+          for (int r = j + 1 + lane; r < m; r += 64) V[c][r] -= f * V[j][r];
+          if (lane == 0) V[c][j] -= f;
+        }
       }
     }
     __syncthreads();
   }
 
-  // write back R (upper) and V (below the diagonal), and the taus
   for (int idx = tid; idx < m * w; idx += 256) {
     const int r = idx / w, c = idx % w;
     A[(long)(a0 + r) * k + c0 + c] = V[c][r];
   }
-  if (tid < w) tau_at(q.tau, mat, p, leaf, nb, q.P)[tid] = tau_s[tid];
+  const long sl = slot(mat, p, leaf, nb, q.P);
+  if (tid < w) q.tau[sl * kPanel + tid] = tau_s[tid];
 
-  // trailing columns [c0+w, k) in chunks of kPanel
+  // unit lower-trapezoidal V (implicit ones, zeros above) of the WY factor
+  auto Veff = [&](int r, int a) -> double {
+    return r > a ? V[a][r] : (r == a ? 1.0 : 0.0);
+  };
+  lds_mm(w, w, m, [&](int a, int r) { return Veff(r, a); }, Veff,
+         [&](int i, int j, double x) { G[i][j] = x; }, wave, lane);
+  __syncthreads();
+  if (wave == 0) build_T(T, G, tau_s, w, lane);
+  __syncthreads();
+  for (int idx = tid; idx < kPanel * kPanel; idx += 256)
+    q.Tl[sl * kPanel * kPanel + idx] = T[idx / kPanel][idx % kPanel];
+
   for (int cb = c0 + w; cb < k; cb += kPanel) {
     const int nc = min(kPanel, k - cb);
     __syncthreads();
-    for (int idx = tid; idx < m * kPanel; idx += 256) {
-      const int r = idx / kPanel, c = idx % kPanel;
-      if (c < nc) Cc[c][r] = A[(long)(a0 + r) * k + cb + c];
-    }
+    g2l(m * kPanel, tid,
+        [&](int idx) {
+          const int r = idx / kPanel, c = idx % kPanel;
+          return c < nc ? A[(long)(a0 + r) * k + cb + c] : 0.0;
+        },
+        [&](int idx, double v) { Cc[idx % kPanel][idx / kPanel] = v; });
     __syncthreads();
-    for (int c = wave; c < nc; c += 4) apply_panel(V, tau_s, Cc[c], m, w, lane, false);
+    // W1 = V^T C  (w x nc)
+    lds_mm(w, nc, m, [&](int a, int r) { return Veff(r, a); },
+           [&](int r, int c) { return Cc[c][r]; }, [&](int i, int j, double x) { W1[i][j] = x; },
+           wave, lane);
+    __syncthreads();
+    // G <- T^T W1   (G reused as scratch)
+    lds_mm(w, nc, w, [&](int i, int l) { return T[l][i]; }, [&](int l, int c) { return W1[l][c]; },
+           [&](int i, int j, double x) { G[i][j] = x; }, wave, lane);
+    __syncthreads();
+    // C -= V G
+    lds_mm(m, nc, w, Veff, [&](int l, int c) { return G[l][c]; },
+           [&](int r, int c, double x) { Cc[c][r] -= x; }, wave, lane);
     __syncthreads();
     for (int idx = tid; idx < m * kPanel; idx += 256) {
       const int r = idx / kPanel, c = idx % kPanel;
@@ -186,8 +266,11 @@ __device__ __forceinline__ int top_row(int leaf, int c0, int N, int nb) {
 // tree combine at level L of panel p: node = right child b, left child b-2^L
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
-  __shared__ double Ra[kPanel][kPanel + 1];   // [row][col]
-  __shared__ double Rb[kPanel][kPanel + 1];
+  __shared__ double Ra[kPanel][kT];   // [row][col]
+  __shared__ double Rb[kPanel][kT];
+  __shared__ double T[kPanel][kT], G[kPanel][kT];
+  __shared__ double Ca[kPanel][kTrail + 1], Cb[kPanel][kTrail + 1];
+  __shared__ double W1[kPanel][kTrail + 1], W2[kPanel][kTrail + 1];
   __shared__ double tau_s[kPanel];
   const int step = 1 << (L + 1);
   const int b = blockIdx.x * step + (1 << L);
@@ -199,18 +282,24 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
   const int ta = top_row(a, c0, N, nb), tb = top_row(b, c0, N, nb);
   double* A = q.A[mat];
-  for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
-    const int r = idx / kPanel, c = idx % kPanel;
-    const bool up = r <= c && r < w && c < w;
-    Ra[r][c] = up ? A[(long)(ta + r) * k + c0 + c] : 0.0;
-    Rb[r][c] = up ? A[(long)(tb + r) * k + c0 + c] : 0.0;
-  }
+  g2l(2 * kPanel * kPanel, tid,
+      [&](int idx) {
+        const int h = idx / (kPanel * kPanel), rc = idx % (kPanel * kPanel);
+        const int r = rc / kPanel, c = rc % kPanel;
+        const bool up = r <= c && r < w && c < w;
+        return up ? A[(long)((h ? tb : ta) + r) * k + c0 + c] : 0.0;
+      },
+      [&](int idx, double v) {
+        const int h = idx / (kPanel * kPanel), rc = idx % (kPanel * kPanel);
+        (h ? Rb : Ra)[rc / kPanel][rc % kPanel] = v;
+      });
   __syncthreads();
   for (int j = 0; j < w; ++j) {
     if (wave == 0) {
       double ss = 0.0;
       if (lane <= j) ss = Rb[lane][j] * Rb[lane][j];
-      ss = wave_sum(ss);
+#pragma unroll
+      for (int off = 16; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
       const double alpha = Ra[j][j];
       double tau = 0.0, beta = alpha, scal = 0.0;
       if (ss > 0.0) {
@@ -225,12 +314,25 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
     __syncthreads();
     const double tau = tau_s[j];
     if (tau != 0.0) {
-      for (int c = j + 1 + wave; c < w; c += 4) {
-        double d = (lane <= j) ? Rb[lane][j] * Rb[lane][c] : 0.0;
-        d = wave_sum(d) + Ra[j][c];
-        const double f = tau * d;
-        if (lane <= j) Rb[lane][c] -= f * Rb[lane][j];
-        if (lane == 0) Ra[j][c] -= f;
+      double d[kPanel / 4];
+#pragma unroll
+      for (int t = 0; t < kPanel / 4; ++t) {
+        const int c = j + 1 + wave + 4 * t;
+        d[t] = (c < w && lane <= j) ? Rb[lane][j] * Rb[lane][c] : 0.0;
+      }
+      // rows live in lanes 0..j <= 31: a 32-lane reduction suffices
+#pragma unroll
+      for (int off = 16; off >= 1; off >>= 1)
+#pragma unroll
+        for (int t = 0; t < kPanel / 4; ++t) d[t] += __shfl_xor(d[t], off, 64);
+#pragma unroll
+      for (int t = 0; t < kPanel / 4; ++t) {
+        const int c = j + 1 + wave + 4 * t;
+        if (c < w) {
+          const double f = tau * (d[t] + Ra[j][c]);
+          if (lane <= j) Rb[lane][c] -= f * Rb[lane][j];
+          if (lane == 0) Ra[j][c] -= f;
+        }
       }
     }
     __syncthreads();
@@ -242,24 +344,52 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
       A[(long)(tb + r) * k + c0 + c] = Rb[r][c];
     }
   }
-  if (tid < w) tau_at(q.tau_node, mat, p, b, nb, q.P)[tid] = tau_s[tid];
-  // trailing columns: rows ta..ta+w and tb..tb+w; one wavefront per column,
-  // lane r < w holds row r of both blocks
-  for (int c = c0 + w + wave; c < k; c += 4) {
-    double xa = (lane < w) ? A[(long)(ta + lane) * k + c] : 0.0;
-    double xb = (lane < w) ? A[(long)(tb + lane) * k + c] : 0.0;
-    for (int j = 0; j < w; ++j) {
-      const double tau = tau_s[j];
-      if (tau == 0.0) continue;
-      const double vb = (lane <= j) ? Rb[lane][j] : 0.0;
-      double d = wave_sum(vb * xb) + __shfl(xa, j, 64);
-      const double f = tau * d;
-      xb -= f * vb;
-      if (lane == j) xa -= f;
+  // Vb = upper triangle of Rb (lower parts of the node's reflectors);
+  // G = I + Vb^T Vb, then T
+  auto Vb = [&](int r, int c) -> double { return r <= c ? Rb[r][c] : 0.0; };
+  lds_mm(w, w, w, [&](int i, int r) { return Vb(r, i); }, Vb,
+         [&](int i, int j, double x) { G[i][j] = x + (i == j ? 1.0 : 0.0); }, wave, lane);
+  __syncthreads();
+  if (wave == 0) build_T(T, G, tau_s, w, lane);
+  __syncthreads();
+  const long sl = slot(mat, p, b, nb, q.P);
+  for (int idx = tid; idx < kPanel * kPanel; idx += 256)
+    q.Tn[sl * kPanel * kPanel + idx] = T[idx / kPanel][idx % kPanel];
+  // trailing columns [c0+w, k) of the 2w rows: W1 = Ca + Vb^T Cb;
+  // W2 = T^T W1; Ca -= W2; Cb -= Vb W2
+  for (int cb = c0 + w; cb < k; cb += kTrail) {
+    const int nc = min(kTrail, k - cb);
+    __syncthreads();
+    g2l(2 * w * kTrail, tid,
+        [&](int idx) {
+          const int h = idx / (w * kTrail), rc = idx % (w * kTrail);
+          const int r = rc / kTrail, c = rc % kTrail;
+          return c < nc ? A[(long)((h ? tb : ta) + r) * k + cb + c] : 0.0;
+        },
+        [&](int idx, double v) {
+          const int h = idx / (w * kTrail), rc = idx % (w * kTrail);
+          (h ? Cb : Ca)[rc / kTrail][rc % kTrail] = v;
+        });
+    __syncthreads();
+    lds_mm(w, nc, w, [&](int i, int r) { return Vb(r, i); }, [&](int r, int c) { return Cb[r][c]; },
+           [&](int i, int j, double x) { W1[i][j] = x + Ca[i][j]; }, wave, lane);
+    __syncthreads();
+    lds_mm(w, nc, w, [&](int i, int l) { return T[l][i]; }, [&](int l, int c) { return W1[l][c]; },
+           [&](int i, int j, double x) { W2[i][j] = x; }, wave, lane);
+    __syncthreads();
+    lds_mm(w, nc, w, Vb, [&](int l, int c) { return W2[l][c]; },
+           [&](int r, int c, double x) { Cb[r][c] -= x; }, wave, lane);
+    for (int idx = tid; idx < w * kTrail; idx += 256) {
+      const int r = idx / kTrail, c = idx % kTrail;
+      if (c < nc) Ca[r][c] -= W2[r][c];
     }
-    if (lane < w) {
-      A[(long)(ta + lane) * k + c] = xa;
-      A[(long)(tb + lane) * k + c] = xb;
+    __syncthreads();
+    for (int idx = tid; idx < w * kTrail; idx += 256) {
+      const int r = idx / kTrail, c = idx % kTrail;
+      if (c < nc) {
+        A[(long)(ta + r) * k + cb + c] = Ca[r][c];
+        A[(long)(tb + r) * k + cb + c] = Cb[r][c];
+      }
     }
   }
 }
@@ -278,9 +408,12 @@ __global__ void qr_init_e(QrArgs q) {
   }
 }
 
+// E rows of the node <- Q_node E on columns [c0, k): W1 = Ea + Vb^T Eb;
+// W2 = T W1; Ea -= W2; Eb -= Vb W2.
 __global__ __launch_bounds__(256) void qr_tree_apply(QrArgs q, int p, int L) {
-  __shared__ double Vb[kPanel][kPanel + 1];
-  __shared__ double tau_s[kPanel];
+  __shared__ double Vs[kPanel][kT], T[kPanel][kT];
+  __shared__ double Ca[kPanel][kTrail + 1], Cb[kPanel][kTrail + 1];
+  __shared__ double W1[kPanel][kTrail + 1], W2[kPanel][kTrail + 1];
   const int step = 1 << (L + 1);
   const int b = blockIdx.x * step + (1 << L);
   const int mat = blockIdx.y;
@@ -292,35 +425,60 @@ __global__ __launch_bounds__(256) void qr_tree_apply(QrArgs q, int p, int L) {
   const int ta = top_row(a, c0, N, nb), tb = top_row(b, c0, N, nb);
   const double* A = q.A[mat];
   double* E = q.E[mat];
-  for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
-    const int r = idx / kPanel, c = idx % kPanel;
-    Vb[r][c] = (r <= c && r < w && c < w) ? A[(long)(tb + r) * k + c0 + c] : 0.0;
-  }
-  if (tid < kPanel) tau_s[tid] = tid < w ? tau_at(q.tau_node, mat, p, b, nb, q.P)[tid] : 0.0;
-  __syncthreads();
-  for (int c = c0 + wave; c < k; c += 4) {
-    double xa = (lane < w) ? E[(long)(ta + lane) * k + c] : 0.0;
-    double xb = (lane < w) ? E[(long)(tb + lane) * k + c] : 0.0;
-    for (int j = w - 1; j >= 0; --j) {
-      const double tau = tau_s[j];
-      if (tau == 0.0) continue;
-      const double vb = (lane <= j) ? Vb[lane][j] : 0.0;
-      double d = wave_sum(vb * xb) + __shfl(xa, j, 64);
-      const double f = tau * d;
-      xb -= f * vb;
-      if (lane == j) xa -= f;
+  const long sl = slot(mat, p, b, nb, q.P);
+  g2l(2 * kPanel * kPanel, tid,
+      [&](int idx) {
+        const int h = idx / (kPanel * kPanel), rc = idx % (kPanel * kPanel);
+        const int r = rc / kPanel, c = rc % kPanel;
+        if (h) return q.Tn[sl * kPanel * kPanel + rc];
+        return (r <= c && r < w && c < w) ? A[(long)(tb + r) * k + c0 + c] : 0.0;
+      },
+      [&](int idx, double v) {
+        const int h = idx / (kPanel * kPanel), rc = idx % (kPanel * kPanel);
+        (h ? T : Vs)[rc / kPanel][rc % kPanel] = v;
+      });
+  for (int cb = c0; cb < k; cb += kTrail) {
+    const int nc = min(kTrail, k - cb);
+    __syncthreads();
+    g2l(2 * w * kTrail, tid,
+        [&](int idx) {
+          const int h = idx / (w * kTrail), rc = idx % (w * kTrail);
+          const int r = rc / kTrail, c = rc % kTrail;
+          return c < nc ? E[(long)((h ? tb : ta) + r) * k + cb + c] : 0.0;
+        },
+        [&](int idx, double v) {
+          const int h = idx / (w * kTrail), rc = idx % (w * kTrail);
+          (h ? Cb : Ca)[rc / kTrail][rc % kTrail] = v;
+        });
+    __syncthreads();
+    lds_mm(w, nc, w, [&](int i, int r) { return Vs[r][i]; }, [&](int r, int c) { return Cb[r][c]; },
+           [&](int i, int j, double x) { W1[i][j] = x + Ca[i][j]; }, wave, lane);
+    __syncthreads();
+    lds_mm(w, nc, w, [&](int i, int l) { return T[i][l]; }, [&](int l, int c) { return W1[l][c]; },
+           [&](int i, int j, double x) { W2[i][j] = x; }, wave, lane);
+    __syncthreads();
+    lds_mm(w, nc, w, [&](int r, int l) { return Vs[r][l]; }, [&](int l, int c) { return W2[l][c]; },
+           [&](int r, int c, double x) { Cb[r][c] -= x; }, wave, lane);
+    for (int idx = tid; idx < w * kTrail; idx += 256) {
+      const int r = idx / kTrail, c = idx % kTrail;
+      if (c < nc) Ca[r][c] -= W2[r][c];
     }
-    if (lane < w) {
-      E[(long)(ta + lane) * k + c] = xa;
-      E[(long)(tb + lane) * k + c] = xb;
+    __syncthreads();
+    for (int idx = tid; idx < w * kTrail; idx += 256) {
+      const int r = idx / kTrail, c = idx % kTrail;
+      if (c < nc) {
+        E[(long)(ta + r) * k + cb + c] = Ca[r][c];
+        E[(long)(tb + r) * k + cb + c] = Cb[r][c];
+      }
     }
   }
 }
 
+// E rows of the leaf <- Q_leaf E on columns [c0, k): C -= V T (V^T C).
 __global__ __launch_bounds__(256) void qr_leaf_apply(QrArgs q, int p) {
-  __shared__ double V[kPanel][kLeafRows];
-  __shared__ double Cc[kPanel][kLeafRows];
-  __shared__ double tau_s[kPanel];
+  __shared__ double V[kPanel][kLR];
+  __shared__ double Cc[kPanel][kLR];
+  __shared__ double T[kPanel][kT], W1[kPanel][kT], W2[kPanel][kT];
   const int leaf = blockIdx.x, mat = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = q.N, k = q.k, nb = q.nb;
@@ -330,22 +488,34 @@ __global__ __launch_bounds__(256) void qr_leaf_apply(QrArgs q, int p) {
   const int m = e - a0;
   const double* A = q.A[mat];
   double* E = q.E[mat];
-  for (int idx = tid; idx < kPanel * kLeafRows; idx += 256) {
-    const int r = idx / kPanel, c = idx % kPanel;
-    double v = 0.0;
-    if (r < m && c < w && r > c) v = A[(long)(a0 + r) * k + c0 + c];
-    V[c][r] = v;
-  }
-  if (tid < kPanel) tau_s[tid] = tid < w ? tau_at(q.tau, mat, p, leaf, nb, q.P)[tid] : 0.0;
+  const long sl = slot(mat, p, leaf, nb, q.P);
+  g2l(kPanel * kLeafRows, tid,
+      [&](int idx) {
+        const int r = idx / kPanel, c = idx % kPanel;
+        if (r >= m || c >= w) return 0.0;
+        return r > c ? A[(long)(a0 + r) * k + c0 + c] : (r == c ? 1.0 : 0.0);
+      },
+      [&](int idx, double v) { V[idx % kPanel][idx / kPanel] = v; });
+  g2l(kPanel * kPanel, tid, [&](int idx) { return q.Tl[sl * kPanel * kPanel + idx]; },
+      [&](int idx, double v) { T[idx / kPanel][idx % kPanel] = v; });
   for (int cb = c0; cb < k; cb += kPanel) {
     const int nc = min(kPanel, k - cb);
     __syncthreads();
-    for (int idx = tid; idx < m * kPanel; idx += 256) {
-      const int r = idx / kPanel, c = idx % kPanel;
-      if (c < nc) Cc[c][r] = E[(long)(a0 + r) * k + cb + c];
-    }
+    g2l(m * kPanel, tid,
+        [&](int idx) {
+          const int r = idx / kPanel, c = idx % kPanel;
+          return c < nc ? E[(long)(a0 + r) * k + cb + c] : 0.0;
+        },
+        [&](int idx, double v) { Cc[idx % kPanel][idx / kPanel] = v; });
     __syncthreads();
-    for (int c = wave; c < nc; c += 4) apply_panel(V, tau_s, Cc[c], m, w, lane, true);
+    lds_mm(w, nc, m, [&](int a, int r) { return V[a][r]; }, [&](int r, int c) { return Cc[c][r]; },
+           [&](int i, int j, double x) { W1[i][j] = x; }, wave, lane);
+    __syncthreads();
+    lds_mm(w, nc, w, [&](int i, int l) { return T[i][l]; }, [&](int l, int c) { return W1[l][c]; },
+           [&](int i, int j, double x) { W2[i][j] = x; }, wave, lane);
+    __syncthreads();
+    lds_mm(m, nc, w, [&](int r, int l) { return V[l][r]; }, [&](int l, int c) { return W2[l][c]; },
+           [&](int r, int c, double x) { Cc[c][r] -= x; }, wave, lane);
     __syncthreads();
     for (int idx = tid; idx < m * kPanel; idx += 256) {
       const int r = idx / kPanel, c = idx % kPanel;
@@ -396,9 +566,10 @@ QrPlan make_plan(int N, int k) {
 
 size_t qr_workspace_bytes(int count, int N, int k) {
   const QrPlan pl = make_plan(N, k);
-  const size_t taus = 2ull * count * pl.P * pl.nb * kPanel;
-  const size_t e = (size_t)count * N * k + (size_t)count * k;
-  return (taus + e) * sizeof(double);
+  const size_t slots = (size_t)count * pl.P * pl.nb;
+  const size_t n = slots * kPanel + 2 * slots * kPanel * kPanel + (size_t)count * N * k +
+                   (size_t)count * k;
+  return n * sizeof(double);
 }
 
 int launch_qr(int count, double* const* W, int N, int k, void* ws, hipStream_t s) {
@@ -418,10 +589,12 @@ int launch_qr(int count, double* const* W, int N, int k, void* ws, hipStream_t s
   q.k = k;
   q.nb = pl.nb;
   q.P = pl.P;
+  const size_t slots = (size_t)count * pl.P * pl.nb;
   double* base = (double*)ws;
   q.tau = base;
-  q.tau_node = base + (size_t)count * pl.P * pl.nb * kPanel;
-  double* e = q.tau_node + (size_t)count * pl.P * pl.nb * kPanel;
+  q.Tl = q.tau + slots * kPanel;
+  q.Tn = q.Tl + slots * kPanel * kPanel;
+  double* e = q.Tn + slots * kPanel * kPanel;
   for (int i = 0; i < count; ++i) {
     q.A[i] = W[i];
     q.E[i] = e + (size_t)i * N * k;

@@ -2,31 +2,41 @@
 // projector section, step 2), and of the chi x chi corners for the
 // convergence measure.
 //
-// One-sided (Hestenes) Jacobi: U <- A V with V accumulating plane rotations
+// One-sided (Hestenes) Jacobi: U <- X V with V accumulating plane rotations
 // until all column pairs of U are orthogonal to working precision; then
 // s_j = |u_j|, u_j <- u_j / s_j.  One-sided Jacobi computes small singular
 // values to high relative accuracy, which matters here because the
 // pseudo-inverse s^-1/2 keeps directions down to a relative 1e-12.
+// Preconditioning (Drmac & Veselic): the columns of A are sorted by norm
+// (permutation P), A P = Q R by the Householder QR of this library, and the
+// Jacobi iteration runs on X = R^T, which converges in a few sweeps where A
+// itself needs dozens: R^T = Ut S V'^T gives A = (Q V') S (P Ut)^T.
 //
-// One workgroup of 1024 threads (16 wavefronts) per matrix.  A sweep visits
-// all n(n-1)/2 pairs in n-1 rounds of n/2 disjoint pairs (round-robin
-// tournament order); each wavefront rotates its pairs with the column data in
-// registers (rows spread over the 64 lanes, reductions by cross-lane
-// shuffles), and rounds are separated by workgroup barriers.  The working
-// columns live in the workspace (L2-resident).  Sweeps stop when a full sweep
-// performs no rotation.  Columns that end exactly zero (rank-deficient input)
-// are replaced by an orthonormal completion so that u stays orthogonal.
-// Singular values are returned in descending order (ties by index).
+// Block-pair parallel ordering: the columns are cut into blocks of kBlk; an
+// outer sweep pairs the blocks in a round-robin tournament, one launch per
+// round, one workgroup per block pair and matrix.  The workgroup loads the
+// 2 kBlk columns of U (and V) into LDS and rotates all pairs among them in
+// 2 kBlk - 1 inner rounds of kBlk disjoint pairs, 16 lanes per pair
+// (rows spread over the lanes, dot products reduced by cross-lane shuffles).
+// Every column pair meets in every outer sweep; a per-matrix flag records
+// whether a sweep rotated anything, and later launches return at once after
+// a sweep without rotations.  Columns that end exactly zero (rank-deficient
+// input) are replaced by an orthonormal completion so that u stays
+// orthogonal.  Singular values are returned in descending order (ties by
+// index).
 
 #include "common.h"
 
 namespace sictm {
 namespace {
 
-constexpr int kSvdThreads = 1024;
 constexpr int kSvdMaxN = 256;
-constexpr int kRPL = kSvdMaxN / 64;   // rows per lane
-constexpr int kMaxSweeps = 40;
+constexpr int kRPL = kSvdMaxN / 64;   // rows per lane in the finalisation
+constexpr int kBlk = 16;              // columns per block
+constexpr int kMaxSweeps = 24;
+constexpr int kInner = 2;            // inner sweeps per block-pair visit
+constexpr int kLanesPerPair = 16;
+constexpr int kRowsPerLane = kSvdMaxN / kLanesPerPair;
 
 __device__ __forceinline__ double wsum(double x) {
 #pragma unroll
@@ -34,96 +44,210 @@ __device__ __forceinline__ double wsum(double x) {
   return x;
 }
 
+__device__ __forceinline__ double gsum16(double x) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
 struct SvdArgs {
-  const double* A[kMaxProb];
-  double* U[kMaxProb];
+  const double* A[kMaxProb];   // matrices the Jacobi kernels act on (R^T)
+  double* U[kMaxProb];         // Jacobi outputs: left vectors of R^T (Ut) ...
   double* S[kMaxProb];
-  double* V[kMaxProb];
-  double* work;       // [count][2][n][n] column-major U, V
-  int n;
+  double* V[kMaxProb];         // ... and right vectors (V')
+  double* work;       // [count][2][n][n] column-major working columns
+  int* flags;         // [count][kMaxSweeps] "a rotation happened in sweep s"
+  int n, nblk, want_v;
+  // preconditioning
+  const double* Ain[kMaxProb]; // the caller's matrices
+  double* Wp[kMaxProb];        // A P, then Q
+  double* Wc[kMaxProb];        // A P
+  double* Ut[kMaxProb];        // left vectors of R^T
+  int* perm;                   // [count][n]
+  double* fro2;                // [count] squared Frobenius norm of each input
 };
 
-__global__ __launch_bounds__(kSvdThreads) void jacobi_svd(SvdArgs a) {
-  const int mat = blockIdx.x;
+// Tournament position -> block / column index (position 0 fixed).
+__device__ __forceinline__ int tour(int pos, int round, int m) {
+  return pos == 0 ? 0 : ((pos - 1 + round) % (m - 1)) + 1;
+}
+
+__global__ void svd_init(SvdArgs a) {
+  const int mat = blockIdx.y;
   const int n = a.n;
-  const int ne = n + (n & 1);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int nwaves = kSvdThreads / 64;
-  double* Uc = a.work + (size_t)mat * 2 * n * n;   // column c at Uc + c*n
+  double* Uc = a.work + (size_t)mat * 2 * n * n;
   double* Vc = Uc + (size_t)n * n;
-  const bool want_v = a.V[mat] != nullptr;
   const double* A = a.A[mat];
-
-  __shared__ int rotated;
-  __shared__ double snorm[kSvdMaxN];
-  __shared__ int order[kSvdMaxN];
-
-  for (int i = tid; i < n * n; i += kSvdThreads) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * n; i += gridDim.x * blockDim.x) {
     const int r = i / n, c = i % n;
     Uc[(size_t)c * n + r] = A[i];
-    Vc[(size_t)c * n + r] = (r == c) ? 1.0 : 0.0;
+    if (a.want_v) Vc[(size_t)c * n + r] = (r == c) ? 1.0 : 0.0;
+  }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kMaxSweeps; i += blockDim.x) a.flags[mat * kMaxSweeps + i] = 0;
+}
+
+// Column norms, stable descending sort -> perm; Wp = Wc = A[:, perm].
+__global__ __launch_bounds__(256) void svd_prep(SvdArgs a) {
+  __shared__ double nrm[kSvdMaxN];
+  __shared__ int perm[kSvdMaxN];
+  const int mat = blockIdx.x, n = a.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* A = a.Ain[mat];
+  for (int c = wave; c < n; c += 4) {
+    double ss = 0.0;
+    for (int r = lane; r < n; r += 64) ss += A[(size_t)r * n + c] * A[(size_t)r * n + c];
+    ss = wsum(ss);
+    if (lane == 0) nrm[c] = ss;
   }
   __syncthreads();
+  if (tid == 0) {
+    double f = 0.0;
+    for (int c = 0; c < n; ++c) f += nrm[c];
+    a.fro2[mat] = f;
+  }
+  for (int c = tid; c < n; c += 256) {
+    int rank = 0;
+    for (int o = 0; o < n; ++o) rank += (nrm[o] > nrm[c]) || (nrm[o] == nrm[c] && o < c);
+    perm[rank] = c;
+  }
+  __syncthreads();
+  int* pg = a.perm + (size_t)mat * n;
+  for (int c = tid; c < n; c += 256) pg[c] = perm[c];
+  double* Wp = a.Wp[mat];
+  double* Wc = a.Wc[mat];
+  for (int i = tid; i < n * n; i += 256) {
+    const int r = i / n, j = i % n;
+    const double v = A[(size_t)r * n + perm[j]];
+    Wp[i] = v;
+    Wc[i] = v;
+  }
+}
 
-  const double tol = 1e-15 * sqrt((double)n);
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    int my_rot = 0;
-    for (int round = 0; round < ne - 1; ++round) {
-      for (int pi = wave; pi < ne / 2; pi += nwaves) {
-        // tournament positions pi and ne-1-pi
-        const int pos_a = pi, pos_b = ne - 1 - pi;
-        int ca = pos_a == 0 ? 0 : ((pos_a - 1 + round) % (ne - 1)) + 1;
-        int cb = ((pos_b - 1 + round) % (ne - 1)) + 1;
-        if (ca >= n || cb >= n) continue;
-        const int p = min(ca, cb), q = max(ca, cb);
-        double up[kRPL], uq[kRPL];
-        double al = 0.0, be = 0.0, ga = 0.0;
+// v[perm[i], :] = Ut[i, :]
+__global__ void svd_unpermute_rows(SvdArgs a) {
+  const int mat = blockIdx.y, n = a.n;
+  const int* pg = a.perm + (size_t)mat * n;
+  const double* Ut = a.Ut[mat];
+  double* V = a.V[mat];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * n; i += gridDim.x * blockDim.x) {
+    const int r = i / n, c = i % n;
+    V[(size_t)pg[r] * n + c] = Ut[i];
+  }
+}
+
+// One round of an outer sweep: block pair (tournament positions bp, nblk-1-bp).
+__global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int round) {
+  __shared__ double Ul[2 * kBlk][kSvdMaxN + 1];   // odd row length: no bank conflicts
+  __shared__ double Vl[2 * kBlk][kSvdMaxN + 1];
+  __shared__ int rot;
+  const int mat = blockIdx.y;
+  if (sweep > 0 && a.flags[mat * kMaxSweeps + sweep - 1] == 0) return;   // converged
+  const int n = a.n, nblk = a.nblk;
+  const int bp = blockIdx.x;
+  const int b0 = tour(bp, round, nblk), b1 = tour(nblk - 1 - bp, round, nblk);
+  const int tid = threadIdx.x;
+  double* Uc = a.work + (size_t)mat * 2 * n * n;
+  double* Vc = Uc + (size_t)n * n;
+  // local column j -> global column: j < kBlk from b0, else from b1
+  auto gcol = [&](int j) { return (j < kBlk ? b0 : b1) * kBlk + (j % kBlk); };
+  // 8 independent loads in flight per thread (one workgroup per CU)
+  const int nv = a.want_v ? 2 : 1;
+  for (int base = tid; base < nv * 2 * kBlk * n; base += 256 * 8) {
+    double t[8];
 #pragma unroll
-        for (int t = 0; t < kRPL; ++t) {
-          const int r = lane + 64 * t;
-          up[t] = r < n ? Uc[(size_t)p * n + r] : 0.0;
-          uq[t] = r < n ? Uc[(size_t)q * n + r] : 0.0;
-          al += up[t] * up[t];
-          be += uq[t] * uq[t];
-          ga += up[t] * uq[t];
-        }
-        al = wsum(al);
-        be = wsum(be);
-        ga = wsum(ga);
-        if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * 256;
+      const int h = idx / (2 * kBlk * n), rem = idx % (2 * kBlk * n);
+      const int g = gcol(rem / n);
+      t[u] = (idx < nv * 2 * kBlk * n && g < n) ? (h ? Vc : Uc)[(size_t)g * n + rem % n] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * 256;
+      if (idx < nv * 2 * kBlk * n) {
+        const int h = idx / (2 * kBlk * n), rem = idx % (2 * kBlk * n);
+        (h ? Vl : Ul)[rem / n][rem % n] = t[u];
+      }
+    }
+  }
+  if (tid == 0) rot = 0;
+  __syncthreads();
+  const int grp = tid / kLanesPerPair, li = tid % kLanesPerPair;   // 16 pair groups
+  const double tol = 1e-15 * sqrt((double)n);
+  // columns below 1e-15 of the matrix norm are numerically zero: rotating
+  // them against the others cannot converge in the relative sense and does
+  // not change the result above roundoff; they are completed at the end
+  const double negl = 1e-30 * a.fro2[mat];
+  int my_rot = 0;
+  for (int rr = 0; rr < kInner * (2 * kBlk - 1); ++rr) {
+    const int r = rr % (2 * kBlk - 1);
+    const int ca = tour(grp, r, 2 * kBlk), cb = tour(2 * kBlk - 1 - grp, r, 2 * kBlk);
+    const int p = min(ca, cb), q = max(ca, cb);
+    const bool live = gcol(p) < n && gcol(q) < n;
+    if (live) {
+      double up[kRowsPerLane], uq[kRowsPerLane];
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int t = 0; t < kRowsPerLane; ++t) {
+        const int row = li + kLanesPerPair * t;
+        up[t] = row < n ? Ul[p][row] : 0.0;
+        uq[t] = row < n ? Ul[q][row] : 0.0;
+        al += up[t] * up[t];
+        be += uq[t] * uq[t];
+        ga += up[t] * uq[t];
+      }
+      al = gsum16(al);
+      be = gsum16(be);
+      ga = gsum16(ga);
+      const double thr = tol * sqrt(al) * sqrt(be);
+      if (ga != 0.0 && fabs(ga) > thr && al > negl && be > negl) {
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        ++my_rot;
+        // convergence counts only rotations clearly above roundoff: a pair
+        // left at |gamma| ~ tol sqrt(alpha beta) keeps being rotated but does
+        // not prevent the sweep loop from stopping
+        if (fabs(ga) > 16.0 * thr) ++my_rot;
 #pragma unroll
-        for (int tt = 0; tt < kRPL; ++tt) {
-          const int r = lane + 64 * tt;
-          if (r < n) {
-            Uc[(size_t)p * n + r] = c * up[tt] - s * uq[tt];
-            Uc[(size_t)q * n + r] = s * up[tt] + c * uq[tt];
-          }
-        }
-        if (want_v) {
-#pragma unroll
-          for (int tt = 0; tt < kRPL; ++tt) {
-            const int r = lane + 64 * tt;
-            if (r < n) {
-              const double vp = Vc[(size_t)p * n + r], vq = Vc[(size_t)q * n + r];
-              Vc[(size_t)p * n + r] = c * vp - s * vq;
-              Vc[(size_t)q * n + r] = s * vp + c * vq;
+        for (int tt = 0; tt < kRowsPerLane; ++tt) {
+          const int row = li + kLanesPerPair * tt;
+          if (row < n) {
+            Ul[p][row] = c * up[tt] - s * uq[tt];
+            Ul[q][row] = s * up[tt] + c * uq[tt];
+            if (a.want_v) {
+              const double vp = Vl[p][row], vq = Vl[q][row];
+              Vl[p][row] = c * vp - s * vq;
+              Vl[q][row] = s * vp + c * vq;
             }
           }
         }
       }
-      __syncthreads();
     }
-    if (lane == 0 && my_rot) atomicAdd(&rotated, my_rot);
     __syncthreads();
-    if (rotated == 0) break;
   }
+  if (li == 0 && my_rot) atomicAdd(&rot, my_rot);
+  __syncthreads();
+  for (int idx = tid; idx < 2 * kBlk * n; idx += 256) {
+    const int j = idx / n, rr = idx % n;
+    const int g = gcol(j);
+    if (g < n) {
+      Uc[(size_t)g * n + rr] = Ul[j][rr];
+      if (a.want_v) Vc[(size_t)g * n + rr] = Vl[j][rr];
+    }
+  }
+  if (tid == 0 && rot) atomicOr(&a.flags[mat * kMaxSweeps + sweep], 1);
+}
 
+// Singular values, normalisation, completion of zero columns, ordering.
+__global__ __launch_bounds__(1024) void svd_finalize(SvdArgs a) {
+  const int mat = blockIdx.x;
+  const int n = a.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int nwaves = 1024 / 64;
+  double* Uc = a.work + (size_t)mat * 2 * n * n;
+  double* Vc = Uc + (size_t)n * n;
+  __shared__ double snorm[kSvdMaxN];
+  __shared__ int order[kSvdMaxN];
   // singular values = column norms
   for (int c = wave; c < n; c += nwaves) {
     double ss = 0.0;
@@ -139,18 +263,20 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd(SvdArgs a) {
       for (int r = lane; r < n; r += 64) Uc[(size_t)c * n + r] /= sn;
   }
   __syncthreads();
-  // orthonormal completion of exactly-zero columns (sequential, wavefront 0)
+  // orthonormal completion of numerically zero columns (sequential, wavefront
+  // 0); the cut is the one below which the rotations left a column alone
+  const double zero_cut = 1e-15 * sqrt(a.fro2[mat]);
   if (a.U[mat] != nullptr && wave == 0) {
     int cand = 0;
     for (int c = 0; c < n; ++c) {
-      if (snorm[c] > 0.0) continue;
+      if (snorm[c] > zero_cut) continue;
       for (; cand < n; ++cand) {
         double x[kRPL];
 #pragma unroll
         for (int t = 0; t < kRPL; ++t) x[t] = (lane + 64 * t == cand) ? 1.0 : 0.0;
         for (int pass = 0; pass < 2; ++pass) {
           for (int o = 0; o < n; ++o) {
-            if (o == c || (snorm[o] <= 0.0 && o > c)) continue;
+            if (o == c || (snorm[o] <= zero_cut && o > c)) continue;
             double d = 0.0;
 #pragma unroll
             for (int t = 0; t < kRPL; ++t) {
@@ -183,7 +309,7 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd(SvdArgs a) {
   }
   __syncthreads();
   // descending order, ties by index
-  for (int c = tid; c < n; c += kSvdThreads) {
+  for (int c = tid; c < n; c += 1024) {
     const double sc = snorm[c];
     int rank = 0;
     for (int o = 0; o < n; ++o) {
@@ -196,8 +322,8 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd(SvdArgs a) {
   double* S = a.S[mat];
   double* U = a.U[mat];
   double* V = a.V[mat];
-  for (int i = tid; i < n; i += kSvdThreads) S[i] = snorm[order[i]];
-  for (int i = tid; i < n * n; i += kSvdThreads) {
+  for (int i = tid; i < n; i += 1024) S[i] = snorm[order[i]];
+  for (int i = tid; i < n * n; i += 1024) {
     const int r = i / n, j = i % n;
     const int c = order[j];
     if (U) U[i] = Uc[(size_t)c * n + r];
@@ -207,7 +333,12 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd(SvdArgs a) {
 
 }  // namespace
 
-size_t svd_workspace_bytes(int count, int n) { return (size_t)count * 2 * n * n * sizeof(double); }
+size_t svd_workspace_bytes(int count, int n) {
+  const size_t nn = (size_t)n * n;
+  return (size_t)count * (2 * nn + 5 * nn) * sizeof(double) +
+         (size_t)count * (kMaxSweeps + n) * sizeof(int) + (size_t)count * sizeof(double) +
+         qr_workspace_bytes(count, n, n) + 4096;
+}
 
 int launch_svd(int count, const double* const* A, double* const* U, double* const* S,
                double* const* V, int n, void* ws, hipStream_t s) {
@@ -216,17 +347,80 @@ int launch_svd(int count, const double* const* A, double* const* U, double* cons
     set_thread_error("launch_svd: n <= 256 and at most 8 matrices per launch");
     return 1;
   }
+  const size_t nn = (size_t)n * n;
+  double* base = (double*)ws;
   SvdArgs a{};
   a.n = n;
-  a.work = (double*)ws;
+  a.work = base;                                   // 2 nn per matrix
+  double* wp = a.work + (size_t)count * 2 * nn;    // A P -> Q
+  double* wc = wp + (size_t)count * nn;            // A P
+  double* rt = wc + (size_t)count * nn;            // R^T
+  double* ut = rt + (size_t)count * nn;            // left vectors of R^T
+  double* vp = ut + (size_t)count * nn;            // right vectors of R^T
+  a.flags = (int*)(vp + (size_t)count * nn);
+  a.perm = a.flags + (size_t)count * kMaxSweeps;
+  a.fro2 = (double*)(((uintptr_t)(a.perm + (size_t)count * n) + 7) & ~(uintptr_t)7);
+  char* qws = (char*)(a.fro2 + count);
+  qws = (char*)(((uintptr_t)qws + 255) & ~(uintptr_t)255);
+  int nblk = (n + kBlk - 1) / kBlk;
+  nblk += nblk & 1;
+  if (nblk < 2) nblk = 2;
+  a.nblk = nblk;
+  const bool want_u = U != nullptr, want_vout = V != nullptr;
+  a.want_v = want_u ? 1 : 0;                       // V' is needed for u = Q V'
+  double* qptr[kMaxProb];
   for (int i = 0; i < count; ++i) {
-    a.A[i] = A[i];
-    a.U[i] = U ? U[i] : nullptr;
+    a.Ain[i] = A[i];
+    a.Wp[i] = wp + i * nn;
+    a.Wc[i] = wc + i * nn;
+    a.A[i] = rt + i * nn;
+    a.Ut[i] = ut + i * nn;
+    a.U[i] = want_vout ? a.Ut[i] : nullptr;
     a.S[i] = S[i];
-    a.V[i] = V ? V[i] : nullptr;
+    a.V[i] = want_u ? vp + i * nn : nullptr;
+    qptr[i] = a.Wp[i];
   }
-  jacobi_svd<<<count, kSvdThreads, 0, s>>>(a);
+  svd_prep<<<count, 256, 0, s>>>(a);
   CTM_HIP_TRY(hipGetLastError());
+  int r = launch_qr(count, qptr, n, n, qws, s);
+  if (r) return r;
+  // R^T = (A P)^T Q
+  GemmBatch g{};
+  g.count = count;
+  g.M = g.N = g.K = n;
+  g.lda = g.ldb = n;
+  gemm_set_rowmajor_c(g, n);
+  g.nbatch = 1;
+  g.alpha = 1.0;
+  for (int i = 0; i < count; ++i) {
+    g.A[i] = a.Wc[i];
+    g.transA[i] = 1;
+    g.B[i] = a.Wp[i];
+    g.C[i] = rt + i * nn;
+  }
+  r = launch_gemm(g, DT::F64, DT::F64, DT::F64, s);
+  if (r) return r;
+  svd_init<<<dim3(std::max(1, std::min(64, n * n / 256)), count), 256, 0, s>>>(a);
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep)
+    for (int round = 0; round < nblk - 1; ++round)
+      svd_block_round<<<dim3(nblk / 2, count), 256, 0, s>>>(a, sweep, round);
+  svd_finalize<<<count, 1024, 0, s>>>(a);
+  CTM_HIP_TRY(hipGetLastError());
+  if (want_u) {   // u = Q V'
+    for (int i = 0; i < count; ++i) {
+      g.A[i] = a.Wp[i];
+      g.transA[i] = 0;
+      g.B[i] = vp + i * nn;
+      g.C[i] = U[i];
+    }
+    r = launch_gemm(g, DT::F64, DT::F64, DT::F64, s);
+    if (r) return r;
+  }
+  if (want_vout) {   // v = P Ut
+    for (int i = 0; i < count; ++i) a.V[i] = V[i];
+    svd_unpermute_rows<<<dim3(std::max(1, std::min(64, n * n / 256)), count), 256, 0, s>>>(a);
+    CTM_HIP_TRY(hipGetLastError());
+  }
   return 0;
 }
 
