@@ -3,7 +3,7 @@
 The binding only marshals arguments: every step of a CTMRG move runs in the
 library's HIP kernels.  PyTorch supplies device memory (the workspace and the
 input tensors) and the stream.  Importing this package fails loudly when the
-library has not been built (``python -m paper_2607_15158_amd.build_lib``).
+library has not been built (``python paper_2607_15158_amd/build_lib.py``).
 """
 from __future__ import annotations
 
@@ -21,6 +21,13 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build it with `python paper_2607_15158_amd/build_lib.py` "
         "(the HIP library is required; there is no CPU fallback)")
+
+# torch is imported first so that its HIP runtime is the one in the process:
+# the library's libamdhip64.so.7 / libhsa-runtime64.so.1 dependencies then
+# bind to the copies torch already loaded (same sonames).  Loading the
+# library first would bring in a second HIP/HSA runtime, which cannot share
+# the device, the streams or the allocations with torch.
+import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 

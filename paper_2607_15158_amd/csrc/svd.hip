@@ -295,7 +295,9 @@ __global__ __launch_bounds__(1024) void svd_finalize(SvdArgs a) {
 #pragma unroll
         for (int t = 0; t < kRPL; ++t) nn += x[t] * x[t];
         nn = sqrt(wsum(nn));
-        if (nn > 0.5) {
+        // the complement has dimension >= 1, so some unit vector keeps at
+        // least 1/sqrt(n) of its length after the projection
+        if (nn > 0.5 / sqrt((double)n)) {
 #pragma unroll
           for (int t = 0; t < kRPL; ++t) {
             const int r = lane + 64 * t;

@@ -76,3 +76,15 @@ def test_null_arguments_are_errors_not_crashes():
     assert P._lib.ctm_init(ctypes.byref(h), ctypes.byref(c), None, None, None, 0, None) == P.CTM_E_ARG
     assert P._lib.ctm_move(None, None) == P.CTM_E_ARG
     assert P._lib.ctm_observable(None, 0, None, None) == P.CTM_E_ARG
+
+
+def test_single_hip_runtime_in_process():
+    """The library shares torch's HIP/HSA runtime instead of loading a second one.
+
+    Two runtimes in one process cannot share the device: whichever initialises
+    second reports that no GPU is present.
+    """
+    maps = open("/proc/self/maps").read().splitlines()
+    for stem in ("libamdhip64", "libhsa-runtime64"):
+        files = {ln.split()[-1] for ln in maps if stem in ln.split()[-1]}
+        assert len(files) <= 1, files
