@@ -13,8 +13,10 @@ Also reported, in the same JSON line:
   * roofline of the dominant kernel (the enlarged-corner applications of the
     subspace iteration) from HIP events recorded around every launch of it on
     the library's stream during the timed region;
-  * the full-SVD CTMRG move on the same GPU (rocSOLVER dgesvd of the four
-    5184 x 5184 M_b), timed over --svd-moves moves;
+  * the full-SVD CTMRG move on the same GPU (the four 5184 x 5184 M_b formed
+    with the library's GEMM and decomposed with rocSOLVER's divide-and-conquer
+    dgesdd, the fastest dense SVD available there), timed over --svd-moves
+    moves from the same environment;
   * the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
@@ -45,26 +47,37 @@ def workload(D=6, chi=144, p=16, seed=3):
     return A, X, Y
 
 
-def cpu_baseline(args, A, X, Y, state=None):
-    """Times the FP64 oracle on one SI move of the same workload (bounded sample)."""
+def cpu_baseline(args, A, X, Y):
+    """Times the FP64 oracle on a bounded sample of one SI move of this workload.
+
+    The sample is steps 1-4 of the move: the four enlarged corners and the SI
+    projectors of the four bonds (n_si subspace steps with QRs, rho, its SVD,
+    the projectors and the recycled blocks).  The oracle's renormalisation of
+    the edges (its a-absorption contractions run in NumPy's einsum loops) takes
+    several minutes at this size and is left out, so the rate reported is an
+    upper bound on the oracle's move rate.  The environment is a seeded random
+    one of the move's shapes (the cost does not depend on the values).
+    """
     import oracle as O
     import synth as S
     threads = len(os.sched_getaffinity(0))
     chi, D = args.chi, args.D
+    Dl = D * D
     a = O.double_layer(A)
-    env = O.initial_env(a, S.trace_boundary(D))
+    env = O.Env([S.gaussian_block(chi, chi, 60 + i) for i in range(4)],
+                [S.gaussian_block(chi * Dl, chi, 70 + i).reshape(chi, Dl, chi) for i in range(4)])
     t0 = time.perf_counter()
-    if state is not None:
-        env = state
-    else:
-        env, _ = O.ctm_move(env, a, chi, "si", None, eps=args.pinv_rtol)    # growth move
-    si = O.SIState(list(X), list(Y))
+    Ct = O.enlarged_corners(env, a)
     t1 = time.perf_counter()
-    env, _ = O.ctm_move(env, a, chi, "si", si, n_si=args.n_si, eps=args.pinv_rtol)
+    for b in range(4):
+        O.si_projectors(Ct, b, X[b], Y[b], chi, args.n_si, args.pinv_rtol, True)
     t2 = time.perf_counter()
-    return {"value": 1.0 / (t2 - t1), "unit": "moves/s", "cores": threads, "kind": "oracle",
-            "sample": f"one SI move (n_si={args.n_si}) of the same D={D}, chi={chi} workload, "
-                      f"numpy/OpenBLAS float64, {t2 - t1:.1f} s (+{t1 - t0:.1f} s growth move untimed)"}
+    return {"value": round(1.0 / (t2 - t0), 5), "unit": "moves/s", "cores": threads, "kind": "oracle",
+            "sample": f"steps 1-4 of one SI move (n_si={args.n_si}) of the same D={D}, chi={chi} "
+                      f"workload: enlarged corners {t1 - t0:.1f} s + SI projectors of the four "
+                      f"bonds {t2 - t1:.1f} s, numpy float64 on {threads} threads; the edge "
+                      f"renormalisation (minutes in the oracle) is not in the sample, so the "
+                      f"value is an upper bound on the oracle's full-move rate"}
 
 
 def main():
@@ -78,7 +91,9 @@ def main():
     ap.add_argument("--n-si", type=int, default=2)
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--pinv-rtol", type=float, default=1e-12)
-    ap.add_argument("--svd-moves", type=int, default=1, help="full-SVD comparator moves (0: skip)")
+    ap.add_argument("--svd-moves", type=int, default=2, help="full-SVD comparator moves (0: skip)")
+    ap.add_argument("--svd-driver", default="gesdd", choices=["gesdd", "gesvd"],
+                    help="dense SVD of the growth move and of the full-SVD comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -93,7 +108,8 @@ def main():
     dev = torch.device("cuda", 0)
     A, X, Y = workload(args.D, args.chi, args.p)
     cfg = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="si",
-                   prec=args.prec, stabilized=1, pinv_rtol=args.pinv_rtol)
+                   prec=args.prec, stabilized=1, pinv_rtol=args.pinv_rtol,
+                   svd_driver=args.svd_driver)
     log(f"config d=2 D={args.D} chi={args.chi} k={cfg.k} N={cfg.N} prec={args.prec}; "
         f"workspace {P.workspace_bytes(cfg) / 2**30:.2f} GiB")
     ctx = P.Ctm(cfg, torch.from_numpy(A).to(dev))
@@ -143,7 +159,8 @@ def main():
     svd = None
     if args.svd_moves > 0:
         cfg_s = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="svd",
-                         prec="f64", stabilized=1, pinv_rtol=args.pinv_rtol)
+                         prec="f64", stabilized=1, pinv_rtol=args.pinv_rtol,
+                         svd_driver=args.svd_driver)
         del ctx
         torch.cuda.empty_cache()
         cs = P.Ctm(cfg_s, torch.from_numpy(A).to(dev))

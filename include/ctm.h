@@ -77,6 +77,11 @@ typedef struct {
   int prec;         /* ctm_prec                                                          */
   int stabilized;   /* 1: orthonormalise after M and after M^T; 0: only after M^T M      */
   double pinv_rtol; /* s_i <= pinv_rtol * s_1 gives s_i^-1/2 := 0 (e.g. 1e-12 in f64)   */
+  int svd_driver;   /* dense SVD of M_b (full-SVD projectors and the growth moves):
+                       0 = QR iteration (rocSOLVER gesvd; small singular values to
+                       high relative accuracy), 1 = divide and conquer (rocSOLVER
+                       gesdd via the eigenvectors of M^T M; an order of magnitude
+                       faster, weak directions below ~1e-8 s_1 less accurate)     */
 } ctm_config;
 
 typedef struct {

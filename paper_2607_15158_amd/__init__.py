@@ -35,6 +35,7 @@ CTM_OK, CTM_E_ARG, CTM_E_SHAPE, CTM_E_NOMEM, CTM_E_DEVICE, CTM_E_NUMERIC, \
     CTM_E_NOT_CONVERGED, CTM_E_STATE = range(8)
 PROJ = {"svd": 0, "fullsvd": 0, "si": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
+SVD_DRIVER = {"gesvd": 0, "gesdd": 1}
 OBS_NORM, OBS_ONESITE, OBS_BOND_H, OBS_BOND_V = range(4)
 
 
@@ -42,7 +43,7 @@ class ctm_config(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("D", ctypes.c_int), ("chi", ctypes.c_int),
                 ("p", ctypes.c_int), ("n_si", ctypes.c_int), ("proj", ctypes.c_int),
                 ("prec", ctypes.c_int), ("stabilized", ctypes.c_int),
-                ("pinv_rtol", ctypes.c_double)]
+                ("pinv_rtol", ctypes.c_double), ("svd_driver", ctypes.c_int)]
 
 
 class ctm_move_info(ctypes.Structure):
@@ -121,10 +122,12 @@ class Config:
     prec: str = "f64"
     stabilized: int = 1
     pinv_rtol: float = 1e-12
+    svd_driver: str = "gesvd"
 
     def c(self) -> ctm_config:
         return ctm_config(self.d, self.D, self.chi, self.p, self.n_si, PROJ[self.proj],
-                          PREC[self.prec], self.stabilized, self.pinv_rtol)
+                          PREC[self.prec], self.stabilized, self.pinv_rtol,
+                          SVD_DRIVER[self.svd_driver])
 
     @property
     def Dl(self) -> int:

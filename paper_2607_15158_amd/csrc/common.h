@@ -68,6 +68,9 @@ inline void gemm_set_rowmajor_c(GemmBatch& g, long ldc) {
 // Launches a batched GEMM; ta = element type of A, tb of B, tc of C.
 // Accumulation is float64 for F64 inputs and float32 otherwise.
 int launch_gemm(const GemmBatch& g, DT ta, DT tb, DT tc, hipStream_t s);
+// float64 C = op(A) B with N <= 160 (the enlarged corner applied to an
+// isometry block); other shapes fall back to launch_gemm.
+int launch_gemm_si(const GemmBatch& g, hipStream_t s);
 
 // Householder QR (in place, Q returned with R_ii >= 0) of `count` N x k
 // row-major matrices.  ws must hold qr_workspace_bytes(count, N, k) bytes.

@@ -159,6 +159,8 @@ int validate(const ctm_config* cfg) {
   if (cfg->prec < CTM_PREC_F64 || cfg->prec > CTM_PREC_BF16)
     return fail(nullptr, CTM_E_ARG, "unknown precision");
   if (!(cfg->pinv_rtol >= 0.0)) return fail(nullptr, CTM_E_ARG, "pinv_rtol must be >= 0");
+  if (cfg->svd_driver != 0 && cfg->svd_driver != 1)
+    return fail(nullptr, CTM_E_ARG, "svd_driver must be 0 (gesvd) or 1 (gesdd)");
   const int Dl = cfg->d > 0 ? cfg->D * cfg->D : cfg->D;
   const long N = (long)cfg->chi * Dl;
   const long k = std::min<long>(cfg->chi + cfg->p, N);
@@ -396,7 +398,11 @@ int apply_step(ctm_ctx* c, int count, const int* ci, const int* trans, double* c
     g.C[i] = dst[i];
   }
   const double bytes = (double)count * ((double)N1 * N1 * dt_size(c->cp) + 2.0 * N1 * k * 8.0);
-  return run_gemm(c, PC_SI_APPLY, g, c->cp, DT::F64, DT::F64, bytes);
+  if (c->cp != DT::F64) return run_gemm(c, PC_SI_APPLY, g, c->cp, DT::F64, DT::F64, bytes);
+  const int chk = check_gemm(c, g, DT::F64, DT::F64, DT::F64);
+  if (chk) return chk;
+  ProfScope ps(c, PC_SI_APPLY, gemm_flops(g), bytes);
+  return launch_gemm_si(g, c->st);
 }
 
 inline int md(int i) { return ((i % 4) + 4) % 4; }
@@ -613,11 +619,15 @@ int full_projectors(ctm_ctx* c, int keep) {
     {
       ProfScope ps(c, PC_FULLSVD);
       // rocSOLVER is column-major: it sees M^T = (V) S (U^T)
-      rocblas_status st = rocsolver_dgesvd(c->rb, rocblas_svect_all, rocblas_svect_all, N1, N1, M,
-                                           N1, c->fs_s, Ut, N1, Uv, N1, c->fs_E,
-                                           rocblas_outofplace, c->fs_info);
+      rocblas_status st =
+          c->cfg.svd_driver == 1
+              ? rocsolver_dgesdd(c->rb, rocblas_svect_singular, rocblas_svect_singular, N1, N1, M,
+                                 N1, c->fs_s, Ut, N1, Uv, N1, c->fs_info)
+              : rocsolver_dgesvd(c->rb, rocblas_svect_singular, rocblas_svect_singular, N1, N1, M,
+                                 N1, c->fs_s, Ut, N1, Uv, N1, c->fs_E, rocblas_outofplace,
+                                 c->fs_info);
       if (st != rocblas_status_success)
-        return fail(c, CTM_E_DEVICE, "rocsolver_dgesvd failed: " + std::to_string((int)st));
+        return fail(c, CTM_E_DEVICE, "rocSOLVER SVD failed: " + std::to_string((int)st));
     }
     SignArgs sa{};
     sa.N = N1;
@@ -1336,7 +1346,7 @@ ctm_status ctm_gemm_f64(int count, const double* const* A, const double* const* 
     g.C[i] = C[i];
     g.transA[i] = trans_a;
   }
-  int r = launch_gemm(g, DT::F64, DT::F64, DT::F64, (hipStream_t)stream);
+  int r = launch_gemm_si(g, (hipStream_t)stream);   // skinny kernel when N <= 160
   return r ? CTM_E_DEVICE : CTM_OK;
 }
 

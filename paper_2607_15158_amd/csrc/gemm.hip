@@ -190,6 +190,161 @@ __global__ __launch_bounds__(256) void gemm_k4(GemmBatch g, int tiles_m, int til
 }
 
 // ---------------------------------------------------------------------------
+// Skinny float64 path for C (M x N) = op(A) (M x K) B (K x N) with N <= BN:
+// the enlarged corner applied to an N x k isometry block.  One workgroup owns
+// a BM x BN tile (the whole width of B), so A is streamed from HBM exactly
+// once; K is staged through double-buffered LDS in BK slices with 16-byte
+// global loads, one barrier per slice.  The launch is flattened over
+// (problem, tile) and dealt to the XCDs in contiguous chunks, so the
+// workgroups of one problem share an L2 and its slice of B.
+// ROLE only separates instantiations (and kernel names in profiles).
+// ---------------------------------------------------------------------------
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <int BM, int BN, int WGM, int WGN, int ROLE>
+__global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles_m, int tiles_n) {
+  constexpr int BK = 16;
+  constexpr int LA = BM + 16, LB = BN + 16;   // row lengths: 16-lane groups on distinct banks
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int MI = WTM / 16, NI = WTN / 16;
+  constexpr int VA = BM * BK / 2 / 256, VB = BN * BK / 2 / 256;
+  static_assert(WGM * WGN == 4, "four wavefronts");
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile multiple of 16");
+  static_assert((BM * BK / 2) % 256 == 0 && (BN * BK / 2) % 256 == 0, "tile loads");
+
+  __shared__ double As[2][BK][LA];
+  __shared__ double Bs[2][BK][LB];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int per_prob = tiles_m * tiles_n;
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int pb = lin / per_prob, tile = lin % per_prob;
+  const int prob = pb / g.nbatch, batch = pb % g.nbatch;
+  const int tn = tile % tiles_n, tm = tile / tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int M = g.M, N = g.N, K = g.K;
+  const bool trans = g.transA[prob] != 0;
+  const double* A = (const double*)g.A[prob] + (long)batch * g.a_bs;
+  const double* B = (const double*)g.B[prob] + (long)batch * g.b_bs;
+  double* C = (double*)g.C[prob] + (long)batch * g.c_bs;
+  const long lda = g.lda, ldb = g.ldb;
+
+  v2d ra[VA], rb[VB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < VA; ++e) {
+      const int i = tid + e * 256;
+      int gm, gk;
+      if (trans) { gk = k0 + i / (BM / 2); gm = m0 + 2 * (i % (BM / 2)); }
+      else { gm = m0 + i / (BK / 2); gk = k0 + 2 * (i % (BK / 2)); }
+      v2d v = {0.0, 0.0};
+      if (trans) {
+        if (gk < K) {
+          const double* p = A + (long)gk * lda + gm;
+          if (gm + 1 < M) v = *(const v2d*)p;
+          else if (gm < M) v.x = p[0];
+        }
+      } else if (gm < M) {
+        const double* p = A + (long)gm * lda + gk;
+        if (gk + 1 < K) v = *(const v2d*)p;
+        else if (gk < K) v.x = p[0];
+      }
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < VB; ++e) {
+      const int i = tid + e * 256;
+      const int gk = k0 + i / (BN / 2), gn = n0 + 2 * (i % (BN / 2));
+      v2d v = {0.0, 0.0};
+      if (gk < K) {
+        const double* p = B + (long)gk * ldb + gn;
+        if (gn + 1 < N) v = *(const v2d*)p;
+        else if (gn < N) v.x = p[0];
+      }
+      rb[e] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < VA; ++e) {
+      const int i = tid + e * 256;
+      if (trans) {
+        const int kk = i / (BM / 2), m = 2 * (i % (BM / 2));
+        *(v2d*)&As[buf][kk][m] = ra[e];
+      } else {
+        const int m = i / (BK / 2), kk = 2 * (i % (BK / 2));
+        As[buf][kk][m] = ra[e].x;
+        As[buf][kk + 1][m] = ra[e].y;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VB; ++e) {
+      const int i = tid + e * 256;
+      *(v2d*)&Bs[buf][i / (BN / 2)][2 * (i % (BN / 2))] = rb[e];
+    }
+  };
+
+  v4d acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double a[MI], b[NI];
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < MI; ++i) a[i] = As[buf][kr][wm * WTM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  long offn[NI];
+  bool okn[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+    okn[j] = n < N;
+    offn[j] = okn[j] ? map2(n, g.cdiv_n, g.cs_n1, g.cs_n0) : 0;
+  }
+  const double alpha = g.alpha;
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+      if (m >= M) continue;
+      const long offm = map2(m, g.cdiv_m, g.cs_m1, g.cs_m0);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        if (!okn[j]) continue;
+        double* p = C + offm + offn[j];
+        double v = alpha * acc[i][j][r];
+        if (g.accumulate) v += *p;
+        *p = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // bf16 path: v_mfma_f32_16x16x32_bf16, float32 accumulation.
 // LDS keeps k contiguous per row so that a lane reads its 8 k-values at once.
 // ---------------------------------------------------------------------------
@@ -378,7 +533,31 @@ int launch_b16(const GemmBatch& g, hipStream_t s) {
   return 0;
 }
 
+// The skinny kernel needs 16-byte aligned rows: even leading dimensions and
+// batch strides, 16-byte aligned base pointers.
+bool skinny_ok(const GemmBatch& g) {
+  if ((g.lda & 1) || (g.ldb & 1) || (g.a_bs & 1) || (g.b_bs & 1)) return false;
+  for (int i = 0; i < g.count; ++i)
+    if (((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & 15)) return false;
+  return true;
+}
+
+template <int BM, int BN, int WGM, int WGN, int ROLE>
+int launch_skinny(const GemmBatch& g, hipStream_t s) {
+  const int tm = ceil_div(g.M, BM), tn = ceil_div(g.N, BN);
+  dim3 grid(tm * tn * g.count * g.nbatch), block(256);
+  gemm_skinny_f64<BM, BN, WGM, WGN, ROLE><<<grid, block, 0, s>>>(g, tm, tn);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 }  // namespace
+
+int launch_gemm_si(const GemmBatch& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch <= 0) return 0;
+  if (g.N > 160 || !skinny_ok(g)) return launch_gemm(g, DT::F64, DT::F64, DT::F64, s);
+  return launch_skinny<96, 160, 2, 2, 1>(g, s);
+}
 
 // Compute type: float64 when any operand is float64 and the mode is f64;
 // the caller selects the mode through the operand types:

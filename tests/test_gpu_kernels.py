@@ -1,6 +1,7 @@
 """GPU parity of the building-block kernels through the C ABI.
 
-GEMM against float64 NumPy products; Householder QR against the oracle's
+GEMM against float64 NumPy products (N <= 160 runs the skinny kernel of the
+enlarged-corner applications, wider N the general tiles); Householder QR against the oracle's
 QR convention (R_ii >= 0) and orthogonality; Jacobi SVD against NumPy's
 singular values and the reconstruction.  Shapes span several tiles and
 ragged tails.
@@ -23,7 +24,9 @@ def dev(x):
 
 @pytest.mark.parametrize("M,N,K,trans", [(5, 7, 3, 0), (130, 70, 33, 0), (130, 70, 33, 1),
                                          (257, 160, 300, 0), (300, 161, 257, 1),
-                                         (1000, 144, 520, 0), (64, 1296, 1296, 0)])
+                                         (1000, 144, 520, 0), (64, 1296, 1296, 0),
+                                         (5184, 160, 5184, 0), (5184, 160, 5184, 1),
+                                         (97, 159, 33, 1)])
 def test_gemm_f64_matches_numpy(M, N, K, trans):
     rng = np.random.default_rng(M * 7 + N)
     A = [rng.standard_normal((K, M) if trans else (M, K)) for _ in range(3)]
