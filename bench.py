@@ -172,7 +172,8 @@ def main():
             tt.append(time.perf_counter() - t)
             log(f"full-SVD move {i}: {tt[-1]:.2f} s")
         svd = {"moves_per_s": round(1.0 / float(np.mean(tt)), 4), "ms_per_move": round(1e3 * float(np.mean(tt)), 1),
-               "moves": args.svd_moves, "solver": "rocsolver_dgesvd on 4 x (5184 x 5184)"}
+               "moves": args.svd_moves,
+               "solver": f"rocsolver_d{args.svd_driver} on 4 x ({cfg.N} x {cfg.N})"}
         del cs
 
     cpu = None

@@ -12,6 +12,41 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+// ---------------------------------------------------------------------------
+// Cross-lane sums of doubles without LDS round trips.  DPP moves act on
+// 32-bit halves; the patterns below pair every lane with a partner, so each
+// stage adds the same two values in every lane and all lanes end with
+// bitwise identical sums.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_f64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each aligned group of 16 lanes, in every lane of the group:
+// quad_perm(1,0,3,2), quad_perm(2,3,0,1), row_half_mirror, row_mirror.
+__device__ __forceinline__ double row_sum16(double x) {
+  x += dpp_mov_f64<0xB1>(x);
+  x += dpp_mov_f64<0x4E>(x);
+  x += dpp_mov_f64<0x141>(x);
+  x += dpp_mov_f64<0x140>(x);
+  return x;
+}
+
+// Sum over the 64 lanes of a wavefront (uniform result).
+__device__ __forceinline__ double wave_sum64(double x) {
+  x = row_sum16(x);
+  return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
+}
+
 #define CTM_HIP_TRY(expr)                                              \
   do {                                                                 \
     hipError_t _e = (expr);                                            \

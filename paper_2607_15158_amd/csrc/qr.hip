@@ -42,11 +42,7 @@ __host__ __device__ inline int leaf_start(int i, int N, int nb) {
   return (int)(((long)i * N) / nb);
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
+__device__ __forceinline__ double wave_sum(double x) { return wave_sum64(x); }
 
 // C(M x N) = sum_k A(m, k) B(k, n) for operands in LDS, on the FP64 matrix
 // cores (v_mfma_f64_16x16x4: operand lane l -> (row l%16, k l/16), result
@@ -192,9 +188,7 @@ __global__ __launch_bounds__(256) void qr_leaf_factor(QrArgs q, int p) {
         d[t] = acc;
       }
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-        for (int t = 0; t < kPanel / 4; ++t) d[t] += __shfl_xor(d[t], off, 64);
+      for (int t = 0; t < kPanel / 4; ++t) d[t] = wave_sum64(d[t]);
 #pragma unroll
       for (int t = 0; t < kPanel / 4; ++t) {
         const int c = j + 1 + wave + 4 * t;
@@ -298,8 +292,8 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
     if (wave == 0) {
       double ss = 0.0;
       if (lane <= j) ss = Rb[lane][j] * Rb[lane][j];
-#pragma unroll
-      for (int off = 16; off >= 1; off >>= 1) ss += __shfl_xor(ss, off, 64);
+      ss = row_sum16(ss);
+      ss = readlane_f64(ss, 0) + readlane_f64(ss, 16);
       const double alpha = Ra[j][j];
       double tau = 0.0, beta = alpha, scal = 0.0;
       if (ss > 0.0) {
@@ -322,9 +316,10 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
       }
       // rows live in lanes 0..j <= 31: a 32-lane reduction suffices
 #pragma unroll
-      for (int off = 16; off >= 1; off >>= 1)
-#pragma unroll
-        for (int t = 0; t < kPanel / 4; ++t) d[t] += __shfl_xor(d[t], off, 64);
+      for (int t = 0; t < kPanel / 4; ++t) {
+        d[t] = row_sum16(d[t]);
+        d[t] = readlane_f64(d[t], 0) + readlane_f64(d[t], 16);
+      }
 #pragma unroll
       for (int t = 0; t < kPanel / 4; ++t) {
         const int c = j + 1 + wave + 4 * t;

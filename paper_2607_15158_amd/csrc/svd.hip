@@ -38,17 +38,9 @@ constexpr int kInner = 2;            // inner sweeps per block-pair visit
 constexpr int kLanesPerPair = 16;
 constexpr int kRowsPerLane = kSvdMaxN / kLanesPerPair;
 
-__device__ __forceinline__ double wsum(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
+__device__ __forceinline__ double wsum(double x) { return wave_sum64(x); }
 
-__device__ __forceinline__ double gsum16(double x) {
-#pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
+__device__ __forceinline__ double gsum16(double x) { return row_sum16(x); }
 
 struct SvdArgs {
   const double* A[kMaxProb];   // matrices the Jacobi kernels act on (R^T)
