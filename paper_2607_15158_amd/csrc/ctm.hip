@@ -164,7 +164,7 @@ int validate(const ctm_config* cfg) {
   const int Dl = cfg->d > 0 ? cfg->D * cfg->D : cfg->D;
   const long N = (long)cfg->chi * Dl;
   const long k = std::min<long>(cfg->chi + cfg->p, N);
-  if (k > 256) return fail(nullptr, CTM_E_SHAPE, "chi + p must be <= 256");
+  if (k > 192) return fail(nullptr, CTM_E_SHAPE, "chi + p must be <= 192");
   if (N > 65536) return fail(nullptr, CTM_E_SHAPE, "chi * Dl must be <= 65536");
   return CTM_OK;
 }

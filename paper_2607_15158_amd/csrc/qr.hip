@@ -29,7 +29,7 @@ namespace sictm {
 namespace {
 
 constexpr int kPanel = 32;
-constexpr int kLeafRows = 256;
+constexpr int kLeafRows = 192;   // three rows per lane of one wavefront
 constexpr int kLR = kLeafRows + 1;   // odd row length: fragment reads hit distinct banks
 constexpr int kT = kPanel + 1;   // padded row length of the small LDS matrices
 constexpr int kTrail = 64;       // trailing columns per LDS chunk in the tree kernels
@@ -116,20 +116,119 @@ __device__ __forceinline__ long slot(int mat, int p, int leaf, int nb, int P) {
 }
 
 // T (w x w, upper) of H_0...H_(w-1) = I - V T V^T from the Gram matrix
-// G = V^T V and the taus (forward, columnwise): T_jj = tau_j,
-// T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].  One wavefront, lane i = row i.
+// G = V^T V (strict upper part) and the taus, forward columnwise:
+// T_jj = tau_j, T[i, j] = -tau_j sum_{l=i}^{j-1} T[i, l] G[l, j] for i < j.
+// Row i depends only on itself, so lane i builds row i in registers.
 __device__ __forceinline__ void build_T(double (*T)[kT], double (*G)[kT], const double* tau,
                                         int w, int lane) {
-  for (int j = 0; j < w; ++j) {
-    double t = 0.0;
-    if (lane < j) {
-      for (int l = lane; l < j; ++l) t += T[lane][l] * G[l][j];
-      t *= -tau[j];
-      T[lane][j] = t;
-    }
-    if (lane == j) T[j][j] = tau[j];
-    if (lane > j && lane < kPanel) T[lane][j] = 0.0;
+  double t[kPanel];
+#pragma unroll
+  for (int j = 0; j < kPanel; ++j) {
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < j; ++l) acc += t[l] * G[l][j];   // t[l] = 0 for l < lane
+    const double tj = j < w ? tau[j] : 0.0;
+    t[j] = lane < j ? -tj * acc : (lane == j ? tj : 0.0);
   }
+  if (lane < kPanel) {
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) T[lane][j] = t[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Householder factorisation of one panel by a single wavefront, with the
+// panel in registers: x[r][c] is row (lane + 64 r), column c.  The pivot of
+// column j is row j (lane j, r = 0); below(j, r) selects the rows that carry
+// reflector j under the pivot.  Per column the wavefront forms the reflector
+// (dlarfg convention); one reduction then gives both v_j^T x_s for the later
+// columns s > j (applied at once) and v_s^T v_j for the earlier ones (the
+// Gram column of the WY factor T).  The 32 per-lane partial sums of a step
+// are reduced through LDS: every lane writes its row of partials, lane l
+// adds column l % 32 over one half of the rows, and the halves meet in one
+// cross-lane exchange; the scaled sums are read back as LDS broadcasts.
+// The wavefront's LDS traffic is ordered by itself, so no barrier is needed.
+// ---------------------------------------------------------------------------
+struct PanelScratch {
+  double P[64][kT];   // per-lane partial sums
+  double F[kPanel];   // tau * v_j^T x_s
+};
+
+// 1/x to full double precision from the hardware estimate (two Newton
+// steps); x is never zero where it is used.
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Step J of the panel factorisation (J is a template parameter so that every
+// register of the panel is addressed statically).  Branch-free when FULL
+// (w == 32), so consecutive steps form one block the scheduler can overlap.
+template <int J, bool FULL, int RPL, typename Below>
+__device__ __forceinline__ void panel_step(double (&x)[RPL][kPanel], int w, int lane,
+                                           const Below& below, double* tau_out, double (*G)[kT],
+                                           PanelScratch& ps) {
+  if (FULL || J < w) {
+    bool bl[RPL];
+    double ss = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      bl[r] = below(J, r);
+      ss += bl[r] ? x[r][J] * x[r][J] : 0.0;
+    }
+    ss = wave_sum64(ss);
+    const double alpha = readlane_f64(x[0][J], J);
+    // dlarfg: beta = -sign(alpha) |(alpha, x)|, tau = (beta - alpha) / beta,
+    // v = x / (alpha - beta); H = I (tau = 0) when x is exactly zero
+    const bool live = ss > 0.0;
+    const double nrm = sqrt(alpha * alpha + ss);
+    const double beta = live ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+    const double tau = live ? (beta - alpha) * fast_rcp(beta) : 0.0;
+    const double scal = live ? fast_rcp(alpha - beta) : 0.0;
+    double vj[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      vj[r] = bl[r] ? x[r][J] * scal : ((r == 0 && lane == J) ? 1.0 : 0.0);
+      if (bl[r]) x[r][J] = vj[r];
+    }
+    if (lane == J) x[0][J] = beta;
+    if (lane == 0) tau_out[J] = tau;
+#pragma unroll
+    for (int s = 0; s < kPanel; ++s) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc += vj[r] * x[r][s];
+      ps.P[lane][s] = acc;
+    }
+    const int col = lane & 31, h = (lane >> 5) * 32;
+    double tot = 0.0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) tot += ps.P[h + i][col];
+    tot += __shfl_xor(tot, 32, 64);
+    if (lane < 32) {
+      ps.F[lane] = tau * tot;
+      if (lane < J) G[lane][J] = tot;
+    }
+#pragma unroll
+    for (int s = J + 1; s < kPanel; ++s) {
+      if (FULL || s < w) {
+        const double f = ps.F[s];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) x[r][s] -= f * vj[r];
+      }
+    }
+  }
+  if constexpr (J + 1 < kPanel) panel_step<J + 1, FULL>(x, w, lane, below, tau_out, G, ps);
+}
+
+template <int RPL, typename Below>
+__device__ __forceinline__ void wave_panel_qr(double (&x)[RPL][kPanel], int w, int lane, Below below,
+                                              double* tau_out, double (*G)[kT], PanelScratch& ps) {
+  if (w == kPanel)
+    panel_step<0, true>(x, w, lane, below, tau_out, G, ps);
+  else
+    panel_step<0, false>(x, w, lane, below, tau_out, G, ps);
 }
 
 // ---------------------------------------------------------------------------
@@ -140,6 +239,7 @@ __global__ __launch_bounds__(256) void qr_leaf_factor(QrArgs q, int p) {
   __shared__ double Cc[kPanel][kLR];          // trailing chunk, column-major
   __shared__ double T[kPanel][kT], G[kPanel][kT], W1[kPanel][kT];
   __shared__ double tau_s[kPanel];
+  __shared__ PanelScratch ps;
   const int leaf = blockIdx.x, mat = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = q.N, k = q.k, nb = q.nb;
@@ -149,78 +249,45 @@ __global__ __launch_bounds__(256) void qr_leaf_factor(QrArgs q, int p) {
   const int m = e - a0;
   double* A = q.A[mat];
 
-  g2l(kPanel * kLeafRows, tid,
-      [&](int idx) {
-        const int r = idx / kPanel, c = idx % kPanel;
-        return (r < m && c < w) ? A[(long)(a0 + r) * k + c0 + c] : 0.0;
-      },
-      [&](int idx, double v) { V[idx % kPanel][idx / kPanel] = v; });
+  if (wave == 0) {
+    constexpr int RPL = kLeafRows / 64;
+    double x[RPL][kPanel];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = lane + 64 * r;
+      const double* src = A + (long)(a0 + row) * k + c0;
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) x[r][c] = (row < m && c < w) ? src[c] : 0.0;
+    }
+    wave_panel_qr<RPL>(
+        x, w, lane,
+        [&](int j, int r) {
+          const int row = lane + 64 * r;
+          return row > j && row < m;
+        },
+        tau_s, G, ps);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = lane + 64 * r;
+      double* dst = A + (long)(a0 + row) * k + c0;
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) {
+        if (row < m && c < w) dst[c] = x[r][c];
+        if (row < kLR) V[c][row] = x[r][c];
+      }
+    }
+    build_T(T, G, tau_s, w, lane);
+  }
   __syncthreads();
-
-  for (int j = 0; j < w; ++j) {
-    if (wave == 0) {
-      double ss = 0.0;
-      for (int r = j + 1 + lane; r < m; r += 64) ss += V[j][r] * V[j][r];
-      ss = wave_sum(ss);
-      const double alpha = V[j][j];
-      double tau = 0.0, beta = alpha, scal = 0.0;
-      if (ss > 0.0) {
-        const double nrm = sqrt(alpha * alpha + ss);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      for (int r = j + 1 + lane; r < m; r += 64) V[j][r] *= scal;
-      if (lane == 0) { V[j][j] = beta; tau_s[j] = tau; }
-    }
-    __syncthreads();
-    const double tau = tau_s[j];
-    if (tau != 0.0) {
-      // all columns of this wavefront at once: the cross-lane reductions of
-      // the (up to 8) dot products are independent and overlap
-      double d[kPanel / 4];
-#pragma unroll
-      for (int t = 0; t < kPanel / 4; ++t) {
-        const int c = j + 1 + wave + 4 * t;
-        double acc = 0.0;
-        if (c < w)
-          for (int r = j + 1 + lane; r < m; r += 64) acc += V[j][r] * V[c][r];
-        d[t] = acc;
-      }
-#pragma unroll
-      for (int t = 0; t < kPanel / 4; ++t) d[t] = wave_sum64(d[t]);
-#pragma unroll
-      for (int t = 0; t < kPanel / 4; ++t) {
-        const int c = j + 1 + wave + 4 * t;
-        if (c < w) {
-          const double f = tau * (d[t] + V[c][j]);
-          for (int r = j + 1 + lane; r < m; r += 64) V[c][r] -= f * V[j][r];
-          if (lane == 0) V[c][j] -= f;
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  for (int idx = tid; idx < m * w; idx += 256) {
-    const int r = idx / w, c = idx % w;
-    A[(long)(a0 + r) * k + c0 + c] = V[c][r];
-  }
   const long sl = slot(mat, p, leaf, nb, q.P);
   if (tid < w) q.tau[sl * kPanel + tid] = tau_s[tid];
+  for (int idx = tid; idx < kPanel * kPanel; idx += 256)
+    q.Tl[sl * kPanel * kPanel + idx] = T[idx / kPanel][idx % kPanel];
 
   // unit lower-trapezoidal V (implicit ones, zeros above) of the WY factor
   auto Veff = [&](int r, int a) -> double {
     return r > a ? V[a][r] : (r == a ? 1.0 : 0.0);
   };
-  lds_mm(w, w, m, [&](int a, int r) { return Veff(r, a); }, Veff,
-         [&](int i, int j, double x) { G[i][j] = x; }, wave, lane);
-  __syncthreads();
-  if (wave == 0) build_T(T, G, tau_s, w, lane);
-  __syncthreads();
-  for (int idx = tid; idx < kPanel * kPanel; idx += 256)
-    q.Tl[sl * kPanel * kPanel + idx] = T[idx / kPanel][idx % kPanel];
-
   for (int cb = c0 + w; cb < k; cb += kPanel) {
     const int nc = min(kPanel, k - cb);
     __syncthreads();
@@ -257,15 +324,18 @@ __device__ __forceinline__ int top_row(int leaf, int c0, int N, int nb) {
 }
 
 // ---------------------------------------------------------------------------
-// tree combine at level L of panel p: node = right child b, left child b-2^L
+// tree combine at level L of panel p: node = right child b, left child b-2^L.
+// Wavefront 0 factors [Ra; Rb] (lanes 0..31 hold the rows of Ra, lanes
+// 32..63 those of Rb); the reflectors are [e_j; v_j] with v_j stored in the
+// upper triangle of Rb.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
-  __shared__ double Ra[kPanel][kT];   // [row][col]
   __shared__ double Rb[kPanel][kT];
   __shared__ double T[kPanel][kT], G[kPanel][kT];
   __shared__ double Ca[kPanel][kTrail + 1], Cb[kPanel][kTrail + 1];
   __shared__ double W1[kPanel][kTrail + 1], W2[kPanel][kTrail + 1];
   __shared__ double tau_s[kPanel];
+  __shared__ PanelScratch ps;
   const int step = 1 << (L + 1);
   const int b = blockIdx.x * step + (1 << L);
   const int mat = blockIdx.y;
@@ -276,80 +346,27 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
   const int ta = top_row(a, c0, N, nb), tb = top_row(b, c0, N, nb);
   double* A = q.A[mat];
-  g2l(2 * kPanel * kPanel, tid,
-      [&](int idx) {
-        const int h = idx / (kPanel * kPanel), rc = idx % (kPanel * kPanel);
-        const int r = rc / kPanel, c = rc % kPanel;
-        const bool up = r <= c && r < w && c < w;
-        return up ? A[(long)((h ? tb : ta) + r) * k + c0 + c] : 0.0;
-      },
-      [&](int idx, double v) {
-        const int h = idx / (kPanel * kPanel), rc = idx % (kPanel * kPanel);
-        (h ? Rb : Ra)[rc / kPanel][rc % kPanel] = v;
-      });
-  __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    if (wave == 0) {
-      double ss = 0.0;
-      if (lane <= j) ss = Rb[lane][j] * Rb[lane][j];
-      ss = row_sum16(ss);
-      ss = readlane_f64(ss, 0) + readlane_f64(ss, 16);
-      const double alpha = Ra[j][j];
-      double tau = 0.0, beta = alpha, scal = 0.0;
-      if (ss > 0.0) {
-        const double nrm = sqrt(alpha * alpha + ss);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      if (lane <= j) Rb[lane][j] *= scal;
-      if (lane == 0) { Ra[j][j] = beta; tau_s[j] = tau; }
+  if (wave == 0) {
+    const int rr = lane & 31;
+    double x[1][kPanel];
+    const double* src = A + (long)((lane < 32 ? ta : tb) + rr) * k + c0;
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c) x[0][c] = (rr <= c && c < w) ? src[c] : 0.0;
+    wave_panel_qr<1>(
+        x, w, lane, [&](int j, int) { return lane >= 32 && rr <= j; }, tau_s, G, ps);
+    double* dst = A + (long)((lane < 32 ? ta : tb) + rr) * k + c0;
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c) {
+      if (rr <= c && c < w) dst[c] = x[0][c];
+      if (lane >= 32) Rb[rr][c] = (rr <= c && c < w) ? x[0][c] : 0.0;
     }
-    __syncthreads();
-    const double tau = tau_s[j];
-    if (tau != 0.0) {
-      double d[kPanel / 4];
-#pragma unroll
-      for (int t = 0; t < kPanel / 4; ++t) {
-        const int c = j + 1 + wave + 4 * t;
-        d[t] = (c < w && lane <= j) ? Rb[lane][j] * Rb[lane][c] : 0.0;
-      }
-      // rows live in lanes 0..j <= 31: a 32-lane reduction suffices
-#pragma unroll
-      for (int t = 0; t < kPanel / 4; ++t) {
-        d[t] = row_sum16(d[t]);
-        d[t] = readlane_f64(d[t], 0) + readlane_f64(d[t], 16);
-      }
-#pragma unroll
-      for (int t = 0; t < kPanel / 4; ++t) {
-        const int c = j + 1 + wave + 4 * t;
-        if (c < w) {
-          const double f = tau * (d[t] + Ra[j][c]);
-          if (lane <= j) Rb[lane][c] -= f * Rb[lane][j];
-          if (lane == 0) Ra[j][c] -= f;
-        }
-      }
-    }
-    __syncthreads();
+    build_T(T, G, tau_s, w, lane);
   }
-  for (int idx = tid; idx < w * w; idx += 256) {
-    const int r = idx / w, c = idx % w;
-    if (r <= c) {
-      A[(long)(ta + r) * k + c0 + c] = Ra[r][c];
-      A[(long)(tb + r) * k + c0 + c] = Rb[r][c];
-    }
-  }
-  // Vb = upper triangle of Rb (lower parts of the node's reflectors);
-  // G = I + Vb^T Vb, then T
-  auto Vb = [&](int r, int c) -> double { return r <= c ? Rb[r][c] : 0.0; };
-  lds_mm(w, w, w, [&](int i, int r) { return Vb(r, i); }, Vb,
-         [&](int i, int j, double x) { G[i][j] = x + (i == j ? 1.0 : 0.0); }, wave, lane);
-  __syncthreads();
-  if (wave == 0) build_T(T, G, tau_s, w, lane);
   __syncthreads();
   const long sl = slot(mat, p, b, nb, q.P);
   for (int idx = tid; idx < kPanel * kPanel; idx += 256)
     q.Tn[sl * kPanel * kPanel + idx] = T[idx / kPanel][idx % kPanel];
+  auto Vb = [&](int r, int c) -> double { return r <= c ? Rb[r][c] : 0.0; };
   // trailing columns [c0+w, k) of the 2w rows: W1 = Ca + Vb^T Cb;
   // W2 = T^T W1; Ca -= W2; Cb -= Vb W2
   for (int cb = c0 + w; cb < k; cb += kTrail) {
@@ -570,7 +587,7 @@ size_t qr_workspace_bytes(int count, int N, int k) {
 int launch_qr(int count, double* const* W, int N, int k, void* ws, hipStream_t s) {
   if (count <= 0 || k <= 0) return 0;
   if (count > kMaxProb || N < k || k > kLeafRows) {
-    set_thread_error("launch_qr: need k <= N, k <= 256 and at most 8 matrices per launch");
+    set_thread_error("launch_qr: need k <= N, k <= 192 and at most 8 matrices per launch");
     return 1;
   }
   const QrPlan pl = make_plan(N, k);

@@ -30,7 +30,7 @@
 namespace sictm {
 namespace {
 
-constexpr int kSvdMaxN = 256;
+constexpr int kSvdMaxN = 192;   // the preconditioning QR holds n <= 192 rows per leaf
 constexpr int kRPL = kSvdMaxN / 64;   // rows per lane in the finalisation
 constexpr int kBlk = 16;              // columns per block
 constexpr int kMaxSweeps = 24;
@@ -338,7 +338,7 @@ int launch_svd(int count, const double* const* A, double* const* U, double* cons
                double* const* V, int n, void* ws, hipStream_t s) {
   if (count <= 0 || n <= 0) return 0;
   if (count > kMaxProb || n > kSvdMaxN) {
-    set_thread_error("launch_svd: n <= 256 and at most 8 matrices per launch");
+    set_thread_error("launch_svd: n <= 192 and at most 8 matrices per launch");
     return 1;
   }
   const size_t nn = (size_t)n * n;

@@ -261,3 +261,51 @@ def test_noisy_state_observables_match_oracle():
     Zs = S.pauli("z")
     assert abs(ctx.observable(P.OBS_ONESITE, Zs)[0] -
                O.onesite_value(env, a, O.double_layer_op(A, Zs))) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,pinv", [("f32", 1e-6), ("bf16", 1e-2)])
+def test_precision_modes_converged_energy(prec, pinv):
+    """Contractions in float32 / bfloat16 (float32 accumulation), QR, SVD and
+    projectors in float64: the converged bond energy and norm per site agree
+    with the float64 oracle to 1e-5 relative (the precision-mode bound).
+
+    In bfloat16 the enlarged corners are rounded to 8 significant bits, so
+    once the environment moves by less than that the rounded corners, and
+    with them the move, repeat exactly: the iteration stops at a fixed point
+    of the rounded map (delta = 0) near the float64 one.
+    """
+    A = S.product_plus_noise_site(2, 3, 2)
+    chi = 12
+    cfg = P.Config(d=2, D=3, chi=chi, p=6, prec=prec, pinv_rtol=pinv)
+    ctx, si = make(cfg, A)
+    a = O.double_layer(A)
+    env, _ = O.run_ctmrg(a, S.trace_boundary(3), chi, "si", iso0=si, tol=1e-13, max_moves=60)
+    ctx.converge(1e-9, 80)
+    h = S.heisenberg_bond()
+    e_ref = O.bond_value(env, A, h, "h") + O.bond_value(env, A, h, "v")
+    e = ctx.observable(P.OBS_BOND_H, h)[0] + ctx.observable(P.OBS_BOND_V, h)[0]
+    print(f"{prec}: e = {e:.12f}, oracle {e_ref:.12f}, rel err {abs(e - e_ref) / abs(e_ref):.2e}")
+    assert abs(e - e_ref) <= 1e-5 * abs(e_ref)
+    assert abs(ctx.kappa() / O.kappa(env, a) - 1) <= 1e-5
+
+
+def test_f32_si_move_matches_oracle():
+    """One SI move with float32 contractions from the same state and blocks:
+    the new corner spectra agree with the float64 oracle to float32 accuracy.
+
+    Element-wise parity is not asked for: the sign rule's tie tolerance
+    (relative 1e-8) is below float32 resolution, so exact ket/bra ties of the
+    double layer can resolve to the other entry and flip the sign gauge of a
+    projector column.
+    """
+    A = random_site(2, 11)
+    chi, p = 4, 4
+    cfg = P.Config(d=2, D=2, chi=chi, p=p, n_si=2, prec="f32", pinv_rtol=1e-6)
+    ctx, si = make(cfg, A)
+    a = O.double_layer(A)
+    env = O.initial_env(a, S.trace_boundary(2))
+    ctx.move()
+    env, _ = O.ctm_move(env, a, chi, "si", si, n_si=2, eps=1e-6)
+    st = ctx.unpack_state(ctx.get_state())
+    assert st["chi_env"] == env.chi
+    assert_spectra_close(st, env, 1e-5)
