@@ -80,6 +80,78 @@ def cpu_baseline(args, A, X, Y):
                       f"value is an upper bound on the oracle's full-move rate"}
 
 
+def serving(args):
+    """Serving workload: mixed (D, chi) environment solves, Poisson arrivals.
+
+    Request i: D uniform in {3,4,5,6}, chi uniform in {D^2, 2D^2, 3D^2}
+    (default_rng(4)), site tensor as in the main workload with seed 4000+i,
+    p = max(4, ceil(0.15 chi)), n_si = 2, tol 1e-10, at most --serve-moves moves,
+    Heisenberg bond energy evaluated at the end.  Phase 1 submits every request
+    at t = 0 and measures the service rate mu; phase 2 replays them with
+    Poisson arrivals at lambda = 0.7 mu (inter-arrival times from
+    default_rng(44)) and reports latency p50/p99 and throughput.
+    """
+    import math
+    import paper_2607_15158_amd as P
+    import synth as S
+    rng = np.random.default_rng(4)
+    reqs = []
+    for i in range(args.serving):
+        D = int(rng.choice([3, 4, 5, 6]))
+        chi = int(rng.choice([D * D, 2 * D * D, 3 * D * D]))
+        p = max(4, math.ceil(0.15 * chi))
+        cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2, svd_driver="gesdd")
+        reqs.append((cfg, S.product_plus_noise_site(2, D, 4000 + i)))
+    h = S.heisenberg_bond()
+
+    def run(arrivals):
+        srv = P.Server(arena_bytes=args.serve_arena_gb << 30, max_slots=args.serve_slots)
+        t0 = srv.clock()
+        ids, nxt, done_log = [None] * len(reqs), 0, 0
+        while True:
+            now = srv.clock() - t0
+            while nxt < len(reqs) and arrivals[nxt] <= now:
+                cfg, A = reqs[nxt]
+                ids[nxt] = srv.submit(cfg, A, op=h, tol=1e-10, max_moves=args.serve_moves)
+                nxt += 1
+            running, queued = srv.pump()
+            if nxt == len(reqs) and running == 0 and queued == 0:
+                break
+            fin = sum(1 for r in ids if r is not None and srv.result(r)["state"] in ("done", "failed"))
+            if fin >= done_log + max(1, len(reqs) // 8):
+                done_log = fin
+                log(f"  serving: {fin}/{len(reqs)} done, {running} running, {queued} queued, "
+                    f"t = {srv.clock() - t0:.1f} s")
+        res = [srv.result(r) for r in ids]
+        span = max(r["t_done"] for r in res) - t0
+        srv.close()
+        return res, span
+
+    log(f"serving phase 1: {len(reqs)} requests at t = 0")
+    res1, span1 = run([0.0] * len(reqs))
+    mu = len(reqs) / span1
+    lam = 0.7 * mu
+    gaps = np.random.default_rng(44).exponential(1.0 / lam, size=len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    log(f"serving phase 2: Poisson arrivals at lambda = {lam:.3f} req/s (mu = {mu:.3f})")
+    res2, span2 = run(list(arrivals))
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res2])
+    failed = sum(r["state"] != "done" for r in res2)
+    same = all(a["kappa"] == b["kappa"] and a["bond_h"] == b["bond_h"] and a["moves"] == b["moves"]
+               for a, b in zip(res1, res2))
+    return {"metric": "serving latency p50/p99 of mixed (D, chi) environment solves",
+            "value": round(len(reqs) / span2, 4), "unit": "requests/s", "n_gpus": 1,
+            "requests": len(reqs), "mu_req_per_s": round(mu, 4), "lambda_req_per_s": round(lam, 4),
+            "p50_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_moves": round(float(np.mean([r["moves"] for r in res2])), 2),
+            "converged": int(sum(r["converged"] for r in res2)), "failed": int(failed),
+            "results_identical_across_phases": bool(same),
+            "slots": args.serve_slots, "arena_gb": args.serve_arena_gb,
+            "max_moves": args.serve_moves, "dtype": "f64", "data": "synthetic",
+            "higher_is_better": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +167,11 @@ def main():
     ap.add_argument("--svd-driver", default="gesdd", choices=["gesdd", "gesvd"],
                     help="dense SVD of the growth move and of the full-SVD comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="run the serving workload with this many requests instead")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-arena-gb", type=int, default=96)
+    ap.add_argument("--serve-moves", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -105,6 +182,9 @@ def main():
     import paper_2607_15158_amd as P
 
     torch.cuda.set_device(0)
+    if args.serving:
+        print(json.dumps(serving(args)), flush=True)
+        return
     dev = torch.device("cuda", 0)
     A, X, Y = workload(args.D, args.chi, args.p)
     cfg = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="si",

@@ -135,6 +135,19 @@ ctm_status ctm_set_isometries(ctm_ctx* ctx, const double* X_dev, const double* Y
  * CTM_E_NUMERIC the previous environment is kept. */
 ctm_status ctm_move(ctm_ctx* ctx, ctm_move_info* info);
 
+/* Asynchronous move: enqueues one move on the context's stream and returns
+ * without waiting (growth moves with full-SVD projectors may still block
+ * inside rocSOLVER).  Only one move may be in flight per context
+ * (CTM_E_STATE otherwise).  Every other call on the context first completes
+ * the move in flight. */
+ctm_status ctm_move_async(ctm_ctx* ctx);
+
+/* Non-blocking completion check of the move in flight: *done = 0 while it
+ * runs; *done = 1 once it has finished, with info (if non-NULL) filled as by
+ * ctm_move and the context switched to the new environment.  CTM_E_STATE
+ * when no move is in flight; CTM_E_NUMERIC as for ctm_move. */
+ctm_status ctm_move_poll(ctm_ctx* ctx, int* done, ctm_move_info* info);
+
 /* Moves until delta < tol or max_moves moves were made.  Returns
  * CTM_E_NOT_CONVERGED when the budget ran out (the state stays valid). */
 ctm_status ctm_converge(ctm_ctx* ctx, double tol, int max_moves, int* moves_done,
@@ -173,6 +186,69 @@ typedef struct {
 
 ctm_status ctm_profile(ctm_ctx* ctx, int enable);
 ctm_status ctm_profile_read(ctm_ctx* ctx, ctm_prof_entry* out, int max_entries, int* n);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of environment solves on one GPU.
+ *
+ * A server owns one device arena (allocated once, at creation) and
+ * max_slots HIP streams.  Submitted requests wait in a queue and are
+ * admitted, in submission order, while a slot is free and their footprint
+ * (ctm_workspace_bytes of their configuration plus their staged inputs)
+ * fits into the free part of the arena, first fit; a request that does not
+ * fit does not hold back smaller ones behind it.  A running request is one
+ * context on its slot's stream, with C, T, X and Y resident in its
+ * workspace; every ctm_server_pump completes the moves that have finished,
+ * launches the next move of each request still iterating (so the moves of
+ * different requests overlap on the device), retires requests that reached
+ * delta < tol at the full environment dimension or their move budget, and
+ * admits queued ones.  A request runs exactly the kernels of a solo
+ * ctm_converge with the same inputs, so its result does not depend on the
+ * other requests.  The server is not thread safe; requests are numbered
+ * from 0 in submission order.
+ * ------------------------------------------------------------------------- */
+typedef struct ctm_server ctm_server;
+
+typedef struct {
+  int state;             /* 0 queued, 1 running, 2 done, 3 failed                  */
+  int moves;             /* moves made                                             */
+  int converged;         /* 1 if delta < tol was reached                           */
+  double delta;          /* delta of the last move                                 */
+  double kappa;          /* norm per site of the final environment                 */
+  double bond_h, bond_v; /* <op> on a horizontal / vertical bond (0 without op)    */
+  double t_submit, t_admit, t_done; /* seconds on the server clock                 */
+  size_t bytes;          /* arena bytes held while running                         */
+} ctm_result;
+
+/* Creates a server with an arena of arena_bytes device bytes and max_slots
+ * (1..64) concurrent requests.  CTM_E_NOMEM if the arena cannot be allocated. */
+ctm_status ctm_server_create(ctm_server** out, size_t arena_bytes, int max_slots);
+
+/* Waits for and releases everything the server holds. */
+void ctm_server_destroy(ctm_server* server);
+
+/* Queues one environment solve.  All inputs are host arrays, copied before
+ * the call returns: site_host as site_dev of ctm_init; boundary_host (Dl
+ * doubles) or NULL as in ctm_init; X0_host and Yt0_host (4 N k doubles each,
+ * as ctm_set_isometries) or both NULL; op_host a d^2 x d^2 bond operator
+ * evaluated on both bond directions at the end, or NULL.  The solve stops at
+ * delta < tol (full environment dimension) or after max_moves moves.
+ * CTM_E_NOMEM if the request could never fit into the arena. */
+ctm_status ctm_server_submit(ctm_server* server, const ctm_config* cfg, const double* site_host,
+                             const double* boundary_host, const double* X0_host,
+                             const double* Yt0_host, const double* op_host, double tol,
+                             int max_moves, int* id);
+
+/* Non-blocking progress (see above); n_running and n_queued may be NULL. */
+ctm_status ctm_server_pump(ctm_server* server, int* n_running, int* n_queued);
+
+/* Snapshot of request id's state and result. */
+ctm_status ctm_server_result(const ctm_server* server, int id, ctm_result* out);
+
+/* Error message of a failed request ("" otherwise). */
+const char* ctm_server_error(const ctm_server* server, int id);
+
+/* Seconds since the server was created (the clock of the result stamps). */
+double ctm_server_clock(const ctm_server* server);
 
 /* ---------------------------------------------------------------------------
  * Building blocks of a move, exposed for testing and for callers composing

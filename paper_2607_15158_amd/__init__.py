@@ -51,6 +51,14 @@ class ctm_move_info(ctypes.Structure):
                 ("gap", ctypes.c_double)]
 
 
+class ctm_result(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("moves", ctypes.c_int), ("converged", ctypes.c_int),
+                ("delta", ctypes.c_double), ("kappa", ctypes.c_double), ("bond_h", ctypes.c_double),
+                ("bond_v", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("bytes", ctypes.c_size_t)]
+
+
 class ctm_prof_entry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -66,6 +74,16 @@ _sigs = {
     "ctm_destroy": (None, [_vp]),
     "ctm_set_isometries": (ctypes.c_int, [_vp, _vp, _vp]),
     "ctm_move": (ctypes.c_int, [_vp, ctypes.POINTER(ctm_move_info)]),
+    "ctm_move_async": (ctypes.c_int, [_vp]),
+    "ctm_move_poll": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctm_move_info)]),
+    "ctm_server_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_int]),
+    "ctm_server_destroy": (None, [_vp]),
+    "ctm_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(ctm_config), _dp, _dp, _dp, _dp, _dp,
+                                         ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "ctm_server_pump": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ctm_server_result": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctm_result)]),
+    "ctm_server_error": (ctypes.c_char_p, [_vp, ctypes.c_int]),
+    "ctm_server_clock": (ctypes.c_double, [_vp]),
     "ctm_converge": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), _dp]),
     "ctm_observable": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
@@ -189,6 +207,18 @@ class Ctm:
         _check(_lib.ctm_move(self._h, ctypes.byref(info)), self._h)
         return {"delta": info.delta, "mode": info.mode, "chi_env": info.chi_env, "gap": info.gap}
 
+    def move_async(self) -> None:
+        _check(_lib.ctm_move_async(self._h), self._h)
+
+    def move_poll(self) -> Optional[dict]:
+        """None while the move in flight runs, else its info."""
+        done = ctypes.c_int(0)
+        info = ctm_move_info()
+        _check(_lib.ctm_move_poll(self._h, ctypes.byref(done), ctypes.byref(info)), self._h)
+        if not done.value:
+            return None
+        return {"delta": info.delta, "mode": info.mode, "chi_env": info.chi_env, "gap": info.gap}
+
     def converge(self, tol: float, max_moves: int, raise_on_budget: bool = False):
         n = ctypes.c_int(0)
         dl = ctypes.c_double(0.0)
@@ -276,6 +306,64 @@ def _ptr_array(ts):
     for i, t in enumerate(ts):
         arr[i] = None if t is None else t.data_ptr()
     return arr
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+class Server:
+    """Continuous batching of environment solves (see ctm_server_* in include/ctm.h)."""
+
+    STATES = ("queued", "running", "done", "failed")
+
+    def __init__(self, arena_bytes: int, max_slots: int):
+        self._h = _vp()
+        st = _lib.ctm_server_create(ctypes.byref(self._h), int(arena_bytes), int(max_slots))
+        if st != CTM_OK:
+            raise CtmError(st, "ctm_server_create failed")
+
+    def submit(self, cfg: Config, site, boundary=None, X0=None, Yt0=None, op=None,
+               tol: float = 1e-10, max_moves: int = 100) -> int:
+        c = cfg.c()
+        keep = [_dptr(site), _dptr(boundary), _dptr(X0), _dptr(Yt0), _dptr(op)]
+        rid = ctypes.c_int(-1)
+        st = _lib.ctm_server_submit(self._h, ctypes.byref(c), *[p for _, p in keep], float(tol),
+                                    int(max_moves), ctypes.byref(rid))
+        if st != CTM_OK:
+            raise CtmError(st, "ctm_server_submit rejected the request")
+        return rid.value
+
+    def pump(self):
+        run, queued = ctypes.c_int(0), ctypes.c_int(0)
+        _check(_lib.ctm_server_pump(self._h, ctypes.byref(run), ctypes.byref(queued)))
+        return run.value, queued.value
+
+    def result(self, rid: int) -> dict:
+        r = ctm_result()
+        _check(_lib.ctm_server_result(self._h, int(rid), ctypes.byref(r)))
+        out = {f: getattr(r, f) for f, _ in ctm_result._fields_}
+        out["state"] = self.STATES[r.state]
+        if r.state == 3:
+            out["error"] = _lib.ctm_server_error(self._h, int(rid)).decode()
+        return out
+
+    def clock(self) -> float:
+        return _lib.ctm_server_clock(self._h)
+
+    def close(self):
+        if self._h:
+            _lib.ctm_server_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gemm_f64(A: Sequence, B: Sequence, C: Sequence, M, N, K, trans_a=0, lda=None, ldb=None,

@@ -122,6 +122,12 @@ struct ctm_ctx {
   double* obs_op;            // [d^4] device copy of an operator
   rocblas_handle rb = nullptr;
   std::string err;
+  // asynchronous moves: results land in pinned host memory, completion is
+  // signalled by done_ev; the host-side state advances in finish_move
+  double* hbuf = nullptr;    // [0..15] scal copy, [16] bad flag (as int)
+  hipEvent_t done_ev = nullptr;
+  bool pending = false;
+  int pend_mode = 0, pend_keep = 0;
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -762,7 +768,12 @@ int spectra(ctm_ctx* c, int buf, int x) {
   return elem_spectra_delta(sp, c->st);
 }
 
-int do_move(ctm_ctx* c, ctm_move_info* info) {
+// Enqueues one move on the context's stream; its scalar results (norms,
+// delta, gaps, the numeric-guard flag) are copied to pinned host memory and
+// done_ev is recorded behind them.  The environment buffers of the next
+// generation are written; the context switches to them in finish_move.
+int enqueue_move(ctm_ctx* c) {
+  if (c->pending) return fail(c, CTM_E_STATE, "a move is already in flight");
   const int x = c->chi_env, N1 = x * c->Dl;
   int mode, keep;
   if (N1 <= c->chi) {
@@ -786,20 +797,32 @@ int do_move(ctm_ctx* c, ctm_move_info* info) {
     TRY(full_projectors(c, keep));
   } else {
     TRY(si_projectors(c, keep));
-    ++c->si_moves;
   }
   TRY(renormalize(c, keep));
   const int nxt = 1 - c->cur;
   TRY(normalize_env(c, nxt, keep));
   TRY(spectra(c, nxt, keep));
-  double host[16];
+  CTM_HIP_TRY(hipMemcpyAsync(c->hbuf, c->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  CTM_HIP_TRY(hipMemcpyAsync(c->hbuf + 16, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  CTM_HIP_TRY(hipEventRecord(c->done_ev, c->st));
+  c->pending = true;
+  c->pend_mode = mode;
+  c->pend_keep = keep;
+  return CTM_OK;
+}
+
+// Completes the move in flight (done_ev has fired): checks the numeric guard
+// and switches to the new environment generation.
+int finish_move(ctm_ctx* c, ctm_move_info* info) {
+  c->pending = false;
+  const double* host = c->hbuf;
   int bad = 0;
-  CTM_HIP_TRY(hipMemcpyAsync(host, c->scal, sizeof(host), hipMemcpyDeviceToHost, c->st));
-  CTM_HIP_TRY(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
-  CTM_HIP_TRY(hipStreamSynchronize(c->st));
+  std::memcpy(&bad, c->hbuf + 16, sizeof(int));
   if (bad || !std::isfinite(host[8]))
     return fail(c, CTM_E_NUMERIC, "move produced a zero or non-finite norm; environment kept");
-  c->cur = nxt;
+  const int mode = c->pend_mode, keep = c->pend_keep;
+  if (mode == 2) ++c->si_moves;
+  c->cur = 1 - c->cur;
   c->chi_env = keep;
   c->spec_cur = 1 - c->spec_cur;
   ++c->moves;
@@ -815,6 +838,23 @@ int do_move(ctm_ctx* c, ctm_move_info* info) {
     info->gap = gap;
   }
   return CTM_OK;
+}
+
+int wait_move(ctm_ctx* c, ctm_move_info* info) {
+  CTM_HIP_TRY(hipEventSynchronize(c->done_ev));
+  return finish_move(c, info);
+}
+
+int do_move(ctm_ctx* c, ctm_move_info* info) {
+  TRY(enqueue_move(c));
+  return wait_move(c, info);
+}
+
+// Completes a move still in flight before a call that reads or replaces the
+// environment.
+int drain(ctm_ctx* c) {
+  if (!c->pending) return CTM_OK;
+  return wait_move(c, nullptr);
 }
 
 
@@ -1101,6 +1141,12 @@ ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev
   }
   c->ws_bytes = need;
   carve(c, (char*)c->ws);
+  if (hipHostMalloc((void**)&c->hbuf, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess) {
+    std::string m = "pinned host buffer or event creation failed";
+    ctm_destroy(c);
+    return (ctm_status)fail(nullptr, CTM_E_NOMEM, m);
+  }
   auto bail = [&](int code) {
     std::string m = c->err.empty() ? g_err : c->err;
     ctm_destroy(c);
@@ -1163,6 +1209,8 @@ void ctm_destroy(ctm_ctx* c) {
   if (c->st) (void)hipStreamSynchronize(c->st);
   else (void)hipDeviceSynchronize();
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->done_ev) (void)hipEventDestroy(c->done_ev);
+  if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->rb) rocblas_destroy_handle(c->rb);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   delete c;
@@ -1170,6 +1218,7 @@ void ctm_destroy(ctm_ctx* c) {
 
 ctm_status ctm_set_isometries(ctm_ctx* c, const double* X_dev, const double* Yt_dev) {
   if (!c || !X_dev || !Yt_dev) return (ctm_status)fail(c, CTM_E_ARG, "null argument");
+  if (c->pending) return (ctm_status)fail(c, CTM_E_STATE, "a move is in flight");
   const size_t nk = (size_t)c->N * c->k;
   for (int b = 0; b < 4; ++b) {
     if (hipMemcpyAsync(c->X0[b], X_dev + b * nk, nk * 8, hipMemcpyDeviceToDevice, c->st) !=
@@ -1187,7 +1236,30 @@ ctm_status ctm_move(ctm_ctx* c, ctm_move_info* info) {
   if (!c) return (ctm_status)fail(nullptr, CTM_E_ARG, "null context");
   c->err.clear();
   g_err.clear();
+  const int r = drain(c);
+  if (r) return (ctm_status)r;
   return (ctm_status)do_move(c, info);
+}
+
+ctm_status ctm_move_async(ctm_ctx* c) {
+  if (!c) return (ctm_status)fail(nullptr, CTM_E_ARG, "null context");
+  c->err.clear();
+  return (ctm_status)enqueue_move(c);
+}
+
+ctm_status ctm_move_poll(ctm_ctx* c, int* done, ctm_move_info* info) {
+  if (!c || !done) return (ctm_status)fail(c, CTM_E_ARG, "null argument");
+  *done = 0;
+  if (!c->pending) return (ctm_status)fail(c, CTM_E_STATE, "no move in flight");
+  const hipError_t q = hipEventQuery(c->done_ev);
+  if (q == hipErrorNotReady) return CTM_OK;
+  if (q != hipSuccess) {
+    c->pending = false;
+    return (ctm_status)fail(c, CTM_E_DEVICE, std::string("move failed on the device: ") +
+                                                 hipGetErrorString(q));
+  }
+  *done = 1;
+  return (ctm_status)finish_move(c, info);
 }
 
 ctm_status ctm_converge(ctm_ctx* c, double tol, int max_moves, int* moves_done,
@@ -1226,6 +1298,10 @@ ctm_status ctm_state_size(const ctm_ctx* c, size_t* n) {
 
 ctm_status ctm_get_state(ctm_ctx* c, double* host, size_t n) {
   size_t need;
+  if (c && c->pending) {
+    const int rd = drain(c);
+    if (rd) return (ctm_status)rd;
+  }
   if (ctm_state_size(c, &need) != CTM_OK || !host || n < need)
     return (ctm_status)fail(c, CTM_E_ARG, "state buffer too small");
   const size_t chi = c->chi, Dl = c->Dl, N = c->N, k = c->k;
@@ -1254,6 +1330,10 @@ ctm_status ctm_get_state(ctm_ctx* c, double* host, size_t n) {
 
 ctm_status ctm_set_state(ctm_ctx* c, const double* host, size_t n) {
   size_t need;
+  if (c && c->pending) {
+    const int rd = drain(c);
+    if (rd) return (ctm_status)rd;
+  }
   if (ctm_state_size(c, &need) != CTM_OK || !host || n < need)
     return (ctm_status)fail(c, CTM_E_ARG, "state buffer too small");
   const size_t chi = c->chi, Dl = c->Dl, N = c->N, k = c->k;
@@ -1290,6 +1370,8 @@ ctm_status ctm_set_state(ctm_ctx* c, const double* host, size_t n) {
 ctm_status ctm_observable(ctm_ctx* c, int kind, const double* op_host, double* out_host) {
   if (!c || !out_host) return (ctm_status)fail(c, CTM_E_ARG, "null argument");
   c->err.clear();
+  const int rd = drain(c);
+  if (rd) return (ctm_status)rd;
   const bool prof = c->prof;
   c->prof = false;
   const int r = observable(c, kind, op_host, out_host);
