@@ -207,10 +207,10 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
   constexpr int LA = BM + 16, LB = BN + 16;   // row lengths: 16-lane groups on distinct banks
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int MI = WTM / 16, NI = WTN / 16;
-  constexpr int VA = BM * BK / 2 / 256, VB = BN * BK / 2 / 256;
+  constexpr int NA = BM * BK / 2, NB = BN * BK / 2;    // 16-byte loads per slice
+  constexpr int VA = (NA + 255) / 256, VB = (NB + 255) / 256;
   static_assert(WGM * WGN == 4, "four wavefronts");
   static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile multiple of 16");
-  static_assert((BM * BK / 2) % 256 == 0 && (BN * BK / 2) % 256 == 0, "tile loads");
 
   __shared__ double As[2][BK][LA];
   __shared__ double Bs[2][BK][LB];
@@ -239,7 +239,8 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
       if (trans) { gk = k0 + i / (BM / 2); gm = m0 + 2 * (i % (BM / 2)); }
       else { gm = m0 + i / (BK / 2); gk = k0 + 2 * (i % (BK / 2)); }
       v2d v = {0.0, 0.0};
-      if (trans) {
+      if (i >= NA) {
+      } else if (trans) {
         if (gk < K) {
           const double* p = A + (long)gk * lda + gm;
           if (gm + 1 < M) v = *(const v2d*)p;
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
       const int i = tid + e * 256;
       const int gk = k0 + i / (BN / 2), gn = n0 + 2 * (i % (BN / 2));
       v2d v = {0.0, 0.0};
-      if (gk < K) {
+      if (i < NB && gk < K) {
         const double* p = B + (long)gk * ldb + gn;
         if (gn + 1 < N) v = *(const v2d*)p;
         else if (gn < N) v.x = p[0];
@@ -269,7 +270,8 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
 #pragma unroll
     for (int e = 0; e < VA; ++e) {
       const int i = tid + e * 256;
-      if (trans) {
+      if (i >= NA) {
+      } else if (trans) {
         const int kk = i / (BM / 2), m = 2 * (i % (BM / 2));
         *(v2d*)&As[buf][kk][m] = ra[e];
       } else {
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
 #pragma unroll
     for (int e = 0; e < VB; ++e) {
       const int i = tid + e * 256;
-      *(v2d*)&Bs[buf][i / (BN / 2)][2 * (i % (BN / 2))] = rb[e];
+      if (i < NB) *(v2d*)&Bs[buf][i / (BN / 2)][2 * (i % (BN / 2))] = rb[e];
     }
   };
 
@@ -559,6 +561,21 @@ int launch_gemm_si(const GemmBatch& g, hipStream_t s) {
   return launch_skinny<96, 160, 2, 2, 1>(g, s);
 }
 
+namespace {
+// float64 GEMMs long enough for the double-buffered tiles: N <= 160 takes
+// the 96 x 160 tile, wider N the 128 x 144 tile (144 divides the D^4 = 1296
+// columns of the double-layer absorptions at D = 6).
+bool launch_f64_db(const GemmBatch& g, hipStream_t s, int* rc) {
+  // short K (a few slices per tile) gains nothing from the double buffer
+  if (g.K < 512 || g.M < 256 || !skinny_ok(g)) return false;
+  if (g.N <= 160)
+    *rc = launch_skinny<96, 160, 2, 2, 0>(g, s);
+  else
+    *rc = launch_skinny<128, 144, 4, 1, 0>(g, s);
+  return true;
+}
+}  // namespace
+
 // Compute type: float64 when any operand is float64 and the mode is f64;
 // the caller selects the mode through the operand types:
 //   (F64, F64, *)   -> float64 MFMA
@@ -570,6 +587,8 @@ int launch_gemm(const GemmBatch& g, DT ta, DT tb, DT tc, hipStream_t s) {
     // empty sum: the kernels still write zeros (load loop does not run)
   }
   if (ta == DT::F64 && tb == DT::F64) {
+    int rc = 0;
+    if (tc == DT::F64 && launch_f64_db(g, s, &rc)) return rc;
     if (tc == DT::F64) return launch_k4<double, double, double, double>(g, s);
     if (tc == DT::F32) return launch_k4<double, double, float, double>(g, s);
   }

@@ -15,14 +15,16 @@
 // Block-pair parallel ordering: the columns are cut into blocks of kBlk; an
 // outer sweep pairs the blocks in a round-robin tournament, one launch per
 // round, one workgroup per block pair and matrix.  The workgroup loads the
-// 2 kBlk columns of U (and V) into LDS and rotates all pairs among them in
-// 2 kBlk - 1 inner rounds of kBlk disjoint pairs, 16 lanes per pair
-// (rows spread over the lanes, dot products reduced by cross-lane shuffles).
+// 2 kBlk columns of U into LDS and rotates all pairs among them once, in
+// 2 kBlk - 1 inner rounds of kBlk disjoint pairs, 16 lanes per pair (rows
+// spread over the lanes, dot products reduced by DPP row sums); the
+// rotations of the visit are accumulated in a 2 kBlk x 2 kBlk matrix W and
+// applied to the right vectors once at the end (V_cols <- V_cols W).
 // Every column pair meets in every outer sweep; a per-matrix flag records
 // whether a sweep rotated anything, and later launches return at once after
-// a sweep without rotations.  Columns that end exactly zero (rank-deficient
-// input) are replaced by an orthonormal completion so that u stays
-// orthogonal.  Singular values are returned in descending order (ties by
+// a sweep without rotations.  Columns that end numerically zero
+// (rank-deficient input) are replaced by an orthonormal completion so that
+// u stays orthogonal.  Singular values are returned in descending order (ties by
 // index).
 
 #include "common.h"
@@ -34,9 +36,8 @@ constexpr int kSvdMaxN = 192;   // the preconditioning QR holds n <= 192 rows pe
 constexpr int kRPL = kSvdMaxN / 64;   // rows per lane in the finalisation
 constexpr int kBlk = 16;              // columns per block
 constexpr int kMaxSweeps = 24;
-constexpr int kInner = 2;            // inner sweeps per block-pair visit
+constexpr int kInner = 1;            // inner sweeps per block-pair visit
 constexpr int kLanesPerPair = 16;
-constexpr int kRowsPerLane = kSvdMaxN / kLanesPerPair;
 
 __device__ __forceinline__ double wsum(double x) { return wave_sum64(x); }
 
@@ -127,10 +128,33 @@ __global__ void svd_unpermute_rows(SvdArgs a) {
   }
 }
 
-// One round of an outer sweep: block pair (tournament positions bp, nblk-1-bp).
-__global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int round) {
-  __shared__ double Ul[2 * kBlk][kSvdMaxN + 1];   // odd row length: no bank conflicts
-  __shared__ double Vl[2 * kBlk][kSvdMaxN + 1];
+// 1/sqrt(x) and 1/x to full double precision from the hardware estimates
+// (Newton steps); used for the rotation angles, where x > 0.
+__device__ __forceinline__ double fast_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x * y;
+  y = fma(y, fma(-h, y, 0.5), y);
+  h = 0.5 * x * y;
+  return fma(y, fma(-h, y, 0.5), y);
+}
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// One round of an outer sweep: block pair (tournament positions bp,
+// nblk-1-bp).  The 2 kBlk columns of U live in LDS; the rotations of the
+// visit are accumulated in a 2 kBlk x 2 kBlk matrix W (also in LDS) and the
+// right vectors are updated once at the end, V_cols <- V_cols W.  RPL is the
+// number of rows per lane (n <= 16 RPL).
+template <int RPL>
+__global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int round, int inner) {
+  constexpr int kC = 2 * kBlk;
+  constexpr int LD = 16 * RPL + 1;   // odd row length: no bank conflicts
+  __shared__ double Ul[kC][LD];
+  __shared__ double Vl[kC][LD];
+  __shared__ double Wl[kC][kC + 1];
   __shared__ int rot;
   const int mat = blockIdx.y;
   if (sweep > 0 && a.flags[mat * kMaxSweeps + sweep - 1] == 0) return;   // converged
@@ -144,24 +168,25 @@ __global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int
   auto gcol = [&](int j) { return (j < kBlk ? b0 : b1) * kBlk + (j % kBlk); };
   // 8 independent loads in flight per thread (one workgroup per CU)
   const int nv = a.want_v ? 2 : 1;
-  for (int base = tid; base < nv * 2 * kBlk * n; base += 256 * 8) {
+  for (int base = tid; base < nv * kC * n; base += 256 * 8) {
     double t[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = base + u * 256;
-      const int h = idx / (2 * kBlk * n), rem = idx % (2 * kBlk * n);
+      const int h = idx / (kC * n), rem = idx % (kC * n);
       const int g = gcol(rem / n);
-      t[u] = (idx < nv * 2 * kBlk * n && g < n) ? (h ? Vc : Uc)[(size_t)g * n + rem % n] : 0.0;
+      t[u] = (idx < nv * kC * n && g < n) ? (h ? Vc : Uc)[(size_t)g * n + rem % n] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = base + u * 256;
-      if (idx < nv * 2 * kBlk * n) {
-        const int h = idx / (2 * kBlk * n), rem = idx % (2 * kBlk * n);
+      if (idx < nv * kC * n) {
+        const int h = idx / (kC * n), rem = idx % (kC * n);
         (h ? Vl : Ul)[rem / n][rem % n] = t[u];
       }
     }
   }
+  for (int idx = tid; idx < kC * kC; idx += 256) Wl[idx / kC][idx % kC] = (idx / kC == idx % kC);
   if (tid == 0) rot = 0;
   __syncthreads();
   const int grp = tid / kLanesPerPair, li = tid % kLanesPerPair;   // 16 pair groups
@@ -171,16 +196,16 @@ __global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int
   // not change the result above roundoff; they are completed at the end
   const double negl = 1e-30 * a.fro2[mat];
   int my_rot = 0;
-  for (int rr = 0; rr < kInner * (2 * kBlk - 1); ++rr) {
-    const int r = rr % (2 * kBlk - 1);
-    const int ca = tour(grp, r, 2 * kBlk), cb = tour(2 * kBlk - 1 - grp, r, 2 * kBlk);
+  for (int rr = 0; rr < inner * (kC - 1); ++rr) {
+    const int r = rr % (kC - 1);
+    const int ca = tour(grp, r, kC), cb = tour(kC - 1 - grp, r, kC);
     const int p = min(ca, cb), q = max(ca, cb);
     const bool live = gcol(p) < n && gcol(q) < n;
     if (live) {
-      double up[kRowsPerLane], uq[kRowsPerLane];
+      double up[RPL], uq[RPL];
       double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-      for (int t = 0; t < kRowsPerLane; ++t) {
+      for (int t = 0; t < RPL; ++t) {
         const int row = li + kLanesPerPair * t;
         up[t] = row < n ? Ul[p][row] : 0.0;
         uq[t] = row < n ? Ul[q][row] : 0.0;
@@ -193,24 +218,30 @@ __global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int
       ga = gsum16(ga);
       const double thr = tol * sqrt(al) * sqrt(be);
       if (ga != 0.0 && fabs(ga) > thr && al > negl && be > negl) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        // tan of the rotation angle, the smaller root of t^2 + 2 zeta t = 1
+        const double zeta = (be - al) * fast_rcp(2.0 * ga);
+        const double z2 = 1.0 + zeta * zeta;
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) * fast_rcp(fabs(zeta) + z2 * fast_rsqrt(z2));
+        const double c = fast_rsqrt(1.0 + t * t), s = c * t;
         // convergence counts only rotations clearly above roundoff: a pair
         // left at |gamma| ~ tol sqrt(alpha beta) keeps being rotated but does
         // not prevent the sweep loop from stopping
         if (fabs(ga) > 16.0 * thr) ++my_rot;
 #pragma unroll
-        for (int tt = 0; tt < kRowsPerLane; ++tt) {
+        for (int tt = 0; tt < RPL; ++tt) {
           const int row = li + kLanesPerPair * tt;
           if (row < n) {
             Ul[p][row] = c * up[tt] - s * uq[tt];
             Ul[q][row] = s * up[tt] + c * uq[tt];
-            if (a.want_v) {
-              const double vp = Vl[p][row], vq = Vl[q][row];
-              Vl[p][row] = c * vp - s * vq;
-              Vl[q][row] = s * vp + c * vq;
-            }
+          }
+        }
+        if (a.want_v) {
+#pragma unroll
+          for (int tt = 0; tt < kC / kLanesPerPair; ++tt) {
+            const int row = li + kLanesPerPair * tt;
+            const double wp = Wl[row][p], wq = Wl[row][q];
+            Wl[row][p] = c * wp - s * wq;
+            Wl[row][q] = s * wp + c * wq;
           }
         }
       }
@@ -218,15 +249,28 @@ __global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int
     __syncthreads();
   }
   if (li == 0 && my_rot) atomicAdd(&rot, my_rot);
-  __syncthreads();
-  for (int idx = tid; idx < 2 * kBlk * n; idx += 256) {
+  for (int idx = tid; idx < kC * n; idx += 256) {
     const int j = idx / n, rr = idx % n;
     const int g = gcol(j);
-    if (g < n) {
-      Uc[(size_t)g * n + rr] = Ul[j][rr];
-      if (a.want_v) Vc[(size_t)g * n + rr] = Vl[j][rr];
+    if (g < n) Uc[(size_t)g * n + rr] = Ul[j][rr];
+  }
+  if (a.want_v) {
+    // V_cols <- V_cols W: thread t owns row t (n <= 16 RPL <= 256)
+    for (int r = tid; r < n; r += 256) {
+      double v[kC];
+#pragma unroll
+      for (int l = 0; l < kC; ++l) v[l] = Vl[l][r];
+#pragma unroll 4
+      for (int j = 0; j < kC; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < kC; ++l) acc += v[l] * Wl[l][j];
+        const int g = gcol(j);
+        if (g < n) Vc[(size_t)g * n + r] = acc;
+      }
     }
   }
+  __syncthreads();
   if (tid == 0 && rot) atomicOr(&a.flags[mat * kMaxSweeps + sweep], 1);
 }
 
@@ -395,9 +439,19 @@ int launch_svd(int count, const double* const* A, double* const* U, double* cons
   r = launch_gemm(g, DT::F64, DT::F64, DT::F64, s);
   if (r) return r;
   svd_init<<<dim3(std::max(1, std::min(64, n * n / 256)), count), 256, 0, s>>>(a);
+  const int rpl = (n + kLanesPerPair - 1) / kLanesPerPair;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep)
-    for (int round = 0; round < nblk - 1; ++round)
-      svd_block_round<<<dim3(nblk / 2, count), 256, 0, s>>>(a, sweep, round);
+    for (int round = 0; round < nblk - 1; ++round) {
+      const dim3 grid(nblk / 2, count);
+      if (rpl <= 4)
+        svd_block_round<4><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
+      else if (rpl <= 8)
+        svd_block_round<8><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
+      else if (rpl <= 10)
+        svd_block_round<10><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
+      else
+        svd_block_round<12><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
+    }
   svd_finalize<<<count, 1024, 0, s>>>(a);
   CTM_HIP_TRY(hipGetLastError());
   if (want_u) {   // u = Q V'
