@@ -201,19 +201,30 @@ __global__ __launch_bounds__(256) void gemm_k4(GemmBatch g, int tiles_m, int til
 // ---------------------------------------------------------------------------
 typedef double v2d __attribute__((ext_vector_type(2)));
 
-template <int BM, int BN, int WGM, int WGN, int ROLE>
-__global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles_m, int tiles_n) {
+// LDS layouts of the A slice: transposed operands arrive m-contiguous and are
+// kept as [k][m] (rows padded by 16 doubles); plain ones arrive
+// k-contiguous and are kept as [m][k] with rows of BK + 1 doubles, so that
+// both the 16-byte row loads and the fragment reads (16 consecutive m at
+// fixed k per lane group) avoid bank conflicts.
+template <int BM, int BK>
+struct SkinnyA {
+  static constexpr int LT = BM + 16;          // [k][m] row length
+  static constexpr int LN = BK + 1;           // [m][k] row length
+  static constexpr int SIZE = (BK * LT > BM * LN) ? BK * LT : BM * LN;
+};
+
+template <int BM, int BN, int WGM, int WGN, bool TRANS>
+__device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int tiles_n,
+                                            double (*As)[SkinnyA<BM, 16>::SIZE],
+                                            double (*Bs)[16][BN + 16]) {
   constexpr int BK = 16;
-  constexpr int LA = BM + 16, LB = BN + 16;   // row lengths: 16-lane groups on distinct banks
+  using AL = SkinnyA<BM, BK>;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int MI = WTM / 16, NI = WTN / 16;
   constexpr int NA = BM * BK / 2, NB = BN * BK / 2;    // 16-byte loads per slice
   constexpr int VA = (NA + 255) / 256, VB = (NB + 255) / 256;
   static_assert(WGM * WGN == 4, "four wavefronts");
   static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile multiple of 16");
-
-  __shared__ double As[2][BK][LA];
-  __shared__ double Bs[2][BK][LB];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
@@ -224,7 +235,6 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
   const int tn = tile % tiles_n, tm = tile / tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
   const int M = g.M, N = g.N, K = g.K;
-  const bool trans = g.transA[prob] != 0;
   const double* A = (const double*)g.A[prob] + (long)batch * g.a_bs;
   const double* B = (const double*)g.B[prob] + (long)batch * g.b_bs;
   double* C = (double*)g.C[prob] + (long)batch * g.c_bs;
@@ -235,21 +245,23 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
 #pragma unroll
     for (int e = 0; e < VA; ++e) {
       const int i = tid + e * 256;
-      int gm, gk;
-      if (trans) { gk = k0 + i / (BM / 2); gm = m0 + 2 * (i % (BM / 2)); }
-      else { gm = m0 + i / (BK / 2); gk = k0 + 2 * (i % (BK / 2)); }
       v2d v = {0.0, 0.0};
-      if (i >= NA) {
-      } else if (trans) {
-        if (gk < K) {
-          const double* p = A + (long)gk * lda + gm;
-          if (gm + 1 < M) v = *(const v2d*)p;
-          else if (gm < M) v.x = p[0];
+      if (i < NA) {
+        if (TRANS) {
+          const int gk = k0 + i / (BM / 2), gm = m0 + 2 * (i % (BM / 2));
+          if (gk < K) {
+            const double* p = A + (long)gk * lda + gm;
+            if (gm + 1 < M) v = *(const v2d*)p;
+            else if (gm < M) v.x = p[0];
+          }
+        } else {
+          const int gm = m0 + i / (BK / 2), gk = k0 + 2 * (i % (BK / 2));
+          if (gm < M) {
+            const double* p = A + (long)gm * lda + gk;
+            if (gk + 1 < K) v = *(const v2d*)p;
+            else if (gk < K) v.x = p[0];
+          }
         }
-      } else if (gm < M) {
-        const double* p = A + (long)gm * lda + gk;
-        if (gk + 1 < K) v = *(const v2d*)p;
-        else if (gk < K) v.x = p[0];
       }
       ra[e] = v;
     }
@@ -270,14 +282,15 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
 #pragma unroll
     for (int e = 0; e < VA; ++e) {
       const int i = tid + e * 256;
-      if (i >= NA) {
-      } else if (trans) {
-        const int kk = i / (BM / 2), m = 2 * (i % (BM / 2));
-        *(v2d*)&As[buf][kk][m] = ra[e];
-      } else {
-        const int m = i / (BK / 2), kk = 2 * (i % (BK / 2));
-        As[buf][kk][m] = ra[e].x;
-        As[buf][kk + 1][m] = ra[e].y;
+      if (i < NA) {
+        if (TRANS) {
+          const int kk = i / (BM / 2), m = 2 * (i % (BM / 2));
+          *(v2d*)&As[buf][kk * AL::LT + m] = ra[e];
+        } else {
+          const int m = i / (BK / 2), kk = 2 * (i % (BK / 2));
+          As[buf][m * AL::LN + kk] = ra[e].x;
+          As[buf][m * AL::LN + kk + 1] = ra[e].y;
+        }
       }
     }
 #pragma unroll
@@ -305,7 +318,10 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
       double a[MI], b[NI];
       const int kr = ks + (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < MI; ++i) a[i] = As[buf][kr][wm * WTM + i * 16 + (lane & 15)];
+      for (int i = 0; i < MI; ++i) {
+        const int m = wm * WTM + i * 16 + (lane & 15);
+        a[i] = TRANS ? As[buf][kr * AL::LT + m] : As[buf][m * AL::LN + kr];
+      }
 #pragma unroll
       for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn * WTN + j * 16 + (lane & 15)];
 #pragma unroll
@@ -344,6 +360,18 @@ __global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles
       }
     }
   }
+}
+
+template <int BM, int BN, int WGM, int WGN, int ROLE>
+__global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles_m, int tiles_n) {
+  __shared__ double As[2][SkinnyA<BM, 16>::SIZE];
+  __shared__ double Bs[2][16][BN + 16];
+  const int per_prob = tiles_m * tiles_n;
+  const int prob = xcd_remap(blockIdx.x, gridDim.x) / per_prob / g.nbatch;
+  if (g.transA[prob])
+    skinny_tile<BM, BN, WGM, WGN, true>(g, tiles_m, tiles_n, As, Bs);
+  else
+    skinny_tile<BM, BN, WGM, WGN, false>(g, tiles_m, tiles_n, As, Bs);
 }
 
 // ---------------------------------------------------------------------------
