@@ -47,6 +47,21 @@ def workload(D=6, chi=144, p=16, seed=3):
     return A, X, Y
 
 
+def measured_traffic(args):
+    """HBM bytes per SI-application launch from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when the GEMM
+    source or the workload differs from the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "si_apply_traffic.json")
+    if not os.path.exists(path) or args.prec != "f64" or (args.D, args.chi, args.p) != (6, 144, 16):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2607_15158_amd", "csrc", "gemm.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["gemm_hip_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(args, A, X, Y):
     """Times the FP64 oracle on a bounded sample of one SI move of this workload.
 
@@ -167,6 +182,12 @@ def main():
     ap.add_argument("--svd-driver", default="gesdd", choices=["gesdd", "gesvd"],
                     help="dense SVD of the growth move and of the full-SVD comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="copy 1 GiB device to device once before the moves (the reference "
+                         "dispatch for scaling hardware byte counters)")
+    ap.add_argument("--random-env", action="store_true",
+                    help="start from a seeded random environment of full dimension instead of "
+                         "the growth move (no rocSOLVER call; used for counter runs)")
     ap.add_argument("--serving", type=int, default=0,
                     help="run the serving workload with this many requests instead")
     ap.add_argument("--serve-slots", type=int, default=16)
@@ -186,6 +207,13 @@ def main():
         print(json.dumps(serving(args)), flush=True)
         return
     dev = torch.device("cuda", 0)
+    if args.copy_calib:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read, 1 GiB written")
+        del src, dst
     A, X, Y = workload(args.D, args.chi, args.p)
     cfg = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="si",
                    prec=args.prec, stabilized=1, pinv_rtol=args.pinv_rtol,
@@ -194,10 +222,19 @@ def main():
         f"workspace {P.workspace_bytes(cfg) / 2**30:.2f} GiB")
     ctx = P.Ctm(cfg, torch.from_numpy(A).to(dev))
     ctx.set_isometries(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
-    t = time.perf_counter()
-    info = ctx.move()                      # growth move (full SVD of the first M_b)
-    log(f"growth move mode={info['mode']} chi_env={info['chi_env']} "
-        f"{time.perf_counter() - t:.2f} s")
+    if args.random_env:
+        import synth as S
+        Dl = args.D * args.D
+        C = [S.gaussian_block(args.chi, args.chi, 60 + i) for i in range(4)]
+        T = [S.gaussian_block(args.chi * Dl, args.chi, 70 + i).reshape(args.chi, Dl, args.chi)
+             for i in range(4)]
+        ctx.set_state(ctx.pack_state(C, T, X, Y))
+        log("seeded random environment of full dimension (no growth move)")
+    else:
+        t = time.perf_counter()
+        info = ctx.move()                  # growth move (full SVD of the first M_b)
+        log(f"growth move mode={info['mode']} chi_env={info['chi_env']} "
+            f"{time.perf_counter() - t:.2f} s")
     for i in range(args.warmup):
         t = time.perf_counter()
         info = ctx.move()
@@ -230,7 +267,7 @@ def main():
     achieved = flops_launch / (per_launch_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": "si_apply (8 enlarged-corner applications per launch)",
                 "achieved": round(achieved, 2), "peak": PEAK[args.prec], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK[args.prec], 4), "traffic": None,
+                "frac": round(achieved / PEAK[args.prec], 4), "traffic": measured_traffic(args),
                 "launch_ms": round(per_launch_ms, 4), "flops_per_launch": flops_launch,
                 "algorithmic_GBps": round(bytes_launch / (per_launch_ms * 1e-3) / 1e9, 1)}
     total_flops = sum(e["flops"] for e in prof) / args.steps
