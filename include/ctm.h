@@ -56,6 +56,15 @@ typedef enum {
 
 typedef enum { CTM_PROJ_FULLSVD = 0, CTM_PROJ_SI = 1 } ctm_proj;
 
+/* Lattice symmetry exploited by the move.  CTM_SYM_C4V: a single symmetric
+ * corner C and edge T (stored in all four slots); the enlarged corner is
+ * symmetric and the projector an isometry shared by all bonds (full mode:
+ * eigenvectors of the chi largest |eigenvalues|; SI mode: QR iterations on
+ * one block and the eigenvectors of X^T Ct X).  The caller's site tensor
+ * must be invariant under the lattice rotations and reflections; float64
+ * contractions only. */
+typedef enum { CTM_SYM_NONE = 0, CTM_SYM_C4V = 1 } ctm_sym;
+
 /* Precision of the contractions only; QR, small SVD, pseudo-inverse,
  * projector scaling and the stored environment are always float64. */
 typedef enum { CTM_PREC_F64 = 0, CTM_PREC_F32 = 1, CTM_PREC_BF16 = 2 } ctm_prec;
@@ -82,6 +91,7 @@ typedef struct {
                        high relative accuracy), 1 = divide and conquer (rocSOLVER
                        gesdd via the eigenvectors of M^T M; an order of magnitude
                        faster, weak directions below ~1e-8 s_1 less accurate)     */
+  int sym;          /* ctm_sym                                                           */
 } ctm_config;
 
 typedef struct {

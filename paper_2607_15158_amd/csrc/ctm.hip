@@ -167,6 +167,10 @@ int validate(const ctm_config* cfg) {
   if (!(cfg->pinv_rtol >= 0.0)) return fail(nullptr, CTM_E_ARG, "pinv_rtol must be >= 0");
   if (cfg->svd_driver != 0 && cfg->svd_driver != 1)
     return fail(nullptr, CTM_E_ARG, "svd_driver must be 0 (gesvd) or 1 (gesdd)");
+  if (cfg->sym != CTM_SYM_NONE && cfg->sym != CTM_SYM_C4V)
+    return fail(nullptr, CTM_E_ARG, "sym must be CTM_SYM_NONE or CTM_SYM_C4V");
+  if (cfg->sym == CTM_SYM_C4V && cfg->prec != CTM_PREC_F64)
+    return fail(nullptr, CTM_E_ARG, "the C4v mode runs in float64 only");
   const int Dl = cfg->d > 0 ? cfg->D * cfg->D : cfg->D;
   const long N = (long)cfg->chi * Dl;
   const long k = std::min<long>(cfg->chi + cfg->p, N);
@@ -768,6 +772,121 @@ int spectra(ctm_ctx* c, int buf, int x) {
   return elem_spectra_delta(sp, c->st);
 }
 
+// ---------------------------------------------------------------------------
+// C4v moves (a single symmetric corner C and edge T; the QR-based projector
+// section specialised to the symmetric case, which the paper inherits from
+// the C4v QR-CTMRG): the enlarged corner Ct is symmetric and the projector is
+// an isometry P, the same for every bond.
+//  - growth: P = I;  full: P = eigenvectors of the chi largest |lambda| of Ct
+//    (rocSOLVER dsyevd), sign rule on the columns of P;
+//  - SI: X <- QR(Ct X) n_si times, rho = X^T Ct X, its eigenvectors v (from the
+//    Jacobi SVD of the symmetric rho: v_i with s_i = |lambda_i|), sign rule on
+//    the columns of X v, X <- X v, P = X[:, :chi].
+// The move then runs the four-direction renormalisation with P on every bond,
+// symmetrises C' and T' of the first corner and edge and copies them to the
+// other three.
+// ---------------------------------------------------------------------------
+int c4v_projectors(ctm_ctx* c, int mode, int keep) {
+  const int N1 = c->chi_env * c->Dl, k = c->k;
+  double* Ct0 = (double*)c->Ct[0];
+  TRY(elem_symmetrize(Ct0, N1, c->st));
+  double* P = c->Pl[0];
+  if (mode == 0) {
+    TRY(elem_identity(P, N1, N1, c->st));
+  } else if (mode == 1) {
+    TRY(ensure_rocblas(c));
+    CTM_HIP_TRY(hipMemcpyAsync(c->S2[0], Ct0, (size_t)N1 * N1 * 8, hipMemcpyDeviceToDevice, c->st));
+    {
+      ProfScope ps(c, PC_FULLSVD);
+      // column-major view of a symmetric matrix: the same matrix
+      const rocblas_status st = rocsolver_dsyevd(c->rb, rocblas_evect_original, rocblas_fill_upper,
+                                                 N1, c->S2[0], N1, c->fs_s, c->fs_E, c->fs_info);
+      if (st != rocblas_status_success)
+        return fail(c, CTM_E_DEVICE, "rocsolver_dsyevd failed: " + std::to_string((int)st));
+    }
+    TRY(elem_c4v_order(c->fs_s, c->S2[0], N1, keep, P, c->st));
+    SignArgs sa{};
+    sa.N = N1;
+    sa.k = keep;
+    sa.ld = keep;
+    sa.Y[0] = P;
+    sa.sg[0] = c->fs_sg;
+    TRY(elem_col_sign(sa, 1, c->st));
+    TRY(elem_scale_cols(sa, 1, c->st));
+  } else {
+    TRY(ensure_si_blocks(c));
+    auto apply = [&](const double* in, double* out) {
+      GemmBatch g = gemm_rowmajor(1, N1, k, N1, N1, k, k);
+      g.A[0] = Ct0;
+      g.B[0] = in;
+      g.C[0] = out;
+      const int chk = check_gemm(c, g, DT::F64, DT::F64, DT::F64);
+      if (chk) return chk;
+      ProfScope ps(c, PC_SI_APPLY, gemm_flops(g), (double)N1 * N1 * 8 + 2.0 * N1 * k * 8);
+      return launch_gemm_si(g, c->st);
+    };
+    for (int step = 0; step < c->cfg.n_si; ++step) {
+      TRY(apply(c->X[0], c->W[0][0]));
+      {
+        ProfScope ps(c, PC_QR, 4.0 * N1 * (double)k * k);
+        TRY(launch_qr(1, &c->W[0][0], N1, k, c->qr_ws, c->st));
+      }
+      std::swap(c->X[0], c->W[0][0]);
+    }
+    TRY(apply(c->X[0], c->W[0][0]));
+    {
+      GemmBatch g = gemm_rowmajor(1, k, k, N1, k, k, k);   // rho = X^T (Ct X)
+      g.A[0] = c->X[0];
+      g.transA[0] = 1;
+      g.B[0] = c->W[0][0];
+      g.C[0] = c->rho[0];
+      TRY(run_gemm(c, PC_PROJ, g, DT::F64, DT::F64, DT::F64));
+    }
+    TRY(elem_symmetrize(c->rho[0], k, c->st));
+    {
+      ProfScope ps(c, PC_SVD);
+      TRY(launch_svd(1, &c->rho[0], &c->u[0], &c->s[0], &c->v[0], k, c->svd_ws, c->st));
+    }
+    {
+      GemmBatch g = gemm_rowmajor(1, N1, k, k, k, k, k);   // X v
+      g.A[0] = c->X[0];
+      g.B[0] = c->v[0];
+      g.C[0] = c->W[0][0];
+      TRY(run_gemm(c, PC_PROJ, g, DT::F64, DT::F64, DT::F64));
+    }
+    SignArgs sa{};
+    sa.N = N1;
+    sa.k = k;
+    sa.ld = k;
+    sa.Y[0] = c->W[0][0];
+    sa.sg[0] = c->sg[0];
+    TRY(elem_col_sign(sa, 1, c->st));
+    TRY(elem_scale_cols(sa, 1, c->st));
+    std::swap(c->X[0], c->W[0][0]);
+    TRY(elem_copy_cols(c->X[0], N1, k, keep, P, c->st));
+  }
+  const size_t pb = (size_t)N1 * keep * 8;
+  for (int b = 0; b < 4; ++b) {
+    if (b) CTM_HIP_TRY(hipMemcpyAsync(c->Pl[b], P, pb, hipMemcpyDeviceToDevice, c->st));
+    CTM_HIP_TRY(hipMemcpyAsync(c->Prt[b], P, pb, hipMemcpyDeviceToDevice, c->st));
+  }
+  return 0;
+}
+
+// C' and T' of the first corner and edge, symmetrised, become all four.
+int c4v_finish(ctm_ctx* c, int gen, int keep) {
+  const int Dl = c->Dl;
+  TRY(elem_symmetrize(c->C[gen][0], keep, c->st));
+  TRY(elem_symmetrize_edge(c->T[gen][0], keep, Dl, c->st));
+  for (int i = 1; i < 4; ++i) {
+    CTM_HIP_TRY(hipMemcpyAsync(c->C[gen][i], c->C[gen][0], (size_t)keep * keep * 8,
+                               hipMemcpyDeviceToDevice, c->st));
+    CTM_HIP_TRY(hipMemcpyAsync(c->T[gen][i], c->T[gen][0], (size_t)keep * Dl * keep * 8,
+                               hipMemcpyDeviceToDevice, c->st));
+  }
+  return 0;
+}
+
 // Enqueues one move on the context's stream; its scalar results (norms,
 // delta, gaps, the numeric-guard flag) are copied to pinned host memory and
 // done_ev is recorded behind them.  The environment buffers of the next
@@ -788,7 +907,9 @@ int enqueue_move(ctm_ctx* c) {
   }
   CTM_HIP_TRY(hipMemsetAsync(c->bad, 0, sizeof(int), c->st));
   TRY(build_corners(c));
-  if (mode == 0) {
+  if (c->cfg.sym == CTM_SYM_C4V) {
+    TRY(c4v_projectors(c, mode, keep));
+  } else if (mode == 0) {
     for (int b = 0; b < 4; ++b) {
       TRY(elem_identity(c->Pl[b], N1, N1, c->st));
       TRY(elem_identity(c->Prt[b], N1, N1, c->st));
@@ -800,6 +921,7 @@ int enqueue_move(ctm_ctx* c) {
   }
   TRY(renormalize(c, keep));
   const int nxt = 1 - c->cur;
+  if (c->cfg.sym == CTM_SYM_C4V) TRY(c4v_finish(c, nxt, keep));
   TRY(normalize_env(c, nxt, keep));
   TRY(spectra(c, nxt, keep));
   CTM_HIP_TRY(hipMemcpyAsync(c->hbuf, c->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->st));
@@ -831,7 +953,7 @@ int finish_move(ctm_ctx* c, ctm_move_info* info) {
     info->mode = mode;
     info->chi_env = keep;
     double gap = -1.0;
-    if (mode != 0) {
+    if (mode != 0 && c->cfg.sym != CTM_SYM_C4V) {
       gap = 1e300;
       for (int b = 0; b < 4; ++b) gap = std::min(gap, host[9 + b]);
     }
@@ -1184,6 +1306,7 @@ ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev
                        c->st);
   if (rc) return bail(rc);
   rc = elem_init_env(c->a, c->e, Dl, c->C[0], c->T[0], c->st);
+  if (!rc && c->cfg.sym == CTM_SYM_C4V) rc = c4v_finish(c, 0, Dl);
   if (rc) return bail(rc);
   c->cur = 0;
   c->chi_env = Dl;

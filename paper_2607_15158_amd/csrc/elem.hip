@@ -387,6 +387,67 @@ __global__ void k_ratio(const double* a, const double* b, double* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = a[0] / b[0];
 }
 
+// ---------------------------------------------------------------------------
+// C4v helpers
+// ---------------------------------------------------------------------------
+// A <- (A + A^T) / 2 for a square row-major n x n matrix, one thread per pair.
+__global__ void k_symmetrize(double* A, int n) {
+  const long total = (long)n * n;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(i / n), c = (int)(i % n);
+    if (c < r) continue;
+    const double v = 0.5 * (A[(long)r * n + c] + A[(long)c * n + r]);
+    A[(long)r * n + c] = v;
+    A[(long)c * n + r] = v;
+  }
+}
+
+// T[a, m, b] <- (T[a, m, b] + T[b, m, a]) / 2 for an x x Dl x x edge tensor.
+__global__ void k_symmetrize_edge(double* T, int x, int Dl) {
+  const long total = (long)x * Dl * x;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    const int a = (int)(i / ((long)Dl * x)), m = (int)((i / x) % Dl), b = (int)(i % x);
+    if (b < a) continue;
+    const long p = ((long)a * Dl + m) * x + b, q = ((long)b * Dl + m) * x + a;
+    const double v = 0.5 * (T[p] + T[q]);
+    T[p] = v;
+    T[q] = v;
+  }
+}
+
+// P (n x keep, row-major) = eigenvectors of the keep eigenvalues of largest
+// |w|, in descending |w| with ties by index; V holds the eigenvectors as
+// columns of a column-major n x n matrix (rocSOLVER's layout).  One block.
+__global__ void k_c4v_order(const double* w, const double* V, int n, int keep, double* P) {
+  extern __shared__ int order[];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double aj = fabs(w[j]);
+    int rank = 0;
+    for (int o = 0; o < n; ++o) {
+      const double ao = fabs(w[o]);
+      rank += (ao > aj) || (ao == aj && o < j);
+    }
+    order[rank] = j;
+  }
+  __syncthreads();
+  for (long i = threadIdx.x; i < (long)n * keep; i += blockDim.x) {
+    const int r = (int)(i / keep), c = (int)(i % keep);
+    P[i] = V[(long)order[c] * n + r];
+  }
+}
+
+// P[r, c] = X[r, c] for c < keep (X has leading dimension ld).
+__global__ void k_copy_cols(const double* X, int n, long ld, int keep, double* P) {
+  const long total = (long)n * keep;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(i / keep), c = (int)(i % keep);
+    P[i] = X[(long)r * ld + c];
+  }
+}
+
 }  // namespace
 
 int elem_pair_dot(const double* X, const double* Y, long stride, int ni, int nj, int x, int m,
@@ -486,6 +547,36 @@ int elem_proj_prep_full(const double* U, const double* Vt, const double* sv, con
   const long total = (long)N * keep;
   const int blocks = (int)std::min<long>(2048, (total + 255) / 256);
   k_proj_prep_full<<<blocks, 256, 0, s>>>(U, Vt, sv, sg, N, keep, rtol, Us, Vs, gap);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_symmetrize(double* A, int n, hipStream_t s) {
+  const long total = (long)n * n;
+  const int blocks = (int)std::min<long>(1024, (total + 255) / 256);
+  k_symmetrize<<<blocks, 256, 0, s>>>(A, n);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_symmetrize_edge(double* T, int x, int Dl, hipStream_t s) {
+  const long total = (long)x * Dl * x;
+  const int blocks = (int)std::min<long>(1024, (total + 255) / 256);
+  k_symmetrize_edge<<<blocks, 256, 0, s>>>(T, x, Dl);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_c4v_order(const double* w, const double* V, int n, int keep, double* P, hipStream_t s) {
+  k_c4v_order<<<1, 256, n * sizeof(int), s>>>(w, V, n, keep, P);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_copy_cols(const double* X, int n, long ld, int keep, double* P, hipStream_t s) {
+  const long total = (long)n * keep;
+  const int blocks = (int)std::min<long>(1024, (total + 255) / 256);
+  k_copy_cols<<<blocks, 256, 0, s>>>(X, n, ld, keep, P);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -309,3 +309,49 @@ def test_f32_si_move_matches_oracle():
     st = ctx.unpack_state(ctx.get_state())
     assert st["chi_env"] == env.chi
     assert_spectra_close(st, env, 1e-5)
+
+
+@pytest.mark.parametrize("proj", ["svd", "si"])
+def test_c4v_ising_closed_forms_on_gpu(proj):
+    """The C4v mode (one symmetric corner and edge, isometric projector)
+    reproduces Onsager's free energy, Yang's magnetisation and the exact
+    nearest-neighbour correlation of the 2D Ising model at beta = 0.5."""
+    beta, chi = 0.5, 16
+    a, asig, e = S.ising_site(beta), S.ising_impurity(beta), S.ising_boundary(beta)
+    cfg = P.Config(d=0, D=2, chi=chi, p=8, n_si=2, proj=proj, sym="c4v")
+    ctx, _ = make(cfg, a, e)
+    res = ctx.converge(1e-12, 200)
+    assert res["converged"], res
+    lnk = np.log(ctx.kappa())
+    assert abs(lnk - gold(beta, "minus_beta_f")) <= 1e-10 * lnk
+    assert abs(ctx.observable(P.OBS_ONESITE, asig)[0] - gold(beta, "magnetisation")) <= 1e-9
+    two = np.concatenate([asig.ravel(), asig.ravel()])
+    for kind in (P.OBS_BOND_H, P.OBS_BOND_V):
+        assert abs(ctx.observable(kind, two)[0] - gold(beta, "nn_correlation")) <= 1e-9
+
+
+@pytest.mark.parametrize("proj", ["si", "svd"])
+def test_c4v_moves_match_oracle_step_by_step(proj):
+    """Growth, then full (eigen-decomposition) or SI C4v moves against the
+    oracle's C4v move, element by element, from the same initial
+    environment and start block."""
+    beta, chi = 0.45, 8
+    a, e = S.ising_site(beta), S.ising_boundary(beta)
+    cfg = P.Config(d=0, D=2, chi=chi, p=4, n_si=2, proj=proj, sym="c4v")
+    ctx, si = make(cfg, a, e)
+    C, T = O.c4v_initial_env(a, e)
+    X = si.X[0]
+    st = ctx.unpack_state(ctx.get_state())
+    assert rel(st["C"][0], C) <= 1e-14 and rel(st["T"][0], T) <= 1e-14
+    modes = []
+    for n in range(8):
+        info = ctx.move()
+        C, T, X, mode = O.c4v_move(C, T, a, chi, proj, X, n_si=2)
+        modes.append((info["mode"], mode))
+        st = ctx.unpack_state(ctx.get_state())
+        err = max(rel(st["C"][0], C), rel(st["T"][0], T))
+        print(f"move {n + 1}: gpu mode {info['mode']} oracle {mode} max rel err {err:.2e}")
+        assert info["mode"] == {"grow": 0, "svd": 1, "si": 2}[mode]
+        for i in range(4):
+            assert rel(st["C"][i], C) <= 1e-10 and rel(st["T"][i], T) <= 1e-10
+    assert [m[0] for m in modes] == [0, 0] + [2 if proj == "si" else 1] * 6
