@@ -185,6 +185,10 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="copy 1 GiB device to device once before the moves (the reference "
                          "dispatch for scaling hardware byte counters)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="run the moves on a dedicated stream with SI moves replayed from "
+                         "captured HIP graphs (the timed loop is then not profiled; the "
+                         "roofline comes from a profiled pass of 5 eager moves after it)")
     ap.add_argument("--random-env", action="store_true",
                     help="start from a seeded random environment of full dimension instead of "
                          "the growth move (no rocSOLVER call; used for counter runs)")
@@ -220,7 +224,8 @@ def main():
                    svd_driver=args.svd_driver)
     log(f"config d=2 D={args.D} chi={args.chi} k={cfg.k} N={cfg.N} prec={args.prec}; "
         f"workspace {P.workspace_bytes(cfg) / 2**30:.2f} GiB")
-    ctx = P.Ctm(cfg, torch.from_numpy(A).to(dev))
+    stream = torch.cuda.Stream() if args.graphs else None
+    ctx = P.Ctm(cfg, torch.from_numpy(A).to(dev), stream=stream)
     ctx.set_isometries(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
     if args.random_env:
         import synth as S
@@ -242,7 +247,10 @@ def main():
             f"{(time.perf_counter() - t) * 1e3:.1f} ms")
     state_after_warmup = ctx.get_state()
 
-    ctx.profile(True)
+    if args.graphs:
+        ctx.use_graphs(True)
+    else:
+        ctx.profile(True)
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
@@ -252,8 +260,17 @@ def main():
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile(False)
+    if args.graphs:
+        ctx.profile(True)                  # eager moves: events around every launch
+        for i in range(5):
+            ctx.move()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        prof_steps = 5
+    else:
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        prof_steps = args.steps
     ms_step = 1e3 * elapsed / args.steps
     log(f"timed {args.steps} moves: {ms_step:.2f} ms/move, last delta {info['delta']:.3e}")
     for e in prof:
@@ -270,8 +287,8 @@ def main():
                 "frac": round(achieved / PEAK[args.prec], 4), "traffic": measured_traffic(args),
                 "launch_ms": round(per_launch_ms, 4), "flops_per_launch": flops_launch,
                 "algorithmic_GBps": round(bytes_launch / (per_launch_ms * 1e-3) / 1e9, 1)}
-    total_flops = sum(e["flops"] for e in prof) / args.steps
-    breakdown = {e["name"]: round(e["ms"] / args.steps, 3) for e in prof}
+    total_flops = sum(e["flops"] for e in prof) / prof_steps
+    breakdown = {e["name"]: round(e["ms"] / prof_steps, 3) for e in prof}
 
     svd = None
     if args.svd_moves > 0:

@@ -158,6 +158,14 @@ ctm_status ctm_move_async(ctm_ctx* ctx);
  * when no move is in flight; CTM_E_NUMERIC as for ctm_move. */
 ctm_status ctm_move_poll(ctm_ctx* ctx, int* done, ctm_move_info* info);
 
+/* Enables (1) or disables (0) graph replay of SI moves.  With graphs on, the
+ * device work of an SI move is captured into a HIP graph the first time a
+ * given buffer arrangement occurs (two arrangements alternate) and replayed
+ * afterwards; growth and full-SVD moves, and moves while profiling, run
+ * eagerly.  Results are identical to eager moves.  Needs a non-default
+ * stream (CTM_E_STATE otherwise).  Off by default. */
+ctm_status ctm_use_graphs(ctm_ctx* ctx, int enable);
+
 /* Moves until delta < tol or max_moves moves were made.  Returns
  * CTM_E_NOT_CONVERGED when the budget ran out (the state stays valid). */
 ctm_status ctm_converge(ctm_ctx* ctx, double tol, int max_moves, int* moves_done,

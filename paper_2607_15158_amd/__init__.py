@@ -76,6 +76,7 @@ _sigs = {
     "ctm_set_isometries": (ctypes.c_int, [_vp, _vp, _vp]),
     "ctm_move": (ctypes.c_int, [_vp, ctypes.POINTER(ctm_move_info)]),
     "ctm_move_async": (ctypes.c_int, [_vp]),
+    "ctm_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ctm_move_poll": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctm_move_info)]),
     "ctm_server_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_int]),
     "ctm_server_destroy": (None, [_vp]),
@@ -208,6 +209,9 @@ class Ctm:
         info = ctm_move_info()
         _check(_lib.ctm_move(self._h, ctypes.byref(info)), self._h)
         return {"delta": info.delta, "mode": info.mode, "chi_env": info.chi_env, "gap": info.gap}
+
+    def use_graphs(self, enable: bool = True) -> None:
+        _check(_lib.ctm_use_graphs(self._h, int(enable)), self._h)
 
     def move_async(self) -> None:
         _check(_lib.ctm_move_async(self._h), self._h)

@@ -128,6 +128,17 @@ struct ctm_ctx {
   hipEvent_t done_ev = nullptr;
   bool pending = false;
   int pend_mode = 0, pend_keep = 0;
+  // captured SI moves: the device work of a move depends on the generation
+  // `cur` and on the arrangement of the block pointers (the QR and the
+  // recycling swap them), so a graph is kept per (cur, arrangement) with the
+  // arrangement the move leaves behind
+  bool use_graphs = false;
+  struct GraphRec {
+    int cur, spec_cur;
+    std::vector<void*> pre, post;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphRec> graphs;
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -887,25 +898,37 @@ int c4v_finish(ctm_ctx* c, int gen, int keep) {
   return 0;
 }
 
-// Enqueues one move on the context's stream; its scalar results (norms,
-// delta, gaps, the numeric-guard flag) are copied to pinned host memory and
-// done_ev is recorded behind them.  The environment buffers of the next
-// generation are written; the context switches to them in finish_move.
-int enqueue_move(ctm_ctx* c) {
-  if (c->pending) return fail(c, CTM_E_STATE, "a move is already in flight");
-  const int x = c->chi_env, N1 = x * c->Dl;
-  int mode, keep;
-  if (N1 <= c->chi) {
-    mode = 0;
-    keep = N1;
-  } else if (x != c->chi || c->cfg.proj == CTM_PROJ_FULLSVD) {
-    mode = 1;
-    keep = c->chi;
-  } else {
-    mode = 2;
-    keep = c->chi;
+std::vector<void*> block_ptrs(const ctm_ctx* c) {
+  std::vector<void*> v;
+  for (int b = 0; b < 4; ++b) {
+    v.push_back(c->X[b]);
+    v.push_back(c->Yt[b]);
   }
-  CTM_HIP_TRY(hipMemsetAsync(c->bad, 0, sizeof(int), c->st));
+  for (int s2 = 0; s2 < 2; ++s2)
+    for (int i = 0; i < 8; ++i) v.push_back(c->W[s2][i]);
+  return v;
+}
+
+void set_block_ptrs(ctm_ctx* c, const std::vector<void*>& v) {
+  size_t o = 0;
+  for (int b = 0; b < 4; ++b) {
+    c->X[b] = (double*)v[o++];
+    c->Yt[b] = (double*)v[o++];
+  }
+  for (int s2 = 0; s2 < 2; ++s2)
+    for (int i = 0; i < 8; ++i) c->W[s2][i] = (double*)v[o++];
+}
+
+void drop_graphs(ctm_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+// Device work of a move (everything between the guard reset and the
+// read-back of its scalars).
+int move_work(ctm_ctx* c, int mode, int keep) {
+  const int N1 = c->chi_env * c->Dl;
+  TRY(elem_zero_int(c->bad, c->st));
   TRY(build_corners(c));
   if (c->cfg.sym == CTM_SYM_C4V) {
     TRY(c4v_projectors(c, mode, keep));
@@ -924,6 +947,69 @@ int enqueue_move(ctm_ctx* c) {
   if (c->cfg.sym == CTM_SYM_C4V) TRY(c4v_finish(c, nxt, keep));
   TRY(normalize_env(c, nxt, keep));
   TRY(spectra(c, nxt, keep));
+  return 0;
+}
+
+// SI moves through a captured graph (one per (cur, pointer arrangement)).
+int move_work_graph(ctm_ctx* c, int mode, int keep) {
+  TRY(ensure_si_blocks(c));   // may copy the start blocks: outside the graph
+  const std::vector<void*> pre = block_ptrs(c);
+  for (auto& g : c->graphs) {
+    if (g.cur == c->cur && g.spec_cur == c->spec_cur && g.pre == pre) {
+      set_block_ptrs(c, g.post);
+      CTM_HIP_TRY(hipGraphLaunch(g.exec, c->st));
+      return 0;
+    }
+  }
+  CTM_HIP_TRY(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+  const int rc = move_work(c, mode, keep);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->st, &graph);
+  if (rc || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    set_block_ptrs(c, pre);
+    return rc ? rc : fail(c, CTM_E_DEVICE, "stream capture of the move failed");
+  }
+  ctm_ctx::GraphRec g;
+  g.cur = c->cur;
+  g.spec_cur = c->spec_cur;
+  g.pre = pre;
+  g.post = block_ptrs(c);
+  const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    set_block_ptrs(c, pre);
+    return fail(c, CTM_E_DEVICE, "graph instantiation failed");
+  }
+  c->graphs.push_back(g);
+  CTM_HIP_TRY(hipGraphLaunch(g.exec, c->st));
+  return 0;
+}
+
+// Enqueues one move on the context's stream; its scalar results (norms,
+// delta, gaps, the numeric-guard flag) are copied to pinned host memory and
+// done_ev is recorded behind them.  The environment buffers of the next
+// generation are written; the context switches to them in finish_move.
+int enqueue_move(ctm_ctx* c) {
+  if (c->pending) return fail(c, CTM_E_STATE, "a move is already in flight");
+  const int x = c->chi_env, N1 = x * c->Dl;
+  int mode, keep;
+  if (N1 <= c->chi) {
+    mode = 0;
+    keep = N1;
+  } else if (x != c->chi || c->cfg.proj == CTM_PROJ_FULLSVD) {
+    mode = 1;
+    keep = c->chi;
+  } else {
+    mode = 2;
+    keep = c->chi;
+  }
+  // growth and full-SVD moves call rocSOLVER and run eagerly; SI moves are
+  // captured when graphs are enabled on a non-default stream
+  if (mode == 2 && c->use_graphs && !c->prof && c->st != nullptr)
+    TRY(move_work_graph(c, mode, keep));
+  else
+    TRY(move_work(c, mode, keep));
   CTM_HIP_TRY(hipMemcpyAsync(c->hbuf, c->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->st));
   CTM_HIP_TRY(hipMemcpyAsync(c->hbuf + 16, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
   CTM_HIP_TRY(hipEventRecord(c->done_ev, c->st));
@@ -1332,6 +1418,7 @@ void ctm_destroy(ctm_ctx* c) {
   if (c->st) (void)hipStreamSynchronize(c->st);
   else (void)hipDeviceSynchronize();
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  drop_graphs(c);
   if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->rb) rocblas_destroy_handle(c->rb);
@@ -1362,6 +1449,19 @@ ctm_status ctm_move(ctm_ctx* c, ctm_move_info* info) {
   const int r = drain(c);
   if (r) return (ctm_status)r;
   return (ctm_status)do_move(c, info);
+}
+
+ctm_status ctm_use_graphs(ctm_ctx* c, int enable) {
+  if (!c) return (ctm_status)fail(nullptr, CTM_E_ARG, "null context");
+  const int rd = drain(c);
+  if (rd) return (ctm_status)rd;
+  if (enable && c->st == nullptr)
+    return (ctm_status)fail(c, CTM_E_STATE, "graphs need a non-default stream");
+  if (hipStreamSynchronize(c->st) != hipSuccess)
+    return (ctm_status)fail(c, CTM_E_DEVICE, "synchronisation failed");
+  if (!enable) drop_graphs(c);
+  c->use_graphs = enable != 0;
+  return CTM_OK;
 }
 
 ctm_status ctm_move_async(ctm_ctx* c) {

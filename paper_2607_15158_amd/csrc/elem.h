@@ -62,6 +62,7 @@ int elem_proj_prep_full(const double* U, const double* Vt, const double* sv, con
                         int N, int keep, double rtol, double* Us, double* Vs, double* gap,
                         hipStream_t s);
 int elem_identity(double* P, int n, int m, hipStream_t s);
+int elem_zero_int(int* x, hipStream_t s);
 int elem_symmetrize(double* A, int n, hipStream_t s);
 int elem_symmetrize_edge(double* T, int x, int Dl, hipStream_t s);
 int elem_c4v_order(const double* w, const double* V, int n, int keep, double* P, hipStream_t s);

@@ -387,6 +387,11 @@ __global__ void k_ratio(const double* a, const double* b, double* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = a[0] / b[0];
 }
 
+// x[0] = 0 (a kernel, so that it can be captured into a graph)
+__global__ void k_zero_int(int* x) {
+  if (threadIdx.x == 0) x[0] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // C4v helpers
 // ---------------------------------------------------------------------------
@@ -547,6 +552,12 @@ int elem_proj_prep_full(const double* U, const double* Vt, const double* sv, con
   const long total = (long)N * keep;
   const int blocks = (int)std::min<long>(2048, (total + 255) / 256);
   k_proj_prep_full<<<blocks, 256, 0, s>>>(U, Vt, sv, sg, N, keep, rtol, Us, Vs, gap);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_zero_int(int* x, hipStream_t s) {
+  k_zero_int<<<1, 64, 0, s>>>(x);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -11,8 +11,9 @@
 // workspace; each pump completes the moves that have finished, launches the
 // next move of every request that is still iterating, retires requests that
 // reached delta < tol (at the full environment dimension) or their move
-// budget, and admits new ones.  Moves of different requests therefore
-// overlap on the device, and a result does not depend on what else runs:
+// budget, and admits new ones.  SI moves replay a captured HIP graph per
+// request.  Moves of different requests therefore overlap on the device,
+// and a result does not depend on what else runs:
 // each request executes exactly the kernels, launch shapes and reduction
 // orders of a solo ctm_converge.
 
@@ -183,6 +184,11 @@ bool admit(ctm_server* s, int id, int slot) {
   if (ctm_init(&r.ctx, &r.cfg, site, bnd, base, st.ws, stream) != CTM_OK) {
     r.err = std::string("ctm_init: ") + ctm_last_error(nullptr);
     retire(s, id, 3);
+    return true;
+  }
+  // SI moves replay captured graphs (the slot stream is not the default one)
+  if (ctm_use_graphs(r.ctx, 1) != CTM_OK) {
+    fail_request(s, id, "ctm_use_graphs");
     return true;
   }
   if (X0 && ctm_set_isometries(r.ctx, X0, Y0) != CTM_OK) {

@@ -53,6 +53,29 @@ def test_async_moves_equal_sync_moves():
     assert np.array_equal(a.get_state(), b.get_state())
 
 
+def test_graph_replay_matches_eager_moves():
+    """SI moves replayed from captured graphs equal eager moves bit for bit,
+    on every replay, with unrelated eager work and synchronisations between
+    the replays."""
+    cfg, A, X, Y = request(2, 6, 7)
+    dev = torch.device("cuda", 0)
+    eager = P.Ctm(cfg, torch.from_numpy(A).to(dev))
+    side = torch.cuda.Stream()
+    graphed = P.Ctm(cfg, torch.from_numpy(A).to(dev), stream=side)
+    for c in (eager, graphed):
+        c.set_isometries(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
+    graphed.use_graphs(True)
+    noise = torch.randn(512, 512, device=dev)
+    for n in range(10):
+        ie = eager.move()
+        ig = graphed.move()
+        assert ie == ig, n
+        assert np.array_equal(eager.get_state(), graphed.get_state()), n
+        noise = noise @ noise.T / 512.0            # eager work between replays
+        torch.cuda.synchronize()
+    assert ig["mode"] == 2
+
+
 def test_mix_equals_solo_runs():
     tol, max_moves = 1e-10, 40
     specs = [(2, 4, 1), (3, 9, 2), (2, 8, 3), (3, 12, 4), (2, 6, 5), (3, 18, 6)]
