@@ -29,6 +29,8 @@
 
 #include "common.h"
 
+#include <hip/hip_cooperative_groups.h>
+
 namespace sictm {
 namespace {
 
@@ -149,17 +151,24 @@ __device__ __forceinline__ double fast_rcp(double x) {
 // right vectors are updated once at the end, V_cols <- V_cols W.  RPL is the
 // number of rows per lane (n <= 16 RPL).
 template <int RPL>
-__global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int round, int inner) {
-  constexpr int kC = 2 * kBlk;
-  constexpr int LD = 16 * RPL + 1;   // odd row length: no bank conflicts
-  __shared__ double Ul[kC][LD];
-  __shared__ double Vl[kC][LD];
-  __shared__ double Wl[kC][kC + 1];
-  __shared__ int rot;
-  const int mat = blockIdx.y;
-  if (sweep > 0 && a.flags[mat * kMaxSweeps + sweep - 1] == 0) return;   // converged
+struct RoundLds {
+  static constexpr int kC = 2 * kBlk;
+  static constexpr int LD = 16 * RPL + 1;   // odd row length: no bank conflicts
+  double Ul[kC][LD];
+  double Vl[kC][LD];
+  double Wl[kC][kC + 1];
+  int rot;
+};
+
+template <int RPL>
+__device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int round, int inner,
+                                            int mat, int bp, RoundLds<RPL>& sh) {
+  constexpr int kC = RoundLds<RPL>::kC;
+  auto& Ul = sh.Ul;
+  auto& Vl = sh.Vl;
+  auto& Wl = sh.Wl;
+  int& rot = sh.rot;
   const int n = a.n, nblk = a.nblk;
-  const int bp = blockIdx.x;
   const int b0 = tour(bp, round, nblk), b1 = tour(nblk - 1 - bp, round, nblk);
   const int tid = threadIdx.x;
   double* Uc = a.work + (size_t)mat * 2 * n * n;
@@ -272,6 +281,37 @@ __global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int
   }
   __syncthreads();
   if (tid == 0 && rot) atomicOr(&a.flags[mat * kMaxSweeps + sweep], 1);
+}
+
+// One round per launch; later launches return at once after a sweep
+// without rotations.
+template <int RPL>
+__global__ __launch_bounds__(256) void svd_block_round(SvdArgs a, int sweep, int round, int inner) {
+  __shared__ RoundLds<RPL> sh;
+  const int mat = blockIdx.y;
+  if (sweep > 0 && a.flags[mat * kMaxSweeps + sweep - 1] == 0) return;   // converged
+  block_round<RPL>(a, sweep, round, inner, mat, blockIdx.x, sh);
+}
+
+// All sweeps in one cooperative launch: a grid-wide barrier separates the
+// rounds, matrices whose last sweep rotated nothing stop working, and the
+// launch ends when every matrix has converged (a decision every workgroup
+// takes from the same flags after the barrier).
+template <int RPL>
+__global__ __launch_bounds__(256) void svd_sweeps(SvdArgs a, int inner, int count) {
+  __shared__ RoundLds<RPL> sh;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int mat = blockIdx.y;
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    const bool active = sweep == 0 || a.flags[mat * kMaxSweeps + sweep - 1] != 0;
+    for (int round = 0; round < a.nblk - 1; ++round) {
+      if (active) block_round<RPL>(a, sweep, round, inner, mat, blockIdx.x, sh);
+      grid.sync();
+    }
+    bool any = false;
+    for (int m = 0; m < count; ++m) any |= a.flags[m * kMaxSweeps + sweep] != 0;
+    if (!any) break;
+  }
 }
 
 // Singular values, normalisation, completion of zero columns, ordering.
@@ -440,18 +480,34 @@ int launch_svd(int count, const double* const* A, double* const* U, double* cons
   if (r) return r;
   svd_init<<<dim3(std::max(1, std::min(64, n * n / 256)), count), 256, 0, s>>>(a);
   const int rpl = (n + kLanesPerPair - 1) / kLanesPerPair;
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep)
-    for (int round = 0; round < nblk - 1; ++round) {
-      const dim3 grid(nblk / 2, count);
-      if (rpl <= 4)
-        svd_block_round<4><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
-      else if (rpl <= 8)
-        svd_block_round<8><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
-      else if (rpl <= 10)
-        svd_block_round<10><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
-      else
-        svd_block_round<12><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
-    }
+  {
+    const dim3 grid(nblk / 2, count);
+    int inner = kInner, cnt = count;
+    void* args[] = {&a, &inner, &cnt};
+    const void* fn = rpl <= 4    ? (const void*)svd_sweeps<4>
+                     : rpl <= 8  ? (const void*)svd_sweeps<8>
+                     : rpl <= 10 ? (const void*)svd_sweeps<10>
+                                 : (const void*)svd_sweeps<12>;
+    // inside a stream capture (graph) the per-round launches are used
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cs);
+    if (cs == hipStreamCaptureStatusNone &&
+        hipLaunchCooperativeKernel(fn, grid, dim3(256), args, 0, s) == hipSuccess)
+      goto sweeps_done;
+    (void)hipGetLastError();
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep)
+      for (int round = 0; round < nblk - 1; ++round) {
+        if (rpl <= 4)
+          svd_block_round<4><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
+        else if (rpl <= 8)
+          svd_block_round<8><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
+        else if (rpl <= 10)
+          svd_block_round<10><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
+        else
+          svd_block_round<12><<<grid, 256, 0, s>>>(a, sweep, round, kInner);
+      }
+  }
+sweeps_done:
   svd_finalize<<<count, 1024, 0, s>>>(a);
   CTM_HIP_TRY(hipGetLastError());
   if (want_u) {   // u = Q V'
