@@ -733,13 +733,10 @@ int renormalize(ctm_ctx* c, int keep) {
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, c->cp, DT::F64));
   }
-  // T'[b', d, g'] = sum_(b,l) P_r^T[(b, l), b'] Z2[(b, l), d, g']   (batched over d)
+  // T'[b', (d, g')] = sum_(b,l) P_r^T[(b, l), b'] Z2[(b, l), (d, g')]: one
+  // GEMM per edge, (d, g') contiguous in both Z2 and T'
   {
-    GemmBatch g = gemm_rowmajor(4, xp, xp, x * Dl, xp, (long)Dl * xp, (long)Dl * xp);
-    g.nbatch = Dl;
-    g.a_bs = 0;
-    g.b_bs = xp;
-    g.c_bs = xp;
+    GemmBatch g = gemm_rowmajor(4, xp, Dl * xp, x * Dl, xp, (long)Dl * xp, (long)Dl * xp);
     for (int j = 0; j < 4; ++j) {
       g.A[j] = c->Prt[j];
       g.transA[j] = 1;

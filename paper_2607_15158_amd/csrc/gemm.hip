@@ -221,9 +221,9 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
   using AL = SkinnyA<BM, BK>;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int MI = WTM / 16, NI = WTN / 16;
+  constexpr int NT = 64 * WGM * WGN;                   // threads per workgroup
   constexpr int NA = BM * BK / 2, NB = BN * BK / 2;    // 16-byte loads per slice
-  constexpr int VA = (NA + 255) / 256, VB = (NB + 255) / 256;
-  static_assert(WGM * WGN == 4, "four wavefronts");
+  constexpr int VA = (NA + NT - 1) / NT, VB = (NB + NT - 1) / NT;
   static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile multiple of 16");
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -244,7 +244,7 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < VA; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       v2d v = {0.0, 0.0};
       if (i < NA) {
         if (TRANS) {
@@ -267,7 +267,7 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
     }
 #pragma unroll
     for (int e = 0; e < VB; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       const int gk = k0 + i / (BN / 2), gn = n0 + 2 * (i % (BN / 2));
       v2d v = {0.0, 0.0};
       if (i < NB && gk < K) {
@@ -281,7 +281,7 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
   auto store = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < VA; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       if (i < NA) {
         if (TRANS) {
           const int kk = i / (BM / 2), m = 2 * (i % (BM / 2));
@@ -295,7 +295,7 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
     }
 #pragma unroll
     for (int e = 0; e < VB; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       if (i < NB) *(v2d*)&Bs[buf][i / (BN / 2)][2 * (i % (BN / 2))] = rb[e];
     }
   };
@@ -363,7 +363,8 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
 }
 
 template <int BM, int BN, int WGM, int WGN, int ROLE>
-__global__ __launch_bounds__(256, 2) void gemm_skinny_f64(GemmBatch g, int tiles_m, int tiles_n) {
+__global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_skinny_f64(
+    GemmBatch g, int tiles_m, int tiles_n) {
   __shared__ double As[2][SkinnyA<BM, 16>::SIZE];
   __shared__ double Bs[2][16][BN + 16];
   const int per_prob = tiles_m * tiles_n;
@@ -575,7 +576,7 @@ bool skinny_ok(const GemmBatch& g) {
 template <int BM, int BN, int WGM, int WGN, int ROLE>
 int launch_skinny(const GemmBatch& g, hipStream_t s) {
   const int tm = ceil_div(g.M, BM), tn = ceil_div(g.N, BN);
-  dim3 grid(tm * tn * g.count * g.nbatch), block(256);
+  dim3 grid(tm * tn * g.count * g.nbatch), block(64 * WGM * WGN);
   gemm_skinny_f64<BM, BN, WGM, WGN, ROLE><<<grid, block, 0, s>>>(g, tm, tn);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
@@ -598,6 +599,8 @@ bool launch_f64_db(const GemmBatch& g, hipStream_t s, int* rc) {
   if (g.K < 512 || g.M < 256 || !skinny_ok(g)) return false;
   if (g.N <= 160)
     *rc = launch_skinny<96, 160, 2, 2, 0>(g, s);
+  else if ((long)g.M * g.count * g.nbatch >= 16384)
+    *rc = launch_skinny<256, 144, 8, 1, 0>(g, s);
   else
     *rc = launch_skinny<128, 144, 4, 1, 0>(g, s);
   return true;

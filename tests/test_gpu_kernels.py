@@ -1,7 +1,8 @@
 """GPU parity of the building-block kernels through the C ABI.
 
 GEMM against float64 NumPy products (N <= 160 runs the skinny kernel of the
-enlarged-corner applications, wider N the general tiles); Householder QR against the oracle's
+enlarged-corner applications, wide N with long K the 256 x 144 double-
+buffered tiles, short K the general tiles); Householder QR against the oracle's
 QR convention (R_ii >= 0) and orthogonality; Jacobi SVD against NumPy's
 singular values and the reconstruction.  Shapes span several tiles and
 ragged tails.
@@ -26,7 +27,8 @@ def dev(x):
                                          (257, 160, 300, 0), (300, 161, 257, 1),
                                          (1000, 144, 520, 0), (64, 1296, 1296, 0),
                                          (5184, 160, 5184, 0), (5184, 160, 5184, 1),
-                                         (97, 159, 33, 1)])
+                                         (97, 159, 33, 1), (5600, 300, 600, 0),
+                                         (5600, 300, 600, 1)])
 def test_gemm_f64_matches_numpy(M, N, K, trans):
     rng = np.random.default_rng(M * 7 + N)
     A = [rng.standard_normal((K, M) if trans else (M, K)) for _ in range(3)]
