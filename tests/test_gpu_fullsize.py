@@ -1,0 +1,72 @@
+"""Parity at the benchmark's full size (D=6, chi=144, p=16, N=5184, n_si=2).
+
+The oracle cannot run whole moves at this size in test time (its edge
+renormalisation takes minutes), so the GPU move is checked on the outputs the
+oracle computes in seconds: the four renormalised corners (the oracle's
+enlarged corners and SI projectors of all four bonds, then its corner formula
+C_i' = P_r^(i-1) Ct_i P_l^(i)), the kept columns of the recycled blocks and
+the corner spectra.  The start is a seeded random environment of full
+dimension (every move is then an SI move) with the benchmark's site tensor
+and start blocks; the GPU runs the same kernels and launch shapes as
+bench.py.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import paper_2607_15158_amd as P  # noqa: E402
+import synth as S  # noqa: E402
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_full_size_si_move_matches_oracle():
+    D, chi, p, n_si = 6, 144, 16, 2
+    Dl = D * D
+    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=n_si)
+    N, k = cfg.N, cfg.k
+    A = S.product_plus_noise_site(2, D, 3)
+    X = np.stack([S.gaussian_block(N, k, 40 + b) for b in range(4)])
+    Y = np.stack([S.gaussian_block(N, k, 50 + b) for b in range(4)])
+    C = [S.gaussian_block(chi, chi, 60 + i) for i in range(4)]
+    T = [S.gaussian_block(chi * Dl, chi, 70 + i).reshape(chi, Dl, chi) for i in range(4)]
+
+    dev = torch.device("cuda", 0)
+    ctx = P.Ctm(cfg, torch.from_numpy(A).to(dev))
+    ctx.set_state(ctx.pack_state(C, T, X, Y))
+    info = ctx.move()
+    assert info["mode"] == 2
+    st = ctx.unpack_state(ctx.get_state())
+    del ctx
+    torch.cuda.empty_cache()
+
+    a = O.double_layer(A)
+    env = O.Env([c.copy() for c in C], [t.copy() for t in T])
+    Ct = O.enlarged_corners(env, a)
+    Pl, Prt, Xn, Ytn = [], [], [], []
+    for b in range(4):
+        pl, prt, _, xn, ytn = O.si_projectors(Ct, b, X[b], Y[b], chi, n_si, 1e-12, True)
+        Pl.append(pl)
+        Prt.append(prt)
+        Xn.append(xn)
+        Ytn.append(ytn)
+    for i in range(4):
+        Ci = Prt[(i - 1) % 4].T @ Ct[i] @ Pl[i]
+        Ci = Ci / np.linalg.norm(Ci)
+        err = rel(st["C"][i], Ci)
+        print(f"corner {i + 1}: max rel err {err:.2e}")
+        assert err <= 1e-10
+        sg = np.linalg.svd(st["C"][i], compute_uv=False)
+        so = np.linalg.svd(Ci, compute_uv=False)
+        assert np.abs(sg - so).max() <= 1e-12
+    for b in range(4):
+        ex = rel(st["X"][b][:, :chi], Xn[b][:, :chi])
+        ey = rel(st["Yt"][b][:, :chi], Ytn[b][:, :chi])
+        print(f"bond {b}: recycled X err {ex:.2e}, Y^T err {ey:.2e}")
+        assert ex <= 1e-9 and ey <= 1e-9
