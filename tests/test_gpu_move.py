@@ -355,3 +355,32 @@ def test_c4v_moves_match_oracle_step_by_step(proj):
         for i in range(4):
             assert rel(st["C"][i], C) <= 1e-10 and rel(st["T"][i], T) <= 1e-10
     assert [m[0] for m in modes] == [0, 0] + [2 if proj == "si" else 1] * 6
+
+
+def test_config2_si_fixed_point_is_the_full_svd_fixed_point():
+    """D=4, chi=64 (N=1024), p=8, n_si=2: SI converges (delta < 1e-11), and
+    full-SVD moves (QR-iteration driver) started from the SI environment keep
+    its norm per site and nearest-neighbour Heisenberg energy: the subspace
+    iteration's fixed point is the truncated-SVD fixed point.  (The
+    divide-and-conquer driver cannot be used for this check: it resolves
+    singular directions only down to ~1e-7 s_1, and its environment drifts
+    at that level.)"""
+    A = S.product_plus_noise_site(2, 4, 2)
+    h = S.heisenberg_bond()
+    cfg = P.Config(d=2, D=4, chi=64, p=8, n_si=2)
+    si, _ = make(cfg, A)
+    res = si.converge(1e-11, 60)
+    assert res["converged"], res
+    e_si = si.observable(P.OBS_BOND_H, h)[0] + si.observable(P.OBS_BOND_V, h)[0]
+    k_si = si.kappa()
+    svd, _ = make(P.Config(d=2, D=4, chi=64, p=8, proj="svd"), A, iso=False)
+    svd.set_state(si.get_state())
+    for _ in range(2):
+        info = svd.move()
+        assert info["mode"] == 1
+    e_svd = svd.observable(P.OBS_BOND_H, h)[0] + svd.observable(P.OBS_BOND_V, h)[0]
+    print(f"SI: {res['moves']} moves, kappa {k_si:.14f} e {e_si:.14f}; "
+          f"after full-SVD moves: delta {info['delta']:.2e} kappa {svd.kappa():.14f} e {e_svd:.14f}")
+    assert info["delta"] <= 1e-8
+    assert abs(svd.kappa() / k_si - 1) <= 1e-10
+    assert abs(e_svd - e_si) <= 1e-9
