@@ -70,6 +70,7 @@ __all__ = [
     "corner_spectra",
     "spectrum_delta",
     "ctm_move",
+    "mean_sin2",
     "run_ctmrg",
     "norm_values",
     "kappa",
@@ -405,19 +406,49 @@ def ctm_move(env: Env, a: np.ndarray, chi: int, proj: str = "si",
     return renormalize(Ct, env, a, Pl, Prt), info
 
 
+def mean_sin2(Q_old: np.ndarray, Q_new: np.ndarray, chi: int) -> float:
+    """Mean squared sine of the principal angles between the spans of the
+    first ``chi`` columns of two blocks (the recycling criterion of the
+    triangular Heisenberg benchmark passage).  The angles come from the
+    singular values of the product of orthonormal bases of the two spans."""
+    A = np.linalg.qr(Q_old[:, :chi])[0]
+    B = np.linalg.qr(Q_new[:, :chi])[0]
+    cos = np.clip(np.linalg.svd(A.T @ B, compute_uv=False), 0.0, 1.0)
+    return float(np.mean(1.0 - cos ** 2))
+
+
+RECYCLE_GUARD = 10.0
+
+
 def run_ctmrg(a: np.ndarray, e: np.ndarray, chi: int, proj: str = "si", k: Optional[int] = None,
               iso0: Optional[SIState] = None, n_si: int = 2, eps: float = 1e-12,
               tol: float = 0.0, max_moves: int = 100, stabilized: bool = True,
-              env0: Optional[Env] = None):
+              env0: Optional[Env] = None, recycle_sin2: float = 0.0, min_si_moves: int = 3):
     """Moves from ``initial_env(a, e)`` (or ``env0``) until ``delta < tol``.
 
     In SI mode ``iso0`` supplies the Gaussian start blocks; they are used at
-    the first move with ``chi_env == chi``.  Returns ``(env, history)``.
+    the first move with ``chi_env == chi``.
+
+    Recycling (QR-based projector section, step 4, and the triangular
+    Heisenberg benchmark passage): with ``recycle_sin2 > 0`` the subspace
+    updates stop once, after at least ``min_si_moves`` SI moves with updates,
+    the largest over the eight blocks (X and Y of four bonds) of the mean
+    sin^2 of the principal angles between the kept subspaces of two
+    successive moves is below ``recycle_sin2``; later moves build rho and the
+    projectors from the recycled blocks alone (``n_si = 0``).  The angles are
+    measured only when the previous move was an SI move (the Gaussian start
+    blocks are no subspace estimate).  Updates resume, and the count starts
+    again, when delta grows by more than ``RECYCLE_GUARD`` from one move to
+    the next (a stale subspace shows up in the corner spectra).
+
+    Returns ``(env, history)``; each history entry holds the move number, the
+    mode, delta, the subspace steps used and the measured sin^2 (or None).
     """
     env = initial_env(a, e) if env0 is None else env0.copy()
     si = None
     hist = []
     spec = corner_spectra(env, chi)
+    recycling, updates, prev_delta = False, 0, None
     for n in range(max_moves):
         use_si = None
         if proj == "si" and env.chi == chi:
@@ -425,14 +456,32 @@ def run_ctmrg(a: np.ndarray, e: np.ndarray, chi: int, proj: str = "si", k: Optio
                 if iso0 is None:
                     raise ValueError("SI needs iso0")
                 si = iso0
+                first_si = True
+            else:
+                first_si = False
             use_si = si
-        env, info = ctm_move(env, a, chi, proj, use_si, n_si, eps, stabilized)
+        steps = 0 if recycling else n_si
+        env, info = ctm_move(env, a, chi, proj, use_si, steps, eps, stabilized)
+        sin2 = None
         if info["mode"] == "si":
-            si = info["si"]
+            new = info["si"]
+            if recycle_sin2 > 0 and steps > 0:
+                updates += 1
+                if not first_si:
+                    sin2 = max(max(mean_sin2(si.X[b], new.X[b], chi),
+                                   mean_sin2(si.Yt[b], new.Yt[b], chi)) for b in range(4))
+                    if updates >= min_si_moves and sin2 < recycle_sin2:
+                        recycling = True
+            si = new
         new_spec = corner_spectra(env, chi)
         delta = spectrum_delta(new_spec, spec)
         spec = new_spec
-        hist.append({"move": n + 1, "mode": info["mode"], "delta": delta})
+        if (info["mode"] == "si" and steps == 0 and prev_delta is not None
+                and delta > RECYCLE_GUARD * prev_delta):
+            recycling, updates = False, 0
+        prev_delta = delta if info["mode"] == "si" else None
+        hist.append({"move": n + 1, "mode": info["mode"], "delta": delta,
+                     "n_si": steps if info["mode"] == "si" else None, "sin2": sin2})
         if delta < tol:
             break
     return env, hist

@@ -211,6 +211,54 @@ def test_subspace_iteration_converges_to_leading_subspace():
     assert prev < 1e-7
 
 
+def test_mean_sin2_against_scipy_principal_angles():
+    """The recycling criterion is the mean squared sine of the principal
+    angles; scipy computes the angles by its own route."""
+    from scipy.linalg import subspace_angles
+    rng = np.random.default_rng(5)
+    for n, k, chi in [(40, 12, 9), (64, 20, 20), (30, 7, 3)]:
+        Qa = np.linalg.qr(rng.standard_normal((n, k)))[0]
+        Qb = np.linalg.qr(Qa + 0.3 * rng.standard_normal((n, k)))[0]
+        ref = np.mean(np.sin(subspace_angles(Qa[:, :chi], Qb[:, :chi])) ** 2)
+        assert abs(O.mean_sin2(Qa, Qb, chi) - ref) <= 1e-13
+        # a rotated basis of the same span, and an orthogonal span
+        G = np.linalg.qr(rng.standard_normal((chi, chi)))[0]
+        assert O.mean_sin2(Qa, Qa[:, :chi] @ G, chi) <= 1e-14
+        Qfull = np.linalg.qr(rng.standard_normal((n, 2 * chi)))[0]
+        assert abs(O.mean_sin2(Qfull[:, :chi], Qfull[:, chi:], chi) - 1.0) <= 1e-14
+
+
+def test_recycled_blocks_keep_their_span_without_updates():
+    """With no subspace step the recycled blocks are X v and Y^T u for
+    orthogonal v, u: the spans of all k columns are unchanged."""
+    Ct, N = small_corners(seed=6, chi=4, D2=4)
+    k = 10
+    X = np.linalg.qr(S.gaussian_block(N, k, 3))[0]
+    Yt = np.linalg.qr(S.gaussian_block(N, k, 4))[0]
+    for b in range(4):
+        _, _, _, Xn, Ytn = O.si_projectors(Ct, b, X, Yt, 6, 0, 1e-14)
+        assert O.mean_sin2(X, Xn, k) <= 1e-13 and O.mean_sin2(Yt, Ytn, k) <= 1e-13
+        assert np.allclose(Xn.T @ Xn, np.eye(k), atol=1e-13)
+
+
+def test_recycle_mode_reaches_the_ising_closed_forms():
+    """Recycling after the subspaces align still converges to Onsager's free
+    energy and Yang's magnetisation; the moves after the switch use no
+    subspace step."""
+    beta, chi = 0.5, 16
+    a, asig, e = S.ising_site(beta), S.ising_impurity(beta), S.ising_boundary(beta)
+    env, hist = O.run_ctmrg(a, e, chi, proj="si", iso0=iso_for(2 * chi, chi + 8),
+                            tol=1e-12, max_moves=150, recycle_sin2=1e-3, min_si_moves=3)
+    steps = [h["n_si"] for h in hist if h["mode"] == "si"]
+    assert steps[:3] == [2, 2, 2] and steps[-1] == 0
+    first = steps.index(0)
+    assert all(st == 0 for st in steps[first:])
+    assert hist[3 + first - 1]["sin2"] < 1e-3
+    lnk = np.log(O.kappa(env, a))
+    assert abs(lnk - gold(beta, "minus_beta_f")) <= 1e-10 * lnk
+    assert abs(O.onesite_value(env, a, asig) - gold(beta, "magnetisation")) <= 1e-9
+
+
 def test_stabilized_and_plain_si_agree():
     Ct, N = small_corners(seed=8)
     X0, Y0 = S.gaussian_block(N, 7, 1), S.gaussian_block(N, 7, 2)
