@@ -176,6 +176,11 @@ def main():
     ap.add_argument("--chi", type=int, default=144)
     ap.add_argument("--p", type=int, default=16)
     ap.add_argument("--n-si", type=int, default=2)
+    ap.add_argument("--recycle-sin2", type=float, default=0.0,
+                    help="> 0: stop the subspace steps once the kept subspaces of successive "
+                         "moves align to this mean sin^2 (the paper's recycling); 0: n_si "
+                         "steps every move")
+    ap.add_argument("--min-si-moves", type=int, default=3)
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--pinv-rtol", type=float, default=1e-12)
     ap.add_argument("--svd-moves", type=int, default=2, help="full-SVD comparator moves (0: skip)")
@@ -221,7 +226,8 @@ def main():
     A, X, Y = workload(args.D, args.chi, args.p)
     cfg = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="si",
                    prec=args.prec, stabilized=1, pinv_rtol=args.pinv_rtol,
-                   svd_driver=args.svd_driver)
+                   svd_driver=args.svd_driver, recycle_sin2=args.recycle_sin2,
+                   min_si_moves=args.min_si_moves)
     log(f"config d=2 D={args.D} chi={args.chi} k={cfg.k} N={cfg.N} prec={args.prec}; "
         f"workspace {P.workspace_bytes(cfg) / 2**30:.2f} GiB")
     stream = torch.cuda.Stream() if args.graphs else None
@@ -243,8 +249,8 @@ def main():
     for i in range(args.warmup):
         t = time.perf_counter()
         info = ctx.move()
-        log(f"warmup {i}: mode={info['mode']} delta={info['delta']:.3e} "
-            f"{(time.perf_counter() - t) * 1e3:.1f} ms")
+        log(f"warmup {i}: mode={info['mode']} n_si={info['n_si']} delta={info['delta']:.3e} "
+            f"sin2={info['sin2']:.2e} {(time.perf_counter() - t) * 1e3:.1f} ms")
     state_after_warmup = ctx.get_state()
 
     if args.graphs:
@@ -252,12 +258,13 @@ def main():
     else:
         ctx.profile(True)
     torch.cuda.synchronize()
-    lat = []
+    lat, steps_used = [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
         info = ctx.move()                  # synchronises (reads delta)
         lat.append(time.perf_counter() - ts)
+        steps_used.append(info["n_si"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     if args.graphs:
@@ -325,7 +332,9 @@ def main():
         "config": {"workload": f"SI-CTMRG move, single-site iPEPS d=2 D={args.D} chi={args.chi} "
                                f"p={args.p} n_si={args.n_si}, enlarged corner {cfg.N}x{cfg.N}",
                    "D": args.D, "chi": args.chi, "k": cfg.k, "n_si": args.n_si,
-                   "contraction_precision": args.prec, "parallelism": "1 GPU"},
+                   "contraction_precision": args.prec, "parallelism": "1 GPU",
+                   "recycle_sin2": args.recycle_sin2},
+        "timed_moves_without_subspace_steps": int(sum(1 for n in steps_used if n == 0)),
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
         "tflops_per_move": round(total_flops / 1e12, 4),

@@ -92,6 +92,18 @@ typedef struct {
                        gesdd via the eigenvectors of M^T M; an order of magnitude
                        faster, weak directions below ~1e-8 s_1 less accurate)     */
   int sym;          /* ctm_sym                                                           */
+  double recycle_sin2; /* recycling of the SI blocks (QR-based projector section, step 4;
+                       recycling criterion of the triangular Heisenberg benchmark):
+                       > 0: after at least min_si_moves SI moves with subspace steps,
+                       once the largest over the 8 blocks (X, Y of 4 bonds) of the
+                       mean sin^2 of the principal angles between the kept chi
+                       columns of two successive moves is below this value, later
+                       moves take no subspace step (n_si = 0: rho and projectors
+                       from the recycled blocks); the steps resume, and the count
+                       restarts, when delta grows more than tenfold from one SI
+                       move to the next.  The angles are measured only when the
+                       previous move was an SI move.  <= 0: n_si steps every move */
+  int min_si_moves;    /* SI moves with subspace steps before recycling may start (>= 1) */
 } ctm_config;
 
 typedef struct {
@@ -99,6 +111,8 @@ typedef struct {
   int mode;       /* 0: growth without truncation, 1: full-SVD projectors, 2: SI       */
   int chi_env;    /* environment dimension after the move                              */
   double gap;     /* min over bonds of s_chi / s_(chi+1) - 1 (-1 when not truncated)   */
+  int n_si;       /* subspace steps this move took (0 when recycling or not an SI move) */
+  double sin2;    /* recycling criterion measured this move, or -1 when not measured    */
 } ctm_move_info;
 
 /* Human-readable name of a status code (static string). */
@@ -177,8 +191,9 @@ ctm_status ctm_converge(ctm_ctx* ctx, double tol, int max_moves, int* moves_done
 ctm_status ctm_observable(ctm_ctx* ctx, int kind, const double* op_host, double* out_host);
 
 /* Number of doubles of the state vector: C1..C4, T1..T4, then X_0..X_3 and
- * Yt_0..Yt_3 (each N x k), then one double holding chi_env and one holding
- * the number of SI moves made. */
+ * Yt_0..Yt_3 (each N x k), then four doubles: chi_env, the number of SI
+ * moves made, 1 if the SI blocks are being recycled without subspace steps
+ * (else 0), and the SI moves with steps counted towards min_si_moves. */
 ctm_status ctm_state_size(const ctm_ctx* ctx, size_t* n);
 
 /* Copies the state vector to / from host memory (n doubles, see

@@ -44,12 +44,13 @@ class ctm_config(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("D", ctypes.c_int), ("chi", ctypes.c_int),
                 ("p", ctypes.c_int), ("n_si", ctypes.c_int), ("proj", ctypes.c_int),
                 ("prec", ctypes.c_int), ("stabilized", ctypes.c_int),
-                ("pinv_rtol", ctypes.c_double), ("svd_driver", ctypes.c_int), ("sym", ctypes.c_int)]
+                ("pinv_rtol", ctypes.c_double), ("svd_driver", ctypes.c_int), ("sym", ctypes.c_int),
+                ("recycle_sin2", ctypes.c_double), ("min_si_moves", ctypes.c_int)]
 
 
 class ctm_move_info(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("mode", ctypes.c_int), ("chi_env", ctypes.c_int),
-                ("gap", ctypes.c_double)]
+                ("gap", ctypes.c_double), ("n_si", ctypes.c_int), ("sin2", ctypes.c_double)]
 
 
 class ctm_result(ctypes.Structure):
@@ -144,11 +145,14 @@ class Config:
     pinv_rtol: float = 1e-12
     svd_driver: str = "gesvd"
     sym: str = "none"
+    recycle_sin2: float = 0.0
+    min_si_moves: int = 3
 
     def c(self) -> ctm_config:
         return ctm_config(self.d, self.D, self.chi, self.p, self.n_si, PROJ[self.proj],
                           PREC[self.prec], self.stabilized, self.pinv_rtol,
-                          SVD_DRIVER[self.svd_driver], SYM[self.sym])
+                          SVD_DRIVER[self.svd_driver], SYM[self.sym], self.recycle_sin2,
+                          self.min_si_moves)
 
     @property
     def Dl(self) -> int:
@@ -208,7 +212,8 @@ class Ctm:
     def move(self) -> dict:
         info = ctm_move_info()
         _check(_lib.ctm_move(self._h, ctypes.byref(info)), self._h)
-        return {"delta": info.delta, "mode": info.mode, "chi_env": info.chi_env, "gap": info.gap}
+        return {"delta": info.delta, "mode": info.mode, "chi_env": info.chi_env, "gap": info.gap,
+                "n_si": info.n_si, "sin2": info.sin2}
 
     def use_graphs(self, enable: bool = True) -> None:
         _check(_lib.ctm_use_graphs(self._h, int(enable)), self._h)
@@ -223,7 +228,8 @@ class Ctm:
         _check(_lib.ctm_move_poll(self._h, ctypes.byref(done), ctypes.byref(info)), self._h)
         if not done.value:
             return None
-        return {"delta": info.delta, "mode": info.mode, "chi_env": info.chi_env, "gap": info.gap}
+        return {"delta": info.delta, "mode": info.mode, "chi_env": info.chi_env, "gap": info.gap,
+                "n_si": info.n_si, "sin2": info.sin2}
 
     def converge(self, tol: float, max_moves: int, raise_on_budget: bool = False):
         n = ctypes.c_int(0)
@@ -274,9 +280,11 @@ class Ctm:
         x = int(state[o])
         C = [c[: x * x].reshape(x, x) for c in C]
         T = [t[: x * Dl * x].reshape(x, Dl, x) for t in T]
-        return {"C": C, "T": T, "X": X, "Yt": Yt, "chi_env": x, "si_moves": int(state[o + 1])}
+        return {"C": C, "T": T, "X": X, "Yt": Yt, "chi_env": x, "si_moves": int(state[o + 1]),
+                "recycling": bool(state[o + 2]), "si_updates": int(state[o + 3])}
 
-    def pack_state(self, C, T, X, Yt, si_moves: int = 0) -> np.ndarray:
+    def pack_state(self, C, T, X, Yt, si_moves: int = 0, recycling: bool = False,
+                   si_updates: int = 0) -> np.ndarray:
         chi, Dl, N, k = self.cfg.chi, self.cfg.Dl, self.cfg.N, self.cfg.k
         x = C[0].shape[0]
         out = np.zeros(self.state_size())
@@ -293,6 +301,8 @@ class Ctm:
         o += 4 * N * k
         out[o] = x
         out[o + 1] = si_moves
+        out[o + 2] = 1.0 if recycling else 0.0
+        out[o + 3] = si_updates
         return out
 
     # profiling ---------------------------------------------------------------

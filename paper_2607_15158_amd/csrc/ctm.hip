@@ -71,6 +71,10 @@ struct Carver {
   void* take_bytes(size_t bytes) { return take<char>(bytes); }
 };
 
+// Recycling stops when delta grows by more than this factor between two
+// successive SI moves (a stale subspace shows up in the corner spectra).
+constexpr double kRecycleGuard = 10.0;
+
 enum ProfClass { PC_CORNER = 0, PC_SI_APPLY, PC_QR, PC_SVD, PC_PROJ, PC_RENORM, PC_FULLSVD, PC_MISC, PC_N };
 const char* kProfNames[PC_N] = {"corner_build", "si_apply", "householder_qr", "jacobi_svd",
                                 "projector_gemm", "renormalise", "full_svd", "misc"};
@@ -89,6 +93,12 @@ struct ctm_ctx {
   int chi_env = 0, cur = 0, spec_cur = 0;
   bool si_ready = false, iso_pending = false;
   long si_moves = 0, moves = 0;
+  // recycling of the SI blocks: `recycling` turns the subspace steps off;
+  // si_upd counts SI moves with steps since recycling last stopped;
+  // last_si_delta is the delta of the previous move if it was an SI move
+  bool recycling = false;
+  int si_upd = 0;
+  double last_si_delta = -1.0;
   // buffers
   double* A_site = nullptr;
   double* a = nullptr;
@@ -103,6 +113,8 @@ struct ctm_ctx {
   double* X0[4];
   double* Yt0[4];
   double* W[2][8];
+  double* Xprev[8];          // recycling: blocks of the previous move (X then Y^T)
+  double* ov[8];             // recycling: chi x chi overlaps of old and new blocks
   void* Ct[4];
   double* S1[4];
   double* S2[4];
@@ -127,14 +139,16 @@ struct ctm_ctx {
   double* hbuf = nullptr;    // [0..15] scal copy, [16] bad flag (as int)
   hipEvent_t done_ev = nullptr;
   bool pending = false;
-  int pend_mode = 0, pend_keep = 0;
+  int pend_mode = 0, pend_keep = 0, pend_nsi = 0;
+  bool pend_measure = false;
   // captured SI moves: the device work of a move depends on the generation
   // `cur` and on the arrangement of the block pointers (the QR and the
   // recycling swap them), so a graph is kept per (cur, arrangement) with the
   // arrangement the move leaves behind
   bool use_graphs = false;
   struct GraphRec {
-    int cur, spec_cur;
+    int cur, spec_cur, nsi;
+    bool measure;
     std::vector<void*> pre, post;
     hipGraphExec_t exec;
   };
@@ -182,6 +196,12 @@ int validate(const ctm_config* cfg) {
     return fail(nullptr, CTM_E_ARG, "sym must be CTM_SYM_NONE or CTM_SYM_C4V");
   if (cfg->sym == CTM_SYM_C4V && cfg->prec != CTM_PREC_F64)
     return fail(nullptr, CTM_E_ARG, "the C4v mode runs in float64 only");
+  if (!(cfg->recycle_sin2 == cfg->recycle_sin2))
+    return fail(nullptr, CTM_E_ARG, "recycle_sin2 must be a number");
+  if (cfg->recycle_sin2 > 0 && cfg->min_si_moves < 1)
+    return fail(nullptr, CTM_E_ARG, "min_si_moves must be >= 1 when recycling");
+  if (cfg->recycle_sin2 > 0 && cfg->sym == CTM_SYM_C4V)
+    return fail(nullptr, CTM_E_ARG, "recycling is implemented for the four-direction move only");
   const int Dl = cfg->d > 0 ? cfg->D * cfg->D : cfg->D;
   const long N = (long)cfg->chi * Dl;
   const long k = std::min<long>(cfg->chi + cfg->p, N);
@@ -232,6 +252,11 @@ size_t carve(ctm_ctx* c, char* base) {
   }
   for (int s = 0; s < 2; ++s)
     for (int i = 0; i < 8; ++i) c->W[s][i] = cv.take<double>(N * k);
+  const bool rec = c->cfg.recycle_sin2 > 0;
+  for (int i = 0; i < 8; ++i) {
+    c->Xprev[i] = rec ? cv.take<double>(N * k) : nullptr;
+    c->ov[i] = rec ? cv.take<double>(chi * chi) : nullptr;
+  }
   for (int i = 0; i < 4; ++i) c->Ct[i] = cv.take_bytes(Nm * Nm * es);
   for (int i = 0; i < 4; ++i) c->S1[i] = cv.take<double>(Nm * Nm);
   for (int i = 0; i < 4; ++i) c->S2[i] = cv.take<double>(Nm * Nm);
@@ -488,11 +513,21 @@ int ensure_si_blocks(ctm_ctx* c) {
   return 0;
 }
 
-// SI projectors of the four bonds (QR-based projector section, steps 1-3).
-int si_projectors(ctm_ctx* c, int keep) {
+// SI projectors of the four bonds (QR-based projector section, steps 1-3)
+// with nsi subspace steps.  With `measure`, the recycling criterion (the
+// largest over the 8 blocks of the mean sin^2 of the principal angles between
+// the kept columns before and after the move) is written to scal[13].
+int si_projectors(ctm_ctx* c, int keep, int nsi, bool measure) {
   const int N1 = c->N, k = c->k;
   TRY(ensure_si_blocks(c));
-  for (int step = 0; step < c->cfg.n_si; ++step) {
+  if (measure) {
+    const size_t nk = (size_t)N1 * k * sizeof(double);
+    for (int b = 0; b < 4; ++b) {
+      CTM_HIP_TRY(hipMemcpyAsync(c->Xprev[b], c->X[b], nk, hipMemcpyDeviceToDevice, c->st));
+      CTM_HIP_TRY(hipMemcpyAsync(c->Xprev[4 + b], c->Yt[b], nk, hipMemcpyDeviceToDevice, c->st));
+    }
+  }
+  for (int step = 0; step < nsi; ++step) {
     if (c->cfg.stabilized) {
       TRY(half_step(c, true, N1));   // X: M X      Y: M^T Y^T
       TRY(qr_and_swap(c, N1));
@@ -597,6 +632,24 @@ int si_projectors(ctm_ctx* c, int keep) {
   for (int b = 0; b < 4; ++b) {
     std::swap(c->X[b], c->W[0][b]);
     std::swap(c->Yt[b], c->W[0][4 + b]);
+  }
+  if (measure) {
+    // G_b = Q_old[:, :chi]^T Q_new[:, :chi] for the 8 blocks, then the criterion
+    const int chi = c->chi;
+    GemmBatch g = gemm_rowmajor(8, chi, chi, N1, k, k, chi);
+    for (int b = 0; b < 8; ++b) {
+      g.A[b] = c->Xprev[b];
+      g.transA[b] = 1;
+      g.B[b] = b < 4 ? c->X[b] : c->Yt[b - 4];
+      g.C[b] = c->ov[b];
+    }
+    TRY(run_gemm(c, PC_PROJ, g, DT::F64, DT::F64, DT::F64));
+    OverlapArgs oa{};
+    for (int b = 0; b < 8; ++b) oa.G[b] = c->ov[b];
+    oa.count = 8;
+    oa.chi = chi;
+    oa.out = c->scal + 13;
+    TRY(elem_sin2(oa, c->st));
   }
   return 0;
 }
@@ -923,7 +976,7 @@ void drop_graphs(ctm_ctx* c) {
 
 // Device work of a move (everything between the guard reset and the
 // read-back of its scalars).
-int move_work(ctm_ctx* c, int mode, int keep) {
+int move_work(ctm_ctx* c, int mode, int keep, int nsi, bool measure) {
   const int N1 = c->chi_env * c->Dl;
   TRY(elem_zero_int(c->bad, c->st));
   TRY(build_corners(c));
@@ -937,7 +990,7 @@ int move_work(ctm_ctx* c, int mode, int keep) {
   } else if (mode == 1) {
     TRY(full_projectors(c, keep));
   } else {
-    TRY(si_projectors(c, keep));
+    TRY(si_projectors(c, keep, nsi, measure));
   }
   TRY(renormalize(c, keep));
   const int nxt = 1 - c->cur;
@@ -948,18 +1001,19 @@ int move_work(ctm_ctx* c, int mode, int keep) {
 }
 
 // SI moves through a captured graph (one per (cur, pointer arrangement)).
-int move_work_graph(ctm_ctx* c, int mode, int keep) {
+int move_work_graph(ctm_ctx* c, int mode, int keep, int nsi, bool measure) {
   TRY(ensure_si_blocks(c));   // may copy the start blocks: outside the graph
   const std::vector<void*> pre = block_ptrs(c);
   for (auto& g : c->graphs) {
-    if (g.cur == c->cur && g.spec_cur == c->spec_cur && g.pre == pre) {
+    if (g.cur == c->cur && g.spec_cur == c->spec_cur && g.nsi == nsi && g.measure == measure &&
+        g.pre == pre) {
       set_block_ptrs(c, g.post);
       CTM_HIP_TRY(hipGraphLaunch(g.exec, c->st));
       return 0;
     }
   }
   CTM_HIP_TRY(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-  const int rc = move_work(c, mode, keep);
+  const int rc = move_work(c, mode, keep, nsi, measure);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(c->st, &graph);
   if (rc || ec != hipSuccess) {
@@ -970,6 +1024,8 @@ int move_work_graph(ctm_ctx* c, int mode, int keep) {
   ctm_ctx::GraphRec g;
   g.cur = c->cur;
   g.spec_cur = c->spec_cur;
+  g.nsi = nsi;
+  g.measure = measure;
   g.pre = pre;
   g.post = block_ptrs(c);
   const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
@@ -1003,16 +1059,29 @@ int enqueue_move(ctm_ctx* c) {
   }
   // growth and full-SVD moves call rocSOLVER and run eagerly; SI moves are
   // captured when graphs are enabled on a non-default stream
+  // recycling: no subspace step while `recycling`; the criterion is measured
+  // on moves with steps whose previous move was an SI move
+  const bool rec = c->cfg.recycle_sin2 > 0;
+  int nsi = 0;
+  bool measure = false;
+  if (mode == 2 && c->cfg.sym != CTM_SYM_C4V) {
+    nsi = (rec && c->recycling) ? 0 : c->cfg.n_si;
+    measure = rec && nsi > 0 && c->last_si_delta >= 0.0 && !c->iso_pending;
+  } else if (mode == 2) {
+    nsi = c->cfg.n_si;
+  }
   if (mode == 2 && c->use_graphs && !c->prof && c->st != nullptr)
-    TRY(move_work_graph(c, mode, keep));
+    TRY(move_work_graph(c, mode, keep, nsi, measure));
   else
-    TRY(move_work(c, mode, keep));
+    TRY(move_work(c, mode, keep, nsi, measure));
   CTM_HIP_TRY(hipMemcpyAsync(c->hbuf, c->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->st));
   CTM_HIP_TRY(hipMemcpyAsync(c->hbuf + 16, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->st));
   CTM_HIP_TRY(hipEventRecord(c->done_ev, c->st));
   c->pending = true;
   c->pend_mode = mode;
   c->pend_keep = keep;
+  c->pend_nsi = nsi;
+  c->pend_measure = measure;
   return CTM_OK;
 }
 
@@ -1027,6 +1096,18 @@ int finish_move(ctm_ctx* c, ctm_move_info* info) {
     return fail(c, CTM_E_NUMERIC, "move produced a zero or non-finite norm; environment kept");
   const int mode = c->pend_mode, keep = c->pend_keep;
   if (mode == 2) ++c->si_moves;
+  const double sin2 = c->pend_measure ? host[13] : -1.0;
+  if (c->cfg.recycle_sin2 > 0 && mode == 2) {
+    if (c->pend_nsi > 0) {
+      ++c->si_upd;
+      if (c->pend_measure && c->si_upd >= c->cfg.min_si_moves && sin2 < c->cfg.recycle_sin2)
+        c->recycling = true;
+    } else if (c->last_si_delta >= 0.0 && host[8] > kRecycleGuard * c->last_si_delta) {
+      c->recycling = false;
+      c->si_upd = 0;
+    }
+  }
+  c->last_si_delta = mode == 2 ? host[8] : -1.0;
   c->cur = 1 - c->cur;
   c->chi_env = keep;
   c->spec_cur = 1 - c->spec_cur;
@@ -1041,6 +1122,8 @@ int finish_move(ctm_ctx* c, ctm_move_info* info) {
       for (int b = 0; b < 4; ++b) gap = std::min(gap, host[9 + b]);
     }
     info->gap = gap;
+    info->n_si = c->pend_nsi;
+    info->sin2 = sin2;
   }
   return CTM_OK;
 }
@@ -1436,6 +1519,8 @@ ctm_status ctm_set_isometries(ctm_ctx* c, const double* X_dev, const double* Yt_
   }
   c->iso_pending = true;
   c->si_ready = false;
+  c->recycling = false;
+  c->si_upd = 0;
   return CTM_OK;
 }
 
@@ -1512,7 +1597,7 @@ ctm_status ctm_converge(ctm_ctx* c, double tol, int max_moves, int* moves_done,
 ctm_status ctm_state_size(const ctm_ctx* c, size_t* n) {
   if (!c || !n) return (ctm_status)fail(nullptr, CTM_E_ARG, "null argument");
   const size_t chi = c->chi, Dl = c->Dl, N = c->N, k = c->k;
-  *n = 4 * chi * chi + 4 * chi * Dl * chi + 8 * N * k + 2;
+  *n = 4 * chi * chi + 4 * chi * Dl * chi + 8 * N * k + 4;
   return CTM_OK;
 }
 
@@ -1545,6 +1630,8 @@ ctm_status ctm_get_state(ctm_ctx* c, double* host, size_t n) {
     return (ctm_status)fail(c, CTM_E_DEVICE, "synchronisation failed");
   p[0] = (double)c->chi_env;
   p[1] = (double)c->si_moves;
+  p[2] = c->recycling ? 1.0 : 0.0;
+  p[3] = (double)c->si_upd;
   return CTM_OK;
 }
 
@@ -1575,6 +1662,9 @@ ctm_status ctm_set_state(ctm_ctx* c, const double* host, size_t n) {
       return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
   c->chi_env = x;
   c->si_moves = (long)p[1];
+  c->recycling = c->cfg.recycle_sin2 > 0 && p[2] != 0.0;
+  c->si_upd = (int)p[3];
+  c->last_si_delta = -1.0;
   c->si_ready = (x == (int)chi);
   c->iso_pending = false;
   // spectra of the restored corners become the reference of the next delta

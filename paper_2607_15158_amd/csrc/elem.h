@@ -32,6 +32,12 @@ struct ProjPrepArgs {
   double rtol;
 };
 
+struct OverlapArgs {
+  const double* G[8];   // chi x chi products Q_old^T Q_new of orthonormal blocks
+  int count, chi;
+  double* out;          // largest over the blocks of the mean sin^2
+};
+
 struct SpecArgs {
   const double* s[4];
   const double* old_spec;  // [4][chi]
@@ -68,6 +74,7 @@ int elem_symmetrize_edge(double* T, int x, int Dl, hipStream_t s);
 int elem_c4v_order(const double* w, const double* V, int n, int keep, double* P, hipStream_t s);
 int elem_copy_cols(const double* X, int n, long ld, int keep, double* P, hipStream_t s);
 int elem_spectra_delta(const SpecArgs& sp, hipStream_t s);
+int elem_sin2(const OverlapArgs& oa, hipStream_t s);
 int elem_gauss(double* x, long n, uint64_t seed, hipStream_t s);
 int elem_dot_rev(const double* X, const double* Y, int x, int m, double* out, hipStream_t s);
 int elem_dot_rev_batched(const double* X, long xs, const double* Y, long ys, int nb, int x, int m,

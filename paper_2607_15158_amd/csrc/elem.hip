@@ -135,6 +135,24 @@ __global__ void k_scale(NormArgs na) {
     x[i] *= inv;
 }
 
+// Mean sin^2 of the principal angles between the spans of two orthonormal
+// chi-column blocks: the cosines are the singular values of G = Q_old^T Q_new,
+// so the mean is 1 - |G|_F^2 / chi.  One block of 256 threads; out[0] is the
+// largest value over the count products.
+__global__ __launch_bounds__(256) void k_sin2(OverlapArgs oa) {
+  __shared__ double sh[4];
+  const long n = (long)oa.chi * oa.chi;
+  double worst = -1.0;
+  for (int b = 0; b < oa.count; ++b) {
+    const double* G = oa.G[b];
+    double acc = 0.0;
+    for (long i = threadIdx.x; i < n; i += blockDim.x) acc += G[i] * G[i];
+    acc = block_sum(acc, sh);
+    worst = fmax(worst, 1.0 - acc / oa.chi);
+  }
+  if (threadIdx.x == 0) oa.out[0] = worst;
+}
+
 // Sign rule: for every column j of the N x k block Y (ld = ld), the dominant
 // entry -- the lowest-index entry whose magnitude is within a relative 1e-8
 // of the column's largest magnitude -- is made positive; sg[j] = +-1.
@@ -521,6 +539,13 @@ int elem_normalize(const NormArgs& na, int count, hipStream_t s) {
 
 int elem_norms(const NormArgs& na, int count, hipStream_t s) {
   k_norms<<<count, 256, 0, s>>>(na);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_sin2(const OverlapArgs& oa, hipStream_t s) {
+  if (oa.count < 1 || oa.count > 8 || oa.chi < 1) return 1;
+  k_sin2<<<1, 256, 0, s>>>(oa);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -72,6 +72,22 @@ def test_unknown_projector_and_precision_rejected():
     assert P._lib.ctm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == P.CTM_E_ARG
 
 
+def test_recycling_configs():
+    """Recycling keeps two more sets of blocks; it needs min_si_moves >= 1, a
+    numeric threshold and the four-direction move."""
+    base = dict(d=2, D=3, chi=18, p=6)
+    plain = P.workspace_bytes(P.Config(**base))
+    rec = P.workspace_bytes(P.Config(**base, recycle_sin2=1e-3))
+    N, k, chi = 18 * 9, 24, 18
+    assert rec - plain >= 8 * (N * k + chi * chi) * 8
+    n = ctypes.c_size_t()
+    for kw in (dict(recycle_sin2=1e-3, min_si_moves=0),
+               dict(recycle_sin2=float("nan")),
+               dict(recycle_sin2=1e-3, sym="c4v")):
+        c = P.Config(**base, **kw).c()
+        assert P._lib.ctm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == P.CTM_E_ARG, kw
+
+
 def test_null_arguments_are_errors_not_crashes():
     assert P._lib.ctm_workspace_bytes(None, None) == P.CTM_E_ARG
     h = ctypes.c_void_p()

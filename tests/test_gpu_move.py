@@ -384,3 +384,36 @@ def test_config2_si_fixed_point_is_the_full_svd_fixed_point():
     assert info["delta"] <= 1e-8
     assert abs(svd.kappa() / k_si - 1) <= 1e-10
     assert abs(e_svd - e_si) <= 1e-9
+
+
+@pytest.mark.parametrize("D,chi,p,noise,seed", [(2, 8, 4, 1.0, 1), (2, 12, 4, 0.3, 2)])
+def test_recycle_mode_follows_the_oracle(D, chi, p, noise, seed):
+    """Recycling of the SI blocks: the same moves take subspace steps as in
+    the oracle (the switch after the subspaces align, and in the second case
+    the resumption when delta jumps), with the same deltas, recycling
+    criteria and converged energies.  Every decision in these runs is far
+    from its threshold (sin^2 1e-3, delta ratio 10)."""
+    A = S.product_plus_noise_site(2, D, seed, noise=noise)
+    a, e = O.double_layer(A), S.trace_boundary(D)
+    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2, recycle_sin2=1e-3, min_si_moves=3)
+    ctx, si = make(cfg, A)
+    env, hist = O.run_ctmrg(a, e, chi, proj="si", iso0=si, tol=1e-10, max_moves=80,
+                            recycle_sin2=1e-3, min_si_moves=3)
+    code = {"grow": 0, "svd": 1, "si": 2}
+    for h in hist:
+        info = ctx.move()
+        assert info["mode"] == code[h["mode"]], h
+        assert info["n_si"] == (h["n_si"] or 0), (h, info)
+        assert abs(info["delta"] - h["delta"]) <= 1e-7 * h["delta"] + 1e-13, (h, info)
+        if h["sin2"] is None:
+            assert info["sin2"] == -1.0
+        else:
+            assert abs(info["sin2"] - h["sin2"]) <= 1e-8 * max(h["sin2"], 1e-3), (h, info)
+    assert any(h["n_si"] == 0 for h in hist)
+    zz = np.kron(S.pauli("z"), S.pauli("z"))
+    hb = S.heisenberg_bond()
+    for op in (zz, hb):
+        got = ctx.observable(P.OBS_BOND_H, op)[0]
+        assert abs(got - O.bond_value(env, A, op, "h")) <= 1e-9
+    st = ctx.unpack_state(ctx.get_state())
+    assert st["recycling"] == (hist[-1]["n_si"] == 0)

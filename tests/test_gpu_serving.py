@@ -53,11 +53,14 @@ def test_async_moves_equal_sync_moves():
     assert np.array_equal(a.get_state(), b.get_state())
 
 
-def test_graph_replay_matches_eager_moves():
+@pytest.mark.parametrize("recycle", [0.0, 1e-3])
+def test_graph_replay_matches_eager_moves(recycle):
     """SI moves replayed from captured graphs equal eager moves bit for bit,
     on every replay, with unrelated eager work and synchronisations between
-    the replays."""
+    the replays; with recycling, the moves with and without subspace steps
+    (and with the criterion measured) are captured separately."""
     cfg, A, X, Y = request(2, 6, 7)
+    cfg.recycle_sin2 = recycle
     dev = torch.device("cuda", 0)
     eager = P.Ctm(cfg, torch.from_numpy(A).to(dev))
     side = torch.cuda.Stream()
@@ -66,14 +69,18 @@ def test_graph_replay_matches_eager_moves():
         c.set_isometries(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
     graphed.use_graphs(True)
     noise = torch.randn(512, 512, device=dev)
-    for n in range(10):
+    steps = []
+    for n in range(14):
         ie = eager.move()
         ig = graphed.move()
         assert ie == ig, n
         assert np.array_equal(eager.get_state(), graphed.get_state()), n
+        if ig["mode"] == 2:
+            steps.append(ig["n_si"])
         noise = noise @ noise.T / 512.0            # eager work between replays
         torch.cuda.synchronize()
     assert ig["mode"] == 2
+    assert (0 in steps) == (recycle > 0)
 
 
 def test_mix_equals_solo_runs():
