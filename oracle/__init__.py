@@ -12,6 +12,10 @@ paper's equations are tensor diagrams; the matrix reading used here (index
 order, which bond each enlarged-corner product is open at, sign and cutoff
 rules) is written out in the module docstring of :mod:`oracle.ctmrg`.
 
+The reverse-mode reference of one move (:mod:`oracle.adjoint`, PyTorch CPU
+autograd in float64) is imported explicitly; it is pinned to central finite
+differences of the NumPy move.
+
 Parity status: every function is pinned by ``tests/test_oracle_*.py``
 (Onsager/Yang closed forms, exact product states, Eckart-Young, k = N
 reduction of subspace iteration to the SVD, gauge and rotation invariances,
