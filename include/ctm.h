@@ -284,6 +284,45 @@ const char* ctm_server_error(const ctm_server* server, int id);
 double ctm_server_clock(const ctm_server* server);
 
 /* ---------------------------------------------------------------------------
+ * Adjoint of one SI move (Differentiable fixed point passage, eq. implicit:
+ * gradients of CTMRG observables are built from vector-Jacobian products
+ * of the single move; unrolled over moves, or iterated at the fixed point).
+ *
+ * The move (C, T, X, Y^T, A) -> (C', T', X', Y^T') of the context's
+ * configuration is recomputed from state_in, with its intermediates kept
+ * in ws, and the cotangents are propagated back through every step (unit
+ * norms, renormalisation, projectors with the pseudo-inverse, the SVD of
+ * rho, the QRs of the subspace steps, every enlarged-corner application,
+ * the enlarged corners and the double layer).  The discrete choices of
+ * the forward move (QR diagonal signs, the sign rule, the pseudo-inverse
+ * mask) are held constant.  Inverse singular-value gaps of rho carry a
+ * Lorentzian broadening (1e-12 s_1^2)^2, relevant only for (near-)
+ * degenerate pairs.
+ *
+ * Requirements: d >= 1, proj = SI, prec = F64, stabilized = 1, sym = NONE,
+ * and chi_env == chi in state_in (an SI move); otherwise CTM_E_ARG /
+ * CTM_E_STATE.  The context's own environment is not read or changed.
+ * --------------------------------------------------------------------------- */
+
+/* Device bytes of the adjoint workspace for cfg. */
+ctm_status ctm_vjp_workspace_bytes(const ctm_config* cfg, size_t* bytes);
+
+/* All pointers are device memory in the state-vector layout of
+ * ctm_state_size (C1..C4, T1..T4, X_0..X_3, Yt_0..Yt_3, 4 counters):
+ *  state_in       the move's input state (read);
+ *  state_out_bar  cotangents of the move's outputs C', T', X', Y^T'
+ *                 (counters ignored) (read);
+ *  state_in_bar   cotangents of C, T, X, Y^T (written; counters set to 0);
+ *  state_out      the move's output state, or NULL (written);
+ *  site_bar       d*D^4 cotangent of the site tensor A, accumulated (+=),
+ *                 or NULL;
+ *  ws, ws_bytes   caller-owned workspace of ctm_vjp_workspace_bytes bytes.
+ * Stream-ordered on the context's stream; returns after it has finished. */
+ctm_status ctm_move_vjp(ctm_ctx* ctx, const double* state_in, const double* state_out_bar,
+                        double* state_in_bar, double* state_out, double* site_bar, void* ws,
+                        size_t ws_bytes);
+
+/* ---------------------------------------------------------------------------
  * Building blocks of a move, exposed for testing and for callers composing
  * their own loops.  All operate on caller device memory on `stream`.
  * ------------------------------------------------------------------------- */

@@ -101,6 +101,8 @@ _sigs = {
                                     ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long,
                                     ctypes.c_double, ctypes.c_int, _vp]),
     "ctm_qr_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),
+    "ctm_vjp_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ctm_config), ctypes.POINTER(ctypes.c_size_t)]),
+    "ctm_move_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t]),
     "ctm_svd_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _vp]),
 }
@@ -188,6 +190,7 @@ class Ctm:
         self.workspace = (torch.empty(nbytes, dtype=torch.uint8, device=dev)
                           if workspace is None else workspace)
         self.stream = stream
+        self._vjp_ws = None
         h = ctypes.c_void_p()
         _check(_lib.ctm_init(ctypes.byref(h), ctypes.byref(self._c), _ptr(self._site),
                              None if self._bnd is None else _ptr(self._bnd),
@@ -264,6 +267,29 @@ class Ctm:
     def set_state(self, state: np.ndarray):
         buf = np.ascontiguousarray(state, dtype=np.float64)
         _check(_lib.ctm_set_state(self._h, buf.ctypes.data_as(_dp), buf.size), self._h)
+
+    # adjoint -----------------------------------------------------------------
+    def move_vjp(self, state_in, out_bar, want_out: bool = True, site_bar=None):
+        """Vector-Jacobian product of one SI move from ``state_in`` (a float64
+        device tensor in the state layout): returns the cotangent of the input
+        state, the move's output state (or None) and ``site_bar`` (the site
+        tensor's cotangent, accumulated into the given tensor or a new one)."""
+        import torch
+        if self._vjp_ws is None:
+            n = ctypes.c_size_t(0)
+            _check(_lib.ctm_vjp_workspace_bytes(ctypes.byref(self._c), ctypes.byref(n)))
+            self._vjp_ws = torch.empty(n.value, dtype=torch.uint8, device=self._site.device)
+        dev = self._site.device
+        sin = state_in.to(dev, torch.float64).contiguous()
+        sbar = out_bar.to(dev, torch.float64).contiguous()
+        in_bar = torch.empty_like(sin)
+        out = torch.empty_like(sin) if want_out else None
+        if site_bar is None:
+            site_bar = torch.zeros_like(self._site)
+        _check(_lib.ctm_move_vjp(self._h, sin.data_ptr(), sbar.data_ptr(), in_bar.data_ptr(),
+                                 None if out is None else out.data_ptr(), site_bar.data_ptr(),
+                                 self._vjp_ws.data_ptr(), self._vjp_ws.numel()), self._h)
+        return in_bar, out, site_bar
 
     def unpack_state(self, state: np.ndarray) -> dict:
         """Splits a state vector into C, T (cut to chi_env), X, Yt, chi_env."""

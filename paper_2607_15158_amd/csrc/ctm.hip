@@ -35,6 +35,7 @@
 
 #include "common.h"
 #include "elem.h"
+#include "vjp.h"
 
 namespace sictm {
 
@@ -1676,6 +1677,39 @@ ctm_status ctm_set_state(ctm_ctx* c, const double* host, size_t n) {
   return CTM_OK;
 }
 
+
+}  // extern "C"
+
+namespace sictm {
+
+int vjp_view(ctm_ctx* c, VjpView* v) {
+  const int rd = drain(c);
+  if (rd) return rd;
+  v->cfg = c->cfg;
+  v->d = c->d;
+  v->D = c->D;
+  v->Dl = c->Dl;
+  v->chi = c->chi;
+  v->k = c->k;
+  v->N = c->N;
+  v->st = c->st;
+  v->A_site = c->A_site;
+  v->a = c->a;
+  const long Dl = c->Dl;
+  const long su = Dl * Dl * Dl, sl = Dl * Dl, sd = Dl, sr = 1;
+  const long perm[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
+  for (int i = 0; i < 4; ++i) {
+    v->ap[i] = (const double*)c->ap[i];
+    for (int j = 0; j < 4; ++j) v->ap_strides[i][j] = perm[i][j];
+  }
+  return 0;
+}
+
+int vjp_fail(ctm_ctx* c, int code, const std::string& msg) { return fail(c, code, msg); }
+
+}  // namespace sictm
+
+extern "C" {
 
 ctm_status ctm_observable(ctm_ctx* c, int kind, const double* op_host, double* out_host) {
   if (!c || !out_host) return (ctm_status)fail(c, CTM_E_ARG, "null argument");

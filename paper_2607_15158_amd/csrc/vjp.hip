@@ -1,0 +1,1413 @@
+// Adjoint of one SI-CTMRG move: the vector-Jacobian product
+//   (C, T, X, Y^T, A) -> (C', T', X', Y^T')
+// that the paper's differentiation of CTMRG is built from (Differentiable
+// fixed point passage, eq. implicit: the fixed-point gradient needs only
+// VJPs of the single move; the timing figure unrolls the moves instead).
+//
+// The move is recomputed from the caller's input state with its
+// intermediates kept in a caller-owned workspace (the "tape"), then the
+// cotangents are propagated back through every step on the GPU:
+//   - unit-norm scaling:  x_bar = (y_bar - y <y, y_bar>) / |x|;
+//   - renormalisation (Fig. 1): the GEMM chain of C' = P_r Ct P_l and
+//     T' = P_r (T a) P_l, with the a-absorption's permutations inverted;
+//   - projectors (eq. projectors_diag) with the pseudo-inverse mask and the
+//     signs of the sign rule held constant;
+//   - the small SVD of rho (eq. rho_hat_diag): for rho = u s v^T (square,
+//     full u, v),  rho_bar = u [F o (u^T u_bar - u_bar^T u) s + diag(s_bar)
+//     + s F o (v^T v_bar - v_bar^T v)] v^T,  F_ij = 1 / (s_j^2 - s_i^2);
+//   - the QRs of the subspace steps (eq. xy_iter, stabilised): for H = Q R
+//     with only Q used,  H_bar = (Q_bar + Q copyltu(-Q_bar^T Q)) R^-T;
+//   - every application of an enlarged corner: the block cotangent goes
+//     back through op(Ct)^T, the corner cotangent gains a rank-k term;
+//   - enlarged corners (eq. rho_M_diag) and the double layer (eq.
+//     double_layer).
+// Discrete choices (QR diagonal signs, sign rule, pseudo-inverse mask) are
+// piecewise constant in the input and are held fixed, as in any
+// reverse-mode treatment of the move.
+
+#include "../../include/ctm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "elem.h"
+#include "vjp.h"
+
+using namespace sictm;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// dst[i] (=, or += when acc) alpha * src[i0 s0 + i1 s1 + i2 s2 + i3 s3] over
+// the index box n0 x n1 x n2 x n3 (row-major in dst).
+__global__ __launch_bounds__(256) void k_gather4(const double* __restrict__ src,
+                                                 double* __restrict__ dst, int n0, int n1,
+                                                 int n2, int n3, long s0, long s1, long s2,
+                                                 long s3, double alpha, int acc) {
+  const long total = (long)n0 * n1 * n2 * n3;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    long r = i;
+    const long i3 = r % n3;
+    r /= n3;
+    const long i2 = r % n2;
+    r /= n2;
+    const long i1 = r % n1;
+    const long i0 = r / n1;
+    const double v = alpha * src[i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3];
+    dst[i] = acc ? dst[i] + v : v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill(double* __restrict__ x, long n, double v) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__device__ __forceinline__ double block_sum256(double x, double* sh) {
+  x = wave_sum64(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = x;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+struct DotArgs {
+  const double* x[8];
+  const double* y[8];
+  long n[8];
+  double* out;
+};
+
+// out[t] = <x_t, y_t>, one block of 256 threads per pair.
+__global__ __launch_bounds__(256) void k_dots(DotArgs a) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x;
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < a.n[t]; i += 256) acc += a.x[t][i] * a.y[t][i];
+  acc = block_sum256(acc, sh);
+  if (threadIdx.x == 0) a.out[t] = acc;
+}
+
+struct NormBwdArgs {
+  const double* y[8];    // unit-norm outputs
+  const double* yb[8];   // their cotangents
+  double* xb[8];         // cotangents of the unscaled tensors
+  long n[8];
+  const double* dot;     // <y_t, yb_t>
+  const double* nrm;     // |x_t|
+};
+
+__global__ __launch_bounds__(256) void k_norm_bwd(NormBwdArgs a) {
+  const int t = blockIdx.y;
+  const double dt = a.dot[t], inv = 1.0 / a.nrm[t];
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < a.n[t]; i += (long)gridDim.x * 256)
+    a.xb[t][i] = (a.yb[t][i] - a.y[t][i] * dt) * inv;
+}
+
+struct SmallArgs {
+  const double* in[8];
+  double* out[8];
+  int n;
+};
+
+// out = tril(in) + tril(in, -1)^T (the lower triangle mirrored up).
+__global__ __launch_bounds__(256) void k_copyltu(SmallArgs a) {
+  const int b = blockIdx.y, n = a.n;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < n * n; idx += gridDim.x * 256) {
+    const int i = idx / n, j = idx % n;
+    a.out[b][idx] = i >= j ? a.in[b][idx] : a.in[b][j * n + i];
+  }
+}
+
+// Inverse of an upper-triangular n x n matrix (n <= 256), one block per
+// matrix, thread j owns column j: back substitution row by row.  A zero
+// diagonal entry (a rank-deficient block) gives a zero row.
+__global__ __launch_bounds__(256) void k_tri_inv(SmallArgs a) {
+  const int b = blockIdx.x, n = a.n, j = threadIdx.x;
+  const double* R = a.in[b];
+  double* X = a.out[b];
+  if (j >= n) return;
+  for (int i = n - 1; i >= 0; --i) {
+    double v = 0.0;
+    if (j >= i) {
+      double acc = i == j ? 1.0 : 0.0;
+      for (int l = i + 1; l <= j; ++l) acc -= R[(long)i * n + l] * X[(long)l * n + j];
+      const double d = R[(long)i * n + i];
+      v = d != 0.0 ? acc / d : 0.0;
+    }
+    X[(long)i * n + j] = v;
+  }
+}
+
+struct PrepArgs {
+  const double* u[4];
+  const double* v[4];
+  const double* s[4];
+  const double* sg[4];
+  double* us[4];
+  double* vs[4];
+  double* sinv[4];
+  double* vsc[4];
+  double* usc[4];
+  int k, keep;
+  double rtol;
+};
+
+// Signed singular vectors, s^-1/2 with the cut s_i <= rtol s_1 (and beyond
+// keep) set to 0, and the scaled kept columns v_s sinv, u_s sinv.
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+  const int b = blockIdx.y, k = a.k, keep = a.keep;
+  const double s0 = a.s[b][0];
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < k * k; idx += gridDim.x * 256) {
+    const int r = idx / k, c = idx % k;
+    const double sc = c < keep && s0 > 0.0 && a.s[b][c] > a.rtol * s0 ? 1.0 / sqrt(a.s[b][c]) : 0.0;
+    const double us = a.u[b][idx] * a.sg[b][c], vs = a.v[b][idx] * a.sg[b][c];
+    a.us[b][idx] = us;
+    a.vs[b][idx] = vs;
+    if (c < keep) {
+      a.vsc[b][r * keep + c] = vs * sc;
+      a.usc[b][r * keep + c] = us * sc;
+    }
+    if (r == 0) a.sinv[b][c] = sc;
+  }
+}
+
+struct ProjBwdArgs {
+  const double* us[4];
+  const double* vs[4];
+  const double* sinv[4];
+  const double* vscb[4];   // A^T P_l_bar    (k x keep)
+  const double* uscb[4];   // B^T P_rT_bar   (k x keep)
+  double* ub[4];           // in: recycle term Y^T Y'_bar; out: full u_bar
+  double* vb[4];
+  double* sb[4];
+  int k, keep;
+};
+
+// Adds the projector terms to u_bar, v_bar and forms s_bar from
+// d(s^-1/2)/ds = -s^-3/2 / 2 = -sinv^3 / 2 (zero where the cut applies).
+__global__ __launch_bounds__(256) void k_proj_bwd(ProjBwdArgs a) {
+  const int b = blockIdx.x, k = a.k, keep = a.keep;
+  for (int c = threadIdx.x; c < k; c += 256) {
+    if (c >= keep) {
+      a.sb[b][c] = 0.0;
+      continue;
+    }
+    const double si = a.sinv[b][c];
+    double acc = 0.0;
+    for (int r = 0; r < k; ++r) {
+      const double vq = a.vscb[b][r * keep + c], uq = a.uscb[b][r * keep + c];
+      a.vb[b][r * k + c] += vq * si;
+      a.ub[b][r * k + c] += uq * si;
+      acc += vq * a.vs[b][r * k + c] + uq * a.us[b][r * k + c];
+    }
+    a.sb[b][c] = si > 0.0 ? -0.5 * acc * si * si * si : 0.0;
+  }
+}
+
+struct KmatArgs {
+  const double* Ju[4];   // u^T u_bar
+  const double* Jv[4];   // v^T v_bar
+  const double* s[4];
+  const double* sb[4];
+  double* K[4];
+  int n;
+};
+
+// Inner matrix of the SVD adjoint; the inverse gaps carry a Lorentzian
+// broadening (1e-12 s_1^2)^2 that only matters for (near-)degenerate pairs.
+__global__ __launch_bounds__(256) void k_svd_kmat(KmatArgs a) {
+  const int b = blockIdx.y, n = a.n;
+  const double* s = a.s[b];
+  const double e2 = 1e-12 * s[0] * s[0], eps = e2 * e2;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < n * n; idx += gridDim.x * 256) {
+    const int i = idx / n, j = idx % n;
+    double v;
+    if (i == j) {
+      v = a.sb[b][i];
+    } else {
+      const double dl = s[j] * s[j] - s[i] * s[i];
+      const double F = dl / (dl * dl + eps);
+      v = F * (a.Ju[b][idx] - a.Ju[b][j * n + i]) * s[j] +
+          s[i] * F * (a.Jv[b][idx] - a.Jv[b][j * n + i]);
+    }
+    a.K[b][idx] = v;
+  }
+}
+
+// msym[ket, bra] = ab[ket, bra] + ab[bra, ket] with ab in the double-layer
+// order [(uU),(lL),(dD),(rR)] and ket = (u,l,d,r), bra = (U,L,D,R).
+__global__ __launch_bounds__(256) void k_dl_sym(const double* __restrict__ ab,
+                                                double* __restrict__ out, int D) {
+  const long D4 = (long)D * D * D * D, Dl = (long)D * D;
+  for (long idx = blockIdx.x * 256L + threadIdx.x; idx < D4 * D4; idx += (long)gridDim.x * 256) {
+    long p = idx / D4, q = idx % D4;
+    const long r0 = p % D, d0 = (p / D) % D, l0 = (p / Dl) % D, u0 = p / (Dl * D);
+    const long r1 = q % D, d1 = (q / D) % D, l1 = (q / Dl) % D, u1 = q / (Dl * D);
+    const long i1 = (((u0 * D + u1) * Dl + (l0 * D + l1)) * Dl + (d0 * D + d1)) * Dl + (r0 * D + r1);
+    const long i2 = (((u1 * D + u0) * Dl + (l1 * D + l0)) * Dl + (d1 * D + d0)) * Dl + (r1 * D + r0);
+    out[idx] = ab[i1] + ab[i2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// buffers of one adjoint call, carved from the caller's workspace
+// ---------------------------------------------------------------------------
+struct Dims {
+  int d, D, Dl, x, N, k, nsi;
+};
+
+struct Bufs {
+  double *Ct[4], *Ctb[4], *CT[4], *Wc[4], *apT[4];
+  std::vector<double*> tape[8];           // 10 n_si blocks per side
+  double *W1[4], *Ab[4], *W2[4], *Bt[4];
+  double *rho[4], *u[4], *v[4], *us[4], *vs[4], *s[4], *sg[4], *sinv[4], *vsc[4], *usc[4];
+  double *Pl[4], *Prt[4], *Zc[4], *Z1[4], *Z2[4];
+  double *Cn[4], *Tn[4], *Ch[4], *Th[4];
+  double *nrm, *dots;
+  double *Chb[4], *Thb[4], *Plb[4], *Prtb[4], *Zcb;
+  double *Sa, *Sb, *St;                   // N x N scratch, and a transposition buffer
+  double *ab, *apb, *msym;
+  double *Qb[8], *Hb[8], *Yq[8], *tr[8];
+  double *R[8], *Rinv[8], *RinvT[8], *Mm[8], *Mc[8];
+  double *Ju[4], *Jv[4], *Km[4], *uK[4], *vsT[4], *usT[4], *rhob[4], *rhobT[4];
+  double *vscb[4], *uscb[4], *vscT[4], *uscT[4], *ub[4], *vb[4], *sb[4];
+  double *smallT;                         // x x x / k x k transposes
+  void *qr_ws, *svd_ws;
+};
+
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  std::vector<std::pair<uintptr_t, uintptr_t>>* reg = nullptr;
+  double* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    double* p = base ? reinterpret_cast<double*>(base + off) : nullptr;
+    if (base && reg) reg->push_back({(uintptr_t)p, (uintptr_t)p + count * sizeof(double)});
+    off += count * sizeof(double);
+    return p;
+  }
+  void* bytes(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    void* p = base ? base + off : nullptr;
+    if (base && reg) reg->push_back({(uintptr_t)p, (uintptr_t)p + n});
+    off += n;
+    return p;
+  }
+};
+
+size_t carve(const Dims& m, Bufs* b, char* base, std::vector<std::pair<uintptr_t, uintptr_t>>* reg) {
+  Carver cv;
+  cv.base = base;
+  cv.reg = reg;
+  const size_t N = m.N, k = m.k, x = m.x, Dl = m.Dl, NN = N * N, Nk = N * k;
+  const size_t D4 = (size_t)m.D * m.D * m.D * m.D;
+  for (int i = 0; i < 4; ++i) {
+    b->Ct[i] = cv.take(NN);
+    b->Ctb[i] = cv.take(NN);
+    b->CT[i] = cv.take(x * Dl * x);
+    b->Wc[i] = cv.take(NN);
+    b->apT[i] = cv.take(Dl * Dl * Dl * Dl);
+  }
+  for (int j = 0; j < 8; ++j) {
+    b->tape[j].resize(10 * m.nsi);
+    for (int t = 0; t < 10 * m.nsi; ++t) b->tape[j][t] = cv.take(Nk);
+  }
+  for (int i = 0; i < 4; ++i) {
+    b->W1[i] = cv.take(Nk);
+    b->Ab[i] = cv.take(Nk);
+    b->W2[i] = cv.take(Nk);
+    b->Bt[i] = cv.take(Nk);
+    b->rho[i] = cv.take(k * k);
+    b->u[i] = cv.take(k * k);
+    b->v[i] = cv.take(k * k);
+    b->us[i] = cv.take(k * k);
+    b->vs[i] = cv.take(k * k);
+    b->s[i] = cv.take(k);
+    b->sg[i] = cv.take(k);
+    b->sinv[i] = cv.take(k);
+    b->vsc[i] = cv.take(k * x);
+    b->usc[i] = cv.take(k * x);
+    b->Pl[i] = cv.take(N * x);
+    b->Prt[i] = cv.take(N * x);
+    b->Zc[i] = cv.take(N * x);
+    b->Z1[i] = cv.take(NN);
+    b->Z2[i] = cv.take(NN);
+    b->Cn[i] = cv.take(x * x);
+    b->Tn[i] = cv.take(x * Dl * x);
+    b->Ch[i] = cv.take(x * x);
+    b->Th[i] = cv.take(x * Dl * x);
+    b->Chb[i] = cv.take(x * x);
+    b->Thb[i] = cv.take(x * Dl * x);
+    b->Plb[i] = cv.take(N * x);
+    b->Prtb[i] = cv.take(N * x);
+    b->Ju[i] = cv.take(k * k);
+    b->Jv[i] = cv.take(k * k);
+    b->Km[i] = cv.take(k * k);
+    b->uK[i] = cv.take(k * k);
+    b->vsT[i] = cv.take(k * k);
+    b->usT[i] = cv.take(k * k);
+    b->rhob[i] = cv.take(k * k);
+    b->rhobT[i] = cv.take(k * k);
+    b->vscb[i] = cv.take(k * x);
+    b->uscb[i] = cv.take(k * x);
+    b->vscT[i] = cv.take(k * x);
+    b->uscT[i] = cv.take(k * x);
+    b->ub[i] = cv.take(k * k);
+    b->vb[i] = cv.take(k * k);
+    b->sb[i] = cv.take(k);
+  }
+  b->nrm = cv.take(8);
+  b->dots = cv.take(8);
+  b->Zcb = cv.take(N * x);
+  b->Sa = cv.take(NN);
+  b->Sb = cv.take(NN);
+  b->St = cv.take(std::max(NN, Nk));
+  b->ab = cv.take(Dl * Dl * Dl * Dl);
+  b->apb = cv.take(Dl * Dl * Dl * Dl);
+  b->msym = cv.take(D4 * D4);
+  for (int j = 0; j < 8; ++j) {
+    b->Qb[j] = cv.take(Nk);
+    b->Hb[j] = cv.take(Nk);
+    b->Yq[j] = cv.take(Nk);
+    b->tr[j] = cv.take(Nk);
+    b->R[j] = cv.take(k * k);
+    b->Rinv[j] = cv.take(k * k);
+    b->RinvT[j] = cv.take(k * k);
+    b->Mm[j] = cv.take(k * k);
+    b->Mc[j] = cv.take(k * k);
+  }
+  b->smallT = cv.take(std::max(x * x, k * k));
+  b->qr_ws = cv.bytes(qr_workspace_bytes(8, m.N, m.k));
+  b->svd_ws = cv.bytes(svd_workspace_bytes(4, m.k));
+  return cv.off + 256;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers with host-side bounds checks
+// ---------------------------------------------------------------------------
+struct Run {
+  ctm_ctx* c;
+  hipStream_t st;
+  std::vector<std::pair<uintptr_t, uintptr_t>> reg;
+
+  bool inside(const void* p, size_t bytes) const {
+    const uintptr_t a = (uintptr_t)p;
+    for (const auto& r : reg)
+      if (a >= r.first && a + bytes <= r.second) return true;
+    return false;
+  }
+  int fail(const std::string& msg) { return vjp_fail(c, CTM_E_SHAPE, msg); }
+};
+
+long extent(int n, int div, long s1, long s0) {
+  if (n <= 0) return 0;
+  return (long)((n - 1) / div) * s1 + (long)std::min(div - 1, n - 1) * s0;
+}
+
+GemmBatch rowmajor(int count, int M, int N, int K, long lda, long ldb, long ldc) {
+  GemmBatch g{};
+  g.count = count;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  gemm_set_rowmajor_c(g, ldc);
+  g.nbatch = 1;
+  g.alpha = 1.0;
+  return g;
+}
+
+// Float64 GEMM after checking every operand against the registered buffers.
+int gemm(Run& r, const GemmBatch& g, bool si = false) {
+  if (g.M <= 0 || g.N <= 0) return 0;
+  for (int i = 0; i < g.count; ++i) {
+    const long ea = g.K <= 0 ? 0
+                    : (g.transA[i] ? (long)(g.K - 1) * g.lda + (g.M - 1)
+                                   : (long)(g.M - 1) * g.lda + (g.K - 1)) +
+                          (long)(g.nbatch - 1) * g.a_bs;
+    const long eb = g.K <= 0 ? 0 : (long)(g.K - 1) * g.ldb + (g.N - 1) + (long)(g.nbatch - 1) * g.b_bs;
+    const long ec = extent(g.M, g.cdiv_m, g.cs_m1, g.cs_m0) +
+                    extent(g.N, g.cdiv_n, g.cs_n1, g.cs_n0) + (long)(g.nbatch - 1) * g.c_bs;
+    if (!(g.K <= 0 || r.inside(g.A[i], (size_t)(ea + 1) * 8)) ||
+        !(g.K <= 0 || r.inside(g.B[i], (size_t)(eb + 1) * 8)) || !r.inside(g.C[i], (size_t)(ec + 1) * 8))
+      return r.fail("adjoint GEMM operand out of its buffer (M=" + std::to_string(g.M) + " N=" +
+                    std::to_string(g.N) + " K=" + std::to_string(g.K) + ", problem " +
+                    std::to_string(i) + "); launch refused");
+  }
+  const int rc = si ? launch_gemm_si(g, r.st) : launch_gemm(g, DT::F64, DT::F64, DT::F64, r.st);
+  if (rc) return vjp_fail(r.c, rc == 1 ? CTM_E_ARG : rc, thread_error());
+  return 0;
+}
+
+// dst (n0 x n1 x n2 x n3, row-major) (=|+=) alpha * src[strided].
+int gather(Run& r, const double* src, double* dst, int n0, int n1, int n2, int n3, long s0,
+           long s1, long s2, long s3, bool acc = false, double alpha = 1.0) {
+  const long total = (long)n0 * n1 * n2 * n3;
+  if (total <= 0) return 0;
+  const long es = (long)(n0 - 1) * s0 + (long)(n1 - 1) * s1 + (long)(n2 - 1) * s2 + (long)(n3 - 1) * s3;
+  if (!r.inside(src, (size_t)(es + 1) * 8) || !r.inside(dst, (size_t)total * 8))
+    return r.fail("adjoint permutation out of its buffer; launch refused");
+  const int blocks = (int)std::min<long>(4096, (total + 255) / 256);
+  k_gather4<<<blocks, 256, 0, r.st>>>(src, dst, n0, n1, n2, n3, s0, s1, s2, s3, alpha, acc ? 1 : 0);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+// dst (cols x rows) = src (rows x cols)^T
+int transpose(Run& r, const double* src, double* dst, long rows, long cols) {
+  return gather(r, src, dst, 1, 1, (int)cols, (int)rows, 0, 0, 1, cols);
+}
+
+int fill(Run& r, double* x, long n, double v) {
+  if (n <= 0) return 0;
+  if (!r.inside(x, (size_t)n * 8)) return r.fail("adjoint fill out of its buffer; launch refused");
+  k_fill<<<(int)std::min<long>(2048, (n + 255) / 256), 256, 0, r.st>>>(x, n, v);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int copy(Run& r, const double* src, double* dst, long n) {
+  if (!r.inside(src, (size_t)n * 8) || !r.inside(dst, (size_t)n * 8))
+    return r.fail("adjoint copy out of its buffer; refused");
+  CTM_HIP_TRY(hipMemcpyAsync(dst, src, (size_t)n * 8, hipMemcpyDeviceToDevice, r.st));
+  return 0;
+}
+
+#define VTRY(expr)              \
+  do {                          \
+    const int _r = (expr);      \
+    if (_r) return _r;          \
+  } while (0)
+
+inline int md(int i) { return ((i % 4) + 4) % 4; }
+
+// Corner index and orientation of application t of half h for side j
+// (sides 0..3: X of bond j; 4..7: Y^T of bond j-4).  X: M then M^T;
+// Y^T: M^T then M.  M X applies Ct[b+2], Ct[b+1], Ct[b], Ct[b-1] in turn.
+void app(int j, int h, int t, int* ci, int* trans) {
+  const int b = j & 3;
+  const bool x_side = j < 4;
+  const bool with_M = (h == 0) == x_side;
+  const int mseq[4] = {md(b + 2), md(b + 1), md(b), md(b - 1)};
+  const int tseq[4] = {md(b - 1), md(b), md(b + 1), md(b + 2)};
+  *ci = with_M ? mseq[t] : tseq[t];
+  *trans = with_M ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// forward with the tape
+// ---------------------------------------------------------------------------
+struct State {
+  const double* C[4];
+  const double* T[4];
+  const double* X[4];
+  const double* Yt[4];
+};
+
+int forward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in, double rtol) {
+  const int x = m.x, Dl = m.Dl, N = m.N, k = m.k;
+  // enlarged corners: CT = C T, W = T_(i-1) (C T), Ct = W ap_i
+  {
+    GemmBatch g = rowmajor(4, x, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = in.C[i];
+      g.B[i] = in.T[i];
+      g.C[i] = b.CT[i];
+    }
+    VTRY(gemm(r, g));
+  }
+  {
+    GemmBatch g = rowmajor(4, x * Dl, Dl * x, x, x, (long)Dl * x, 0);
+    g.cdiv_m = Dl;
+    g.cs_m1 = (long)x * Dl * Dl;
+    g.cs_m0 = Dl;
+    g.cdiv_n = x;
+    g.cs_n1 = 1;
+    g.cs_n0 = (long)Dl * Dl;
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = in.T[md(i - 1)];
+      g.B[i] = b.CT[i];
+      g.C[i] = b.Wc[i];
+    }
+    VTRY(gemm(r, g));
+  }
+  {
+    GemmBatch g = rowmajor(4, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
+    g.cdiv_m = x;
+    g.cs_m1 = (long)Dl * N;
+    g.cs_m0 = Dl;
+    g.cdiv_n = Dl;
+    g.cs_n1 = N;
+    g.cs_n0 = 1;
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Wc[i];
+      g.B[i] = v.ap[i];
+      g.C[i] = b.Ct[i];
+    }
+    VTRY(gemm(r, g));
+  }
+  // subspace steps of all 8 sides, every product and every Q on the tape
+  const double* cur[8];
+  for (int j = 0; j < 8; ++j) cur[j] = j < 4 ? in.X[j] : in.Yt[j - 4];
+  for (int s = 0; s < m.nsi; ++s) {
+    for (int h = 0; h < 2; ++h) {
+      const int base = (s * 2 + h) * 5;
+      for (int t = 0; t < 4; ++t) {
+        GemmBatch g = rowmajor(8, N, k, N, N, k, k);
+        for (int j = 0; j < 8; ++j) {
+          int ci, tr;
+          app(j, h, t, &ci, &tr);
+          g.A[j] = b.Ct[ci];
+          g.transA[j] = tr;
+          g.B[j] = t == 0 ? cur[j] : b.tape[j][base + t - 1];
+          g.C[j] = b.tape[j][base + t];
+        }
+        VTRY(gemm(r, g, true));
+      }
+      double* q[8];
+      for (int j = 0; j < 8; ++j) {
+        VTRY(copy(r, b.tape[j][base + 3], b.tape[j][base + 4], (long)N * k));
+        q[j] = b.tape[j][base + 4];
+      }
+      const int rc = launch_qr(8, q, N, k, b.qr_ws, r.st);
+      if (rc) return vjp_fail(r.c, rc == 1 ? CTM_E_ARG : rc, thread_error());
+      for (int j = 0; j < 8; ++j) cur[j] = q[j];
+    }
+  }
+  // A = Ct[b+1] (Ct[b+2] X),  B^T = Ct[b]^T (Ct[b-1]^T Y^T)
+  {
+    GemmBatch g = rowmajor(8, N, k, N, N, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Ct[md(i + 2)];
+      g.B[i] = cur[i];
+      g.C[i] = b.W1[i];
+      g.A[4 + i] = b.Ct[md(i - 1)];
+      g.transA[4 + i] = 1;
+      g.B[4 + i] = cur[4 + i];
+      g.C[4 + i] = b.W2[i];
+    }
+    VTRY(gemm(r, g, true));
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Ct[md(i + 1)];
+      g.B[i] = b.W1[i];
+      g.C[i] = b.Ab[i];
+      g.A[4 + i] = b.Ct[i];
+      g.B[4 + i] = b.W2[i];
+      g.C[4 + i] = b.Bt[i];
+    }
+    VTRY(gemm(r, g, true));
+  }
+  {
+    GemmBatch g = rowmajor(4, k, k, N, k, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Bt[i];
+      g.transA[i] = 1;
+      g.B[i] = b.Ab[i];
+      g.C[i] = b.rho[i];
+    }
+    VTRY(gemm(r, g));
+  }
+  {
+    const double* rho[4] = {b.rho[0], b.rho[1], b.rho[2], b.rho[3]};
+    const int rc = launch_svd(4, rho, b.u, b.s, b.v, k, b.svd_ws, r.st);
+    if (rc) return vjp_fail(r.c, rc == 1 ? CTM_E_ARG : rc, thread_error());
+  }
+  // signs from Y^T u (the sign rule), then the signed factors and s^-1/2
+  {
+    GemmBatch g = rowmajor(4, N, k, k, k, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = cur[4 + i];
+      g.B[i] = b.u[i];
+      g.C[i] = b.Hb[i];
+    }
+    VTRY(gemm(r, g));
+    SignArgs sa{};
+    sa.N = N;
+    sa.k = k;
+    sa.ld = k;
+    for (int i = 0; i < 4; ++i) {
+      sa.Y[i] = b.Hb[i];
+      sa.sg[i] = b.sg[i];
+    }
+    const int rc = elem_col_sign(sa, 4, r.st);
+    if (rc) return vjp_fail(r.c, rc == 1 ? CTM_E_ARG : rc, thread_error());
+    PrepArgs pa{};
+    for (int i = 0; i < 4; ++i) {
+      pa.u[i] = b.u[i];
+      pa.v[i] = b.v[i];
+      pa.s[i] = b.s[i];
+      pa.sg[i] = b.sg[i];
+      pa.us[i] = b.us[i];
+      pa.vs[i] = b.vs[i];
+      pa.sinv[i] = b.sinv[i];
+      pa.vsc[i] = b.vsc[i];
+      pa.usc[i] = b.usc[i];
+    }
+    pa.k = k;
+    pa.keep = x;
+    pa.rtol = rtol;
+    k_prep<<<dim3((k * k + 255) / 256, 4), 256, 0, r.st>>>(pa);
+    CTM_HIP_TRY(hipGetLastError());
+  }
+  // P_l = A v_s sinv, P_r^T = B^T u_s sinv
+  {
+    GemmBatch g = rowmajor(8, N, x, k, k, x, x);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Ab[i];
+      g.B[i] = b.vsc[i];
+      g.C[i] = b.Pl[i];
+      g.A[4 + i] = b.Bt[i];
+      g.B[4 + i] = b.usc[i];
+      g.C[4 + i] = b.Prt[i];
+    }
+    VTRY(gemm(r, g));
+  }
+  // renormalisation (unscaled), then the unit-norm outputs
+  {
+    GemmBatch g = rowmajor(4, N, x, N, N, x, x);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Ct[i];
+      g.B[i] = b.Pl[i];
+      g.C[i] = b.Zc[i];
+    }
+    VTRY(gemm(r, g));
+    GemmBatch g2 = rowmajor(4, x, x, N, x, x, x);
+    for (int i = 0; i < 4; ++i) {
+      g2.A[i] = b.Prt[md(i - 1)];
+      g2.transA[i] = 1;
+      g2.B[i] = b.Zc[i];
+      g2.C[i] = b.Ch[i];
+    }
+    VTRY(gemm(r, g2));
+  }
+  {
+    // Z1[(b,g'),(u,r)] = sum_g T_j[(b,u),g] P_l[(g,r),g']   (batched over r)
+    GemmBatch g = rowmajor(4, x * Dl, x, x, x, (long)Dl * x, 0);
+    g.cdiv_m = Dl;
+    g.cs_m1 = (long)x * Dl * Dl;
+    g.cs_m0 = Dl;
+    g.cdiv_n = 1 << 30;
+    g.cs_n1 = 0;
+    g.cs_n0 = (long)Dl * Dl;
+    g.nbatch = Dl;
+    g.a_bs = 0;
+    g.b_bs = x;
+    g.c_bs = 1;
+    for (int j = 0; j < 4; ++j) {
+      g.A[j] = in.T[j];
+      g.B[j] = b.Pl[j];
+      g.C[j] = b.Z1[j];
+    }
+    VTRY(gemm(r, g));
+    // Z2[(b,l),(d,g')] = Z1[(b,g'),(u,r)] ap_(j+1)[(u,r),(l,d)]
+    GemmBatch g2 = rowmajor(4, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
+    g2.cdiv_m = x;
+    g2.cs_m1 = (long)Dl * Dl * x;
+    g2.cs_m0 = 1;
+    g2.cdiv_n = Dl;
+    g2.cs_n1 = (long)Dl * x;
+    g2.cs_n0 = x;
+    for (int j = 0; j < 4; ++j) {
+      g2.A[j] = b.Z1[j];
+      g2.B[j] = v.ap[md(j + 1)];
+      g2.C[j] = b.Z2[j];
+    }
+    VTRY(gemm(r, g2));
+    // T'[b',(d,g')] = sum_(b,l) P_r^T[(b,l),b'] Z2[(b,l),(d,g')]
+    GemmBatch g3 = rowmajor(4, x, Dl * x, x * Dl, x, (long)Dl * x, (long)Dl * x);
+    for (int j = 0; j < 4; ++j) {
+      g3.A[j] = b.Prt[j];
+      g3.transA[j] = 1;
+      g3.B[j] = b.Z2[j];
+      g3.C[j] = b.Th[j];
+    }
+    VTRY(gemm(r, g3));
+  }
+  {
+    NormArgs na{};
+    for (int i = 0; i < 4; ++i) {
+      na.x[i] = b.Ch[i];
+      na.n[i] = (long)x * x;
+      na.x[4 + i] = b.Th[i];
+      na.n[4 + i] = (long)x * Dl * x;
+    }
+    na.out = b.nrm;
+    na.bad = nullptr;
+    DotArgs da{};
+    for (int t = 0; t < 8; ++t) {
+      da.x[t] = na.x[t];
+      da.y[t] = na.x[t];
+      da.n[t] = na.n[t];
+    }
+    da.out = b.dots;   // squared norms; the square roots are taken below
+    k_dots<<<8, 256, 0, r.st>>>(da);
+    CTM_HIP_TRY(hipGetLastError());
+  }
+  return 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// kernels that need the forward norms: sqrt of the squared norms, then scale
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void k_sqrt8(const double* sq, double* nrm) {
+  if (threadIdx.x < 8) nrm[threadIdx.x] = sqrt(sq[threadIdx.x]);
+}
+
+struct ScaleArgs {
+  const double* x[8];
+  double* y[8];
+  long n[8];
+  const double* nrm;
+};
+
+__global__ __launch_bounds__(256) void k_scale_out(ScaleArgs a) {
+  const int t = blockIdx.y;
+  const double inv = 1.0 / a.nrm[t];
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < a.n[t]; i += (long)gridDim.x * 256)
+    a.y[t][i] = a.x[t][i] * inv;
+}
+
+// inverse strides of a corner permutation: ab[u,l,d,r] gathers from apb
+void inverse_strides(const long s[4], long Dl, long out[4]) {
+  const long pw[4] = {Dl * Dl * Dl, Dl * Dl, Dl, 1};
+  for (int p = 0; p < 4; ++p)
+    for (int j = 0; j < 4; ++j)
+      if (s[j] == pw[p]) out[p] = pw[j];
+}
+
+int backward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in,
+             const State& bar, double* const* Cb_out, double* const* Tb_out,
+             double* const* Xb_out, double* const* Yb_out, double* site_bar) {
+  const int x = m.x, Dl = m.Dl, N = m.N, k = m.k;
+  const long NN = (long)N * N, Nk = (long)N * k;
+  for (int i = 0; i < 4; ++i) {
+    VTRY(fill(r, b.Ctb[i], NN, 0.0));
+    VTRY(fill(r, b.Plb[i], (long)N * x, 0.0));
+    VTRY(fill(r, b.Prtb[i], (long)N * x, 0.0));
+    VTRY(fill(r, Tb_out[i], (long)x * Dl * x, 0.0));
+  }
+  VTRY(fill(r, b.ab, (long)Dl * Dl * Dl * Dl, 0.0));
+  for (int i = 0; i < 4; ++i) VTRY(transpose(r, v.ap[i], b.apT[i], (long)Dl * Dl, (long)Dl * Dl));
+  // unit-norm scaling
+  {
+    DotArgs da{};
+    NormBwdArgs nb{};
+    for (int i = 0; i < 4; ++i) {
+      da.x[i] = b.Cn[i];
+      da.y[i] = bar.C[i];
+      da.n[i] = (long)x * x;
+      da.x[4 + i] = b.Tn[i];
+      da.y[4 + i] = bar.T[i];
+      da.n[4 + i] = (long)x * Dl * x;
+    }
+    da.out = b.dots;
+    k_dots<<<8, 256, 0, r.st>>>(da);
+    CTM_HIP_TRY(hipGetLastError());
+    for (int t = 0; t < 8; ++t) {
+      nb.y[t] = da.x[t];
+      nb.yb[t] = da.y[t];
+      nb.n[t] = da.n[t];
+      nb.xb[t] = t < 4 ? b.Chb[t] : b.Thb[t - 4];
+    }
+    nb.dot = b.dots;
+    nb.nrm = b.nrm;
+    const long mx = (long)x * Dl * x;
+    k_norm_bwd<<<dim3((int)std::min<long>(512, (mx + 255) / 256), 8), 256, 0, r.st>>>(nb);
+    CTM_HIP_TRY(hipGetLastError());
+  }
+  // C_i' = P_r^(i-1)T Zc_i, Zc_i = Ct_i P_l^(i)
+  for (int i = 0; i < 4; ++i) {
+    const int ip = md(i - 1);
+    VTRY(transpose(r, b.Chb[i], b.smallT, x, x));
+    GemmBatch g = rowmajor(1, N, x, x, x, x, x);
+    g.A[0] = b.Zc[i];
+    g.B[0] = b.smallT;
+    g.C[0] = b.Prtb[ip];
+    g.accumulate = 1;
+    VTRY(gemm(r, g));
+    GemmBatch g2 = rowmajor(1, N, x, x, x, x, x);
+    g2.A[0] = b.Prt[ip];
+    g2.B[0] = b.Chb[i];
+    g2.C[0] = b.Zcb;
+    VTRY(gemm(r, g2));
+    VTRY(transpose(r, b.Pl[i], b.St, N, x));
+    GemmBatch g3 = rowmajor(1, N, N, x, x, N, N);
+    g3.A[0] = b.Zcb;
+    g3.B[0] = b.St;
+    g3.C[0] = b.Ctb[i];
+    g3.accumulate = 1;
+    VTRY(gemm(r, g3));
+    GemmBatch g4 = rowmajor(1, N, x, N, N, x, x);
+    g4.A[0] = b.Ct[i];
+    g4.transA[0] = 1;
+    g4.B[0] = b.Zcb;
+    g4.C[0] = b.Plb[i];
+    g4.accumulate = 1;
+    VTRY(gemm(r, g4));
+  }
+  // T_j' = P_r^T Z2,  Z2 = perm(Z1 ap_(j+1)),  Z1 = T_j P_l
+  for (int j = 0; j < 4; ++j) {
+    const int jn = md(j + 1);
+    VTRY(transpose(r, b.Thb[j], b.St, x, (long)Dl * x));
+    GemmBatch g = rowmajor(1, N, x, Dl * x, (long)Dl * x, x, x);
+    g.A[0] = b.Z2[j];
+    g.B[0] = b.St;
+    g.C[0] = b.Prtb[j];
+    g.accumulate = 1;
+    VTRY(gemm(r, g));
+    GemmBatch g2 = rowmajor(1, N, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
+    g2.A[0] = b.Prt[j];
+    g2.B[0] = b.Thb[j];
+    g2.C[0] = b.Sa;                                   // Z2_bar [(b,l)][(d,g')]
+    VTRY(gemm(r, g2));
+    VTRY(gather(r, b.Sa, b.Sb, x, x, Dl, Dl, (long)Dl * Dl * x, 1, (long)Dl * x, x));  // [(b,g')][(l,d)]
+    GemmBatch g3 = rowmajor(1, Dl * Dl, Dl * Dl, x * x, (long)Dl * Dl, (long)Dl * Dl, (long)Dl * Dl);
+    g3.A[0] = b.Z1[j];
+    g3.transA[0] = 1;
+    g3.B[0] = b.Sb;
+    g3.C[0] = b.apb;
+    VTRY(gemm(r, g3));
+    long inv[4];
+    inverse_strides(v.ap_strides[jn], Dl, inv);
+    VTRY(gather(r, b.apb, b.ab, Dl, Dl, Dl, Dl, inv[0], inv[1], inv[2], inv[3], true));
+    GemmBatch g4 = rowmajor(1, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, (long)Dl * Dl);
+    g4.A[0] = b.Sb;
+    g4.B[0] = b.apT[jn];
+    g4.C[0] = b.Sa;                                   // Z1_bar [(b,g')][(u,r)]
+    VTRY(gemm(r, g4));
+    VTRY(gather(r, b.Sa, b.Sb, x, Dl, Dl, x, (long)x * Dl * Dl, Dl, 1, (long)Dl * Dl));  // [(b,u)][(r,g')]
+    VTRY(transpose(r, b.Pl[j], b.St, x, (long)Dl * x));
+    GemmBatch g5 = rowmajor(1, x * Dl, x, Dl * x, (long)Dl * x, x, x);
+    g5.A[0] = b.Sb;
+    g5.B[0] = b.St;
+    g5.C[0] = Tb_out[j];
+    g5.accumulate = 1;
+    VTRY(gemm(r, g5));
+    GemmBatch g6 = rowmajor(1, x, Dl * x, x * Dl, x, (long)Dl * x, (long)Dl * x);
+    g6.A[0] = in.T[j];
+    g6.transA[0] = 1;
+    g6.B[0] = b.Sb;
+    g6.C[0] = b.Plb[j];
+    g6.accumulate = 1;
+    VTRY(gemm(r, g6));
+  }
+  // projectors, recycled blocks, rho and its SVD, per bond (batched over 4)
+  double* Xf[4];
+  double* Yf[4];
+  for (int i = 0; i < 4; ++i) {
+    Xf[i] = m.nsi > 0 ? b.tape[i][10 * m.nsi - 1] : (double*)in.X[i];
+    Yf[i] = m.nsi > 0 ? b.tape[4 + i][10 * m.nsi - 1] : (double*)in.Yt[i];
+  }
+  for (int i = 0; i < 4; ++i) {
+    VTRY(transpose(r, b.vsc[i], b.vscT[i], k, x));
+    VTRY(transpose(r, b.usc[i], b.uscT[i], k, x));
+    VTRY(transpose(r, b.vs[i], b.vsT[i], k, k));
+    VTRY(transpose(r, b.us[i], b.usT[i], k, k));
+  }
+  {
+    // A_bar = P_l_bar vsc^T -> Hb[i];  B^T_bar = P_rT_bar usc^T -> Hb[4+i]
+    GemmBatch g = rowmajor(8, N, k, x, x, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Plb[i];
+      g.B[i] = b.vscT[i];
+      g.C[i] = b.Hb[i];
+      g.A[4 + i] = b.Prtb[i];
+      g.B[4 + i] = b.uscT[i];
+      g.C[4 + i] = b.Hb[4 + i];
+    }
+    VTRY(gemm(r, g));
+    GemmBatch g2 = rowmajor(8, k, x, N, k, x, x);
+    for (int i = 0; i < 4; ++i) {
+      g2.A[i] = b.Ab[i];
+      g2.transA[i] = 1;
+      g2.B[i] = b.Plb[i];
+      g2.C[i] = b.vscb[i];
+      g2.A[4 + i] = b.Bt[i];
+      g2.transA[4 + i] = 1;
+      g2.B[4 + i] = b.Prtb[i];
+      g2.C[4 + i] = b.uscb[i];
+    }
+    VTRY(gemm(r, g2));
+    // recycled blocks X' = Xf v_s, Y^T' = Yf u_s
+    GemmBatch g3 = rowmajor(8, N, k, k, k, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g3.A[i] = bar.X[i];
+      g3.B[i] = b.vsT[i];
+      g3.C[i] = b.Qb[i];
+      g3.A[4 + i] = bar.Yt[i];
+      g3.B[4 + i] = b.usT[i];
+      g3.C[4 + i] = b.Qb[4 + i];
+    }
+    VTRY(gemm(r, g3));
+    GemmBatch g4 = rowmajor(8, k, k, N, k, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g4.A[i] = Xf[i];
+      g4.transA[i] = 1;
+      g4.B[i] = bar.X[i];
+      g4.C[i] = b.vb[i];
+      g4.A[4 + i] = Yf[i];
+      g4.transA[4 + i] = 1;
+      g4.B[4 + i] = bar.Yt[i];
+      g4.C[4 + i] = b.ub[i];
+    }
+    VTRY(gemm(r, g4));
+  }
+  {
+    ProjBwdArgs pb{};
+    KmatArgs ka{};
+    for (int i = 0; i < 4; ++i) {
+      pb.us[i] = b.us[i];
+      pb.vs[i] = b.vs[i];
+      pb.sinv[i] = b.sinv[i];
+      pb.vscb[i] = b.vscb[i];
+      pb.uscb[i] = b.uscb[i];
+      pb.ub[i] = b.ub[i];
+      pb.vb[i] = b.vb[i];
+      pb.sb[i] = b.sb[i];
+    }
+    pb.k = k;
+    pb.keep = x;
+    k_proj_bwd<<<4, 256, 0, r.st>>>(pb);
+    CTM_HIP_TRY(hipGetLastError());
+    GemmBatch g = rowmajor(8, k, k, k, k, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.us[i];
+      g.transA[i] = 1;
+      g.B[i] = b.ub[i];
+      g.C[i] = b.Ju[i];
+      g.A[4 + i] = b.vs[i];
+      g.transA[4 + i] = 1;
+      g.B[4 + i] = b.vb[i];
+      g.C[4 + i] = b.Jv[i];
+    }
+    VTRY(gemm(r, g));
+    for (int i = 0; i < 4; ++i) {
+      ka.Ju[i] = b.Ju[i];
+      ka.Jv[i] = b.Jv[i];
+      ka.s[i] = b.s[i];
+      ka.sb[i] = b.sb[i];
+      ka.K[i] = b.Km[i];
+    }
+    ka.n = k;
+    k_svd_kmat<<<dim3((k * k + 255) / 256, 4), 256, 0, r.st>>>(ka);
+    CTM_HIP_TRY(hipGetLastError());
+    GemmBatch g2 = rowmajor(4, k, k, k, k, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g2.A[i] = b.us[i];
+      g2.B[i] = b.Km[i];
+      g2.C[i] = b.uK[i];
+    }
+    VTRY(gemm(r, g2));
+    for (int i = 0; i < 4; ++i) {
+      g2.A[i] = b.uK[i];
+      g2.B[i] = b.vsT[i];
+      g2.C[i] = b.rhob[i];
+    }
+    VTRY(gemm(r, g2));
+    for (int i = 0; i < 4; ++i) VTRY(transpose(r, b.rhob[i], b.rhobT[i], k, k));
+    // rho = B A:  A_bar += B^T rho_bar,  B^T_bar += A rho_bar^T
+    GemmBatch g3 = rowmajor(8, N, k, k, k, k, k);
+    g3.accumulate = 1;
+    for (int i = 0; i < 4; ++i) {
+      g3.A[i] = b.Bt[i];
+      g3.B[i] = b.rhob[i];
+      g3.C[i] = b.Hb[i];
+      g3.A[4 + i] = b.Ab[i];
+      g3.B[4 + i] = b.rhobT[i];
+      g3.C[4 + i] = b.Hb[4 + i];
+    }
+    VTRY(gemm(r, g3));
+  }
+  // A = Ct[b+1] W1, W1 = Ct[b+2] Xf;  B^T = Ct[b]^T W2, W2 = Ct[b-1]^T Yf
+  {
+    // rank-k terms of the outer applications (A and B^T)
+    for (int i = 0; i < 4; ++i) VTRY(transpose(r, b.W1[i], b.tr[i], N, k));
+    for (int i = 0; i < 4; ++i) VTRY(transpose(r, b.Hb[4 + i], b.tr[4 + i], N, k));
+    GemmBatch g = rowmajor(4, N, N, k, k, N, N);
+    g.accumulate = 1;
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Hb[i];
+      g.B[i] = b.tr[i];
+      g.C[i] = b.Ctb[md(i + 1)];
+    }
+    VTRY(gemm(r, g));
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.W2[i];
+      g.B[i] = b.tr[4 + i];
+      g.C[i] = b.Ctb[i];
+    }
+    VTRY(gemm(r, g));
+    // W1_bar = Ct[b+1]^T A_bar,  W2_bar = Ct[b] B^T_bar
+    GemmBatch g2 = rowmajor(8, N, k, N, N, k, k);
+    for (int i = 0; i < 4; ++i) {
+      g2.A[i] = b.Ct[md(i + 1)];
+      g2.transA[i] = 1;
+      g2.B[i] = b.Hb[i];
+      g2.C[i] = b.Yq[i];
+      g2.A[4 + i] = b.Ct[i];
+      g2.B[4 + i] = b.Hb[4 + i];
+      g2.C[4 + i] = b.Yq[4 + i];
+    }
+    VTRY(gemm(r, g2, true));
+    for (int i = 0; i < 4; ++i) VTRY(transpose(r, Xf[i], b.tr[i], N, k));
+    for (int i = 0; i < 4; ++i) VTRY(transpose(r, b.Yq[4 + i], b.tr[4 + i], N, k));
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Yq[i];
+      g.B[i] = b.tr[i];
+      g.C[i] = b.Ctb[md(i + 2)];
+    }
+    VTRY(gemm(r, g));
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = Yf[i];
+      g.B[i] = b.tr[4 + i];
+      g.C[i] = b.Ctb[md(i - 1)];
+    }
+    VTRY(gemm(r, g));
+    // Xf_bar += Ct[b+2]^T W1_bar,  Yf_bar += Ct[b-1] W2_bar
+    GemmBatch g3 = rowmajor(8, N, k, N, N, k, k);
+    g3.accumulate = 1;
+    for (int i = 0; i < 4; ++i) {
+      g3.A[i] = b.Ct[md(i + 2)];
+      g3.transA[i] = 1;
+      g3.B[i] = b.Yq[i];
+      g3.C[i] = b.Qb[i];
+      g3.A[4 + i] = b.Ct[md(i - 1)];
+      g3.B[4 + i] = b.Yq[4 + i];
+      g3.C[4 + i] = b.Qb[4 + i];
+    }
+    VTRY(gemm(r, g3, true));
+  }
+  // subspace steps in reverse: QR adjoint, then the four applications
+  for (int s = m.nsi - 1; s >= 0; --s) {
+    for (int h = 1; h >= 0; --h) {
+      const int base = (s * 2 + h) * 5;
+      // R = Q^T H, M = -Q_bar^T Q, Y = Q_bar + Q copyltu(M), H_bar = Y R^-T
+      GemmBatch g = rowmajor(8, k, k, N, k, k, k);
+      for (int j = 0; j < 8; ++j) {
+        g.A[j] = b.tape[j][base + 4];
+        g.transA[j] = 1;
+        g.B[j] = b.tape[j][base + 3];
+        g.C[j] = b.R[j];
+      }
+      VTRY(gemm(r, g));
+      GemmBatch gm = rowmajor(8, k, k, N, k, k, k);
+      gm.alpha = -1.0;
+      for (int j = 0; j < 8; ++j) {
+        gm.A[j] = b.Qb[j];
+        gm.transA[j] = 1;
+        gm.B[j] = b.tape[j][base + 4];
+        gm.C[j] = b.Mm[j];
+      }
+      VTRY(gemm(r, gm));
+      SmallArgs sa{};
+      for (int j = 0; j < 8; ++j) {
+        sa.in[j] = b.Mm[j];
+        sa.out[j] = b.Mc[j];
+      }
+      sa.n = k;
+      k_copyltu<<<dim3((k * k + 255) / 256, 8), 256, 0, r.st>>>(sa);
+      CTM_HIP_TRY(hipGetLastError());
+      for (int j = 0; j < 8; ++j) {
+        sa.in[j] = b.R[j];
+        sa.out[j] = b.Rinv[j];
+      }
+      k_tri_inv<<<8, 256, 0, r.st>>>(sa);
+      CTM_HIP_TRY(hipGetLastError());
+      for (int j = 0; j < 8; ++j) {
+        VTRY(transpose(r, b.Rinv[j], b.RinvT[j], k, k));
+        VTRY(copy(r, b.Qb[j], b.Yq[j], Nk));
+      }
+      GemmBatch gy = rowmajor(8, N, k, k, k, k, k);
+      gy.accumulate = 1;
+      for (int j = 0; j < 8; ++j) {
+        gy.A[j] = b.tape[j][base + 4];
+        gy.B[j] = b.Mc[j];
+        gy.C[j] = b.Yq[j];
+      }
+      VTRY(gemm(r, gy));
+      for (int j = 0; j < 8; ++j) {
+        gy.A[j] = b.Yq[j];
+        gy.B[j] = b.RinvT[j];
+        gy.C[j] = b.Hb[j];
+      }
+      gy.accumulate = 0;
+      VTRY(gemm(r, gy));
+      // applications t = 3 .. 0
+      for (int t = 3; t >= 0; --t) {
+        const double* hin[8];
+        int ci[8], trn[8];
+        for (int j = 0; j < 8; ++j) {
+          app(j, h, t, &ci[j], &trn[j]);
+          if (t > 0) {
+            hin[j] = b.tape[j][base + t - 1];
+          } else if (h == 1) {
+            hin[j] = b.tape[j][base - 1];            // Q of the first half
+          } else if (s > 0) {
+            hin[j] = b.tape[j][base - 1];            // Q of the previous step
+          } else {
+            hin[j] = j < 4 ? in.X[j] : in.Yt[j - 4];
+          }
+        }
+        // corner cotangents: plain H_out = Ct H_in gives Ct_bar += H_bar H_in^T;
+        // transposed H_out = Ct^T H_in gives Ct_bar += H_in H_bar^T
+        for (int j = 0; j < 8; ++j)
+          VTRY(transpose(r, trn[j] ? b.Hb[j] : hin[j], b.tr[j], N, k));
+        for (int half = 0; half < 2; ++half) {
+          GemmBatch gc = rowmajor(4, N, N, k, k, N, N);
+          gc.accumulate = 1;
+          for (int q = 0; q < 4; ++q) {
+            const int j = half * 4 + q;
+            gc.A[q] = trn[j] ? hin[j] : b.Hb[j];
+            gc.B[q] = b.tr[j];
+            gc.C[q] = b.Ctb[ci[j]];
+          }
+          VTRY(gemm(r, gc));
+        }
+        GemmBatch gb = rowmajor(8, N, k, N, N, k, k);
+        for (int j = 0; j < 8; ++j) {
+          gb.A[j] = b.Ct[ci[j]];
+          gb.transA[j] = trn[j] ? 0 : 1;
+          gb.B[j] = b.Hb[j];
+          gb.C[j] = b.Yq[j];
+        }
+        VTRY(gemm(r, gb, true));
+        for (int j = 0; j < 8; ++j) std::swap(b.Hb[j], b.Yq[j]);
+      }
+      for (int j = 0; j < 8; ++j) std::swap(b.Qb[j], b.Hb[j]);
+    }
+  }
+  for (int i = 0; i < 4; ++i) {
+    VTRY(copy(r, b.Qb[i], Xb_out[i], Nk));
+    VTRY(copy(r, b.Qb[4 + i], Yb_out[i], Nk));
+  }
+  // enlarged corners
+  for (int i = 0; i < 4; ++i) {
+    const int ip = md(i - 1);
+    // Gp[(x_in,y),(o1,o2)] from Ct_bar[(x_in,o1),(y,o2)]
+    VTRY(gather(r, b.Ctb[i], b.Sa, x, x, Dl, Dl, (long)Dl * N, Dl, N, 1));
+    GemmBatch g = rowmajor(1, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, (long)Dl * Dl);
+    g.A[0] = b.Sa;
+    g.B[0] = b.apT[i];
+    g.C[0] = b.Sb;                                     // W_bar [(x_in,y)][(p,q)]
+    VTRY(gemm(r, g));
+    GemmBatch g2 = rowmajor(1, Dl * Dl, Dl * Dl, x * x, (long)Dl * Dl, (long)Dl * Dl, (long)Dl * Dl);
+    g2.A[0] = b.Wc[i];
+    g2.transA[0] = 1;
+    g2.B[0] = b.Sa;
+    g2.C[0] = b.apb;
+    VTRY(gemm(r, g2));
+    long inv[4];
+    inverse_strides(v.ap_strides[i], Dl, inv);
+    VTRY(gather(r, b.apb, b.ab, Dl, Dl, Dl, Dl, inv[0], inv[1], inv[2], inv[3], true));
+    // Wbp[(x_in,p),(q,y)] from W_bar[(x_in,y),(p,q)]
+    VTRY(gather(r, b.Sb, b.Sa, x, Dl, Dl, x, (long)x * Dl * Dl, Dl, 1, (long)Dl * Dl));
+    VTRY(transpose(r, b.CT[i], b.St, x, (long)Dl * x));
+    GemmBatch g3 = rowmajor(1, x * Dl, x, Dl * x, (long)Dl * x, x, x);
+    g3.A[0] = b.Sa;
+    g3.B[0] = b.St;
+    g3.C[0] = Tb_out[ip];
+    g3.accumulate = 1;
+    VTRY(gemm(r, g3));
+    GemmBatch g4 = rowmajor(1, x, Dl * x, x * Dl, x, (long)Dl * x, (long)Dl * x);
+    g4.A[0] = in.T[ip];
+    g4.transA[0] = 1;
+    g4.B[0] = b.Sa;
+    g4.C[0] = b.Sb;                                    // CT_bar [a][(q,y)]
+    VTRY(gemm(r, g4));
+    VTRY(transpose(r, in.T[i], b.St, x, (long)Dl * x));
+    GemmBatch g5 = rowmajor(1, x, x, Dl * x, (long)Dl * x, x, x);
+    g5.A[0] = b.Sb;
+    g5.B[0] = b.St;
+    g5.C[0] = Cb_out[i];
+    VTRY(gemm(r, g5));
+    GemmBatch g6 = rowmajor(1, x, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
+    g6.A[0] = in.C[i];
+    g6.transA[0] = 1;
+    g6.B[0] = b.Sb;
+    g6.C[0] = Tb_out[i];
+    g6.accumulate = 1;
+    VTRY(gemm(r, g6));
+  }
+  // double layer: A_bar[s, ket] += sum_bra (ab[ket,bra] + ab[bra,ket]) A[s, bra]
+  if (site_bar) {
+    const long D4 = (long)m.D * m.D * m.D * m.D;
+    if (!r.inside(b.msym, (size_t)D4 * D4 * 8)) return r.fail("adjoint buffer too small");
+    k_dl_sym<<<(int)std::min<long>(4096, (D4 * D4 + 255) / 256), 256, 0, r.st>>>(b.ab, b.msym, m.D);
+    CTM_HIP_TRY(hipGetLastError());
+    GemmBatch g = rowmajor(1, m.d, (int)D4, (int)D4, D4, D4, D4);
+    g.A[0] = v.A_site;
+    g.B[0] = b.msym;
+    g.C[0] = site_bar;
+    g.accumulate = 1;
+    VTRY(gemm(r, g));
+  }
+  return 0;
+}
+
+Dims dims_of(const ctm_config& cfg) {
+  Dims m{};
+  m.d = cfg.d;
+  m.D = cfg.D;
+  m.Dl = cfg.d > 0 ? cfg.D * cfg.D : cfg.D;
+  m.x = cfg.chi;
+  m.N = m.x * m.Dl;
+  m.k = std::min(cfg.chi + cfg.p, m.N);
+  m.nsi = cfg.n_si;
+  return m;
+}
+
+int check_cfg(const ctm_config* cfg) {
+  if (!cfg) return CTM_E_ARG;
+  size_t ws = 0;
+  const ctm_status st = ctm_workspace_bytes(cfg, &ws);
+  if (st != CTM_OK) return st;
+  if (cfg->d < 1 || cfg->proj != CTM_PROJ_SI || cfg->prec != CTM_PREC_F64 || cfg->stabilized != 1 ||
+      cfg->sym != CTM_SYM_NONE)
+    return CTM_E_ARG;
+  return CTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctm_status ctm_vjp_workspace_bytes(const ctm_config* cfg, size_t* bytes) {
+  if (!bytes) return CTM_E_ARG;
+  const int rc = check_cfg(cfg);
+  if (rc) {
+    set_thread_error("the adjoint needs an iPEPS site (d >= 1), SI projectors, float64 "
+                     "contractions, the stabilised update and no lattice symmetry");
+    return (ctm_status)rc;
+  }
+  Bufs b;
+  *bytes = carve(dims_of(*cfg), &b, nullptr, nullptr);
+  return CTM_OK;
+}
+
+ctm_status ctm_move_vjp(ctm_ctx* ctx, const double* state_in, const double* state_out_bar,
+                        double* state_in_bar, double* state_out, double* site_bar, void* ws,
+                        size_t ws_bytes) {
+  if (!ctx || !state_in || !state_out_bar || !state_in_bar || !ws) {
+    set_thread_error("null argument");
+    return CTM_E_ARG;
+  }
+  VjpView v;
+  const int rv = vjp_view(ctx, &v);
+  if (rv) return (ctm_status)rv;
+  if (check_cfg(&v.cfg))
+    return (ctm_status)vjp_fail(ctx, CTM_E_ARG,
+                                "the adjoint needs an iPEPS site (d >= 1), SI projectors, float64 "
+                                "contractions, the stabilised update and no lattice symmetry");
+  const Dims m = dims_of(v.cfg);
+  Bufs b;
+  const size_t need = carve(m, &b, nullptr, nullptr);
+  if (ws_bytes < need)
+    return (ctm_status)vjp_fail(ctx, CTM_E_ARG, "adjoint workspace too small (need " +
+                                                    std::to_string(need) + " bytes)");
+  Run r;
+  r.c = ctx;
+  r.st = v.st;
+  const size_t x = m.x, Dl = m.Dl, N = m.N, k = m.k;
+  const size_t nstate = 4 * x * x + 4 * x * Dl * x + 8 * N * k + 4;
+  {
+    // the chi_env entry of the input state must be chi (SI moves only)
+    double chi_env = 0.0;
+    if (hipMemcpyAsync(&chi_env, state_in + (nstate - 4), sizeof(double), hipMemcpyDeviceToHost,
+                       v.st) != hipSuccess ||
+        hipStreamSynchronize(v.st) != hipSuccess)
+      return (ctm_status)vjp_fail(ctx, CTM_E_DEVICE, "reading chi_env of the input state failed");
+    if ((int)chi_env != m.x)
+      return (ctm_status)vjp_fail(ctx, CTM_E_STATE,
+                                  "the adjoint is defined for SI moves: the input state needs chi_env == chi");
+  }
+  carve(m, &b, (char*)ws, &r.reg);
+  const size_t D4 = (size_t)m.D * m.D * m.D * m.D;
+  r.reg.push_back({(uintptr_t)state_in, (uintptr_t)(state_in + nstate)});
+  r.reg.push_back({(uintptr_t)state_out_bar, (uintptr_t)(state_out_bar + nstate)});
+  r.reg.push_back({(uintptr_t)state_in_bar, (uintptr_t)(state_in_bar + nstate)});
+  if (state_out) r.reg.push_back({(uintptr_t)state_out, (uintptr_t)(state_out + nstate)});
+  if (site_bar) r.reg.push_back({(uintptr_t)site_bar, (uintptr_t)(site_bar + m.d * D4)});
+  r.reg.push_back({(uintptr_t)v.A_site, (uintptr_t)(v.A_site + m.d * D4)});
+  r.reg.push_back({(uintptr_t)v.a, (uintptr_t)(v.a + Dl * Dl * Dl * Dl)});
+  for (int i = 0; i < 4; ++i) r.reg.push_back({(uintptr_t)v.ap[i], (uintptr_t)(v.ap[i] + Dl * Dl * Dl * Dl)});
+
+  auto unpack = [&](const double* base, State& s) {
+    const double* p = base;
+    for (int i = 0; i < 4; ++i, p += x * x) s.C[i] = p;
+    for (int i = 0; i < 4; ++i, p += x * Dl * x) s.T[i] = p;
+    for (int i = 0; i < 4; ++i, p += N * k) s.X[i] = p;
+    for (int i = 0; i < 4; ++i, p += N * k) s.Yt[i] = p;
+  };
+  State in{}, bar{};
+  unpack(state_in, in);
+  unpack(state_out_bar, bar);
+  double *Cb[4], *Tb[4], *Xb[4], *Yb[4];
+  {
+    double* p = state_in_bar;
+    for (int i = 0; i < 4; ++i, p += x * x) Cb[i] = p;
+    for (int i = 0; i < 4; ++i, p += x * Dl * x) Tb[i] = p;
+    for (int i = 0; i < 4; ++i, p += N * k) Xb[i] = p;
+    for (int i = 0; i < 4; ++i, p += N * k) Yb[i] = p;
+    const int rz = fill(r, p, 4, 0.0);
+    if (rz) return (ctm_status)rz;
+  }
+  int rc = forward(r, v, m, b, in, v.cfg.pinv_rtol);
+  if (!rc) {
+    k_sqrt8<<<1, 64, 0, r.st>>>(b.dots, b.nrm);
+    ScaleArgs sa{};
+    for (int i = 0; i < 4; ++i) {
+      sa.x[i] = b.Ch[i];
+      sa.y[i] = b.Cn[i];
+      sa.n[i] = (long)x * x;
+      sa.x[4 + i] = b.Th[i];
+      sa.y[4 + i] = b.Tn[i];
+      sa.n[4 + i] = (long)x * Dl * x;
+    }
+    sa.nrm = b.nrm;
+    k_scale_out<<<dim3((int)std::min<size_t>(512, (x * Dl * x + 255) / 256), 8), 256, 0, r.st>>>(sa);
+    if (hipGetLastError() != hipSuccess) rc = vjp_fail(ctx, CTM_E_DEVICE, "scaling launch failed");
+  }
+  if (!rc && state_out) {
+    State o{};
+    unpack(state_out, o);
+    for (int i = 0; i < 4 && !rc; ++i) {
+      rc = copy(r, b.Cn[i], (double*)o.C[i], (long)x * x);
+      if (!rc) rc = copy(r, b.Tn[i], (double*)o.T[i], (long)x * Dl * x);
+    }
+    // recycled blocks X' = Xf v_s, Y^T' = Yf u_s
+    if (!rc) {
+      GemmBatch g = rowmajor(8, (int)N, (int)k, (int)k, k, k, k);
+      for (int i = 0; i < 4; ++i) {
+        g.A[i] = m.nsi > 0 ? b.tape[i][10 * m.nsi - 1] : in.X[i];
+        g.B[i] = b.vs[i];
+        g.C[i] = (double*)o.X[i];
+        g.A[4 + i] = m.nsi > 0 ? b.tape[4 + i][10 * m.nsi - 1] : in.Yt[i];
+        g.B[4 + i] = b.us[i];
+        g.C[4 + i] = (double*)o.Yt[i];
+      }
+      rc = gemm(r, g);
+    }
+    if (!rc) rc = copy(r, state_in + (nstate - 4), state_out + (nstate - 4), 4);
+  }
+  if (!rc) rc = backward(r, v, m, b, in, bar, Cb, Tb, Xb, Yb, site_bar);
+  if (rc) return (ctm_status)rc;
+  if (hipStreamSynchronize(v.st) != hipSuccess)
+    return (ctm_status)vjp_fail(ctx, CTM_E_DEVICE, "synchronisation failed");
+  return CTM_OK;
+}
+
+}  // extern "C"
