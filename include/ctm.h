@@ -322,6 +322,25 @@ ctm_status ctm_move_vjp(ctm_ctx* ctx, const double* state_in, const double* stat
                         double* state_in_bar, double* state_out, double* site_bar, void* ws,
                         size_t ws_bytes);
 
+/* Gradient at a fixed point (Differentiable fixed point passage, eq.
+ * implicit): for a converged state x* = F(x*, A) and the cotangent g of an
+ * objective's dependence on x*, sums the Neumann series
+ *     x_bar    = sum_n (J_x^T)^n g,
+ *     site_bar += sum_n J_A^T (J_x^T)^n g      (= J_A^T [I - J_x^T]^-1 g)
+ * by repeated reverse passes of the move at x* (its forward move is
+ * recomputed once), until |(J_x^T)^n g| <= tol |g| or max_iter passes.
+ *  state_star  converged state (device, state layout);
+ *  g_bar       cotangent g (device, state layout; counters ignored);
+ *  x_bar       the summed cotangent (device, state layout), or NULL;
+ *  site_bar    d*D^4, accumulated (+=);
+ *  iters, rel_norm  passes made and the final |(J_x^T)^n g| / |g| (may be NULL).
+ * Returns CTM_E_NOT_CONVERGED (with the partial sums written) when max_iter
+ * passes do not reach tol; the series converges when the move is a
+ * contraction at x*. */
+ctm_status ctm_fixed_point_vjp(ctm_ctx* ctx, const double* state_star, const double* g_bar,
+                               double tol, int max_iter, double* x_bar, double* site_bar,
+                               void* ws, size_t ws_bytes, int* iters, double* rel_norm);
+
 /* ---------------------------------------------------------------------------
  * Building blocks of a move, exposed for testing and for callers composing
  * their own loops.  All operate on caller device memory on `stream`.

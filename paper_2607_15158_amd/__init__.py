@@ -103,6 +103,9 @@ _sigs = {
     "ctm_qr_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),
     "ctm_vjp_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ctm_config), ctypes.POINTER(ctypes.c_size_t)]),
     "ctm_move_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t]),
+    "ctm_fixed_point_vjp": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
+                                           _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int),
+                                           _dp]),
     "ctm_svd_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _vp]),
 }
@@ -275,10 +278,7 @@ class Ctm:
         state, the move's output state (or None) and ``site_bar`` (the site
         tensor's cotangent, accumulated into the given tensor or a new one)."""
         import torch
-        if self._vjp_ws is None:
-            n = ctypes.c_size_t(0)
-            _check(_lib.ctm_vjp_workspace_bytes(ctypes.byref(self._c), ctypes.byref(n)))
-            self._vjp_ws = torch.empty(n.value, dtype=torch.uint8, device=self._site.device)
+        self._ensure_vjp_ws()
         dev = self._site.device
         sin = state_in.to(dev, torch.float64).contiguous()
         sbar = out_bar.to(dev, torch.float64).contiguous()
@@ -290,6 +290,36 @@ class Ctm:
                                  None if out is None else out.data_ptr(), site_bar.data_ptr(),
                                  self._vjp_ws.data_ptr(), self._vjp_ws.numel()), self._h)
         return in_bar, out, site_bar
+
+    def _ensure_vjp_ws(self):
+        import torch
+        if self._vjp_ws is None:
+            n = ctypes.c_size_t(0)
+            _check(_lib.ctm_vjp_workspace_bytes(ctypes.byref(self._c), ctypes.byref(n)))
+            self._vjp_ws = torch.empty(n.value, dtype=torch.uint8, device=self._site.device)
+        return self._vjp_ws
+
+    def fixed_point_vjp(self, state_star, g_bar, tol: float = 1e-10, max_iter: int = 200,
+                        site_bar=None):
+        """Fixed-point gradient (eq. implicit) at the converged ``state_star``
+        for the state cotangent ``g_bar``: returns (x_bar, site_bar, passes,
+        relative norm of the last term); raises if the series did not reach
+        ``tol`` within ``max_iter`` passes."""
+        import torch
+        ws = self._ensure_vjp_ws()
+        dev = self._site.device
+        x = state_star.to(dev, torch.float64).contiguous()
+        g = g_bar.to(dev, torch.float64).contiguous()
+        x_bar = torch.empty_like(x)
+        if site_bar is None:
+            site_bar = torch.zeros_like(self._site)
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        _check(_lib.ctm_fixed_point_vjp(self._h, x.data_ptr(), g.data_ptr(), float(tol),
+                                        int(max_iter), x_bar.data_ptr(), site_bar.data_ptr(),
+                                        ws.data_ptr(), ws.numel(), ctypes.byref(it),
+                                        ctypes.byref(rel)), self._h)
+        return x_bar, site_bar, it.value, rel.value
 
     def unpack_state(self, state: np.ndarray) -> dict:
         """Splits a state vector into C, T (cut to chi_env), X, Yt, chi_env."""

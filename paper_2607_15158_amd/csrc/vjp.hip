@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -281,6 +282,7 @@ struct Bufs {
   double *Ju[4], *Jv[4], *Km[4], *uK[4], *vsT[4], *usT[4], *rhob[4], *rhobT[4];
   double *vscb[4], *uscb[4], *vscT[4], *uscT[4], *ub[4], *vb[4], *sb[4];
   double *smallT;                         // x x x / k x k transposes
+  double *fp_v[2], *fp_dot;               // fixed-point iteration: cotangent ping-pong
   void *qr_ws, *svd_ws;
 };
 
@@ -386,6 +388,10 @@ size_t carve(const Dims& m, Bufs* b, char* base, std::vector<std::pair<uintptr_t
     b->Mc[j] = cv.take(k * k);
   }
   b->smallT = cv.take(std::max(x * x, k * k));
+  const size_t nstate = 4 * x * x + 4 * x * Dl * x + 8 * Nk + 4;
+  b->fp_v[0] = cv.take(nstate);
+  b->fp_v[1] = cv.take(nstate);
+  b->fp_dot = cv.take(8);
   b->qr_ws = cv.bytes(qr_workspace_bytes(8, m.N, m.k));
   b->svd_ws = cv.bytes(svd_workspace_bytes(4, m.k));
   return cv.off + 256;
@@ -1283,6 +1289,106 @@ int check_cfg(const ctm_config* cfg) {
 
 }  // namespace
 
+namespace {
+
+// Validation, carving, buffer registration and the taped forward move from
+// state_in (with its unit-norm outputs in b.Cn, b.Tn).
+struct Prepared {
+  VjpView v;
+  Dims m;
+  Bufs b;
+  Run r;
+  State in;
+  size_t nstate;
+};
+
+int prepare(ctm_ctx* ctx, const double* state_in, void* ws, size_t ws_bytes, Prepared& P,
+            std::initializer_list<std::pair<const double*, size_t>> extra) {
+  const int rv = vjp_view(ctx, &P.v);
+  if (rv) return rv;
+  if (check_cfg(&P.v.cfg))
+    return vjp_fail(ctx, CTM_E_ARG,
+                    "the adjoint needs an iPEPS site (d >= 1), SI projectors, float64 "
+                    "contractions, the stabilised update and no lattice symmetry");
+  P.m = dims_of(P.v.cfg);
+  const size_t need = carve(P.m, &P.b, nullptr, nullptr);
+  if (ws_bytes < need)
+    return vjp_fail(ctx, CTM_E_ARG, "adjoint workspace too small (need " + std::to_string(need) +
+                                        " bytes)");
+  P.r.c = ctx;
+  P.r.st = P.v.st;
+  const size_t x = P.m.x, Dl = P.m.Dl, N = P.m.N, k = P.m.k;
+  P.nstate = 4 * x * x + 4 * x * Dl * x + 8 * N * k + 4;
+  double chi_env = 0.0;
+  if (hipMemcpyAsync(&chi_env, state_in + (P.nstate - 4), sizeof(double), hipMemcpyDeviceToHost,
+                     P.v.st) != hipSuccess ||
+      hipStreamSynchronize(P.v.st) != hipSuccess)
+    return vjp_fail(ctx, CTM_E_DEVICE, "reading chi_env of the input state failed");
+  if ((int)chi_env != P.m.x)
+    return vjp_fail(ctx, CTM_E_STATE,
+                    "the adjoint is defined for SI moves: the input state needs chi_env == chi");
+  carve(P.m, &P.b, (char*)ws, &P.r.reg);
+  const size_t D4 = (size_t)P.m.D * P.m.D * P.m.D * P.m.D;
+  auto reg = [&](const double* p, size_t n) {
+    if (p) P.r.reg.push_back({(uintptr_t)p, (uintptr_t)(p + n)});
+  };
+  reg(state_in, P.nstate);
+  for (const auto& e : extra) reg(e.first, e.second == 0 ? P.nstate : e.second);
+  reg(P.v.A_site, P.m.d * D4);
+  reg(P.v.a, Dl * Dl * Dl * Dl);
+  for (int i = 0; i < 4; ++i) reg(P.v.ap[i], Dl * Dl * Dl * Dl);
+  const double* p = state_in;
+  for (int i = 0; i < 4; ++i, p += x * x) P.in.C[i] = p;
+  for (int i = 0; i < 4; ++i, p += x * Dl * x) P.in.T[i] = p;
+  for (int i = 0; i < 4; ++i, p += N * k) P.in.X[i] = p;
+  for (int i = 0; i < 4; ++i, p += N * k) P.in.Yt[i] = p;
+  int rc = forward(P.r, P.v, P.m, P.b, P.in, P.v.cfg.pinv_rtol);
+  if (rc) return rc;
+  k_sqrt8<<<1, 64, 0, P.r.st>>>(P.b.dots, P.b.nrm);
+  ScaleArgs sa{};
+  for (int i = 0; i < 4; ++i) {
+    sa.x[i] = P.b.Ch[i];
+    sa.y[i] = P.b.Cn[i];
+    sa.n[i] = (long)x * x;
+    sa.x[4 + i] = P.b.Th[i];
+    sa.y[4 + i] = P.b.Tn[i];
+    sa.n[4 + i] = (long)x * Dl * x;
+  }
+  sa.nrm = P.b.nrm;
+  k_scale_out<<<dim3((int)std::min<size_t>(512, (x * Dl * x + 255) / 256), 8), 256, 0, P.r.st>>>(sa);
+  if (hipGetLastError() != hipSuccess) return vjp_fail(ctx, CTM_E_DEVICE, "scaling launch failed");
+  return 0;
+}
+
+// Splits a state-layout buffer into its tensors.
+void split(double* base, const Dims& m, double** C, double** T, double** X, double** Y) {
+  const size_t x = m.x, Dl = m.Dl, N = m.N, k = m.k;
+  double* p = base;
+  for (int i = 0; i < 4; ++i, p += x * x) C[i] = p;
+  for (int i = 0; i < 4; ++i, p += x * Dl * x) T[i] = p;
+  for (int i = 0; i < 4; ++i, p += N * k) X[i] = p;
+  for (int i = 0; i < 4; ++i, p += N * k) Y[i] = p;
+}
+
+// One reverse pass of the prepared move: bar (state layout) -> in_bar.
+int reverse(Prepared& P, const double* bar, double* in_bar, double* site_bar) {
+  State sb{};
+  double *C[4], *T[4], *X[4], *Y[4];
+  split(const_cast<double*>(bar), P.m, C, T, X, Y);
+  for (int i = 0; i < 4; ++i) {
+    sb.C[i] = C[i];
+    sb.T[i] = T[i];
+    sb.X[i] = X[i];
+    sb.Yt[i] = Y[i];
+  }
+  double *Cb[4], *Tb[4], *Xb[4], *Yb[4];
+  split(in_bar, P.m, Cb, Tb, Xb, Yb);
+  VTRY(fill(P.r, in_bar + (P.nstate - 4), 4, 0.0));
+  return backward(P.r, P.v, P.m, P.b, P.in, sb, Cb, Tb, Xb, Yb, site_bar);
+}
+
+}  // namespace
+
 extern "C" {
 
 ctm_status ctm_vjp_workspace_bytes(const ctm_config* cfg, size_t* bytes) {
@@ -1305,109 +1411,97 @@ ctm_status ctm_move_vjp(ctm_ctx* ctx, const double* state_in, const double* stat
     set_thread_error("null argument");
     return CTM_E_ARG;
   }
-  VjpView v;
-  const int rv = vjp_view(ctx, &v);
-  if (rv) return (ctm_status)rv;
-  if (check_cfg(&v.cfg))
-    return (ctm_status)vjp_fail(ctx, CTM_E_ARG,
-                                "the adjoint needs an iPEPS site (d >= 1), SI projectors, float64 "
-                                "contractions, the stabilised update and no lattice symmetry");
-  const Dims m = dims_of(v.cfg);
-  Bufs b;
-  const size_t need = carve(m, &b, nullptr, nullptr);
-  if (ws_bytes < need)
-    return (ctm_status)vjp_fail(ctx, CTM_E_ARG, "adjoint workspace too small (need " +
-                                                    std::to_string(need) + " bytes)");
-  Run r;
-  r.c = ctx;
-  r.st = v.st;
-  const size_t x = m.x, Dl = m.Dl, N = m.N, k = m.k;
-  const size_t nstate = 4 * x * x + 4 * x * Dl * x + 8 * N * k + 4;
-  {
-    // the chi_env entry of the input state must be chi (SI moves only)
-    double chi_env = 0.0;
-    if (hipMemcpyAsync(&chi_env, state_in + (nstate - 4), sizeof(double), hipMemcpyDeviceToHost,
-                       v.st) != hipSuccess ||
-        hipStreamSynchronize(v.st) != hipSuccess)
-      return (ctm_status)vjp_fail(ctx, CTM_E_DEVICE, "reading chi_env of the input state failed");
-    if ((int)chi_env != m.x)
-      return (ctm_status)vjp_fail(ctx, CTM_E_STATE,
-                                  "the adjoint is defined for SI moves: the input state needs chi_env == chi");
-  }
-  carve(m, &b, (char*)ws, &r.reg);
-  const size_t D4 = (size_t)m.D * m.D * m.D * m.D;
-  r.reg.push_back({(uintptr_t)state_in, (uintptr_t)(state_in + nstate)});
-  r.reg.push_back({(uintptr_t)state_out_bar, (uintptr_t)(state_out_bar + nstate)});
-  r.reg.push_back({(uintptr_t)state_in_bar, (uintptr_t)(state_in_bar + nstate)});
-  if (state_out) r.reg.push_back({(uintptr_t)state_out, (uintptr_t)(state_out + nstate)});
-  if (site_bar) r.reg.push_back({(uintptr_t)site_bar, (uintptr_t)(site_bar + m.d * D4)});
-  r.reg.push_back({(uintptr_t)v.A_site, (uintptr_t)(v.A_site + m.d * D4)});
-  r.reg.push_back({(uintptr_t)v.a, (uintptr_t)(v.a + Dl * Dl * Dl * Dl)});
-  for (int i = 0; i < 4; ++i) r.reg.push_back({(uintptr_t)v.ap[i], (uintptr_t)(v.ap[i] + Dl * Dl * Dl * Dl)});
-
-  auto unpack = [&](const double* base, State& s) {
-    const double* p = base;
-    for (int i = 0; i < 4; ++i, p += x * x) s.C[i] = p;
-    for (int i = 0; i < 4; ++i, p += x * Dl * x) s.T[i] = p;
-    for (int i = 0; i < 4; ++i, p += N * k) s.X[i] = p;
-    for (int i = 0; i < 4; ++i, p += N * k) s.Yt[i] = p;
-  };
-  State in{}, bar{};
-  unpack(state_in, in);
-  unpack(state_out_bar, bar);
-  double *Cb[4], *Tb[4], *Xb[4], *Yb[4];
-  {
-    double* p = state_in_bar;
-    for (int i = 0; i < 4; ++i, p += x * x) Cb[i] = p;
-    for (int i = 0; i < 4; ++i, p += x * Dl * x) Tb[i] = p;
-    for (int i = 0; i < 4; ++i, p += N * k) Xb[i] = p;
-    for (int i = 0; i < 4; ++i, p += N * k) Yb[i] = p;
-    const int rz = fill(r, p, 4, 0.0);
-    if (rz) return (ctm_status)rz;
-  }
-  int rc = forward(r, v, m, b, in, v.cfg.pinv_rtol);
-  if (!rc) {
-    k_sqrt8<<<1, 64, 0, r.st>>>(b.dots, b.nrm);
-    ScaleArgs sa{};
-    for (int i = 0; i < 4; ++i) {
-      sa.x[i] = b.Ch[i];
-      sa.y[i] = b.Cn[i];
-      sa.n[i] = (long)x * x;
-      sa.x[4 + i] = b.Th[i];
-      sa.y[4 + i] = b.Tn[i];
-      sa.n[4 + i] = (long)x * Dl * x;
-    }
-    sa.nrm = b.nrm;
-    k_scale_out<<<dim3((int)std::min<size_t>(512, (x * Dl * x + 255) / 256), 8), 256, 0, r.st>>>(sa);
-    if (hipGetLastError() != hipSuccess) rc = vjp_fail(ctx, CTM_E_DEVICE, "scaling launch failed");
+  Prepared P;
+  int rc = prepare(ctx, state_in, ws, ws_bytes, P,
+                   {{state_out_bar, 0}, {state_in_bar, 0}, {state_out, 0}});
+  if (!rc && site_bar) {
+    const size_t D4 = (size_t)P.m.D * P.m.D * P.m.D * P.m.D;
+    P.r.reg.push_back({(uintptr_t)site_bar, (uintptr_t)(site_bar + P.m.d * D4)});
   }
   if (!rc && state_out) {
-    State o{};
-    unpack(state_out, o);
+    double *C[4], *T[4], *X[4], *Y[4];
+    split(state_out, P.m, C, T, X, Y);
+    const long x = P.m.x, Dl = P.m.Dl;
     for (int i = 0; i < 4 && !rc; ++i) {
-      rc = copy(r, b.Cn[i], (double*)o.C[i], (long)x * x);
-      if (!rc) rc = copy(r, b.Tn[i], (double*)o.T[i], (long)x * Dl * x);
+      rc = copy(P.r, P.b.Cn[i], C[i], x * x);
+      if (!rc) rc = copy(P.r, P.b.Tn[i], T[i], x * Dl * x);
     }
-    // recycled blocks X' = Xf v_s, Y^T' = Yf u_s
     if (!rc) {
-      GemmBatch g = rowmajor(8, (int)N, (int)k, (int)k, k, k, k);
+      // recycled blocks X' = Xf v_s, Y^T' = Yf u_s
+      const int N = P.m.N, k = P.m.k, last = 10 * P.m.nsi - 1;
+      GemmBatch g = rowmajor(8, N, k, k, k, k, k);
       for (int i = 0; i < 4; ++i) {
-        g.A[i] = m.nsi > 0 ? b.tape[i][10 * m.nsi - 1] : in.X[i];
-        g.B[i] = b.vs[i];
-        g.C[i] = (double*)o.X[i];
-        g.A[4 + i] = m.nsi > 0 ? b.tape[4 + i][10 * m.nsi - 1] : in.Yt[i];
-        g.B[4 + i] = b.us[i];
-        g.C[4 + i] = (double*)o.Yt[i];
+        g.A[i] = P.m.nsi > 0 ? P.b.tape[i][last] : P.in.X[i];
+        g.B[i] = P.b.vs[i];
+        g.C[i] = X[i];
+        g.A[4 + i] = P.m.nsi > 0 ? P.b.tape[4 + i][last] : P.in.Yt[i];
+        g.B[4 + i] = P.b.us[i];
+        g.C[4 + i] = Y[i];
       }
-      rc = gemm(r, g);
+      rc = gemm(P.r, g);
     }
-    if (!rc) rc = copy(r, state_in + (nstate - 4), state_out + (nstate - 4), 4);
+    if (!rc) rc = copy(P.r, state_in + (P.nstate - 4), state_out + (P.nstate - 4), 4);
   }
-  if (!rc) rc = backward(r, v, m, b, in, bar, Cb, Tb, Xb, Yb, site_bar);
+  if (!rc) rc = reverse(P, state_out_bar, state_in_bar, site_bar);
   if (rc) return (ctm_status)rc;
-  if (hipStreamSynchronize(v.st) != hipSuccess)
+  if (hipStreamSynchronize(P.v.st) != hipSuccess)
     return (ctm_status)vjp_fail(ctx, CTM_E_DEVICE, "synchronisation failed");
   return CTM_OK;
+}
+
+ctm_status ctm_fixed_point_vjp(ctm_ctx* ctx, const double* state_star, const double* g_bar,
+                               double tol, int max_iter, double* x_bar, double* site_bar,
+                               void* ws, size_t ws_bytes, int* iters, double* rel_norm) {
+  if (!ctx || !state_star || !g_bar || !site_bar || !ws || max_iter < 1 || !(tol >= 0.0)) {
+    set_thread_error("invalid argument");
+    return CTM_E_ARG;
+  }
+  Prepared P;
+  int rc = prepare(ctx, state_star, ws, ws_bytes, P, {{g_bar, 0}, {x_bar, 0}});
+  if (rc) return (ctm_status)rc;
+  const size_t D4 = (size_t)P.m.D * P.m.D * P.m.D * P.m.D;
+  P.r.reg.push_back({(uintptr_t)site_bar, (uintptr_t)(site_bar + P.m.d * D4)});
+  const long n = (long)P.nstate - 4;
+  // |v|^2 of the cotangent (counters excluded), read back to the host
+  auto norm2 = [&](const double* v, double* out) -> int {
+    DotArgs da{};
+    da.x[0] = v;
+    da.y[0] = v;
+    da.n[0] = n;
+    da.out = P.b.fp_dot;
+    k_dots<<<1, 256, 0, P.r.st>>>(da);
+    CTM_HIP_TRY(hipGetLastError());
+    CTM_HIP_TRY(hipMemcpyAsync(out, P.b.fp_dot, sizeof(double), hipMemcpyDeviceToHost, P.r.st));
+    CTM_HIP_TRY(hipStreamSynchronize(P.r.st));
+    return 0;
+  };
+  double g2 = 0.0;
+  rc = norm2(g_bar, &g2);
+  if (rc) return (ctm_status)rc;
+  rc = copy(P.r, g_bar, P.b.fp_v[0], (long)P.nstate);
+  if (!rc && x_bar) rc = copy(P.r, g_bar, x_bar, (long)P.nstate);
+  int it = 0, cur = 0;
+  double rel = g2 > 0.0 ? 1.0 : 0.0;
+  // x_bar = sum_n (J_x^T)^n g,  site_bar += sum_n J_A^T (J_x^T)^n g
+  while (!rc && it < max_iter && rel > tol) {
+    rc = reverse(P, P.b.fp_v[cur], P.b.fp_v[1 - cur], site_bar);
+    if (rc) break;
+    cur = 1 - cur;
+    ++it;
+    if (x_bar) {
+      rc = gather(P.r, P.b.fp_v[cur], x_bar, 1, 1, 1, (int)n, 0, 0, 0, 1, true);
+      if (rc) break;
+    }
+    double v2 = 0.0;
+    rc = norm2(P.b.fp_v[cur], &v2);
+    rel = g2 > 0.0 ? std::sqrt(v2 / g2) : 0.0;
+  }
+  if (iters) *iters = it;
+  if (rel_norm) *rel_norm = rel;
+  if (rc) return (ctm_status)rc;
+  if (hipStreamSynchronize(P.v.st) != hipSuccess)
+    return (ctm_status)vjp_fail(ctx, CTM_E_DEVICE, "synchronisation failed");
+  return rel <= tol ? CTM_OK : CTM_E_NOT_CONVERGED;
 }
 
 }  // extern "C"

@@ -98,3 +98,42 @@ def test_move_vjp_matches_finite_differences_of_gpu_moves():
         an = float(in_bar[:-4] @ d[:-4])
         print(trial, fd, an)
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0), (trial, fd, an)
+
+
+def test_fixed_point_gradient_matches_finite_differences_of_converged_environments():
+    """eq. implicit: the site-tensor gradient of a functional of the
+    converged environment, from the Neumann series of reverse passes at the
+    fixed point, equals central differences of fully converged GPU runs."""
+    D, chi, p = 2, 8, 4
+    A = S.product_plus_noise_site(2, D, 2, noise=0.3)
+    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2)
+    N, k = cfg.N, cfg.k
+    X0 = np.stack([S.gaussian_block(N, k, 20 + b) for b in range(4)])
+    Y0 = np.stack([S.gaussian_block(N, k, 30 + b) for b in range(4)])
+    dev = torch.device("cuda", 0)
+
+    def converged(site):
+        ctx = P.Ctm(cfg, torch.from_numpy(site).to(dev))
+        ctx.set_isometries(torch.from_numpy(X0).to(dev), torch.from_numpy(Y0).to(dev))
+        r = ctx.converge(1e-14, 400)
+        assert r["delta"] < 1e-12, r
+        return ctx, ctx.get_state()
+
+    ctx, star = converged(A)
+    rng = np.random.default_rng(12)
+    n_ct = 4 * chi * chi + 4 * chi * D * D * chi
+    w = np.zeros_like(star)
+    w[:n_ct] = rng.standard_normal(n_ct)
+    x_bar, site_bar, passes, rel_norm = ctx.fixed_point_vjp(
+        torch.from_numpy(star), torch.from_numpy(w), tol=1e-12, max_iter=400)
+    print("passes", passes, "last term", rel_norm)
+    site_bar = site_bar.cpu().numpy()
+    for trial in range(2):
+        d = rng.standard_normal(A.shape)
+        h = 1e-5
+        lp = float(converged(A + h * d)[1] @ w)
+        lm = float(converged(A - h * d)[1] @ w)
+        fd = (lp - lm) / (2 * h)
+        an = float((site_bar * d).sum())
+        print(trial, fd, an)
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1.0), (trial, fd, an)
