@@ -16,9 +16,14 @@ the signs of the QR diagonal, the sign rule on the singular triples and the
 pseudo-inverse mask -- are taken from the forward values and held constant,
 as they are piecewise constant functions of the input.
 
-Its pin is independent of autograd: central finite differences of the NumPy
-move of :mod:`oracle.ctmrg` along random directions (``tests/``), and the
-forward values of both implementations agree to rounding.
+It also writes the nearest-neighbour bond energy <op>_H + <op>_V of the
+two-site reduced density matrices (iPEPS section, observables) in PyTorch,
+for the gradient of the energy's direct dependence on (C, T, A).
+
+Its pins are independent of autograd: central finite differences of the
+NumPy move and of the NumPy bond values of :mod:`oracle.ctmrg` along random
+directions (``tests/``), and the forward values of both implementations
+agree to rounding.
 """
 from __future__ import annotations
 
@@ -30,7 +35,7 @@ import torch
 from .ctmrg import SIGN_TIE_RTOL, sign_fix_columns
 
 __all__ = ["move_torch", "move_vjp", "si_projectors_torch", "renormalize_torch",
-           "enlarged_corners_torch", "double_layer_torch"]
+           "enlarged_corners_torch", "double_layer_torch", "energy_torch", "energy_vjp"]
 
 _f64 = torch.float64
 
@@ -159,6 +164,68 @@ def move_vjp(C, T, X, Yt, A, bars, chi: int, n_si: int = 2, eps: float = 1e-12):
     g = [np.zeros(v.shape) if gr is None else gr.numpy() for v, gr in
          zip(Cl + Tl + Xl + Yl + [Al], grads)]
     return g[0:4], g[4:8], g[8:12], g[12:16], g[16]
+
+
+def _double_layer_open_torch(A):
+    """a_open[s, t, (uU), (lL), (dD), (rR)] = A[s,u,l,d,r] A[t,U,L,D,R]."""
+    d, D = A.shape[0], A.shape[1]
+    a = torch.einsum("sijkl,tIJKL->stiIjJkKlL", A, A)
+    return a.reshape(d, d, D * D, D * D, D * D, D * D)
+
+
+def _two_site_h_torch(C, T, x1, x2):
+    """Horizontal pair (site 1 left of site 2), as :func:`oracle.ctmrg._two_site_h`."""
+    C1, C2, C3, C4 = C
+    T1, T2, T3, T4 = T
+    left = torch.einsum("ab,kla,jk->blj", C1, T4, C4)
+    y1 = torch.einsum("blj,bug->gulj", left, T1)
+    y2 = torch.einsum("gulj,ABuldm->ABgdmj", y1, x1)
+    y3 = torch.einsum("ABgdmj,idj->ABgmi", y2, T3)
+    right = torch.einsum("hc,cwe,ef->hwf", C2, T2, C3)
+    w1 = torch.einsum("gvh,hwf->gvwf", T1, right)
+    w2 = torch.einsum("gvwf,EFvmyw->EFgmyf", w1, x2)
+    w3 = torch.einsum("EFgmyf,fyi->EFgmi", w2, T3)
+    return torch.einsum("ABgmi,EFgmi->ABEF", y3, w3)
+
+
+def _two_site_v_torch(C, T, x1, x2):
+    """Vertical pair (site 1 above site 2), as :func:`oracle.ctmrg._two_site_v`."""
+    C1, C2, C3, C4 = C
+    T1, T2, T3, T4 = T
+    top = torch.einsum("ab,bug,gh->auh", C1, T1, C2)
+    p1 = torch.einsum("nla,auh->nluh", T4, top)
+    p2 = torch.einsum("nluh,ABulxr->ABnxrh", p1, x1)
+    p3 = torch.einsum("ABnxrh,hrc->ABnxc", p2, T2)
+    bot = torch.einsum("ij,jwk,km->iwm", C3, T3, C4)
+    q1 = torch.einsum("csi,iwm->cswm", T2, bot)
+    q2 = torch.einsum("cswm,EFxpws->EFcxpm", q1, x2)
+    q3 = torch.einsum("EFcxpm,mpn->EFcxn", q2, T4)
+    return torch.einsum("ABnxc,EFcxn->ABEF", p3, q3)
+
+
+def energy_torch(C, T, A, op):
+    """<op>_H + <op>_V of a nearest-neighbour operator op[(t1 t2), (s1 s2)]
+    (bra, ket) from the two-site reduced density matrices (iPEPS section,
+    observables), as :func:`oracle.ctmrg.bond_value` for both bonds."""
+    d = A.shape[0]
+    ao = _double_layer_open_torch(A)
+    out = 0.0
+    for E in (_two_site_h_torch(C, T, ao, ao), _two_site_v_torch(C, T, ao, ao)):
+        rho = E.permute(0, 2, 1, 3).reshape(d * d, d * d)
+        rho = rho / torch.trace(rho)
+        out = out + torch.trace(op @ rho)
+    return out
+
+
+def energy_vjp(C, T, A, op):
+    """(e, C_bar, T_bar, A_bar) for e = <op>_H + <op>_V at environment (C, T)."""
+    leaf = lambda v: torch.tensor(np.asarray(v), dtype=_f64, requires_grad=True)  # noqa: E731
+    Cl = [leaf(c) for c in C]
+    Tl = [leaf(t) for t in T]
+    Al = leaf(A)
+    e = energy_torch(Cl, Tl, Al, torch.as_tensor(np.asarray(op), dtype=_f64))
+    g = torch.autograd.grad(e, Cl + Tl + [Al])
+    return float(e), [x.numpy() for x in g[:4]], [x.numpy() for x in g[4:8]], g[8].numpy()
 
 
 # the sign rule's tie tolerance is shared with the NumPy move

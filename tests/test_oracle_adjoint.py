@@ -98,3 +98,36 @@ def test_planted_detached_pinv_is_caught(monkeypatch):
     fd = (f(1e-6) - f(-1e-6)) / 2e-6
     an = (gA * d).sum()
     assert abs(fd - an) > 1e-3 * abs(fd)
+
+
+def test_energy_gradient_matches_central_differences_of_bond_values():
+    """The torch energy equals the NumPy bond values, and its autograd
+    gradient matches central differences of oracle.ctmrg.bond_value for the
+    corners, the edges and the site tensor."""
+    A, C, T, _, _ = case(D=2, chi=4)
+    h = S.heisenberg_bond()
+    env = O.Env(C, T)
+
+    def e_np(C_, T_, A_):
+        en = O.Env(C_, T_)
+        return O.bond_value(en, A_, h, "h") + O.bond_value(en, A_, h, "v")
+
+    e, gC, gT, gA = J.energy_vjp(C, T, A, h)
+    assert abs(e - e_np(env.C, env.T, A)) <= 1e-12
+    rng = np.random.default_rng(4)
+    for group in ("C", "T", "A"):
+        d = ([rng.standard_normal(c.shape) for c in C] if group == "C" else
+             [rng.standard_normal(t.shape) for t in T] if group == "T" else
+             rng.standard_normal(A.shape))
+
+        def f(hh):
+            if group == "C":
+                return e_np([c + hh * dc for c, dc in zip(C, d)], T, A)
+            if group == "T":
+                return e_np(C, [t + hh * dt for t, dt in zip(T, d)], A)
+            return e_np(C, T, A + hh * d)
+
+        fd = (f(1e-6) - f(-1e-6)) / 2e-6
+        an = (sum((g * dd).sum() for g, dd in zip(gC, d)) if group == "C" else
+              sum((g * dd).sum() for g, dd in zip(gT, d)) if group == "T" else (gA * d).sum())
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0), (group, fd, an)
