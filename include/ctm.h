@@ -341,6 +341,19 @@ ctm_status ctm_fixed_point_vjp(ctm_ctx* ctx, const double* state_star, const dou
                                double tol, int max_iter, double* x_bar, double* site_bar,
                                void* ws, size_t ws_bytes, int* iters, double* rel_norm);
 
+/* Bond energy and its gradient (iPEPS section, observables): for the
+ * environment C, T of `state` (device, state layout, chi_env == chi) and
+ * the site tensor of the context,
+ *     e = <op>_H + <op>_V      (two-site reduced density matrices, trace 1),
+ * op[(t1 t2), (s1 s2)] a d^2 x d^2 host operator (bra, ket).  Writes e to
+ * *e_out (host, may be NULL), de/d(C, T) to state_bar (device, state layout;
+ * X, Y^T and counters 0) and adds de/dA to site_bar (device, d*D^4).  The
+ * vertical pair is evaluated as the horizontal pair of the network turned
+ * by 90 degrees.  Together with ctm_fixed_point_vjp (g = state_bar) this
+ * gives the gradient of the converged energy.  ws: ctm_vjp_workspace_bytes. */
+ctm_status ctm_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_host, double* e_out,
+                          double* state_bar, double* site_bar, void* ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------------------
  * Building blocks of a move, exposed for testing and for callers composing
  * their own loops.  All operate on caller device memory on `stream`.

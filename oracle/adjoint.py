@@ -225,7 +225,7 @@ def energy_vjp(C, T, A, op):
     Al = leaf(A)
     e = energy_torch(Cl, Tl, Al, torch.as_tensor(np.asarray(op), dtype=_f64))
     g = torch.autograd.grad(e, Cl + Tl + [Al])
-    return float(e), [x.numpy() for x in g[:4]], [x.numpy() for x in g[4:8]], g[8].numpy()
+    return float(e.detach()), [x.numpy() for x in g[:4]], [x.numpy() for x in g[4:8]], g[8].numpy()
 
 
 # the sign rule's tie tolerance is shared with the NumPy move

@@ -103,6 +103,7 @@ _sigs = {
     "ctm_qr_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),
     "ctm_vjp_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ctm_config), ctypes.POINTER(ctypes.c_size_t)]),
     "ctm_move_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t]),
+    "ctm_energy_vjp": (ctypes.c_int, [_vp, _vp, _dp, _dp, _vp, _vp, _vp, ctypes.c_size_t]),
     "ctm_fixed_point_vjp": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
                                            _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int),
                                            _dp]),
@@ -320,6 +321,34 @@ class Ctm:
                                         ws.data_ptr(), ws.numel(), ctypes.byref(it),
                                         ctypes.byref(rel)), self._h)
         return x_bar, site_bar, it.value, rel.value
+
+    def energy_vjp(self, state, op, site_bar=None):
+        """e = <op>_H + <op>_V at the environment of ``state`` (device tensor,
+        state layout) and its gradient: returns (e, state_bar, site_bar)."""
+        import torch
+        ws = self._ensure_vjp_ws()
+        dev = self._site.device
+        st = state.to(dev, torch.float64).contiguous()
+        opb = np.ascontiguousarray(op, dtype=np.float64)
+        e = ctypes.c_double(0.0)
+        bar = torch.empty_like(st)
+        if site_bar is None:
+            site_bar = torch.zeros_like(self._site)
+        _check(_lib.ctm_energy_vjp(self._h, st.data_ptr(), opb.ctypes.data_as(_dp), ctypes.byref(e),
+                                   bar.data_ptr(), site_bar.data_ptr(), ws.data_ptr(), ws.numel()),
+               self._h)
+        return e.value, bar, site_bar
+
+    def energy_gradient(self, op, tol: float = 1e-12, max_iter: int = 400):
+        """Gradient of the converged energy e = <op>_H + <op>_V with respect to
+        the site tensor at the context's current (converged) environment: the
+        direct term plus the fixed-point term (eq. implicit).  Returns
+        (e, dE/dA as a device tensor, passes of the fixed-point series)."""
+        import torch
+        star = torch.from_numpy(self.get_state()).to(self._site.device)
+        e, g, site_bar = self.energy_vjp(star, op)
+        _, site_bar, passes, _ = self.fixed_point_vjp(star, g, tol, max_iter, site_bar)
+        return e, site_bar, passes
 
     def unpack_state(self, state: np.ndarray) -> dict:
         """Splits a state vector into C, T (cut to chi_env), X, Yt, chi_env."""

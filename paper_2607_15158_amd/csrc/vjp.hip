@@ -1389,6 +1389,237 @@ int reverse(Prepared& P, const double* bar, double* in_bar, double* site_bar) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// bond energy <op>_H + <op>_V and its gradient (iPEPS section, observables:
+// two-site reduced density matrices).  The horizontal pair is contracted
+// column by column; the vertical pair is the horizontal pair of the network
+// turned by 90 degrees (corner and edge i+1 in slot i, site legs
+// (u,l,d,r) <- (r,u,l,d)), so one chain and its reverse serve both.
+// ---------------------------------------------------------------------------
+namespace {
+
+// [ket][bra] matrix of an open double-layer cotangent in the order
+// [(uU),(lL),(dD),(rR)]: out[ket, bra] = xb[pairs(ket, bra)].
+__global__ __launch_bounds__(256) void k_open_reorder(const double* __restrict__ xb,
+                                                      double* __restrict__ out, int D) {
+  const long D4 = (long)D * D * D * D, Dl = (long)D * D;
+  for (long idx = blockIdx.x * 256L + threadIdx.x; idx < D4 * D4; idx += (long)gridDim.x * 256) {
+    const long p = idx / D4, q = idx % D4;
+    const long r0 = p % D, d0 = (p / D) % D, l0 = (p / Dl) % D, u0 = p / (Dl * D);
+    const long r1 = q % D, d1 = (q / D) % D, l1 = (q / Dl) % D, u1 = q / (Dl * D);
+    out[idx] = xb[(((u0 * D + u1) * Dl + (l0 * D + l1)) * Dl + (d0 * D + d1)) * Dl + (r0 * D + r1)];
+  }
+}
+
+struct EBufs {
+  int n;                                   // d^2 open-leg pairs (ket s, bra t)
+  double *L0, *left, *R1, *Y1, *W1, *W1p, *R0, *right;
+  std::vector<double*> xs, xb, x2p, Y2p, W2p;
+  double *Y3s, *W3s, *W3sT, *E, *Eb;
+  double *Y3b, *W3b, *T3Tb, *Y1b, *R1b, *leftb, *L0b, *W1pb, *W1b, *rightb, *R0b;
+  double *Ta, *Tb, *Tc, *St;
+  double *Ar, *Abr, *mopen;
+};
+
+size_t ecarve(const Dims& m, EBufs* b, char* base, std::vector<std::pair<uintptr_t, uintptr_t>>* reg) {
+  Carver cv;
+  cv.base = base;
+  cv.reg = reg;
+  const size_t x = m.x, Dl = m.Dl, NN = (size_t)m.N * m.N, L = x * Dl * x;
+  const size_t Dl4 = Dl * Dl * Dl * Dl, D4 = (size_t)m.D * m.D * m.D * m.D;
+  const int n = m.d * m.d;
+  b->n = n;
+  b->L0 = cv.take(L);
+  b->left = cv.take(L);
+  b->R1 = cv.take(NN);
+  b->Y1 = cv.take(NN);
+  b->W1 = cv.take(NN);
+  b->W1p = cv.take(NN);
+  b->R0 = cv.take(L);
+  b->right = cv.take(L);
+  b->xs.resize(n);
+  b->xb.resize(n);
+  b->x2p.resize(n);
+  b->Y2p.resize(n);
+  b->W2p.resize(n);
+  for (int i = 0; i < n; ++i) {
+    b->xs[i] = cv.take(Dl4);
+    b->xb[i] = cv.take(Dl4);
+    b->x2p[i] = cv.take(Dl4);
+    b->Y2p[i] = cv.take(NN);
+    b->W2p[i] = cv.take(NN);
+  }
+  b->Y3s = cv.take(n * L);
+  b->W3s = cv.take(n * L);
+  b->W3sT = cv.take(n * L);
+  b->E = cv.take(n * n);
+  b->Eb = cv.take(n * n);
+  b->Y3b = cv.take(n * L);
+  b->W3b = cv.take(n * L);
+  b->T3Tb = cv.take(L);
+  b->Y1b = cv.take(NN);
+  b->R1b = cv.take(NN);
+  b->leftb = cv.take(L);
+  b->L0b = cv.take(L);
+  b->W1pb = cv.take(NN);
+  b->W1b = cv.take(NN);
+  b->rightb = cv.take(L);
+  b->R0b = cv.take(L);
+  b->Ta = cv.take(NN);
+  b->Tb = cv.take(NN);
+  b->Tc = cv.take(NN);
+  b->St = cv.take(NN);
+  b->Ar = cv.take(m.d * D4);
+  b->Abr = cv.take(m.d * D4);
+  b->mopen = cv.take(D4 * D4);
+  return cv.off + 256;
+}
+
+GemmBatch one(int M, int N, int K, const void* A, long lda, int transA, const void* B, long ldb,
+              void* C, long ldc, bool acc = false) {
+  GemmBatch g = rowmajor(1, M, N, K, lda, ldb, ldc);
+  g.A[0] = A;
+  g.transA[0] = transA;
+  g.B[0] = B;
+  g.C[0] = C;
+  g.accumulate = acc ? 1 : 0;
+  return g;
+}
+
+// Forward horizontal chain: E[st1, st2] = <Y3_st1, W3_st2> for the open
+// site tensors xs (a-layout [(u,l)][(d,r)]), slots C[0..3], T[0..3].
+int echain_fwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const double* const* T) {
+  const int x = m.x, Dl = m.Dl, n = b.n;
+  const long L = (long)x * Dl * x, D2 = (long)Dl * Dl;
+  VTRY(gemm(r, one(x, Dl * x, x, C[3], x, 0, T[3], (long)Dl * x, b.L0, (long)Dl * x)));       // [j][(l,a)]
+  VTRY(gemm(r, one(x * Dl, x, x, b.L0, x, 0, C[0], x, b.left, x)));                            // [(j,l)][b]
+  VTRY(gemm(r, one(x * Dl, Dl * x, x, b.left, x, 0, T[0], (long)Dl * x, b.R1, (long)Dl * x)));  // [(j,l)][(u,g)]
+  VTRY(gather(r, b.R1, b.Y1, x, x, Dl, Dl, D2 * x, 1, x, (long)Dl * x));                       // [(j,g)][(u,l)]
+  VTRY(transpose(r, T[2], b.St, x, (long)Dl * x));                                             // [(d,j)][i]
+  for (int st = 0; st < n; ++st) {
+    VTRY(gemm(r, one(x * x, D2, D2, b.Y1, D2, 0, b.xs[st], D2, b.Ta, D2)));                   // [(j,g)][(d,m)]
+    VTRY(gather(r, b.Ta, b.Y2p[st], x, Dl, Dl, x, D2, 1, Dl, (long)x * D2));                  // [(g,m)][(d,j)]
+    VTRY(gemm(r, one(x * Dl, x, Dl * x, b.Y2p[st], (long)Dl * x, 0, b.St, x, b.Y3s + st * L, x)));
+  }
+  VTRY(gemm(r, one(x, Dl * x, x, C[1], x, 0, T[1], (long)Dl * x, b.R0, (long)Dl * x)));       // [h][(w,e)]
+  VTRY(gemm(r, one(x * Dl, x, x, b.R0, x, 0, C[2], x, b.right, x)));                           // [(h,w)][f]
+  VTRY(gemm(r, one(x * Dl, Dl * x, x, T[0], x, 0, b.right, (long)Dl * x, b.W1, (long)Dl * x)));  // [(g,v)][(w,f)]
+  VTRY(gather(r, b.W1, b.W1p, x, x, Dl, Dl, D2 * x, 1, (long)Dl * x, x));                      // [(g,f)][(v,w)]
+  for (int st = 0; st < n; ++st) {
+    VTRY(gather(r, b.xs[st], b.x2p[st], Dl, Dl, Dl, Dl, D2 * Dl, 1, D2, Dl));                  // [(v,w)][(m,y)]
+    VTRY(gemm(r, one(x * x, D2, D2, b.W1p, D2, 0, b.x2p[st], D2, b.Ta, D2)));                 // [(g,f)][(m,y)]
+    VTRY(gather(r, b.Ta, b.W2p[st], x, Dl, x, Dl, (long)x * D2, Dl, D2, 1));                  // [(g,m)][(f,y)]
+    VTRY(gemm(r, one(x * Dl, x, x * Dl, b.W2p[st], (long)x * Dl, 0, T[2], x, b.W3s + st * L, x)));
+  }
+  VTRY(transpose(r, b.W3s, b.W3sT, n, L));
+  VTRY(gemm(r, one(n, n, (int)L, b.Y3s, L, 0, b.W3sT, n, b.E, n)));
+  return 0;
+}
+
+// Reverse horizontal chain from Eb: accumulates into Cb, Tb (slots as C, T)
+// and into the open-layer cotangents b.xb.
+int echain_bwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const double* const* T,
+               double* const* Cb, double* const* Tb) {
+  const int x = m.x, Dl = m.Dl, n = b.n;
+  const long L = (long)x * Dl * x, D2 = (long)Dl * Dl, NN = (long)m.N * m.N;
+  VTRY(gemm(r, one(n, (int)L, n, b.Eb, n, 0, b.W3s, L, b.Y3b, L)));
+  VTRY(gemm(r, one(n, (int)L, n, b.Eb, n, 1, b.Y3s, L, b.W3b, L)));
+  VTRY(fill(r, b.T3Tb, L, 0.0));
+  VTRY(fill(r, b.Y1b, NN, 0.0));
+  VTRY(fill(r, b.W1pb, NN, 0.0));
+  for (int st = 0; st < n; ++st) {
+    VTRY(gemm(r, one(x * Dl, Dl * x, x, b.Y3b + st * L, x, 0, T[2], (long)Dl * x, b.Ta, (long)Dl * x)));
+    VTRY(gemm(r, one(Dl * x, x, x * Dl, b.Y2p[st], (long)Dl * x, 1, b.Y3b + st * L, x, b.T3Tb, x, true)));
+    VTRY(gather(r, b.Ta, b.Tb, x, x, Dl, Dl, 1, D2 * x, x, (long)Dl * x));                    // Y2b [(j,g)][(d,m)]
+    VTRY(transpose(r, b.xs[st], b.Tc, D2, D2));
+    VTRY(gemm(r, one(x * x, D2, D2, b.Tb, D2, 0, b.Tc, D2, b.Y1b, D2, true)));
+    VTRY(gemm(r, one(D2, D2, x * x, b.Y1, D2, 1, b.Tb, D2, b.xb[st], D2, true)));
+  }
+  VTRY(gather(r, b.T3Tb, Tb[2], 1, 1, x, (int)(Dl * x), 0, 0, 1, x, true));                    // += T3Tb^T
+  VTRY(gather(r, b.Y1b, b.R1b, x, Dl, Dl, x, (long)x * D2, 1, Dl, D2));                       // [(j,l)][(u,g)]
+  VTRY(transpose(r, T[0], b.St, x, (long)Dl * x));
+  VTRY(gemm(r, one(x * Dl, x, Dl * x, b.R1b, (long)Dl * x, 0, b.St, x, b.leftb, x)));
+  VTRY(gemm(r, one(x, Dl * x, x * Dl, b.left, x, 1, b.R1b, (long)Dl * x, Tb[0], (long)Dl * x, true)));
+  VTRY(transpose(r, C[0], b.St, x, x));
+  VTRY(gemm(r, one(x * Dl, x, x, b.leftb, x, 0, b.St, x, b.L0b, x)));
+  VTRY(gemm(r, one(x, x, x * Dl, b.L0, x, 1, b.leftb, x, Cb[0], x, true)));
+  VTRY(transpose(r, T[3], b.St, x, (long)Dl * x));
+  VTRY(gemm(r, one(x, x, Dl * x, b.L0b, (long)Dl * x, 0, b.St, x, Cb[3], x, true)));
+  VTRY(gemm(r, one(x, Dl * x, x, C[3], x, 1, b.L0b, (long)Dl * x, Tb[3], (long)Dl * x, true)));
+  // w chain
+  VTRY(transpose(r, T[2], b.St, (long)x * Dl, x));                                            // [i][(f,y)]
+  for (int st = 0; st < n; ++st) {
+    VTRY(gemm(r, one(x * Dl, x * Dl, x, b.W3b + st * L, x, 0, b.St, (long)x * Dl, b.Ta, (long)x * Dl)));
+    VTRY(gemm(r, one(x * Dl, x, x * Dl, b.W2p[st], (long)x * Dl, 1, b.W3b + st * L, x, Tb[2], x, true)));
+    VTRY(gather(r, b.Ta, b.Tb, x, x, Dl, Dl, D2 * x, Dl, (long)x * Dl, 1));                   // W2b [(g,f)][(m,y)]
+    VTRY(transpose(r, b.x2p[st], b.Tc, D2, D2));
+    VTRY(gemm(r, one(x * x, D2, D2, b.Tb, D2, 0, b.Tc, D2, b.W1pb, D2, true)));
+    VTRY(gemm(r, one(D2, D2, x * x, b.W1p, D2, 1, b.Tb, D2, b.Ta, D2)));                      // x2p_bar
+    VTRY(gather(r, b.Ta, b.xb[st], Dl, Dl, Dl, Dl, D2 * Dl, Dl, 1, D2, true));
+  }
+  VTRY(gather(r, b.W1pb, b.W1b, x, Dl, Dl, x, (long)x * D2, Dl, 1, D2));                      // [(g,v)][(w,f)]
+  VTRY(transpose(r, b.right, b.St, x, (long)Dl * x));
+  VTRY(gemm(r, one(x * Dl, x, Dl * x, b.W1b, (long)Dl * x, 0, b.St, x, Tb[0], x, true)));
+  VTRY(gemm(r, one(x, Dl * x, x * Dl, T[0], x, 1, b.W1b, (long)Dl * x, b.rightb, (long)Dl * x)));
+  VTRY(transpose(r, C[2], b.St, x, x));
+  VTRY(gemm(r, one(x * Dl, x, x, b.rightb, x, 0, b.St, x, b.R0b, x)));
+  VTRY(gemm(r, one(x, x, x * Dl, b.R0, x, 1, b.rightb, x, Cb[2], x, true)));
+  VTRY(transpose(r, T[1], b.St, x, (long)Dl * x));
+  VTRY(gemm(r, one(x, x, Dl * x, b.R0b, (long)Dl * x, 0, b.St, x, Cb[1], x, true)));
+  VTRY(gemm(r, one(x, Dl * x, x, C[1], x, 1, b.R0b, (long)Dl * x, Tb[1], (long)Dl * x, true)));
+  return 0;
+}
+
+// Open double layers of the site tensor `site` into b.xs (pairs (s,t)).
+int open_layers(Run& r, const Dims& m, EBufs& b, const double* site) {
+  for (int s = 0; s < m.d; ++s)
+    for (int t = 0; t < m.d; ++t) {
+      const int rc = elem_double_layer(site, nullptr, b.xs[s * m.d + t], m.d, m.D, r.st, s, t);
+      if (rc) return vjp_fail(r.c, rc == 1 ? CTM_E_ARG : rc, thread_error());
+    }
+  return 0;
+}
+
+// site_bar[s] += M_st site[t],  site_bar[t] += M_st^T site[s]  (M_st = [ket][bra] of xb_st)
+int open_vjp(Run& r, const Dims& m, EBufs& b, const double* site, double* site_bar) {
+  const long D4 = (long)m.D * m.D * m.D * m.D;
+  for (int s = 0; s < m.d; ++s)
+    for (int t = 0; t < m.d; ++t) {
+      if (!r.inside(b.mopen, (size_t)D4 * D4 * 8)) return r.fail("adjoint buffer too small");
+      k_open_reorder<<<(int)std::min<long>(4096, (D4 * D4 + 255) / 256), 256, 0, r.st>>>(
+          b.xb[s * m.d + t], b.mopen, m.D);
+      CTM_HIP_TRY(hipGetLastError());
+      VTRY(gemm(r, one((int)D4, 1, (int)D4, b.mopen, D4, 0, site + t * D4, 1, site_bar + s * D4, 1, true)));
+      VTRY(gemm(r, one((int)D4, 1, (int)D4, b.mopen, D4, 1, site + s * D4, 1, site_bar + t * D4, 1, true)));
+    }
+  return 0;
+}
+
+// value = sum E op' / sum_diag E and dvalue/dE (host, d^4 numbers)
+double bond_value_and_bar(const std::vector<double>& E, const double* op, int d, std::vector<double>& Eb) {
+  const int n = d * d;
+  double num = 0.0, den = 0.0;
+  for (int s1 = 0; s1 < d; ++s1)
+    for (int t1 = 0; t1 < d; ++t1)
+      for (int s2 = 0; s2 < d; ++s2)
+        for (int t2 = 0; t2 < d; ++t2) {
+          const double e = E[(s1 * d + t1) * n + (s2 * d + t2)];
+          num += op[(t1 * d + t2) * n + (s1 * d + s2)] * e;
+          if (s1 == t1 && s2 == t2) den += e;
+        }
+  const double val = num / den;
+  Eb.assign(n * n, 0.0);
+  for (int s1 = 0; s1 < d; ++s1)
+    for (int t1 = 0; t1 < d; ++t1)
+      for (int s2 = 0; s2 < d; ++s2)
+        for (int t2 = 0; t2 < d; ++t2)
+          Eb[(s1 * d + t1) * n + (s2 * d + t2)] =
+              (op[(t1 * d + t2) * n + (s1 * d + s2)] - (s1 == t1 && s2 == t2 ? val : 0.0)) / den;
+  return val;
+}
+
+}  // namespace
+
 extern "C" {
 
 ctm_status ctm_vjp_workspace_bytes(const ctm_config* cfg, size_t* bytes) {
@@ -1400,7 +1631,9 @@ ctm_status ctm_vjp_workspace_bytes(const ctm_config* cfg, size_t* bytes) {
     return (ctm_status)rc;
   }
   Bufs b;
-  *bytes = carve(dims_of(*cfg), &b, nullptr, nullptr);
+  EBufs eb;
+  *bytes = std::max(carve(dims_of(*cfg), &b, nullptr, nullptr),
+                    ecarve(dims_of(*cfg), &eb, nullptr, nullptr));
   return CTM_OK;
 }
 
@@ -1502,6 +1735,123 @@ ctm_status ctm_fixed_point_vjp(ctm_ctx* ctx, const double* state_star, const dou
   if (hipStreamSynchronize(P.v.st) != hipSuccess)
     return (ctm_status)vjp_fail(ctx, CTM_E_DEVICE, "synchronisation failed");
   return rel <= tol ? CTM_OK : CTM_E_NOT_CONVERGED;
+}
+
+
+}  // extern "C"
+
+namespace {
+
+int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, double* e_out,
+                    double* state_bar, double* site_bar, void* ws, size_t ws_bytes) {
+  VjpView v;
+  int rc = vjp_view(ctx, &v);
+  if (rc) return rc;
+  if (check_cfg(&v.cfg))
+    return (ctm_status)vjp_fail(ctx, CTM_E_ARG,
+                                "the energy gradient needs an iPEPS site (d >= 1), SI projectors, "
+                                "float64 contractions, the stabilised update and no lattice symmetry");
+  const Dims m = dims_of(v.cfg);
+  EBufs b;
+  const size_t need = ecarve(m, &b, nullptr, nullptr);
+  if (ws_bytes < need)
+    return (ctm_status)vjp_fail(ctx, CTM_E_ARG, "adjoint workspace too small (need " +
+                                                    std::to_string(need) + " bytes)");
+  Run r;
+  r.c = ctx;
+  r.st = v.st;
+  const size_t x = m.x, Dl = m.Dl, N = m.N, k = m.k, D4 = (size_t)m.D * m.D * m.D * m.D;
+  const size_t nstate = 4 * x * x + 4 * x * Dl * x + 8 * N * k + 4;
+  double chi_env = 0.0;
+  if (hipMemcpyAsync(&chi_env, state + (nstate - 4), sizeof(double), hipMemcpyDeviceToHost, v.st) !=
+          hipSuccess ||
+      hipStreamSynchronize(v.st) != hipSuccess)
+    return (ctm_status)vjp_fail(ctx, CTM_E_DEVICE, "reading chi_env of the state failed");
+  if ((int)chi_env != m.x)
+    return (ctm_status)vjp_fail(ctx, CTM_E_STATE, "the energy gradient needs chi_env == chi");
+  ecarve(m, &b, (char*)ws, &r.reg);
+  r.reg.push_back({(uintptr_t)state, (uintptr_t)(state + nstate)});
+  r.reg.push_back({(uintptr_t)state_bar, (uintptr_t)(state_bar + nstate)});
+  r.reg.push_back({(uintptr_t)site_bar, (uintptr_t)(site_bar + m.d * D4)});
+  r.reg.push_back({(uintptr_t)v.A_site, (uintptr_t)(v.A_site + m.d * D4)});
+  const double *C[4], *T[4];
+  double *Cb[4], *Tb[4];
+  {
+    const double* p = state;
+    double* q = state_bar;
+    for (int i = 0; i < 4; ++i, p += x * x, q += x * x) {
+      C[i] = p;
+      Cb[i] = q;
+    }
+    for (int i = 0; i < 4; ++i, p += x * Dl * x, q += x * Dl * x) {
+      T[i] = p;
+      Tb[i] = q;
+    }
+  }
+  VTRY(fill(r, state_bar, (long)nstate, 0.0));
+  const int n = b.n;
+  std::vector<double> op(op_host, op_host + n * n), E(n * n), Eb;
+  double total = 0.0;
+  for (int dir = 0; dir < 2; ++dir) {
+    // dir 0: horizontal pair; dir 1: vertical pair = horizontal pair of the
+    // turned network (slot i holds corner / edge i+1, site legs rotated)
+    const double* Cs[4];
+    const double* Ts[4];
+    double* Cbs[4];
+    double* Tbs[4];
+    for (int i = 0; i < 4; ++i) {
+      const int j = dir ? md(i + 1) : i;
+      Cs[i] = C[j];
+      Ts[i] = T[j];
+      Cbs[i] = Cb[j];
+      Tbs[i] = Tb[j];
+    }
+    const double* site = v.A_site;
+    if (dir) {
+      // Ar[s, i1, i2, i3, i4] = A[s, u = i2, l = i3, d = i4, r = i1]
+      const long D = m.D;
+      for (int s = 0; s < m.d; ++s)
+        VTRY(gather(r, v.A_site + s * D4, b.Ar + s * D4, (int)D, (int)D, (int)D, (int)D, 1, D * D * D,
+                    D * D, D));
+      site = b.Ar;
+    }
+    VTRY(open_layers(r, m, b, site));
+    VTRY(echain_fwd(r, m, b, Cs, Ts));
+    CTM_HIP_TRY(hipMemcpyAsync(E.data(), b.E, n * n * sizeof(double), hipMemcpyDeviceToHost, r.st));
+    CTM_HIP_TRY(hipStreamSynchronize(r.st));
+    total += bond_value_and_bar(E, op.data(), m.d, Eb);
+    CTM_HIP_TRY(hipMemcpyAsync(b.Eb, Eb.data(), n * n * sizeof(double), hipMemcpyHostToDevice, r.st));
+    for (int st = 0; st < n; ++st) VTRY(fill(r, b.xb[st], (long)Dl * Dl * Dl * Dl, 0.0));
+    VTRY(echain_bwd(r, m, b, Cs, Ts, Cbs, Tbs));
+    if (!dir) {
+      VTRY(open_vjp(r, m, b, v.A_site, site_bar));
+    } else {
+      VTRY(fill(r, b.Abr, (long)(m.d * D4), 0.0));
+      VTRY(open_vjp(r, m, b, b.Ar, b.Abr));
+      // A_bar[s,u,l,d,r] += Ar_bar[s, r, u, l, d]
+      const long D = m.D;
+      for (int s = 0; s < m.d; ++s)
+        VTRY(gather(r, b.Abr + s * D4, site_bar + s * D4, (int)D, (int)D, (int)D, (int)D, D * D, D, 1,
+                    D * D * D, true));
+    }
+  }
+  if (hipStreamSynchronize(v.st) != hipSuccess)
+    return vjp_fail(ctx, CTM_E_DEVICE, "synchronisation failed");
+  if (e_out) *e_out = total;
+  return CTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctm_status ctm_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_host, double* e_out,
+                          double* state_bar, double* site_bar, void* ws, size_t ws_bytes) {
+  if (!ctx || !state || !op_host || !state_bar || !site_bar || !ws) {
+    set_thread_error("null argument");
+    return CTM_E_ARG;
+  }
+  return (ctm_status)energy_vjp_impl(ctx, state, op_host, e_out, state_bar, site_bar, ws, ws_bytes);
 }
 
 }  // extern "C"

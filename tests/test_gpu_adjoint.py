@@ -137,3 +137,66 @@ def test_fixed_point_gradient_matches_finite_differences_of_converged_environmen
         an = float((site_bar * d).sum())
         print(trial, fd, an)
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1.0), (trial, fd, an)
+
+
+@pytest.mark.parametrize("D,chi", [(2, 4), (3, 9)])
+def test_energy_gradient_matches_autograd_reference(D, chi):
+    A, C, T, X, Y = make_state(D, chi, 4)
+    cfg = P.Config(d=2, D=D, chi=chi, p=4, n_si=2)
+    ctx = P.Ctm(cfg, torch.from_numpy(A).to(torch.device("cuda", 0)))
+    state = torch.from_numpy(ctx.pack_state(C, T, np.stack(X), np.stack(Y)))
+    h = S.heisenberg_bond()
+    e, bar, site_bar = ctx.energy_vjp(state, h)
+    ref_e, gC, gT, gA = J.energy_vjp(C, T, A, h)
+    assert abs(e - ref_e) <= 1e-12 * max(1.0, abs(ref_e))
+    b = bar.cpu().numpy()
+    assert not b[-4:].any()
+    b[-4] = chi
+    g = ctx.unpack_state(b)
+    errs = {"C": max(rel(a, r) for a, r in zip(g["C"], gC)),
+            "T": max(rel(a, r) for a, r in zip(g["T"], gT)),
+            "A": rel(site_bar.cpu().numpy(), gA)}
+    print(errs)
+    assert all(v <= 1e-10 for v in errs.values()), errs
+    assert not g["X"].any() and not g["Yt"].any()
+
+
+def test_gradient_of_the_converged_energy_matches_finite_differences():
+    """The full gradient of the converged Heisenberg bond energy with respect
+    to the site tensor (direct term + fixed-point term, eq. implicit)
+    against central differences of converged GPU runs."""
+    D, chi, p = 2, 8, 4
+    A = S.product_plus_noise_site(2, D, 2, noise=0.3)
+    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2)
+    N, k = cfg.N, cfg.k
+    X0 = np.stack([S.gaussian_block(N, k, 20 + b) for b in range(4)])
+    Y0 = np.stack([S.gaussian_block(N, k, 30 + b) for b in range(4)])
+    h = S.heisenberg_bond()
+    dev = torch.device("cuda", 0)
+
+    def converged(site):
+        ctx = P.Ctm(cfg, torch.from_numpy(site).to(dev))
+        ctx.set_isometries(torch.from_numpy(X0).to(dev), torch.from_numpy(Y0).to(dev))
+        r = ctx.converge(1e-14, 400)
+        assert r["delta"] < 1e-12, r
+        return ctx
+
+    ctx = converged(A)
+    e, grad, passes = ctx.energy_gradient(h)
+    grad = grad.cpu().numpy()
+    eh = ctx.observable(P.OBS_BOND_H, h)[0] + ctx.observable(P.OBS_BOND_V, h)[0]
+    assert abs(e - eh) <= 1e-12
+    print("energy", e, "passes", passes)
+    rng = np.random.default_rng(21)
+    for trial in range(2):
+        d = rng.standard_normal(A.shape)
+        hh = 1e-5
+
+        def energy(site):
+            c = converged(site)
+            return c.observable(P.OBS_BOND_H, h)[0] + c.observable(P.OBS_BOND_V, h)[0]
+
+        fd = (energy(A + hh * d) - energy(A - hh * d)) / (2 * hh)
+        an = float((grad * d).sum())
+        print(trial, fd, an)
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3), (trial, fd, an)
