@@ -181,6 +181,9 @@ def main():
                          "moves align to this mean sin^2 (the paper's recycling); 0: n_si "
                          "steps every move")
     ap.add_argument("--min-si-moves", type=int, default=3)
+    ap.add_argument("--vjp", type=int, default=0,
+                    help="time this many adjoints of the move (ctm_move_vjp) at the state after "
+                         "the timed moves (0: skip)")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--pinv-rtol", type=float, default=1e-12)
     ap.add_argument("--svd-moves", type=int, default=2, help="full-SVD comparator moves (0: skip)")
@@ -297,6 +300,23 @@ def main():
     total_flops = sum(e["flops"] for e in prof) / prof_steps
     breakdown = {e["name"]: round(e["ms"] / prof_steps, 3) for e in prof}
 
+    vjp = None
+    if args.vjp > 0 and args.prec == "f64":
+        st = torch.from_numpy(ctx.get_state()).to(dev)
+        bar = torch.randn(st.numel(), dtype=torch.float64, device=dev,
+                          generator=torch.Generator(device=dev).manual_seed(7))
+        ctx.move_vjp(st, bar, want_out=False)               # workspace and warm-up
+        torch.cuda.synchronize()
+        tv = []
+        for _ in range(args.vjp):
+            t1 = time.perf_counter()
+            ctx.move_vjp(st, bar, want_out=False)           # returns after the stream finished
+            tv.append(time.perf_counter() - t1)
+        vjp = {"ms_per_vjp": round(1e3 * float(np.median(tv)), 2), "count": args.vjp,
+               "ratio_to_move": round(1e3 * float(np.median(tv)) / ms_step, 2),
+               "what": "reverse pass of one SI move incl. its recomputed forward (tape)"}
+        log(f"adjoint: {vjp['ms_per_vjp']} ms per move VJP ({vjp['ratio_to_move']}x the move)")
+
     svd = None
     if args.svd_moves > 0:
         cfg_s = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="svd",
@@ -342,6 +362,7 @@ def main():
         "phase_ms_per_move": breakdown,
         "roofline": roofline,
         "full_svd_same_gpu": svd,
+        "adjoint": vjp,
         "speedup_vs_full_svd": None if svd is None else round(value / svd["moves_per_s"], 2),
         "cpu_baseline": cpu,
     }
