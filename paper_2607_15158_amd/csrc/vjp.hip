@@ -283,6 +283,9 @@ struct Bufs {
   double *vscb[4], *uscb[4], *vscT[4], *uscT[4], *ub[4], *vb[4], *sb[4];
   double *smallT;                         // x x x / k x k transposes
   double *fp_v[2], *fp_dot;               // fixed-point iteration: cotangent ping-pong
+  double *PTs[4], *QTs[4];                // per corner: 8 transposed blocks stacked along K
+  double *Ga[4], *Gb[4];                  // per corner / edge N x N scratch (batched launches)
+  double *apb4[4];                        // per corner / edge cotangents of the permuted a
   void *qr_ws, *svd_ws;
 };
 
@@ -392,6 +395,13 @@ size_t carve(const Dims& m, Bufs* b, char* base, std::vector<std::pair<uintptr_t
   b->fp_v[0] = cv.take(nstate);
   b->fp_v[1] = cv.take(nstate);
   b->fp_dot = cv.take(8);
+  for (int i = 0; i < 4; ++i) {
+    b->PTs[i] = cv.take(8 * Nk);
+    b->QTs[i] = cv.take(8 * Nk);
+    b->Ga[i] = cv.take(NN);
+    b->Gb[i] = cv.take(NN);
+    b->apb4[i] = cv.take(Dl * Dl * Dl * Dl);
+  }
   b->qr_ws = cv.bytes(qr_workspace_bytes(8, m.N, m.k));
   b->svd_ws = cv.bytes(svd_workspace_bytes(4, m.k));
   return cv.off + 256;
@@ -865,50 +875,68 @@ int backward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in,
     g4.accumulate = 1;
     VTRY(gemm(r, g4));
   }
-  // T_j' = P_r^T Z2,  Z2 = perm(Z1 ap_(j+1)),  Z1 = T_j P_l
-  for (int j = 0; j < 4; ++j) {
-    const int jn = md(j + 1);
-    VTRY(transpose(r, b.Thb[j], b.St, x, (long)Dl * x));
-    GemmBatch g = rowmajor(1, N, x, Dl * x, (long)Dl * x, x, x);
-    g.A[0] = b.Z2[j];
-    g.B[0] = b.St;
-    g.C[0] = b.Prtb[j];
+  // T_j' = P_r^T Z2,  Z2 = perm(Z1 ap_(j+1)),  Z1 = T_j P_l; the four edges
+  // go through each step in one launch
+  {
+    const long D2 = (long)Dl * Dl;
+    for (int j = 0; j < 4; ++j) VTRY(transpose(r, b.Thb[j], b.Gb[j], x, (long)Dl * x));
+    GemmBatch g = rowmajor(4, N, x, Dl * x, (long)Dl * x, x, x);
     g.accumulate = 1;
+    for (int j = 0; j < 4; ++j) {
+      g.A[j] = b.Z2[j];
+      g.B[j] = b.Gb[j];
+      g.C[j] = b.Prtb[j];
+    }
     VTRY(gemm(r, g));
-    GemmBatch g2 = rowmajor(1, N, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
-    g2.A[0] = b.Prt[j];
-    g2.B[0] = b.Thb[j];
-    g2.C[0] = b.Sa;                                   // Z2_bar [(b,l)][(d,g')]
+    GemmBatch g2 = rowmajor(4, N, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
+    for (int j = 0; j < 4; ++j) {
+      g2.A[j] = b.Prt[j];
+      g2.B[j] = b.Thb[j];
+      g2.C[j] = b.Ga[j];                                   // Z2_bar [(b,l)][(d,g')]
+    }
     VTRY(gemm(r, g2));
-    VTRY(gather(r, b.Sa, b.Sb, x, x, Dl, Dl, (long)Dl * Dl * x, 1, (long)Dl * x, x));  // [(b,g')][(l,d)]
-    GemmBatch g3 = rowmajor(1, Dl * Dl, Dl * Dl, x * x, (long)Dl * Dl, (long)Dl * Dl, (long)Dl * Dl);
-    g3.A[0] = b.Z1[j];
-    g3.transA[0] = 1;
-    g3.B[0] = b.Sb;
-    g3.C[0] = b.apb;
+    for (int j = 0; j < 4; ++j)                            // -> [(b,g')][(l,d)]
+      VTRY(gather(r, b.Ga[j], b.Gb[j], x, x, Dl, Dl, D2 * x, 1, (long)Dl * x, x));
+    GemmBatch g3 = rowmajor(4, (int)D2, (int)D2, x * x, D2, D2, D2);
+    for (int j = 0; j < 4; ++j) {
+      g3.A[j] = b.Z1[j];
+      g3.transA[j] = 1;
+      g3.B[j] = b.Gb[j];
+      g3.C[j] = b.apb4[j];
+    }
     VTRY(gemm(r, g3));
-    long inv[4];
-    inverse_strides(v.ap_strides[jn], Dl, inv);
-    VTRY(gather(r, b.apb, b.ab, Dl, Dl, Dl, Dl, inv[0], inv[1], inv[2], inv[3], true));
-    GemmBatch g4 = rowmajor(1, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, (long)Dl * Dl);
-    g4.A[0] = b.Sb;
-    g4.B[0] = b.apT[jn];
-    g4.C[0] = b.Sa;                                   // Z1_bar [(b,g')][(u,r)]
+    for (int j = 0; j < 4; ++j) {
+      long inv[4];
+      inverse_strides(v.ap_strides[md(j + 1)], Dl, inv);
+      VTRY(gather(r, b.apb4[j], b.ab, Dl, Dl, Dl, Dl, inv[0], inv[1], inv[2], inv[3], true));
+    }
+    GemmBatch g4 = rowmajor(4, x * x, (int)D2, (int)D2, D2, D2, D2);
+    for (int j = 0; j < 4; ++j) {
+      g4.A[j] = b.Gb[j];
+      g4.B[j] = b.apT[md(j + 1)];
+      g4.C[j] = b.Ga[j];                                   // Z1_bar [(b,g')][(u,r)]
+    }
     VTRY(gemm(r, g4));
-    VTRY(gather(r, b.Sa, b.Sb, x, Dl, Dl, x, (long)x * Dl * Dl, Dl, 1, (long)Dl * Dl));  // [(b,u)][(r,g')]
-    VTRY(transpose(r, b.Pl[j], b.St, x, (long)Dl * x));
-    GemmBatch g5 = rowmajor(1, x * Dl, x, Dl * x, (long)Dl * x, x, x);
-    g5.A[0] = b.Sb;
-    g5.B[0] = b.St;
-    g5.C[0] = Tb_out[j];
+    for (int j = 0; j < 4; ++j) {                          // -> [(b,u)][(r,g')]
+      VTRY(gather(r, b.Ga[j], b.Gb[j], x, Dl, Dl, x, (long)x * D2, Dl, 1, D2));
+      VTRY(transpose(r, b.Pl[j], b.Ga[j], x, (long)Dl * x));
+    }
+    GemmBatch g5 = rowmajor(4, x * Dl, x, Dl * x, (long)Dl * x, x, x);
     g5.accumulate = 1;
+    for (int j = 0; j < 4; ++j) {
+      g5.A[j] = b.Gb[j];
+      g5.B[j] = b.Ga[j];
+      g5.C[j] = Tb_out[j];
+    }
     VTRY(gemm(r, g5));
-    GemmBatch g6 = rowmajor(1, x, Dl * x, x * Dl, x, (long)Dl * x, (long)Dl * x);
-    g6.A[0] = in.T[j];
-    g6.transA[0] = 1;
-    g6.B[0] = b.Sb;
-    g6.C[0] = b.Plb[j];
+    GemmBatch g6 = rowmajor(4, x, Dl * x, x * Dl, x, (long)Dl * x, (long)Dl * x);
     g6.accumulate = 1;
+    for (int j = 0; j < 4; ++j) {
+      g6.A[j] = in.T[j];
+      g6.transA[j] = 1;
+      g6.B[j] = b.Gb[j];
+      g6.C[j] = b.Plb[j];
+    }
     VTRY(gemm(r, g6));
   }
   // projectors, recycled blocks, rho and its SVD, per bond (batched over 4)
@@ -1169,19 +1197,14 @@ int backward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in,
           }
         }
         // corner cotangents: plain H_out = Ct H_in gives Ct_bar += H_bar H_in^T;
-        // transposed H_out = Ct^T H_in gives Ct_bar += H_in H_bar^T
-        for (int j = 0; j < 8; ++j)
-          VTRY(transpose(r, trn[j] ? b.Hb[j] : hin[j], b.tr[j], N, k));
-        for (int half = 0; half < 2; ++half) {
-          GemmBatch gc = rowmajor(4, N, N, k, k, N, N);
-          gc.accumulate = 1;
-          for (int q = 0; q < 4; ++q) {
-            const int j = half * 4 + q;
-            gc.A[q] = trn[j] ? hin[j] : b.Hb[j];
-            gc.B[q] = b.tr[j];
-            gc.C[q] = b.Ctb[ci[j]];
-          }
-          VTRY(gemm(r, gc));
+        // transposed H_out = Ct^T H_in gives Ct_bar += H_in H_bar^T.  Both
+        // factors go transposed into the corner's K-stacks (slot 2t for the X
+        // side, 2t+1 for the Y side: each corner meets one of each per t);
+        // the stacks are contracted once per half step below.
+        for (int j = 0; j < 8; ++j) {
+          const long slot = (2 * t + (j >= 4 ? 1 : 0)) * Nk;
+          VTRY(transpose(r, trn[j] ? hin[j] : b.Hb[j], b.PTs[ci[j]] + slot, N, k));
+          VTRY(transpose(r, trn[j] ? b.Hb[j] : hin[j], b.QTs[ci[j]] + slot, N, k));
         }
         GemmBatch gb = rowmajor(8, N, k, N, N, k, k);
         for (int j = 0; j < 8; ++j) {
@@ -1193,6 +1216,18 @@ int backward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in,
         VTRY(gemm(r, gb, true));
         for (int j = 0; j < 8; ++j) std::swap(b.Hb[j], b.Yq[j]);
       }
+      // Ct_bar[i] += sum over the 8 stacked pairs P Q^T = PTs^T QTs  (K = 8k)
+      {
+        GemmBatch gc = rowmajor(4, N, N, 8 * k, N, N, N);
+        gc.accumulate = 1;
+        for (int i = 0; i < 4; ++i) {
+          gc.A[i] = b.PTs[i];
+          gc.transA[i] = 1;
+          gc.B[i] = b.QTs[i];
+          gc.C[i] = b.Ctb[i];
+        }
+        VTRY(gemm(r, gc));
+      }
       for (int j = 0; j < 8; ++j) std::swap(b.Qb[j], b.Hb[j]);
     }
   }
@@ -1200,52 +1235,66 @@ int backward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in,
     VTRY(copy(r, b.Qb[i], Xb_out[i], Nk));
     VTRY(copy(r, b.Qb[4 + i], Yb_out[i], Nk));
   }
-  // enlarged corners
-  for (int i = 0; i < 4; ++i) {
-    const int ip = md(i - 1);
-    // Gp[(x_in,y),(o1,o2)] from Ct_bar[(x_in,o1),(y,o2)]
-    VTRY(gather(r, b.Ctb[i], b.Sa, x, x, Dl, Dl, (long)Dl * N, Dl, N, 1));
-    GemmBatch g = rowmajor(1, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, (long)Dl * Dl);
-    g.A[0] = b.Sa;
-    g.B[0] = b.apT[i];
-    g.C[0] = b.Sb;                                     // W_bar [(x_in,y)][(p,q)]
+  // enlarged corners, the four corners batched in every step
+  {
+    const long D2 = (long)Dl * Dl;
+    for (int i = 0; i < 4; ++i)   // Gp[(x_in,y),(o1,o2)] from Ct_bar[(x_in,o1),(y,o2)]
+      VTRY(gather(r, b.Ctb[i], b.Ga[i], x, x, Dl, Dl, (long)Dl * N, Dl, N, 1));
+    GemmBatch g = rowmajor(4, x * x, (int)D2, (int)D2, D2, D2, D2);
+    for (int i = 0; i < 4; ++i) {
+      g.A[i] = b.Ga[i];
+      g.B[i] = b.apT[i];
+      g.C[i] = b.Gb[i];                                    // W_bar [(x_in,y)][(p,q)]
+    }
     VTRY(gemm(r, g));
-    GemmBatch g2 = rowmajor(1, Dl * Dl, Dl * Dl, x * x, (long)Dl * Dl, (long)Dl * Dl, (long)Dl * Dl);
-    g2.A[0] = b.Wc[i];
-    g2.transA[0] = 1;
-    g2.B[0] = b.Sa;
-    g2.C[0] = b.apb;
+    GemmBatch g2 = rowmajor(4, (int)D2, (int)D2, x * x, D2, D2, D2);
+    for (int i = 0; i < 4; ++i) {
+      g2.A[i] = b.Wc[i];
+      g2.transA[i] = 1;
+      g2.B[i] = b.Ga[i];
+      g2.C[i] = b.apb4[i];
+    }
     VTRY(gemm(r, g2));
-    long inv[4];
-    inverse_strides(v.ap_strides[i], Dl, inv);
-    VTRY(gather(r, b.apb, b.ab, Dl, Dl, Dl, Dl, inv[0], inv[1], inv[2], inv[3], true));
-    // Wbp[(x_in,p),(q,y)] from W_bar[(x_in,y),(p,q)]
-    VTRY(gather(r, b.Sb, b.Sa, x, Dl, Dl, x, (long)x * Dl * Dl, Dl, 1, (long)Dl * Dl));
-    VTRY(transpose(r, b.CT[i], b.St, x, (long)Dl * x));
-    GemmBatch g3 = rowmajor(1, x * Dl, x, Dl * x, (long)Dl * x, x, x);
-    g3.A[0] = b.Sa;
-    g3.B[0] = b.St;
-    g3.C[0] = Tb_out[ip];
+    for (int i = 0; i < 4; ++i) {
+      long inv[4];
+      inverse_strides(v.ap_strides[i], Dl, inv);
+      VTRY(gather(r, b.apb4[i], b.ab, Dl, Dl, Dl, Dl, inv[0], inv[1], inv[2], inv[3], true));
+      // Wbp[(x_in,p),(q,y)] from W_bar[(x_in,y),(p,q)]
+      VTRY(gather(r, b.Gb[i], b.Ga[i], x, Dl, Dl, x, (long)x * D2, Dl, 1, D2));
+      VTRY(transpose(r, b.CT[i], b.Gb[i], x, (long)Dl * x));
+    }
+    GemmBatch g3 = rowmajor(4, x * Dl, x, Dl * x, (long)Dl * x, x, x);
     g3.accumulate = 1;
+    for (int i = 0; i < 4; ++i) {
+      g3.A[i] = b.Ga[i];
+      g3.B[i] = b.Gb[i];
+      g3.C[i] = Tb_out[md(i - 1)];
+    }
     VTRY(gemm(r, g3));
-    GemmBatch g4 = rowmajor(1, x, Dl * x, x * Dl, x, (long)Dl * x, (long)Dl * x);
-    g4.A[0] = in.T[ip];
-    g4.transA[0] = 1;
-    g4.B[0] = b.Sa;
-    g4.C[0] = b.Sb;                                    // CT_bar [a][(q,y)]
+    GemmBatch g4 = rowmajor(4, x, Dl * x, x * Dl, x, (long)Dl * x, (long)Dl * x);
+    for (int i = 0; i < 4; ++i) {
+      g4.A[i] = in.T[md(i - 1)];
+      g4.transA[i] = 1;
+      g4.B[i] = b.Ga[i];
+      g4.C[i] = b.Gb[i];                                   // CT_bar [a][(q,y)]
+    }
     VTRY(gemm(r, g4));
-    VTRY(transpose(r, in.T[i], b.St, x, (long)Dl * x));
-    GemmBatch g5 = rowmajor(1, x, x, Dl * x, (long)Dl * x, x, x);
-    g5.A[0] = b.Sb;
-    g5.B[0] = b.St;
-    g5.C[0] = Cb_out[i];
+    for (int i = 0; i < 4; ++i) VTRY(transpose(r, in.T[i], b.Ga[i], x, (long)Dl * x));
+    GemmBatch g5 = rowmajor(4, x, x, Dl * x, (long)Dl * x, x, x);
+    for (int i = 0; i < 4; ++i) {
+      g5.A[i] = b.Gb[i];
+      g5.B[i] = b.Ga[i];
+      g5.C[i] = Cb_out[i];
+    }
     VTRY(gemm(r, g5));
-    GemmBatch g6 = rowmajor(1, x, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
-    g6.A[0] = in.C[i];
-    g6.transA[0] = 1;
-    g6.B[0] = b.Sb;
-    g6.C[0] = Tb_out[i];
+    GemmBatch g6 = rowmajor(4, x, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
     g6.accumulate = 1;
+    for (int i = 0; i < 4; ++i) {
+      g6.A[i] = in.C[i];
+      g6.transA[i] = 1;
+      g6.B[i] = b.Gb[i];
+      g6.C[i] = Tb_out[i];
+    }
     VTRY(gemm(r, g6));
   }
   // double layer: A_bar[s, ket] += sum_bra (ab[ket,bra] + ab[bra,ket]) A[s, bra]
