@@ -181,7 +181,7 @@ def main():
                          "moves align to this mean sin^2 (the paper's recycling); 0: n_si "
                          "steps every move")
     ap.add_argument("--min-si-moves", type=int, default=3)
-    ap.add_argument("--vjp", type=int, default=0,
+    ap.add_argument("--vjp", type=int, default=3,
                     help="time this many adjoints of the move (ctm_move_vjp) at the state after "
                          "the timed moves (0: skip)")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])

@@ -198,7 +198,11 @@ ctm_status ctm_state_size(const ctm_ctx* ctx, size_t* n);
 
 /* Copies the state vector to / from host memory (n doubles, see
  * ctm_state_size).  Corner and edge blocks are laid out for chi, with the
- * leading chi_env x ... sub-block meaningful during growth.  Synchronises. */
+ * leading chi_env x ... sub-block meaningful during growth.  X, Yt are the
+ * blocks the next SI move starts from: while the environment is still
+ * growing, the start blocks given to ctm_set_isometries (zeros if none were
+ * given; on set, non-zero blocks become the pending start blocks).
+ * Synchronises. */
 ctm_status ctm_get_state(ctm_ctx* ctx, double* host, size_t n);
 ctm_status ctm_set_state(ctm_ctx* ctx, const double* host, size_t n);
 

@@ -1621,11 +1621,16 @@ ctm_status ctm_get_state(ctm_ctx* c, double* host, size_t n) {
     if (hipMemcpyAsync(p, c->T[c->cur][i], x * Dl * x * 8, hipMemcpyDeviceToHost, c->st) !=
         hipSuccess)
       return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  // the blocks the next SI move starts from: the caller's start blocks while
+  // they are pending, none (zeros) before any exist
+  const bool blocks = c->iso_pending || c->si_ready;
   for (int i = 0; i < 4; ++i, p += N * k)
-    if (hipMemcpyAsync(p, c->X[i], N * k * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess)
+    if (blocks && hipMemcpyAsync(p, c->iso_pending ? c->X0[i] : c->X[i], N * k * 8,
+                                 hipMemcpyDeviceToHost, c->st) != hipSuccess)
       return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
   for (int i = 0; i < 4; ++i, p += N * k)
-    if (hipMemcpyAsync(p, c->Yt[i], N * k * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess)
+    if (blocks && hipMemcpyAsync(p, c->iso_pending ? c->Yt0[i] : c->Yt[i], N * k * 8,
+                                 hipMemcpyDeviceToHost, c->st) != hipSuccess)
       return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
   if (hipStreamSynchronize(c->st) != hipSuccess)
     return (ctm_status)fail(c, CTM_E_DEVICE, "synchronisation failed");
@@ -1655,19 +1660,24 @@ ctm_status ctm_set_state(ctm_ctx* c, const double* host, size_t n) {
   for (int i = 0; i < 4; ++i, p += chi * Dl * chi)
     if (hipMemcpy(c->T[c->cur][i], p, (size_t)x * Dl * x * 8, hipMemcpyHostToDevice) != hipSuccess)
       return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+  // blocks: the current ones at chi_env == chi; during growth, non-zero
+  // blocks are the pending start blocks of the first SI move
+  bool has_blocks = false;
+  for (size_t i = 0; i < 8 * N * k && !has_blocks; ++i) has_blocks = p[i] != 0.0;
+  const bool grow = x < (int)chi;
   for (int i = 0; i < 4; ++i, p += N * k)
-    if (hipMemcpy(c->X[i], p, N * k * 8, hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(grow ? c->X0[i] : c->X[i], p, N * k * 8, hipMemcpyHostToDevice) != hipSuccess)
       return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
   for (int i = 0; i < 4; ++i, p += N * k)
-    if (hipMemcpy(c->Yt[i], p, N * k * 8, hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(grow ? c->Yt0[i] : c->Yt[i], p, N * k * 8, hipMemcpyHostToDevice) != hipSuccess)
       return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
   c->chi_env = x;
   c->si_moves = (long)p[1];
   c->recycling = c->cfg.recycle_sin2 > 0 && p[2] != 0.0;
   c->si_upd = (int)p[3];
   c->last_si_delta = -1.0;
-  c->si_ready = (x == (int)chi);
-  c->iso_pending = false;
+  c->si_ready = !grow;
+  c->iso_pending = grow && has_blocks;
   // spectra of the restored corners become the reference of the next delta
   const int rs = spectra(c, c->cur, x);
   if (rs) return (ctm_status)(rs == 1 ? CTM_E_ARG : rs);

@@ -417,3 +417,25 @@ def test_recycle_mode_follows_the_oracle(D, chi, p, noise, seed):
         assert abs(got - O.bond_value(env, A, op, "h")) <= 1e-9
     st = ctx.unpack_state(ctx.get_state())
     assert st["recycling"] == (hist[-1]["n_si"] == 0)
+
+
+def test_state_during_growth_holds_the_start_blocks():
+    """Before the first SI move the state's blocks are the caller's start
+    blocks (never unwritten workspace), and a state saved during growth and
+    restored into a fresh context continues exactly as the original run."""
+    A = S.product_plus_noise_site(2, 2, 7, noise=0.3)
+    cfg = P.Config(d=2, D=2, chi=20, p=4, n_si=2)     # growth: chi_env 4 -> 16 -> 20
+    a, si = make(cfg, A)
+    b, _ = make(cfg, A)
+    a.move()
+    b.move()
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa, sb)
+    st = a.unpack_state(sa)
+    assert st["chi_env"] < cfg.chi
+    assert np.array_equal(st["X"], np.stack(si.X)) and np.array_equal(st["Yt"], np.stack(si.Yt))
+    c = P.Ctm(cfg, dev(A))
+    c.set_state(sa)
+    for _ in range(4):
+        assert a.move() == c.move()
+    assert np.array_equal(a.get_state(), c.get_state())
