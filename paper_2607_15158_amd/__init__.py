@@ -402,6 +402,38 @@ class Ctm:
                  "flops": arr[i].flops, "bytes": arr[i].bytes} for i in range(n.value)]
 
 
+def converged_energy(A, cfg: Config, op, X0, Yt0, tol: float = 1e-12, max_moves: int = 400,
+                     fp_tol: float = 1e-12, fp_max_iter: int = 400):
+    """Energy <op>_H + <op>_V of the converged environment of the site tensor
+    ``A`` (a float64 device tensor with ``requires_grad``), differentiable:
+    the backward pass is the energy's gradient plus the fixed-point term of
+    eq. implicit, computed by the library (ctm_energy_vjp,
+    ctm_fixed_point_vjp) together with the value in the forward call.
+    ``X0, Yt0`` are the start blocks of the SI moves (4 x N x k each)."""
+    import torch
+
+    class _ConvergedEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, site):
+            c = Ctm(cfg, site.detach())
+            c.set_isometries(torch.as_tensor(X0).to(site.device), torch.as_tensor(Yt0).to(site.device))
+            r = c.converge(tol, max_moves)
+            if not r["converged"]:
+                raise CtmError(CTM_E_NOT_CONVERGED, f"no convergence in {max_moves} moves "
+                                                    f"(delta {r['delta']:.2e})")
+            e, grad, _ = c.energy_gradient(op, fp_tol, fp_max_iter)
+            ctx.save_for_backward(grad)
+            c.close()
+            return torch.tensor(e, dtype=torch.float64, device=site.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            (grad,) = ctx.saved_tensors
+            return g * grad
+
+    return _ConvergedEnergy.apply(A)
+
+
 def _ptr_array(ts):
     arr = (ctypes.c_void_p * len(ts))()
     for i, t in enumerate(ts):

@@ -200,3 +200,28 @@ def test_gradient_of_the_converged_energy_matches_finite_differences():
         an = float((grad * d).sum())
         print(trial, fd, an)
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3), (trial, fd, an)
+
+
+def test_converged_energy_as_a_torch_function_descends():
+    """The differentiable converged energy plugs into torch autograd: its
+    gradient equals the library's, and a small step against it lowers the
+    converged energy by the first-order amount."""
+    D, chi, p = 2, 8, 4
+    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2)
+    N, k = cfg.N, cfg.k
+    X0 = np.stack([S.gaussian_block(N, k, 20 + b) for b in range(4)])
+    Y0 = np.stack([S.gaussian_block(N, k, 30 + b) for b in range(4)])
+    h = S.heisenberg_bond()
+    dev = torch.device("cuda", 0)
+    A = torch.from_numpy(S.product_plus_noise_site(2, D, 2, noise=0.3)).to(dev).requires_grad_(True)
+    e = P.converged_energy(A, cfg, h, X0, Y0)
+    e.backward()
+    g = A.grad.detach().clone()
+    step = 1e-4 * g / g.norm()
+    with torch.no_grad():
+        e2 = P.converged_energy(A - step, cfg, h, X0, Y0)
+    drop = float(e.detach() - e2)
+    first_order = float((g * step).sum())
+    print(float(e), float(e2), drop, first_order)
+    assert drop > 0
+    assert abs(drop - first_order) <= 1e-2 * first_order
