@@ -39,9 +39,10 @@ reason in the design notes of the repository):
   largest magnitude (roundoff-level ties are resolved by index).
 * Pseudo-inverse: ``s_i <= eps * s_1`` gives ``s_i^-1/2 := 0``.
 * Normalisation: every new ``C`` and ``T`` is scaled to unit Frobenius norm.
-* Growth phase: while the environment dimension is below ``chi`` the move
-  uses full-SVD projectors, or no truncation at all when ``chi_env * D^2 <=
-  chi``; SI starts at the first move with ``chi_env == chi``.
+* Growth phase: while the environment dimension differs from ``chi`` the
+  move uses full-SVD projectors (this includes an initial boundary larger
+  than ``chi``), or no truncation at all when ``chi_env * D^2 <= chi``; SI
+  starts at the first move with ``chi_env == chi``.
 * Convergence measure ``delta``: max over the four corners of the 2-norm of
   the change of the unit-2-norm, zero-padded singular-value spectrum.
 """
@@ -380,7 +381,7 @@ def ctm_move(env: Env, a: np.ndarray, chi: int, proj: str = "si",
         Pl = [np.eye(N)] * 4
         Prt = [np.eye(N)] * 4
         info["mode"] = "grow"
-    elif proj == "svd" or x < chi:
+    elif proj == "svd" or x != chi:
         Pl, Prt = [], []
         for b in range(4):
             pl, prt, s = svd_projectors(Ct, b, chi, eps)
@@ -618,7 +619,7 @@ def c4v_move(C, T, a, chi, proj="si", X=None, n_si=2):
     mode = "grow"
     if N <= chi:
         P = np.eye(N)
-    elif proj == "svd" or x < chi:
+    elif proj == "svd" or x != chi:
         w, V = np.linalg.eigh(Ct)
         order = _order_abs(w)[:chi]
         P = V[:, order]

@@ -386,3 +386,17 @@ def test_planted_mistakes_are_caught(monkeypatch):
     env, _ = O.run_ctmrg(a, e, 8, proj="si", iso0=iso_for(32, 12), tol=1e-12, max_moves=60)
     zz = O.bond_value(env, A, np.kron(S.pauli("z"), S.pauli("z")), "h")
     assert abs(zz - gold(0.5, "nn_correlation")) > 1e-6 or not np.isfinite(zz)
+
+
+def test_boundary_larger_than_chi_truncates_with_full_svd():
+    """chi = 1 < D^2: the first move truncates the initial boundary with
+    full-SVD projectors; from then on SI moves with k = N reproduce the
+    full-SVD moves (k = N reduces subspace iteration to the SVD)."""
+    A = noisy_site(D=2, seed=5)
+    a, e = O.double_layer(A), S.trace_boundary(2)
+    chi, N = 1, 4
+    env_si, h_si = O.run_ctmrg(a, e, chi, proj="si", iso0=iso_for(N, N), tol=0, max_moves=4)
+    env_sv, h_sv = O.run_ctmrg(a, e, chi, proj="svd", tol=0, max_moves=4)
+    assert [h["mode"] for h in h_si] == ["svd", "si", "si", "si"]
+    for c1, c2 in zip(env_si.C + env_si.T, env_sv.C + env_sv.T):
+        assert np.allclose(c1, c2, atol=1e-12)
