@@ -80,7 +80,8 @@ typedef struct {
   int d;            /* physical dimension; 0 = the network tensor a is given directly    */
   int D;            /* virtual bond dimension of A, or leg dimension of a when d == 0    */
   int chi;          /* environment bond dimension (>= 1)                                 */
-  int p;            /* oversampling of the subspace (>= 0); min(chi + p, N) <= 192       */
+  int p;            /* oversampling of the subspace (>= 0); k = min(chi + p, N) <= 192,
+                       and (SI) the N rows must split into QR leaves of k to 192 rows  */
   int n_si;         /* subspace-iteration steps per move (>= 0)                          */
   int proj;         /* ctm_proj                                                          */
   int prec;         /* ctm_prec                                                          */

@@ -110,6 +110,9 @@ int launch_gemm_si(const GemmBatch& g, hipStream_t s);
 // Householder QR (in place, Q returned with R_ii >= 0) of `count` N x k
 // row-major matrices.  ws must hold qr_workspace_bytes(count, N, k) bytes.
 size_t qr_workspace_bytes(int count, int N, int k);
+// True if N rows split into leaves of k .. 192 rows (every leaf holds a
+// k x k triangle): the shapes launch_qr accepts.
+bool qr_plan_ok(int N, int k);
 int launch_qr(int count, double* const* W, int N, int k, void* ws, hipStream_t s);
 
 // One-sided Jacobi SVD of `count` n x n row-major matrices (see ctm.h).

@@ -207,6 +207,11 @@ int validate(const ctm_config* cfg) {
   const long N = (long)cfg->chi * Dl;
   const long k = std::min<long>(cfg->chi + cfg->p, N);
   if (k > 192) return fail(nullptr, CTM_E_SHAPE, "chi + p must be <= 192");
+  if (cfg->proj == CTM_PROJ_SI && !qr_plan_ok((int)N, (int)k))
+    return fail(nullptr, CTM_E_SHAPE,
+                "no QR leaf partition for N = chi*Dl = " + std::to_string(N) + " rows and k = " +
+                    std::to_string(k) + " columns: the rows must split into leaves of k to 192 "
+                    "rows (reduce p, or choose chi so that such a split exists)");
   if (N > 65536) return fail(nullptr, CTM_E_SHAPE, "chi * Dl must be <= 65536");
   return CTM_OK;
 }

@@ -576,6 +576,12 @@ QrPlan make_plan(int N, int k) {
 
 }  // namespace
 
+bool qr_plan_ok(int N, int k) {
+  if (k <= 0 || N < k || k > kLeafRows) return false;
+  const QrPlan pl = make_plan(N, k);
+  return (N + pl.nb - 1) / pl.nb <= kLeafRows;
+}
+
 size_t qr_workspace_bytes(int count, int N, int k) {
   const QrPlan pl = make_plan(N, k);
   const size_t slots = (size_t)count * pl.P * pl.nb;

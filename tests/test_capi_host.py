@@ -51,7 +51,8 @@ def test_workspace_bytes_scale_and_config3_fits_hbm():
 
 
 @pytest.mark.parametrize("kw", [dict(chi=0), dict(D=0), dict(p=-1), dict(n_si=-1),
-                                dict(chi=180, p=13)])
+                                dict(chi=180, p=13),
+                                dict(D=4, chi=176, p=16)])   # k = 192, N = 2816: no leaf split
 def test_invalid_configs_are_rejected(kw):
     base = dict(d=2, D=2, chi=8, p=4)
     base.update(kw)

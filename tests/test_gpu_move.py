@@ -439,3 +439,57 @@ def test_state_during_growth_holds_the_start_blocks():
     for _ in range(4):
         assert a.move() == c.move()
     assert np.array_equal(a.get_state(), c.get_state())
+
+
+@pytest.mark.parametrize("p", [0, 3])
+def test_single_column_environment(p):
+    """chi = 1 (the smallest environment): the growth move truncates the
+    initial 4-dimensional boundary to one state, then SI moves with
+    k = min(1 + p, N) columns (with p = 3, k = N: the subspace is the whole
+    space)."""
+    A = random_site(2, 5)
+    chi = 1
+    cfg = P.Config(d=2, D=2, chi=chi, p=p, n_si=2)
+    ctx, si = make(cfg, A)
+    a = O.double_layer(A)
+    env = O.initial_env(a, S.trace_boundary(2))
+    _, _, modes = run_pair(ctx, env, a, chi, si, 5, tol=1e-10, check_iso=False)
+    assert [m[0] for m in modes] == [1, 2, 2, 2, 2]
+
+
+@pytest.mark.parametrize("chi,p", [(180, 12), (176, 10)])
+def test_widest_subspace_blocks(chi, p):
+    """The widest blocks the QR leaves and the small SVD take: k = 192 with
+    N = 2880 rows in fifteen leaves of exactly 192 rows, and k = 186 with
+    N = 2816 rows in ragged leaves of 187 and 188 rows.  One SI move from a
+    seeded random environment of full dimension against the oracle's
+    corners (C_i' = P_r Ct_i P_l from its enlarged corners and SI
+    projectors) and the kept columns of the recycled blocks."""
+    D, n_si = 4, 2
+    Dl = D * D
+    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=n_si)
+    N, k = cfg.N, cfg.k
+    assert (N, k) in ((2880, 192), (2816, 186))
+    A = S.product_plus_noise_site(2, D, 3)
+    X = np.stack([S.gaussian_block(N, k, 40 + b) for b in range(4)])
+    Y = np.stack([S.gaussian_block(N, k, 50 + b) for b in range(4)])
+    C = [S.gaussian_block(chi, chi, 60 + i) for i in range(4)]
+    T = [S.gaussian_block(chi * Dl, chi, 70 + i).reshape(chi, Dl, chi) for i in range(4)]
+    ctx = P.Ctm(cfg, dev(A))
+    ctx.set_state(ctx.pack_state(C, T, X, Y))
+    assert ctx.move()["mode"] == 2
+    st = ctx.unpack_state(ctx.get_state())
+    a = O.double_layer(A)
+    Ct = O.enlarged_corners(O.Env([c.copy() for c in C], [t.copy() for t in T]), a)
+    Pl, Prt, Xn = [], [], []
+    for b in range(4):
+        pl, prt, _, xn, _ = O.si_projectors(Ct, b, X[b], Y[b], chi, n_si, 1e-12, True)
+        Pl.append(pl)
+        Prt.append(prt)
+        Xn.append(xn)
+    for i in range(4):
+        Ci = Prt[(i - 1) % 4].T @ Ct[i] @ Pl[i]
+        Ci = Ci / np.linalg.norm(Ci)
+        assert rel(st["C"][i], Ci) <= 1e-10, i
+    for b in range(4):
+        assert rel(st["X"][b][:, :chi], Xn[b][:, :chi]) <= 1e-9, b
