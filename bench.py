@@ -62,6 +62,21 @@ def measured_traffic(args):
     return rec["traffic_bytes_per_launch"]
 
 
+def measured_mfma_util(args):
+    """MFMA busy fraction (%) of the SI-application kernel from the committed
+    counter pass (MfmaUtil), or None when the GEMM source or the workload
+    differs from the one it was taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "si_apply_mfma.json")
+    if not os.path.exists(path) or args.prec != "f64" or (args.D, args.chi, args.p) != (6, 144, 16):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2607_15158_amd", "csrc", "gemm.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["gemm_hip_sha256"]:
+        return None
+    return rec["mfma_util_pct"]
+
+
 def cpu_baseline(args, A, X, Y):
     """Times the FP64 oracle on a bounded sample of one SI move of this workload.
 
@@ -296,7 +311,8 @@ def main():
                 "achieved": round(achieved, 2), "peak": PEAK[args.prec], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK[args.prec], 4), "traffic": measured_traffic(args),
                 "launch_ms": round(per_launch_ms, 4), "flops_per_launch": flops_launch,
-                "algorithmic_GBps": round(bytes_launch / (per_launch_ms * 1e-3) / 1e9, 1)}
+                "algorithmic_GBps": round(bytes_launch / (per_launch_ms * 1e-3) / 1e9, 1),
+                "mfma_busy_pct_counters": measured_mfma_util(args)}
     total_flops = sum(e["flops"] for e in prof) / prof_steps
     breakdown = {e["name"]: round(e["ms"] / prof_steps, 3) for e in prof}
 
