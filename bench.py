@@ -14,9 +14,11 @@ Also reported, in the same JSON line:
     subspace iteration) from HIP events recorded around every launch of it on
     the library's stream during the timed region;
   * the full-SVD CTMRG move on the same GPU (the four 5184 x 5184 M_b formed
-    with the library's GEMM and decomposed with rocSOLVER's divide-and-conquer
-    dgesdd, the fastest dense SVD available there), timed over --svd-moves
-    moves from the same environment;
+    with the library's GEMM and decomposed with rocSOLVER's QR-iteration
+    dgesvd, the fastest of its dense SVDs that is accurate for these
+    matrices: dgesdd is faster but returns wrong weak directions once
+    s_chi / s_1 is far below 1e-8, as here), timed over --svd-moves moves
+    from the same environment;
   * the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
@@ -130,7 +132,7 @@ def serving(args):
         D = int(rng.choice([3, 4, 5, 6]))
         chi = int(rng.choice([D * D, 2 * D * D, 3 * D * D]))
         p = max(4, math.ceil(0.15 * chi))
-        cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2, svd_driver="gesdd")
+        cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2, svd_driver="gesvd")
         reqs.append((cfg, S.product_plus_noise_site(2, D, 4000 + i)))
     h = S.heisenberg_bond()
 
@@ -196,14 +198,20 @@ def main():
                          "moves align to this mean sin^2 (the paper's recycling); 0: n_si "
                          "steps every move")
     ap.add_argument("--min-si-moves", type=int, default=3)
+    ap.add_argument("--converge-tol", type=float, default=0.0,
+                    help="> 0: also time SI and full-SVD environments from the same start until "
+                         "delta < this (each from its own growth move)")
+    ap.add_argument("--converge-max", type=int, default=120)
     ap.add_argument("--vjp", type=int, default=3,
                     help="time this many adjoints of the move (ctm_move_vjp) at the state after "
                          "the timed moves (0: skip)")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--pinv-rtol", type=float, default=1e-12)
-    ap.add_argument("--svd-moves", type=int, default=2, help="full-SVD comparator moves (0: skip)")
-    ap.add_argument("--svd-driver", default="gesdd", choices=["gesdd", "gesvd"],
-                    help="dense SVD of the growth move and of the full-SVD comparator")
+    ap.add_argument("--svd-moves", type=int, default=1, help="full-SVD comparator moves (0: skip)")
+    ap.add_argument("--svd-driver", default="gesvd", choices=["gesvd", "gesdd", "gesvdx"],
+                    help="dense SVD of the growth move and of the full-SVD comparator (gesvd: "
+                         "accurate; gesdd: fast but its weak directions are noise at this "
+                         "conditioning; gesvdx: accurate, slow)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="copy 1 GiB device to device once before the moves (the reference "
@@ -353,6 +361,32 @@ def main():
                "solver": f"rocsolver_d{args.svd_driver} on 4 x ({cfg.N} x {cfg.N})"}
         del cs
 
+    conv = None
+    if args.converge_tol > 0:
+        conv = {"tol": args.converge_tol, "max_moves": args.converge_max,
+                "svd_driver": args.svd_driver}
+        for name, proj in (("si", "si"), ("full_svd", "svd")):
+            cfg_c = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj=proj,
+                             prec=args.prec if proj == "si" else "f64", stabilized=1,
+                             pinv_rtol=args.pinv_rtol, svd_driver=args.svd_driver)
+            torch.cuda.empty_cache()
+            cc = P.Ctm(cfg_c, torch.from_numpy(A).to(dev))
+            cc.set_isometries(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = cc.converge(args.converge_tol, args.converge_max)
+            dt = time.perf_counter() - t
+            import synth as S
+            h = S.heisenberg_bond()
+            e = cc.observable(P.OBS_BOND_H, h)[0] + cc.observable(P.OBS_BOND_V, h)[0]
+            conv[name] = {"moves": r["moves"], "seconds": round(dt, 3), "converged": r["converged"],
+                          "last_delta": r["delta"], "energy": e}
+            log(f"converged environment ({name}): {r['moves']} moves, {dt:.2f} s, "
+                f"delta {r['delta']:.2e}, energy {e:.10f}")
+            del cc
+        conv["time_ratio_full_svd_over_si"] = round(conv["full_svd"]["seconds"] /
+                                                    conv["si"]["seconds"], 2)
+
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline (one SI move) ...")
@@ -379,6 +413,7 @@ def main():
         "roofline": roofline,
         "full_svd_same_gpu": svd,
         "adjoint": vjp,
+        "converged_environment": conv,
         "speedup_vs_full_svd": None if svd is None else round(value / svd["moves_per_s"], 2),
         "cpu_baseline": cpu,
     }

@@ -90,8 +90,11 @@ typedef struct {
   int svd_driver;   /* dense SVD of M_b (full-SVD projectors and the growth moves):
                        0 = QR iteration (rocSOLVER gesvd; small singular values to
                        high relative accuracy), 1 = divide and conquer (rocSOLVER
-                       gesdd via the eigenvectors of M^T M; an order of magnitude
-                       faster, weak directions below ~1e-8 s_1 less accurate)     */
+                       gesdd via the eigenvectors of M^T M: fast, but its weak
+                       directions are noise once s_chi / s_1 is below ~1e-8, which
+                       the products of four enlarged corners reach), 2 = selected
+                       triples (rocSOLVER gesvdx: bidiagonalisation, then
+                       bisection and inverse iteration for the leading chi + 1) */
   int sym;          /* ctm_sym                                                           */
   double recycle_sin2; /* recycling of the SI blocks (QR-based projector section, step 4;
                        recycling criterion of the triangular Heisenberg benchmark):

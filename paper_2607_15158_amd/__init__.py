@@ -35,7 +35,7 @@ CTM_OK, CTM_E_ARG, CTM_E_SHAPE, CTM_E_NOMEM, CTM_E_DEVICE, CTM_E_NUMERIC, \
     CTM_E_NOT_CONVERGED, CTM_E_STATE = range(8)
 PROJ = {"svd": 0, "fullsvd": 0, "si": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-SVD_DRIVER = {"gesvd": 0, "gesdd": 1}
+SVD_DRIVER = {"gesvd": 0, "gesdd": 1, "gesvdx": 2}
 SYM = {"none": 0, "c4v": 1}
 OBS_NORM, OBS_ONESITE, OBS_BOND_H, OBS_BOND_V = range(4)
 

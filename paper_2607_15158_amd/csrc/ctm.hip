@@ -130,6 +130,7 @@ struct ctm_ctx {
   void* svd_ws;
   double *fs_s, *fs_E, *fs_sg, *fs_Us, *fs_Vs;
   int* fs_info;
+  int* fs_perm;              // descending order of the dense SVD's singular values
   double* obs_y;             // [d^2][x Dl x]
   double* obs_w;             // [d^2][x Dl x]
   double* obs_op;            // [d^4] device copy of an operator
@@ -191,8 +192,8 @@ int validate(const ctm_config* cfg) {
   if (cfg->prec < CTM_PREC_F64 || cfg->prec > CTM_PREC_BF16)
     return fail(nullptr, CTM_E_ARG, "unknown precision");
   if (!(cfg->pinv_rtol >= 0.0)) return fail(nullptr, CTM_E_ARG, "pinv_rtol must be >= 0");
-  if (cfg->svd_driver != 0 && cfg->svd_driver != 1)
-    return fail(nullptr, CTM_E_ARG, "svd_driver must be 0 (gesvd) or 1 (gesdd)");
+  if (cfg->svd_driver < 0 || cfg->svd_driver > 2)
+    return fail(nullptr, CTM_E_ARG, "svd_driver must be 0 (gesvd), 1 (gesdd) or 2 (gesvdx)");
   if (cfg->sym != CTM_SYM_NONE && cfg->sym != CTM_SYM_C4V)
     return fail(nullptr, CTM_E_ARG, "sym must be CTM_SYM_NONE or CTM_SYM_C4V");
   if (cfg->sym == CTM_SYM_C4V && cfg->prec != CTM_PREC_F64)
@@ -292,6 +293,7 @@ size_t carve(ctm_ctx* c, char* base) {
   c->fs_Us = cv.take<double>(Nm * chi);
   c->fs_Vs = cv.take<double>(Nm * chi);
   c->fs_info = cv.take<int>(64);
+  c->fs_perm = cv.take<int>(Nm);
   c->obs_y = cv.take<double>((size_t)dd * xm * Dl * xm);
   c->obs_w = cv.take<double>((size_t)dd * xm * Dl * xm);
   c->obs_op = cv.take<double>(256);
@@ -699,15 +701,33 @@ int full_projectors(ctm_ctx* c, int keep) {
     {
       ProfScope ps(c, PC_FULLSVD);
       // rocSOLVER is column-major: it sees M^T = (V) S (U^T)
-      rocblas_status st =
-          c->cfg.svd_driver == 1
-              ? rocsolver_dgesdd(c->rb, rocblas_svect_singular, rocblas_svect_singular, N1, N1, M,
-                                 N1, c->fs_s, Ut, N1, Uv, N1, c->fs_info)
-              : rocsolver_dgesvd(c->rb, rocblas_svect_singular, rocblas_svect_singular, N1, N1, M,
-                                 N1, c->fs_s, Ut, N1, Uv, N1, c->fs_E, rocblas_outofplace,
-                                 c->fs_info);
+      // gesvdx computes only the leading min(N1, keep + 1) triples (bisection and
+      // inverse iteration on the bidiagonal); its right vectors of M^T are
+      // stored with leading dimension N1, the same layout as the others'
+      rocblas_status st;
+      if (c->cfg.svd_driver == 1)
+        st = rocsolver_dgesdd(c->rb, rocblas_svect_singular, rocblas_svect_singular, N1, N1, M, N1,
+                              c->fs_s, Ut, N1, Uv, N1, c->fs_info);
+      else if (c->cfg.svd_driver == 2)
+        st = rocsolver_dgesvdx(c->rb, rocblas_svect_singular, rocblas_svect_singular,
+                               rocblas_srange_index, N1, N1, M, N1, 0.0, 0.0, 1,
+                               std::min(N1, keep + 1), c->fs_info + 1, c->fs_s, Ut, N1, Uv, N1,
+                               c->fs_perm, c->fs_info);
+      else
+        st = rocsolver_dgesvd(c->rb, rocblas_svect_singular, rocblas_svect_singular, N1, N1, M, N1,
+                              c->fs_s, Ut, N1, Uv, N1, c->fs_E, rocblas_outofplace, c->fs_info);
       if (st != rocblas_status_success)
         return fail(c, CTM_E_DEVICE, "rocSOLVER SVD failed: " + std::to_string((int)st));
+    }
+    // keep the triples in descending order of the singular value: the
+    // divide-and-conquer driver does not return them ordered at every size
+    // (a no-op permutation for the QR-iteration driver); U into M's buffer,
+    // V^T into S2[3], the values into fs_E
+    {
+      const int m = std::min(N1, keep + 1);
+      TRY(elem_sort_triples(c->fs_s, Uv, Ut, N1, m, c->fs_perm, c->fs_E, M, c->S2[3], c->st));
+      Uv = M;
+      Ut = c->S2[3];
     }
     SignArgs sa{};
     sa.N = N1;
@@ -716,7 +736,7 @@ int full_projectors(ctm_ctx* c, int keep) {
     sa.Y[0] = Uv;
     sa.sg[0] = c->fs_sg;
     TRY(elem_col_sign(sa, 1, c->st));
-    TRY(elem_proj_prep_full(Uv, Ut, c->fs_s, c->fs_sg, N1, keep, c->cfg.pinv_rtol, c->fs_Us,
+    TRY(elem_proj_prep_full(Uv, Ut, c->fs_E, c->fs_sg, N1, keep, c->cfg.pinv_rtol, c->fs_Us,
                             c->fs_Vs, c->scal + 9 + b, c->st));
     // P_l = R Vs ; P_r^T = L^T Us
     GemmBatch g = gemm_rowmajor(2, N1, keep, N1, N1, keep, keep);

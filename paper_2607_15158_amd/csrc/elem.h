@@ -64,6 +64,11 @@ int elem_norms(const NormArgs& na, int count, hipStream_t s);
 int elem_col_sign(const SignArgs& sa, int count, hipStream_t s);
 int elem_scale_cols(const SignArgs& sa, int count, hipStream_t s);
 int elem_proj_prep(const ProjPrepArgs& pa, int count, hipStream_t s);
+// The first m singular triples of a dense SVD in descending order of the
+// singular value (stable): s_out[j], U_out[:, j], Vt_out[j, :] (row-major,
+// leading dimension n); perm holds n ints.
+int elem_sort_triples(const double* s, const double* U, const double* Vt, int n, int m, int* perm,
+                      double* s_out, double* U_out, double* Vt_out, hipStream_t st);
 int elem_proj_prep_full(const double* U, const double* Vt, const double* sv, const double* sg,
                         int N, int keep, double rtol, double* Us, double* Vs, double* gap,
                         hipStream_t s);

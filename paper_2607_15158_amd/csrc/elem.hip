@@ -239,6 +239,40 @@ __global__ void k_proj_prep_full(const double* U, const double* Vt, const double
   }
 }
 
+// Descending order of n singular values: perm[rank] = i, rank = number of
+// values larger than s[i] (ties by index), so the order is stable.
+__global__ __launch_bounds__(256) void k_rank_desc(const double* __restrict__ s, int n,
+                                                   int* __restrict__ perm) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double v = s[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+      const double w = s[j];
+      r += (w > v || (w == v && j < i)) ? 1 : 0;
+    }
+    perm[r] = i;
+  }
+}
+
+// Sorted copies of the first m singular triples: s_out[j] = s[perm[j]],
+// U_out[:, j] = U[:, perm[j]] (row-major, ld n), Vt_out[j, :] = Vt[perm[j], :].
+__global__ __launch_bounds__(256) void k_gather_triples(const double* __restrict__ s,
+                                                        const double* __restrict__ U,
+                                                        const double* __restrict__ Vt,
+                                                        const int* __restrict__ perm, int n, int m,
+                                                        double* __restrict__ s_out,
+                                                        double* __restrict__ U_out,
+                                                        double* __restrict__ Vt_out) {
+  const long total = (long)n * m;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+    const int r = (int)(i / m), j = (int)(i % m);
+    const int pj = perm[j];
+    U_out[(long)r * n + j] = U[(long)r * n + pj];
+    Vt_out[(long)j * n + r] = Vt[(long)pj * n + r];
+    if (r == 0) s_out[j] = s[pj];
+  }
+}
+
 __global__ void k_scale_cols(SignArgs sa) {
   const int b = blockIdx.y;
   double* Y = sa.Y[b];
@@ -577,6 +611,18 @@ int elem_proj_prep_full(const double* U, const double* Vt, const double* sv, con
   const long total = (long)N * keep;
   const int blocks = (int)std::min<long>(2048, (total + 255) / 256);
   k_proj_prep_full<<<blocks, 256, 0, s>>>(U, Vt, sv, sg, N, keep, rtol, Us, Vs, gap);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_sort_triples(const double* s, const double* U, const double* Vt, int n, int m, int* perm,
+                      double* s_out, double* U_out, double* Vt_out, hipStream_t st) {
+  if (n < 1 || m < 1 || m > n) return 1;
+  k_rank_desc<<<(n + 255) / 256, 256, 0, st>>>(s, n, perm);
+  CTM_HIP_TRY(hipGetLastError());
+  const long total = (long)n * m;
+  k_gather_triples<<<(int)std::min<long>(4096, (total + 255) / 256), 256, 0, st>>>(
+      s, U, Vt, perm, n, m, s_out, U_out, Vt_out);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }
