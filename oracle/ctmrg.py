@@ -366,12 +366,20 @@ def spectrum_delta(s_new: np.ndarray, s_old: np.ndarray) -> float:
 # --------------------------------------------------------------------------
 def ctm_move(env: Env, a: np.ndarray, chi: int, proj: str = "si",
              si: Optional[SIState] = None, n_si: int = 2, eps: float = 1e-12,
-             stabilized: bool = True):
+             stabilized: bool = True, grow_iso: Optional[SIState] = None):
     """One simultaneous four-direction CTMRG move.
 
     ``proj`` is ``"si"`` or ``"svd"``.  Returns ``(env_new, info)`` where
-    ``info`` holds the mode used (``grow``, ``svd`` or ``si``), the singular
-    values found for each bond and the updated ``SIState`` (or None).
+    ``info`` holds the mode used (``grow``, ``svd``, ``grow-si`` or ``si``),
+    the singular values found for each bond and the updated ``SIState`` (or
+    None).
+
+    ``grow_iso`` selects randomized projectors for a truncating growth move
+    (the warm-up the paper allows to use a randomized SVD instead of the full
+    one, multi-site passage): with ``chi_env < chi`` and ``N = chi_env D^2``
+    at least the block width k, the SI projectors are built from the first N
+    rows of the start blocks ``grow_iso``; the start blocks themselves are
+    left for the first SI move.
     """
     x, D2 = env.chi, a.shape[0]
     N = x * D2
@@ -381,6 +389,16 @@ def ctm_move(env: Env, a: np.ndarray, chi: int, proj: str = "si",
         Pl = [np.eye(N)] * 4
         Prt = [np.eye(N)] * 4
         info["mode"] = "grow"
+    elif (proj == "si" and grow_iso is not None and x < chi
+          and N >= grow_iso.X[0].shape[1]):
+        Pl, Prt = [], []
+        for b in range(4):
+            pl, prt, s, _, _ = si_projectors(Ct, b, grow_iso.X[b][:N], grow_iso.Yt[b][:N], chi,
+                                             n_si, eps, stabilized)
+            Pl.append(pl)
+            Prt.append(prt)
+            info["svals"].append(s)
+        info["mode"] = "grow-si"
     elif proj == "svd" or x != chi:
         Pl, Prt = [], []
         for b in range(4):
@@ -424,7 +442,8 @@ RECYCLE_GUARD = 10.0
 def run_ctmrg(a: np.ndarray, e: np.ndarray, chi: int, proj: str = "si", k: Optional[int] = None,
               iso0: Optional[SIState] = None, n_si: int = 2, eps: float = 1e-12,
               tol: float = 0.0, max_moves: int = 100, stabilized: bool = True,
-              env0: Optional[Env] = None, recycle_sin2: float = 0.0, min_si_moves: int = 3):
+              env0: Optional[Env] = None, recycle_sin2: float = 0.0, min_si_moves: int = 3,
+              growth: str = "svd"):
     """Moves from ``initial_env(a, e)`` (or ``env0``) until ``delta < tol``.
 
     In SI mode ``iso0`` supplies the Gaussian start blocks; they are used at
@@ -441,6 +460,10 @@ def run_ctmrg(a: np.ndarray, e: np.ndarray, chi: int, proj: str = "si", k: Optio
     blocks are no subspace estimate).  Updates resume, and the count starts
     again, when delta grows by more than ``RECYCLE_GUARD`` from one move to
     the next (a stale subspace shows up in the corner spectra).
+
+    ``growth = "si"`` builds the projectors of truncating growth moves from
+    the first rows of ``iso0`` (see :func:`ctm_move`); ``"svd"`` uses the full
+    SVD.
 
     Returns ``(env, history)``; each history entry holds the move number, the
     mode, delta, the subspace steps used and the measured sin^2 (or None).
@@ -462,7 +485,8 @@ def run_ctmrg(a: np.ndarray, e: np.ndarray, chi: int, proj: str = "si", k: Optio
                 first_si = False
             use_si = si
         steps = 0 if recycling else n_si
-        env, info = ctm_move(env, a, chi, proj, use_si, steps, eps, stabilized)
+        env, info = ctm_move(env, a, chi, proj, use_si, steps, eps, stabilized,
+                             grow_iso=iso0 if growth == "si" else None)
         sin2 = None
         if info["mode"] == "si":
             new = info["si"]

@@ -400,3 +400,22 @@ def test_boundary_larger_than_chi_truncates_with_full_svd():
     assert [h["mode"] for h in h_si] == ["svd", "si", "si", "si"]
     for c1, c2 in zip(env_si.C + env_si.T, env_sv.C + env_sv.T):
         assert np.allclose(c1, c2, atol=1e-12)
+
+
+def test_randomized_growth_reaches_the_same_fixed_point():
+    """Truncating growth moves with SI projectors from the first rows of the
+    start blocks (a randomized SVD warm-up) lead to the same converged
+    environment as full-SVD growth: equal bond energies and norms."""
+    A = S.product_plus_noise_site(2, 3, 2, noise=0.3)
+    a, e = O.double_layer(A), S.trace_boundary(3)
+    chi = 18
+    iso = iso_for(chi * 9, chi + 6)
+    h = S.heisenberg_bond()
+    out = {}
+    for growth in ("svd", "si"):
+        env, hist = O.run_ctmrg(a, e, chi, proj="si", iso0=iso, tol=1e-12, max_moves=300,
+                                growth=growth)
+        assert hist[0]["mode"] == ("grow-si" if growth == "si" else "svd")
+        assert hist[-1]["delta"] < 1e-12
+        out[growth] = (O.bond_value(env, A, h, "h"), O.bond_value(env, A, h, "v"), O.kappa(env, a))
+    assert np.allclose(out["si"], out["svd"], rtol=1e-10, atol=1e-12)
