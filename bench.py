@@ -132,7 +132,7 @@ def serving(args):
         D = int(rng.choice([3, 4, 5, 6]))
         chi = int(rng.choice([D * D, 2 * D * D, 3 * D * D]))
         p = max(4, math.ceil(0.15 * chi))
-        cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2, svd_driver="gesvd")
+        cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2, svd_driver="gesvd", growth="si")
         reqs.append((cfg, S.product_plus_noise_site(2, D, 4000 + i)))
     h = S.heisenberg_bond()
 

@@ -108,11 +108,18 @@ typedef struct {
                        move to the next.  The angles are measured only when the
                        previous move was an SI move.  <= 0: n_si steps every move */
   int min_si_moves;    /* SI moves with subspace steps before recycling may start (>= 1) */
+  int growth;          /* truncating growth moves (chi_env < chi): 0 = full-SVD projectors
+                          (svd_driver); 1 = randomized: SI projectors (n_si steps) from
+                          the first chi_env*Dl rows of the start blocks, which stay
+                          pending for the first SI move (the warm-up by a randomized
+                          SVD that the paper allows); used when chi_env*Dl >= k with a
+                          QR leaf split, else full SVD.  Mode 3 in ctm_move_info.   */
 } ctm_config;
 
 typedef struct {
   double delta;   /* max over corners of |s_new - s_old|_2 of unit-norm corner spectra */
-  int mode;       /* 0: growth without truncation, 1: full-SVD projectors, 2: SI       */
+  int mode;       /* 0: growth without truncation, 1: full-SVD projectors, 2: SI,
+                     3: truncating growth with randomized (SI) projectors              */
   int chi_env;    /* environment dimension after the move                              */
   double gap;     /* min over bonds of s_chi / s_(chi+1) - 1 (-1 when not truncated)   */
   int n_si;       /* subspace steps this move took (0 when recycling or not an SI move) */

@@ -36,6 +36,7 @@ CTM_OK, CTM_E_ARG, CTM_E_SHAPE, CTM_E_NOMEM, CTM_E_DEVICE, CTM_E_NUMERIC, \
 PROJ = {"svd": 0, "fullsvd": 0, "si": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 SVD_DRIVER = {"gesvd": 0, "gesdd": 1, "gesvdx": 2}
+GROWTH = {"svd": 0, "si": 1}
 SYM = {"none": 0, "c4v": 1}
 OBS_NORM, OBS_ONESITE, OBS_BOND_H, OBS_BOND_V = range(4)
 
@@ -45,7 +46,8 @@ class ctm_config(ctypes.Structure):
                 ("p", ctypes.c_int), ("n_si", ctypes.c_int), ("proj", ctypes.c_int),
                 ("prec", ctypes.c_int), ("stabilized", ctypes.c_int),
                 ("pinv_rtol", ctypes.c_double), ("svd_driver", ctypes.c_int), ("sym", ctypes.c_int),
-                ("recycle_sin2", ctypes.c_double), ("min_si_moves", ctypes.c_int)]
+                ("recycle_sin2", ctypes.c_double), ("min_si_moves", ctypes.c_int),
+                ("growth", ctypes.c_int)]
 
 
 class ctm_move_info(ctypes.Structure):
@@ -153,12 +155,13 @@ class Config:
     sym: str = "none"
     recycle_sin2: float = 0.0
     min_si_moves: int = 3
+    growth: str = "svd"
 
     def c(self) -> ctm_config:
         return ctm_config(self.d, self.D, self.chi, self.p, self.n_si, PROJ[self.proj],
                           PREC[self.prec], self.stabilized, self.pinv_rtol,
                           SVD_DRIVER[self.svd_driver], SYM[self.sym], self.recycle_sin2,
-                          self.min_si_moves)
+                          self.min_si_moves, GROWTH[self.growth])
 
     @property
     def Dl(self) -> int:

@@ -192,6 +192,8 @@ int validate(const ctm_config* cfg) {
   if (cfg->prec < CTM_PREC_F64 || cfg->prec > CTM_PREC_BF16)
     return fail(nullptr, CTM_E_ARG, "unknown precision");
   if (!(cfg->pinv_rtol >= 0.0)) return fail(nullptr, CTM_E_ARG, "pinv_rtol must be >= 0");
+  if (cfg->growth != 0 && cfg->growth != 1)
+    return fail(nullptr, CTM_E_ARG, "growth must be 0 (full SVD) or 1 (randomized)");
   if (cfg->svd_driver < 0 || cfg->svd_driver > 2)
     return fail(nullptr, CTM_E_ARG, "svd_driver must be 0 (gesvd), 1 (gesdd) or 2 (gesvdx)");
   if (cfg->sym != CTM_SYM_NONE && cfg->sym != CTM_SYM_C4V)
@@ -525,9 +527,33 @@ int ensure_si_blocks(ctm_ctx* c) {
 // with nsi subspace steps.  With `measure`, the recycling criterion (the
 // largest over the 8 blocks of the mean sin^2 of the principal angles between
 // the kept columns before and after the move) is written to scal[13].
+int si_core(ctm_ctx* c, int keep, int nsi, bool measure, int N1);
+
 int si_projectors(ctm_ctx* c, int keep, int nsi, bool measure) {
-  const int N1 = c->N, k = c->k;
   TRY(ensure_si_blocks(c));
+  return si_core(c, keep, nsi, measure, c->N);
+}
+
+// Randomized projectors of a truncating growth move (environment dimension
+// chi_env < chi, N1 = chi_env Dl >= k rows): the SI steps run on the first
+// N1 rows of the start blocks (or on Gaussian blocks when none were given),
+// which stay pending for the first SI move.
+int growth_si_projectors(ctm_ctx* c, int keep, int N1) {
+  const size_t nk = (size_t)N1 * c->k;
+  for (int b = 0; b < 4; ++b) {
+    if (c->iso_pending) {
+      CTM_HIP_TRY(hipMemcpyAsync(c->X[b], c->X0[b], nk * 8, hipMemcpyDeviceToDevice, c->st));
+      CTM_HIP_TRY(hipMemcpyAsync(c->Yt[b], c->Yt0[b], nk * 8, hipMemcpyDeviceToDevice, c->st));
+    } else {
+      TRY(elem_gauss(c->X[b], (long)nk, 3000 + b, c->st));
+      TRY(elem_gauss(c->Yt[b], (long)nk, 4000 + b, c->st));
+    }
+  }
+  return si_core(c, keep, c->cfg.n_si, false, N1);
+}
+
+int si_core(ctm_ctx* c, int keep, int nsi, bool measure, int N1) {
+  const int k = c->k;
   if (measure) {
     const size_t nk = (size_t)N1 * k * sizeof(double);
     for (int b = 0; b < 4; ++b) {
@@ -1015,6 +1041,8 @@ int move_work(ctm_ctx* c, int mode, int keep, int nsi, bool measure) {
     }
   } else if (mode == 1) {
     TRY(full_projectors(c, keep));
+  } else if (mode == 3) {
+    TRY(growth_si_projectors(c, keep, N1));
   } else {
     TRY(si_projectors(c, keep, nsi, measure));
   }
@@ -1077,7 +1105,12 @@ int enqueue_move(ctm_ctx* c) {
     mode = 0;
     keep = N1;
   } else if (x != c->chi || c->cfg.proj == CTM_PROJ_FULLSVD) {
-    mode = 1;
+    // truncating growth: randomized (SI) projectors on request, when the
+    // N1 rows hold a k-column block with a QR leaf split; else full SVD
+    const bool rnd = c->cfg.growth == 1 && c->cfg.proj == CTM_PROJ_SI &&
+                     c->cfg.sym == CTM_SYM_NONE && x < c->chi && N1 >= c->k &&
+                     qr_plan_ok(N1, c->k);
+    mode = rnd ? 3 : 1;
     keep = c->chi;
   } else {
     mode = 2;

@@ -69,6 +69,9 @@ def test_unknown_projector_and_precision_rejected():
     c.prec = 9
     assert P._lib.ctm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == P.CTM_E_ARG
     c = P.Config(d=2, D=2, chi=8).c()
+    c.growth = 2
+    assert P._lib.ctm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == P.CTM_E_ARG
+    c = P.Config(d=2, D=2, chi=8).c()
     c.svd_driver = 3
     assert P._lib.ctm_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == P.CTM_E_ARG
 

@@ -508,3 +508,30 @@ def test_widest_subspace_blocks(chi, p):
         assert rel(st["C"][i], Ci) <= 1e-10, i
     for b in range(4):
         assert rel(st["X"][b][:, :chi], Xn[b][:, :chi]) <= 1e-9, b
+
+
+def test_randomized_growth_moves_match_oracle():
+    """growth = "si": the truncating growth move takes SI projectors from the
+    first rows of the start blocks (mode 3), then SI moves start from the
+    full start blocks; move by move against the oracle."""
+    A = S.product_plus_noise_site(2, 3, 2, noise=0.3)
+    chi, p = 18, 6
+    cfg = P.Config(d=2, D=3, chi=chi, p=p, n_si=2, growth="si")
+    ctx, si = make(cfg, A)
+    a = O.double_layer(A)
+    env = O.initial_env(a, S.trace_boundary(3))
+    iso0 = O.SIState([x.copy() for x in si.X], [y.copy() for y in si.Yt])
+    cur = None
+    modes = []
+    for n in range(5):
+        info = ctx.move()
+        use = (cur or iso0) if env.chi == chi else None
+        env, oinfo = O.ctm_move(env, a, chi, "si", use, n_si=2, eps=1e-12, grow_iso=iso0)
+        if oinfo["mode"] == "si":
+            cur = oinfo["si"]
+        modes.append(info["mode"])
+        assert info["mode"] == {"grow": 0, "svd": 1, "si": 2, "grow-si": 3}[oinfo["mode"]]
+        st = ctx.unpack_state(ctx.get_state())
+        assert_spectra_close(st, env, 1e-11)
+        assert_env_close(st, env, 1e-8)
+    assert modes[:2] == [3, 2]

@@ -18,7 +18,7 @@ import synth as S  # noqa: E402
 
 
 def request(D, chi, seed, p=4):
-    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2, svd_driver="gesvd")
+    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2, svd_driver="gesvd", growth="si")
     A = S.product_plus_noise_site(2, D, seed, noise=0.3)
     X = np.stack([S.gaussian_block(cfg.N, cfg.k, 100 * seed + b) for b in range(4)])
     Y = np.stack([S.gaussian_block(cfg.N, cfg.k, 100 * seed + 10 + b) for b in range(4)])
