@@ -202,6 +202,10 @@ def main():
                     help="> 0: also time SI and full-SVD environments from the same start until "
                          "delta < this (each from its own growth move)")
     ap.add_argument("--converge-max", type=int, default=120)
+    ap.add_argument("--opt-moves", type=int, default=0,
+                    help="> 0: time one optimisation step (the energy after this many SI moves "
+                         "from the state after the timed moves, and its site-tensor gradient by "
+                         "the unrolled adjoint with move-boundary checkpoints)")
     ap.add_argument("--vjp", type=int, default=3,
                     help="time this many adjoints of the move (ctm_move_vjp) at the state after "
                          "the timed moves (0: skip)")
@@ -341,6 +345,23 @@ def main():
                "what": "reverse pass of one SI move incl. its recomputed forward (tape)"}
         log(f"adjoint: {vjp['ms_per_vjp']} ms per move VJP ({vjp['ratio_to_move']}x the move)")
 
+    opt = None
+    if args.opt_moves > 0 and args.prec == "f64":
+        import synth as S
+        st0 = ctx.get_state_device()
+        At = torch.from_numpy(A).to(dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e_opt = P.unrolled_energy(At, cfg, S.heisenberg_bond(), st0, args.opt_moves)
+        e_opt.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        opt = {"moves": args.opt_moves, "seconds": round(dt, 3),
+               "what": "energy after the moves and its gradient wrt the site tensor (unrolled "
+                       "adjoint, checkpoints at move boundaries, moves recomputed in reverse)"}
+        log(f"optimisation step ({args.opt_moves} unrolled moves, forward + backward): {dt:.2f} s")
+        del At, e_opt
+
     svd = None
     if args.svd_moves > 0:
         cfg_s = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="svd",
@@ -413,6 +434,7 @@ def main():
         "roofline": roofline,
         "full_svd_same_gpu": svd,
         "adjoint": vjp,
+        "optimisation_step": opt,
         "converged_environment": conv,
         "speedup_vs_full_svd": None if svd is None else round(value / svd["moves_per_s"], 2),
         "cpu_baseline": cpu,

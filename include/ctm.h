@@ -215,6 +215,8 @@ ctm_status ctm_state_size(const ctm_ctx* ctx, size_t* n);
  * given; on set, non-zero blocks become the pending start blocks).
  * Synchronises. */
 ctm_status ctm_get_state(ctm_ctx* ctx, double* host, size_t n);
+/* As ctm_get_state, into device memory (n doubles); synchronises. */
+ctm_status ctm_get_state_device(ctm_ctx* ctx, double* dev, size_t n);
 ctm_status ctm_set_state(ctm_ctx* ctx, const double* host, size_t n);
 
 /* Per-kernel-class timing of the context's launches, measured with HIP

@@ -94,6 +94,7 @@ _sigs = {
     "ctm_observable": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
     "ctm_state_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "ctm_get_state": (ctypes.c_int, [_vp, _dp, ctypes.c_size_t]),
+    "ctm_get_state_device": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "ctm_set_state": (ctypes.c_int, [_vp, _dp, ctypes.c_size_t]),
     "ctm_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ctm_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctm_prof_entry), ctypes.c_int,
@@ -271,6 +272,14 @@ class Ctm:
         _check(_lib.ctm_get_state(self._h, buf.ctypes.data_as(_dp), n), self._h)
         return buf
 
+    def get_state_device(self):
+        """The state vector as a float64 device tensor (a device-to-device copy)."""
+        import torch
+        n = self.state_size()
+        out = torch.empty(n, dtype=torch.float64, device=self._site.device)
+        _check(_lib.ctm_get_state_device(self._h, out.data_ptr(), n), self._h)
+        return out
+
     def set_state(self, state: np.ndarray):
         buf = np.ascontiguousarray(state, dtype=np.float64)
         _check(_lib.ctm_set_state(self._h, buf.ctypes.data_as(_dp), buf.size), self._h)
@@ -435,6 +444,40 @@ def converged_energy(A, cfg: Config, op, X0, Yt0, tol: float = 1e-12, max_moves:
             return g * grad
 
     return _ConvergedEnergy.apply(A)
+
+
+def unrolled_energy(A, cfg: Config, op, state0, moves: int):
+    """Energy <op>_H + <op>_V after ``moves`` SI moves from ``state0`` (a
+    float64 device tensor in the state layout, chi_env == chi), differentiable
+    with respect to the site tensor ``A`` by unrolling: the forward pass keeps
+    the state at every move boundary on the device (checkpoints), the
+    backward pass runs the library's energy gradient and then ctm_move_vjp
+    from each checkpoint in reverse order, recomputing each move from its
+    checkpoint."""
+    import torch
+
+    class _UnrolledEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, site):
+            c = Ctm(cfg, site.detach())
+            c.set_state(state0.detach().cpu().numpy())
+            states = [c.get_state_device()]
+            for _ in range(moves):
+                c.move()
+                states.append(c.get_state_device())
+            e, bar, site_bar = c.energy_vjp(states[-1], op)
+            for st in reversed(states[:-1]):
+                bar, _, site_bar = c.move_vjp(st, bar, want_out=False, site_bar=site_bar)
+            ctx.save_for_backward(site_bar)
+            c.close()
+            return torch.tensor(e, dtype=torch.float64, device=site.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            (grad,) = ctx.saved_tensors
+            return g * grad
+
+    return _UnrolledEnergy.apply(A)
 
 
 def _ptr_array(ts):

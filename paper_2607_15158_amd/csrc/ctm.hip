@@ -1660,43 +1660,62 @@ ctm_status ctm_state_size(const ctm_ctx* c, size_t* n) {
   return CTM_OK;
 }
 
-ctm_status ctm_get_state(ctm_ctx* c, double* host, size_t n) {
+}  // extern "C"
+
+namespace {
+
+// Copies the state vector (layout of ctm_state_size) to host or device memory.
+int copy_state(ctm_ctx* c, double* dst, size_t n, bool device) {
   size_t need;
   if (c && c->pending) {
     const int rd = drain(c);
-    if (rd) return (ctm_status)rd;
+    if (rd) return rd;
   }
-  if (ctm_state_size(c, &need) != CTM_OK || !host || n < need)
-    return (ctm_status)fail(c, CTM_E_ARG, "state buffer too small");
+  if (ctm_state_size(c, &need) != CTM_OK || !dst || n < need)
+    return fail(c, CTM_E_ARG, "state buffer too small");
   const size_t chi = c->chi, Dl = c->Dl, N = c->N, k = c->k;
   const size_t x = c->chi_env;
-  std::fill(host, host + need, 0.0);
-  double* p = host;
+  const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (device) {
+    CTM_HIP_TRY(hipMemsetAsync(dst, 0, need * sizeof(double), c->st));
+  } else {
+    std::fill(dst, dst + need, 0.0);
+  }
+  double* p = dst;
   for (int i = 0; i < 4; ++i, p += chi * chi)
-    if (hipMemcpyAsync(p, c->C[c->cur][i], x * x * 8, hipMemcpyDeviceToHost, c->st) != hipSuccess)
-      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+    CTM_HIP_TRY(hipMemcpyAsync(p, c->C[c->cur][i], x * x * 8, kind, c->st));
   for (int i = 0; i < 4; ++i, p += chi * Dl * chi)
-    if (hipMemcpyAsync(p, c->T[c->cur][i], x * Dl * x * 8, hipMemcpyDeviceToHost, c->st) !=
-        hipSuccess)
-      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+    CTM_HIP_TRY(hipMemcpyAsync(p, c->T[c->cur][i], x * Dl * x * 8, kind, c->st));
   // the blocks the next SI move starts from: the caller's start blocks while
   // they are pending, none (zeros) before any exist
   const bool blocks = c->iso_pending || c->si_ready;
   for (int i = 0; i < 4; ++i, p += N * k)
-    if (blocks && hipMemcpyAsync(p, c->iso_pending ? c->X0[i] : c->X[i], N * k * 8,
-                                 hipMemcpyDeviceToHost, c->st) != hipSuccess)
-      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
+    if (blocks)
+      CTM_HIP_TRY(hipMemcpyAsync(p, c->iso_pending ? c->X0[i] : c->X[i], N * k * 8, kind, c->st));
   for (int i = 0; i < 4; ++i, p += N * k)
-    if (blocks && hipMemcpyAsync(p, c->iso_pending ? c->Yt0[i] : c->Yt[i], N * k * 8,
-                                 hipMemcpyDeviceToHost, c->st) != hipSuccess)
-      return (ctm_status)fail(c, CTM_E_DEVICE, "copy failed");
-  if (hipStreamSynchronize(c->st) != hipSuccess)
-    return (ctm_status)fail(c, CTM_E_DEVICE, "synchronisation failed");
-  p[0] = (double)c->chi_env;
-  p[1] = (double)c->si_moves;
-  p[2] = c->recycling ? 1.0 : 0.0;
-  p[3] = (double)c->si_upd;
+    if (blocks)
+      CTM_HIP_TRY(hipMemcpyAsync(p, c->iso_pending ? c->Yt0[i] : c->Yt[i], N * k * 8, kind, c->st));
+  const double tail[4] = {(double)c->chi_env, (double)c->si_moves, c->recycling ? 1.0 : 0.0,
+                          (double)c->si_upd};
+  if (device) {
+    CTM_HIP_TRY(hipMemcpyAsync(p, tail, sizeof(tail), hipMemcpyHostToDevice, c->st));
+  } else {
+    std::copy(tail, tail + 4, p);
+  }
+  CTM_HIP_TRY(hipStreamSynchronize(c->st));
   return CTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctm_status ctm_get_state(ctm_ctx* c, double* host, size_t n) {
+  return (ctm_status)copy_state(c, host, n, false);
+}
+
+ctm_status ctm_get_state_device(ctm_ctx* c, double* dev, size_t n) {
+  return (ctm_status)copy_state(c, dev, n, true);
 }
 
 ctm_status ctm_set_state(ctm_ctx* c, const double* host, size_t n) {

@@ -225,3 +225,46 @@ def test_converged_energy_as_a_torch_function_descends():
     print(float(e), float(e2), drop, first_order)
     assert drop > 0
     assert abs(drop - first_order) <= 1e-2 * first_order
+
+
+def test_unrolled_energy_gradient_matches_autograd_and_finite_differences():
+    """Energy after n SI moves from a fixed state, differentiated by unrolling
+    with move-boundary checkpoints (the adjoint behind a torch autograd
+    function): against PyTorch CPU autograd through the oracle's moves, and
+    against central differences of the GPU's own moves."""
+    D, chi, p, n_si, moves = 2, 4, 4, 2, 3
+    A, C, T, X, Y = make_state(D, chi, p)
+    cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=n_si)
+    h = S.heisenberg_bond()
+    dev = torch.device("cuda", 0)
+    ctx = P.Ctm(cfg, torch.from_numpy(A).to(dev))
+    state0 = torch.from_numpy(ctx.pack_state(C, T, np.stack(X), np.stack(Y))).to(dev)
+    At = torch.from_numpy(A).to(dev).requires_grad_(True)
+    e = P.unrolled_energy(At, cfg, h, state0, moves)
+    e.backward()
+    g = At.grad.cpu().numpy()
+    # CPU autograd through the oracle's moves
+    leaf = torch.tensor(A, requires_grad=True)
+    tt = lambda L: [torch.tensor(v) for v in L]   # noqa: E731
+    Cs, Ts, Xs, Ys = tt(C), tt(T), tt(X), tt(Y)
+    for _ in range(moves):
+        Cs, Ts, Xs, Ys = J.move_torch(Cs, Ts, Xs, Ys, leaf, chi, n_si)
+    e_ref = J.energy_torch(Cs, Ts, leaf, torch.tensor(h))
+    (g_ref,) = torch.autograd.grad(e_ref, leaf)
+    assert abs(float(e.detach()) - float(e_ref.detach())) <= 1e-12
+    assert rel(g, g_ref.numpy()) <= 1e-9, rel(g, g_ref.numpy())
+    # central differences of GPU moves
+    st0 = state0.cpu().numpy()
+
+    def energy(site):
+        c = P.Ctm(cfg, torch.from_numpy(site).to(dev))
+        c.set_state(st0)
+        for _ in range(moves):
+            c.move()
+        return c.observable(P.OBS_BOND_H, h)[0] + c.observable(P.OBS_BOND_V, h)[0]
+
+    rng = np.random.default_rng(8)
+    d = rng.standard_normal(A.shape)
+    fd = (energy(A + 1e-6 * d) - energy(A - 1e-6 * d)) / 2e-6
+    an = float((g * d).sum())
+    assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-2), (fd, an)
