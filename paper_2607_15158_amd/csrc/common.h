@@ -106,6 +106,10 @@ int launch_gemm(const GemmBatch& g, DT ta, DT tb, DT tc, hipStream_t s);
 // float64 C = op(A) B with N <= 160 (the enlarged corner applied to an
 // isometry block); other shapes fall back to launch_gemm.
 int launch_gemm_si(const GemmBatch& g, hipStream_t s);
+// float32 contractions of the same shape: A float32, B and C float64 (B
+// rounded to float32, float32 accumulation); other shapes fall back to
+// launch_gemm.
+int launch_gemm_si_f32(const GemmBatch& g, hipStream_t s);
 
 // Householder QR (in place, Q returned with R_ii >= 0) of `count` N x k
 // row-major matrices.  ws must hold qr_workspace_bytes(count, N, k) bytes.

@@ -454,6 +454,12 @@ int apply_step(ctm_ctx* c, int count, const int* ci, const int* trans, double* c
     g.C[i] = dst[i];
   }
   const double bytes = (double)count * ((double)N1 * N1 * dt_size(c->cp) + 2.0 * N1 * k * 8.0);
+  if (c->cp == DT::F32) {
+    const int chk = check_gemm(c, g, DT::F32, DT::F64, DT::F64);
+    if (chk) return chk;
+    ProfScope ps(c, PC_SI_APPLY, gemm_flops(g), bytes);
+    return launch_gemm_si_f32(g, c->st);
+  }
   if (c->cp != DT::F64) return run_gemm(c, PC_SI_APPLY, g, c->cp, DT::F64, DT::F64, bytes);
   const int chk = check_gemm(c, g, DT::F64, DT::F64, DT::F64);
   if (chk) return chk;
