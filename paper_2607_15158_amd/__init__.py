@@ -103,6 +103,13 @@ _sigs = {
                                     ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_long,
                                     ctypes.c_double, ctypes.c_int, _vp]),
+    "ctm_gemm_f64_split_scratch_bytes": (ctypes.c_size_t, []),
+    "ctm_gemm_f64_split": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                          ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_long,
+                                          ctypes.c_long, ctypes.c_long, ctypes.c_double, ctypes.c_int,
+                                          _vp, ctypes.c_size_t, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int), _vp]),
     "ctm_qr_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),
     "ctm_vjp_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ctm_config), ctypes.POINTER(ctypes.c_size_t)]),
     "ctm_move_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t]),
@@ -552,6 +559,31 @@ def gemm_f64(A: Sequence, B: Sequence, C: Sequence, M, N, K, trans_a=0, lda=None
     ldc = N if ldc is None else ldc
     _check(_lib.ctm_gemm_f64(len(A), _ptr_array(A), _ptr_array(B), _ptr_array(C), M, N, K,
                              trans_a, lda, ldb, ldc, alpha, accumulate, _stream(stream)))
+
+
+def gemm_f64_split_scratch_bytes() -> int:
+    return int(_lib.ctm_gemm_f64_split_scratch_bytes())
+
+
+def gemm_f64_split(A: Sequence, B: Sequence, C: Sequence, M, N, K, trans_a: Sequence, scratch,
+                   nwg=512, lda=None, ldb=None, ldc=None, alpha=1.0, accumulate=0,
+                   stream=None) -> bool:
+    """The SI product split evenly over nwg workgroups; returns whether the
+    split ran (else the plain tile kernel did)."""
+    tr = (ctypes.c_int * len(A))(*[int(t) for t in trans_a])
+    if lda is None:
+        if len(set(int(t) for t in trans_a)) > 1 and M != K:
+            raise ValueError("mixed trans_a with M != K needs an explicit lda")
+        lda = M if trans_a[0] else K
+    ldb = N if ldb is None else ldb
+    ldc = N if ldc is None else ldc
+    used = ctypes.c_int(0)
+    sp = None if scratch is None else ctypes.c_void_p(scratch.data_ptr())
+    sb = 0 if scratch is None else scratch.numel() * scratch.element_size()
+    _check(_lib.ctm_gemm_f64_split(len(A), _ptr_array(A), _ptr_array(B), _ptr_array(C), M, N, K,
+                                   tr, lda, ldb, ldc, alpha, accumulate, sp, sb, nwg,
+                                   ctypes.byref(used), _stream(stream)))
+    return bool(used.value)
 
 
 def qr_f64(W: Sequence, stream=None):

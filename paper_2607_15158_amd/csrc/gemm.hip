@@ -362,6 +362,246 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// Stream-K form of the skinny tile for the SI applications.  A launch of
+// count x tiles_m tiles of BM rows (432 at D = 6) leaves a ninth of the
+// chip's 2-per-CU workgroup slots idle or half-loaded; here exactly nwg
+// workgroups (2 per CU) each take an equal, contiguous range of the
+// (tile, K-slice) space.  A tile inside one range is written directly; a
+// tile cut by range boundaries leaves partial tiles in scratch (slot 2w for
+// the segment that starts a range, 2w+1 for the one that ends it), which a
+// second kernel sums in workgroup order, so results do not depend on timing.
+// ---------------------------------------------------------------------------
+struct StreamK {
+  long total;     // count * tiles_m * nslices
+  int nslices;    // BK-slices of K per tile
+  int tiles_m;
+  int nwg;        // workgroups of the main kernel
+  double* part;   // 2 * nwg partial BM x BN tiles (row-major)
+};
+
+__device__ __forceinline__ long sk_begin(long w, const StreamK& sk) { return w * sk.total / sk.nwg; }
+
+__device__ __forceinline__ int sk_owner(long p, const StreamK& sk) {
+  int w = (int)((p * sk.nwg) / sk.total);
+  while (w + 1 < sk.nwg && sk_begin(w + 1, sk) <= p) ++w;
+  while (w > 0 && sk_begin(w, sk) > p) --w;
+  return w;
+}
+
+// acc += op(A)[m0 .. m0+BM) x B over the K slices [s0, s1) of problem prob.
+template <int BM, int BN, int WGM, int WGN, bool TRANS, int MI, int NI>
+__device__ __forceinline__ void sk_segment(const GemmBatch& g, int prob, int m0, int s0, int s1,
+                                           double (*As)[SkinnyA<BM, 16>::SIZE],
+                                           double (*Bs)[16][BN + 16], v4d (&acc)[MI][NI]) {
+  constexpr int BK = 16;
+  using AL = SkinnyA<BM, BK>;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int NA = BM * BK / 2, NB = BN * BK / 2;
+  constexpr int VA = (NA + NT - 1) / NT, VB = (NB + NT - 1) / NT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int M = g.M, N = g.N, K = g.K;
+  const double* A = (const double*)g.A[prob];
+  const double* B = (const double*)g.B[prob];
+  const long lda = g.lda, ldb = g.ldb;
+  v2d ra[VA], rb[VB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < VA; ++e) {
+      const int i = tid + e * NT;
+      v2d v = {0.0, 0.0};
+      if (i < NA) {
+        if (TRANS) {
+          const int gk = k0 + i / (BM / 2), gm = m0 + 2 * (i % (BM / 2));
+          if (gk < K) {
+            const double* p = A + (long)gk * lda + gm;
+            if (gm + 1 < M) v = *(const v2d*)p;
+            else if (gm < M) v.x = p[0];
+          }
+        } else {
+          const int gm = m0 + i / (BK / 2), gk = k0 + 2 * (i % (BK / 2));
+          if (gm < M) {
+            const double* p = A + (long)gm * lda + gk;
+            if (gk + 1 < K) v = *(const v2d*)p;
+            else if (gk < K) v.x = p[0];
+          }
+        }
+      }
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < VB; ++e) {
+      const int i = tid + e * NT;
+      const int gk = k0 + i / (BN / 2), gn = 2 * (i % (BN / 2));
+      v2d v = {0.0, 0.0};
+      if (i < NB && gk < K) {
+        const double* p = B + (long)gk * ldb + gn;
+        if (gn + 1 < N) v = *(const v2d*)p;
+        else if (gn < N) v.x = p[0];
+      }
+      rb[e] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < VA; ++e) {
+      const int i = tid + e * NT;
+      if (i < NA) {
+        if (TRANS) {
+          const int kk = i / (BM / 2), m = 2 * (i % (BM / 2));
+          *(v2d*)&As[buf][kk * AL::LT + m] = ra[e];
+        } else {
+          const int m = i / (BK / 2), kk = 2 * (i % (BK / 2));
+          As[buf][m * AL::LN + kk] = ra[e].x;
+          As[buf][m * AL::LN + kk + 1] = ra[e].y;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VB; ++e) {
+      const int i = tid + e * NT;
+      if (i < NB) *(v2d*)&Bs[buf][i / (BN / 2)][2 * (i % (BN / 2))] = rb[e];
+    }
+  };
+  load(s0 * BK);
+  store(0);
+  __syncthreads();
+  for (int kt = s0; kt < s1; ++kt) {
+    const int buf = (kt - s0) & 1;
+    if (kt + 1 < s1) load((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double a[MI], b[NI];
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const int m = wm * WTM + i * 16 + (lane & 15);
+        a[i] = TRANS ? As[buf][kr * AL::LT + m] : As[buf][m * AL::LN + kr];
+      }
+#pragma unroll
+      for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < s1) store(buf ^ 1);
+    __syncthreads();
+  }
+}
+
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_streamk_f64(
+    GemmBatch g, StreamK sk) {
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int MI = WTM / 16, NI = WTN / 16;
+  __shared__ double As[2][SkinnyA<BM, 16>::SIZE];
+  __shared__ double Bs[2][16][BN + 16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const long begin = sk_begin(w, sk), end = sk_begin(w + 1, sk);
+  const int M = g.M, N = g.N;
+  long pos = begin;
+  while (pos < end) {
+    const long tile = pos / sk.nslices;
+    const int s0 = (int)(pos % sk.nslices);
+    const int s1 = (int)((long)s0 + (end - pos) < sk.nslices ? s0 + (end - pos) : sk.nslices);
+    const int prob = (int)(tile / sk.tiles_m), m0 = (int)(tile % sk.tiles_m) * BM;
+    v4d acc[MI][NI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+    if (g.transA[prob])
+      sk_segment<BM, BN, WGM, WGN, true, MI, NI>(g, prob, m0, s0, s1, As, Bs, acc);
+    else
+      sk_segment<BM, BN, WGM, WGN, false, MI, NI>(g, prob, m0, s0, s1, As, Bs, acc);
+    if (s0 == 0 && s1 == sk.nslices) {
+      // the whole tile: written here
+      double* C = (double*)g.C[prob];
+      long offn[NI];
+      bool okn[NI];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int n = wn * WTN + j * 16 + (lane & 15);
+        okn[j] = n < N;
+        offn[j] = okn[j] ? map2(n, g.cdiv_n, g.cs_n1, g.cs_n0) : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+          if (m >= M) continue;
+          const long offm = map2(m, g.cdiv_m, g.cs_m1, g.cs_m0);
+#pragma unroll
+          for (int j = 0; j < NI; ++j) {
+            if (!okn[j]) continue;
+            double* p = C + offm + offn[j];
+            double v = g.alpha * acc[i][j][r];
+            if (g.accumulate) v += *p;
+            *p = v;
+          }
+        }
+      }
+    } else {
+      // part of a tile: into the slot of this segment
+      double* P = sk.part + (long)(2 * w + (pos == begin ? 0 : 1)) * (BM * BN);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ml = wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+#pragma unroll
+          for (int j = 0; j < NI; ++j) P[ml * BN + wn * WTN + j * 16 + (lane & 15)] = acc[i][j][r];
+        }
+    }
+    pos += s1 - s0;
+  }
+}
+
+// Sums the partial tiles of every tile cut by range boundaries, in
+// workgroup order, and writes them (alpha and accumulate as in the main
+// kernel; the split runs only with a plain row-major C).  kFixRows-row strips of a tile per block of 256
+// threads, two adjacent columns per thread.  Ranges are never empty here (the
+// split runs only with at least 8 slices per workgroup), so every workgroup
+// between the first and the last owner of a tile left a partial in slot 2w.
+constexpr int kFixRows = 24;
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_streamk_fixup(GemmBatch g, StreamK sk) {
+  static_assert(BM % kFixRows == 0 && BN % 2 == 0, "strip shape");
+  const long tile = blockIdx.x / (BM / kFixRows);
+  const int r0 = (blockIdx.x % (BM / kFixRows)) * kFixRows;
+  const long t0 = tile * sk.nslices, t1 = t0 + sk.nslices;
+  const int wf = sk_owner(t0, sk), wl = sk_owner(t1 - 1, sk);
+  if (wf == wl) return;
+  const int prob = (int)(tile / sk.tiles_m), m0 = (int)(tile % sk.tiles_m) * BM;
+  const int first_slot = sk_begin(wf, sk) < t0 ? 2 * wf + 1 : 2 * wf;
+  double* C = (double*)g.C[prob];
+  constexpr int PR = BN / 2;   // column pairs per row
+  for (int q = threadIdx.x; q < kFixRows * PR; q += 256) {
+    const int ml = r0 + q / PR, n = 2 * (q % PR), m = m0 + ml;
+    if (m >= g.M || n >= g.N) continue;
+    const long e = (long)ml * BN + n;
+    v2d v = *(const v2d*)&sk.part[(long)first_slot * (BM * BN) + e];
+    for (int w = wf + 1; w <= wl; ++w) v += *(const v2d*)&sk.part[(long)(2 * w) * (BM * BN) + e];
+    const bool two = n + 1 < g.N;
+    double* p = C + (long)m * g.cs_m0 + n;
+    double o0 = g.alpha * v.x, o1 = g.alpha * v.y;
+    if (g.accumulate) {
+      o0 += p[0];
+      if (two) o1 += p[1];
+    }
+    p[0] = o0;
+    if (two) p[1] = o1;
+  }
+}
+
 template <int BM, int BN, int WGM, int WGN, int ROLE>
 __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_skinny_f64(
     GemmBatch g, int tiles_m, int tiles_n) {
@@ -588,6 +828,41 @@ int launch_gemm_si(const GemmBatch& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch <= 0) return 0;
   if (g.N > 160 || !skinny_ok(g)) return launch_gemm(g, DT::F64, DT::F64, DT::F64, s);
   return launch_skinny<96, 160, 2, 2, 1>(g, s);
+}
+
+size_t gemm_si_scratch_bytes() { return (size_t)2 * kStreamKWgs * 96 * 160 * sizeof(double); }
+
+bool gemm_si_balanced_useful(int count, int M, int N, int K, int nwg) {
+  // balanced ranges pay off once the tiles outnumber the CUs and each tile
+  // holds several slices; below that the plain tile kernel
+  return nwg >= 2 && nwg <= kStreamKWgs && N <= 160 && (long)ceil_div(M, 96) * count >= nwg / 2 &&
+         ceil_div(K, 16) >= 16;
+}
+
+bool gemm_si_balanced_applies(const GemmBatch& g, const void* scratch, int nwg) {
+  if (!scratch || ((uintptr_t)scratch & 15) || g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch != 1)
+    return false;
+  const bool rowmajor_c = g.cdiv_m >= g.M && g.cdiv_n >= g.N && g.cs_n0 == 1;
+  return gemm_si_balanced_useful(g.count, g.M, g.N, g.K, nwg) && skinny_ok(g) && rowmajor_c &&
+         (long)g.count * ceil_div(g.M, 96) * ceil_div(g.K, 16) <= (1L << 40);
+}
+
+int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int nwg, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch <= 0) return 0;
+  if (!gemm_si_balanced_applies(g, scratch, nwg)) return launch_gemm_si(g, s);
+  const int tm = ceil_div(g.M, 96);
+  const int ns = ceil_div(g.K, 16);
+  StreamK sk;
+  sk.nslices = ns;
+  sk.tiles_m = tm;
+  sk.total = (long)g.count * tm * ns;
+  sk.nwg = nwg;
+  sk.part = scratch;
+  gemm_streamk_f64<96, 160, 2, 2><<<nwg, 256, 0, s>>>(g, sk);
+  CTM_HIP_TRY(hipGetLastError());
+  gemm_streamk_fixup<96, 160><<<(int)((long)g.count * tm * (96 / kFixRows)), 256, 0, s>>>(g, sk);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
 }
 
 namespace {

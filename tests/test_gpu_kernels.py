@@ -2,7 +2,10 @@
 
 GEMM against float64 NumPy products (N <= 160 runs the skinny kernel of the
 enlarged-corner applications, wide N with long K the 256 x 144 double-
-buffered tiles, short K the general tiles); Householder QR against the oracle's
+buffered tiles, short K the general tiles; the split form of the skinny
+kernel with ranges shorter and longer than a tile, mixed transposes, padded
+rows, alpha and accumulation, and the cases where it hands over to the
+plain tiles); Householder QR against the oracle's
 QR convention (R_ii >= 0) and orthogonality; Jacobi SVD against NumPy's
 singular values and the reconstruction.  Shapes span several tiles and
 ragged tails.
@@ -50,6 +53,61 @@ def test_gemm_accumulate_and_alpha():
     P.gemm_f64([dev(A)], [dev(B)], [Cd], 40, 30, 50, alpha=-0.5, accumulate=1)
     torch.cuda.synchronize()
     assert np.allclose(Cd.cpu().numpy(), C0 - 0.5 * A @ B, atol=1e-12)
+
+
+SPLIT_CASES = [
+    # count, M, N, K, trans per problem, lda, nwg, alpha, accumulate, split expected
+    (8, 3000, 160, 3000, [0, 0, 0, 0, 1, 1, 1, 1], None, 512, 1.0, 0, True),   # ragged M and K
+    (3, 1000, 78, 515, [1, 0, 1], 1000, 64, -0.5, 1, True),                  # mixed, padded lda
+    (1, 4000, 160, 250, [0], None, 16, 1.0, 0, True),       # ranges of 2.6 tiles
+    (1, 200, 16, 300, [1], None, 2, 2.0, 1, True),          # two workgroups, 1.5 tiles each
+    (2, 2000, 33, 4001, [0, 0], None, 512, 1.0, 0, False),  # odd lda: the plain tile kernel
+    (8, 500, 160, 500, [0] * 8, None, 512, 1.0, 0, False),  # 48 tiles: too few to split
+]
+
+
+@pytest.mark.parametrize("case", range(len(SPLIT_CASES)))
+def test_gemm_split_matches_numpy(case):
+    count, M, N, K, trans, lda, nwg, alpha, acc, expect = SPLIT_CASES[case]
+    rng = np.random.default_rng(100 + case)
+    lda = lda or (M if trans[0] else K)
+    A = []
+    for t in trans:
+        rows, cols = (K, M) if t else (M, K)
+        full = rng.standard_normal((rows, lda))
+        A.append(full)
+    B = [rng.standard_normal((K, N)) for _ in range(count)]
+    C0 = [rng.standard_normal((M, N)) for _ in range(count)]
+    scratch = torch.empty(P.gemm_f64_split_scratch_bytes() // 8, dtype=torch.float64, device="cuda")
+    Ad, Bd = [dev(a) for a in A], [dev(b) for b in B]
+    outs = []
+    for rep in range(2):
+        Cd = [dev(c.copy()) for c in C0]
+        used = P.gemm_f64_split(Ad, Bd, Cd, M, N, K, trans, scratch, nwg=nwg, lda=lda,
+                                alpha=alpha, accumulate=acc)
+        torch.cuda.synchronize()
+        assert used == expect
+        outs.append([c.cpu().numpy() for c in Cd])
+    for i, (a, t) in enumerate(zip(A, trans)):
+        op = a[:, :M].T if t else a[:, :K]
+        ref = alpha * (op @ B[i]) + (C0[i] if acc else 0.0)
+        # a length-K float64 dot product in any order is within (K + 2) u of
+        # the sum of |terms| (u = 2^-53); twice that covers NumPy's own rounding
+        bound = 2 * (K + 2) * 2.0 ** -53 * (abs(alpha) * (np.abs(op) @ np.abs(B[i])) +
+                                           (np.abs(C0[i]) if acc else 0.0))
+        assert np.all(np.abs(outs[0][i] - ref) <= bound), i
+        assert np.array_equal(outs[0][i], outs[1][i]), i      # fixed summation order
+
+
+def test_gemm_split_without_scratch_runs_plain_tiles():
+    rng = np.random.default_rng(5)
+    A, B = rng.standard_normal((3000, 3000)), rng.standard_normal((3000, 96))
+    Cd = [torch.zeros(3000, 96, dtype=torch.float64, device="cuda") for _ in range(8)]
+    used = P.gemm_f64_split([dev(A)] * 8, [dev(B)] * 8, Cd, 3000, 96, 3000, [0] * 8, None)
+    torch.cuda.synchronize()
+    assert not used
+    ref = A @ B
+    assert np.abs(Cd[7].cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("N,k", [(32, 24), (100, 100), (1024, 72), (2500, 105), (5184, 160),

@@ -472,19 +472,21 @@ def test_single_column_environment(p):
     assert [m[0] for m in modes] == [1, 2, 2, 2, 2]
 
 
-@pytest.mark.parametrize("chi,p", [(180, 12), (176, 10)])
-def test_widest_subspace_blocks(chi, p):
+@pytest.mark.parametrize("D,chi,p", [(4, 180, 12), (4, 176, 10), (5, 120, 8)])
+def test_widest_subspace_blocks(D, chi, p):
     """The widest blocks the QR leaves and the small SVD take: k = 192 with
     N = 2880 rows in fifteen leaves of exactly 192 rows, and k = 186 with
-    N = 2816 rows in ragged leaves of 187 and 188 rows.  One SI move from a
-    seeded random environment of full dimension against the oracle's
+    N = 2816 rows in ragged leaves of 187 and 188 rows; and N = 3000, k = 128
+    (D = 5), where the SI applications (8 x 32 row tiles, 188 K slices, the
+    last one half full) run split evenly over the workgroups.  One SI move
+    from a seeded random environment of full dimension against the oracle's
     corners (C_i' = P_r Ct_i P_l from its enlarged corners and SI
     projectors) and the kept columns of the recycled blocks."""
-    D, n_si = 4, 2
+    n_si = 2
     Dl = D * D
     cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=n_si)
     N, k = cfg.N, cfg.k
-    assert (N, k) in ((2880, 192), (2816, 186))
+    assert (N, k) in ((2880, 192), (2816, 186), (3000, 128))
     A = S.product_plus_noise_site(2, D, 3)
     X = np.stack([S.gaussian_block(N, k, 40 + b) for b in range(4)])
     Y = np.stack([S.gaussian_block(N, k, 50 + b) for b in range(4)])
