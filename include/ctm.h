@@ -386,23 +386,25 @@ ctm_status ctm_gemm_f64(int count, const double* const* A, const double* const* 
 
 /* The product of ctm_gemm_f64 for the subspace-iteration applications
  * (QR-based projector section: M X and M^T Y^T with thin blocks, N <= 160),
- * with the (96-row tile, 16-wide K slice) space of all `count` problems split
- * into `nwg` equal contiguous ranges, one per workgroup (2 per CU fill the
- * chip: 512 on 256 CUs; 2 <= nwg <= 512), so that no CU idles while another
- * finishes a tile.  Tiles cut by range boundaries are summed from partial
- * tiles in `scratch` (device memory of ctm_gemm_f64_split_scratch_bytes()
- * bytes, owned by the caller, contents not preserved) by a second kernel in
- * a fixed order: the result is the same on every call.  trans_a is a host
- * array of `count` flags (0 or 1) as in ctm_gemm_f64.  When the split does not
- * apply (scratch NULL, N > 160, fewer than nwg/2 tiles, fewer than 16 K
- * slices, operands or scratch not 16-byte aligned, odd lda or ldb) the plain
- * tile kernel runs; if
- * used_split is non-NULL it receives 1 when the split ran, else 0. */
+ * with the (192-row tile, 16-wide K slice) space of all `count` problems
+ * split into `ncu` equal contiguous ranges, one per workgroup of 8 wavefronts
+ * (one workgroup per CU: 256 on MI355X; 1 <= ncu <= 256), so that no CU idles
+ * while another finishes a tile.  Tiles cut by range boundaries are summed
+ * from partial tiles in `scratch` (device memory of
+ * ctm_gemm_f64_split_scratch_bytes() bytes, owned by the caller, contents not
+ * preserved; calls sharing one scratch must be ordered on one stream) by a
+ * second kernel in a fixed order: the result is the same on every call.
+ * trans_a is a host array of `count` flags (0 or 1) as in ctm_gemm_f64; C is
+ * row-major with leading dimension ldc.  When the split does not apply
+ * (scratch NULL, N > 160, fewer than ncu/2 tiles, fewer than 16 K slices,
+ * operands or scratch not 16-byte aligned, odd lda or ldb) the plain tile
+ * kernel runs; if used_split is non-NULL it receives 1 when the split ran,
+ * else 0. */
 size_t ctm_gemm_f64_split_scratch_bytes(void);
 ctm_status ctm_gemm_f64_split(int count, const double* const* A, const double* const* B,
                               double* const* C, int M, int N, int K, const int* trans_a, long lda,
                               long ldb, long ldc, double alpha, int accumulate, void* scratch,
-                              size_t scratch_bytes, int nwg, int* used_split, void* stream);
+                              size_t scratch_bytes, int ncu, int* used_split, void* stream);
 
 /* Thin Householder QR of `count` N x k row-major matrices W_i (N >= k), in
  * place: on return W_i holds Q with R_ii >= 0 (QR-based projector section,

@@ -566,10 +566,10 @@ def gemm_f64_split_scratch_bytes() -> int:
 
 
 def gemm_f64_split(A: Sequence, B: Sequence, C: Sequence, M, N, K, trans_a: Sequence, scratch,
-                   nwg=512, lda=None, ldb=None, ldc=None, alpha=1.0, accumulate=0,
+                   ncu=256, lda=None, ldb=None, ldc=None, alpha=1.0, accumulate=0,
                    stream=None) -> bool:
-    """The SI product split evenly over nwg workgroups; returns whether the
-    split ran (else the plain tile kernel did)."""
+    """The SI product split evenly over ncu CUs; returns whether the split
+    ran (else the plain tile kernel did)."""
     tr = (ctypes.c_int * len(A))(*[int(t) for t in trans_a])
     if lda is None:
         if len(set(int(t) for t in trans_a)) > 1 and M != K:
@@ -581,7 +581,7 @@ def gemm_f64_split(A: Sequence, B: Sequence, C: Sequence, M, N, K, trans_a: Sequ
     sp = None if scratch is None else ctypes.c_void_p(scratch.data_ptr())
     sb = 0 if scratch is None else scratch.numel() * scratch.element_size()
     _check(_lib.ctm_gemm_f64_split(len(A), _ptr_array(A), _ptr_array(B), _ptr_array(C), M, N, K,
-                                   tr, lda, ldb, ldc, alpha, accumulate, sp, sb, nwg,
+                                   tr, lda, ldb, ldc, alpha, accumulate, sp, sb, ncu,
                                    ctypes.byref(used), _stream(stream)))
     return bool(used.value)
 

@@ -106,14 +106,15 @@ int launch_gemm(const GemmBatch& g, DT ta, DT tb, DT tc, hipStream_t s);
 // float64 C = op(A) B with N <= 160 (the enlarged corner applied to an
 // isometry block); other shapes fall back to launch_gemm.
 int launch_gemm_si(const GemmBatch& g, hipStream_t s);
-// The same product with the (tile, K-slice) space split evenly over nwg
-// workgroups (2 per CU; at most kStreamKWgs) and the cut tiles summed by a
-// second kernel in a fixed order; scratch holds gemm_si_scratch_bytes().
-constexpr int kStreamKWgs = 512;
+// The same product with the (192-row tile, 16-wide K slice) space split
+// evenly over ncu workgroups of 8 wavefronts (one per CU; at most
+// kSplitMaxCus) and the cut tiles summed by a second kernel in a fixed order;
+// scratch holds gemm_si_scratch_bytes().  Other shapes: launch_gemm_si.
+constexpr int kSplitMaxCus = 256;
 size_t gemm_si_scratch_bytes();
-bool gemm_si_balanced_useful(int count, int M, int N, int K, int nwg);
-bool gemm_si_balanced_applies(const GemmBatch& g, const void* scratch, int nwg);
-int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int nwg, hipStream_t s);
+bool gemm_si_balanced_useful(int count, int M, int N, int K, int ncu);
+bool gemm_si_balanced_applies(const GemmBatch& g, const void* scratch, int ncu);
+int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStream_t s);
 // float32 contractions of the same shape: A float32, B and C float64 (B
 // rounded to float32, float32 accumulation); other shapes fall back to
 // launch_gemm.

@@ -132,7 +132,7 @@ struct ctm_ctx {
   int* fs_info;
   int* fs_perm;              // descending order of the dense SVD's singular values
   double* sk_part = nullptr;  // partial tiles of the balanced SI applications
-  int sk_wgs = kStreamKWgs;  // workgroups of a balanced launch (2 per CU)
+  int sk_cus = kSplitMaxCus;  // CUs a balanced launch spreads over
   double* obs_y;             // [d^2][x Dl x]
   double* obs_w;             // [d^2][x Dl x]
   double* obs_op;            // [d^4] device copy of an operator
@@ -298,7 +298,7 @@ size_t carve(ctm_ctx* c, char* base) {
   c->fs_Vs = cv.take<double>(Nm * chi);
   c->fs_info = cv.take<int>(64);
   c->fs_perm = cv.take<int>(Nm);
-  c->sk_part = c->cp == DT::F64 && gemm_si_balanced_useful(8, (int)N, (int)k, (int)N, kStreamKWgs)
+  c->sk_part = c->cp == DT::F64 && gemm_si_balanced_useful(8, (int)N, (int)k, (int)N, kSplitMaxCus)
                    ? (double*)cv.take_bytes(gemm_si_scratch_bytes())
                    : nullptr;
   c->obs_y = cv.take<double>((size_t)dd * xm * Dl * xm);
@@ -469,7 +469,7 @@ int apply_step(ctm_ctx* c, int count, const int* ci, const int* trans, double* c
   const int chk = check_gemm(c, g, DT::F64, DT::F64, DT::F64);
   if (chk) return chk;
   ProfScope ps(c, PC_SI_APPLY, gemm_flops(g), bytes);
-  return launch_gemm_si_balanced(g, c->sk_part, c->sk_wgs, c->st);
+  return launch_gemm_si_balanced(g, c->sk_part, c->sk_cus, c->st);
 }
 
 inline int md(int i) { return ((i % 4) + 4) % 4; }
@@ -947,7 +947,7 @@ int c4v_projectors(ctm_ctx* c, int mode, int keep) {
       const int chk = check_gemm(c, g, DT::F64, DT::F64, DT::F64);
       if (chk) return chk;
       ProfScope ps(c, PC_SI_APPLY, gemm_flops(g), (double)N1 * N1 * 8 + 2.0 * N1 * k * 8);
-      return launch_gemm_si_balanced(g, c->sk_part, c->sk_wgs, c->st);
+      return launch_gemm_si_balanced(g, c->sk_part, c->sk_cus, c->st);
     };
     for (int step = 0; step < c->cfg.n_si; ++step) {
       TRY(apply(c->X[0], c->W[0][0]));
@@ -1487,7 +1487,7 @@ ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      c->sk_wgs = std::min(2 * cus, kStreamKWgs);
+      c->sk_cus = std::min(cus, kSplitMaxCus);
   }
   const size_t need = carve(c, nullptr);
   if (workspace) {
@@ -1800,7 +1800,7 @@ int vjp_view(ctm_ctx* c, VjpView* v) {
   v->A_site = c->A_site;
   v->a = c->a;
   v->sk_part = c->sk_part;
-  v->sk_wgs = c->sk_wgs;
+  v->sk_cus = c->sk_cus;
   const long Dl = c->Dl;
   const long su = Dl * Dl * Dl, sl = Dl * Dl, sd = Dl, sr = 1;
   const long perm[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
@@ -1887,13 +1887,13 @@ size_t ctm_gemm_f64_split_scratch_bytes(void) { return gemm_si_scratch_bytes(); 
 ctm_status ctm_gemm_f64_split(int count, const double* const* A, const double* const* B,
                               double* const* C, int M, int N, int K, const int* trans_a, long lda,
                               long ldb, long ldc, double alpha, int accumulate, void* scratch,
-                              size_t scratch_bytes, int nwg, int* used_split, void* stream) {
+                              size_t scratch_bytes, int ncu, int* used_split, void* stream) {
   if (count < 0 || count > kMaxProb || M < 0 || N < 0 || K < 0 || !A || !B || !C || !trans_a)
     return (ctm_status)fail(nullptr, CTM_E_ARG, "invalid gemm arguments");
   if (scratch && scratch_bytes < gemm_si_scratch_bytes())
     return (ctm_status)fail(nullptr, CTM_E_ARG, "split scratch smaller than ctm_gemm_f64_split_scratch_bytes");
-  if (nwg < 2 || nwg > kStreamKWgs)
-    return (ctm_status)fail(nullptr, CTM_E_ARG, "nwg outside [2, 512]");
+  if (ncu < 1 || ncu > kSplitMaxCus)
+    return (ctm_status)fail(nullptr, CTM_E_ARG, "ncu outside [1, 256]");
   GemmBatch g = gemm_rowmajor(count, M, N, K, lda, ldb, ldc);
   g.alpha = alpha;
   g.accumulate = accumulate;
@@ -1905,8 +1905,8 @@ ctm_status ctm_gemm_f64_split(int count, const double* const* A, const double* c
     g.C[i] = C[i];
     g.transA[i] = trans_a[i];
   }
-  if (used_split) *used_split = gemm_si_balanced_applies(g, scratch, nwg) ? 1 : 0;
-  int r = launch_gemm_si_balanced(g, (double*)scratch, nwg, (hipStream_t)stream);
+  if (used_split) *used_split = gemm_si_balanced_applies(g, scratch, ncu) ? 1 : 0;
+  int r = launch_gemm_si_balanced(g, (double*)scratch, ncu, (hipStream_t)stream);
   return r ? CTM_E_DEVICE : CTM_OK;
 }
 

@@ -363,20 +363,22 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
 }
 
 // ---------------------------------------------------------------------------
-// Stream-K form of the skinny tile for the SI applications.  A launch of
-// count x tiles_m tiles of BM rows (432 at D = 6) leaves a ninth of the
-// chip's 2-per-CU workgroup slots idle or half-loaded; here exactly nwg
-// workgroups (2 per CU) each take an equal, contiguous range of the
-// (tile, K-slice) space.  A tile inside one range is written directly; a
-// tile cut by range boundaries leaves partial tiles in scratch (slot 2w for
-// the segment that starts a range, 2w+1 for the one that ends it), which a
-// second kernel sums in workgroup order, so results do not depend on timing.
+// Split form of the skinny tile for the SI applications (stream-K style).  A
+// launch of one tile per workgroup leaves CUs idle or half loaded when the
+// count x tiles_m tiles do not fill the chip evenly (432 tiles of 96 rows on
+// 512 slots at D = 6).  Here one workgroup of 8 wavefronts per CU (192 x 160
+// tiles: each B block is re-read by half as many tiles as with 96 rows) takes
+// an equal, contiguous range of the (tile, K-slice) space.  A tile inside one
+// range is written directly; a tile cut by range boundaries leaves partial
+// tiles in scratch (slot 2w for the segment that starts range w, 2w+1 for the
+// one that ends it), which a second kernel sums in workgroup order, so
+// results do not depend on timing.
 // ---------------------------------------------------------------------------
 struct StreamK {
   long total;     // count * tiles_m * nslices
   int nslices;    // BK-slices of K per tile
   int tiles_m;
-  int nwg;        // workgroups of the main kernel
+  int nwg;        // workgroups (ranges) of the main kernel
   double* part;   // 2 * nwg partial BM x BN tiles (row-major)
 };
 
@@ -505,11 +507,15 @@ __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_s
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const long begin = sk_begin(w, sk), end = sk_begin(w + 1, sk);
   const int M = g.M, N = g.N;
-  long pos = begin;
-  while (pos < end) {
-    const long tile = pos / sk.nslices;
-    const int s0 = (int)(pos % sk.nslices);
-    const int s1 = (int)((long)s0 + (end - pos) < sk.nslices ? s0 + (end - pos) : sk.nslices);
+  // segments last to first: a range of L <= nslices slices then reads slice
+  // t of its second tile, and later slice t + nslices - L of its first, at
+  // step t, so the ranges sharing a problem (and an XCD) walk K in two
+  // phases and reuse each B slice from L2
+  long pend = end;
+  while (pend > begin) {
+    const long tile = (pend - 1) / sk.nslices;
+    const long pos = tile * sk.nslices > begin ? tile * sk.nslices : begin;
+    const int s0 = (int)(pos - tile * sk.nslices), s1 = (int)(pend - tile * sk.nslices);
     const int prob = (int)(tile / sk.tiles_m), m0 = (int)(tile % sk.tiles_m) * BM;
     v4d acc[MI][NI];
 #pragma unroll
@@ -560,7 +566,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_s
           for (int j = 0; j < NI; ++j) P[ml * BN + wn * WTN + j * 16 + (lane & 15)] = acc[i][j][r];
         }
     }
-    pos += s1 - s0;
+    pend = pos;
   }
 }
 
@@ -830,37 +836,38 @@ int launch_gemm_si(const GemmBatch& g, hipStream_t s) {
   return launch_skinny<96, 160, 2, 2, 1>(g, s);
 }
 
-size_t gemm_si_scratch_bytes() { return (size_t)2 * kStreamKWgs * 96 * 160 * sizeof(double); }
+size_t gemm_si_scratch_bytes() { return (size_t)2 * kSplitMaxCus * 192 * 160 * sizeof(double); }
 
-bool gemm_si_balanced_useful(int count, int M, int N, int K, int nwg) {
-  // balanced ranges pay off once the tiles outnumber the CUs and each tile
-  // holds several slices; below that the plain tile kernel
-  return nwg >= 2 && nwg <= kStreamKWgs && N <= 160 && (long)ceil_div(M, 96) * count >= nwg / 2 &&
+bool gemm_si_balanced_useful(int count, int M, int N, int K, int ncu) {
+  // ranges pay off once the tiles reach half the CUs and each tile holds
+  // several slices; below that the plain tile kernel.  With these bounds
+  // every range holds at least 8 slices, so none is empty.
+  return ncu >= 1 && ncu <= kSplitMaxCus && N <= 160 && (long)ceil_div(M, 192) * count >= ncu / 2 &&
          ceil_div(K, 16) >= 16;
 }
 
-bool gemm_si_balanced_applies(const GemmBatch& g, const void* scratch, int nwg) {
+bool gemm_si_balanced_applies(const GemmBatch& g, const void* scratch, int ncu) {
   if (!scratch || ((uintptr_t)scratch & 15) || g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch != 1)
     return false;
   const bool rowmajor_c = g.cdiv_m >= g.M && g.cdiv_n >= g.N && g.cs_n0 == 1;
-  return gemm_si_balanced_useful(g.count, g.M, g.N, g.K, nwg) && skinny_ok(g) && rowmajor_c &&
-         (long)g.count * ceil_div(g.M, 96) * ceil_div(g.K, 16) <= (1L << 40);
+  return gemm_si_balanced_useful(g.count, g.M, g.N, g.K, ncu) && skinny_ok(g) && rowmajor_c &&
+         (long)g.count * ceil_div(g.M, 192) * ceil_div(g.K, 16) <= (1L << 40);
 }
 
-int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int nwg, hipStream_t s) {
+int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch <= 0) return 0;
-  if (!gemm_si_balanced_applies(g, scratch, nwg)) return launch_gemm_si(g, s);
-  const int tm = ceil_div(g.M, 96);
+  if (!gemm_si_balanced_applies(g, scratch, ncu)) return launch_gemm_si(g, s);
+  const int tm = ceil_div(g.M, 192);
   const int ns = ceil_div(g.K, 16);
   StreamK sk;
   sk.nslices = ns;
   sk.tiles_m = tm;
   sk.total = (long)g.count * tm * ns;
-  sk.nwg = nwg;
+  sk.nwg = ncu;
   sk.part = scratch;
-  gemm_streamk_f64<96, 160, 2, 2><<<nwg, 256, 0, s>>>(g, sk);
+  gemm_streamk_f64<192, 160, 4, 2><<<ncu, 512, 0, s>>>(g, sk);
   CTM_HIP_TRY(hipGetLastError());
-  gemm_streamk_fixup<96, 160><<<(int)((long)g.count * tm * (96 / kFixRows)), 256, 0, s>>>(g, sk);
+  gemm_streamk_fixup<192, 160><<<(int)((long)g.count * tm * (192 / kFixRows)), 256, 0, s>>>(g, sk);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -17,7 +17,7 @@ struct VjpView {
   const double* ap[4];    // the corner permutations of a (float64 contractions)
   long ap_strides[4][4];  // ap[i][i0,i1,i2,i3] = a[sum_j i_j * ap_strides[i][j]]
   double* sk_part;        // partial tiles of balanced SI products (or null)
-  int sk_wgs;             // workgroups of such a launch
+  int sk_cus;             // CUs such a launch spreads over
 };
 
 // Fills v after completing a move still in flight; 0 or a ctm_status.

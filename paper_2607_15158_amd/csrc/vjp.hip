@@ -414,7 +414,7 @@ struct Run {
   ctm_ctx* c;
   hipStream_t st;
   double* sk_part = nullptr;
-  int sk_wgs = 0;
+  int sk_cus = 0;
   std::vector<std::pair<uintptr_t, uintptr_t>> reg;
 
   bool inside(const void* p, size_t bytes) const {
@@ -462,7 +462,7 @@ int gemm(Run& r, const GemmBatch& g, bool si = false) {
                     std::to_string(g.N) + " K=" + std::to_string(g.K) + ", problem " +
                     std::to_string(i) + "); launch refused");
   }
-  const int rc = si ? launch_gemm_si_balanced(g, r.sk_part, r.sk_wgs, r.st)
+  const int rc = si ? launch_gemm_si_balanced(g, r.sk_part, r.sk_cus, r.st)
                      : launch_gemm(g, DT::F64, DT::F64, DT::F64, r.st);
   if (rc) return vjp_fail(r.c, rc == 1 ? CTM_E_ARG : rc, thread_error());
   return 0;
@@ -1370,7 +1370,7 @@ int prepare(ctm_ctx* ctx, const double* state_in, void* ws, size_t ws_bytes, Pre
   P.r.c = ctx;
   P.r.st = P.v.st;
   P.r.sk_part = P.v.sk_part;
-  P.r.sk_wgs = P.v.sk_wgs;
+  P.r.sk_cus = P.v.sk_cus;
   const size_t x = P.m.x, Dl = P.m.Dl, N = P.m.N, k = P.m.k;
   P.nstate = 4 * x * x + 4 * x * Dl * x + 8 * N * k + 4;
   double chi_env = 0.0;
@@ -1815,7 +1815,7 @@ int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, do
   r.c = ctx;
   r.st = v.st;
   r.sk_part = v.sk_part;
-  r.sk_wgs = v.sk_wgs;
+  r.sk_cus = v.sk_cus;
   const size_t x = m.x, Dl = m.Dl, N = m.N, k = m.k, D4 = (size_t)m.D * m.D * m.D * m.D;
   const size_t nstate = 4 * x * x + 4 * x * Dl * x + 8 * N * k + 4;
   double chi_env = 0.0;

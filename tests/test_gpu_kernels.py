@@ -56,19 +56,20 @@ def test_gemm_accumulate_and_alpha():
 
 
 SPLIT_CASES = [
-    # count, M, N, K, trans per problem, lda, nwg, alpha, accumulate, split expected
-    (8, 3000, 160, 3000, [0, 0, 0, 0, 1, 1, 1, 1], None, 512, 1.0, 0, True),   # ragged M and K
-    (3, 1000, 78, 515, [1, 0, 1], 1000, 64, -0.5, 1, True),                  # mixed, padded lda
-    (1, 4000, 160, 250, [0], None, 16, 1.0, 0, True),       # ranges of 2.6 tiles
-    (1, 200, 16, 300, [1], None, 2, 2.0, 1, True),          # two workgroups, 1.5 tiles each
-    (2, 2000, 33, 4001, [0, 0], None, 512, 1.0, 0, False),  # odd lda: the plain tile kernel
-    (8, 500, 160, 500, [0] * 8, None, 512, 1.0, 0, False),  # 48 tiles: too few to split
+    # count, M, N, K, trans per problem, lda, CUs, alpha, accumulate, split expected
+    (8, 3000, 160, 3000, [0, 0, 0, 0, 1, 1, 1, 1], None, 256, 1.0, 0, True),  # ragged M and K
+    (3, 1000, 78, 515, [1, 0, 1], 1000, 32, -0.5, 1, True),   # mixed, padded lda, 0.6-tile ranges
+    (1, 4000, 160, 250, [0], None, 8, 1.0, 0, True),          # ranges of 2.6 tiles
+    (1, 400, 16, 300, [1], None, 2, 2.0, 1, True),            # two ranges of 1.5 tiles
+    (2, 700, 100, 260, [0, 1], 700, 1, 1.0, 0, True),         # one range: every tile whole
+    (2, 2000, 33, 4001, [0, 0], None, 256, 1.0, 0, False),    # odd lda: the plain tile kernel
+    (8, 500, 160, 500, [0] * 8, None, 256, 1.0, 0, False),    # 24 tiles: too few to split
 ]
 
 
 @pytest.mark.parametrize("case", range(len(SPLIT_CASES)))
 def test_gemm_split_matches_numpy(case):
-    count, M, N, K, trans, lda, nwg, alpha, acc, expect = SPLIT_CASES[case]
+    count, M, N, K, trans, lda, ncu, alpha, acc, expect = SPLIT_CASES[case]
     rng = np.random.default_rng(100 + case)
     lda = lda or (M if trans[0] else K)
     A = []
@@ -83,7 +84,7 @@ def test_gemm_split_matches_numpy(case):
     outs = []
     for rep in range(2):
         Cd = [dev(c.copy()) for c in C0]
-        used = P.gemm_f64_split(Ad, Bd, Cd, M, N, K, trans, scratch, nwg=nwg, lda=lda,
+        used = P.gemm_f64_split(Ad, Bd, Cd, M, N, K, trans, scratch, ncu=ncu, lda=lda,
                                 alpha=alpha, accumulate=acc)
         torch.cuda.synchronize()
         assert used == expect

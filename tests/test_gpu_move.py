@@ -477,8 +477,9 @@ def test_widest_subspace_blocks(D, chi, p):
     """The widest blocks the QR leaves and the small SVD take: k = 192 with
     N = 2880 rows in fifteen leaves of exactly 192 rows, and k = 186 with
     N = 2816 rows in ragged leaves of 187 and 188 rows; and N = 3000, k = 128
-    (D = 5), where the SI applications (8 x 32 row tiles, 188 K slices, the
-    last one half full) run split evenly over the workgroups.  One SI move
+    (D = 5), where the SI applications (8 x 16 tiles of 192 rows, the last of
+    120, and 188 K slices, the last one half full) run split evenly over the
+    CUs.  One SI move
     from a seeded random environment of full dimension against the oracle's
     corners (C_i' = P_r Ct_i P_l from its enlarged corners and SI
     projectors) and the kept columns of the recycled blocks."""
