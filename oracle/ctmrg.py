@@ -587,10 +587,49 @@ def _two_site_v(env: Env, x1: np.ndarray, x2: np.ndarray) -> np.ndarray:
     return np.einsum("ABnxc,EFcxn->ABEF", p3, q3)
 
 
+_CORNER_SPECS = ("tla,ab,bug,...uldr->...tdgr", "bug,gh,hre,...uldr->...bled",
+                 "hre,ez,zdn,...uldr->...hunl", "zdn,nt,tla,...uldr->...zrau")
+
+
+def _corner_with(env: Env, i: int, x: np.ndarray) -> np.ndarray:
+    """Enlarged corner ``i`` (the index order of ``enlarged_corners``) with the
+    site tensor ``x`` in place of ``a``: ``N x N``, or ``[s, t, N, N]`` for an
+    open double layer ``x[s, t, u, l, d, r]``."""
+    C1, C2, C3, C4 = env.C
+    T1, T2, T3, T4 = env.T
+    env_ops = ((T4, C1, T1), (T1, C2, T2), (T2, C3, T3), (T3, C4, T4))[i]
+    c = np.einsum(_CORNER_SPECS[i], *env_ops, x, **_EIN)
+    N = env.chi * x.shape[-1]
+    return c.reshape(c.shape[:-4] + (N, N))
+
+
+def _two_site_diag(env: Env, x1: np.ndarray, x2: np.ndarray, anti: bool) -> np.ndarray:
+    """Next-nearest (diagonal) pair on the 2x2 plaquette ``Tr(Ct1 Ct2 Ct3 Ct4)``:
+    site 1 top-left and site 2 bottom-right (``anti``: site 1 top-right and
+    site 2 bottom-left); the other two sites carry the plain double layer
+    ``x`` closed over its physical legs."""
+    o = 1 if anti else 0
+    a = x1 if x1.ndim == 4 else np.einsum("ss...->...", x1)
+    Ct = [_corner_with(env, i, x1 if i == o else x2 if i == o + 2 else a) for i in range(4)]
+    c0, c1, c2, c3 = (Ct[(o + j) % 4] for j in range(4))
+    if x1.ndim == 4:
+        return np.einsum("ij,jk,kl,li->", c0, c1, c2, c3, **_EIN)
+    return np.einsum("ABij,jk,EFkl,li->ABEF", c0, c1, c2, c3, **_EIN)
+
+
 def bond_rdm(env: Env, A: np.ndarray, direction: str) -> np.ndarray:
-    """Two-site reduced density matrix ``rho[(s1 s2), (t1 t2)]`` (ket s, bra t), trace 1."""
+    """Two-site reduced density matrix ``rho[(s1 s2), (t1 t2)]`` (ket s, bra t), trace 1.
+
+    ``direction``: ``h`` (site 1 left of site 2), ``v`` (site 1 above site 2),
+    ``d`` (site 1 top-left, site 2 bottom-right of a plaquette) or ``ad``
+    (site 1 top-right, site 2 bottom-left).  The diagonal bonds are the extra
+    interaction of the triangular lattice drawn on the square one
+    (triangular-lattice section)."""
     ao = double_layer_open(A)
-    E = _two_site_h(env, ao, ao) if direction == "h" else _two_site_v(env, ao, ao)
+    if direction in ("d", "ad"):
+        E = _two_site_diag(env, ao, ao, direction == "ad")
+    else:
+        E = _two_site_h(env, ao, ao) if direction == "h" else _two_site_v(env, ao, ao)
     d = A.shape[0]
     rho = E.transpose(0, 2, 1, 3).reshape(d * d, d * d)
     return rho / np.trace(rho)
@@ -604,9 +643,24 @@ def bond_value(env: Env, A: np.ndarray, op: np.ndarray, direction: str) -> float
 
 def classical_bond_value(env: Env, a: np.ndarray, a1: np.ndarray, a2: np.ndarray,
                          direction: str) -> float:
-    """Two impurities on a bond of a classical network, divided by the plain network."""
+    """Two impurities on a bond of a classical network, divided by the plain
+    network; ``direction`` as in ``bond_rdm``."""
+    if direction in ("d", "ad"):
+        anti = direction == "ad"
+        num, den = _two_site_diag_plain(env, a, a1, a2, anti), _two_site_diag_plain(env, a, a, a, anti)
+        return float(num / den)
     f = _two_site_h if direction == "h" else _two_site_v
     return float(f(env, a1, a2) / f(env, a, a))
+
+
+def _two_site_diag_plain(env: Env, a: np.ndarray, a1: np.ndarray, a2: np.ndarray,
+                         anti: bool) -> float:
+    """Plaquette value with rank-4 tensors ``a1``, ``a2`` on the diagonal pair
+    and ``a`` on the other two sites."""
+    o = 1 if anti else 0
+    Ct = [_corner_with(env, i, a1 if i == o else a2 if i == o + 2 else a) for i in range(4)]
+    c0, c1, c2, c3 = (Ct[(o + j) % 4] for j in range(4))
+    return float(np.einsum("ij,jk,kl,li->", c0, c1, c2, c3, **_EIN))
 
 
 __all__.append("classical_bond_value")

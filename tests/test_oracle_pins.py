@@ -1,6 +1,6 @@
 """Pins of the FP64 oracle against facts that do not come from the oracle itself.
 
-* exact 2D Ising values (Onsager / Yang closed forms, ``tests/golden``),
+* exact 2D Ising values (Onsager / Yang / McCoy-Wu closed forms, ``tests/golden``),
   reached through the classical path (a given directly) and through the
   quantum path (a d=2, D=2 iPEPS whose norm network is the Ising model);
 * exact product states;
@@ -48,6 +48,9 @@ def test_classical_ising_closed_forms(proj):
     for direction in "hv":
         ss = O.classical_bond_value(env, a, asig, asig, direction)
         assert abs(ss - gold(beta, "nn_correlation")) <= 1e-9
+    for direction in ("d", "ad"):
+        ss = O.classical_bond_value(env, a, asig, asig, direction)
+        assert abs(ss - gold(beta, "diag_correlation")) <= 1e-9
     if proj == "si":
         assert hist[-1]["delta"] < 1e-12
 
@@ -81,6 +84,9 @@ def test_ising_peps_bond_correlation(beta):
     for direction in "hv":
         zz = O.bond_value(env, A, np.kron(Z, Z), direction)
         assert abs(zz - gold(beta, "nn_correlation")) <= 2e-11
+    for direction in ("d", "ad"):
+        zz = O.bond_value(env, A, np.kron(Z, Z), direction)
+        assert abs(zz - gold(beta, "diag_correlation")) <= 1e-10
     # symmetric boundary: the Z2-even state has <sigma^z> = 0 exactly
     assert abs(O.onesite_value(env, a, O.double_layer_op(A, Z))) <= 1e-9
 
@@ -102,7 +108,7 @@ def test_product_state_exact(proj):
     p = phi / np.linalg.norm(phi)
     for op in (S.heisenberg_bond(), np.kron(X, Zp)):
         exact = np.kron(p, p) @ op @ np.kron(p, p)
-        for direction in "hv":
+        for direction in ("h", "v", "d", "ad"):
             assert abs(O.bond_value(env, A, op, direction) - exact) <= 1e-12
 
 
@@ -340,6 +346,73 @@ def test_rotation_swaps_horizontal_and_vertical():
     assert abs(h1 - v1) > 1e-6
     assert abs(k1 - k2) <= 1e-10 * k1
     assert abs(h1 - v2) <= 1e-10 and abs(v1 - h2) <= 1e-10
+
+
+def _mps_values(B, O1, O2):
+    """<O1>, <O2> and the nearest-neighbour <O1 O2> of the infinite MPS with
+    real tensors B[s, l, r], from the dominant eigenvectors of its transfer
+    matrix E[(l l'), (r r')] = sum_s B[s,l,r] B[s,l',r'] (ket, bra)."""
+    def tm(O=None):
+        if O is None:
+            return np.einsum("slr,sLR->lLrR", B, B).reshape(B.shape[1] ** 2, -1)
+        return np.einsum("slr,ts,tLR->lLrR", B, O, B).reshape(B.shape[1] ** 2, -1)
+    E = tm()
+    w, vr = np.linalg.eig(E)
+    wl, vl = np.linalg.eig(E.T)
+    r, l = np.real(vr[:, np.argmax(abs(w))]), np.real(vl[:, np.argmax(abs(wl))])
+    lam, norm = np.max(abs(w)), l @ r
+    e1 = l @ tm(O1) @ r / (lam * norm)
+    e2 = l @ tm(O2) @ r / (lam * norm)
+    e12 = l @ tm(O1) @ tm(O2) @ r / (lam ** 2 * norm)
+    return e1, e2, e12
+
+
+@pytest.mark.parametrize("rows", [True, False])
+def test_uncoupled_chains_factorise_on_the_diagonals(rows):
+    """A PEPS whose vertical (or horizontal) legs are trivial is a stack of
+    independent MPS rows (columns): a diagonal pair sits on two different
+    chains, so <O1 O2> = <O1><O2>, while the bond along the chain is the
+    MPS nearest-neighbour value.  Both sides from the 1D transfer matrix."""
+    rng = np.random.default_rng(7)
+    B = rng.standard_normal((2, 2, 2)) + 0.3 * np.eye(2)[None]   # MPS gap |l2/l1| = 0.10
+    A = np.zeros((2, 2, 2, 2, 2))
+    if rows:
+        A[:, 0, :, 0, :] = B                       # A[s, u=0, l, d=0, r] = B[s, l, r]
+    else:
+        A[:, :, 0, :, 0] = B                       # A[s, u, l=0, d, r=0] = B[s, u, d]
+    X, Zp = S.pauli("x"), S.pauli("z")
+    e1, e2, e12 = _mps_values(B, X, Zp)
+    a, e = O.double_layer(A), S.trace_boundary(2)
+    # every corner has rank 1 here, so the spectrum change is 0 from the
+    # first move on: run a fixed number of moves instead
+    env, hist = O.run_ctmrg(a, e, 4, proj="svd", tol=0.0, max_moves=80)
+    op = np.kron(X, Zp)
+    along = "h" if rows else "v"
+    assert abs(O.bond_value(env, A, op, along) - e12) <= 1e-10
+    for direction in ("d", "ad"):
+        assert abs(O.bond_value(env, A, op, direction) - e1 * e2) <= 1e-10
+    assert abs(e12 - e1 * e2) > 1e-3                # the two pins are distinct
+
+
+def test_rotation_maps_the_diagonal_to_the_antidiagonal():
+    """Turning the lattice by 90 degrees (new (u,l,d,r) = old (r,u,l,d), so
+    the old right is the new up) carries the top-left / bottom-right pair to
+    a bottom-left / top-right one: rho_d(A) equals rho_ad(A_rot) with the two
+    sites exchanged, which a non-symmetric operator distinguishes."""
+    A = S.product_plus_noise_site(2, 2, 14, noise=0.6)
+    Ar = np.einsum("suldr->sruld", A)
+    X, Zp = S.pauli("x"), S.pauli("z")
+    ops = {"xz": np.kron(X, Zp), "zx": np.kron(Zp, X)}
+    vals = {}
+    for name, site in (("A", A), ("Ar", Ar)):
+        a, e = O.double_layer(site), S.trace_boundary(2)
+        env, _ = O.run_ctmrg(a, e, 8, proj="svd", tol=1e-13, max_moves=120)
+        for dr in ("d", "ad"):
+            for o, op in ops.items():
+                vals[name, dr, o] = O.bond_value(env, site, op, dr)
+    assert abs(vals["A", "d", "xz"] - vals["Ar", "ad", "zx"]) <= 1e-10
+    assert abs(vals["A", "d", "zx"] - vals["Ar", "ad", "xz"]) <= 1e-10
+    assert abs(vals["A", "d", "xz"] - vals["A", "d", "zx"]) > 1e-4
 
 
 def test_si_and_svd_agree_on_noisy_state():
