@@ -345,6 +345,22 @@ def main():
                "what": "reverse pass of one SI move incl. its recomputed forward (tape)"}
         log(f"adjoint: {vjp['ms_per_vjp']} ms per move VJP ({vjp['ratio_to_move']}x the move)")
 
+    obs = None
+    if args.prec == "f64":
+        import synth as S
+        h = S.heisenberg_bond()
+        kinds = (("bond_h", P.OBS_BOND_H), ("bond_v", P.OBS_BOND_V), ("bond_d", P.OBS_BOND_D))
+        ctx.observable(P.OBS_BOND_D, h)                      # first call: code paths warm
+        obs = {"what": "Heisenberg bond values of the final environment and the time of one "
+                       "call each (the diagonal contracts the 2x2 plaquette through its four "
+                       "enlarged corners, 2 d^2 products of N x N matrices)"}
+        for name, kind in kinds:
+            t1 = time.perf_counter()
+            val = ctx.observable(kind, h)[0]
+            obs[name] = {"value": val, "ms": round(1e3 * (time.perf_counter() - t1), 2)}
+        log("observables: " + ", ".join(f"{k} {obs[k]['value']:.8f} ({obs[k]['ms']} ms)"
+                                        for k, _ in kinds))
+
     opt = None
     if args.opt_moves > 0 and args.prec == "f64":
         import synth as S
@@ -434,6 +450,7 @@ def main():
         "roofline": roofline,
         "full_svd_same_gpu": svd,
         "adjoint": vjp,
+        "observables": obs,
         "optimisation_step": opt,
         "converged_environment": conv,
         "speedup_vs_full_svd": None if svd is None else round(value / svd["moves_per_s"], 2),

@@ -73,7 +73,11 @@ typedef enum {
   CTM_OBS_NORM = 0,    /* out[0] = kappa = Z11 Z00 / (Z10 Z01), out[1..4] = Z11,Z00,Z10,Z01 */
   CTM_OBS_ONESITE = 1, /* d > 0: op is d x d (bra, ket); d == 0: op is an impurity a_O[u,l,d,r] */
   CTM_OBS_BOND_H = 2,  /* d > 0: op is d^2 x d^2 on (site1 site2); d == 0: two impurities     */
-  CTM_OBS_BOND_V = 3   /* as BOND_H for the vertical bond (site 1 above site 2)               */
+  CTM_OBS_BOND_V = 3,  /* as BOND_H for the vertical bond (site 1 above site 2)               */
+  CTM_OBS_BOND_D = 4,  /* as BOND_H for the diagonal of a plaquette: site 1 top-left, site 2
+                          bottom-right (the extra bond of the triangular lattice drawn on the
+                          square one, triangular-lattice section)                             */
+  CTM_OBS_BOND_AD = 5  /* the other diagonal: site 1 top-right, site 2 bottom-left            */
 } ctm_obs;
 
 typedef struct {
@@ -198,7 +202,10 @@ ctm_status ctm_converge(ctm_ctx* ctx, double tol, int max_moves, int* moves_done
 
 /* Observable of the current environment (iPEPS section: operator insertion
  * into the norm network).  op_host and out_host are host arrays; see ctm_obs
- * for their meaning.  Synchronises the stream. */
+ * for their meaning.  The diagonal bonds contract the 2x2 plaquette through
+ * its four enlarged corners (2 d^2 products of N x N matrices, N = chi D^2;
+ * d <= 3) and use the move's intermediate buffers, so they run between
+ * moves.  Synchronises the stream. */
 ctm_status ctm_observable(ctm_ctx* ctx, int kind, const double* op_host, double* out_host);
 
 /* Number of doubles of the state vector: C1..C4, T1..T4, then X_0..X_3 and

@@ -38,7 +38,7 @@ PREC = {"f64": 0, "f32": 1, "bf16": 2}
 SVD_DRIVER = {"gesvd": 0, "gesdd": 1, "gesvdx": 2}
 GROWTH = {"svd": 0, "si": 1}
 SYM = {"none": 0, "c4v": 1}
-OBS_NORM, OBS_ONESITE, OBS_BOND_H, OBS_BOND_V = range(4)
+OBS_NORM, OBS_ONESITE, OBS_BOND_H, OBS_BOND_V, OBS_BOND_D, OBS_BOND_AD = range(6)
 
 
 class ctm_config(ctypes.Structure):

@@ -132,6 +132,7 @@ struct ctm_ctx {
   int* fs_info;
   int* fs_perm;              // descending order of the dense SVD's singular values
   double* sk_part = nullptr;  // partial tiles of the balanced SI applications
+  double* dot_part = nullptr; // partial sums of the plaquette dot products
   int sk_cus = kSplitMaxCus;  // CUs a balanced launch spreads over
   double* obs_y;             // [d^2][x Dl x]
   double* obs_w;             // [d^2][x Dl x]
@@ -298,6 +299,7 @@ size_t carve(ctm_ctx* c, char* base) {
   c->fs_Vs = cv.take<double>(Nm * chi);
   c->fs_info = cv.take<int>(64);
   c->fs_perm = cv.take<int>(Nm);
+  c->dot_part = cv.take<double>((size_t)kMaxDots * kDotBlocks);
   c->sk_part = c->cp == DT::F64 && gemm_si_balanced_useful(8, (int)N, (int)k, (int)N, kSplitMaxCus)
                    ? (double*)cv.take_bytes(gemm_si_scratch_bytes())
                    : nullptr;
@@ -404,8 +406,10 @@ int run_gemm(ctm_ctx* c, int cls, const GemmBatch& g, DT ta, DT tb, DT tc, doubl
 // ---------------------------------------------------------------------------
 // step 1: enlarged corners (batched over the four corners)
 // ---------------------------------------------------------------------------
-int build_corners(ctm_ctx* c) {
-  const int x = c->chi_env, Dl = c->Dl, N1 = x * Dl;
+// The environment part of the four enlarged corners (float64):
+// CT_i = C_i T_i into CT[i] and W_i = T_(i-1) CT_i into S1[i].
+int corner_stems(ctm_ctx* c, int phase) {
+  const int x = c->chi_env, Dl = c->Dl;
   double* const* C = c->C[c->cur];
   double* const* T = c->T[c->cur];
   // CT_i[a, (q, y)] = C_i[a, b] T_i[b, q, y]
@@ -415,7 +419,7 @@ int build_corners(ctm_ctx* c) {
     g1.B[i] = T[i];
     g1.C[i] = c->CT[i];
   }
-  TRY(run_gemm(c, PC_CORNER, g1, DT::F64, DT::F64, DT::F64));
+  TRY(run_gemm(c, phase, g1, DT::F64, DT::F64, DT::F64));
   // W_i[(x_in, y), (p, q)] = T_(i-1)[(x_in, p), a] CT_i[a, (q, y)]
   GemmBatch g2 = gemm_rowmajor(4, x * Dl, Dl * x, x, x, (long)Dl * x, 0);
   g2.cdiv_m = Dl;
@@ -429,15 +433,28 @@ int build_corners(ctm_ctx* c) {
     g2.B[i] = c->CT[i];
     g2.C[i] = c->S1[i];
   }
-  TRY(run_gemm(c, PC_CORNER, g2, DT::F64, DT::F64, DT::F64));
-  // Ct_i[(x_in, o1), (y, o2)] = W_i[(x_in, y), (p, q)] ap_i[(p, q), (o1, o2)]
-  GemmBatch g3 = gemm_rowmajor(4, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
+  TRY(run_gemm(c, phase, g2, DT::F64, DT::F64, DT::F64));
+  return 0;
+}
+
+// The site absorption of enlarged corners (after corner_stems):
+// Ct_i[(x_in, o1), (y, o2)] = W_i[(x_in, y), (p, q)] site_i[(p, q), (o1, o2)]
+// with site_i the corner-i permutation of the site tensor.
+GemmBatch corner_site_gemm(ctm_ctx* c, int count) {
+  const int x = c->chi_env, Dl = c->Dl, N1 = x * Dl;
+  GemmBatch g3 = gemm_rowmajor(count, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
   g3.cdiv_m = x;
   g3.cs_m1 = (long)Dl * N1;
   g3.cs_m0 = Dl;
   g3.cdiv_n = Dl;
   g3.cs_n1 = N1;
   g3.cs_n0 = 1;
+  return g3;
+}
+
+int build_corners(ctm_ctx* c) {
+  TRY(corner_stems(c, PC_CORNER));
+  GemmBatch g3 = corner_site_gemm(c, 4);
   for (int i = 0; i < 4; ++i) {
     g3.A[i] = c->S1[i];
     g3.B[i] = c->ap[i];
@@ -1352,6 +1369,52 @@ int two_site(ctm_ctx* c, bool horizontal, const double* const* s1, int n1,
   return elem_pair_dot(c->obs_y, c->obs_w, L, n1, n2, x, Dl, 1, E, c->st);
 }
 
+// Enlarged corner i (float64, N x N, after corner_stems) with the rank-4
+// site tensor xs (a-layout) in place of a; imp[1] holds its permutation.
+int corner_with(ctm_ctx* c, int i, const double* xs, double* out) {
+  const long Dl = c->Dl;
+  const long su = Dl * Dl * Dl, sl = Dl * Dl, sd = Dl, sr = 1;
+  const long perm[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
+  TRY(elem_permute4(xs, c->imp[1], DT::F64, (int)Dl, perm[i][0], perm[i][1], perm[i][2], perm[i][3],
+                    c->st));
+  GemmBatch g = corner_site_gemm(c, 1);
+  g.A[0] = c->S1[i];
+  g.B[0] = c->imp[1];
+  g.C[0] = out;
+  return g64(c, g);
+}
+
+// Diagonal pair on the 2x2 plaquette Tr(Ct1 Ct2 Ct3 Ct4): site 1 in the
+// corner o (0: top-left, 1: top-right for the anti-diagonal) and site 2 in
+// corner o + 2, the plain double layer in the other two.
+// E[i * n2 + j] = Tr(Ct_o(s1[i]) Ct_o+1 Ct_o+2(s2[j]) Ct_o+3), as
+// <Ct_o(s1[i]), Z_j^T> with Z_j = Ct_o+1 Ct_o+2(s2[j]) Ct_o+3 stored
+// transposed (n2 <= kMaxDots of them in Pl, Prt, Zc[0]).
+int diag_pair(ctm_ctx* c, bool anti, const double* const* s1, int n1, const double* const* s2,
+              int n2, double* E) {
+  const int x = c->chi_env, Dl = c->Dl;
+  const long N = (long)x * Dl;
+  if (n1 < 1 || n2 < 1 || n2 > kMaxDots) return fail(c, CTM_E_SHAPE, "diagonal pair: bad count");
+  const int o = anti ? 1 : 0, i1 = (o + 1) % 4, i2 = (o + 2) % 4, i3 = (o + 3) % 4;
+  TRY(corner_stems(c, PC_MISC));
+  TRY(corner_with(c, i1, c->a, c->S2[i1]));
+  TRY(corner_with(c, i3, c->a, c->S2[i3]));
+  double* Z[kMaxDots] = {c->Pl[0], c->Pl[1], c->Pl[2], c->Pl[3], c->Prt[0],
+                         c->Prt[1], c->Prt[2], c->Prt[3], c->Zc[0]};
+  for (int j = 0; j < n2; ++j) {
+    TRY(corner_with(c, i2, s2[j], c->S2[o]));
+    TRY(g64(c, gb1((int)N, (int)N, (int)N, c->S2[i1], N, 0, c->S2[o], N, c->S2[i2], N)));
+    GemmBatch g = gb1((int)N, (int)N, (int)N, c->S2[i2], N, 0, c->S2[i3], N, Z[j], 0);
+    set_map(g, 1 << 30, 0, 1, 1 << 30, 0, N);   // Z_j^T
+    TRY(g64(c, g));
+  }
+  for (int i = 0; i < n1; ++i) {
+    TRY(corner_with(c, o, s1[i], c->S2[o]));
+    TRY(elem_dots(c->S2[o], Z, n2, N * N, c->dot_part, E + (long)i * n2, c->st));
+  }
+  return 0;
+}
+
 int observable(ctm_ctx* c, int kind, const double* op_host, double* out_host) {
   const int Dl = c->Dl, d = c->d;
   const size_t Dl4 = (size_t)Dl * Dl * Dl * Dl;
@@ -1384,6 +1447,40 @@ int observable(ctm_ctx* c, int kind, const double* op_host, double* out_host) {
     CTM_HIP_TRY(hipMemcpyAsync(host, sc, 3 * 8, hipMemcpyDeviceToHost, c->st));
     CTM_HIP_TRY(hipStreamSynchronize(c->st));
     out_host[0] = host[2];
+    return 0;
+  }
+  if (kind == CTM_OBS_BOND_D || kind == CTM_OBS_BOND_AD) {
+    const bool anti = kind == CTM_OBS_BOND_AD;
+    if (d == 0) {
+      // two impurities (site 1 then site 2) against the plain plaquette
+      CTM_HIP_TRY(hipMemcpy(c->imps[0], op_host, Dl4 * 8, hipMemcpyHostToDevice));
+      CTM_HIP_TRY(hipMemcpy(c->imps[1], op_host + Dl4, Dl4 * 8, hipMemcpyHostToDevice));
+      const double* a1[1] = {c->imps[0]};
+      const double* a2[1] = {c->imps[1]};
+      TRY(diag_pair(c, anti, a1, 1, a2, 1, sc));
+      const double* b1[1] = {c->a};
+      TRY(diag_pair(c, anti, b1, 1, b1, 1, sc + 1));
+      TRY(elem_ratio(sc, sc + 1, sc + 2, c->st));
+      CTM_HIP_TRY(hipMemcpyAsync(host, sc, 3 * 8, hipMemcpyDeviceToHost, c->st));
+      CTM_HIP_TRY(hipStreamSynchronize(c->st));
+      out_host[0] = host[2];
+      return 0;
+    }
+    const int d2 = d * d;
+    if (d2 > kMaxDots) return fail(c, CTM_E_SHAPE, "diagonal bond observables support d <= 3");
+    std::vector<const double*> so(d2);
+    for (int st = 0; st < d2; ++st) {
+      double* p = c->imps[0] + st * Dl4;
+      TRY(elem_double_layer(c->A_site, nullptr, p, d, c->D, c->st, st / d, st % d));
+      so[st] = p;
+    }
+    double* E = c->scal + 64;
+    TRY(diag_pair(c, anti, so.data(), d2, so.data(), d2, E));
+    CTM_HIP_TRY(hipMemcpy(c->obs_op, op_host, (size_t)d2 * d2 * 8, hipMemcpyHostToDevice));
+    TRY(elem_bond_value(E, c->obs_op, d, sc, c->st));
+    CTM_HIP_TRY(hipMemcpyAsync(host, sc, 8, hipMemcpyDeviceToHost, c->st));
+    CTM_HIP_TRY(hipStreamSynchronize(c->st));
+    out_host[0] = host[0];
     return 0;
   }
   if (kind != CTM_OBS_BOND_H && kind != CTM_OBS_BOND_V)

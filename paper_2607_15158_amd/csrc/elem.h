@@ -54,6 +54,12 @@ int elem_pair_dot(const double* X, const double* Y, long stride, int ni, int nj,
                   int rev, double* out, hipStream_t s);
 int elem_kappa(const double* z, double* out, hipStream_t s);
 int elem_bond_value(const double* E, const double* op, int d, double* out, hipStream_t s);
+// out[j] = <X, Y_j> over n doubles for ny <= kMaxDots vectors, in a fixed
+// summation order; part holds kDotBlocks * ny doubles of partial sums.
+constexpr int kMaxDots = 9;
+constexpr int kDotBlocks = 1024;
+int elem_dots(const double* X, const double* const* Y, int ny, long n, double* part,
+              double* out, hipStream_t s);
 int elem_ratio(const double* a, const double* b, double* out, hipStream_t s);
 int elem_permute4(const double* src, void* dst, DT t, int n, long s0, long s1, long s2, long s3,
                   hipStream_t s);

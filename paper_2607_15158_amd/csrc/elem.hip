@@ -414,6 +414,38 @@ __global__ void k_pair_dot(const double* X, const double* Y, long stride, int nj
   if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
+// Partial sums of <X, Y_j> for up to kMaxDots vectors Y_j of n doubles: each
+// block writes one partial per j; k_dots_final adds them in block order.
+struct DotPtrs {
+  const double* y[kMaxDots];
+};
+
+__global__ __launch_bounds__(256) void k_dots_part(const double* X, DotPtrs Y, int ny, long n,
+                                                   double* part) {
+  __shared__ double sh[4];
+  double acc[kMaxDots];
+#pragma unroll
+  for (int j = 0; j < kMaxDots; ++j) acc[j] = 0.0;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+    const double xv = X[e];
+#pragma unroll
+    for (int j = 0; j < kMaxDots; ++j)
+      if (j < ny) acc[j] += xv * Y.y[j][e];
+  }
+  for (int j = 0; j < ny; ++j) {
+    const double t = block_sum(acc[j], sh);
+    if (threadIdx.x == 0) part[(long)j * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dots_final(const double* part, int nb, double* out) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[(long)blockIdx.x * nb + b];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
 // vals = [Z11, Z00, Z10, Z01] -> out = Z11 Z00 / (Z10 Z01)
 __global__ void k_kappa(const double* z, double* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = z[0] * z[1] / (z[2] * z[3]);
@@ -510,6 +542,18 @@ __global__ void k_copy_cols(const double* X, int n, long ld, int keep, double* P
 int elem_pair_dot(const double* X, const double* Y, long stride, int ni, int nj, int x, int m,
                   int rev, double* out, hipStream_t s) {
   k_pair_dot<<<ni * nj, 256, 0, s>>>(X, Y, stride, nj, x, m, rev, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_dots(const double* X, const double* const* Y, int ny, long n, double* part,
+              double* out, hipStream_t s) {
+  if (ny < 1 || ny > kMaxDots || n < 0) return 1;
+  DotPtrs p{};
+  for (int j = 0; j < ny; ++j) p.y[j] = Y[j];
+  k_dots_part<<<kDotBlocks, 256, 0, s>>>(X, p, ny, n, part);
+  CTM_HIP_TRY(hipGetLastError());
+  k_dots_final<<<ny, 256, 0, s>>>(part, kDotBlocks, out);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -224,6 +224,8 @@ def test_classical_ising_closed_forms_on_gpu(proj):
     two = np.concatenate([asig.ravel(), asig.ravel()])
     for kind in (P.OBS_BOND_H, P.OBS_BOND_V):
         assert abs(ctx.observable(kind, two)[0] - gold(beta, "nn_correlation")) <= 1e-9
+    for kind in (P.OBS_BOND_D, P.OBS_BOND_AD):
+        assert abs(ctx.observable(kind, two)[0] - gold(beta, "diag_correlation")) <= 1e-9
     if proj == "si":
         assert res["converged"]
 
@@ -241,6 +243,9 @@ def test_ising_peps_bond_correlation_on_gpu():
     for kind in (P.OBS_BOND_H, P.OBS_BOND_V):
         zz = ctx.observable(kind, np.kron(Z, Z))[0]
         assert abs(zz - gold(beta, "nn_correlation")) <= 2e-11
+    for kind in (P.OBS_BOND_D, P.OBS_BOND_AD):
+        zz = ctx.observable(kind, np.kron(Z, Z))[0]
+        assert abs(zz - gold(beta, "diag_correlation")) <= 1e-10
 
 
 @pytest.mark.parametrize("proj", ["si", "svd"])
@@ -257,7 +262,7 @@ def test_product_state_exact_on_gpu(proj):
     p = phi / np.linalg.norm(phi)
     for op in (S.heisenberg_bond(), np.kron(S.pauli("x"), S.pauli("z"))):
         exact = np.kron(p, p) @ op @ np.kron(p, p)
-        for kind in (P.OBS_BOND_H, P.OBS_BOND_V):
+        for kind in (P.OBS_BOND_H, P.OBS_BOND_V, P.OBS_BOND_D, P.OBS_BOND_AD):
             assert abs(ctx.observable(kind, op)[0] - exact) <= 1e-12
 
 
@@ -276,6 +281,54 @@ def test_noisy_state_observables_match_oracle():
     Zs = S.pauli("z")
     assert abs(ctx.observable(P.OBS_ONESITE, Zs)[0] -
                O.onesite_value(env, a, O.double_layer_op(A, Zs))) <= 1e-10
+    assert abs(ctx.observable(P.OBS_BOND_D, h)[0] - O.bond_value(env, A, h, "d")) <= 1e-10
+    assert abs(ctx.observable(P.OBS_BOND_AD, h)[0] - O.bond_value(env, A, h, "ad")) <= 1e-10
+
+
+@pytest.mark.parametrize("d,D,chi", [(2, 2, 7), (3, 2, 5), (2, 3, 30)])
+def test_diagonal_bonds_match_oracle_on_a_given_environment(d, D, chi):
+    """Diagonal and anti-diagonal two-site values on the same seeded random
+    environment as the oracle (set through the state vector, no moves), for
+    operators that tell the two sites and ket from bra apart: every entry of
+    the plaquette's open-leg tensor enters.  chi = 30, D = 3 gives N = 270:
+    several GEMM tiles with a ragged edge."""
+    rng = np.random.default_rng(40 + d + chi)
+    A = rng.standard_normal((d, D, D, D, D))
+    Dl = D * D
+    cfg = P.Config(d=d, D=D, chi=chi, p=2)
+    C = [S.gaussian_block(chi, chi, 60 + i) for i in range(4)]
+    T = [S.gaussian_block(chi * Dl, chi, 70 + i).reshape(chi, Dl, chi) for i in range(4)]
+    X = np.stack([S.gaussian_block(cfg.N, cfg.k, 80 + b) for b in range(4)])
+    ctx = P.Ctm(cfg, dev(A))
+    ctx.set_state(ctx.pack_state(C, T, X, X))
+    env = O.Env([c.copy() for c in C], [t.copy() for t in T])
+    ops = [rng.standard_normal((d * d, d * d)) for _ in range(2)]
+    for op in ops:
+        for kind, direction in ((P.OBS_BOND_D, "d"), (P.OBS_BOND_AD, "ad")):
+            got = ctx.observable(kind, op)[0]
+            ref = O.bond_value(env, A, op, direction)
+            assert abs(got - ref) <= 1e-11 * max(1.0, abs(ref)), (kind, got, ref)
+
+
+def test_classical_diagonal_impurities_match_oracle():
+    """d = 0: two impurity tensors on the diagonal pair of a given network
+    and a seeded random environment, against the oracle's plaquette ratio."""
+    rng = np.random.default_rng(9)
+    D, chi = 2, 9
+    a = np.abs(rng.standard_normal((D, D, D, D))) + 0.5
+    a1, a2 = rng.standard_normal((D, D, D, D)), rng.standard_normal((D, D, D, D))
+    cfg = P.Config(d=0, D=D, chi=chi, p=2)
+    ctx = P.Ctm(cfg, dev(a), boundary=dev(S.ising_boundary(0.4)))
+    C = [S.gaussian_block(chi, chi, 61 + i) for i in range(4)]
+    T = [S.gaussian_block(chi * D, chi, 71 + i).reshape(chi, D, chi) for i in range(4)]
+    X = np.stack([S.gaussian_block(cfg.N, cfg.k, 81 + b) for b in range(4)])
+    ctx.set_state(ctx.pack_state(C, T, X, X))
+    env = O.Env([c.copy() for c in C], [t.copy() for t in T])
+    two = np.concatenate([a1.ravel(), a2.ravel()])
+    for kind, direction in ((P.OBS_BOND_D, "d"), (P.OBS_BOND_AD, "ad")):
+        got = ctx.observable(kind, two)[0]
+        ref = O.classical_bond_value(env, a, a1, a2, direction)
+        assert abs(got - ref) <= 1e-11 * max(1.0, abs(ref)), (kind, got, ref)
 
 
 @pytest.mark.parametrize("prec,pinv", [("f32", 1e-6), ("bf16", 1e-2)])
