@@ -203,27 +203,59 @@ def _two_site_v_torch(C, T, x1, x2):
     return torch.einsum("ABnxc,EFcxn->ABEF", p3, q3)
 
 
-def energy_torch(C, T, A, op):
-    """<op>_H + <op>_V of a nearest-neighbour operator op[(t1 t2), (s1 s2)]
-    (bra, ket) from the two-site reduced density matrices (iPEPS section,
-    observables), as :func:`oracle.ctmrg.bond_value` for both bonds."""
+_CORNER_SPECS = ("tla,ab,bug,...uldr->...tdgr", "bug,gh,hre,...uldr->...bled",
+                 "hre,ez,zdn,...uldr->...hunl", "zdn,nt,tla,...uldr->...zrau")
+
+
+def _two_site_diag_torch(C, T, ao, anti: bool):
+    """Diagonal pair of the 2x2 plaquette Tr(Ct1 Ct2 Ct3 Ct4), as
+    :func:`oracle.ctmrg._two_site_diag`: site 1 top-left and site 2
+    bottom-right (``anti``: top-right and bottom-left); the two other corners
+    hold the closed double layer."""
+    C1, C2, C3, C4 = C
+    T1, T2, T3, T4 = T
+    ops = ((T4, C1, T1), (T1, C2, T2), (T2, C3, T3), (T3, C4, T4))
+    a = torch.einsum("ss...->...", ao)
+    o = 1 if anti else 0
+    Ct = []
+    for i in range(4):
+        x = ao if i in (o, o + 2) else a
+        c = torch.einsum(_CORNER_SPECS[i], *ops[i], x)
+        N = C1.shape[0] * x.shape[-1]
+        Ct.append(c.reshape(c.shape[:-4] + (N, N)))
+    c0, c1, c2, c3 = (Ct[(o + j) % 4] for j in range(4))
+    return torch.einsum("ABij,jk,EFkl,li->ABEF", c0, c1, c2, c3)
+
+
+def energy_torch(C, T, A, op, bonds: str = "hv"):
+    """Sum over ``bonds`` (``h``, ``v``, ``d`` for the diagonal, ``a`` for the
+    anti-diagonal) of <op> with op[(t1 t2), (s1 s2)] (bra, ket), from the
+    two-site reduced density matrices (iPEPS section, observables; the
+    diagonal bonds of the triangular-lattice section), as
+    :func:`oracle.ctmrg.bond_value` for each bond."""
     d = A.shape[0]
     ao = _double_layer_open_torch(A)
+    pairs = {"h": lambda: _two_site_h_torch(C, T, ao, ao),
+             "v": lambda: _two_site_v_torch(C, T, ao, ao),
+             "d": lambda: _two_site_diag_torch(C, T, ao, False),
+             "a": lambda: _two_site_diag_torch(C, T, ao, True)}
     out = 0.0
-    for E in (_two_site_h_torch(C, T, ao, ao), _two_site_v_torch(C, T, ao, ao)):
+    for bond in bonds:
+        E = pairs[bond]()
         rho = E.permute(0, 2, 1, 3).reshape(d * d, d * d)
         rho = rho / torch.trace(rho)
         out = out + torch.trace(op @ rho)
     return out
 
 
-def energy_vjp(C, T, A, op):
-    """(e, C_bar, T_bar, A_bar) for e = <op>_H + <op>_V at environment (C, T)."""
+def energy_vjp(C, T, A, op, bonds: str = "hv"):
+    """(e, C_bar, T_bar, A_bar) for e = the sum of <op> over ``bonds`` (see
+    :func:`energy_torch`) at environment (C, T)."""
     leaf = lambda v: torch.tensor(np.asarray(v), dtype=_f64, requires_grad=True)  # noqa: E731
     Cl = [leaf(c) for c in C]
     Tl = [leaf(t) for t in T]
     Al = leaf(A)
-    e = energy_torch(Cl, Tl, Al, torch.as_tensor(np.asarray(op), dtype=_f64))
+    e = energy_torch(Cl, Tl, Al, torch.as_tensor(np.asarray(op), dtype=_f64), bonds)
     g = torch.autograd.grad(e, Cl + Tl + [Al])
     return float(e.detach()), [x.numpy() for x in g[:4]], [x.numpy() for x in g[4:8]], g[8].numpy()
 

@@ -100,19 +100,24 @@ def test_planted_detached_pinv_is_caught(monkeypatch):
     assert abs(fd - an) > 1e-3 * abs(fd)
 
 
-def test_energy_gradient_matches_central_differences_of_bond_values():
+@pytest.mark.parametrize("bonds", ["hv", "da", "hvd"])
+def test_energy_gradient_matches_central_differences_of_bond_values(bonds):
     """The torch energy equals the NumPy bond values, and its autograd
     gradient matches central differences of oracle.ctmrg.bond_value for the
-    corners, the edges and the site tensor."""
+    corners, the edges and the site tensor (nearest-neighbour bonds, the two
+    diagonals, and the triangular-lattice sum h + v + d).  The operator is
+    not symmetric under exchange of the two sites, so a swapped site order
+    in the diagonal reference would show."""
     A, C, T, _, _ = case(D=2, chi=4)
-    h = S.heisenberg_bond()
+    h = S.heisenberg_bond() + 0.3 * np.kron(S.pauli("x"), S.pauli("z"))
     env = O.Env(C, T)
+    names = {"h": "h", "v": "v", "d": "d", "a": "ad"}
 
     def e_np(C_, T_, A_):
         en = O.Env(C_, T_)
-        return O.bond_value(en, A_, h, "h") + O.bond_value(en, A_, h, "v")
+        return sum(O.bond_value(en, A_, h, names[b]) for b in bonds)
 
-    e, gC, gT, gA = J.energy_vjp(C, T, A, h)
+    e, gC, gT, gA = J.energy_vjp(C, T, A, h, bonds)
     assert abs(e - e_np(env.C, env.T, A)) <= 1e-12
     rng = np.random.default_rng(4)
     for group in ("C", "T", "A"):
