@@ -344,6 +344,17 @@ def main():
                "ratio_to_move": round(1e3 * float(np.median(tv)) / ms_step, 2),
                "what": "reverse pass of one SI move incl. its recomputed forward (tape)"}
         log(f"adjoint: {vjp['ms_per_vjp']} ms per move VJP ({vjp['ratio_to_move']}x the move)")
+        import synth as S
+        h = S.heisenberg_bond()
+        vjp["energy_vjp_ms"] = {}
+        for bonds in ("hv", "hvd"):
+            ctx.energy_vjp(st, h, bonds=bonds)                  # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx.energy_vjp(st, h, bonds=bonds)
+            vjp["energy_vjp_ms"][bonds] = round(1e3 * (time.perf_counter() - t1), 2)
+        log(f"energy gradient: {vjp['energy_vjp_ms']} ms (nearest-neighbour bonds; with the "
+            f"diagonal, the triangular lattice)")
 
     obs = None
     if args.prec == "f64":

@@ -378,6 +378,20 @@ ctm_status ctm_fixed_point_vjp(ctm_ctx* ctx, const double* state_star, const dou
 ctm_status ctm_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_host, double* e_out,
                           double* state_bar, double* site_bar, void* ws, size_t ws_bytes);
 
+/* The same for any set of bonds: e = sum over the bonds in the mask `bonds`
+ * (CTM_BOND_H = 1, CTM_BOND_V = 2, CTM_BOND_D = 4, CTM_BOND_AD = 8; the
+ * bonds of CTM_OBS_BOND_H/V/D/AD) of <op>; H + V + D is the energy of the
+ * triangular lattice drawn on the square one (triangular-lattice section).
+ * The diagonal pair is the 2x2 plaquette through its four enlarged corners,
+ * differentiated by hand (2 d^2 products of N x N matrices forward, 4 d^2 in
+ * reverse); the anti-diagonal is the diagonal of the turned network.
+ * ctm_energy_vjp is this call with bonds = 3.  CTM_E_ARG for an empty or
+ * unknown mask. */
+enum { CTM_BOND_H = 1, CTM_BOND_V = 2, CTM_BOND_D = 4, CTM_BOND_AD = 8 };
+ctm_status ctm_bond_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_host, int bonds,
+                               double* e_out, double* state_bar, double* site_bar, void* ws,
+                               size_t ws_bytes);
+
 /* ---------------------------------------------------------------------------
  * Building blocks of a move, exposed for testing and for callers composing
  * their own loops.  All operate on caller device memory on `stream`.

@@ -114,6 +114,8 @@ _sigs = {
     "ctm_vjp_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ctm_config), ctypes.POINTER(ctypes.c_size_t)]),
     "ctm_move_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t]),
     "ctm_energy_vjp": (ctypes.c_int, [_vp, _vp, _dp, _dp, _vp, _vp, _vp, ctypes.c_size_t]),
+    "ctm_bond_energy_vjp": (ctypes.c_int, [_vp, _vp, _dp, ctypes.c_int, _dp, _vp, _vp, _vp,
+                                           ctypes.c_size_t]),
     "ctm_fixed_point_vjp": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _vp, _vp,
                                            _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int),
                                            _dp]),
@@ -341,9 +343,10 @@ class Ctm:
                                         ctypes.byref(rel)), self._h)
         return x_bar, site_bar, it.value, rel.value
 
-    def energy_vjp(self, state, op, site_bar=None):
-        """e = <op>_H + <op>_V at the environment of ``state`` (device tensor,
-        state layout) and its gradient: returns (e, state_bar, site_bar)."""
+    def energy_vjp(self, state, op, site_bar=None, bonds: str = "hv"):
+        """e = sum of <op> over ``bonds`` (``h``, ``v``, ``d`` diagonal, ``a``
+        anti-diagonal) at the environment of ``state`` (device tensor, state
+        layout) and its gradient: returns (e, state_bar, site_bar)."""
         import torch
         ws = self._ensure_vjp_ws()
         dev = self._site.device
@@ -353,19 +356,20 @@ class Ctm:
         bar = torch.empty_like(st)
         if site_bar is None:
             site_bar = torch.zeros_like(self._site)
-        _check(_lib.ctm_energy_vjp(self._h, st.data_ptr(), opb.ctypes.data_as(_dp), ctypes.byref(e),
-                                   bar.data_ptr(), site_bar.data_ptr(), ws.data_ptr(), ws.numel()),
-               self._h)
+        _check(_lib.ctm_bond_energy_vjp(self._h, st.data_ptr(), opb.ctypes.data_as(_dp),
+                                        bond_mask(bonds), ctypes.byref(e), bar.data_ptr(),
+                                        site_bar.data_ptr(), ws.data_ptr(), ws.numel()), self._h)
         return e.value, bar, site_bar
 
-    def energy_gradient(self, op, tol: float = 1e-12, max_iter: int = 400):
-        """Gradient of the converged energy e = <op>_H + <op>_V with respect to
-        the site tensor at the context's current (converged) environment: the
-        direct term plus the fixed-point term (eq. implicit).  Returns
-        (e, dE/dA as a device tensor, passes of the fixed-point series)."""
+    def energy_gradient(self, op, tol: float = 1e-12, max_iter: int = 400, bonds: str = "hv"):
+        """Gradient of the converged energy e (the sum of <op> over ``bonds``,
+        as in :meth:`energy_vjp`) with respect to the site tensor at the
+        context's current (converged) environment: the direct term plus the
+        fixed-point term (eq. implicit).  Returns (e, dE/dA as a device
+        tensor, passes of the fixed-point series)."""
         import torch
         star = torch.from_numpy(self.get_state()).to(self._site.device)
-        e, g, site_bar = self.energy_vjp(star, op)
+        e, g, site_bar = self.energy_vjp(star, op, bonds=bonds)
         _, site_bar, passes, _ = self.fixed_point_vjp(star, g, tol, max_iter, site_bar)
         return e, site_bar, passes
 
@@ -422,8 +426,9 @@ class Ctm:
 
 
 def converged_energy(A, cfg: Config, op, X0, Yt0, tol: float = 1e-12, max_moves: int = 400,
-                     fp_tol: float = 1e-12, fp_max_iter: int = 400):
-    """Energy <op>_H + <op>_V of the converged environment of the site tensor
+                     fp_tol: float = 1e-12, fp_max_iter: int = 400, bonds: str = "hv"):
+    """Energy (the sum of <op> over ``bonds``; ``hvd`` for the triangular
+    lattice) of the converged environment of the site tensor
     ``A`` (a float64 device tensor with ``requires_grad``), differentiable:
     the backward pass is the energy's gradient plus the fixed-point term of
     eq. implicit, computed by the library (ctm_energy_vjp,
@@ -440,7 +445,7 @@ def converged_energy(A, cfg: Config, op, X0, Yt0, tol: float = 1e-12, max_moves:
             if not r["converged"]:
                 raise CtmError(CTM_E_NOT_CONVERGED, f"no convergence in {max_moves} moves "
                                                     f"(delta {r['delta']:.2e})")
-            e, grad, _ = c.energy_gradient(op, fp_tol, fp_max_iter)
+            e, grad, _ = c.energy_gradient(op, fp_tol, fp_max_iter, bonds)
             ctx.save_for_backward(grad)
             c.close()
             return torch.tensor(e, dtype=torch.float64, device=site.device)
@@ -453,8 +458,8 @@ def converged_energy(A, cfg: Config, op, X0, Yt0, tol: float = 1e-12, max_moves:
     return _ConvergedEnergy.apply(A)
 
 
-def unrolled_energy(A, cfg: Config, op, state0, moves: int):
-    """Energy <op>_H + <op>_V after ``moves`` SI moves from ``state0`` (a
+def unrolled_energy(A, cfg: Config, op, state0, moves: int, bonds: str = "hv"):
+    """Energy (the sum of <op> over ``bonds``) after ``moves`` SI moves from ``state0`` (a
     float64 device tensor in the state layout, chi_env == chi), differentiable
     with respect to the site tensor ``A`` by unrolling: the forward pass keeps
     the state at every move boundary on the device (checkpoints), the
@@ -472,7 +477,7 @@ def unrolled_energy(A, cfg: Config, op, state0, moves: int):
             for _ in range(moves):
                 c.move()
                 states.append(c.get_state_device())
-            e, bar, site_bar = c.energy_vjp(states[-1], op)
+            e, bar, site_bar = c.energy_vjp(states[-1], op, bonds=bonds)
             for st in reversed(states[:-1]):
                 bar, _, site_bar = c.move_vjp(st, bar, want_out=False, site_bar=site_bar)
             ctx.save_for_backward(site_bar)
@@ -485,6 +490,19 @@ def unrolled_energy(A, cfg: Config, op, state0, moves: int):
             return g * grad
 
     return _UnrolledEnergy.apply(A)
+
+
+BOND_BITS = {"h": 1, "v": 2, "d": 4, "a": 8}
+
+
+def bond_mask(bonds: str) -> int:
+    """Mask of the bonds named by the letters h, v, d (diagonal), a (anti-diagonal)."""
+    if not bonds or any(c not in BOND_BITS for c in bonds):
+        raise ValueError(f"bonds must be letters of 'hvda', got {bonds!r}")
+    m = 0
+    for c in bonds:
+        m |= BOND_BITS[c]
+    return m
 
 
 def _ptr_array(ts):

@@ -1473,6 +1473,11 @@ struct EBufs {
   double *Y3b, *W3b, *T3Tb, *Y1b, *R1b, *leftb, *L0b, *W1pb, *W1b, *rightb, *R0b;
   double *Ta, *Tb, *Tc, *St;
   double *Ar, *Abr, *mopen;
+  // diagonal pair (plaquette): stacks of n N x N matrices, then N x N scratch
+  double *pCt0, *pCt2, *pY, *pZt, *pCt0b;
+  double *pCt1, *pCt3, *pCt1b, *pCt3b, *pH, *pCt2b, *pP, *pRb;
+  double *pW[4], *pWb[4], *pCT[4], *pCTb, *pCTt, *pTt;
+  double *pSite, *pSiteT, *pSiteB, *pA, *pAb, *pDots;
 };
 
 size_t ecarve(const Dims& m, EBufs* b, char* base, std::vector<std::pair<uintptr_t, uintptr_t>>* reg) {
@@ -1526,6 +1531,23 @@ size_t ecarve(const Dims& m, EBufs* b, char* base, std::vector<std::pair<uintptr
   b->Ar = cv.take(m.d * D4);
   b->Abr = cv.take(m.d * D4);
   b->mopen = cv.take(D4 * D4);
+  b->pCt0 = cv.take(n * NN);
+  b->pCt2 = cv.take(n * NN);
+  b->pY = cv.take(n * NN);
+  b->pZt = cv.take(n * NN);
+  b->pCt0b = cv.take(n * NN);
+  for (double** q : {&b->pCt1, &b->pCt3, &b->pCt1b, &b->pCt3b, &b->pH, &b->pCt2b, &b->pP, &b->pRb})
+    *q = cv.take(NN);
+  for (int i = 0; i < 4; ++i) {
+    b->pW[i] = cv.take(NN);
+    b->pWb[i] = cv.take(NN);
+    b->pCT[i] = cv.take(L);
+  }
+  b->pCTb = cv.take(L);
+  b->pCTt = cv.take(L);
+  b->pTt = cv.take(L);
+  for (double** q : {&b->pSite, &b->pSiteT, &b->pSiteB, &b->pA, &b->pAb}) *q = cv.take(Dl4);
+  b->pDots = cv.take((size_t)kMaxDots * kDotBlocks);
   return cv.off + 256;
 }
 
@@ -1796,8 +1818,165 @@ ctm_status ctm_fixed_point_vjp(ctm_ctx* ctx, const double* state_star, const dou
 
 namespace {
 
-int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, double* e_out,
-                    double* state_bar, double* site_bar, void* ws, size_t ws_bytes) {
+// ---------------------------------------------------------------------------
+// Diagonal pair of the 2x2 plaquette (site 1 in corner 0, site 2 in corner 2):
+// E[i, j] = Tr(Ct0(xs_i) Ct1 Ct2(xs_j) Ct3) with Ct_k = W_k site_k,
+// W_k = T_(k-1) (C_k T_k), and its reverse pass.  The anti-diagonal is the
+// diagonal of the network turned by 90 degrees (slots shifted by one, site
+// legs rotated), as the vertical bond is the turned horizontal one.
+// ---------------------------------------------------------------------------
+const long kPerm[4][4] = {{2, 3, 1, 0}, {3, 0, 2, 1}, {0, 1, 3, 2}, {1, 2, 0, 3}};
+// site_k[i0, i1, i2, i3] = a[sum_j i_j * Dl^kPerm[k][j]]: the a-leg strides
+// (as powers of Dl: u = 3, l = 2, d = 1, r = 0) of the four site-tensor
+// legs in the corner-k absorption.
+
+long dl_pow(long Dl, int e) {
+  long v = 1;
+  for (int i = 0; i < e; ++i) v *= Dl;
+  return v;
+}
+
+int pq_site(Run& r, const Dims& m, int k, const double* a_layout, double* out) {
+  const long Dl = m.Dl;
+  return gather(r, a_layout, out, (int)Dl, (int)Dl, (int)Dl, (int)Dl, dl_pow(Dl, kPerm[k][0]),
+                dl_pow(Dl, kPerm[k][1]), dl_pow(Dl, kPerm[k][2]), dl_pow(Dl, kPerm[k][3]));
+}
+
+// out (N x N) = enlarged corner k with the site tensor xs (a-layout).
+int pq_corner(Run& r, const Dims& m, EBufs& b, int k, const double* xs, double* out) {
+  const int x = m.x, Dl = m.Dl;
+  const long N = m.N;
+  VTRY(pq_site(r, m, k, xs, b.pSite));
+  GemmBatch g = one(x * x, Dl * Dl, Dl * Dl, b.pW[k], (long)Dl * Dl, 0, b.pSite, (long)Dl * Dl, out, 0);
+  g.cdiv_m = x;
+  g.cs_m1 = (long)Dl * N;
+  g.cs_m0 = Dl;
+  g.cdiv_n = Dl;
+  g.cs_n1 = N;
+  g.cs_n0 = 1;
+  return gemm(r, g);
+}
+
+void transposed_out(GemmBatch& g, long N) {
+  g.cdiv_m = 1 << 30;
+  g.cs_m1 = 0;
+  g.cs_m0 = 1;
+  g.cdiv_n = 1 << 30;
+  g.cs_n1 = 0;
+  g.cs_n0 = N;
+}
+
+// Forward: fills b.E (n x n) from the open layers b.xs; keeps the tape.
+int pq_fwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const double* const* T) {
+  const int x = m.x, Dl = m.Dl, n = b.n;
+  const long N = m.N, NN = N * N, Dl4 = (long)Dl * Dl * Dl * Dl;
+  for (int k = 0; k < 4; ++k) {
+    VTRY(gemm(r, one(x, Dl * x, x, C[k], x, 0, T[k], (long)Dl * x, b.pCT[k], (long)Dl * x)));
+    GemmBatch g = one(x * Dl, Dl * x, x, T[(k + 3) % 4], x, 0, b.pCT[k], (long)Dl * x, b.pW[k], 0);
+    g.cdiv_m = Dl;
+    g.cs_m1 = (long)x * Dl * Dl;
+    g.cs_m0 = Dl;
+    g.cdiv_n = x;
+    g.cs_n1 = 1;
+    g.cs_n0 = (long)Dl * Dl;
+    VTRY(gemm(r, g));
+  }
+  // the closed double layer a = sum_s xs[(s, s)]
+  VTRY(fill(r, b.pA, Dl4, 0.0));
+  for (int s = 0; s < m.d; ++s)
+    VTRY(gather(r, b.xs[s * m.d + s], b.pA, Dl, Dl, Dl, Dl, (long)Dl * Dl * Dl, (long)Dl * Dl, Dl, 1,
+                true));
+  VTRY(pq_corner(r, m, b, 1, b.pA, b.pCt1));
+  VTRY(pq_corner(r, m, b, 3, b.pA, b.pCt3));
+  const double* zt[kMaxDots];
+  for (int j = 0; j < n; ++j) {
+    double* c2 = b.pCt2 + j * NN;
+    double* y = b.pY + j * NN;
+    VTRY(pq_corner(r, m, b, 2, b.xs[j], c2));
+    VTRY(gemm(r, one((int)N, (int)N, (int)N, b.pCt1, N, 0, c2, N, y, N)));
+    GemmBatch g = one((int)N, (int)N, (int)N, y, N, 0, b.pCt3, N, b.pZt + j * NN, 0);
+    transposed_out(g, N);
+    VTRY(gemm(r, g));
+    zt[j] = b.pZt + j * NN;
+  }
+  for (int i = 0; i < n; ++i) {
+    double* c0 = b.pCt0 + i * NN;
+    VTRY(pq_corner(r, m, b, 0, b.xs[i], c0));
+    const int rc = elem_dots(c0, zt, n, NN, b.pDots, b.E + i * n, r.st);
+    if (rc) return vjp_fail(r.c, rc == 1 ? CTM_E_ARG : rc, thread_error());
+  }
+  return 0;
+}
+
+// Reverse pass of the site absorption of corner k with cotangent Ctb of the
+// corner: pWb[k] += P site^T and xbar += (W^T P) in a-layout, with P the
+// cotangent regrouped as [(x_in, y), (o1, o2)].
+int pq_absorb_bwd(Run& r, const Dims& m, EBufs& b, int k, const double* Ctb, const double* xs,
+                  double* xbar) {
+  const int x = m.x, Dl = m.Dl;
+  const long N = m.N, D2 = (long)Dl * Dl;
+  VTRY(gather(r, Ctb, b.pP, x, x, Dl, Dl, (long)Dl * N, Dl, N, 1));
+  VTRY(pq_site(r, m, k, xs, b.pSite));
+  VTRY(transpose(r, b.pSite, b.pSiteT, D2, D2));
+  VTRY(gemm(r, one(x * x, (int)D2, (int)D2, b.pP, D2, 0, b.pSiteT, D2, b.pWb[k], D2, true)));
+  VTRY(gemm(r, one((int)D2, (int)D2, x * x, b.pW[k], D2, 1, b.pP, D2, b.pSiteB, D2)));
+  // xbar[u, l, d, r] += siteB[i0..i3] where leg j of the site carries a-leg kPerm[k][j]
+  long st[4];
+  for (int j = 0; j < 4; ++j) st[3 - kPerm[k][j]] = dl_pow(Dl, 3 - j);
+  return gather(r, b.pSiteB, xbar, Dl, Dl, Dl, Dl, st[0], st[1], st[2], st[3], true);
+}
+
+// Reverse pass from b.Eb: accumulates into Cb, Tb (slots as C, T) and b.xb.
+int pq_bwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const double* const* T,
+           double* const* Cb, double* const* Tb) {
+  const int x = m.x, Dl = m.Dl, n = b.n;
+  const long N = m.N, NN = N * N, Dl4 = (long)Dl * Dl * Dl * Dl;
+  for (int k = 0; k < 4; ++k) VTRY(fill(r, b.pWb[k], NN, 0.0));
+  VTRY(fill(r, b.pCt1b, NN, 0.0));
+  VTRY(fill(r, b.pCt3b, NN, 0.0));
+  VTRY(fill(r, b.pAb, Dl4, 0.0));
+  // Ct0b_i = sum_j Eb[i, j] Zt_j;  G_j = sum_i Eb[i, j] Ct0_i (into the Zt stack)
+  VTRY(gemm(r, one(n, (int)NN, n, b.Eb, n, 0, b.pZt, NN, b.pCt0b, NN)));
+  VTRY(gemm(r, one(n, (int)NN, n, b.Eb, n, 1, b.pCt0, NN, b.pZt, NN)));
+  for (int i = 0; i < n; ++i) VTRY(pq_absorb_bwd(r, m, b, 0, b.pCt0b + i * NN, b.xs[i], b.xb[i]));
+  for (int j = 0; j < n; ++j) {
+    const double* G = b.pZt + j * NN;       // cotangent of Zt_j = (Y_j Ct3)^T
+    const double* c2 = b.pCt2 + j * NN;
+    const double* y = b.pY + j * NN;
+    // H = Y_j_bar^T = Ct3 G
+    VTRY(gemm(r, one((int)N, (int)N, (int)N, b.pCt3, N, 0, G, N, b.pH, N)));
+    GemmBatch g = one((int)N, (int)N, (int)N, G, N, 0, y, N, b.pCt3b, 0, true);   // (G Y)^T
+    transposed_out(g, N);
+    VTRY(gemm(r, g));
+    g = one((int)N, (int)N, (int)N, c2, N, 0, b.pH, N, b.pCt1b, 0, true);          // (Ct2 H)^T
+    transposed_out(g, N);
+    VTRY(gemm(r, g));
+    g = one((int)N, (int)N, (int)N, b.pH, N, 0, b.pCt1, N, b.pCt2b, 0);            // (H Ct1)^T
+    transposed_out(g, N);
+    VTRY(gemm(r, g));
+    VTRY(pq_absorb_bwd(r, m, b, 2, b.pCt2b, b.xs[j], b.xb[j]));
+  }
+  VTRY(pq_absorb_bwd(r, m, b, 1, b.pCt1b, b.pA, b.pAb));
+  VTRY(pq_absorb_bwd(r, m, b, 3, b.pCt3b, b.pA, b.pAb));
+  for (int s = 0; s < m.d; ++s)
+    VTRY(gather(r, b.pAb, b.xb[s * m.d + s], Dl, Dl, Dl, Dl, (long)Dl * Dl * Dl, (long)Dl * Dl, Dl, 1,
+                true));
+  // W_k = R_k regrouped, R_k = T_(k-1) CT_k, CT_k = C_k T_k
+  for (int k = 0; k < 4; ++k) {
+    const int km = (k + 3) % 4;
+    VTRY(gather(r, b.pWb[k], b.pRb, x, Dl, Dl, x, (long)x * Dl * Dl, Dl, 1, (long)Dl * Dl));
+    VTRY(transpose(r, b.pCT[k], b.pCTt, x, (long)Dl * x));
+    VTRY(gemm(r, one(x * Dl, x, Dl * x, b.pRb, (long)Dl * x, 0, b.pCTt, x, Tb[km], x, true)));
+    VTRY(gemm(r, one(x, Dl * x, x * Dl, T[km], x, 1, b.pRb, (long)Dl * x, b.pCTb, (long)Dl * x)));
+    VTRY(transpose(r, T[k], b.pTt, x, (long)Dl * x));
+    VTRY(gemm(r, one(x, x, Dl * x, b.pCTb, (long)Dl * x, 0, b.pTt, x, Cb[k], x, true)));
+    VTRY(gemm(r, one(x, Dl * x, x, C[k], x, 1, b.pCTb, (long)Dl * x, Tb[k], (long)Dl * x, true)));
+  }
+  return 0;
+}
+
+int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, int bonds,
+                    double* e_out, double* state_bar, double* site_bar, void* ws, size_t ws_bytes) {
   VjpView v;
   int rc = vjp_view(ctx, &v);
   if (rc) return rc;
@@ -1848,22 +2027,25 @@ int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, do
   const int n = b.n;
   std::vector<double> op(op_host, op_host + n * n), E(n * n), Eb;
   double total = 0.0;
-  for (int dir = 0; dir < 2; ++dir) {
+  for (int dir = 0; dir < 4; ++dir) {
     // dir 0: horizontal pair; dir 1: vertical pair = horizontal pair of the
-    // turned network (slot i holds corner / edge i+1, site legs rotated)
+    // turned network (slot i holds corner / edge i+1, site legs rotated);
+    // dir 2: diagonal pair; dir 3: anti-diagonal = diagonal of the turned one
+    if (!(bonds & (1 << dir))) continue;
+    const bool turned = dir & 1;
     const double* Cs[4];
     const double* Ts[4];
     double* Cbs[4];
     double* Tbs[4];
     for (int i = 0; i < 4; ++i) {
-      const int j = dir ? md(i + 1) : i;
+      const int j = turned ? md(i + 1) : i;
       Cs[i] = C[j];
       Ts[i] = T[j];
       Cbs[i] = Cb[j];
       Tbs[i] = Tb[j];
     }
     const double* site = v.A_site;
-    if (dir) {
+    if (turned) {
       // Ar[s, i1, i2, i3, i4] = A[s, u = i2, l = i3, d = i4, r = i1]
       const long D = m.D;
       for (int s = 0; s < m.d; ++s)
@@ -1872,14 +2054,20 @@ int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, do
       site = b.Ar;
     }
     VTRY(open_layers(r, m, b, site));
-    VTRY(echain_fwd(r, m, b, Cs, Ts));
+    if (dir < 2)
+      VTRY(echain_fwd(r, m, b, Cs, Ts));
+    else
+      VTRY(pq_fwd(r, m, b, Cs, Ts));
     CTM_HIP_TRY(hipMemcpyAsync(E.data(), b.E, n * n * sizeof(double), hipMemcpyDeviceToHost, r.st));
     CTM_HIP_TRY(hipStreamSynchronize(r.st));
     total += bond_value_and_bar(E, op.data(), m.d, Eb);
     CTM_HIP_TRY(hipMemcpyAsync(b.Eb, Eb.data(), n * n * sizeof(double), hipMemcpyHostToDevice, r.st));
     for (int st = 0; st < n; ++st) VTRY(fill(r, b.xb[st], (long)Dl * Dl * Dl * Dl, 0.0));
-    VTRY(echain_bwd(r, m, b, Cs, Ts, Cbs, Tbs));
-    if (!dir) {
+    if (dir < 2)
+      VTRY(echain_bwd(r, m, b, Cs, Ts, Cbs, Tbs));
+    else
+      VTRY(pq_bwd(r, m, b, Cs, Ts, Cbs, Tbs));
+    if (!turned) {
       VTRY(open_vjp(r, m, b, v.A_site, site_bar));
     } else {
       VTRY(fill(r, b.Abr, (long)(m.d * D4), 0.0));
@@ -1907,7 +2095,23 @@ ctm_status ctm_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_ho
     set_thread_error("null argument");
     return CTM_E_ARG;
   }
-  return (ctm_status)energy_vjp_impl(ctx, state, op_host, e_out, state_bar, site_bar, ws, ws_bytes);
+  return (ctm_status)energy_vjp_impl(ctx, state, op_host, 3, e_out, state_bar, site_bar, ws,
+                                     ws_bytes);
+}
+
+ctm_status ctm_bond_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_host, int bonds,
+                               double* e_out, double* state_bar, double* site_bar, void* ws,
+                               size_t ws_bytes) {
+  if (!ctx || !state || !op_host || !state_bar || !site_bar || !ws) {
+    set_thread_error("null argument");
+    return CTM_E_ARG;
+  }
+  if (bonds <= 0 || bonds > 15) {
+    set_thread_error("bonds must be a non-empty mask of H = 1, V = 2, D = 4, AD = 8");
+    return CTM_E_ARG;
+  }
+  return (ctm_status)energy_vjp_impl(ctx, state, op_host, bonds, e_out, state_bar, site_bar, ws,
+                                     ws_bytes);
 }
 
 }  // extern "C"

@@ -161,10 +161,39 @@ def test_energy_gradient_matches_autograd_reference(D, chi):
     assert not g["X"].any() and not g["Yt"].any()
 
 
-def test_gradient_of_the_converged_energy_matches_finite_differences():
-    """The full gradient of the converged Heisenberg bond energy with respect
-    to the site tensor (direct term + fixed-point term, eq. implicit)
-    against central differences of converged GPU runs."""
+@pytest.mark.parametrize("bonds", ["d", "a", "hvd", "hvda"])
+@pytest.mark.parametrize("D,chi", [(2, 4), (3, 9)])
+def test_bond_energy_gradient_matches_autograd_reference(D, chi, bonds):
+    """Energy over a set of bonds, including the diagonal pair of the
+    plaquette (hand-written reverse pass) and the anti-diagonal (the diagonal
+    of the turned network), against the autograd reference, for an operator
+    that is not symmetric under exchange of the two sites."""
+    A, C, T, X, Y = make_state(D, chi, 4)
+    cfg = P.Config(d=2, D=D, chi=chi, p=4, n_si=2)
+    ctx = P.Ctm(cfg, torch.from_numpy(A).to(torch.device("cuda", 0)))
+    state = torch.from_numpy(ctx.pack_state(C, T, np.stack(X), np.stack(Y)))
+    h = S.heisenberg_bond() + 0.3 * np.kron(S.pauli("x"), S.pauli("z"))
+    e, bar, site_bar = ctx.energy_vjp(state, h, bonds=bonds)
+    ref_e, gC, gT, gA = J.energy_vjp(C, T, A, h, bonds)
+    assert abs(e - ref_e) <= 1e-12 * max(1.0, abs(ref_e))
+    b = bar.cpu().numpy()
+    assert not b[-4:].any()
+    b[-4] = chi
+    g = ctx.unpack_state(b)
+    errs = {"C": max(rel(a, r) for a, r in zip(g["C"], gC)),
+            "T": max(rel(a, r) for a, r in zip(g["T"], gT)),
+            "A": rel(site_bar.cpu().numpy(), gA)}
+    print(bonds, errs)
+    assert all(v <= 1e-10 for v in errs.values()), errs
+    assert not g["X"].any() and not g["Yt"].any()
+
+
+@pytest.mark.parametrize("bonds", ["hv", "hvd"])
+def test_gradient_of_the_converged_energy_matches_finite_differences(bonds):
+    """The full gradient of the converged Heisenberg energy (nearest-neighbour
+    bonds, and the triangular lattice's h + v + d) with respect to the site
+    tensor (direct term + fixed-point term, eq. implicit) against central
+    differences of converged GPU runs."""
     D, chi, p = 2, 8, 4
     A = S.product_plus_noise_site(2, D, 2, noise=0.3)
     cfg = P.Config(d=2, D=D, chi=chi, p=p, n_si=2)
@@ -181,11 +210,15 @@ def test_gradient_of_the_converged_energy_matches_finite_differences():
         assert r["delta"] < 1e-12, r
         return ctx
 
+    kinds = {"h": P.OBS_BOND_H, "v": P.OBS_BOND_V, "d": P.OBS_BOND_D}
+
+    def bond_sum(c):
+        return sum(c.observable(kinds[bd], h)[0] for bd in bonds)
+
     ctx = converged(A)
-    e, grad, passes = ctx.energy_gradient(h)
+    e, grad, passes = ctx.energy_gradient(h, bonds=bonds)
     grad = grad.cpu().numpy()
-    eh = ctx.observable(P.OBS_BOND_H, h)[0] + ctx.observable(P.OBS_BOND_V, h)[0]
-    assert abs(e - eh) <= 1e-12
+    assert abs(e - bond_sum(ctx)) <= 1e-12
     print("energy", e, "passes", passes)
     rng = np.random.default_rng(21)
     for trial in range(2):
@@ -193,8 +226,7 @@ def test_gradient_of_the_converged_energy_matches_finite_differences():
         hh = 1e-5
 
         def energy(site):
-            c = converged(site)
-            return c.observable(P.OBS_BOND_H, h)[0] + c.observable(P.OBS_BOND_V, h)[0]
+            return bond_sum(converged(site))
 
         fd = (energy(A + hh * d) - energy(A - hh * d)) / (2 * hh)
         an = float((grad * d).sum())
