@@ -641,6 +641,36 @@ def bond_value(env: Env, A: np.ndarray, op: np.ndarray, direction: str) -> float
     return float(np.trace(op @ rho))
 
 
+def transfer_matrix(env: Env, a: np.ndarray, direction: str = "h") -> np.ndarray:
+    """The transfer matrix of one column (``h``: moving right along a row,
+    between the top edge T1 and the bottom edge T3) or of one row (``v``:
+    moving down a column, between the left edge T4 and the right edge T2) of
+    the converged environment (the transfer matrix whose eigenvalues give
+    the correlation length, iPEPS benchmark section):
+    ``E_h[(b, l, n), (g, r, z)] = T1[b,u,g] a[u,l,d,r] T3[z,d,n]``,
+    ``E_v[(a, u, h), (t, d, e)] = T4[t,l,a] a[u,l,d,r] T2[h,r,e]``."""
+    T1, T2, T3, T4 = env.T
+    x, Dl = env.chi, a.shape[0]
+    if direction == "h":
+        E = np.einsum("bug,uldr,zdn->blngrz", T1, a, T3, **_EIN)
+    else:
+        E = np.einsum("tla,uldr,hre->auhtde", T4, a, T2, **_EIN)
+    return E.reshape(x * Dl * x, x * Dl * x)
+
+
+def correlation_length(env: Env, a: np.ndarray, direction: str = "h", nvals: int = 4):
+    """``xi = -1 / ln(|lambda_2| / |lambda_1|)`` from the two eigenvalues of
+    largest modulus of ``transfer_matrix`` (0 when lambda_2 vanishes), and the
+    moduli ``|lambda_i / lambda_1|`` of the leading ``nvals`` eigenvalues."""
+    w = np.sort(np.abs(np.linalg.eigvals(transfer_matrix(env, a, direction))))[::-1]
+    r = w[:nvals] / w[0]
+    xi = 0.0 if r[1] <= 0.0 else float(-1.0 / np.log(r[1]))
+    return xi, r
+
+
+__all__ += ["transfer_matrix", "correlation_length"]
+
+
 def classical_bond_value(env: Env, a: np.ndarray, a1: np.ndarray, a2: np.ndarray,
                          direction: str) -> float:
     """Two impurities on a bond of a classical network, divided by the plain

@@ -394,6 +394,59 @@ def test_uncoupled_chains_factorise_on_the_diagonals(rows):
     assert abs(e12 - e1 * e2) > 1e-3                # the two pins are distinct
 
 
+@pytest.mark.parametrize("rows", [True, False])
+def test_uncoupled_chains_give_the_mps_correlation_length(rows):
+    """For a stack of independent MPS rows the column transfer matrix is the
+    chain's own transfer matrix (the boundary across the chains is a product),
+    so xi along the chains is the MPS correlation length -1/ln|mu2/mu1|
+    (eigenvalues of sum_s B_s (x) B_s), and across them the transfer matrix
+    has rank one (xi = 0).  Columns: the same with the roles exchanged."""
+    rng = np.random.default_rng(7)
+    B = rng.standard_normal((2, 2, 2)) + 0.3 * np.eye(2)[None]
+    A = np.zeros((2, 2, 2, 2, 2))
+    if rows:
+        A[:, 0, :, 0, :] = B
+    else:
+        A[:, :, 0, :, 0] = B
+    mu = np.sort(np.abs(np.linalg.eigvals(np.einsum("slr,sLR->lLrR", B, B).reshape(4, 4))))[::-1]
+    xi_mps = -1.0 / np.log(mu[1] / mu[0])
+    a, e = O.double_layer(A), S.trace_boundary(2)
+    env, _ = O.run_ctmrg(a, e, 4, proj="svd", tol=0.0, max_moves=80)
+    along, across = ("h", "v") if rows else ("v", "h")
+    xi, r = O.correlation_length(env, a, along)
+    assert abs(xi - xi_mps) <= 1e-9 * xi_mps
+    assert np.allclose(r[:4], mu[:4] / mu[0], atol=1e-10)
+    xi0, r0 = O.correlation_length(env, a, across)
+    assert r0[1] <= 1e-10
+
+
+def test_product_state_has_zero_correlation_length():
+    rng = np.random.default_rng(5)
+    phi, v = rng.standard_normal(2), rng.standard_normal(3)
+    A = np.einsum("s,u,l,d,r->suldr", phi, v, v, v, v)
+    a, e = O.double_layer(A), S.trace_boundary(3)
+    env, _ = O.run_ctmrg(a, e, 6, proj="svd", max_moves=4)
+    for direction in "hv":
+        _, r = O.correlation_length(env, a, direction)
+        assert r[1] <= 1e-12
+
+
+def test_rotation_swaps_the_two_correlation_lengths():
+    """The column transfer matrix of a state is the row transfer matrix of
+    the state turned by 90 degrees (each from its own converged
+    environment): same spectrum, so xi_h(A) = xi_v(A_rot)."""
+    A = S.product_plus_noise_site(2, 2, 14, noise=0.6)
+    Ar = np.einsum("suldr->sruld", A)
+    out = {}
+    for name, site in (("A", A), ("Ar", Ar)):
+        a, e = O.double_layer(site), S.trace_boundary(2)
+        env, _ = O.run_ctmrg(a, e, 8, proj="svd", tol=1e-13, max_moves=200)
+        out[name] = [O.correlation_length(env, a, dr)[0] for dr in "hv"]
+    assert abs(out["A"][0] - out["Ar"][1]) <= 1e-8 * out["A"][0]
+    assert abs(out["A"][1] - out["Ar"][0]) <= 1e-8 * out["A"][1]
+    assert abs(out["A"][0] - out["A"][1]) > 1e-4
+
+
 def test_rotation_maps_the_diagonal_to_the_antidiagonal():
     """Turning the lattice by 90 degrees (new (u,l,d,r) = old (r,u,l,d), so
     the old right is the new up) carries the top-left / bottom-right pair to
