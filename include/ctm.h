@@ -77,7 +77,13 @@ typedef enum {
   CTM_OBS_BOND_D = 4,  /* as BOND_H for the diagonal of a plaquette: site 1 top-left, site 2
                           bottom-right (the extra bond of the triangular lattice drawn on the
                           square one, triangular-lattice section)                             */
-  CTM_OBS_BOND_AD = 5  /* the other diagonal: site 1 top-right, site 2 bottom-left            */
+  CTM_OBS_BOND_AD = 5, /* the other diagonal: site 1 top-right, site 2 bottom-left            */
+  CTM_OBS_XI_H = 6,    /* correlation length along a row from the column transfer matrix
+                          E[(b,l,n),(g,r,z)] = T1[b,u,g] a[u,l,d,r] T3[z,d,n] (iPEPS benchmark
+                          section): out[0] = -1/ln|l2/l1|, out[1] = |l2/l1|, out[2] = l1; op
+                          may be NULL or point to the number of block iterations (default
+                          100) of the 8 vectors whose Rayleigh-Ritz matrix gives l1, l2 */
+  CTM_OBS_XI_V = 7     /* the same along a column (row transfer matrix, edges T4 and T2)     */
 } ctm_obs;
 
 typedef struct {

@@ -38,7 +38,7 @@ PREC = {"f64": 0, "f32": 1, "bf16": 2}
 SVD_DRIVER = {"gesvd": 0, "gesdd": 1, "gesvdx": 2}
 GROWTH = {"svd": 0, "si": 1}
 SYM = {"none": 0, "c4v": 1}
-OBS_NORM, OBS_ONESITE, OBS_BOND_H, OBS_BOND_V, OBS_BOND_D, OBS_BOND_AD = range(6)
+OBS_NORM, OBS_ONESITE, OBS_BOND_H, OBS_BOND_V, OBS_BOND_D, OBS_BOND_AD, OBS_XI_H, OBS_XI_V = range(8)
 
 
 class ctm_config(ctypes.Structure):
@@ -269,6 +269,12 @@ class Ctm:
 
     def kappa(self) -> float:
         return float(self.observable(OBS_NORM)[0])
+
+    def correlation_length(self, direction: str = "h", iters: int = 100):
+        """(xi, |l2/l1|) of the column (``h``) or row (``v``) transfer matrix."""
+        out = self.observable(OBS_XI_H if direction == "h" else OBS_XI_V,
+                              np.array([float(iters)]))
+        return float(out[0]), float(out[1])
 
     def state_size(self) -> int:
         n = ctypes.c_size_t(0)

@@ -133,6 +133,10 @@ struct ctm_ctx {
   int* fs_perm;              // descending order of the dense SVD's singular values
   double* sk_part = nullptr;  // partial tiles of the balanced SI applications
   double* dot_part = nullptr; // partial sums of the plaquette dot products
+  // correlation length: block of kXiBlock vectors of the transfer matrix
+  double *xi_V = nullptr, *xi_Vc = nullptr, *xi_W = nullptr, *xi_H = nullptr, *xi_out = nullptr;
+  void* xi_qr = nullptr;
+  int xi_m = 0;
   int sk_cus = kSplitMaxCus;  // CUs a balanced launch spreads over
   double* obs_y;             // [d^2][x Dl x]
   double* obs_w;             // [d^2][x Dl x]
@@ -235,6 +239,9 @@ void set_dims(ctm_ctx* c, const ctm_config* cfg) {
   c->cp = cfg->prec == CTM_PREC_F64 ? DT::F64 : (cfg->prec == CTM_PREC_F32 ? DT::F32 : DT::BF16);
 }
 
+// Vectors of the block iteration for the correlation length.
+constexpr int kXiBlock = 8;
+
 // Assigns every buffer of the context from base (or only sizes it).
 size_t carve(ctm_ctx* c, char* base) {
   Carver cv;
@@ -300,6 +307,17 @@ size_t carve(ctm_ctx* c, char* base) {
   c->fs_info = cv.take<int>(64);
   c->fs_perm = cv.take<int>(Nm);
   c->dot_part = cv.take<double>((size_t)kMaxDots * kDotBlocks);
+  {
+    const size_t nE = chi * Dl * chi;
+    c->xi_m = (int)std::min<size_t>(kXiBlock, nE);
+    const bool qr_ok = qr_plan_ok((int)nE, c->xi_m);
+    c->xi_V = cv.take<double>(nE * c->xi_m);
+    c->xi_Vc = cv.take<double>(nE * c->xi_m);
+    c->xi_W = cv.take<double>(nE * c->xi_m);
+    c->xi_H = cv.take<double>((size_t)kXiBlock * kXiBlock);
+    c->xi_out = cv.take<double>(8);
+    c->xi_qr = qr_ok ? cv.take_bytes(qr_workspace_bytes(1, (int)nE, c->xi_m)) : nullptr;
+  }
   c->sk_part = c->cp == DT::F64 && gemm_si_balanced_useful(8, (int)N, (int)k, (int)N, kSplitMaxCus)
                    ? (double*)cv.take_bytes(gemm_si_scratch_bytes())
                    : nullptr;
@@ -1415,6 +1433,76 @@ int diag_pair(ctm_ctx* c, bool anti, const double* const* s1, int n1, const doub
   return 0;
 }
 
+// w = E v for one vector v (x, Dl, x) of the column transfer matrix
+// E[(b, l, n), (g, r, z)] = T1[b,u,g] a[u,l,d,r] T3[z,d,n], as three GEMMs
+// whose output maps leave each result in the layout the next one reads:
+// X[(g, n), (u, l)] = sum_b T1[b, (u, g)] v[b, (l, n)];
+// Y[(d, n), (g, r)] = sum_(u,l) X[(g, n), (u, l)] a[(u, l), (d, r)];
+// w[(g, r, z)]      = sum_(d,n) T3[z, (d, n)] Y[(d, n), (g, r)],
+// written with stride ws (w + k for column k of a row-major block).
+int transfer_apply(ctm_ctx* c, const double* T1, const double* T3, const double* a,
+                   const double* v, double* w, long ws) {
+  const int x = c->chi_env, Dl = c->Dl;
+  GemmBatch g = gb1(Dl * x, Dl * x, x, T1, (long)Dl * x, 1, v, (long)Dl * x, c->S1[0], 0);
+  set_map(g, x, Dl, (long)x * Dl * Dl, x, 1, (long)Dl * Dl);
+  TRY(g64(c, g));
+  g = gb1(x * x, Dl * Dl, Dl * Dl, c->S1[0], (long)Dl * Dl, 0, a, (long)Dl * Dl, c->S2[0], 0);
+  set_map(g, x, Dl, (long)x * Dl, Dl, (long)x * x * Dl, 1);
+  TRY(g64(c, g));
+  g = gb1(x, x * Dl, Dl * x, T3, (long)Dl * x, 0, c->S2[0], (long)x * Dl, w, 0);
+  set_map(g, 1 << 30, 0, ws, 1 << 30, 0, (long)x * ws);
+  return g64(c, g);
+}
+
+// Correlation length along the rows (vertical: the turned network, edges
+// T2 and T4 with the site legs rotated) by block iteration: W = E V, V =
+// QR(W), `iters` times, then the Rayleigh-Ritz matrix H = V^T E V and its
+// two leading eigenvalue moduli; out: xi, |l2/l1|, l1.
+int correlation_length(ctm_ctx* c, bool vertical, int iters, double* out_host) {
+  const int x = c->chi_env, Dl = c->Dl, m = c->xi_m;
+  const long nE = (long)x * Dl * x;
+  if (!c->xi_qr || (long)c->chi * Dl * c->chi < nE)
+    return fail(c, CTM_E_SHAPE, "correlation length: no QR plan for the transfer-matrix block");
+  const int mm = (int)std::min<long>(m, nE);
+  if (!qr_plan_ok((int)nE, mm))
+    return fail(c, CTM_E_SHAPE, "correlation length: no QR plan for the transfer-matrix block");
+  double* const* T = c->T[c->cur];
+  const double* a = c->a;
+  const double *T1 = T[0], *T3 = T[2];
+  if (vertical) {
+    // turned network: a_r[u', l', d', r'] = a[u = l', l = d', d = r', r = u']
+    const long D1 = Dl, D2 = D1 * Dl, D3 = D2 * Dl;
+    TRY(elem_permute4(c->a, c->imp[2], DT::F64, Dl, 1, D3, D2, D1, c->st));
+    a = c->imp[2];
+    T1 = T[1];
+    T3 = T[3];
+  }
+  // seeded start block (host generator; the same every call), row-major nE x mm
+  std::vector<double> v0((size_t)nE * mm);
+  uint64_t st = 0x9e3779b97f4a7c15ULL;
+  for (double& e : v0) {
+    st ^= st << 13;
+    st ^= st >> 7;
+    st ^= st << 17;
+    e = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+  CTM_HIP_TRY(hipMemcpyAsync(c->xi_W, v0.data(), v0.size() * 8, hipMemcpyHostToDevice, c->st));
+  double* Wp[1] = {c->xi_W};
+  for (int it = 0; it <= iters; ++it) {
+    TRY(launch_qr(1, Wp, (int)nE, mm, c->xi_qr, c->st) ? fail(c, CTM_E_DEVICE, thread_error()) : 0);
+    CTM_HIP_TRY(hipMemcpyAsync(c->xi_V, c->xi_W, (size_t)nE * mm * 8, hipMemcpyDeviceToDevice, c->st));
+    TRY(elem_transpose(c->xi_V, c->xi_Vc, nE, mm, c->st));
+    for (int k = 0; k < mm; ++k)
+      TRY(transfer_apply(c, T1, T3, a, c->xi_Vc + (long)k * nE, c->xi_W + k, mm));
+  }
+  // H = V^T (E V)
+  TRY(g64(c, gb1(mm, mm, (int)nE, c->xi_V, mm, 1, c->xi_W, mm, c->xi_H, mm)));
+  TRY(elem_xi_from_ritz(c->xi_H, mm, 60, c->xi_out, c->st) ? fail(c, CTM_E_ARG, "small eigenproblem") : 0);
+  CTM_HIP_TRY(hipMemcpyAsync(out_host, c->xi_out, 3 * 8, hipMemcpyDeviceToHost, c->st));
+  CTM_HIP_TRY(hipStreamSynchronize(c->st));
+  return 0;
+}
+
 int observable(ctm_ctx* c, int kind, const double* op_host, double* out_host) {
   const int Dl = c->Dl, d = c->d;
   const size_t Dl4 = (size_t)Dl * Dl * Dl * Dl;
@@ -1430,6 +1518,11 @@ int observable(ctm_ctx* c, int kind, const double* op_host, double* out_host) {
     out_host[0] = host[5];
     for (int i = 0; i < 4; ++i) out_host[1 + i] = host[i];
     return 0;
+  }
+  if (kind == CTM_OBS_XI_H || kind == CTM_OBS_XI_V) {
+    const int iters = op_host ? (int)op_host[0] : 100;
+    if (iters < 1 || iters > 100000) return fail(c, CTM_E_ARG, "iterations outside [1, 100000]");
+    return correlation_length(c, kind == CTM_OBS_XI_V, iters, out_host);
   }
   if (!op_host) return fail(c, CTM_E_ARG, "observable needs an operator");
   if (kind == CTM_OBS_ONESITE) {

@@ -60,6 +60,13 @@ constexpr int kMaxDots = 9;
 constexpr int kDotBlocks = 1024;
 int elem_dots(const double* X, const double* const* Y, int ny, long n, double* part,
               double* out, hipStream_t s);
+// dst (cols x rows) = src (rows x cols)^T
+int elem_transpose(const double* src, double* dst, long rows, long cols, hipStream_t s);
+// out[0] = -1/ln(|l2|/|l1|), out[1] = |l2|/|l1|, out[2] = l1 for the two
+// eigenvalues of largest modulus of the m x m row-major matrix H
+// (m <= kMaxSmallEig; l1 simple and dominant).
+constexpr int kMaxSmallEig = 16;
+int elem_xi_from_ritz(const double* H, int m, int squarings, double* out, hipStream_t s);
 int elem_ratio(const double* a, const double* b, double* out, hipStream_t s);
 int elem_permute4(const double* src, void* dst, DT t, int n, long s0, long s1, long s2, long s3,
                   hipStream_t s);

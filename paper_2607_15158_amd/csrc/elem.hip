@@ -446,6 +446,102 @@ __global__ __launch_bounds__(256) void k_dots_final(const double* part, int nb, 
   if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
+// dst (cols x rows) = src (rows x cols)^T
+__global__ void k_transpose(const double* src, double* dst, long rows, long cols) {
+  const long total = rows * cols;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+    const long r = i / cols, c = i % cols;
+    dst[c * rows + r] = src[i];
+  }
+}
+
+// Correlation length from the m x m Rayleigh-Ritz matrix H of a transfer
+// matrix (m <= kMaxSmallEig, row-major): out[0] = -1 / ln(|l2| / |l1|),
+// out[1] = |l2| / |l1|, out[2] = l1 (0, 0, l1 when l2 = 0).  One thread.
+// Normalised repeated squaring of H converges to a multiple of the spectral
+// projector r l^T of the dominant eigenvalue l1 (simple and alone on its
+// circle for a gapped transfer matrix); l1 = l^T H r / l^T r.  |l2| is the
+// spectral radius of H - l1 r l^T / (l^T r), from the norms of its powers
+// 2^j (the logarithms of the normalisations, weighted 2^-j): this needs no
+// separation between |l2| and |l3| and covers complex pairs.
+__device__ void sq_norm(double (*B)[kMaxSmallEig], double (*T)[kMaxSmallEig], int m, double* nb) {
+  double mx = 0.0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      double acc = 0.0;
+      for (int q = 0; q < m; ++q) acc += B[i][q] * B[q][j];
+      T[i][j] = acc;
+      mx = fmax(mx, fabs(acc));
+    }
+  *nb = mx;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) B[i][j] = mx > 0.0 ? T[i][j] / mx : 0.0;
+}
+
+__global__ void k_xi_from_ritz(const double* Hin, int m, int squarings, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double H[kMaxSmallEig][kMaxSmallEig], B[kMaxSmallEig][kMaxSmallEig], T[kMaxSmallEig][kMaxSmallEig];
+  double mx = 0.0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      H[i][j] = Hin[i * m + j];
+      mx = fmax(mx, fabs(H[i][j]));
+    }
+  out[0] = out[1] = out[2] = 0.0;
+  if (mx == 0.0) return;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) B[i][j] = H[i][j] / mx;
+  double nb = 1.0;
+  for (int it = 0; it < squarings && nb > 0.0; ++it) sq_norm(B, T, m, &nb);
+  if (nb == 0.0) return;
+  // r: the column of largest norm, l: the row of largest norm
+  int ci = 0, ri = 0;
+  double bc = -1.0, br = -1.0;
+  for (int q = 0; q < m; ++q) {
+    double c2 = 0.0, r2 = 0.0;
+    for (int p = 0; p < m; ++p) {
+      c2 += B[p][q] * B[p][q];
+      r2 += B[q][p] * B[q][p];
+    }
+    if (c2 > bc) { bc = c2; ci = q; }
+    if (r2 > br) { br = r2; ri = q; }
+  }
+  double r[kMaxSmallEig], l[kMaxSmallEig];
+  for (int p = 0; p < m; ++p) {
+    r[p] = B[p][ci];
+    l[p] = B[ri][p];
+  }
+  double lr = 0.0, lhr = 0.0;
+  for (int p = 0; p < m; ++p) {
+    lr += l[p] * r[p];
+    double hr = 0.0;
+    for (int q = 0; q < m; ++q) hr += H[p][q] * r[q];
+    lhr += l[p] * hr;
+  }
+  if (lr == 0.0) return;
+  const double l1 = lhr / lr;
+  out[2] = l1;
+  double c0 = 0.0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      B[i][j] = H[i][j] - l1 * r[i] * l[j] / lr;
+      c0 = fmax(c0, fabs(B[i][j]));
+    }
+  if (c0 == 0.0 || l1 == 0.0) return;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) B[i][j] /= c0;
+  double logr = log(c0), w = 1.0;
+  for (int it = 0; it < squarings; ++it) {
+    sq_norm(B, T, m, &nb);
+    if (nb == 0.0) return;                 // nilpotent remainder: l2 = 0
+    w *= 0.5;
+    logr += w * log(nb);
+  }
+  const double rat = exp(logr) / fabs(l1);
+  out[1] = rat;
+  out[0] = (rat > 0.0 && rat < 1.0) ? -1.0 / log(rat) : 0.0;
+}
+
 // vals = [Z11, Z00, Z10, Z01] -> out = Z11 Z00 / (Z10 Z01)
 __global__ void k_kappa(const double* z, double* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = z[0] * z[1] / (z[2] * z[3]);
@@ -554,6 +650,21 @@ int elem_dots(const double* X, const double* const* Y, int ny, long n, double* p
   k_dots_part<<<kDotBlocks, 256, 0, s>>>(X, p, ny, n, part);
   CTM_HIP_TRY(hipGetLastError());
   k_dots_final<<<ny, 256, 0, s>>>(part, kDotBlocks, out);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_transpose(const double* src, double* dst, long rows, long cols, hipStream_t s) {
+  const long total = rows * cols;
+  if (total <= 0) return 0;
+  k_transpose<<<(int)std::min<long>(4096, (total + 255) / 256), 256, 0, s>>>(src, dst, rows, cols);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int elem_xi_from_ritz(const double* H, int m, int squarings, double* out, hipStream_t s) {
+  if (m < 1 || m > kMaxSmallEig || squarings < 1) return 1;
+  k_xi_from_ritz<<<1, 64, 0, s>>>(H, m, squarings, out);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }

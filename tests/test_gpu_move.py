@@ -310,6 +310,50 @@ def test_diagonal_bonds_match_oracle_on_a_given_environment(d, D, chi):
             assert abs(got - ref) <= 1e-11 * max(1.0, abs(ref)), (kind, got, ref)
 
 
+@pytest.mark.parametrize("D,chi", [(2, 8), (3, 12)])
+def test_correlation_length_matches_oracle(D, chi):
+    """xi and |l2/l1| of the column and row transfer matrices from the block
+    iteration on the GPU against the oracle's dense eigenvalues of the same
+    transfer matrices, built from the GPU's own converged environment."""
+    A = S.product_plus_noise_site(2, D, 4, noise=0.4)
+    cfg = P.Config(d=2, D=D, chi=chi, p=4)
+    ctx, _ = make(cfg, A)
+    ctx.converge(1e-12, 200)
+    st = ctx.unpack_state(ctx.get_state())
+    env = O.Env(st["C"], st["T"])
+    a = O.double_layer(A)
+    for direction in "hv":
+        xi, r2 = ctx.correlation_length(direction, iters=200)
+        xo, ro = O.correlation_length(env, a, direction)
+        print(direction, xi, xo, r2, ro[1])
+        assert abs(r2 - ro[1]) <= 1e-9 * ro[1], (direction, r2, ro[1])
+        assert abs(xi - xo) <= 1e-8 * xo, (direction, xi, xo)
+
+
+@pytest.mark.parametrize("rows", [True, False])
+def test_correlation_length_of_uncoupled_chains_on_gpu(rows):
+    """A stack of independent MPS rows (columns): along the chains xi is the
+    chain's own correlation length (1D transfer matrix), across them 0."""
+    rng = np.random.default_rng(7)
+    B = rng.standard_normal((2, 2, 2)) + 0.3 * np.eye(2)[None]
+    A = np.zeros((2, 2, 2, 2, 2))
+    if rows:
+        A[:, 0, :, 0, :] = B
+    else:
+        A[:, :, 0, :, 0] = B
+    mu = np.sort(np.abs(np.linalg.eigvals(np.einsum("slr,sLR->lLrR", B, B).reshape(4, 4))))[::-1]
+    xi_mps = -1.0 / np.log(mu[1] / mu[0])
+    cfg = P.Config(d=2, D=2, chi=4, p=4, proj="svd")
+    ctx, _ = make(cfg, A, iso=False)
+    for _ in range(80):
+        ctx.move()
+    along, across = ("h", "v") if rows else ("v", "h")
+    xi, r2 = ctx.correlation_length(along, iters=100)
+    assert abs(xi - xi_mps) <= 1e-8 * xi_mps, (xi, xi_mps)
+    xi0, r0 = ctx.correlation_length(across, iters=100)
+    assert r0 <= 1e-8
+
+
 def test_classical_diagonal_impurities_match_oracle():
     """d = 0: two impurity tensors on the diagonal pair of a given network
     and a seeded random environment, against the oracle's plaquette ratio."""
