@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--vjp", type=int, default=3,
                     help="time this many adjoints of the move (ctm_move_vjp) at the state after "
                          "the timed moves (0: skip)")
+    ap.add_argument("--xi-iters", type=int, default=30,
+                    help="block iterations of the correlation-length observable")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--pinv-rtol", type=float, default=1e-12)
     ap.add_argument("--svd-moves", type=int, default=1, help="full-SVD comparator moves (0: skip)")
@@ -369,6 +371,12 @@ def main():
             t1 = time.perf_counter()
             val = ctx.observable(kind, h)[0]
             obs[name] = {"value": val, "ms": round(1e3 * (time.perf_counter() - t1), 2)}
+        for direction in "hv":
+            t1 = time.perf_counter()
+            xi, r2 = ctx.correlation_length(direction, iters=args.xi_iters)
+            obs[f"xi_{direction}"] = {"value": xi, "l2_over_l1": r2, "iterations": args.xi_iters,
+                                      "ms": round(1e3 * (time.perf_counter() - t1), 2)}
+        kinds = kinds + (("xi_h", None), ("xi_v", None))
         log("observables: " + ", ".join(f"{k} {obs[k]['value']:.8f} ({obs[k]['ms']} ms)"
                                         for k, _ in kinds))
 
