@@ -498,6 +498,51 @@ def unrolled_energy(A, cfg: Config, op, state0, moves: int, bonds: str = "hv"):
     return _UnrolledEnergy.apply(A)
 
 
+def chi_ramp(A, D: int, chis, op=None, bonds: str = "hvd", p_frac: float = 0.15, n_si: int = 2,
+             tol: float = 1e-10, max_moves: int = 300, growth: str = "si", xi_iters: int = 60,
+             seed: int = 0) -> list:
+    """Environment dimension ramp (iPEPS benchmark section): converge the
+    environment of the site tensor ``A`` (float64 device tensor, d x D^4) at
+    each chi of the increasing sequence ``chis``, with the oversampling p the
+    fraction ``p_frac`` of chi (rounded up), each run starting from the
+    previous converged environment (its growth moves enlarge it, randomized
+    when ``growth`` is ``si``).  At every chi: moves, convergence, kappa, the
+    bond values of ``op`` over ``bonds`` and their sum (when ``op`` is given)
+    and the correlation lengths of both transfer matrices."""
+    import torch
+    chis = [int(c) for c in chis]
+    if any(b <= a for a, b in zip(chis, chis[1:])):
+        raise ValueError("chis must increase")
+    kinds = {"h": OBS_BOND_H, "v": OBS_BOND_V, "d": OBS_BOND_D, "a": OBS_BOND_AD}
+    d = int(A.shape[0])
+    rng = np.random.default_rng(seed)
+    prev, out = None, []
+    for chi in chis:
+        p = max(1, int(np.ceil(p_frac * chi)))
+        cfg = Config(d=d, D=D, chi=chi, p=p, n_si=n_si, growth=growth)
+        c = Ctm(cfg, A)
+        X = rng.standard_normal((4, cfg.N, cfg.k))
+        Y = rng.standard_normal((4, cfg.N, cfg.k))
+        if prev is None:
+            c.set_isometries(torch.from_numpy(X).to(A.device), torch.from_numpy(Y).to(A.device))
+        else:
+            c.set_state(c.pack_state(prev[0], prev[1], X, Y))
+        r = c.converge(tol, max_moves)
+        rec = {"chi": chi, "p": p, "moves": r["moves"], "converged": r["converged"],
+               "delta": r["delta"], "kappa": c.kappa()}
+        if op is not None:
+            for bd in bonds:
+                rec["e_" + bd] = float(c.observable(kinds[bd], op)[0])
+            rec["energy"] = sum(rec["e_" + bd] for bd in bonds)
+        for direction in "hv":
+            rec["xi_" + direction], rec["l2_" + direction] = c.correlation_length(direction, xi_iters)
+        st = c.unpack_state(c.get_state())
+        prev = (st["C"], st["T"])
+        out.append(rec)
+        c.close()
+    return out
+
+
 BOND_BITS = {"h": 1, "v": 2, "d": 4, "a": 8}
 
 

@@ -354,6 +354,23 @@ def test_correlation_length_of_uncoupled_chains_on_gpu(rows):
     assert r0 <= 1e-8
 
 
+def test_chi_ramp_reaches_the_direct_fixed_point():
+    """The chi ramp (4 -> 8 -> 12, p = 15% of chi, each run grown from the
+    previous environment) ends at the fixed point of a direct run at chi = 12:
+    the same triangular-lattice energy terms, kappa and correlation lengths."""
+    A = dev(S.product_plus_noise_site(2, 2, 6, noise=0.3))
+    h = S.heisenberg_bond()
+    ramp = P.chi_ramp(A, 2, [4, 8, 12], op=h, bonds="hvd", tol=1e-12, max_moves=400)
+    assert [r["p"] for r in ramp] == [1, 2, 2] and all(r["converged"] for r in ramp)
+    direct = P.chi_ramp(A, 2, [12], op=h, bonds="hvd", tol=1e-12, max_moves=400, seed=3)[0]
+    last = ramp[-1]
+    for key in ("e_h", "e_v", "e_d", "energy"):
+        assert abs(last[key] - direct[key]) <= 1e-9, (key, last[key], direct[key])
+    assert abs(last["kappa"] / direct["kappa"] - 1) <= 1e-9
+    for key in ("xi_h", "xi_v"):
+        assert abs(last[key] - direct[key]) <= 1e-7 * direct[key], (key, last[key], direct[key])
+
+
 def test_classical_diagonal_impurities_match_oracle():
     """d = 0: two impurity tensors on the diagonal pair of a given network
     and a seeded random environment, against the oracle's plaquette ratio."""
