@@ -285,13 +285,14 @@ def test_noisy_state_observables_match_oracle():
     assert abs(ctx.observable(P.OBS_BOND_AD, h)[0] - O.bond_value(env, A, h, "ad")) <= 1e-10
 
 
-@pytest.mark.parametrize("d,D,chi", [(2, 2, 7), (3, 2, 5), (2, 3, 30)])
+@pytest.mark.parametrize("d,D,chi", [(2, 2, 7), (3, 2, 5), (2, 3, 30), (2, 4, 64)])
 def test_diagonal_bonds_match_oracle_on_a_given_environment(d, D, chi):
     """Diagonal and anti-diagonal two-site values on the same seeded random
     environment as the oracle (set through the state vector, no moves), for
     operators that tell the two sites and ket from bra apart: every entry of
     the plaquette's open-leg tensor enters.  chi = 30, D = 3 gives N = 270:
-    several GEMM tiles with a ragged edge."""
+    several GEMM tiles with a ragged edge; chi = 64, D = 4 gives N = 1024,
+    the tile-scale products of the larger environments."""
     rng = np.random.default_rng(40 + d + chi)
     A = rng.standard_normal((d, D, D, D, D))
     Dl = D * D
@@ -310,7 +311,7 @@ def test_diagonal_bonds_match_oracle_on_a_given_environment(d, D, chi):
             assert abs(got - ref) <= 1e-11 * max(1.0, abs(ref)), (kind, got, ref)
 
 
-@pytest.mark.parametrize("D,chi", [(2, 8), (3, 12)])
+@pytest.mark.parametrize("D,chi", [(2, 8), (3, 12), (2, 24)])
 def test_correlation_length_matches_oracle(D, chi):
     """xi and |l2/l1| of the column and row transfer matrices from the block
     iteration on the GPU against the oracle's dense eigenvalues of the same
