@@ -369,13 +369,21 @@ class Ctm:
 
     def energy_gradient(self, op, tol: float = 1e-12, max_iter: int = 400, bonds: str = "hv"):
         """Gradient of the converged energy e (the sum of <op> over ``bonds``,
-        as in :meth:`energy_vjp`) with respect to the site tensor at the
-        context's current (converged) environment: the direct term plus the
-        fixed-point term (eq. implicit).  Returns (e, dE/dA as a device
-        tensor, passes of the fixed-point series)."""
+        as in :meth:`energy_vjp`; or, with ``op`` a dict {bond letter:
+        operator}, the sum of each bond's own operator) with respect to the
+        site tensor at the context's current (converged) environment: the
+        direct term plus the fixed-point term (eq. implicit).  Returns
+        (e, dE/dA as a device tensor, passes of the fixed-point series)."""
         import torch
         star = torch.from_numpy(self.get_state()).to(self._site.device)
-        e, g, site_bar = self.energy_vjp(star, op, bonds=bonds)
+        if isinstance(op, dict):
+            e, g, site_bar = 0.0, None, torch.zeros_like(self._site)
+            for bd, opb in op.items():
+                eb, gb, site_bar = self.energy_vjp(star, opb, site_bar, bonds=bd)
+                e += eb
+                g = gb if g is None else g + gb
+        else:
+            e, g, site_bar = self.energy_vjp(star, op, bonds=bonds)
         _, site_bar, passes, _ = self.fixed_point_vjp(star, g, tol, max_iter, site_bar)
         return e, site_bar, passes
 
@@ -541,6 +549,62 @@ def chi_ramp(A, D: int, chis, op=None, bonds: str = "hvd", p_frac: float = 0.15,
         out.append(rec)
         c.close()
     return out
+
+
+def spiral_bond_operators(h, angles) -> dict:
+    """Bond operators of a single-site ansatz for a spiral state of spin 1/2:
+    the site at lattice vector n carries the rotation exp(-i theta.n S^y), so
+    that a translation-invariant tensor describes the spiral; every bond b
+    then sees h_b = (1 x U_b) h (1 x U_b)^T with U_b the (real) rotation by
+    the angle of its bond vector.  ``angles``: {bond letter: angle}; the 120
+    degree order of the triangular lattice drawn on the square one with the
+    diagonal bond d uses {"h": 2 pi/3, "v": 2 pi/3, "d": 4 pi/3}."""
+    h = np.asarray(h, dtype=np.float64)
+    out = {}
+    for bd, th in angles.items():
+        U = np.array([[np.cos(th / 2), -np.sin(th / 2)], [np.sin(th / 2), np.cos(th / 2)]])
+        K = np.kron(np.eye(2), U)
+        out[bd] = K @ h @ K.T
+    return out
+
+
+def optimize_lbfgs(A0, cfg: Config, bond_ops: dict, iterations: int = 10, tol: float = 1e-10,
+                   max_moves: int = 300, fp_tol: float = 1e-10, fp_max_iter: int = 400,
+                   history_size: int = 10, X0=None, Yt0=None) -> tuple:
+    """Variational optimisation of a single-site tensor (the optimisation
+    loop of the paper: L-BFGS over the site tensor, the energy of the
+    converged environment and its gradient from the fixed-point adjoint,
+    eq. implicit).  Each evaluation starts its CTMRG from the previous
+    converged environment and SI blocks (recycling); the first from ``X0,
+    Yt0`` (4 x N x k) or the library's start blocks.  ``bond_ops``: {bond
+    letter: operator}, e.g. from :func:`spiral_bond_operators`.  Returns the
+    optimised tensor (device) and the history of (energy, gradient norm,
+    CTMRG moves) per evaluation."""
+    import torch
+    A = A0.detach().clone().to(torch.float64).requires_grad_(True)
+    opt = torch.optim.LBFGS([A], lr=1.0, max_iter=iterations, history_size=history_size,
+                            line_search_fn="strong_wolfe", tolerance_grad=1e-12,
+                            tolerance_change=1e-14)
+    prev = {"state": None}
+    history = []
+
+    def closure():
+        opt.zero_grad()
+        c = Ctm(cfg, A.detach())
+        if prev["state"] is not None:
+            c.set_state(prev["state"])
+        elif X0 is not None:
+            c.set_isometries(torch.as_tensor(X0).to(A.device), torch.as_tensor(Yt0).to(A.device))
+        r = c.converge(tol, max_moves)
+        e, grad, _ = c.energy_gradient(bond_ops, fp_tol, fp_max_iter)
+        prev["state"] = c.get_state()
+        c.close()
+        A.grad = grad.detach().clone()
+        history.append((e, float(grad.norm()), r["moves"]))
+        return torch.tensor(e, dtype=torch.float64)
+
+    opt.step(closure)
+    return A.detach(), history
 
 
 BOND_BITS = {"h": 1, "v": 2, "d": 4, "a": 8}
