@@ -1433,23 +1433,40 @@ int diag_pair(ctm_ctx* c, bool anti, const double* const* s1, int n1, const doub
   return 0;
 }
 
-// w = E v for one vector v (x, Dl, x) of the column transfer matrix
-// E[(b, l, n), (g, r, z)] = T1[b,u,g] a[u,l,d,r] T3[z,d,n], as three GEMMs
-// whose output maps leave each result in the layout the next one reads:
+// w_i = E v_i for up to four vectors v_i (x, Dl, x) of the column transfer
+// matrix E[(b, l, n), (g, r, z)] = T1[b,u,g] a[u,l,d,r] T3[z,d,n], as three
+// batched GEMMs whose output maps leave each result in the layout the next
+// one reads (intermediates of vector i in S1[i] and S2[i]):
 // X[(g, n), (u, l)] = sum_b T1[b, (u, g)] v[b, (l, n)];
 // Y[(d, n), (g, r)] = sum_(u,l) X[(g, n), (u, l)] a[(u, l), (d, r)];
 // w[(g, r, z)]      = sum_(d,n) T3[z, (d, n)] Y[(d, n), (g, r)],
-// written with stride ws (w + k for column k of a row-major block).
+// written with stride ws (w_i = block + column, row-major block).
 int transfer_apply(ctm_ctx* c, const double* T1, const double* T3, const double* a,
-                   const double* v, double* w, long ws) {
+                   const double* const* v, double* const* w, int count, long ws) {
   const int x = c->chi_env, Dl = c->Dl;
-  GemmBatch g = gb1(Dl * x, Dl * x, x, T1, (long)Dl * x, 1, v, (long)Dl * x, c->S1[0], 0);
+  GemmBatch g = gemm_rowmajor(count, Dl * x, Dl * x, x, (long)Dl * x, (long)Dl * x, 0);
+  for (int i = 0; i < count; ++i) {
+    g.A[i] = T1;
+    g.transA[i] = 1;
+    g.B[i] = v[i];
+    g.C[i] = c->S1[i];
+  }
   set_map(g, x, Dl, (long)x * Dl * Dl, x, 1, (long)Dl * Dl);
   TRY(g64(c, g));
-  g = gb1(x * x, Dl * Dl, Dl * Dl, c->S1[0], (long)Dl * Dl, 0, a, (long)Dl * Dl, c->S2[0], 0);
+  g = gemm_rowmajor(count, x * x, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
+  for (int i = 0; i < count; ++i) {
+    g.A[i] = c->S1[i];
+    g.B[i] = a;
+    g.C[i] = c->S2[i];
+  }
   set_map(g, x, Dl, (long)x * Dl, Dl, (long)x * x * Dl, 1);
   TRY(g64(c, g));
-  g = gb1(x, x * Dl, Dl * x, T3, (long)Dl * x, 0, c->S2[0], (long)x * Dl, w, 0);
+  g = gemm_rowmajor(count, x, x * Dl, Dl * x, (long)Dl * x, (long)x * Dl, 0);
+  for (int i = 0; i < count; ++i) {
+    g.A[i] = T3;
+    g.B[i] = c->S2[i];
+    g.C[i] = w[i];
+  }
   set_map(g, 1 << 30, 0, ws, 1 << 30, 0, (long)x * ws);
   return g64(c, g);
 }
@@ -1492,8 +1509,16 @@ int correlation_length(ctm_ctx* c, bool vertical, int iters, double* out_host) {
     TRY(launch_qr(1, Wp, (int)nE, mm, c->xi_qr, c->st) ? fail(c, CTM_E_DEVICE, thread_error()) : 0);
     CTM_HIP_TRY(hipMemcpyAsync(c->xi_V, c->xi_W, (size_t)nE * mm * 8, hipMemcpyDeviceToDevice, c->st));
     TRY(elem_transpose(c->xi_V, c->xi_Vc, nE, mm, c->st));
-    for (int k = 0; k < mm; ++k)
-      TRY(transfer_apply(c, T1, T3, a, c->xi_Vc + (long)k * nE, c->xi_W + k, mm));
+    for (int k0 = 0; k0 < mm; k0 += 4) {
+      const int cnt = std::min(4, mm - k0);
+      const double* vs[4];
+      double* ws[4];
+      for (int i = 0; i < cnt; ++i) {
+        vs[i] = c->xi_Vc + (long)(k0 + i) * nE;
+        ws[i] = c->xi_W + k0 + i;
+      }
+      TRY(transfer_apply(c, T1, T3, a, vs, ws, cnt, mm));
+    }
   }
   // H = V^T (E V)
   TRY(g64(c, gb1(mm, mm, (int)nE, c->xi_V, mm, 1, c->xi_W, mm, c->xi_H, mm)));
