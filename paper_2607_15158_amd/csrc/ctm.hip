@@ -1520,8 +1520,16 @@ int correlation_length(ctm_ctx* c, bool vertical, int iters, double* out_host) {
       TRY(transfer_apply(c, T1, T3, a, vs, ws, cnt, mm));
     }
   }
-  // H = V^T (E V)
-  TRY(g64(c, gb1(mm, mm, (int)nE, c->xi_V, mm, 1, c->xi_W, mm, c->xi_H, mm)));
+  // H = V^T (E V): mm^2 dot products over nE between the columns of V
+  // (contiguous in Vc) and of W (transposed into V, no longer needed)
+  TRY(elem_transpose(c->xi_W, c->xi_V, nE, mm, c->st));
+  {
+    const double* wc[kXiBlock];
+    for (int j = 0; j < mm; ++j) wc[j] = c->xi_V + (long)j * nE;
+    for (int i = 0; i < mm; ++i)
+      TRY(elem_dots(c->xi_Vc + (long)i * nE, wc, mm, nE, c->dot_part, c->xi_H + (long)i * mm, c->st)
+              ? fail(c, CTM_E_ARG, "dot products") : 0);
+  }
   TRY(elem_xi_from_ritz(c->xi_H, mm, 60, c->xi_out, c->st) ? fail(c, CTM_E_ARG, "small eigenproblem") : 0);
   CTM_HIP_TRY(hipMemcpyAsync(out_host, c->xi_out, 3 * 8, hipMemcpyDeviceToHost, c->st));
   CTM_HIP_TRY(hipStreamSynchronize(c->st));

@@ -1469,7 +1469,7 @@ struct EBufs {
   int n;                                   // d^2 open-leg pairs (ket s, bra t)
   double *L0, *left, *R1, *Y1, *W1, *W1p, *R0, *right;
   std::vector<double*> xs, xb, x2p, Y2p, W2p;
-  double *Y3s, *W3s, *W3sT, *E, *Eb;
+  double *Y3s, *W3s, *E, *Eb;
   double *Y3b, *W3b, *T3Tb, *Y1b, *R1b, *leftb, *L0b, *W1pb, *W1b, *rightb, *R0b;
   double *Ta, *Tb, *Tc, *St;
   double *Ar, *Abr, *mopen;
@@ -1510,7 +1510,6 @@ size_t ecarve(const Dims& m, EBufs* b, char* base, std::vector<std::pair<uintptr
   }
   b->Y3s = cv.take(n * L);
   b->W3s = cv.take(n * L);
-  b->W3sT = cv.take(n * L);
   b->E = cv.take(n * n);
   b->Eb = cv.take(n * n);
   b->Y3b = cv.take(n * L);
@@ -1587,8 +1586,15 @@ int echain_fwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const do
     VTRY(gather(r, b.Ta, b.W2p[st], x, Dl, x, Dl, (long)x * D2, Dl, D2, 1));                  // [(g,m)][(f,y)]
     VTRY(gemm(r, one(x * Dl, x, x * Dl, b.W2p[st], (long)x * Dl, 0, T[2], x, b.W3s + st * L, x)));
   }
-  VTRY(transpose(r, b.W3s, b.W3sT, n, L));
-  VTRY(gemm(r, one(n, n, (int)L, b.Y3s, L, 0, b.W3sT, n, b.E, n)));
+  // E[i, j] = <Y3_i, W3_j>: n^2 dot products over L = x Dl x, spread over the
+  // chip (a GEMM with an n x n result would run on one workgroup)
+  const double* w3[kMaxDots];
+  if (n > kMaxDots) return r.fail("energy chain: more open-leg pairs than supported");
+  for (int j = 0; j < n; ++j) w3[j] = b.W3s + j * L;
+  for (int i = 0; i < n; ++i) {
+    const int rc = elem_dots(b.Y3s + i * L, w3, n, L, b.pDots, b.E + i * n, r.st);
+    if (rc) return vjp_fail(r.c, rc == 1 ? CTM_E_ARG : rc, thread_error());
+  }
   return 0;
 }
 
