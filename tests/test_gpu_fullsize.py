@@ -70,3 +70,46 @@ def test_full_size_si_move_matches_oracle():
         ey = rel(st["Yt"][b][:, :chi], Ytn[b][:, :chi])
         print(f"bond {b}: recycled X err {ex:.2e}, Y^T err {ey:.2e}")
         assert ex <= 1e-9 and ey <= 1e-9
+
+
+def test_full_size_triangular_energy_gradient_directional_differences():
+    """D=6, chi=144 (N = 5184): at an environment converged by SI moves
+    (randomized growth), the energy of the triangular lattice (h + v + d)
+    returned with its gradient equals the sum of the three bond observables,
+    and the corner and edge cotangents match central differences of that
+    sum along seeded random directions."""
+    import paper_2607_15158_amd as P
+    D, chi = 6, 144
+    cfg = P.Config(d=2, D=D, chi=chi, p=16, n_si=2, growth="si")
+    A = S.product_plus_noise_site(2, D, 9, noise=0.2)
+    ctx = P.Ctm(cfg, torch.from_numpy(A).cuda())
+    print("converge", ctx.converge(1e-6, 40), flush=True)
+    st = ctx.unpack_state(ctx.get_state())
+    C, T, X, Y = st["C"], st["T"], st["X"], st["Yt"]
+    rng = np.random.default_rng(12)
+    h = S.heisenberg_bond()
+    kinds = (P.OBS_BOND_H, P.OBS_BOND_V, P.OBS_BOND_D)
+
+    def energy(C_, T_):
+        ctx.set_state(ctx.pack_state(C_, T_, X, Y))
+        return sum(ctx.observable(k, h)[0] for k in kinds)
+
+    e_obs = energy(C, T)
+    state = torch.from_numpy(ctx.pack_state(C, T, X, Y))
+    e, bar, _ = ctx.energy_vjp(state, h, bonds="hvd")
+    assert abs(e - e_obs) <= 1e-11 * max(1.0, abs(e_obs)), (e, e_obs)
+    b = bar.cpu().numpy()
+    b[-4] = chi
+    g = ctx.unpack_state(b)
+    for group in ("C", "T"):
+        dirs = [rng.standard_normal(x.shape) for x in (C if group == "C" else T)]
+        hh = 1e-6
+        if group == "C":
+            fd = (energy([c + hh * d for c, d in zip(C, dirs)], T) -
+                  energy([c - hh * d for c, d in zip(C, dirs)], T)) / (2 * hh)
+        else:
+            fd = (energy(C, [t + hh * d for t, d in zip(T, dirs)]) -
+                  energy(C, [t - hh * d for t, d in zip(T, dirs)])) / (2 * hh)
+        an = sum(float((gg * d).sum()) for gg, d in zip(g[group], dirs))
+        print(group, fd, an, flush=True)
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3), (group, fd, an)
