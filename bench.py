@@ -209,6 +209,9 @@ def main():
     ap.add_argument("--vjp", type=int, default=3,
                     help="time this many adjoints of the move (ctm_move_vjp) at the state after "
                          "the timed moves (0: skip)")
+    ap.add_argument("--opt-triangular", action="store_true",
+                    help="optimisation step on the triangular-lattice energy (spiral ansatz, "
+                         "h + v + diagonal) instead of the square-lattice h + v")
     ap.add_argument("--xi-iters", type=int, default=30,
                     help="block iterations of the correlation-length observable")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
@@ -387,11 +390,18 @@ def main():
         At = torch.from_numpy(A).to(dev).requires_grad_(True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        e_opt = P.unrolled_energy(At, cfg, S.heisenberg_bond(), st0, args.opt_moves)
+        if args.opt_triangular:
+            th = 2 * np.pi / 3
+            op_opt = P.spiral_bond_operators(S.heisenberg_bond(), {"h": th, "v": th, "d": 2 * th})
+        else:
+            op_opt = S.heisenberg_bond()
+        e_opt = P.unrolled_energy(At, cfg, op_opt, st0, args.opt_moves)
         e_opt.backward()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         opt = {"moves": args.opt_moves, "seconds": round(dt, 3),
+               "energy": ("triangular lattice, spiral ansatz: h + v + d with rotated bond operators"
+                          if args.opt_triangular else "square lattice: h + v"),
                "what": "energy after the moves and its gradient wrt the site tensor (unrolled "
                        "adjoint, checkpoints at move boundaries, moves recomputed in reverse)"}
         log(f"optimisation step ({args.opt_moves} unrolled moves, forward + backward): {dt:.2f} s")

@@ -473,7 +473,9 @@ def converged_energy(A, cfg: Config, op, X0, Yt0, tol: float = 1e-12, max_moves:
 
 
 def unrolled_energy(A, cfg: Config, op, state0, moves: int, bonds: str = "hv"):
-    """Energy (the sum of <op> over ``bonds``) after ``moves`` SI moves from ``state0`` (a
+    """Energy (the sum of <op> over ``bonds``, or with ``op`` a dict {bond
+    letter: operator} the sum of each bond's own operator) after ``moves`` SI
+    moves from ``state0`` (a
     float64 device tensor in the state layout, chi_env == chi), differentiable
     with respect to the site tensor ``A`` by unrolling: the forward pass keeps
     the state at every move boundary on the device (checkpoints), the
@@ -491,7 +493,14 @@ def unrolled_energy(A, cfg: Config, op, state0, moves: int, bonds: str = "hv"):
             for _ in range(moves):
                 c.move()
                 states.append(c.get_state_device())
-            e, bar, site_bar = c.energy_vjp(states[-1], op, bonds=bonds)
+            if isinstance(op, dict):
+                e, bar, site_bar = 0.0, None, None
+                for bd, opb in op.items():
+                    eb, bb, site_bar = c.energy_vjp(states[-1], opb, site_bar, bonds=bd)
+                    e += eb
+                    bar = bb if bar is None else bar + bb
+            else:
+                e, bar, site_bar = c.energy_vjp(states[-1], op, bonds=bonds)
             for st in reversed(states[:-1]):
                 bar, _, site_bar = c.move_vjp(st, bar, want_out=False, site_bar=site_bar)
             ctx.save_for_backward(site_bar)
