@@ -202,16 +202,17 @@ def main():
                     help="> 0: also time SI and full-SVD environments from the same start until "
                          "delta < this (each from its own growth move)")
     ap.add_argument("--converge-max", type=int, default=120)
-    ap.add_argument("--opt-moves", type=int, default=0,
+    ap.add_argument("--opt-moves", type=int, default=10,
                     help="> 0: time one optimisation step (the energy after this many SI moves "
                          "from the state after the timed moves, and its site-tensor gradient by "
                          "the unrolled adjoint with move-boundary checkpoints)")
     ap.add_argument("--vjp", type=int, default=3,
                     help="time this many adjoints of the move (ctm_move_vjp) at the state after "
                          "the timed moves (0: skip)")
-    ap.add_argument("--opt-triangular", action="store_true",
-                    help="optimisation step on the triangular-lattice energy (spiral ansatz, "
-                         "h + v + diagonal) instead of the square-lattice h + v")
+    ap.add_argument("--opt-energy", default="triangular", choices=["triangular", "square"],
+                    help="energy of the optimisation step: the triangular lattice (spiral "
+                         "ansatz, h + v + diagonal; the paper's workload) or the square "
+                         "lattice's h + v")
     ap.add_argument("--xi-iters", type=int, default=30,
                     help="block iterations of the correlation-length observable")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
@@ -390,7 +391,7 @@ def main():
         At = torch.from_numpy(A).to(dev).requires_grad_(True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        if args.opt_triangular:
+        if args.opt_energy == "triangular":
             th = 2 * np.pi / 3
             op_opt = P.spiral_bond_operators(S.heisenberg_bond(), {"h": th, "v": th, "d": 2 * th})
         else:
@@ -401,7 +402,7 @@ def main():
         dt = time.perf_counter() - t1
         opt = {"moves": args.opt_moves, "seconds": round(dt, 3),
                "energy": ("triangular lattice, spiral ansatz: h + v + d with rotated bond operators"
-                          if args.opt_triangular else "square lattice: h + v"),
+                          if args.opt_energy == "triangular" else "square lattice: h + v"),
                "what": "energy after the moves and its gradient wrt the site tensor (unrolled "
                        "adjoint, checkpoints at move boundaries, moves recomputed in reverse)"}
         log(f"optimisation step ({args.opt_moves} unrolled moves, forward + backward): {dt:.2f} s")
