@@ -213,6 +213,8 @@ def main():
                     help="energy of the optimisation step: the triangular lattice (spiral "
                          "ansatz, h + v + diagonal; the paper's workload) or the square "
                          "lattice's h + v")
+    ap.add_argument("--no-obs", action="store_true",
+                    help="skip the observables (bond values, correlation lengths)")
     ap.add_argument("--xi-iters", type=int, default=30,
                     help="block iterations of the correlation-length observable")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
@@ -363,7 +365,7 @@ def main():
             f"diagonal, the triangular lattice)")
 
     obs = None
-    if args.prec == "f64":
+    if args.prec == "f64" and not args.no_obs:
         import synth as S
         h = S.heisenberg_bond()
         kinds = (("bond_h", P.OBS_BOND_H), ("bond_v", P.OBS_BOND_V), ("bond_d", P.OBS_BOND_D))
