@@ -1475,9 +1475,10 @@ struct EBufs {
   double *Ar, *Abr, *mopen;
   // diagonal pair (plaquette): stacks of n N x N matrices, then N x N scratch
   double *pCt0, *pCt2, *pY, *pZt, *pCt0b;
-  double *pCt1, *pCt3, *pCt1b, *pCt3b, *pH, *pCt2b, *pP, *pRb;
+  double *pCt1, *pCt3, *pCt1b, *pCt3b, *pH, *pCt2b, *pRb;
   double *pW[4], *pWb[4], *pCT[4], *pCTb, *pCTt, *pTt;
-  double *pSite, *pSiteT, *pSiteB, *pA, *pAb, *pDots;
+  double *pSite, *pA, *pAb, *pDots;
+  double *pSiteS, *pSiteTS, *pSiteBS;     // per open pair (n of them, or 2)
 };
 
 size_t ecarve(const Dims& m, EBufs* b, char* base, std::vector<std::pair<uintptr_t, uintptr_t>>* reg) {
@@ -1535,7 +1536,7 @@ size_t ecarve(const Dims& m, EBufs* b, char* base, std::vector<std::pair<uintptr
   b->pY = cv.take(n * NN);
   b->pZt = cv.take(n * NN);
   b->pCt0b = cv.take(n * NN);
-  for (double** q : {&b->pCt1, &b->pCt3, &b->pCt1b, &b->pCt3b, &b->pH, &b->pCt2b, &b->pP, &b->pRb})
+  for (double** q : {&b->pCt1, &b->pCt3, &b->pCt1b, &b->pCt3b, &b->pH, &b->pCt2b, &b->pRb})
     *q = cv.take(NN);
   for (int i = 0; i < 4; ++i) {
     b->pW[i] = cv.take(NN);
@@ -1545,8 +1546,12 @@ size_t ecarve(const Dims& m, EBufs* b, char* base, std::vector<std::pair<uintptr
   b->pCTb = cv.take(L);
   b->pCTt = cv.take(L);
   b->pTt = cv.take(L);
-  for (double** q : {&b->pSite, &b->pSiteT, &b->pSiteB, &b->pA, &b->pAb}) *q = cv.take(Dl4);
+  for (double** q : {&b->pSite, &b->pA, &b->pAb}) *q = cv.take(Dl4);
   b->pDots = cv.take((size_t)kMaxDots * kDotBlocks);
+  const size_t ns = (size_t)std::max(n, 2);
+  b->pSiteS = cv.take(ns * Dl4);
+  b->pSiteTS = cv.take(ns * Dl4);
+  b->pSiteBS = cv.take(ns * Dl4);
   return cv.off + 256;
 }
 
@@ -1609,13 +1614,27 @@ int echain_bwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const do
   VTRY(fill(r, b.T3Tb, L, 0.0));
   VTRY(fill(r, b.Y1b, NN, 0.0));
   VTRY(fill(r, b.W1pb, NN, 0.0));
+  // Y2b of every open pair into the plaquette stack (idle here), then the
+  // D2 x D2 x (x x) products xb += Y1^T Y2b batched over the pairs
   for (int st = 0; st < n; ++st) {
+    double* y2b = b.pCt2 + st * NN;
     VTRY(gemm(r, one(x * Dl, Dl * x, x, b.Y3b + st * L, x, 0, T[2], (long)Dl * x, b.Ta, (long)Dl * x)));
     VTRY(gemm(r, one(Dl * x, x, x * Dl, b.Y2p[st], (long)Dl * x, 1, b.Y3b + st * L, x, b.T3Tb, x, true)));
-    VTRY(gather(r, b.Ta, b.Tb, x, x, Dl, Dl, 1, D2 * x, x, (long)Dl * x));                    // Y2b [(j,g)][(d,m)]
+    VTRY(gather(r, b.Ta, y2b, x, x, Dl, Dl, 1, D2 * x, x, (long)Dl * x));                     // Y2b [(j,g)][(d,m)]
     VTRY(transpose(r, b.xs[st], b.Tc, D2, D2));
-    VTRY(gemm(r, one(x * x, D2, D2, b.Tb, D2, 0, b.Tc, D2, b.Y1b, D2, true)));
-    VTRY(gemm(r, one(D2, D2, x * x, b.Y1, D2, 1, b.Tb, D2, b.xb[st], D2, true)));
+    VTRY(gemm(r, one(x * x, D2, D2, y2b, D2, 0, b.Tc, D2, b.Y1b, D2, true)));
+  }
+  for (int s0 = 0; s0 < n; s0 += kMaxProb) {
+    const int cnt = std::min(kMaxProb, n - s0);
+    GemmBatch g = rowmajor(cnt, (int)D2, (int)D2, x * x, D2, D2, D2);
+    g.accumulate = 1;
+    for (int i = 0; i < cnt; ++i) {
+      g.A[i] = b.Y1;
+      g.transA[i] = 1;
+      g.B[i] = b.pCt2 + (s0 + i) * NN;
+      g.C[i] = b.xb[s0 + i];
+    }
+    VTRY(gemm(r, g));
   }
   VTRY(gather(r, b.T3Tb, Tb[2], 1, 1, x, (int)(Dl * x), 0, 0, 1, x, true));                    // += T3Tb^T
   VTRY(gather(r, b.Y1b, b.R1b, x, Dl, Dl, x, (long)x * D2, 1, Dl, D2));                       // [(j,l)][(u,g)]
@@ -1631,14 +1650,27 @@ int echain_bwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const do
   // w chain
   VTRY(transpose(r, T[2], b.St, (long)x * Dl, x));                                            // [i][(f,y)]
   for (int st = 0; st < n; ++st) {
+    double* w2b = b.pCt2 + st * NN;
     VTRY(gemm(r, one(x * Dl, x * Dl, x, b.W3b + st * L, x, 0, b.St, (long)x * Dl, b.Ta, (long)x * Dl)));
     VTRY(gemm(r, one(x * Dl, x, x * Dl, b.W2p[st], (long)x * Dl, 1, b.W3b + st * L, x, Tb[2], x, true)));
-    VTRY(gather(r, b.Ta, b.Tb, x, x, Dl, Dl, D2 * x, Dl, (long)x * Dl, 1));                   // W2b [(g,f)][(m,y)]
+    VTRY(gather(r, b.Ta, w2b, x, x, Dl, Dl, D2 * x, Dl, (long)x * Dl, 1));                    // W2b [(g,f)][(m,y)]
     VTRY(transpose(r, b.x2p[st], b.Tc, D2, D2));
-    VTRY(gemm(r, one(x * x, D2, D2, b.Tb, D2, 0, b.Tc, D2, b.W1pb, D2, true)));
-    VTRY(gemm(r, one(D2, D2, x * x, b.W1p, D2, 1, b.Tb, D2, b.Ta, D2)));                      // x2p_bar
-    VTRY(gather(r, b.Ta, b.xb[st], Dl, Dl, Dl, Dl, D2 * Dl, Dl, 1, D2, true));
+    VTRY(gemm(r, one(x * x, D2, D2, w2b, D2, 0, b.Tc, D2, b.W1pb, D2, true)));
   }
+  // x2p_bar of every pair (D2 x D2 x (x x), batched), then into xb
+  for (int s0 = 0; s0 < n; s0 += kMaxProb) {
+    const int cnt = std::min(kMaxProb, n - s0);
+    GemmBatch g = rowmajor(cnt, (int)D2, (int)D2, x * x, D2, D2, D2);
+    for (int i = 0; i < cnt; ++i) {
+      g.A[i] = b.W1p;
+      g.transA[i] = 1;
+      g.B[i] = b.pCt2 + (s0 + i) * NN;
+      g.C[i] = b.pCt0 + (s0 + i) * NN;
+    }
+    VTRY(gemm(r, g));
+  }
+  for (int st = 0; st < n; ++st)
+    VTRY(gather(r, b.pCt0 + st * NN, b.xb[st], Dl, Dl, Dl, Dl, D2 * Dl, Dl, 1, D2, true));
   VTRY(gather(r, b.W1pb, b.W1b, x, Dl, Dl, x, (long)x * D2, Dl, 1, D2));                      // [(g,v)][(w,f)]
   VTRY(transpose(r, b.right, b.St, x, (long)Dl * x));
   VTRY(gemm(r, one(x * Dl, x, Dl * x, b.W1b, (long)Dl * x, 0, b.St, x, Tb[0], x, true)));
@@ -1914,22 +1946,47 @@ int pq_fwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const double
   return 0;
 }
 
-// Reverse pass of the site absorption of corner k with cotangent Ctb of the
-// corner: pWb[k] += P site^T and xbar += (W^T P) in a-layout, with P the
-// cotangent regrouped as [(x_in, y), (o1, o2)].
-int pq_absorb_bwd(Run& r, const Dims& m, EBufs& b, int k, const double* Ctb, const double* xs,
-                  double* xbar) {
+// Reverse pass of the site absorptions of `cnt` corner instances: corner
+// ks[i] with site tensor xs[i] (a-layout) and its cotangent regrouped as
+// P_i[(x_in, y), (o1, o2)] (at b.pCt0 + i NN): pWb[ks[i]] += P_i site_i^T,
+// and xbar[i] += (W^T P_i) returned to the a-layout; the W^T P products (a
+// D2 x D2 result over K = x^2) run batched.
+int pq_absorb_bwd(Run& r, const Dims& m, EBufs& b, const int* ks, const double* const* xs,
+                  double* const* xbar, int cnt) {
   const int x = m.x, Dl = m.Dl;
-  const long N = m.N, D2 = (long)Dl * Dl;
-  VTRY(gather(r, Ctb, b.pP, x, x, Dl, Dl, (long)Dl * N, Dl, N, 1));
-  VTRY(pq_site(r, m, k, xs, b.pSite));
-  VTRY(transpose(r, b.pSite, b.pSiteT, D2, D2));
-  VTRY(gemm(r, one(x * x, (int)D2, (int)D2, b.pP, D2, 0, b.pSiteT, D2, b.pWb[k], D2, true)));
-  VTRY(gemm(r, one((int)D2, (int)D2, x * x, b.pW[k], D2, 1, b.pP, D2, b.pSiteB, D2)));
+  const long NN = (long)m.N * m.N, D2 = (long)Dl * Dl, Dl4 = D2 * D2;
+  for (int i = 0; i < cnt; ++i) {
+    double* site = b.pSiteS + i * Dl4;
+    VTRY(pq_site(r, m, ks[i], xs[i], site));
+    VTRY(transpose(r, site, b.pSiteTS + i * Dl4, D2, D2));
+    VTRY(gemm(r, one(x * x, (int)D2, (int)D2, b.pCt0 + i * NN, D2, 0, b.pSiteTS + i * Dl4, D2,
+                     b.pWb[ks[i]], D2, true)));
+  }
+  for (int s0 = 0; s0 < cnt; s0 += kMaxProb) {
+    const int c = std::min(kMaxProb, cnt - s0);
+    GemmBatch g = rowmajor(c, (int)D2, (int)D2, x * x, D2, D2, D2);
+    for (int i = 0; i < c; ++i) {
+      g.A[i] = b.pW[ks[s0 + i]];
+      g.transA[i] = 1;
+      g.B[i] = b.pCt0 + (s0 + i) * NN;
+      g.C[i] = b.pSiteBS + (s0 + i) * Dl4;
+    }
+    VTRY(gemm(r, g));
+  }
   // xbar[u, l, d, r] += siteB[i0..i3] where leg j of the site carries a-leg kPerm[k][j]
-  long st[4];
-  for (int j = 0; j < 4; ++j) st[3 - kPerm[k][j]] = dl_pow(Dl, 3 - j);
-  return gather(r, b.pSiteB, xbar, Dl, Dl, Dl, Dl, st[0], st[1], st[2], st[3], true);
+  for (int i = 0; i < cnt; ++i) {
+    long st[4];
+    for (int j = 0; j < 4; ++j) st[3 - kPerm[ks[i]][j]] = dl_pow(Dl, 3 - j);
+    VTRY(gather(r, b.pSiteBS + i * Dl4, xbar[i], Dl, Dl, Dl, Dl, st[0], st[1], st[2], st[3], true));
+  }
+  return 0;
+}
+
+// P[(x_in, y), (o1, o2)] = Ctb[(x_in, o1), (y, o2)]
+int pq_regroup(Run& r, const Dims& m, const double* Ctb, double* P) {
+  const int x = m.x, Dl = m.Dl;
+  const long N = m.N;
+  return gather(r, Ctb, P, x, x, Dl, Dl, (long)Dl * N, Dl, N, 1);
 }
 
 // Reverse pass from b.Eb: accumulates into Cb, Tb (slots as C, T) and b.xb.
@@ -1944,7 +2001,12 @@ int pq_bwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const double
   // Ct0b_i = sum_j Eb[i, j] Zt_j;  G_j = sum_i Eb[i, j] Ct0_i (into the Zt stack)
   VTRY(gemm(r, one(n, (int)NN, n, b.Eb, n, 0, b.pZt, NN, b.pCt0b, NN)));
   VTRY(gemm(r, one(n, (int)NN, n, b.Eb, n, 1, b.pCt0, NN, b.pZt, NN)));
-  for (int i = 0; i < n; ++i) VTRY(pq_absorb_bwd(r, m, b, 0, b.pCt0b + i * NN, b.xs[i], b.xb[i]));
+  int ks[kMaxDots];
+  for (int i = 0; i < n; ++i) {                 // the Ct0 stack is free from here on
+    VTRY(pq_regroup(r, m, b.pCt0b + i * NN, b.pCt0 + i * NN));
+    ks[i] = 0;
+  }
+  VTRY(pq_absorb_bwd(r, m, b, ks, b.xs.data(), b.xb.data(), n));
   for (int j = 0; j < n; ++j) {
     const double* G = b.pZt + j * NN;       // cotangent of Zt_j = (Y_j Ct3)^T
     const double* c2 = b.pCt2 + j * NN;
@@ -1960,10 +2022,18 @@ int pq_bwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const double
     g = one((int)N, (int)N, (int)N, b.pH, N, 0, b.pCt1, N, b.pCt2b, 0);            // (H Ct1)^T
     transposed_out(g, N);
     VTRY(gemm(r, g));
-    VTRY(pq_absorb_bwd(r, m, b, 2, b.pCt2b, b.xs[j], b.xb[j]));
+    VTRY(pq_regroup(r, m, b.pCt2b, b.pCt0 + j * NN));
   }
-  VTRY(pq_absorb_bwd(r, m, b, 1, b.pCt1b, b.pA, b.pAb));
-  VTRY(pq_absorb_bwd(r, m, b, 3, b.pCt3b, b.pA, b.pAb));
+  for (int j = 0; j < n; ++j) ks[j] = 2;
+  VTRY(pq_absorb_bwd(r, m, b, ks, b.xs.data(), b.xb.data(), n));
+  {
+    VTRY(pq_regroup(r, m, b.pCt1b, b.pCt0));
+    VTRY(pq_regroup(r, m, b.pCt3b, b.pCt0 + NN));
+    const int kc[2] = {1, 3};
+    const double* xa[2] = {b.pA, b.pA};
+    double* xab[2] = {b.pAb, b.pAb};
+    VTRY(pq_absorb_bwd(r, m, b, kc, xa, xab, 2));
+  }
   for (int s = 0; s < m.d; ++s)
     VTRY(gather(r, b.pAb, b.xb[s * m.d + s], Dl, Dl, Dl, Dl, (long)Dl * Dl * Dl, (long)Dl * Dl, Dl, 1,
                 true));
