@@ -234,6 +234,32 @@ def test_gradient_of_the_converged_energy_matches_finite_differences(bonds):
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3), (trial, fd, an)
 
 
+def test_bond_energy_gradient_with_three_level_sites():
+    """d = 3 (nine open-leg pairs: the batched products run in two launches
+    of eight and one): energy h + v + d against the autograd reference."""
+    D, chi, d = 2, 4, 3
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((d, D, D, D, D))
+    Dl = D * D
+    C = [S.gaussian_block(chi, chi, 60 + i) for i in range(4)]
+    T = [S.gaussian_block(chi * Dl, chi, 70 + i).reshape(chi, Dl, chi) for i in range(4)]
+    cfg = P.Config(d=d, D=D, chi=chi, p=4, n_si=2)
+    X = np.stack([S.gaussian_block(cfg.N, cfg.k, 20 + b) for b in range(4)])
+    ctx = P.Ctm(cfg, torch.from_numpy(A).to(torch.device("cuda", 0)))
+    state = torch.from_numpy(ctx.pack_state(C, T, X, X))
+    op = rng.standard_normal((d * d, d * d))
+    e, bar, site_bar = ctx.energy_vjp(state, op, bonds="hvd")
+    ref_e, gC, gT, gA = J.energy_vjp(C, T, A, op, "hvd")
+    assert abs(e - ref_e) <= 1e-12 * max(1.0, abs(ref_e))
+    b = bar.cpu().numpy()
+    b[-4] = chi
+    g = ctx.unpack_state(b)
+    errs = {"C": max(rel(a, r) for a, r in zip(g["C"], gC)),
+            "T": max(rel(a, r) for a, r in zip(g["T"], gT)),
+            "A": rel(site_bar.cpu().numpy(), gA)}
+    assert all(v <= 1e-10 for v in errs.values()), errs
+
+
 def spiral_ops():
     th = 2 * np.pi / 3
     return P.spiral_bond_operators(S.heisenberg_bond(), {"h": th, "v": th, "d": 2 * th})

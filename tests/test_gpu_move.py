@@ -331,6 +331,24 @@ def test_correlation_length_matches_oracle(D, chi):
         assert abs(xi - xo) <= 1e-8 * xo, (direction, xi, xo)
 
 
+def test_correlation_length_of_a_classical_network_matches_oracle():
+    """d = 0 (the Ising network given directly): xi of both transfer
+    matrices of the converged environment against the oracle's dense
+    eigenvalues of the same transfer matrices."""
+    beta, chi = 0.35, 12
+    a, e = S.ising_site(beta), S.ising_boundary(beta)
+    cfg = P.Config(d=0, D=2, chi=chi, p=4, n_si=2)
+    ctx, _ = make(cfg, a, e)
+    ctx.converge(1e-12, 300)
+    st = ctx.unpack_state(ctx.get_state())
+    env = O.Env(st["C"], st["T"])
+    for direction in "hv":
+        xi, r2 = ctx.correlation_length(direction, iters=200)
+        xo, ro = O.correlation_length(env, a, direction)
+        assert abs(r2 - ro[1]) <= 1e-9 * ro[1], (direction, r2, ro[1])
+        assert abs(xi - xo) <= 1e-8 * xo, (direction, xi, xo)
+
+
 @pytest.mark.parametrize("rows", [True, False])
 def test_correlation_length_of_uncoupled_chains_on_gpu(rows):
     """A stack of independent MPS rows (columns): along the chains xi is the
