@@ -463,7 +463,8 @@ def test_f32_si_move_matches_oracle():
 def test_c4v_ising_closed_forms_on_gpu(proj):
     """The C4v mode (one symmetric corner and edge, isometric projector)
     reproduces Onsager's free energy, Yang's magnetisation and the exact
-    nearest-neighbour correlation of the 2D Ising model at beta = 0.5."""
+    nearest-neighbour and diagonal correlations of the 2D Ising model at
+    beta = 0.5, and equal correlation lengths in the two directions."""
     beta, chi = 0.5, 16
     a, asig, e = S.ising_site(beta), S.ising_impurity(beta), S.ising_boundary(beta)
     cfg = P.Config(d=0, D=2, chi=chi, p=8, n_si=2, proj=proj, sym="c4v")
@@ -476,6 +477,12 @@ def test_c4v_ising_closed_forms_on_gpu(proj):
     two = np.concatenate([asig.ravel(), asig.ravel()])
     for kind in (P.OBS_BOND_H, P.OBS_BOND_V):
         assert abs(ctx.observable(kind, two)[0] - gold(beta, "nn_correlation")) <= 1e-9
+    for kind in (P.OBS_BOND_D, P.OBS_BOND_AD):
+        assert abs(ctx.observable(kind, two)[0] - gold(beta, "diag_correlation")) <= 1e-9
+    # one symmetric environment: the two transfer matrices have one spectrum
+    xh, _ = ctx.correlation_length("h", iters=150)
+    xv, _ = ctx.correlation_length("v", iters=150)
+    assert abs(xh - xv) <= 1e-8 * xh, (xh, xv)
 
 
 @pytest.mark.parametrize("proj", ["si", "svd"])
