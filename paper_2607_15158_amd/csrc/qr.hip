@@ -11,10 +11,10 @@
 //    (H_0...H_(w-1) = I - V T V^T) and updates its trailing columns with
 //    C <- C - V T^T (V^T C), three small GEMMs on the FP64 matrix cores;
 //  * the w x w triangles the leaves leave in their top rows are combined
-//    pairwise up a binary tree; combining two upper triangles gives
-//    reflectors [e_j; v] with v upper triangular, stored in the place of the
-//    absorbed triangle, and their own WY factor updates the trailing columns
-//    of the node's 2w rows;
+//    four at a time up a reduction tree (depth log4 of the leaf count);
+//    combining stacked upper triangles gives reflectors [e_j; v] with v
+//    upper triangular in each absorbed triangle, stored in its place, and
+//    their own WY factor updates the trailing columns of the node's rows;
 //  * Q = prod_p L_p T_p [I; 0] is then formed by applying the tree and leaf
 //    WY factors (C <- C - V T (V^T C)) in reverse order to [I_k; 0], on the
 //    columns that can be non-trivial, and each column c is multiplied by
@@ -32,7 +32,6 @@ constexpr int kPanel = 32;
 constexpr int kLeafRows = 192;   // three rows per lane of one wavefront
 constexpr int kLR = kLeafRows + 1;   // odd row length: fragment reads hit distinct banks
 constexpr int kT = kPanel + 1;   // padded row length of the small LDS matrices
-constexpr int kTrail = 64;       // trailing columns per LDS chunk in the tree kernels
 
 struct QrPlan {
   int N, k, nb, P, depth;
@@ -324,84 +323,115 @@ __device__ __forceinline__ int top_row(int leaf, int c0, int N, int nb) {
 }
 
 // ---------------------------------------------------------------------------
-// tree combine at level L of panel p: node = right child b, left child b-2^L.
-// Wavefront 0 factors [Ra; Rb] (lanes 0..31 hold the rows of Ra, lanes
-// 32..63 those of Rb); the reflectors are [e_j; v_j] with v_j stored in the
-// upper triangle of Rb.
+// Reduction tree: a node at stride s combines the triangles of the leaves
+// a, a + s, ..., a + (kArity - 1) s (those below nb), a = node * s * kArity;
+// the first child keeps R, the others receive the reflector parts.  Row
+// (lane + 64 r) of the node's wavefront is row (lane & 31) of child
+// (lane >> 5) + 2 r.  The node's WY factor is stored in the slot of child 1,
+// s (4 i + 1), which no other node at any stride shares.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int L) {
-  __shared__ double Rb[kPanel][kT];
+constexpr int kArity = 4;
+constexpr int kNodeRPL = kArity / 2;
+constexpr int kTrailN = 32;   // trailing columns per LDS chunk in the tree kernels
+
+__device__ __forceinline__ int node_children(int a, int s, int nb) {
+  return min(kArity, (nb - a + s - 1) / s);
+}
+
+// Wavefront 0 factors the stacked triangles [R_0; R_1; ...]; the reflectors
+// are [e_j; v_j] with v_j in the upper triangles of the children after the
+// first.  Trailing columns [c0 + w, k) of the node's rows:
+// W1 = C_0 + sum_h V_h^T C_h; W2 = T^T W1; C_0 -= W2; C_h -= V_h W2.
+__global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int s) {
+  __shared__ double Vs[kArity - 1][kPanel][kT];
   __shared__ double T[kPanel][kT], G[kPanel][kT];
-  __shared__ double Ca[kPanel][kTrail + 1], Cb[kPanel][kTrail + 1];
-  __shared__ double W1[kPanel][kTrail + 1], W2[kPanel][kTrail + 1];
+  __shared__ double Cs[kArity][kPanel][kTrailN + 1];
+  __shared__ double W1[kPanel][kTrailN + 1], W2[kPanel][kTrailN + 1];
   __shared__ double tau_s[kPanel];
   __shared__ PanelScratch ps;
-  const int step = 1 << (L + 1);
-  const int b = blockIdx.x * step + (1 << L);
+  const int a = blockIdx.x * s * kArity;
   const int mat = blockIdx.y;
   const int N = q.N, k = q.k, nb = q.nb;
-  if (b >= nb) return;
-  const int a = b - (1 << L);
+  if (a + s >= nb) return;
+  const int nch = node_children(a, s, nb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
-  const int ta = top_row(a, c0, N, nb), tb = top_row(b, c0, N, nb);
+  auto top = [&](int h) { return top_row(a + h * s, c0, N, nb); };
   double* A = q.A[mat];
   if (wave == 0) {
     const int rr = lane & 31;
-    double x[1][kPanel];
-    const double* src = A + (long)((lane < 32 ? ta : tb) + rr) * k + c0;
+    double x[kNodeRPL][kPanel];
 #pragma unroll
-    for (int c = 0; c < kPanel; ++c) x[0][c] = (rr <= c && c < w) ? src[c] : 0.0;
-    wave_panel_qr<1>(
-        x, w, lane, [&](int j, int) { return lane >= 32 && rr <= j; }, tau_s, G, ps);
-    double* dst = A + (long)((lane < 32 ? ta : tb) + rr) * k + c0;
+    for (int r = 0; r < kNodeRPL; ++r) {
+      const int h = (lane >> 5) + 2 * r;
+      const bool live = h < nch;
+      const double* src = A + (long)(live ? top(h) + rr : 0) * k + c0;
 #pragma unroll
-    for (int c = 0; c < kPanel; ++c) {
-      if (rr <= c && c < w) dst[c] = x[0][c];
-      if (lane >= 32) Rb[rr][c] = (rr <= c && c < w) ? x[0][c] : 0.0;
+      for (int c = 0; c < kPanel; ++c) x[r][c] = (live && rr <= c && c < w) ? src[c] : 0.0;
+    }
+    wave_panel_qr<kNodeRPL>(
+        x, w, lane,
+        [&](int j, int r) {
+          const int h = (lane >> 5) + 2 * r;
+          return h > 0 && h < nch && rr <= j;
+        },
+        tau_s, G, ps);
+#pragma unroll
+    for (int r = 0; r < kNodeRPL; ++r) {
+      const int h = (lane >> 5) + 2 * r;
+      if (h < nch) {
+        double* dst = A + (long)(top(h) + rr) * k + c0;
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c) {
+          const bool in = rr <= c && c < w;
+          if (in) dst[c] = x[r][c];
+          if (h > 0) Vs[h - 1][rr][c] = in ? x[r][c] : 0.0;
+        }
+      }
     }
     build_T(T, G, tau_s, w, lane);
   }
   __syncthreads();
-  const long sl = slot(mat, p, b, nb, q.P);
+  const long sl = slot(mat, p, a + s, nb, q.P);
   for (int idx = tid; idx < kPanel * kPanel; idx += 256)
     q.Tn[sl * kPanel * kPanel + idx] = T[idx / kPanel][idx % kPanel];
-  auto Vb = [&](int r, int c) -> double { return r <= c ? Rb[r][c] : 0.0; };
-  // trailing columns [c0+w, k) of the 2w rows: W1 = Ca + Vb^T Cb;
-  // W2 = T^T W1; Ca -= W2; Cb -= Vb W2
-  for (int cb = c0 + w; cb < k; cb += kTrail) {
-    const int nc = min(kTrail, k - cb);
+  // children after the first stacked along one index: u = (h - 1) * kPanel + r
+  const int nv = (nch - 1) * kPanel;
+  auto V = [&](int u, int c) -> double { return Vs[u >> 5][u & 31][c]; };
+  for (int cb = c0 + w; cb < k; cb += kTrailN) {
+    const int nc = min(kTrailN, k - cb);
     __syncthreads();
-    g2l(2 * w * kTrail, tid,
+    // rows r >= w of every child are loaded as zeros, so that the stacked
+    // products may run over full kPanel-row blocks
+    g2l(nch * kPanel * kTrailN, tid,
         [&](int idx) {
-          const int h = idx / (w * kTrail), rc = idx % (w * kTrail);
-          const int r = rc / kTrail, c = rc % kTrail;
-          return c < nc ? A[(long)((h ? tb : ta) + r) * k + cb + c] : 0.0;
+          const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
+          const int r = rc / kTrailN, c = rc % kTrailN;
+          return (r < w && c < nc) ? A[(long)(top(h) + r) * k + cb + c] : 0.0;
         },
         [&](int idx, double v) {
-          const int h = idx / (w * kTrail), rc = idx % (w * kTrail);
-          (h ? Cb : Ca)[rc / kTrail][rc % kTrail] = v;
+          const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
+          Cs[h][rc / kTrailN][rc % kTrailN] = v;
         });
     __syncthreads();
-    lds_mm(w, nc, w, [&](int i, int r) { return Vb(r, i); }, [&](int r, int c) { return Cb[r][c]; },
-           [&](int i, int j, double x) { W1[i][j] = x + Ca[i][j]; }, wave, lane);
+    lds_mm(w, nc, nv, [&](int i, int u) { return V(u, i); },
+           [&](int u, int c) { return Cs[1 + (u >> 5)][u & 31][c]; },
+           [&](int i, int j, double x) { W1[i][j] = x + Cs[0][i][j]; }, wave, lane);
     __syncthreads();
     lds_mm(w, nc, w, [&](int i, int l) { return T[l][i]; }, [&](int l, int c) { return W1[l][c]; },
            [&](int i, int j, double x) { W2[i][j] = x; }, wave, lane);
     __syncthreads();
-    lds_mm(w, nc, w, Vb, [&](int l, int c) { return W2[l][c]; },
-           [&](int r, int c, double x) { Cb[r][c] -= x; }, wave, lane);
-    for (int idx = tid; idx < w * kTrail; idx += 256) {
-      const int r = idx / kTrail, c = idx % kTrail;
-      if (c < nc) Ca[r][c] -= W2[r][c];
+    lds_mm(nv, nc, w, V, [&](int l, int c) { return W2[l][c]; },
+           [&](int u, int c, double x) { Cs[1 + (u >> 5)][u & 31][c] -= x; }, wave, lane);
+    for (int idx = tid; idx < w * kTrailN; idx += 256) {
+      const int r = idx / kTrailN, c = idx % kTrailN;
+      if (c < nc) Cs[0][r][c] -= W2[r][c];
     }
     __syncthreads();
-    for (int idx = tid; idx < w * kTrail; idx += 256) {
-      const int r = idx / kTrail, c = idx % kTrail;
-      if (c < nc) {
-        A[(long)(ta + r) * k + cb + c] = Ca[r][c];
-        A[(long)(tb + r) * k + cb + c] = Cb[r][c];
-      }
+    for (int idx = tid; idx < nch * w * kTrailN; idx += 256) {
+      const int h = idx / (w * kTrailN), rc = idx % (w * kTrailN);
+      const int r = rc / kTrailN, c = rc % kTrailN;
+      if (c < nc) A[(long)(top(h) + r) * k + cb + c] = Cs[h][r][c];
     }
   }
 }
@@ -420,68 +450,69 @@ __global__ void qr_init_e(QrArgs q) {
   }
 }
 
-// E rows of the node <- Q_node E on columns [c0, k): W1 = Ea + Vb^T Eb;
-// W2 = T W1; Ea -= W2; Eb -= Vb W2.
-__global__ __launch_bounds__(256) void qr_tree_apply(QrArgs q, int p, int L) {
-  __shared__ double Vs[kPanel][kT], T[kPanel][kT];
-  __shared__ double Ca[kPanel][kTrail + 1], Cb[kPanel][kTrail + 1];
-  __shared__ double W1[kPanel][kTrail + 1], W2[kPanel][kTrail + 1];
-  const int step = 1 << (L + 1);
-  const int b = blockIdx.x * step + (1 << L);
+// E rows of the node <- Q_node E on columns [c0, k):
+// W1 = E_0 + sum_h V_h^T E_h; W2 = T W1; E_0 -= W2; E_h -= V_h W2.
+__global__ __launch_bounds__(256) void qr_tree_apply(QrArgs q, int p, int s) {
+  __shared__ double Vs[kArity - 1][kPanel][kT], T[kPanel][kT];
+  __shared__ double Cs[kArity][kPanel][kTrailN + 1];
+  __shared__ double W1[kPanel][kTrailN + 1], W2[kPanel][kTrailN + 1];
+  const int a = blockIdx.x * s * kArity;
   const int mat = blockIdx.y;
   const int N = q.N, k = q.k, nb = q.nb;
-  if (b >= nb) return;
-  const int a = b - (1 << L);
+  if (a + s >= nb) return;
+  const int nch = node_children(a, s, nb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
-  const int ta = top_row(a, c0, N, nb), tb = top_row(b, c0, N, nb);
+  auto top = [&](int h) { return top_row(a + h * s, c0, N, nb); };
   const double* A = q.A[mat];
   double* E = q.E[mat];
-  const long sl = slot(mat, p, b, nb, q.P);
-  g2l(2 * kPanel * kPanel, tid,
+  const long sl = slot(mat, p, a + s, nb, q.P);
+  const int nv = (nch - 1) * kPanel;
+  g2l(nv * kPanel, tid,
       [&](int idx) {
-        const int h = idx / (kPanel * kPanel), rc = idx % (kPanel * kPanel);
-        const int r = rc / kPanel, c = rc % kPanel;
-        if (h) return q.Tn[sl * kPanel * kPanel + rc];
-        return (r <= c && r < w && c < w) ? A[(long)(tb + r) * k + c0 + c] : 0.0;
+        const int u = idx / kPanel, c = idx % kPanel;
+        const int h = 1 + (u >> 5), r = u & 31;
+        return (r <= c && c < w) ? A[(long)(top(h) + r) * k + c0 + c] : 0.0;
       },
       [&](int idx, double v) {
-        const int h = idx / (kPanel * kPanel), rc = idx % (kPanel * kPanel);
-        (h ? T : Vs)[rc / kPanel][rc % kPanel] = v;
+        const int u = idx / kPanel;
+        Vs[u >> 5][u & 31][idx % kPanel] = v;
       });
-  for (int cb = c0; cb < k; cb += kTrail) {
-    const int nc = min(kTrail, k - cb);
+  g2l(kPanel * kPanel, tid, [&](int idx) { return q.Tn[sl * kPanel * kPanel + idx]; },
+      [&](int idx, double v) { T[idx / kPanel][idx % kPanel] = v; });
+  auto V = [&](int u, int c) -> double { return Vs[u >> 5][u & 31][c]; };
+  for (int cb = c0; cb < k; cb += kTrailN) {
+    const int nc = min(kTrailN, k - cb);
     __syncthreads();
-    g2l(2 * w * kTrail, tid,
+    g2l(nch * kPanel * kTrailN, tid,
         [&](int idx) {
-          const int h = idx / (w * kTrail), rc = idx % (w * kTrail);
-          const int r = rc / kTrail, c = rc % kTrail;
-          return c < nc ? E[(long)((h ? tb : ta) + r) * k + cb + c] : 0.0;
+          const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
+          const int r = rc / kTrailN, c = rc % kTrailN;
+          return (r < w && c < nc) ? E[(long)(top(h) + r) * k + cb + c] : 0.0;
         },
         [&](int idx, double v) {
-          const int h = idx / (w * kTrail), rc = idx % (w * kTrail);
-          (h ? Cb : Ca)[rc / kTrail][rc % kTrail] = v;
+          const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
+          Cs[h][rc / kTrailN][rc % kTrailN] = v;
         });
     __syncthreads();
-    lds_mm(w, nc, w, [&](int i, int r) { return Vs[r][i]; }, [&](int r, int c) { return Cb[r][c]; },
-           [&](int i, int j, double x) { W1[i][j] = x + Ca[i][j]; }, wave, lane);
+    lds_mm(w, nc, nv, [&](int i, int u) { return V(u, i); },
+           [&](int u, int c) { return Cs[1 + (u >> 5)][u & 31][c]; },
+           [&](int i, int j, double x) { W1[i][j] = x + Cs[0][i][j]; }, wave, lane);
     __syncthreads();
     lds_mm(w, nc, w, [&](int i, int l) { return T[i][l]; }, [&](int l, int c) { return W1[l][c]; },
            [&](int i, int j, double x) { W2[i][j] = x; }, wave, lane);
     __syncthreads();
-    lds_mm(w, nc, w, [&](int r, int l) { return Vs[r][l]; }, [&](int l, int c) { return W2[l][c]; },
-           [&](int r, int c, double x) { Cb[r][c] -= x; }, wave, lane);
-    for (int idx = tid; idx < w * kTrail; idx += 256) {
-      const int r = idx / kTrail, c = idx % kTrail;
-      if (c < nc) Ca[r][c] -= W2[r][c];
+    lds_mm(nv, nc, w, V, [&](int l, int c) { return W2[l][c]; },
+           [&](int u, int c, double x) { Cs[1 + (u >> 5)][u & 31][c] -= x; }, wave, lane);
+    for (int idx = tid; idx < w * kTrailN; idx += 256) {
+      const int r = idx / kTrailN, c = idx % kTrailN;
+      if (c < nc) Cs[0][r][c] -= W2[r][c];
     }
     __syncthreads();
-    for (int idx = tid; idx < w * kTrail; idx += 256) {
-      const int r = idx / kTrail, c = idx % kTrail;
-      if (c < nc) {
-        E[(long)(ta + r) * k + cb + c] = Ca[r][c];
-        E[(long)(tb + r) * k + cb + c] = Cb[r][c];
-      }
+    for (int idx = tid; idx < nch * w * kTrailN; idx += 256) {
+      const int h = idx / (w * kTrailN), rc = idx % (w * kTrailN);
+      const int r = rc / kTrailN, c = rc % kTrailN;
+      if (c < nc) E[(long)(top(h) + r) * k + cb + c] = Cs[h][r][c];
     }
   }
 }
@@ -569,7 +600,7 @@ QrPlan make_plan(int N, int k) {
   pl.nb = nb;
   pl.P = (k + kPanel - 1) / kPanel;
   int depth = 0;
-  while ((1 << depth) < nb) ++depth;
+  for (long span = 1; span < nb; span *= kArity) ++depth;
   pl.depth = depth;
   return pl;
 }
@@ -622,9 +653,9 @@ int launch_qr(int count, double* const* W, int N, int k, void* ws, hipStream_t s
 
   for (int p = 0; p < pl.P; ++p) {
     qr_leaf_factor<<<dim3(pl.nb, count), 256, 0, s>>>(q, p);
-    for (int L = 0; L < pl.depth; ++L) {
-      const int nodes = (pl.nb + (1 << (L + 1)) - 1) >> (L + 1);
-      qr_tree_factor<<<dim3(nodes, count), 256, 0, s>>>(q, p, L);
+    for (int L = 0, st = 1; L < pl.depth; ++L, st *= kArity) {
+      const int nodes = (pl.nb + st * kArity - 1) / (st * kArity);
+      qr_tree_factor<<<dim3(nodes, count), 256, 0, s>>>(q, p, st);
     }
   }
   const long total = (long)N * k;
@@ -632,8 +663,10 @@ int launch_qr(int count, double* const* W, int N, int k, void* ws, hipStream_t s
   qr_init_e<<<dim3(blocks, count), 256, 0, s>>>(q);
   for (int p = pl.P - 1; p >= 0; --p) {
     for (int L = pl.depth - 1; L >= 0; --L) {
-      const int nodes = (pl.nb + (1 << (L + 1)) - 1) >> (L + 1);
-      qr_tree_apply<<<dim3(nodes, count), 256, 0, s>>>(q, p, L);
+      int st = 1;
+      for (int i = 0; i < L; ++i) st *= kArity;
+      const int nodes = (pl.nb + st * kArity - 1) / (st * kArity);
+      qr_tree_apply<<<dim3(nodes, count), 256, 0, s>>>(q, p, st);
     }
     qr_leaf_apply<<<dim3(pl.nb, count), 256, 0, s>>>(q, p);
   }

@@ -111,8 +111,10 @@ def test_gemm_split_without_scratch_runs_plain_tiles():
     assert np.abs(Cd[7].cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+# leaf counts 1, 1, 8, 19, 32, 6, 23 and 156: reduction-tree nodes with two,
+# three and four children at several strides
 @pytest.mark.parametrize("N,k", [(32, 24), (100, 100), (1024, 72), (2500, 105), (5184, 160),
-                                 (777, 33)])
+                                 (777, 33), (3000, 40), (20000, 8)])
 def test_householder_qr(N, k):
     W = [S.gaussian_block(N, k, 3 + i) for i in range(4)]
     W[1][:, 5] = 0.0                              # a zero column (tau = 0 path)
