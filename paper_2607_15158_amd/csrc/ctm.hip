@@ -132,7 +132,7 @@ struct ctm_ctx {
   int* fs_info;
   int* fs_perm;              // descending order of the dense SVD's singular values
   double* sk_part = nullptr;  // partial tiles of the balanced SI applications
-  double* dot_part = nullptr; // partial sums of the plaquette dot products
+  double* dot_part = nullptr; // partial sums of the plaquette dot products and of the norms
   // correlation length: block of kXiBlock vectors of the transfer matrix
   double *xi_V = nullptr, *xi_Vc = nullptr, *xi_W = nullptr, *xi_H = nullptr, *xi_out = nullptr;
   void* xi_qr = nullptr;
@@ -371,6 +371,11 @@ GemmBatch gemm_rowmajor(int count, int M, int N, int K, long lda, long ldb, long
   return g;
 }
 
+void set_map(GemmBatch& g, int mdiv, long m1, long m0, int ndiv, long n1, long n0) {
+  g.cdiv_m = mdiv; g.cs_m1 = m1; g.cs_m0 = m0;
+  g.cdiv_n = ndiv; g.cs_n1 = n1; g.cs_n0 = n0;
+}
+
 double gemm_flops(const GemmBatch& g) { return 2.0 * g.M * g.N * (double)g.K * g.count * g.nbatch; }
 
 // Largest element offset a 2-level map can address for indices < n.
@@ -425,27 +430,27 @@ int run_gemm(ctm_ctx* c, int cls, const GemmBatch& g, DT ta, DT tb, DT tc, doubl
 // step 1: enlarged corners (batched over the four corners)
 // ---------------------------------------------------------------------------
 // The environment part of the four enlarged corners (float64):
-// CT_i = C_i T_i into CT[i] and W_i = T_(i-1) CT_i into S1[i].
+// CT_i = C_i T_i into CT[i] and W_i = T_(i-1) CT_i into S1[i].  CT_i is
+// stored with its last two legs swapped, (y, q) instead of T_i's (q, y), so
+// that the columns of the second product, the large one (x^2 D^4 outputs per
+// corner), run along q, the unit-stride leg of W_i; the scattered stores fall
+// on the first product, whose output is D^2 times smaller.
 int corner_stems(ctm_ctx* c, int phase) {
   const int x = c->chi_env, Dl = c->Dl;
   double* const* C = c->C[c->cur];
   double* const* T = c->T[c->cur];
-  // CT_i[a, (q, y)] = C_i[a, b] T_i[b, q, y]
-  GemmBatch g1 = gemm_rowmajor(4, x, Dl * x, x, x, (long)Dl * x, (long)Dl * x);
+  // CT_i[a, (y, q)] = C_i[a, b] T_i[b, q, y]
+  GemmBatch g1 = gemm_rowmajor(4, x, Dl * x, x, x, (long)Dl * x, 0);
+  set_map(g1, 1 << 30, 0, (long)Dl * x, x, 1, Dl);
   for (int i = 0; i < 4; ++i) {
     g1.A[i] = C[i];
     g1.B[i] = T[i];
     g1.C[i] = c->CT[i];
   }
   TRY(run_gemm(c, phase, g1, DT::F64, DT::F64, DT::F64));
-  // W_i[(x_in, y), (p, q)] = T_(i-1)[(x_in, p), a] CT_i[a, (q, y)]
+  // W_i[(x_in, y), (p, q)] = T_(i-1)[(x_in, p), a] CT_i[a, (y, q)]
   GemmBatch g2 = gemm_rowmajor(4, x * Dl, Dl * x, x, x, (long)Dl * x, 0);
-  g2.cdiv_m = Dl;
-  g2.cs_m1 = (long)x * Dl * Dl;
-  g2.cs_m0 = Dl;
-  g2.cdiv_n = x;
-  g2.cs_n1 = 1;
-  g2.cs_n0 = (long)Dl * Dl;
+  set_map(g2, Dl, (long)x * Dl * Dl, Dl, Dl, (long)Dl * Dl, 1);
   for (int i = 0; i < 4; ++i) {
     g2.A[i] = T[(i + 3) % 4];
     g2.B[i] = c->CT[i];
@@ -911,6 +916,8 @@ int normalize_env(ctm_ctx* c, int buf, int x) {
   }
   na.out = c->scal;
   na.bad = c->bad;
+  na.part = c->dot_part;
+  static_assert(8 * kNormBlocks <= kMaxDots * kDotBlocks, "norm partial sums exceed dot_part");
   return elem_normalize(na, 8, c->st);
 }
 
@@ -1262,11 +1269,6 @@ GemmBatch gb1(int M, int N, int K, const void* A, long lda, int transA, const vo
   g.B[0] = B;
   g.C[0] = C;
   return g;
-}
-
-void set_map(GemmBatch& g, int mdiv, long m1, long m0, int ndiv, long n1, long n0) {
-  g.cdiv_m = mdiv; g.cs_m1 = m1; g.cs_m0 = m0;
-  g.cdiv_n = ndiv; g.cs_n1 = n1; g.cs_n0 = n0;
 }
 
 int g64(ctm_ctx* c, const GemmBatch& g) { return run_gemm(c, PC_MISC, g, DT::F64, DT::F64, DT::F64); }

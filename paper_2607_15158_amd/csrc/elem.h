@@ -5,11 +5,16 @@
 
 namespace sictm {
 
+// Partial sums per tensor of the norm reduction (fixed, so that the norms do
+// not depend on the launch).
+constexpr int kNormBlocks = 128;
+
 struct NormArgs {
   double* x[8];
   long n[8];
-  double* out;   // 8 norms
-  int* bad;      // set to 1 on a zero / non-finite norm
+  double* out;    // 8 norms
+  int* bad;       // set to 1 on a zero / non-finite norm
+  double* part;   // 8 * kNormBlocks partial sums of squares (workspace)
 };
 
 struct SignArgs {

@@ -108,15 +108,26 @@ __global__ void k_init_env(const double* a, const double* e, int n, double* C1, 
   }
 }
 
-// Frobenius norms of up to 8 tensors (one block each) -> out[i]; sets *bad
-// when a norm is zero or not finite.
-__global__ void k_norms(NormArgs na) {
+// Frobenius norms of up to 8 tensors -> out[i]; sets *bad when a norm is
+// zero or not finite.  Block (b, t) sums the squares of the elements
+// b * 256 + j + m * kNormBlocks * 256 of tensor t; k_norms_final adds the
+// kNormBlocks partial sums of a tensor in block order.
+__global__ __launch_bounds__(256) void k_norms_part(NormArgs na) {
   __shared__ double sh[4];
-  const int t = blockIdx.x;
+  const int t = blockIdx.y;
   const double* x = na.x[t];
   const long n = na.n[t];
   double acc = 0.0;
-  for (long i = threadIdx.x; i < n; i += blockDim.x) acc += x[i] * x[i];
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)kNormBlocks * 256)
+    acc += x[i] * x[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) na.part[(long)t * kNormBlocks + blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_norms_final(NormArgs na) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x;
+  double acc = threadIdx.x < kNormBlocks ? na.part[(long)t * kNormBlocks + threadIdx.x] : 0.0;
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) {
     const double nr = sqrt(acc);
@@ -716,8 +727,20 @@ int elem_init_env(const double* a, const double* e, int n, double* const* C, dou
   return 0;
 }
 
+static int launch_norms(const NormArgs& na, int count, hipStream_t s) {
+  if (count < 1 || count > 8 || na.part == nullptr) {
+    set_thread_error("norms: need 1 to 8 tensors and a partial-sum workspace");
+    return 1;
+  }
+  k_norms_part<<<dim3(kNormBlocks, count), 256, 0, s>>>(na);
+  CTM_HIP_TRY(hipGetLastError());
+  k_norms_final<<<count, 256, 0, s>>>(na);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int elem_normalize(const NormArgs& na, int count, hipStream_t s) {
-  k_norms<<<count, 256, 0, s>>>(na);
+  if (launch_norms(na, count, s)) return 1;
   long mx = 0;
   for (int i = 0; i < count; ++i) mx = std::max(mx, na.n[i]);
   const int blocks = (int)std::min<long>(1024, (mx + 255) / 256);
@@ -726,11 +749,7 @@ int elem_normalize(const NormArgs& na, int count, hipStream_t s) {
   return 0;
 }
 
-int elem_norms(const NormArgs& na, int count, hipStream_t s) {
-  k_norms<<<count, 256, 0, s>>>(na);
-  CTM_HIP_TRY(hipGetLastError());
-  return 0;
-}
+int elem_norms(const NormArgs& na, int count, hipStream_t s) { return launch_norms(na, count, s); }
 
 int elem_sin2(const OverlapArgs& oa, hipStream_t s) {
   if (oa.count < 1 || oa.count > 8 || oa.chi < 1) return 1;
