@@ -104,6 +104,7 @@ struct ctm_ctx {
   double* A_site = nullptr;
   double* a = nullptr;
   void* ap[4];
+  void* apr[4];              // ap with its two leading legs swapped (renormalisation)
   double* imp[3];            // impurity scratch (Dl^4 each)
   double* imps[2];           // open-leg impurities of the two bond sites (d^2 Dl^4 each)
   double* e = nullptr;
@@ -255,6 +256,7 @@ size_t carve(ctm_ctx* c, char* base) {
   c->A_site = cv.take<double>(c->d > 0 ? (size_t)c->d * c->D * c->D * c->D * c->D : 1);
   c->a = cv.take<double>(Dl4);
   for (int i = 0; i < 4; ++i) c->ap[i] = cv.take_bytes(Dl4 * es);
+  for (int i = 0; i < 4; ++i) c->apr[i] = cv.take_bytes(Dl4 * es);
   for (int i = 0; i < 3; ++i) c->imp[i] = cv.take<double>(Dl4);
   for (int i = 0; i < 2; ++i) c->imps[i] = cv.take<double>((size_t)dd * Dl4);
   c->e = cv.take<double>(Dl);
@@ -853,19 +855,22 @@ int renormalize(ctm_ctx* c, int keep) {
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
   }
-  // Z1[(b, g'), (u, r)] = sum_g T_j[(b, u), g] P_l[(g, r), g']   (batched over r)
+  // Z1[(b, g'), (r, u)] = sum_g T_j[(b, u), g] P_l[(g, r), g']   (batched over r).
+  // u, the row leg of each product, is Z1's unit-stride leg, so that the rows
+  // of a tile are stored contiguously; the next product contracts (r, u)
+  // against the correspondingly swapped copy of the site tensor.
   {
     GemmBatch g = gemm_rowmajor(4, x * Dl, xp, x, x, (long)Dl * xp, 0);
     g.cdiv_m = Dl;
     g.cs_m1 = (long)xp * Dl * Dl;
-    g.cs_m0 = Dl;
+    g.cs_m0 = 1;
     g.cdiv_n = 1 << 30;
     g.cs_n1 = 0;
     g.cs_n0 = (long)Dl * Dl;
     g.nbatch = Dl;
     g.a_bs = 0;
     g.b_bs = xp;
-    g.c_bs = 1;
+    g.c_bs = Dl;
     for (int j = 0; j < 4; ++j) {
       g.A[j] = T[j];
       g.B[j] = c->Pl[j];
@@ -873,7 +878,7 @@ int renormalize(ctm_ctx* c, int keep) {
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
   }
-  // Z2[(b, l), d, g'] = Z1[(b, g'), (u, r)] ap_(j+1)[(u, r), (l, d)]
+  // Z2[(b, l), d, g'] = Z1[(b, g'), (r, u)] apr_(j+1)[(r, u), (l, d)]
   {
     GemmBatch g = gemm_rowmajor(4, x * xp, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
     g.cdiv_m = xp;
@@ -884,7 +889,7 @@ int renormalize(ctm_ctx* c, int keep) {
     g.cs_n0 = xp;
     for (int j = 0; j < 4; ++j) {
       g.A[j] = c->S1[j];
-      g.B[j] = c->ap[(j + 1) % 4];
+      g.B[j] = c->apr[(j + 1) % 4];
       g.C[j] = c->S2[j];
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, c->cp, DT::F64));
@@ -1768,9 +1773,13 @@ ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev
   // corner 0: (l,u),(d,r); 1: (u,r),(l,d); 2: (r,d),(u,l); 3: (d,l),(r,u)
   const long su = (long)Dl * Dl * Dl, sl = (long)Dl * Dl, sd = Dl, sr = 1;
   const long perm[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
-  for (int i = 0; i < 4 && !rc; ++i)
+  for (int i = 0; i < 4 && !rc; ++i) {
     rc = elem_permute4(c->a, c->ap[i], c->cp, Dl, perm[i][0], perm[i][1], perm[i][2], perm[i][3],
                        c->st);
+    if (!rc)
+      rc = elem_permute4(c->a, c->apr[i], c->cp, Dl, perm[i][1], perm[i][0], perm[i][2],
+                         perm[i][3], c->st);
+  }
   if (rc) return bail(rc);
   rc = elem_init_env(c->a, c->e, Dl, c->C[0], c->T[0], c->st);
   if (!rc && c->cfg.sym == CTM_SYM_C4V) rc = c4v_finish(c, 0, Dl);
