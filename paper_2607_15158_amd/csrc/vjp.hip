@@ -87,14 +87,38 @@ struct DotArgs {
   double* out;
 };
 
-// out[t] = <x_t, y_t>, one block of 256 threads per pair.
-__global__ __launch_bounds__(256) void k_dots(DotArgs a) {
+// out[t] = <x_t, y_t> for up to 8 pairs.  Block (b, t) adds the products
+// b * 256 + j + m * kDotParts * 256 of pair t into part[t * kDotParts + b];
+// k_dots_final adds a pair's partial sums in block order, so the result does
+// not depend on scheduling.
+constexpr int kDotParts = 128;
+
+__global__ __launch_bounds__(256) void k_dots_part(DotArgs a, double* part) {
+  __shared__ double sh[4];
+  const int t = blockIdx.y;
+  const double* x = a.x[t];
+  const double* y = a.y[t];
+  double acc = 0.0;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < a.n[t]; i += (long)kDotParts * 256)
+    acc += x[i] * y[i];
+  acc = block_sum256(acc, sh);
+  if (threadIdx.x == 0) part[(long)t * kDotParts + blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_dots_final(DotArgs a, const double* part) {
   __shared__ double sh[4];
   const int t = blockIdx.x;
-  double acc = 0.0;
-  for (long i = threadIdx.x; i < a.n[t]; i += 256) acc += a.x[t][i] * a.y[t][i];
+  double acc = threadIdx.x < kDotParts ? part[(long)t * kDotParts + threadIdx.x] : 0.0;
   acc = block_sum256(acc, sh);
   if (threadIdx.x == 0) a.out[t] = acc;
+}
+
+int launch_dots(const DotArgs& a, int count, double* part, hipStream_t s) {
+  k_dots_part<<<dim3(kDotParts, count), 256, 0, s>>>(a, part);
+  CTM_HIP_TRY(hipGetLastError());
+  k_dots_final<<<count, 256, 0, s>>>(a, part);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
 }
 
 struct NormBwdArgs {
@@ -283,6 +307,7 @@ struct Bufs {
   double *vscb[4], *uscb[4], *vscT[4], *uscT[4], *ub[4], *vb[4], *sb[4];
   double *smallT;                         // x x x / k x k transposes
   double *fp_v[2], *fp_dot;               // fixed-point iteration: cotangent ping-pong
+  double* dpart;                          // partial sums of the dot products (8 * kDotParts)
   double *PTs[4], *QTs[4];                // per corner: 8 transposed blocks stacked along K
   double *Ga[4], *Gb[4];                  // per corner / edge N x N scratch (batched launches)
   double *apb4[4];                        // per corner / edge cotangents of the permuted a
@@ -395,6 +420,7 @@ size_t carve(const Dims& m, Bufs* b, char* base, std::vector<std::pair<uintptr_t
   b->fp_v[0] = cv.take(nstate);
   b->fp_v[1] = cv.take(nstate);
   b->fp_dot = cv.take(8);
+  b->dpart = cv.take((size_t)8 * kDotParts);
   for (int i = 0; i < 4; ++i) {
     b->PTs[i] = cv.take(8 * Nk);
     b->QTs[i] = cv.take(8 * Nk);
@@ -769,8 +795,7 @@ int forward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in, d
       da.n[t] = na.n[t];
     }
     da.out = b.dots;   // squared norms; the square roots are taken below
-    k_dots<<<8, 256, 0, r.st>>>(da);
-    CTM_HIP_TRY(hipGetLastError());
+    VTRY(launch_dots(da, 8, b.dpart, r.st));
   }
   return 0;
 }
@@ -834,8 +859,7 @@ int backward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in,
       da.n[4 + i] = (long)x * Dl * x;
     }
     da.out = b.dots;
-    k_dots<<<8, 256, 0, r.st>>>(da);
-    CTM_HIP_TRY(hipGetLastError());
+    VTRY(launch_dots(da, 8, b.dpart, r.st));
     for (int t = 0; t < 8; ++t) {
       nb.y[t] = da.x[t];
       nb.yb[t] = da.y[t];
@@ -1816,8 +1840,7 @@ ctm_status ctm_fixed_point_vjp(ctm_ctx* ctx, const double* state_star, const dou
     da.y[0] = v;
     da.n[0] = n;
     da.out = P.b.fp_dot;
-    k_dots<<<1, 256, 0, P.r.st>>>(da);
-    CTM_HIP_TRY(hipGetLastError());
+    if (launch_dots(da, 1, P.b.dpart, P.r.st)) return 1;
     CTM_HIP_TRY(hipMemcpyAsync(out, P.b.fp_dot, sizeof(double), hipMemcpyDeviceToHost, P.r.st));
     CTM_HIP_TRY(hipStreamSynchronize(P.r.st));
     return 0;
