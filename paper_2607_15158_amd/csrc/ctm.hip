@@ -895,13 +895,16 @@ int renormalize(ctm_ctx* c, int keep) {
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, c->cp, DT::F64));
   }
   // T'[b', (d, g')] = sum_(b,l) P_r^T[(b, l), b'] Z2[(b, l), (d, g')]: one
-  // GEMM per edge, (d, g') contiguous in both Z2 and T'
+  // GEMM per edge, computed as its transpose (rows (d, g'), N = xp columns b'),
+  // the tall-skinny shape of the double-buffered kernel; the output map
+  // writes it back in T' order
   {
-    GemmBatch g = gemm_rowmajor(4, xp, Dl * xp, x * Dl, xp, (long)Dl * xp, (long)Dl * xp);
+    GemmBatch g = gemm_rowmajor(4, Dl * xp, xp, x * Dl, (long)Dl * xp, xp, 0);
+    set_map(g, 1 << 30, 0, 1, 1 << 30, 0, (long)Dl * xp);
     for (int j = 0; j < 4; ++j) {
-      g.A[j] = c->Prt[j];
+      g.A[j] = c->S2[j];
       g.transA[j] = 1;
-      g.B[j] = c->S2[j];
+      g.B[j] = c->Prt[j];
       g.C[j] = c->T[nxt][j];
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
