@@ -172,6 +172,38 @@ __global__ __launch_bounds__(256) void k_tri_inv(SmallArgs a) {
   }
 }
 
+// Same result as k_tri_inv, operation for operation, for n <= kTriLds: the
+// upper triangle of X lives in LDS, row-packed (row l starts at
+// l n - l (l - 1) / 2, so the threads of a row step read consecutive words),
+// and row i of R is staged in LDS for step i.  Every thread takes part in
+// the two barriers of each step.
+constexpr int kTriLds = 192;
+
+__global__ __launch_bounds__(256) void k_tri_inv_lds(SmallArgs a) {
+  __shared__ double Xs[kTriLds * (kTriLds + 1) / 2];
+  __shared__ double Rrow[kTriLds];
+  const int b = blockIdx.x, n = a.n, j = threadIdx.x;
+  const double* R = a.in[b];
+  double* X = a.out[b];
+  auto at = [n](int l, int c) { return l * n - l * (l - 1) / 2 + (c - l); };   // l <= c
+  for (int i = n - 1; i >= 0; --i) {
+    __syncthreads();
+    if (j < n) Rrow[j] = R[(long)i * n + j];
+    __syncthreads();
+    if (j < n && j >= i) {
+      double acc = i == j ? 1.0 : 0.0;
+      for (int l = i + 1; l <= j; ++l) acc -= Rrow[l] * Xs[at(l, j)];
+      const double d = Rrow[i];
+      Xs[at(i, j)] = d != 0.0 ? acc / d : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int r = e / n, c = e % n;
+    X[e] = c >= r ? Xs[at(r, c)] : 0.0;
+  }
+}
+
 struct PrepArgs {
   const double* u[4];
   const double* v[4];
@@ -1186,7 +1218,10 @@ int backward(Run& r, const VjpView& v, const Dims& m, Bufs& b, const State& in,
         sa.in[j] = b.R[j];
         sa.out[j] = b.Rinv[j];
       }
-      k_tri_inv<<<8, 256, 0, r.st>>>(sa);
+      if (k <= kTriLds)
+        k_tri_inv_lds<<<8, 256, 0, r.st>>>(sa);
+      else
+        k_tri_inv<<<8, 256, 0, r.st>>>(sa);
       CTM_HIP_TRY(hipGetLastError());
       for (int j = 0; j < 8; ++j) {
         VTRY(transpose(r, b.Rinv[j], b.RinvT[j], k, k));
