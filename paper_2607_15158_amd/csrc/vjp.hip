@@ -46,23 +46,57 @@ namespace {
 // ---------------------------------------------------------------------------
 
 // dst[i] (=, or += when acc) alpha * src[i0 s0 + i1 s1 + i2 s2 + i3 s3] over
-// the index box n0 x n1 x n2 x n3 (row-major in dst).
+// the index box n0 x n1 x n2 x n3 (row-major in dst).  I is the type of the
+// flat index and its decomposition: 32-bit unsigned when the box holds fewer
+// than 2^31 elements (the integer divisions are the kernel's main cost),
+// 64-bit otherwise.
+template <typename I>
 __global__ __launch_bounds__(256) void k_gather4(const double* __restrict__ src,
                                                  double* __restrict__ dst, int n0, int n1,
                                                  int n2, int n3, long s0, long s1, long s2,
                                                  long s3, double alpha, int acc) {
-  const long total = (long)n0 * n1 * n2 * n3;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
-       i += (long)gridDim.x * blockDim.x) {
-    long r = i;
-    const long i3 = r % n3;
-    r /= n3;
-    const long i2 = r % n2;
-    r /= n2;
-    const long i1 = r % n1;
-    const long i0 = r / n1;
-    const double v = alpha * src[i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3];
+  const I total = (I)n0 * (I)n1 * (I)n2 * (I)n3;
+  for (I i = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x; i < total;
+       i += (I)gridDim.x * (I)blockDim.x) {
+    I r = i;
+    const I i3 = r % (I)n3;
+    r /= (I)n3;
+    const I i2 = r % (I)n2;
+    r /= (I)n2;
+    const I i1 = r % (I)n1;
+    const I i0 = r / (I)n1;
+    const double v =
+        alpha * src[(long)i0 * s0 + (long)i1 * s1 + (long)i2 * s2 + (long)i3 * s3];
     dst[i] = acc ? dst[i] + v : v;
+  }
+}
+
+// The transposing case of k_gather4 (n0 = n1 = 1, s2 = 1):
+// dst[i2, i3] (=|+=) alpha * src[i2 + i3 s3], through 32 x 32 LDS tiles so
+// that the reads (along i2) and the writes (along i3) are both unit-stride.
+// One workgroup per tile; the padded row length 33 keeps the column reads of
+// the tile on distinct banks.
+__global__ __launch_bounds__(256) void k_transpose_tiles(const double* __restrict__ src,
+                                                         double* __restrict__ dst, int n2,
+                                                         int n3, long s3, double alpha, int acc) {
+  __shared__ double t[32][33];
+  const int tiles2 = (n2 + 31) / 32;
+  const int b2 = blockIdx.x % tiles2, b3 = blockIdx.x / tiles2;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int i3 = b3 * 32 + ty + k, i2 = b2 * 32 + tx;
+    if (i3 < n3 && i2 < n2) t[ty + k][tx] = src[(long)i3 * s3 + i2];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int i2 = b2 * 32 + ty + k, i3 = b3 * 32 + tx;
+    if (i2 < n2 && i3 < n3) {
+      const double v = alpha * t[tx][ty + k];
+      double* p = dst + (long)i2 * n3 + i3;
+      *p = acc ? *p + v : v;
+    }
   }
 }
 
@@ -535,7 +569,21 @@ int gather(Run& r, const double* src, double* dst, int n0, int n1, int n2, int n
   if (!r.inside(src, (size_t)(es + 1) * 8) || !r.inside(dst, (size_t)total * 8))
     return r.fail("adjoint permutation out of its buffer; launch refused");
   const int blocks = (int)std::min<long>(4096, (total + 255) / 256);
-  k_gather4<<<blocks, 256, 0, r.st>>>(src, dst, n0, n1, n2, n3, s0, s1, s2, s3, alpha, acc ? 1 : 0);
+  if (n0 == 1 && n1 == 1 && s2 == 1 && n2 >= 32 && n3 >= 32) {
+    const long tiles = (long)((n2 + 31) / 32) * ((n3 + 31) / 32);
+    k_transpose_tiles<<<(unsigned)tiles, 256, 0, r.st>>>(src, dst, n2, n3, s3, alpha,
+                                                         acc ? 1 : 0);
+    CTM_HIP_TRY(hipGetLastError());
+    return 0;
+  }
+  // the grid stride is at most 4096 * 256 = 2^20, so a 32-bit index below
+  // 2^31 never wraps
+  if (total < (1L << 31))
+    k_gather4<unsigned><<<blocks, 256, 0, r.st>>>(src, dst, n0, n1, n2, n3, s0, s1, s2, s3,
+                                                   alpha, acc ? 1 : 0);
+  else
+    k_gather4<long><<<blocks, 256, 0, r.st>>>(src, dst, n0, n1, n2, n3, s0, s1, s2, s3, alpha,
+                                               acc ? 1 : 0);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }
