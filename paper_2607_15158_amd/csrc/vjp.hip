@@ -226,6 +226,9 @@ __global__ __launch_bounds__(256) void k_tri_inv_lds(SmallArgs a) {
     __syncthreads();
     if (j < n && j >= i) {
       double acc = i == j ? 1.0 : 0.0;
+      // unrolled so that the LDS loads of later terms issue while earlier
+      // terms are accumulated; the accumulation order is unchanged
+#pragma unroll 4
       for (int l = i + 1; l <= j; ++l) acc -= Rrow[l] * Xs[at(l, j)];
       const double d = Rrow[i];
       Xs[at(i, j)] = d != 0.0 ? acc / d : 0.0;
