@@ -356,7 +356,11 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int s) {
   const int nch = node_children(a, s, nb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
-  auto top = [&](int h) { return top_row(a + h * s, c0, N, nb); };
+  // top rows of the children, computed once (leaf_start divides in 64 bits)
+  __shared__ int tops[kArity];
+  if (tid < kArity) tops[tid] = tid < nch ? top_row(a + tid * s, c0, N, nb) : 0;
+  __syncthreads();
+  auto top = [&](int h) { return tops[h]; };
   double* A = q.A[mat];
   if (wave == 0) {
     const int rr = lane & 31;
@@ -463,7 +467,10 @@ __global__ __launch_bounds__(256) void qr_tree_apply(QrArgs q, int p, int s) {
   const int nch = node_children(a, s, nb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
-  auto top = [&](int h) { return top_row(a + h * s, c0, N, nb); };
+  __shared__ int tops[kArity];
+  if (tid < kArity) tops[tid] = tid < nch ? top_row(a + tid * s, c0, N, nb) : 0;
+  __syncthreads();
+  auto top = [&](int h) { return tops[h]; };
   const double* A = q.A[mat];
   double* E = q.E[mat];
   const long sl = slot(mat, p, a + s, nb, q.P);
