@@ -80,15 +80,15 @@ def measured_mfma_util(args):
 
 
 def cpu_baseline(args, A, X, Y):
-    """Times the FP64 oracle on a bounded sample of one SI move of this workload.
+    """Times the FP64 oracle on one whole SI move of this workload.
 
-    The sample is steps 1-4 of the move: the four enlarged corners and the SI
-    projectors of the four bonds (n_si subspace steps with QRs, rho, its SVD,
-    the projectors and the recycled blocks).  The oracle's renormalisation of
-    the edges (its a-absorption contractions run in NumPy's einsum loops) takes
-    several minutes at this size and is left out, so the rate reported is an
-    upper bound on the oracle's move rate.  The environment is a seeded random
-    one of the move's shapes (the cost does not depend on the values).
+    The sample is one full move (n_si stabilised subspace steps): the four
+    enlarged corners, the SI projectors of the four bonds (QRs, rho, its
+    SVD, the sign rule, the projectors and the recycled blocks), the
+    renormalisation of the four corners and the four edges and the
+    normalisation, from a seeded random environment of the move's shapes
+    (the cost does not depend on the values), with the benchmark's site
+    tensor and start blocks.
     """
     import oracle as O
     import synth as S
@@ -98,21 +98,18 @@ def cpu_baseline(args, A, X, Y):
     a = O.double_layer(A)
     env = O.Env([S.gaussian_block(chi, chi, 60 + i) for i in range(4)],
                 [S.gaussian_block(chi * Dl, chi, 70 + i).reshape(chi, Dl, chi) for i in range(4)])
+    si = O.SIState(list(X), list(Y))
     t0 = time.perf_counter()
-    Ct = O.enlarged_corners(env, a)
-    t1 = time.perf_counter()
-    for b in range(4):
-        O.si_projectors(Ct, b, X[b], Y[b], chi, args.n_si, args.pinv_rtol, True)
-    t2 = time.perf_counter()
-    return {"value": round(1.0 / (t2 - t0), 5), "unit": "moves/s", "cores": threads, "kind": "oracle",
-            "sample": f"steps 1-4 of one SI move (n_si={args.n_si}) of the same D={D}, chi={chi} "
-                      f"workload: enlarged corners {t1 - t0:.1f} s + SI projectors of the four "
-                      f"bonds {t2 - t1:.1f} s, numpy float64 on {threads} threads; the edge "
-                      f"renormalisation (minutes in the oracle) is not in the sample, so the "
-                      f"value is an upper bound on the oracle's full-move rate"}
+    _, info = O.ctm_move(env, a, chi, "si", si, n_si=args.n_si, eps=args.pinv_rtol)
+    dt = time.perf_counter() - t0
+    assert info["mode"] == "si"
+    return {"value": round(1.0 / dt, 5), "unit": "moves/s", "cores": threads, "kind": "oracle",
+            "sample": f"one whole SI move (n_si={args.n_si}, stabilised) of the same D={D}, "
+                      f"chi={chi} workload from a seeded random environment: {dt:.1f} s, numpy "
+                      f"float64 on {threads} threads"}
 
 
-def serving(args):
+def serving(args, n_requests):
     """Serving workload: mixed (D, chi) environment solves, Poisson arrivals.
 
     Request i: D uniform in {3,4,5,6}, chi uniform in {D^2, 2D^2, 3D^2}
@@ -128,7 +125,7 @@ def serving(args):
     import synth as S
     rng = np.random.default_rng(4)
     reqs = []
-    for i in range(args.serving):
+    for i in range(n_requests):
         D = int(rng.choice([3, 4, 5, 6]))
         chi = int(rng.choice([D * D, 2 * D * D, 3 * D * D]))
         p = max(4, math.ceil(0.15 * chi))
@@ -198,10 +195,11 @@ def main():
                          "moves align to this mean sin^2 (the paper's recycling); 0: n_si "
                          "steps every move")
     ap.add_argument("--min-si-moves", type=int, default=3)
-    ap.add_argument("--converge-tol", type=float, default=0.0,
-                    help="> 0: also time SI and full-SVD environments from the same start until "
-                         "delta < this (each from its own growth move)")
-    ap.add_argument("--converge-max", type=int, default=120)
+    ap.add_argument("--converge-tol", type=float, default=1e-10,
+                    help="> 0: time the SI environment from the initial one until delta < this "
+                         "(with randomized growth, and from the shared full-SVD growth move) and "
+                         "set it against the full-SVD moves run from the same growth move")
+    ap.add_argument("--converge-max", type=int, default=200)
     ap.add_argument("--opt-moves", type=int, default=10,
                     help="> 0: time one optimisation step (the energy after this many SI moves "
                          "from the state after the timed moves, and its site-tensor gradient by "
@@ -219,7 +217,8 @@ def main():
                     help="block iterations of the correlation-length observable")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--pinv-rtol", type=float, default=1e-12)
-    ap.add_argument("--svd-moves", type=int, default=1, help="full-SVD comparator moves (0: skip)")
+    ap.add_argument("--svd-moves", type=int, default=1,
+                    help="full-SVD comparator moves from the state after the growth move (0: skip)")
     ap.add_argument("--svd-driver", default="gesvd", choices=["gesvd", "gesdd", "gesvdx"],
                     help="dense SVD of the growth move and of the full-SVD comparator (gesvd: "
                          "accurate; gesdd: fast but its weak directions are noise at this "
@@ -240,6 +239,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-arena-gb", type=int, default=96)
     ap.add_argument("--serve-moves", type=int, default=60)
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving sub-measurement of the default run (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -251,7 +252,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.serving:
-        print(json.dumps(serving(args)), flush=True)
+        print(json.dumps(serving(args, args.serving)), flush=True)
         return
     dev = torch.device("cuda", 0)
     if args.copy_calib:
@@ -262,6 +263,7 @@ def main():
         log("copy calibration: 1 GiB read, 1 GiB written")
         del src, dst
     A, X, Y = workload(args.D, args.chi, args.p)
+    growth_s = None
     cfg = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="si",
                    prec=args.prec, stabilized=1, pinv_rtol=args.pinv_rtol,
                    svd_driver=args.svd_driver, recycle_sin2=args.recycle_sin2,
@@ -282,14 +284,14 @@ def main():
     else:
         t = time.perf_counter()
         info = ctx.move()                  # growth move (full SVD of the first M_b)
-        log(f"growth move mode={info['mode']} chi_env={info['chi_env']} "
-            f"{time.perf_counter() - t:.2f} s")
+        growth_s = time.perf_counter() - t
+        log(f"growth move mode={info['mode']} chi_env={info['chi_env']} {growth_s:.2f} s")
+    state_after_growth = ctx.get_state()
     for i in range(args.warmup):
         t = time.perf_counter()
         info = ctx.move()
         log(f"warmup {i}: mode={info['mode']} n_si={info['n_si']} delta={info['delta']:.3e} "
             f"sin2={info['sin2']:.2e} {(time.perf_counter() - t) * 1e3:.1f} ms")
-    state_after_warmup = ctx.get_state()
 
     if args.graphs:
         ctx.use_graphs(True)
@@ -410,57 +412,93 @@ def main():
         log(f"optimisation step ({args.opt_moves} unrolled moves, forward + backward): {dt:.2f} s")
         del At, e_opt
 
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+
     svd = None
-    if args.svd_moves > 0:
+    if args.svd_moves > 0 and not args.random_env:
+        # full-SVD CTMRG moves from the state after the (shared) growth move
         cfg_s = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="svd",
                          prec="f64", stabilized=1, pinv_rtol=args.pinv_rtol,
                          svd_driver=args.svd_driver)
-        del ctx
-        torch.cuda.empty_cache()
         cs = P.Ctm(cfg_s, torch.from_numpy(A).to(dev))
-        cs.set_state(state_after_warmup)
-        tt = []
+        cs.set_state(state_after_growth)
+        tt, deltas = [], []
         for i in range(args.svd_moves):
             t = time.perf_counter()
-            cs.move()
+            inf = cs.move()
             tt.append(time.perf_counter() - t)
-            log(f"full-SVD move {i}: {tt[-1]:.2f} s")
-        svd = {"moves_per_s": round(1.0 / float(np.mean(tt)), 4), "ms_per_move": round(1e3 * float(np.mean(tt)), 1),
-               "moves": args.svd_moves,
+            deltas.append(inf["delta"])
+            log(f"full-SVD move {i}: {tt[-1]:.2f} s, delta {inf['delta']:.3e}")
+        svd = {"moves_per_s": round(1.0 / float(np.mean(tt)), 4),
+               "ms_per_move": round(1e3 * float(np.mean(tt)), 1), "moves": args.svd_moves,
+               "deltas": deltas, "start": "the state after the growth move",
                "solver": f"rocsolver_d{args.svd_driver} on 4 x ({cfg.N} x {cfg.N})"}
+        cs.close()
         del cs
+        torch.cuda.empty_cache()
 
     conv = None
-    if args.converge_tol > 0:
-        conv = {"tol": args.converge_tol, "max_moves": args.converge_max,
-                "svd_driver": args.svd_driver}
-        for name, proj in (("si", "si"), ("full_svd", "svd")):
-            cfg_c = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj=proj,
-                             prec=args.prec if proj == "si" else "f64", stabilized=1,
-                             pinv_rtol=args.pinv_rtol, svd_driver=args.svd_driver)
-            torch.cuda.empty_cache()
+    if args.converge_tol > 0 and not args.random_env and args.prec == "f64":
+        # time per converged environment (delta < tol at chi_env = chi) from the
+        # same initial environment: SI-CTMRG with its own randomized (SI)
+        # growth, and SI from the full-SVD growth move the comparator shares
+        tol = args.converge_tol
+        conv = {"tol": tol, "max_moves": args.converge_max}
+        runs = (("si_randomized_growth", "si", None), ("si_after_svd_growth", "svd", state_after_growth))
+        for name, growth, start in runs:
+            cfg_c = P.Config(d=2, D=args.D, chi=args.chi, p=args.p, n_si=args.n_si, proj="si",
+                             prec="f64", stabilized=1, pinv_rtol=args.pinv_rtol,
+                             svd_driver=args.svd_driver, growth=growth)
             cc = P.Ctm(cfg_c, torch.from_numpy(A).to(dev))
             cc.set_isometries(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
+            if start is not None:
+                cc.set_state(start)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            r = cc.converge(args.converge_tol, args.converge_max)
+            r = cc.converge(tol, args.converge_max)
             dt = time.perf_counter() - t
+            if start is not None:
+                dt += growth_s
             import synth as S
             h = S.heisenberg_bond()
             e = cc.observable(P.OBS_BOND_H, h)[0] + cc.observable(P.OBS_BOND_V, h)[0]
-            conv[name] = {"moves": r["moves"], "seconds": round(dt, 3), "converged": r["converged"],
-                          "last_delta": r["delta"], "energy": e}
-            log(f"converged environment ({name}): {r['moves']} moves, {dt:.2f} s, "
-                f"delta {r['delta']:.2e}, energy {e:.10f}")
+            conv[name] = {"moves": r["moves"] + (1 if start is not None else 0),
+                          "seconds": round(dt, 3), "converged": r["converged"],
+                          "last_delta": r["delta"], "energy": e, "kappa": cc.kappa()}
+            log(f"converged environment ({name}): {conv[name]['moves']} moves, {dt:.2f} s, "
+                f"delta {r['delta']:.2e}, energy {e:.12f}")
+            cc.close()
             del cc
-        conv["time_ratio_full_svd_over_si"] = round(conv["full_svd"]["seconds"] /
-                                                    conv["si"]["seconds"], 2)
+            torch.cuda.empty_cache()
+        if svd is not None:
+            done = any(d < tol for d in svd["deltas"])
+            t_svd = growth_s + sum(1e-3 * svd["ms_per_move"] for _ in svd["deltas"])
+            conv["full_svd"] = {"moves_run": 1 + len(svd["deltas"]), "seconds_run": round(t_svd, 2),
+                                "deltas_after_growth": svd["deltas"], "converged": done}
+            if not done:
+                # not converged after the moves run: its time per converged
+                # environment exceeds the time already spent
+                conv["ratio_lower_bound_full_svd_over_si"] = {
+                    k: round(t_svd / conv[k]["seconds"], 2) for k, _, _ in runs}
+                conv["ratio_if_full_svd_needed_as_many_moves_as_si"] = round(
+                    (growth_s + (conv["si_after_svd_growth"]["moves"] - 1) * 1e-3 * svd["ms_per_move"])
+                    / conv["si_after_svd_growth"]["seconds"], 1)
+            log(f"full-SVD CTMRG: {conv['full_svd']}; ratio lower bound "
+                f"{conv.get('ratio_lower_bound_full_svd_over_si')}")
 
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline (one SI move) ...")
         cpu = cpu_baseline(args, A, X, Y)
         log(f"CPU oracle: {1.0 / cpu['value']:.1f} s per move on {cpu['cores']} threads")
+
+    serve = None
+    if args.serve_requests > 0 and args.prec == "f64":
+        serve = serving(args, args.serve_requests)
+        log(f"serving: {serve['requests']} requests, mu {serve['mu_req_per_s']} req/s, "
+            f"p50 {serve['p50_s']} s, p99 {serve['p99_s']} s")
 
     value = args.steps / elapsed
     out = {
@@ -486,6 +524,7 @@ def main():
         "optimisation_step": opt,
         "converged_environment": conv,
         "speedup_vs_full_svd": None if svd is None else round(value / svd["moves_per_s"], 2),
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

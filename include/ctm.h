@@ -201,8 +201,16 @@ ctm_status ctm_move_poll(ctm_ctx* ctx, int* done, ctm_move_info* info);
  * stream (CTM_E_STATE otherwise).  Off by default. */
 ctm_status ctm_use_graphs(ctm_ctx* ctx, int enable);
 
-/* Moves until delta < tol or max_moves moves were made.  Returns
- * CTM_E_NOT_CONVERGED when the budget ran out (the state stays valid). */
+/* Moves until the environment has converged (QR-based projector section,
+ * step 4: the moves are repeated until C and T converge; Standard CTMRG
+ * section: the environment is iterated to its fixed point): stops after the
+ * first move at the full environment dimension chi whose delta -- the
+ * largest over the four corners of the l2 distance between the unit-norm,
+ * sorted, zero-padded singular values of the corner before and after the
+ * move -- is below tol, or after max_moves moves.  Returns
+ * CTM_E_NOT_CONVERGED when the budget ran out (the state stays valid, and
+ * *moves_done, *last_delta report the moves made and the last delta; either
+ * may be NULL); a failing move's status otherwise. */
 ctm_status ctm_converge(ctm_ctx* ctx, double tol, int max_moves, int* moves_done,
                         double* last_delta);
 
@@ -384,17 +392,21 @@ ctm_status ctm_fixed_point_vjp(ctm_ctx* ctx, const double* state_star, const dou
 ctm_status ctm_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_host, double* e_out,
                           double* state_bar, double* site_bar, void* ws, size_t ws_bytes);
 
-/* The same for any set of bonds: e = sum over the bonds in the mask `bonds`
- * (CTM_BOND_H = 1, CTM_BOND_V = 2, CTM_BOND_D = 4, CTM_BOND_AD = 8; the
- * bonds of CTM_OBS_BOND_H/V/D/AD) of <op>; H + V + D is the energy of the
- * triangular lattice drawn on the square one (triangular-lattice section).
- * The diagonal pair is the 2x2 plaquette through its four enlarged corners,
- * differentiated by hand (2 d^2 products of N x N matrices forward, 4 d^2 in
- * reverse); the anti-diagonal is the diagonal of the turned network.
- * ctm_energy_vjp is this call with bonds = 3.  CTM_E_ARG for an empty or
- * unknown mask. */
+/* The same for any set of bonds, each with its own operator: e = sum over
+ * the bonds in the mask `bonds` (CTM_BOND_H = 1, CTM_BOND_V = 2, CTM_BOND_D
+ * = 4, CTM_BOND_AD = 8; the bonds of CTM_OBS_BOND_H/V/D/AD) of <op_bond>;
+ * H + V + D is the energy of the triangular lattice drawn on the square one
+ * (triangular-lattice section), and with one rotated operator per bond that
+ * of its spiral ansatz.  ops_host holds one d^2 x d^2 operator (layout of
+ * CTM_OBS_BOND_H) per bond of the mask, consecutively in the order H, V, D,
+ * AD (popcount(bonds) * d^4 doubles, host).  The diagonal pair is the 2x2
+ * plaquette through its four enlarged corners, differentiated by hand
+ * (2 d^2 products of N x N matrices forward, 4 d^2 in reverse); the
+ * anti-diagonal is the diagonal of the turned network.  ctm_energy_vjp is
+ * this call with bonds = 3 and the same operator on both bonds.  CTM_E_ARG
+ * for an empty or unknown mask. */
 enum { CTM_BOND_H = 1, CTM_BOND_V = 2, CTM_BOND_D = 4, CTM_BOND_AD = 8 };
-ctm_status ctm_bond_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_host, int bonds,
+ctm_status ctm_bond_energy_vjp(ctm_ctx* ctx, const double* state, const double* ops_host, int bonds,
                                double* e_out, double* state_bar, double* site_bar, void* ws,
                                size_t ws_bytes);
 

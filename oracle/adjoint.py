@@ -32,7 +32,7 @@ from typing import List, Sequence
 import numpy as np
 import torch
 
-from .ctmrg import SIGN_TIE_RTOL, sign_fix_columns
+from .ctmrg import sign_fix_columns
 
 __all__ = ["move_torch", "move_vjp", "si_projectors_torch", "renormalize_torch",
            "enlarged_corners_torch", "double_layer_torch", "energy_torch", "energy_vjp"]
@@ -259,6 +259,3 @@ def energy_vjp(C, T, A, op, bonds: str = "hv"):
     g = torch.autograd.grad(e, Cl + Tl + [Al])
     return float(e.detach()), [x.numpy() for x in g[:4]], [x.numpy() for x in g[4:8]], g[8].numpy()
 
-
-# the sign rule's tie tolerance is shared with the NumPy move
-assert SIGN_TIE_RTOL > 0

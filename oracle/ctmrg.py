@@ -82,7 +82,6 @@ __all__ = [
     "c4v_move",
     "c4v_kappa",
     "c4v_onesite",
-    "move_flops",
 ]
 
 _EIN = dict(optimize=True)
@@ -320,18 +319,18 @@ def renormalize(Ct, env: Env, a: np.ndarray, Pl, Prt) -> Env:
     C = [Prt[(i - 1) % 4].T @ Ct[i] @ Pl[i] for i in range(4)]
     r = lambda P: P.reshape(x, D2, P.shape[1])   # noqa: E731  (chi, D^2, chi')
     # edge j: contract the out pair with P_l, then the site, then P_r
-    z = np.einsum("bug,gry->buyr", T1, r(Pl[0]))
-    z = np.einsum("buyr,uldr->blyd", z, a)
-    T = [np.einsum("blx,blyd->xdy", r(Prt[0]), z)]
-    z = np.einsum("hre,edy->hyrd", T2, r(Pl[1]))
-    z = np.einsum("hyrd,uldr->huyl", z, a)
-    T.append(np.einsum("hux,huyl->xly", r(Prt[1]), z))
-    z = np.einsum("zdn,nly->zydl", T3, r(Pl[2]))
-    z = np.einsum("zydl,uldr->zryu", z, a)
-    T.append(np.einsum("zrx,zryu->xuy", r(Prt[2]), z))
-    z = np.einsum("tla,auy->tylu", T4, r(Pl[3]))
-    z = np.einsum("tylu,uldr->tdyr", z, a)
-    T.append(np.einsum("tdx,tdyr->xry", r(Prt[3]), z))
+    z = np.einsum("bug,gry->buyr", T1, r(Pl[0]), **_EIN)
+    z = np.einsum("buyr,uldr->blyd", z, a, **_EIN)
+    T = [np.einsum("blx,blyd->xdy", r(Prt[0]), z, **_EIN)]
+    z = np.einsum("hre,edy->hyrd", T2, r(Pl[1]), **_EIN)
+    z = np.einsum("hyrd,uldr->huyl", z, a, **_EIN)
+    T.append(np.einsum("hux,huyl->xly", r(Prt[1]), z, **_EIN))
+    z = np.einsum("zdn,nly->zydl", T3, r(Pl[2]), **_EIN)
+    z = np.einsum("zydl,uldr->zryu", z, a, **_EIN)
+    T.append(np.einsum("zrx,zryu->xuy", r(Prt[2]), z, **_EIN))
+    z = np.einsum("tla,auy->tylu", T4, r(Pl[3]), **_EIN)
+    z = np.einsum("tylu,uldr->tdyr", z, a, **_EIN)
+    T.append(np.einsum("tdx,tdyr->xry", r(Prt[3]), z, **_EIN))
     return normalize_env(Env(C, T))
 
 
@@ -767,21 +766,3 @@ def c4v_kappa(C, T, a) -> float:
 
 def c4v_onesite(C, T, a, a_op) -> float:
     return onesite_value(c4v_env(C, T), a, a_op)
-
-
-# --------------------------------------------------------------------------
-# algorithmic work per move (contractions only), in multiply-adds
-# --------------------------------------------------------------------------
-def move_flops(chi: int, D2: int, k: int, n_si: int, stabilized: bool = True) -> dict:
-    """Multiply-add counts of the executed contraction order of one SI move."""
-    N = chi * D2
-    corner = 4 * (chi ** 3 * D2 + chi ** 3 * D2 ** 2 + chi ** 2 * D2 ** 4)
-    si = 4 * (16 * n_si) * N * N * k
-    rho_apps = 4 * 4 * N * N * k
-    rho = 4 * N * k * k
-    proj = 4 * (2 * N * k * chi + 2 * N * k * k)
-    c_ren = 4 * (N * N * chi + N * chi * chi)
-    t_ren = 4 * (2 * chi ** 3 * D2 ** 2 + chi ** 2 * D2 ** 4)
-    return {"corner": corner, "si": si, "rho_apps": rho_apps, "rho": rho,
-            "proj": proj, "c_ren": c_ren, "t_ren": t_ren,
-            "total": corner + si + rho_apps + rho + proj + c_ren + t_ren}

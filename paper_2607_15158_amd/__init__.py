@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -220,6 +221,11 @@ class Ctm:
             self._h = None
 
     def __del__(self):
+        # At interpreter exit the HIP runtime (and a profiler's tool library)
+        # may already be torn down: a context still open then is left to the
+        # process teardown instead of calling into the runtime.
+        if sys.is_finalizing():
+            return
         self.close()
 
     def set_isometries(self, X, Yt):
@@ -351,20 +357,28 @@ class Ctm:
 
     def energy_vjp(self, state, op, site_bar=None, bonds: str = "hv"):
         """e = sum of <op> over ``bonds`` (``h``, ``v``, ``d`` diagonal, ``a``
-        anti-diagonal) at the environment of ``state`` (device tensor, state
-        layout) and its gradient: returns (e, state_bar, site_bar)."""
+        anti-diagonal), or with ``op`` a dict {bond letter: operator} the sum
+        of each bond's own operator, at the environment of ``state`` (device
+        tensor, state layout) and its gradient: returns (e, state_bar,
+        site_bar).  One library call evaluates every bond."""
         import torch
         ws = self._ensure_vjp_ws()
         dev = self._site.device
         st = state.to(dev, torch.float64).contiguous()
-        opb = np.ascontiguousarray(op, dtype=np.float64)
+        if isinstance(op, dict):
+            bonds = "".join(sorted(op, key="hvda".index))
+        mask = bond_mask(bonds)
+        # one operator per bond of the mask, in the order H, V, D, AD
+        order = [b for b in "hvda" if mask & BOND_BITS[b]]
+        ops = np.ascontiguousarray(np.stack([np.asarray(op[b] if isinstance(op, dict) else op,
+                                                        dtype=np.float64) for b in order]))
         e = ctypes.c_double(0.0)
         bar = torch.empty_like(st)
         if site_bar is None:
             site_bar = torch.zeros_like(self._site)
-        _check(_lib.ctm_bond_energy_vjp(self._h, st.data_ptr(), opb.ctypes.data_as(_dp),
-                                        bond_mask(bonds), ctypes.byref(e), bar.data_ptr(),
-                                        site_bar.data_ptr(), ws.data_ptr(), ws.numel()), self._h)
+        _check(_lib.ctm_bond_energy_vjp(self._h, st.data_ptr(), ops.ctypes.data_as(_dp), mask,
+                                        ctypes.byref(e), bar.data_ptr(), site_bar.data_ptr(),
+                                        ws.data_ptr(), ws.numel()), self._h)
         return e.value, bar, site_bar
 
     def energy_gradient(self, op, tol: float = 1e-12, max_iter: int = 400, bonds: str = "hv"):
@@ -376,14 +390,7 @@ class Ctm:
         (e, dE/dA as a device tensor, passes of the fixed-point series)."""
         import torch
         star = torch.from_numpy(self.get_state()).to(self._site.device)
-        if isinstance(op, dict):
-            e, g, site_bar = 0.0, None, torch.zeros_like(self._site)
-            for bd, opb in op.items():
-                eb, gb, site_bar = self.energy_vjp(star, opb, site_bar, bonds=bd)
-                e += eb
-                g = gb if g is None else g + gb
-        else:
-            e, g, site_bar = self.energy_vjp(star, op, bonds=bonds)
+        e, g, site_bar = self.energy_vjp(star, op, bonds=bonds)
         _, site_bar, passes, _ = self.fixed_point_vjp(star, g, tol, max_iter, site_bar)
         return e, site_bar, passes
 
@@ -493,14 +500,7 @@ def unrolled_energy(A, cfg: Config, op, state0, moves: int, bonds: str = "hv"):
             for _ in range(moves):
                 c.move()
                 states.append(c.get_state_device())
-            if isinstance(op, dict):
-                e, bar, site_bar = 0.0, None, None
-                for bd, opb in op.items():
-                    eb, bb, site_bar = c.energy_vjp(states[-1], opb, site_bar, bonds=bd)
-                    e += eb
-                    bar = bb if bar is None else bar + bb
-            else:
-                e, bar, site_bar = c.energy_vjp(states[-1], op, bonds=bonds)
+            e, bar, site_bar = c.energy_vjp(states[-1], op, bonds=bonds)
             for st in reversed(states[:-1]):
                 bar, _, site_bar = c.move_vjp(st, bar, want_out=False, site_bar=site_bar)
             ctx.save_for_backward(site_bar)
@@ -588,7 +588,7 @@ def optimize_lbfgs(A0, cfg: Config, bond_ops: dict, iterations: int = 10, tol: f
     Yt0`` (4 x N x k) or the library's start blocks.  ``bond_ops``: {bond
     letter: operator}, e.g. from :func:`spiral_bond_operators`.  Returns the
     optimised tensor (device) and the history of (energy, gradient norm,
-    CTMRG moves) per evaluation."""
+    CTMRG moves, the evaluated site tensor as a host array) per evaluation."""
     import torch
     A = A0.detach().clone().to(torch.float64).requires_grad_(True)
     opt = torch.optim.LBFGS([A], lr=1.0, max_iter=iterations, history_size=history_size,
@@ -609,7 +609,7 @@ def optimize_lbfgs(A0, cfg: Config, bond_ops: dict, iterations: int = 10, tol: f
         prev["state"] = c.get_state()
         c.close()
         A.grad = grad.detach().clone()
-        history.append((e, float(grad.norm()), r["moves"]))
+        history.append((e, float(grad.norm()), r["moves"], A.detach().cpu().numpy().copy()))
         return torch.tensor(e, dtype=torch.float64)
 
     opt.step(closure)
@@ -688,10 +688,9 @@ class Server:
             self._h = _vp()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        if sys.is_finalizing():
+            return
+        self.close()
 
 
 def gemm_f64(A: Sequence, B: Sequence, C: Sequence, M, N, K, trans_a=0, lda=None, ldb=None,

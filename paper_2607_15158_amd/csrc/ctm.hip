@@ -2050,6 +2050,8 @@ int vjp_view(ctm_ctx* c, VjpView* v) {
 
 int vjp_fail(ctm_ctx* c, int code, const std::string& msg) { return fail(c, code, msg); }
 
+int ctx_phys_dim(const ctm_ctx* c) { return c->d; }
+
 }  // namespace sictm
 
 extern "C" {

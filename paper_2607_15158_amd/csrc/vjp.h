@@ -24,5 +24,7 @@ struct VjpView {
 int vjp_view(ctm_ctx* c, VjpView* v);
 // Records msg as the context's last error and returns code.
 int vjp_fail(ctm_ctx* c, int code, const std::string& msg);
+// Physical dimension d of the context's site tensor.
+int ctx_phys_dim(const ctm_ctx* c);
 
 }  // namespace sictm

@@ -2160,7 +2160,9 @@ int pq_bwd(Run& r, const Dims& m, EBufs& b, const double* const* C, const double
   return 0;
 }
 
-int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, int bonds,
+// ops[dir] is the d^2 x d^2 operator of bond dir (0 H, 1 V, 2 D, 3 AD) for
+// every dir in the mask `bonds`.
+int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* const* ops, int bonds,
                     double* e_out, double* state_bar, double* site_bar, void* ws, size_t ws_bytes) {
   VjpView v;
   int rc = vjp_view(ctx, &v);
@@ -2210,7 +2212,7 @@ int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, in
   }
   VTRY(fill(r, state_bar, (long)nstate, 0.0));
   const int n = b.n;
-  std::vector<double> op(op_host, op_host + n * n), E(n * n), Eb;
+  std::vector<double> E(n * n), Eb;
   double total = 0.0;
   for (int dir = 0; dir < 4; ++dir) {
     // dir 0: horizontal pair; dir 1: vertical pair = horizontal pair of the
@@ -2245,6 +2247,7 @@ int energy_vjp_impl(ctm_ctx* ctx, const double* state, const double* op_host, in
       VTRY(pq_fwd(r, m, b, Cs, Ts));
     CTM_HIP_TRY(hipMemcpyAsync(E.data(), b.E, n * n * sizeof(double), hipMemcpyDeviceToHost, r.st));
     CTM_HIP_TRY(hipStreamSynchronize(r.st));
+    const std::vector<double> op(ops[dir], ops[dir] + n * n);
     total += bond_value_and_bar(E, op.data(), m.d, Eb);
     CTM_HIP_TRY(hipMemcpyAsync(b.Eb, Eb.data(), n * n * sizeof(double), hipMemcpyHostToDevice, r.st));
     for (int st = 0; st < n; ++st) VTRY(fill(r, b.xb[st], (long)Dl * Dl * Dl * Dl, 0.0));
@@ -2280,14 +2283,14 @@ ctm_status ctm_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_ho
     set_thread_error("null argument");
     return CTM_E_ARG;
   }
-  return (ctm_status)energy_vjp_impl(ctx, state, op_host, 3, e_out, state_bar, site_bar, ws,
-                                     ws_bytes);
+  const double* ops[4] = {op_host, op_host, nullptr, nullptr};
+  return (ctm_status)energy_vjp_impl(ctx, state, ops, 3, e_out, state_bar, site_bar, ws, ws_bytes);
 }
 
-ctm_status ctm_bond_energy_vjp(ctm_ctx* ctx, const double* state, const double* op_host, int bonds,
+ctm_status ctm_bond_energy_vjp(ctm_ctx* ctx, const double* state, const double* ops_host, int bonds,
                                double* e_out, double* state_bar, double* site_bar, void* ws,
                                size_t ws_bytes) {
-  if (!ctx || !state || !op_host || !state_bar || !site_bar || !ws) {
+  if (!ctx || !state || !ops_host || !state_bar || !site_bar || !ws) {
     set_thread_error("null argument");
     return CTM_E_ARG;
   }
@@ -2295,7 +2298,16 @@ ctm_status ctm_bond_energy_vjp(ctm_ctx* ctx, const double* state, const double* 
     set_thread_error("bonds must be a non-empty mask of H = 1, V = 2, D = 4, AD = 8");
     return CTM_E_ARG;
   }
-  return (ctm_status)energy_vjp_impl(ctx, state, op_host, bonds, e_out, state_bar, site_bar, ws,
+  // one d^2 x d^2 operator per bond of the mask, in the order H, V, D, AD
+  const long n2 = (long)ctx_phys_dim(ctx) * ctx_phys_dim(ctx);
+  const double* ops[4] = {nullptr, nullptr, nullptr, nullptr};
+  long o = 0;
+  for (int dir = 0; dir < 4; ++dir)
+    if (bonds & (1 << dir)) {
+      ops[dir] = ops_host + o;
+      o += n2 * n2;
+    }
+  return (ctm_status)energy_vjp_impl(ctx, state, ops, bonds, e_out, state_bar, site_bar, ws,
                                      ws_bytes);
 }
 

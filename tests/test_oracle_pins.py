@@ -545,3 +545,158 @@ def test_randomized_growth_reaches_the_same_fixed_point():
         assert hist[-1]["delta"] < 1e-12
         out[growth] = (O.bond_value(env, A, h, "h"), O.bond_value(env, A, h, "v"), O.kappa(env, a))
     assert np.allclose(out["si"], out["svd"], rtol=1e-10, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# the convergence measure (QR-based projector section, step 4: the corners
+# and edges converge element-wise; the reading used is the largest over the
+# four corners of the l2 distance of their unit-norm, sorted, zero-padded
+# singular-value spectra between two moves)
+# --------------------------------------------------------------------------
+def _env_with_corners(Cs, chi_t=3, D2=2):
+    T = [np.ones((c.shape[0], D2, c.shape[0])) for c in Cs]
+    return O.Env([np.asarray(c, dtype=float) for c in Cs], T)
+
+
+def test_delta_of_a_hand_computed_pair():
+    """Corner 1 goes from diag(1, 0) to diag(3, 4): its unit spectrum moves
+    from (1, 0) to (0.8, 0.6), an l2 step of sqrt(0.04 + 0.36) = sqrt(0.4).
+    Corner 2 goes from diag(1, 1) to diag(1, 0): (1, 1)/sqrt(2) -> (1, 0), a
+    step of sqrt((1 - 1/sqrt2)^2 + 1/2) = sqrt(2 - sqrt2).  Corners 3 and 4
+    are unchanged.  The largest step is corner 2's."""
+    I2 = np.eye(2)
+    old = _env_with_corners([np.diag([1.0, 0.0]), I2, I2, 2 * I2])
+    new = _env_with_corners([np.diag([3.0, 4.0]), np.diag([1.0, 0.0]), I2, 2 * I2])
+    chi = 2
+    s_old, s_new = O.corner_spectra(old, chi), O.corner_spectra(new, chi)
+    assert np.allclose(s_new[0], [0.8, 0.6], atol=1e-15)
+    assert np.allclose(s_old[1], [2 ** -0.5, 2 ** -0.5], atol=1e-15)
+    step = [np.sqrt(0.4), np.sqrt(2.0 - np.sqrt(2.0)), 0.0, 0.0]
+    assert abs(O.spectrum_delta(s_new, s_old) - max(step)) <= 1e-15
+    # a change on corner 1 alone: the max picks it, not the mean over corners
+    new1 = _env_with_corners([np.diag([3.0, 4.0]), I2, I2, 2 * I2])
+    assert abs(O.spectrum_delta(O.corner_spectra(new1, chi), s_old) - np.sqrt(0.4)) <= 1e-15
+
+
+def test_delta_vanishes_at_a_fixed_point_and_ignores_scale_and_gauge():
+    rng = np.random.default_rng(3)
+    chi = 6
+    Cs = [rng.standard_normal((chi, chi)) for _ in range(4)]
+    env = _env_with_corners(Cs)
+    s = O.corner_spectra(env, chi)
+    assert O.spectrum_delta(s, s) == 0.0
+    # the spectra are unit-norm: rescaling a corner changes nothing
+    scaled = _env_with_corners([c * f for c, f in zip(Cs, (7.0, 1e-3, 2.0, 1.0))])
+    assert O.spectrum_delta(O.corner_spectra(scaled, chi), s) <= 1e-15
+    # an orthogonal change of basis on either leg of a corner leaves its spectrum
+    gauged = _env_with_corners([S.random_orthogonal(chi, 10 + i) @ c @ S.random_orthogonal(chi, 20 + i)
+                                for i, c in enumerate(Cs)])
+    assert O.spectrum_delta(O.corner_spectra(gauged, chi), s) <= 1e-14
+    # every unit spectrum has norm 1 and is sorted in descending order
+    assert np.allclose(np.linalg.norm(s, axis=1), 1.0, atol=1e-15)
+    assert np.all(np.diff(s, axis=1) <= 0)
+
+
+def test_delta_zero_pads_a_growing_environment():
+    """While chi_env < chi the spectrum is padded with zeros: a 2x2 corner
+    diag(1, 1) next to a 4x4 corner diag(1, 1, 0, 0) is the same spectrum
+    (distance 0), and against diag(1, 1, 1, 1) the distance is
+    |(1/sqrt2, 1/sqrt2, 0, 0) - (1/2, 1/2, 1/2, 1/2)| = sqrt(2 - sqrt2)."""
+    chi = 4
+    small = _env_with_corners([np.eye(2)] * 4)
+    s_small = O.corner_spectra(small, chi)
+    assert s_small.shape == (4, chi) and np.all(s_small[:, 2:] == 0.0)
+    same = _env_with_corners([np.diag([1.0, 1.0, 0.0, 0.0])] * 4)
+    assert O.spectrum_delta(O.corner_spectra(same, chi), s_small) <= 1e-15
+    full = _env_with_corners([np.eye(4)] * 4)
+    d = O.spectrum_delta(O.corner_spectra(full, chi), s_small)
+    assert abs(d - np.sqrt(2.0 - np.sqrt(2.0))) <= 1e-15
+
+
+def test_planted_delta_mistakes_are_caught(monkeypatch):
+    """The hand-computed pair above fails for the plausible mistakes of the
+    measure: the mean over corners instead of the largest, an l1 or mean
+    absolute step instead of the l2 one, and spectra not scaled to unit norm."""
+    import oracle.ctmrg as mod
+    I2 = np.eye(2)
+    old = _env_with_corners([np.diag([1.0, 0.0]), I2, I2, 2 * I2])
+    new = _env_with_corners([np.diag([3.0, 4.0]), np.diag([1.0, 0.0]), I2, 2 * I2])
+    expect = np.sqrt(2.0 - np.sqrt(2.0))
+
+    def value():
+        return mod.spectrum_delta(mod.corner_spectra(new, 2), mod.corner_spectra(old, 2))
+
+    assert abs(value() - expect) <= 1e-15
+    good_delta, good_spec = mod.spectrum_delta, mod.corner_spectra
+    wrong = {
+        "mean over corners": lambda a, b: float(np.mean(np.linalg.norm(a - b, axis=1))),
+        "mean abs step": lambda a, b: float(np.max(np.mean(np.abs(a - b), axis=1))),
+        "l1 step": lambda a, b: float(np.max(np.sum(np.abs(a - b), axis=1))),
+        "mean abs over everything": lambda a, b: float(np.mean(np.abs(a - b))),
+    }
+    for name, f in wrong.items():
+        monkeypatch.setattr(mod, "spectrum_delta", f)
+        assert abs(value() - expect) > 1e-3, name
+    monkeypatch.setattr(mod, "spectrum_delta", good_delta)
+
+    def unnormalised(env, chi):
+        out = np.zeros((4, chi))
+        for i, c in enumerate(env.C):
+            s = np.linalg.svd(c, compute_uv=False)
+            out[i, :min(chi, s.size)] = s[:chi]
+        return out
+
+    monkeypatch.setattr(mod, "corner_spectra", unnormalised)
+    assert abs(value() - expect) > 1e-3
+    monkeypatch.setattr(mod, "corner_spectra", good_spec)
+
+
+# --------------------------------------------------------------------------
+# the double layer with an operator on the physical leg (iPEPS section)
+# --------------------------------------------------------------------------
+def test_operator_double_layer_of_a_product_state():
+    """For A = phi (x) v (x) v (x) v (x) v the operator double layer is
+    (phi^T O phi) times the plain double layer of v alone, so the one-site
+    value is phi^T O phi / phi^T phi: for phi = (cos t, sin t) that is
+    <sigma^x> = sin 2t and <sigma^z> = cos 2t (nonzero, so a scale or a
+    missing factor shows)."""
+    t = 0.3
+    phi = np.array([np.cos(t), np.sin(t)])
+    v = np.array([0.7, -0.4, 0.2])
+    A = np.einsum("s,u,l,d,r->suldr", phi, v, v, v, v)
+    a = O.double_layer(A)
+    vv = np.outer(v, v).ravel()
+    a_v = np.einsum("i,j,k,l->ijkl", vv, vv, vv, vv)
+    assert np.allclose(a, a_v, atol=1e-15)           # phi^T phi = 1
+    iy = np.array([[0.0, -1.0], [1.0, 0.0]])          # i sigma^y: real, antisymmetric
+    for op, exact in ((S.pauli("x"), np.sin(2 * t)), (S.pauli("z"), np.cos(2 * t)), (iy, 0.0)):
+        ao = O.double_layer_op(A, op)
+        assert np.allclose(ao, exact * a_v, atol=1e-15)
+    # through the converged environment of the product state
+    chi = 9
+    env, _ = O.run_ctmrg(a, S.trace_boundary(3), chi, proj="svd", max_moves=3)
+    assert abs(O.onesite_value(env, a, O.double_layer_op(A, S.pauli("x"))) - np.sin(2 * t)) <= 1e-13
+    assert abs(O.onesite_value(env, a, O.double_layer_op(A, S.pauli("z"))) - np.cos(2 * t)) <= 1e-13
+
+
+def test_operator_double_layer_of_a_two_term_state():
+    """A = phi1 (x) v^4 + phi2 (x) w^4 with orthonormal v, w on every
+    virtual leg: the double layer with O is sum_ij (phi_i^T O phi_j)
+    (v_i v_j)^4 where v_1 = v, v_2 = w, so the operator's matrix elements
+    between the two physical states appear in the four blocks; picking the
+    (v v) and (v w) entries recovers phi1^T O phi1 and phi1^T O phi2 (with
+    the ket on the first index), which pins the ket/bra order of O[t, s]."""
+    rng = np.random.default_rng(9)
+    phi1, phi2 = rng.standard_normal(2), rng.standard_normal(2)
+    v, w = np.array([1.0, 0.0]), np.array([0.0, 1.0])
+    A = (np.einsum("s,u,l,d,r->suldr", phi1, v, v, v, v) +
+         np.einsum("s,u,l,d,r->suldr", phi2, w, w, w, w))
+    O_ = np.array([[0.3, -1.1], [0.5, 0.2]])   # O[t, s]: bra t, ket s
+    ao = O.double_layer_op(A, O_).reshape(2, 2, 2, 2, 2, 2, 2, 2)
+    # ket legs all on v (index 0), bra legs all on v: phi1 (bra) O phi1 (ket)
+    assert abs(ao[0, 0, 0, 0, 0, 0, 0, 0] - phi1 @ O_ @ phi1) <= 1e-15
+    # ket legs on v (0), bra legs on w (1): bra phi2, ket phi1 -> phi2^T O phi1
+    assert abs(ao[0, 1, 0, 1, 0, 1, 0, 1] - phi2 @ O_ @ phi1) <= 1e-15
+    assert abs(ao[1, 0, 1, 0, 1, 0, 1, 0] - phi1 @ O_ @ phi2) <= 1e-15
+    # mixed leg patterns vanish (each virtual leg sees v on one term only)
+    assert ao[0, 0, 1, 1, 0, 0, 0, 0] == 0.0
