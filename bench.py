@@ -133,8 +133,9 @@ def serving(args, n_requests):
         reqs.append((cfg, S.product_plus_noise_site(2, D, 4000 + i)))
     h = S.heisenberg_bond()
 
-    def run(arrivals):
-        srv = P.Server(arena_bytes=args.serve_arena_gb << 30, max_slots=args.serve_slots)
+    def run(arrivals, batch_n):
+        srv = P.Server(arena_bytes=args.serve_arena_gb << 30, max_slots=args.serve_slots,
+                       batch_max_n=batch_n)
         t0 = srv.clock()
         ids, nxt, done_log = [None] * len(reqs), 0, 0
         while True:
@@ -156,29 +157,43 @@ def serving(args, n_requests):
         srv.close()
         return res, span
 
-    log(f"serving phase 1: {len(reqs)} requests at t = 0")
-    res1, span1 = run([0.0] * len(reqs))
-    mu = len(reqs) / span1
-    lam = 0.7 * mu
-    gaps = np.random.default_rng(44).exponential(1.0 / lam, size=len(reqs))
-    arrivals = np.cumsum(gaps) - gaps[0]
-    log(f"serving phase 2: Poisson arrivals at lambda = {lam:.3f} req/s (mu = {mu:.3f})")
-    res2, span2 = run(list(arrivals))
-    lat = np.array([r["t_done"] - r["t_submit"] for r in res2])
-    failed = sum(r["state"] != "done" for r in res2)
-    same = all(a["kappa"] == b["kappa"] and a["bond_h"] == b["bond_h"] and a["moves"] == b["moves"]
-               for a, b in zip(res1, res2))
-    return {"metric": "serving latency p50/p99 of mixed (D, chi) environment solves",
-            "value": round(len(reqs) / span2, 4), "unit": "requests/s", "n_gpus": 1,
-            "requests": len(reqs), "mu_req_per_s": round(mu, 4), "lambda_req_per_s": round(lam, 4),
-            "p50_s": round(float(np.percentile(lat, 50)), 4),
-            "p99_s": round(float(np.percentile(lat, 99)), 4),
-            "mean_moves": round(float(np.mean([r["moves"] for r in res2])), 2),
-            "converged": int(sum(r["converged"] for r in res2)), "failed": int(failed),
-            "results_identical_across_phases": bool(same),
-            "slots": args.serve_slots, "arena_gb": args.serve_arena_gb,
-            "max_moves": args.serve_moves, "dtype": "f64", "data": "synthetic",
-            "higher_is_better": True}
+    out = {"metric": "serving latency p50/p99 of mixed (D, chi) environment solves",
+           "unit": "requests/s", "n_gpus": 1, "requests": len(reqs), "slots": args.serve_slots,
+           "arena_gb": args.serve_arena_gb, "max_moves": args.serve_moves, "dtype": "f64",
+           "data": "synthetic", "higher_is_better": True}
+    results = {}
+    modes = (("per_stream", 0), ("batched", args.serve_batch_n))
+    for name, batch_n in modes:
+        log(f"serving ({name}) phase 1: {len(reqs)} requests at t = 0")
+        res1, span1 = run([0.0] * len(reqs), batch_n)
+        mu = len(reqs) / span1
+        lam = 0.7 * mu
+        gaps = np.random.default_rng(44).exponential(1.0 / lam, size=len(reqs))
+        arrivals = np.cumsum(gaps) - gaps[0]
+        log(f"serving ({name}) phase 2: Poisson arrivals at lambda = {lam:.3f} req/s "
+            f"(mu = {mu:.3f})")
+        res2, span2 = run(list(arrivals), batch_n)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res2])
+        same = all(a["kappa"] == b["kappa"] and a["bond_h"] == b["bond_h"] and
+                   a["moves"] == b["moves"] for a, b in zip(res1, res2))
+        results[name] = (res1, res2)
+        out[name] = {"value": round(len(reqs) / span2, 4), "mu_req_per_s": round(mu, 4),
+                     "lambda_req_per_s": round(lam, 4),
+                     "p50_s": round(float(np.percentile(lat, 50)), 4),
+                     "p99_s": round(float(np.percentile(lat, 99)), 4),
+                     "mean_moves": round(float(np.mean([r["moves"] for r in res2])), 2),
+                     "converged": int(sum(r["converged"] for r in res2)),
+                     "failed": int(sum(r["state"] != "done" for r in res2)),
+                     "results_identical_across_phases": bool(same),
+                     "batch_max_n": batch_n}
+        log(f"serving ({name}): mu {mu:.3f} req/s, p50 {out[name]['p50_s']} s, "
+            f"p99 {out[name]['p99_s']} s")
+    a, b = results["per_stream"][0], results["batched"][0]
+    out["batched_results_identical_to_per_stream"] = bool(all(
+        x["kappa"] == y["kappa"] and x["bond_h"] == y["bond_h"] and x["moves"] == y["moves"]
+        for x, y in zip(a, b)))
+    out["value"] = out["batched"]["value"]
+    return out
 
 
 def main():
@@ -239,6 +254,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-arena-gb", type=int, default=96)
     ap.add_argument("--serve-moves", type=int, default=60)
+    ap.add_argument("--serve-batch-n", type=int, default=1296,
+                    help="requests with chi * D^2 up to this move together in grouped launches "
+                         "(ctm_move_batch) in the batched serving mode")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving sub-measurement of the default run (0: skip)")
     args = ap.parse_args()
@@ -497,8 +515,7 @@ def main():
     serve = None
     if args.serve_requests > 0 and args.prec == "f64":
         serve = serving(args, args.serve_requests)
-        log(f"serving: {serve['requests']} requests, mu {serve['mu_req_per_s']} req/s, "
-            f"p50 {serve['p50_s']} s, p99 {serve['p99_s']} s")
+
 
     value = args.steps / elapsed
     out = {

@@ -66,8 +66,17 @@ typedef enum { CTM_PROJ_FULLSVD = 0, CTM_PROJ_SI = 1 } ctm_proj;
 typedef enum { CTM_SYM_NONE = 0, CTM_SYM_C4V = 1 } ctm_sym;
 
 /* Precision of the contractions only; QR, small SVD, pseudo-inverse,
- * projector scaling and the stored environment are always float64. */
-typedef enum { CTM_PREC_F64 = 0, CTM_PREC_F32 = 1, CTM_PREC_BF16 = 2 } ctm_prec;
+ * projector scaling and the stored environment are always float64.
+ * CTM_PREC_BF16X3: split bfloat16 -- the contraction operands are kept in
+ * float32 and each is written as hi + lo bfloat16 inside the GEMM, whose
+ * product is the sum of the three bf16 matrix-core products hi*hi + hi*lo +
+ * lo*hi with float32 accumulation (about 16 significant bits per operand). */
+typedef enum {
+  CTM_PREC_F64 = 0,
+  CTM_PREC_F32 = 1,
+  CTM_PREC_BF16 = 2,
+  CTM_PREC_BF16X3 = 3
+} ctm_prec;
 
 typedef enum {
   CTM_OBS_NORM = 0,    /* out[0] = kappa = Z11 Z00 / (Z10 Z01), out[1..4] = Z11,Z00,Z10,Z01 */
@@ -193,6 +202,26 @@ ctm_status ctm_move_async(ctm_ctx* ctx);
  * when no move is in flight; CTM_E_NUMERIC as for ctm_move. */
 ctm_status ctm_move_poll(ctm_ctx* ctx, int* done, ctm_move_info* info);
 
+/* One move of each of n contexts (serving pattern: environment solves of
+ * mixed (D, chi) moved together).  The SI moves of float64 contexts without
+ * lattice symmetry are recorded and launched together on the stream of the
+ * first such context: at every step of the move the float64 GEMMs of all of
+ * them (the enlarged corners, the SI applications, rho, the projectors and
+ * the renormalisation) run as one persistent grouped launch over a device
+ * table of (problem, tile) work items, and the other operations (QR, SVD,
+ * signs, norms, spectra) follow one after another.  Each context's results
+ * are bit for bit those of ctm_move (the tile kernels' sums do not depend on
+ * the grid; the split SI product keeps its own launch).  Other moves
+ * (growth, full SVD, C4v, float32/bfloat16) run as ctm_move_async on their
+ * own streams.  Work queued earlier on a batched context's own stream is
+ * waited for first.  infos (n entries) or NULL; returns the first error
+ * after every enqueued move has completed.  A context may appear once. */
+ctm_status ctm_move_batch(ctm_ctx* const* ctxs, int n, ctm_move_info* infos);
+
+/* As ctm_move_batch without waiting: every context then has a move in
+ * flight, completed through ctm_move_poll (or any call that reads it). */
+ctm_status ctm_move_batch_async(ctm_ctx* const* ctxs, int n);
+
 /* Enables (1) or disables (0) graph replay of SI moves.  With graphs on, the
  * device work of an SI move is captured into a HIP graph the first time a
  * given buffer arrangement occurs (two arrangements alternate) and replayed
@@ -308,6 +337,14 @@ ctm_status ctm_server_submit(ctm_server* server, const ctm_config* cfg, const do
                              const double* boundary_host, const double* X0_host,
                              const double* Yt0_host, const double* op_host, double tol,
                              int max_moves, int* id);
+
+/* Batched moves in the server: from now on, the SI moves of running float64
+ * requests with chi * Dl <= max_n are made together through
+ * ctm_move_batch_async (one grouped launch per GEMM step over all of them)
+ * instead of each on its slot stream with graph replay; 0 (the default)
+ * turns it off.  Results do not change (ctm_move_batch gives the bits of
+ * ctm_move). */
+ctm_status ctm_server_batching(ctm_server* server, int max_n);
 
 /* Non-blocking progress (see above); n_running and n_queued may be NULL. */
 ctm_status ctm_server_pump(ctm_server* server, int* n_running, int* n_queued);

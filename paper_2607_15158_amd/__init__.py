@@ -35,7 +35,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 CTM_OK, CTM_E_ARG, CTM_E_SHAPE, CTM_E_NOMEM, CTM_E_DEVICE, CTM_E_NUMERIC, \
     CTM_E_NOT_CONVERGED, CTM_E_STATE = range(8)
 PROJ = {"svd": 0, "fullsvd": 0, "si": 1}
-PREC = {"f64": 0, "f32": 1, "bf16": 2}
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 SVD_DRIVER = {"gesvd": 0, "gesdd": 1, "gesvdx": 2}
 GROWTH = {"svd": 0, "si": 1}
 SYM = {"none": 0, "c4v": 1}
@@ -82,11 +82,14 @@ _sigs = {
     "ctm_move_async": (ctypes.c_int, [_vp]),
     "ctm_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ctm_move_poll": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctm_move_info)]),
+    "ctm_move_batch": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctm_move_info)]),
+    "ctm_move_batch_async": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
     "ctm_server_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_int]),
     "ctm_server_destroy": (None, [_vp]),
     "ctm_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(ctm_config), _dp, _dp, _dp, _dp, _dp,
                                          ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "ctm_server_pump": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ctm_server_batching": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ctm_server_result": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctm_result)]),
     "ctm_server_error": (ctypes.c_char_p, [_vp, ctypes.c_int]),
     "ctm_server_clock": (ctypes.c_double, [_vp]),
@@ -648,11 +651,13 @@ class Server:
 
     STATES = ("queued", "running", "done", "failed")
 
-    def __init__(self, arena_bytes: int, max_slots: int):
+    def __init__(self, arena_bytes: int, max_slots: int, batch_max_n: int = 0):
         self._h = _vp()
         st = _lib.ctm_server_create(ctypes.byref(self._h), int(arena_bytes), int(max_slots))
         if st != CTM_OK:
             raise CtmError(st, "ctm_server_create failed")
+        if batch_max_n:
+            _check(_lib.ctm_server_batching(self._h, int(batch_max_n)))
 
     def submit(self, cfg: Config, site, boundary=None, X0=None, Yt0=None, op=None,
                tol: float = 1e-10, max_moves: int = 100) -> int:
@@ -691,6 +696,19 @@ class Server:
         if sys.is_finalizing():
             return
         self.close()
+
+
+def move_batch(ctxs: Sequence["Ctm"]) -> list:
+    """One move of every context, SI moves of float64 contexts batched into
+    grouped launches (ctm_move_batch); returns each move's info."""
+    n = len(ctxs)
+    hs = (_vp * n)(*[c._h for c in ctxs])
+    infos = (ctm_move_info * n)()
+    st = _lib.ctm_move_batch(hs, n, infos)
+    if st != CTM_OK:
+        raise CtmError(st, _lib.ctm_last_error(None).decode())
+    return [{"delta": i.delta, "mode": i.mode, "chi_env": i.chi_env, "gap": i.gap,
+             "n_si": i.n_si, "sin2": i.sin2} for i in infos]
 
 
 def gemm_f64(A: Sequence, B: Sequence, C: Sequence, M, N, K, trans_a=0, lda=None, ldb=None,

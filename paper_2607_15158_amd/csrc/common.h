@@ -89,6 +89,7 @@ struct GemmBatch {
   long a_bs, b_bs, c_bs;
   double alpha;
   int accumulate;     // 1: C += alpha*AB
+  int split;          // 1: float32 operands as hi + lo bfloat16, three bf16 products
 };
 
 // Element types of a GEMM launch.
@@ -119,6 +120,25 @@ int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStr
 // rounded to float32, float32 accumulation); other shapes fall back to
 // launch_gemm.
 int launch_gemm_si_f32(const GemmBatch& g, hipStream_t s);
+
+// Grouped float64 GEMMs: one persistent launch over the products of several
+// descriptors of different shapes (see gemm.hip).  Each descriptor's work
+// items are (tile, problem, inner batch) in the order of its own launch;
+// `first` is the prefix sum over the descriptors before it.
+struct GroupItem {
+  GemmBatch g;
+  int tiles_m, tiles_n;
+  long first;
+};
+// Tile kernel for a group (0: the 96 x 160 skinny tile, which needs N <= 160
+// and 16-byte aligned rows in every descriptor; else an index into the
+// generic tile shapes), chosen from the descriptors.
+int grouped_kind(const GemmBatch* gs, int n);
+// Fills items[0..n) for the kind and returns the total number of work items.
+long grouped_fill(const GemmBatch* gs, int n, int kind, GroupItem* items);
+// Launches the group whose descriptors (filled by grouped_fill) are in
+// device memory at dev_items.
+int launch_gemm_grouped(const GroupItem* dev_items, int n, long total, int kind, hipStream_t s);
 
 // Householder QR (in place, Q returned with R_ii >= 0) of `count` N x k
 // row-major matrices.  ws must hold qr_workspace_bytes(count, N, k) bytes.

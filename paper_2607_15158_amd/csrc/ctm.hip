@@ -29,7 +29,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -80,12 +82,22 @@ enum ProfClass { PC_CORNER = 0, PC_SI_APPLY, PC_QR, PC_SVD, PC_PROJ, PC_RENORM, 
 const char* kProfNames[PC_N] = {"corner_build", "si_apply", "householder_qr", "jacobi_svd",
                                 "projector_gemm", "renormalise", "full_svd", "misc"};
 
+// One operation of a recorded move (a batched move records the device work
+// of each context's move, then launches the float64 GEMMs of the same step
+// of every context as one grouped launch and the other operations in turn).
+struct BatchOp {
+  bool gemm;                              // a float64 GEMM that may be grouped
+  GemmBatch g;
+  std::function<int(hipStream_t)> fn;     // any other launch, on the given stream
+};
+
 }  // namespace
 
 struct ctm_ctx {
   ctm_config cfg;
   int d, D, Dl, chi, k, N, xmax, Nmax;
   DT cp;
+  bool split = false;        // contractions as split bfloat16 products (cp = F32 storage)
   hipStream_t st;
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -171,6 +183,8 @@ struct ctm_ctx {
   size_t ev_next = 0;
   // carved buffers, for the host-side bounds check of every GEMM launch
   std::vector<std::pair<uintptr_t, uintptr_t>> bufs;
+  // while a batched move records this context's work: its operations
+  std::vector<BatchOp>* rec = nullptr;
 };
 
 namespace {
@@ -191,13 +205,39 @@ int fail(ctm_ctx* c, int code, const std::string& msg) {
     }                                                                \
   } while (0)
 
+// Device work of a move other than a float64 GEMM: launched on the
+// context's stream, or, while a batched move records the context, kept as an
+// operation (`st` names the stream inside the expression; its arguments are
+// evaluated when it runs, so anything the recording changes afterwards -- the
+// block pointers -- is copied into locals first).
+#define ENQ(expr)                                                                 \
+  do {                                                                            \
+    if (c->rec) {                                                                 \
+      c->rec->push_back(BatchOp{false, GemmBatch{}, [=](hipStream_t st) -> int {  \
+                                  return (expr);                                  \
+                                }});                                              \
+    } else {                                                                      \
+      hipStream_t st = c->st;                                                     \
+      TRY(expr);                                                                  \
+    }                                                                             \
+  } while (0)
+
+int hrc(hipError_t e) { return e == hipSuccess ? 0 : hip_fail(e, "stream operation", __LINE__); }
+
+// Propagates a launcher code where no single context is concerned.
+#define TRY_B(expr)                                  \
+  do {                                               \
+    int _r = (expr);                                 \
+    if (_r != 0) return _r == 1 ? (int)CTM_E_ARG : _r; \
+  } while (0)
+
 int validate(const ctm_config* cfg) {
   if (!cfg) return fail(nullptr, CTM_E_ARG, "null config");
   if (cfg->d < 0 || cfg->D < 1 || cfg->chi < 1 || cfg->p < 0 || cfg->n_si < 0)
     return fail(nullptr, CTM_E_SHAPE, "need d >= 0, D >= 1, chi >= 1, p >= 0, n_si >= 0");
   if (cfg->proj != CTM_PROJ_FULLSVD && cfg->proj != CTM_PROJ_SI)
     return fail(nullptr, CTM_E_ARG, "unknown projector kind");
-  if (cfg->prec < CTM_PREC_F64 || cfg->prec > CTM_PREC_BF16)
+  if (cfg->prec < CTM_PREC_F64 || cfg->prec > CTM_PREC_BF16X3)
     return fail(nullptr, CTM_E_ARG, "unknown precision");
   if (!(cfg->pinv_rtol >= 0.0)) return fail(nullptr, CTM_E_ARG, "pinv_rtol must be >= 0");
   if (cfg->growth != 0 && cfg->growth != 1)
@@ -237,7 +277,12 @@ void set_dims(ctm_ctx* c, const ctm_config* cfg) {
   c->k = std::min(c->chi + cfg->p, c->N);
   c->xmax = std::max(c->chi, c->Dl);
   c->Nmax = c->xmax * c->Dl;
-  c->cp = cfg->prec == CTM_PREC_F64 ? DT::F64 : (cfg->prec == CTM_PREC_F32 ? DT::F32 : DT::BF16);
+  // split bfloat16 keeps its contraction operands in float32 and splits them
+  // into bfloat16 pairs inside the GEMM kernels
+  c->cp = cfg->prec == CTM_PREC_F64 ? DT::F64
+          : (cfg->prec == CTM_PREC_F32 || cfg->prec == CTM_PREC_BF16X3) ? DT::F32
+                                                                       : DT::BF16;
+  c->split = cfg->prec == CTM_PREC_BF16X3;
 }
 
 // Vectors of the block iteration for the correlation length.
@@ -421,9 +466,22 @@ int check_gemm(ctm_ctx* c, const GemmBatch& g, DT ta, DT tb, DT tc) {
   return 0;
 }
 
-int run_gemm(ctm_ctx* c, int cls, const GemmBatch& g, DT ta, DT tb, DT tc, double bytes = 0) {
-  const int chk = check_gemm(c, g, ta, tb, tc);
+int run_gemm(ctm_ctx* c, int cls, const GemmBatch& g0, DT ta, DT tb, DT tc, double bytes = 0) {
+  const int chk = check_gemm(c, g0, ta, tb, tc);
   if (chk) return chk;
+  GemmBatch g = g0;
+  // in the split bfloat16 mode every product with a float32-stored operand is
+  // a contraction of the mode
+  if (c->split && (ta == DT::F32 || tb == DT::F32)) g.split = 1;
+  if (c->rec) {
+    if (ta == DT::F64 && tb == DT::F64 && tc == DT::F64)
+      c->rec->push_back(BatchOp{true, g, nullptr});
+    else
+      c->rec->push_back(BatchOp{false, GemmBatch{}, [=](hipStream_t st) {
+                                  return launch_gemm(g, ta, tb, tc, st);
+                                }});
+    return 0;
+  }
   ProfScope ps(c, cls, gemm_flops(g), bytes);
   return launch_gemm(g, ta, tb, tc, c->st);
 }
@@ -501,7 +559,25 @@ int apply_step(ctm_ctx* c, int count, const int* ci, const int* trans, double* c
     g.C[i] = dst[i];
   }
   const double bytes = (double)count * ((double)N1 * N1 * dt_size(c->cp) + 2.0 * N1 * k * 8.0);
-  if (c->cp == DT::F32) {
+  if (c->rec && c->cp == DT::F64) {
+    const int chk = check_gemm(c, g, DT::F64, DT::F64, DT::F64);
+    if (chk) return chk;
+    // the split kernel sums cut tiles in its own order: kept as its own launch
+    // so that the product has the bits of a solo move; the tile kernels give
+    // the same bits in any grid and are grouped
+    if (gemm_si_balanced_applies(g, c->sk_part, c->sk_cus)) {
+      double* part = c->sk_part;
+      const int cus = c->sk_cus;
+      c->rec->push_back(BatchOp{false, GemmBatch{}, [=](hipStream_t st) {
+                                  return launch_gemm_si_balanced(g, part, cus, st);
+                                }});
+    } else {
+      c->rec->push_back(BatchOp{true, g, nullptr});
+    }
+    return 0;
+  }
+  if (c->rec) return fail(c, CTM_E_STATE, "batched moves run float64 contractions only");
+  if (c->cp == DT::F32 && !c->split) {
     const int chk = check_gemm(c, g, DT::F32, DT::F64, DT::F64);
     if (chk) return chk;
     ProfScope ps(c, PC_SI_APPLY, gemm_flops(g), bytes);
@@ -548,7 +624,11 @@ int half_step(ctm_ctx* c, bool x_with_M, int N1) {
 int qr_and_swap(ctm_ctx* c, int N1) {
   {
     ProfScope ps(c, PC_QR, 8.0 * 4.0 * N1 * (double)c->k * c->k);
-    TRY(launch_qr(8, c->W[1], N1, c->k, c->qr_ws, c->st));
+    double* w[8];
+    for (int i = 0; i < 8; ++i) w[i] = c->W[1][i];
+    const int k = c->k;
+    void* ws = c->qr_ws;
+    ENQ(launch_qr(8, w, N1, k, ws, st));
   }
   for (int b = 0; b < 4; ++b) {
     std::swap(c->X[b], c->W[1][b]);
@@ -610,8 +690,9 @@ int si_core(ctm_ctx* c, int keep, int nsi, bool measure, int N1) {
   if (measure) {
     const size_t nk = (size_t)N1 * k * sizeof(double);
     for (int b = 0; b < 4; ++b) {
-      CTM_HIP_TRY(hipMemcpyAsync(c->Xprev[b], c->X[b], nk, hipMemcpyDeviceToDevice, c->st));
-      CTM_HIP_TRY(hipMemcpyAsync(c->Xprev[4 + b], c->Yt[b], nk, hipMemcpyDeviceToDevice, c->st));
+      double *dx = c->Xprev[b], *sx = c->X[b], *dy = c->Xprev[4 + b], *sy = c->Yt[b];
+      ENQ(hrc(hipMemcpyAsync(dx, sx, nk, hipMemcpyDeviceToDevice, st)));
+      ENQ(hrc(hipMemcpyAsync(dy, sy, nk, hipMemcpyDeviceToDevice, st)));
     }
   }
   for (int step = 0; step < nsi; ++step) {
@@ -657,7 +738,7 @@ int si_core(ctm_ctx* c, int keep, int nsi, bool measure, int N1) {
   }
   {
     ProfScope ps(c, PC_SVD);
-    TRY(launch_svd(4, c->rho, c->u, c->s, c->v, k, c->svd_ws, c->st));
+    ENQ(launch_svd(4, c->rho, c->u, c->s, c->v, k, c->svd_ws, st));
   }
   // Y^T u -> W[0][4+b]; signs from it
   {
@@ -677,8 +758,8 @@ int si_core(ctm_ctx* c, int keep, int nsi, bool measure, int N1) {
     sa.Y[b] = c->W[0][4 + b];
     sa.sg[b] = c->sg[b];
   }
-  TRY(elem_col_sign(sa, 4, c->st));
-  TRY(elem_scale_cols(sa, 4, c->st));
+  ENQ(elem_col_sign(sa, 4, st));
+  ENQ(elem_scale_cols(sa, 4, st));
   ProjPrepArgs pa{};
   pa.k = k;
   pa.keep = keep;
@@ -693,7 +774,7 @@ int si_core(ctm_ctx* c, int keep, int nsi, bool measure, int N1) {
     pa.vsc[b] = c->vsc[b];
     pa.usc[b] = c->usc[b];
   }
-  TRY(elem_proj_prep(pa, 4, c->st));
+  ENQ(elem_proj_prep(pa, 4, st));
   // X <- X v diag(sg) (into W[0][b]); P_l = A vsc; P_r^T = B^T usc
   {
     GemmBatch g = gemm_rowmajor(4, N1, k, k, k, k, k);
@@ -736,7 +817,7 @@ int si_core(ctm_ctx* c, int keep, int nsi, bool measure, int N1) {
     oa.count = 8;
     oa.chi = chi;
     oa.out = c->scal + 13;
-    TRY(elem_sin2(oa, c->st));
+    ENQ(elem_sin2(oa, st));
   }
   return 0;
 }
@@ -926,7 +1007,8 @@ int normalize_env(ctm_ctx* c, int buf, int x) {
   na.bad = c->bad;
   na.part = c->dot_part;
   static_assert(8 * kNormBlocks <= kMaxDots * kDotBlocks, "norm partial sums exceed dot_part");
-  return elem_normalize(na, 8, c->st);
+  ENQ(elem_normalize(na, 8, st));
+  return 0;
 }
 
 // Corner spectra of buffer `buf` and delta against the committed spectra.
@@ -934,7 +1016,7 @@ int spectra(ctm_ctx* c, int buf, int x) {
   {
     ProfScope ps(c, PC_SVD);
     const double* A[4] = {c->C[buf][0], c->C[buf][1], c->C[buf][2], c->C[buf][3]};
-    TRY(launch_svd(4, A, nullptr, c->csv, nullptr, x, c->svd_ws, c->st));
+    ENQ(launch_svd(4, A, nullptr, c->csv, nullptr, x, c->svd_ws, st));
   }
   SpecArgs sp{};
   for (int i = 0; i < 4; ++i) sp.s[i] = c->csv[i];
@@ -943,7 +1025,8 @@ int spectra(ctm_ctx* c, int buf, int x) {
   sp.delta = c->scal + 8;
   sp.x = std::min(x, c->chi);
   sp.chi = c->chi;
-  return elem_spectra_delta(sp, c->st);
+  ENQ(elem_spectra_delta(sp, st));
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1091,7 +1174,7 @@ void drop_graphs(ctm_ctx* c) {
 // read-back of its scalars).
 int move_work(ctm_ctx* c, int mode, int keep, int nsi, bool measure) {
   const int N1 = c->chi_env * c->Dl;
-  TRY(elem_zero_int(c->bad, c->st));
+  ENQ(elem_zero_int(c->bad, st));
   TRY(build_corners(c));
   if (c->cfg.sym == CTM_SYM_C4V) {
     TRY(c4v_projectors(c, mode, keep));
@@ -1263,6 +1346,147 @@ int do_move(ctm_ctx* c, ctm_move_info* info) {
 int drain(ctm_ctx* c) {
   if (!c->pending) return CTM_OK;
   return wait_move(c, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Batched moves (serving: environment solves of mixed (D, chi) moved
+// together).  Each context's SI move is recorded as its sequence of
+// operations; step i of every context is then launched together on one
+// stream: the float64 GEMMs of the step as one persistent grouped launch
+// over a device table of (descriptor, tile) work items, the other operations
+// one after another.  Contexts are independent, so only each context's own
+// order matters, and every product gets the bits of the solo move (the tile
+// kernels do not depend on the grid; the split SI kernel, whose summation
+// order does, keeps its own launch).
+// ---------------------------------------------------------------------------
+constexpr int kBatchMaxDevices = 64;
+
+struct BatchTable {
+  GroupItem* dev = nullptr;    // device copy of the descriptors
+  GroupItem* host = nullptr;   // pinned staging of the descriptors
+  size_t cap = 0;              // items both hold
+  hipEvent_t done = nullptr;   // recorded after the last batch that read them
+};
+std::mutex g_batch_mu;
+BatchTable g_batch[kBatchMaxDevices];
+
+// True if the next move of c is an SI move that a batch records.
+bool batchable(const ctm_ctx* c) {
+  return !c->pending && c->chi_env == c->chi && c->chi * c->Dl > c->chi &&
+         c->cfg.proj == CTM_PROJ_SI && c->cfg.sym == CTM_SYM_NONE && c->cp == DT::F64;
+}
+
+int enqueue_batch(ctm_ctx* const* ctxs, int n) {
+  std::vector<ctm_ctx*> grp;
+  for (int i = 0; i < n; ++i) {
+    ctm_ctx* c = ctxs[i];
+    if (!c) return fail(nullptr, CTM_E_ARG, "null context in the batch");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(c, CTM_E_ARG, "a context appears twice in the batch");
+    if (c->pending) return fail(c, CTM_E_STATE, "a move is already in flight");
+  }
+  for (int i = 0; i < n; ++i) {
+    ctm_ctx* c = ctxs[i];
+    c->err.clear();
+    if (batchable(c) && !c->prof) grp.push_back(c);
+    else TRY(enqueue_move(c));                      // growth, full-SVD, C4v, reduced precision
+  }
+  if (grp.empty()) return CTM_OK;
+  hipStream_t S = grp[0]->st;
+  // work already queued on a context's own stream precedes its batched move
+  for (ctm_ctx* c : grp)
+    if (c->st != S) CTM_HIP_TRY(hipStreamSynchronize(c->st));
+  // record every context's move; the recording swaps block pointers on the
+  // host, so a failure before the launch restores every arrangement
+  std::vector<std::vector<BatchOp>> ops(grp.size());
+  std::vector<std::vector<void*>> arrangement(grp.size());
+  for (size_t i = 0; i < grp.size(); ++i) arrangement[i] = block_ptrs(grp[i]);
+  auto restore = [&](int code) {
+    for (size_t i = 0; i < grp.size(); ++i) set_block_ptrs(grp[i], arrangement[i]);
+    return code;
+  };
+  size_t steps = 0;
+  for (size_t i = 0; i < grp.size(); ++i) {
+    ctm_ctx* c = grp[i];
+    hipStream_t own = c->st;
+    c->st = S;                                      // eager parts below run on S
+    const bool rec = c->cfg.recycle_sin2 > 0;
+    const int nsi = (rec && c->recycling) ? 0 : c->cfg.n_si;
+    const bool measure = rec && nsi > 0 && c->last_si_delta >= 0.0 && !c->iso_pending;
+    int r = ensure_si_blocks(c);
+    if (!r) {
+      c->rec = &ops[i];
+      r = move_work(c, 2, c->chi, nsi, measure);
+      c->rec = nullptr;
+    }
+    c->st = own;
+    if (r) return restore(r);
+    c->pend_mode = 2;
+    c->pend_keep = c->chi;
+    c->pend_nsi = nsi;
+    c->pend_measure = measure;
+    steps = std::max(steps, ops[i].size());
+  }
+  // the grouped GEMMs of every step, in one table
+  std::vector<GemmBatch> gs;
+  std::vector<std::pair<size_t, int>> span(steps);   // (first item, items) per step
+  std::vector<std::pair<long, int>> plan(steps);     // (work items, kind) per step
+  for (size_t t = 0; t < steps; ++t) {
+    span[t] = {gs.size(), 0};
+    for (auto& v : ops)
+      if (t < v.size() && v[t].gemm) gs.push_back(v[t].g);
+    span[t].second = (int)(gs.size() - span[t].first);
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kBatchMaxDevices)
+    return restore(fail(nullptr, CTM_E_DEVICE, "no usable current device"));
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  BatchTable& tb = g_batch[dev];
+  if (!tb.done && hipEventCreateWithFlags(&tb.done, hipEventDisableTiming) != hipSuccess)
+    return restore(fail(nullptr, CTM_E_DEVICE, "event creation failed"));
+  // the previous batch has read the table before it is rewritten
+  if (hipEventSynchronize(tb.done) != hipSuccess)
+    return restore(fail(nullptr, CTM_E_DEVICE, "synchronisation failed"));
+  if (gs.size() > tb.cap) {
+    if (tb.dev) (void)hipFree(tb.dev);
+    if (tb.host) (void)hipHostFree(tb.host);
+    tb.dev = nullptr;
+    tb.host = nullptr;
+    tb.cap = 0;
+    const size_t cap = std::max<size_t>(2 * gs.size(), 256);
+    if (hipMalloc((void**)&tb.dev, cap * sizeof(GroupItem)) != hipSuccess ||
+        hipHostMalloc((void**)&tb.host, cap * sizeof(GroupItem), hipHostMallocDefault) != hipSuccess)
+      return restore(fail(nullptr, CTM_E_NOMEM, "descriptor table of the batched move"));
+    tb.cap = cap;
+  }
+  for (size_t t = 0; t < steps; ++t) {
+    const int cnt = span[t].second;
+    if (!cnt) continue;
+    const GemmBatch* g = gs.data() + span[t].first;
+    const int kind = grouped_kind(g, cnt);
+    plan[t] = {grouped_fill(g, cnt, kind, tb.host + span[t].first), kind};
+  }
+  if (!gs.empty())
+    CTM_HIP_TRY(hipMemcpyAsync(tb.dev, tb.host, gs.size() * sizeof(GroupItem),
+                               hipMemcpyHostToDevice, S));
+  for (size_t t = 0; t < steps; ++t) {
+    if (span[t].second)
+      TRY_B(launch_gemm_grouped(tb.dev + span[t].first, span[t].second, plan[t].first,
+                                plan[t].second, S));
+    for (size_t i = 0; i < grp.size(); ++i)
+      if (t < ops[i].size() && !ops[i][t].gemm) {
+        const int r = ops[i][t].fn(S);
+        if (r) return fail(grp[i], r == 1 ? CTM_E_ARG : r, g_err.empty() ? "batched launch" : g_err);
+      }
+  }
+  CTM_HIP_TRY(hipEventRecord(tb.done, S));
+  for (ctm_ctx* c : grp) {
+    CTM_HIP_TRY(hipMemcpyAsync(c->hbuf, c->scal, 16 * sizeof(double), hipMemcpyDeviceToHost, S));
+    CTM_HIP_TRY(hipMemcpyAsync(c->hbuf + 16, c->bad, sizeof(int), hipMemcpyDeviceToHost, S));
+    CTM_HIP_TRY(hipEventRecord(c->done_ev, S));
+    c->pending = true;
+  }
+  return CTM_OK;
 }
 
 
@@ -1808,6 +2032,8 @@ ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev
 
 void ctm_destroy(ctm_ctx* c) {
   if (!c) return;
+  // a move in flight may run on another context's stream (a batched move)
+  if (c->pending) (void)hipEventSynchronize(c->done_ev);
   if (c->st) (void)hipStreamSynchronize(c->st);
   else (void)hipDeviceSynchronize();
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1878,6 +2104,29 @@ ctm_status ctm_move_poll(ctm_ctx* c, int* done, ctm_move_info* info) {
   }
   *done = 1;
   return (ctm_status)finish_move(c, info);
+}
+
+ctm_status ctm_move_batch_async(ctm_ctx* const* ctxs, int n) {
+  if (!ctxs || n < 0) return (ctm_status)fail(nullptr, CTM_E_ARG, "invalid batch");
+  g_err.clear();
+  return (ctm_status)enqueue_batch(ctxs, n);
+}
+
+ctm_status ctm_move_batch(ctm_ctx* const* ctxs, int n, ctm_move_info* infos) {
+  if (!ctxs || n < 0) return (ctm_status)fail(nullptr, CTM_E_ARG, "invalid batch");
+  g_err.clear();
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return (ctm_status)fail(nullptr, CTM_E_ARG, "null context in the batch");
+    const int rd = drain(ctxs[i]);
+    if (rd) return (ctm_status)rd;
+  }
+  int first = enqueue_batch(ctxs, n);
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]->pending) continue;               // not enqueued (an earlier error)
+    const int r = wait_move(ctxs[i], infos ? infos + i : nullptr);
+    if (r && !first) first = r;
+  }
+  return (ctm_status)first;
 }
 
 ctm_status ctm_converge(ctm_ctx* c, double tol, int max_moves, int* moves_done,

@@ -24,6 +24,8 @@
 
 #include "common.h"
 
+#include <algorithm>
+
 namespace sictm {
 namespace {
 
@@ -67,10 +69,15 @@ template <> struct Mfma4<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+constexpr int kK4BK = 16, kK4Pad = 2;
+
+// One BM x BN output tile (tm, tn) of problem `prob`, inner batch `batch`.
+// The K loop runs in ascending 16-wide slices whatever the tile shape, so an
+// output element gets the same bits from every tile shape and grid.
 template <typename TA, typename TB, typename TC, typename CT, int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(256) void gemm_k4(GemmBatch g, int tiles_m, int tiles_n) {
-  constexpr int BK = 16;
-  constexpr int PAD = 2;
+__device__ __forceinline__ void k4_tile(const GemmBatch& g, int prob, int batch, int tm, int tn,
+                                        CT (*As)[BM + kK4Pad], CT (*Bs)[BN + kK4Pad]) {
+  constexpr int BK = kK4BK;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int MI = WTM / 16, NI = WTN / 16;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
@@ -79,14 +86,8 @@ __global__ __launch_bounds__(256) void gemm_k4(GemmBatch g, int tiles_m, int til
   static_assert((BM * BK) % 256 == 0 && (BN * BK) % 256 == 0, "tile loads");
   using Acc = typename Mfma4<CT>::acc_t;
 
-  __shared__ CT As[BK][BM + PAD];
-  __shared__ CT Bs[BK][BN + PAD];
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int tn = tile % tiles_n, tm = tile / tiles_n;
-  const int prob = blockIdx.y / g.nbatch, batch = blockIdx.y % g.nbatch;
   const int m0 = tm * BM, n0 = tn * BN;
   const int M = g.M, N = g.N, K = g.K;
   const int trans = g.transA[prob];
@@ -189,6 +190,15 @@ __global__ __launch_bounds__(256) void gemm_k4(GemmBatch g, int tiles_m, int til
   }
 }
 
+template <typename TA, typename TB, typename TC, typename CT, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void gemm_k4(GemmBatch g, int tiles_m, int tiles_n) {
+  __shared__ CT As[kK4BK][BM + kK4Pad];
+  __shared__ CT Bs[kK4BK][BN + kK4Pad];
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int prob = blockIdx.y / g.nbatch, batch = blockIdx.y % g.nbatch;
+  k4_tile<TA, TB, TC, CT, BM, BN, WGM, WGN>(g, prob, batch, tile / tiles_n, tile % tiles_n, As, Bs);
+}
+
 // ---------------------------------------------------------------------------
 // Skinny float64 path for C (M x N) = op(A) (M x K) B (K x N) with N <= BN:
 // the enlarged corner applied to an N x k isometry block.  One workgroup owns
@@ -214,7 +224,7 @@ struct SkinnyA {
 };
 
 template <int BM, int BN, int WGM, int WGN, bool TRANS>
-__device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int tiles_n,
+__device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int tiles_n, int lin,
                                             double (*As)[SkinnyA<BM, 16>::SIZE],
                                             double (*Bs)[16][BN + 16]) {
   constexpr int BK = 16;
@@ -229,7 +239,6 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int per_prob = tiles_m * tiles_n;
-  const int lin = xcd_remap(blockIdx.x, gridDim.x);
   const int pb = lin / per_prob, tile = lin % per_prob;
   const int prob = pb / g.nbatch, batch = pb % g.nbatch;
   const int tn = tile % tiles_n, tm = tile / tiles_n;
@@ -614,11 +623,63 @@ __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_s
   __shared__ double As[2][SkinnyA<BM, 16>::SIZE];
   __shared__ double Bs[2][16][BN + 16];
   const int per_prob = tiles_m * tiles_n;
-  const int prob = xcd_remap(blockIdx.x, gridDim.x) / per_prob / g.nbatch;
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int prob = lin / per_prob / g.nbatch;
   if (g.transA[prob])
-    skinny_tile<BM, BN, WGM, WGN, true>(g, tiles_m, tiles_n, As, Bs);
+    skinny_tile<BM, BN, WGM, WGN, true>(g, tiles_m, tiles_n, lin, As, Bs);
   else
-    skinny_tile<BM, BN, WGM, WGN, false>(g, tiles_m, tiles_n, As, Bs);
+    skinny_tile<BM, BN, WGM, WGN, false>(g, tiles_m, tiles_n, lin, As, Bs);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped launches: the products of several GemmBatch descriptors of
+// different shapes (one per context of a batched move) in one persistent
+// launch.  The descriptors sit in device memory with the prefix sums of
+// their work items (tiles x problems x inner batches); workgroup w takes
+// items w, w + grid, ... and finds each one's descriptor by binary search.
+// Every item runs the tile code of the ungrouped kernels, whose results do
+// not depend on the grid, so a grouped product equals the same product
+// launched alone, bit for bit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int group_of(const GroupItem* items, int n, long w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_skinny_grouped(
+    const GroupItem* items, int nitems, long total) {
+  __shared__ double As[2][SkinnyA<BM, 16>::SIZE];
+  __shared__ double Bs[2][16][BN + 16];
+  for (long w = blockIdx.x; w < total; w += gridDim.x) {
+    const GroupItem& it = items[group_of(items, nitems, w)];
+    const int lin = (int)(w - it.first);
+    const int prob = lin / (it.tiles_m * it.tiles_n) / it.g.nbatch;
+    if (it.g.transA[prob])
+      skinny_tile<BM, BN, WGM, WGN, true>(it.g, it.tiles_m, it.tiles_n, lin, As, Bs);
+    else
+      skinny_tile<BM, BN, WGM, WGN, false>(it.g, it.tiles_m, it.tiles_n, lin, As, Bs);
+  }
+}
+
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void gemm_k4_grouped(const GroupItem* items, int nitems,
+                                                       long total) {
+  __shared__ double As[kK4BK][BM + kK4Pad];
+  __shared__ double Bs[kK4BK][BN + kK4Pad];
+  for (long w = blockIdx.x; w < total; w += gridDim.x) {
+    const GroupItem& it = items[group_of(items, nitems, w)];
+    const int lin = (int)(w - it.first);
+    const int per = it.tiles_m * it.tiles_n;
+    const int pb = lin / per, tile = lin % per;
+    k4_tile<double, double, double, double, BM, BN, WGM, WGN>(
+        it.g, pb / it.g.nbatch, pb % it.g.nbatch, tile / it.tiles_n, tile % it.tiles_n, As, Bs);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -746,6 +807,149 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmBatch g, int tiles_m, int t
 }
 
 // ---------------------------------------------------------------------------
+// Split bfloat16 path (three bf16 products per step): every operand value x
+// is rounded to float32 and written as hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi) (16 significant bits together); A B is then
+// A_hi B_hi + A_hi B_lo + A_lo B_hi on v_mfma_f32_16x16x32_bf16 with float32
+// accumulation, dropping only A_lo B_lo (relative 2^-16).  This keeps the
+// bf16 matrix-core rate at close to float32 accuracy (Henry, Tang and
+// Heinecke, ARITH 2019).  Same LDS layout as the bf16 path, hi and lo
+// halves side by side.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <typename TA, typename TB, typename TC, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void gemm_bf16x3(GemmBatch g, int tiles_m, int tiles_n) {
+  constexpr int BK = 32;
+  constexpr int PAD = 8;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int MI = WTM / 16, NI = WTN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  static_assert(WGM * WGN == 4, "four wavefronts");
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile multiple of 16");
+
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][BK + PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM][BK + PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][BK + PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][BK + PAD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = tile % tiles_n, tm = tile / tiles_n;
+  const int prob = blockIdx.y / g.nbatch, batch = blockIdx.y % g.nbatch;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int M = g.M, N = g.N, K = g.K;
+  const int trans = g.transA[prob];
+  const TA* A = (const TA*)g.A[prob] + (long)batch * g.a_bs;
+  const TB* B = (const TB*)g.B[prob] + (long)batch * g.b_bs;
+  TC* C = (TC*)g.C[prob] + (long)batch * g.c_bs;
+  const long lda = g.lda, ldb = g.ldb;
+
+  float ra[EA], rb[EB];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int i = tid + e * 256;
+      int m, kk;
+      if (trans) { m = i % BM; kk = i / BM; } else { m = i / BK; kk = i % BK; }
+      const int gm = m0 + m, gk = k0 + kk;
+      float v = 0.0f;
+      if (gm < M && gk < K) v = (float)(trans ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk]);
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int i = tid + e * 256;
+      const int n = i % BN, kk = i / BN;
+      const int gn = n0 + n, gk = k0 + kk;
+      float v = 0.0f;
+      if (gn < N && gk < K) v = (float)B[(long)gk * ldb + gn];
+      rb[e] = v;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int i = tid + e * 256;
+      int m, kk;
+      if (trans) { m = i % BM; kk = i / BM; } else { m = i / BK; kk = i % BK; }
+      split_bf16(ra[e], Ah[m][kk], Al[m][kk]);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int i = tid + e * 256;
+      split_bf16(rb[e], Bh[i % BN][i / BN], Bl[i % BN][i / BN]);
+    }
+  };
+
+  v4f acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+  const int nk = (K + BK - 1) / BK;
+  load_tiles(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    store_tiles();
+    __syncthreads();
+    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+    const int kc = 8 * (lane >> 4);
+    v8bf ah[MI], al[MI], bh[NI], bl[NI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+      ah[i] = *reinterpret_cast<const v8bf*>(&Ah[wm * WTM + i * 16 + (lane & 15)][kc]);
+      al[i] = *reinterpret_cast<const v8bf*>(&Al[wm * WTM + i * 16 + (lane & 15)][kc]);
+    }
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      bh[j] = *reinterpret_cast<const v8bf*>(&Bh[wn * WTN + j * 16 + (lane & 15)][kc]);
+      bl[j] = *reinterpret_cast<const v8bf*>(&Bl[wn * WTN + j * 16 + (lane & 15)][kc]);
+    }
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+
+  long offn[NI];
+  bool okn[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+    okn[j] = n < N;
+    offn[j] = okn[j] ? map2(n, g.cdiv_n, g.cs_n1, g.cs_n0) : 0;
+  }
+  const float alpha = (float)g.alpha;
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
+      if (m >= M) continue;
+      const long offm = map2(m, g.cdiv_m, g.cs_m1, g.cs_m0);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        if (!okn[j]) continue;
+        TC* p = C + offm + offn[j];
+        float v = alpha * acc[i][j][r];
+        if (g.accumulate) v += (float)*p;
+        *p = cvt<TC>(v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // tile selection
 // ---------------------------------------------------------------------------
 struct TileCfg {
@@ -810,6 +1014,24 @@ int launch_b16(const GemmBatch& g, hipStream_t s) {
   return 0;
 }
 
+template <typename TA, typename TB, typename TC>
+int launch_bx3(const GemmBatch& g, hipStream_t s) {
+  const int c = pick_tile(g);
+  const int bm = kTiles[c].bm, bn = kTiles[c].bn;
+  const int tm = ceil_div(g.M, bm), tn = ceil_div(g.N, bn);
+  dim3 grid(tm * tn, g.count * g.nbatch), block(256);
+  switch (c) {
+    case 0: gemm_bf16x3<TA, TB, TC, 128, 128, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 1: gemm_bf16x3<TA, TB, TC, 128, 144, 4, 1><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 2: gemm_bf16x3<TA, TB, TC, 64, 160, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 3: gemm_bf16x3<TA, TB, TC, 64, 80, 4, 1><<<grid, block, 0, s>>>(g, tm, tn); break;
+    case 4: gemm_bf16x3<TA, TB, TC, 64, 64, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+    default: gemm_bf16x3<TA, TB, TC, 32, 32, 2, 2><<<grid, block, 0, s>>>(g, tm, tn); break;
+  }
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 // The skinny kernel needs 16-byte aligned rows: even leading dimensions and
 // batch strides, 16-byte aligned base pointers.
 bool skinny_ok(const GemmBatch& g) {
@@ -829,6 +1051,52 @@ int launch_skinny(const GemmBatch& g, hipStream_t s) {
 }
 
 }  // namespace
+
+int grouped_kind(const GemmBatch* gs, int n) {
+  bool skinny = true;
+  int big = 0;
+  double most = -1.0;
+  for (int i = 0; i < n; ++i) {
+    skinny = skinny && gs[i].N <= 160 && skinny_ok(gs[i]);
+    const double f = (double)gs[i].M * gs[i].N * (double)gs[i].K * gs[i].count * gs[i].nbatch;
+    if (f > most) { most = f; big = i; }
+  }
+  if (skinny) return 0;
+  return 1 + pick_tile(gs[big]);
+}
+
+long grouped_fill(const GemmBatch* gs, int n, int kind, GroupItem* items) {
+  const int bm = kind == 0 ? 96 : kTiles[kind - 1].bm, bn = kind == 0 ? 160 : kTiles[kind - 1].bn;
+  long total = 0;
+  for (int i = 0; i < n; ++i) {
+    items[i].g = gs[i];
+    items[i].tiles_m = gs[i].M > 0 ? ceil_div(gs[i].M, bm) : 0;
+    items[i].tiles_n = gs[i].N > 0 ? ceil_div(gs[i].N, bn) : 0;
+    items[i].first = total;
+    total += (long)items[i].tiles_m * items[i].tiles_n * gs[i].count * gs[i].nbatch;
+  }
+  return total;
+}
+
+int launch_gemm_grouped(const GroupItem* items, int n, long total, int kind, hipStream_t s) {
+  if (n <= 0 || total <= 0) return 0;
+  // persistent grid: at most two workgroups per CU of 256
+  const int grid = (int)std::min<long>(total, 512);
+  if (kind == 0) {
+    gemm_skinny_grouped<96, 160, 2, 2><<<grid, 256, 0, s>>>(items, n, total);
+  } else {
+    switch (kind - 1) {
+      case 0: gemm_k4_grouped<128, 128, 2, 2><<<grid, 256, 0, s>>>(items, n, total); break;
+      case 1: gemm_k4_grouped<128, 144, 4, 1><<<grid, 256, 0, s>>>(items, n, total); break;
+      case 2: gemm_k4_grouped<64, 160, 2, 2><<<grid, 256, 0, s>>>(items, n, total); break;
+      case 3: gemm_k4_grouped<64, 80, 4, 1><<<grid, 256, 0, s>>>(items, n, total); break;
+      case 4: gemm_k4_grouped<64, 64, 2, 2><<<grid, 256, 0, s>>>(items, n, total); break;
+      default: gemm_k4_grouped<32, 32, 2, 2><<<grid, 256, 0, s>>>(items, n, total); break;
+    }
+  }
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
 
 int launch_gemm_si(const GemmBatch& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch <= 0) return 0;
@@ -898,6 +1166,15 @@ int launch_gemm(const GemmBatch& g, DT ta, DT tb, DT tc, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch <= 0) return 0;
   if (g.K <= 0 && !g.accumulate) {
     // empty sum: the kernels still write zeros (load loop does not run)
+  }
+  if (g.split) {
+    // split bfloat16 products of float32-stored contraction operands
+    if (ta == DT::F64 && tb == DT::F32 && tc == DT::F32) return launch_bx3<double, float, float>(g, s);
+    if (ta == DT::F32 && tb == DT::F64 && tc == DT::F64) return launch_bx3<float, double, double>(g, s);
+    if (ta == DT::F32 && tb == DT::F32 && tc == DT::F64) return launch_bx3<float, float, double>(g, s);
+    if (ta == DT::F64 && tb == DT::F32 && tc == DT::F64) return launch_bx3<double, float, double>(g, s);
+    set_thread_error("launch_gemm: unsupported type combination for split bfloat16");
+    return 1;
   }
   if (ta == DT::F64 && tb == DT::F64) {
     int rc = 0;

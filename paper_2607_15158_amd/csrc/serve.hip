@@ -12,7 +12,8 @@
 // next move of every request that is still iterating, retires requests that
 // reached delta < tol (at the full environment dimension) or their move
 // budget, and admits new ones.  SI moves replay a captured HIP graph per
-// request.  Moves of different requests therefore overlap on the device,
+// request, or, for requests up to a size set by ctm_server_batching, move
+// together through ctm_move_batch_async (grouped launches over all of them).  Moves of different requests therefore overlap on the device,
 // and a result does not depend on what else runs:
 // each request executes exactly the kernels, launch shapes and reduction
 // orders of a solo ctm_converge.
@@ -56,6 +57,10 @@ struct ctm_server {
   std::vector<Request> reqs;
   std::chrono::steady_clock::time_point t0;
   std::string err;
+  // batched moves: requests with chi * Dl <= batch_max_n whose next move is
+  // an SI move move together through ctm_move_batch_async (0: every request
+  // moves on its own slot stream)
+  int batch_max_n = 0;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -300,7 +305,8 @@ ctm_status ctm_server_submit(ctm_server* s, const ctm_config* cfg, const double*
 
 ctm_status ctm_server_pump(ctm_server* s, int* n_running, int* n_queued) {
   if (!s) return CTM_E_ARG;
-  // 1. completed moves: retire or relaunch
+  // 1. completed moves: retire, or queue the next move
+  std::vector<int> batch;
   for (size_t slot = 0; slot < s->slot_req.size(); ++slot) {
     const int id = s->slot_req[slot];
     if (id < 0) continue;
@@ -318,9 +324,23 @@ ctm_status ctm_server_pump(ctm_server* s, int* n_running, int* n_queued) {
     if (conv || r.res.moves >= r.max_moves) {
       r.res.converged = conv ? 1 : 0;
       finish(s, id);
-    } else if (ctm_move_async(r.ctx) != CTM_OK) {
-      fail_request(s, id, "ctm_move_async");
+      continue;
     }
+    size_t nsite, Dl, nk;
+    dims(r.cfg, &nsite, &Dl, &nk);
+    const bool si_next = info.chi_env == r.cfg.chi && r.cfg.proj == CTM_PROJ_SI &&
+                         r.cfg.prec == CTM_PREC_F64 && r.cfg.sym == CTM_SYM_NONE;
+    if (s->batch_max_n > 0 && si_next && (long)r.cfg.chi * (long)Dl <= s->batch_max_n)
+      batch.push_back(id);
+    else if (ctm_move_async(r.ctx) != CTM_OK)
+      fail_request(s, id, "ctm_move_async");
+  }
+  // the next moves of the batched requests: one grouped launch sequence
+  if (!batch.empty()) {
+    std::vector<ctm_ctx*> cs;
+    for (int id : batch) cs.push_back(s->reqs[id].ctx);
+    if (ctm_move_batch_async(cs.data(), (int)cs.size()) != CTM_OK)
+      for (int id : batch) fail_request(s, id, "ctm_move_batch_async");
   }
   // 2. admission, in submission order, first fit
   for (size_t id = 0; id < s->reqs.size(); ++id) {
@@ -341,6 +361,12 @@ ctm_status ctm_server_pump(ctm_server* s, int* n_running, int* n_queued) {
   }
   if (n_running) *n_running = run;
   if (n_queued) *n_queued = queued;
+  return CTM_OK;
+}
+
+ctm_status ctm_server_batching(ctm_server* s, int max_n) {
+  if (!s || max_n < 0) return CTM_E_ARG;
+  s->batch_max_n = max_n;
   return CTM_OK;
 }
 

@@ -104,12 +104,13 @@ def test_full_size_si_move_matches_oracle(oracle_move):
 
 
 # Largest deviation of a unit-norm corner spectrum from the float64
-# oracle's after one move, per contraction precision (measured values are
-# printed; the bounds leave a factor of a few above them).
-SPECTRUM_TOL = {"f32": 2e-5, "bf16": 3e-2}
+# oracle's after one move, per contraction precision: measured 3.2e-7
+# (float32) and 5.6e-4 (bfloat16) on MI355X; the bounds leave a factor of
+# about five above them.
+SPECTRUM_TOL = {"f32": 2e-6, "bf16": 3e-3, "bf16x3": 1e-4}
 
 
-@pytest.mark.parametrize("prec,pinv", [("f32", 1e-6), ("bf16", 1e-2)])
+@pytest.mark.parametrize("prec,pinv", [("f32", 1e-6), ("bf16", 1e-2), ("bf16x3", 1e-4)])
 def test_full_size_reduced_precision_move_matches_oracle_spectra(oracle_move, prec, pinv):
     """One SI move with float32 or bfloat16 contractions (float32
     accumulation) from the same state as the float64 oracle move: the corner
@@ -127,16 +128,17 @@ def test_full_size_reduced_precision_move_matches_oracle_spectra(oracle_move, pr
 
 def test_full_size_triangular_energy_gradient_directional_differences():
     """D=6, chi=144 (N = 5184): at an environment converged by SI moves
-    (randomized growth), the energy of the triangular lattice (h + v + d)
+    (randomized growth; the benchmark's site tensor), the energy of the
+    triangular lattice (h + v + d)
     returned with its gradient equals the sum of the three bond observables,
     and the corner and edge cotangents match central differences of that
     sum along seeded random directions."""
     import paper_2607_15158_amd as P
     D, chi = 6, 144
     cfg = P.Config(d=2, D=D, chi=chi, p=16, n_si=2, growth="si")
-    A = S.product_plus_noise_site(2, D, 9, noise=0.2)
+    A = S.product_plus_noise_site(2, D, 3)
     ctx = P.Ctm(cfg, torch.from_numpy(A).cuda())
-    r = ctx.converge(1e-6, 40)
+    r = ctx.converge(1e-6, 150)
     print("converge", r, flush=True)
     assert r["converged"] and r["delta"] < 1e-6, r
     st = ctx.unpack_state(ctx.get_state())
@@ -174,10 +176,12 @@ def test_full_size_precision_modes_converged_energy():
     """Config 3 (D=6, chi=144) converged in each contraction precision from
     one shared growth move (full SVD, float64): the float64 run to delta <
     1e-10, the float32 run to delta < 1e-6, the bfloat16 run for a fixed 40
-    moves (its rounded corners reach a fixed point of the rounded map).  The
-    relative errors of the energy per site (<h>_H + <h>_V) and of the norm
-    per site against the float64 run are printed; float32 meets the 1e-5
-    bound of the precision mode.  (The float64 run is the reference: its
+    moves (its rounded corners reach a fixed point of the rounded map), the
+    split bfloat16 run (three bf16 products per contraction) to delta <
+    1e-5.  The relative errors of the energy per site (<h>_H + <h>_V) and of
+    the norm per site against the float64 run are printed; float32 and split
+    bfloat16 meet the 1e-5 bound of the precision mode, plain bfloat16
+    (8 significant bits) does not.  (The float64 run is the reference: its
     moves match the oracle element-wise at this size, see above, and its
     converged observables are the oracle's fixed point.)"""
     cfg, A, X, Y, _, _ = full_size_inputs()
@@ -194,7 +198,8 @@ def test_full_size_precision_modes_converged_energy():
     ref.close()
     print(f"f64: {r['moves']} moves to delta {r['delta']:.2e}, e = {e64:.12f}, kappa = {k64:.12f}")
     errs = {}
-    for prec, pinv, tol, moves in (("f32", 1e-6, 1e-6, 200), ("bf16", 1e-2, 0.0, 40)):
+    for prec, pinv, tol, moves in (("f32", 1e-6, 1e-6, 200), ("bf16", 1e-2, 0.0, 40),
+                                   ("bf16x3", 1e-4, 1e-5, 200)):
         c2 = P.Config(d=2, D=D6, chi=CHI, p=P16, n_si=NSI, prec=prec, pinv_rtol=pinv)
         ctx = P.Ctm(c2, torch.from_numpy(A).to(dev))
         ctx.set_state(grown)
@@ -205,4 +210,5 @@ def test_full_size_precision_modes_converged_energy():
         print(f"{prec}: {rr['moves']} moves, delta {rr['delta']:.2e}, e = {e:.12f}: energy rel "
               f"err {errs[prec][0]:.2e}, kappa rel err {errs[prec][1]:.2e}")
     assert errs["f32"][0] <= 1e-5 and errs["f32"][1] <= 1e-5
+    assert errs["bf16x3"][0] <= 1e-5 and errs["bf16x3"][1] <= 1e-5
     assert errs["bf16"][0] <= 1e-2

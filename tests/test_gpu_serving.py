@@ -129,3 +129,59 @@ def test_admission_by_arena_footprint():
         r = srv.result(rid)
         assert r["state"] == "done" and r["t_admit"] >= r["t_submit"] and r["t_done"] > r["t_admit"]
     srv.close()
+
+
+def test_move_batch_equals_solo_moves():
+    """ctm_move_batch over contexts of mixed (D, chi): the SI moves of all of
+    them run as grouped launches (one per GEMM step) on one stream, the
+    growth moves on their own; after every move each batched context holds
+    bit for bit the state and move info of a twin moved alone.  The D=6,
+    chi=108 context (N = 3888) takes the split SI product, which keeps its
+    own launch inside the batch."""
+    specs = [(2, 4, 1, 4), (3, 9, 2, 4), (2, 8, 3, 4), (3, 18, 6, 4), (6, 108, 7, 16)]
+    dev = torch.device("cuda", 0)
+    solo, batched = [], []
+    for D, chi, seed, p in specs:
+        cfg, A, X, Y = request(D, chi, seed, p)
+        for group in (solo, batched):
+            c = P.Ctm(cfg, torch.from_numpy(A).to(dev), stream=torch.cuda.Stream())
+            c.set_isometries(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
+            group.append(c)
+    modes = []
+    for n in range(6):
+        want = [c.move() for c in solo]
+        got = P.move_batch(batched)
+        modes.append([g["mode"] for g in got])
+        for i, (a, b) in enumerate(zip(want, got)):
+            assert a == b, (n, specs[i], a, b)
+        for i, (a, b) in enumerate(zip(solo, batched)):
+            assert np.array_equal(a.get_state(), b.get_state()), (n, specs[i])
+    assert all(m == 2 for m in modes[-1]), modes
+    for c in solo + batched:
+        c.close()
+
+
+def test_server_with_batched_moves_equals_solo_runs():
+    """The server with batched moves for every request (ctm_server_batching):
+    results bit for bit those of solo ctm_converge runs, as without it."""
+    tol, max_moves = 1e-10, 40
+    specs = [(2, 4, 1), (3, 9, 2), (2, 8, 3), (3, 12, 4), (2, 6, 5), (3, 18, 6)]
+    reqs = [request(*sp) for sp in specs]
+    srv = P.Server(arena_bytes=1 << 30, max_slots=4, batch_max_n=1 << 20)
+    h = S.heisenberg_bond()
+    ids = []
+    for i, (cfg, A, X, Y) in enumerate(reqs):
+        ids.append(srv.submit(cfg, A, X0=X, Yt0=Y, op=h, tol=tol, max_moves=max_moves))
+        for _ in range(2 * i):
+            srv.pump()
+    while True:
+        run, queued = srv.pump()
+        if run == 0 and queued == 0:
+            break
+    for rid, (cfg, A, X, Y), sp in zip(ids, reqs, specs):
+        got = srv.result(rid)
+        assert got["state"] == "done", got
+        ref = solo(cfg, A, X, Y, tol, max_moves)
+        for key in ("moves", "delta", "kappa", "bond_h", "bond_v"):
+            assert got[key] == ref[key], (sp, key, got[key], ref[key])
+    srv.close()
