@@ -32,7 +32,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}    # dense MFMA TFLOP/s, MI355X
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}   # dense MFMA TFLOP/s, MI355X
 HBM_PEAK = 8000.0                                      # GB/s
 
 
@@ -230,7 +230,9 @@ def main():
                     help="skip the observables (bond values, correlation lengths)")
     ap.add_argument("--xi-iters", type=int, default=30,
                     help="block iterations of the correlation-length observable")
-    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16", "bf16x3"],
+                    help="contraction precision (bf16x3: split bfloat16, three bf16 products "
+                         "per contraction; its roofline counts the three products)")
     ap.add_argument("--pinv-rtol", type=float, default=1e-12)
     ap.add_argument("--svd-moves", type=int, default=1,
                     help="full-SVD comparator moves from the state after the growth move (0: skip)")

@@ -223,11 +223,12 @@ class Ctm:
             _lib.ctm_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # At interpreter exit the HIP runtime (and a profiler's tool library)
         # may already be torn down: a context still open then is left to the
-        # process teardown instead of calling into the runtime.
-        if sys.is_finalizing():
+        # process teardown instead of calling into the runtime (the check is
+        # bound at definition time, since module globals may be gone by then).
+        if _finalizing():
             return
         self.close()
 
@@ -692,8 +693,8 @@ class Server:
             _lib.ctm_server_destroy(self._h)
             self._h = _vp()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         self.close()
 

@@ -120,6 +120,8 @@ int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStr
 // rounded to float32, float32 accumulation); other shapes fall back to
 // launch_gemm.
 int launch_gemm_si_f32(const GemmBatch& g, hipStream_t s);
+// The same product in split bfloat16 (A float32, three bf16 products).
+int launch_gemm_si_bx3(const GemmBatch& g, hipStream_t s);
 
 // Grouped float64 GEMMs: one persistent launch over the products of several
 // descriptors of different shapes (see gemm.hip).  Each descriptor's work

@@ -160,6 +160,10 @@ struct ctm_ctx {
   // signalled by done_ev; the host-side state advances in finish_move
   double* hbuf = nullptr;    // [0..15] scal copy, [16] bad flag (as int)
   hipEvent_t done_ev = nullptr;
+  // second stream of a move: the new corners' norms and spectra run on it
+  // while the edges are renormalised (fork and join by events)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool pending = false;
   int pend_mode = 0, pend_keep = 0, pend_nsi = 0;
   bool pend_measure = false;
@@ -577,11 +581,11 @@ int apply_step(ctm_ctx* c, int count, const int* ci, const int* trans, double* c
     return 0;
   }
   if (c->rec) return fail(c, CTM_E_STATE, "batched moves run float64 contractions only");
-  if (c->cp == DT::F32 && !c->split) {
+  if (c->cp == DT::F32) {
     const int chk = check_gemm(c, g, DT::F32, DT::F64, DT::F64);
     if (chk) return chk;
     ProfScope ps(c, PC_SI_APPLY, gemm_flops(g), bytes);
-    return launch_gemm_si_f32(g, c->st);
+    return c->split ? launch_gemm_si_bx3(g, c->st) : launch_gemm_si_f32(g, c->st);
   }
   if (c->cp != DT::F64) return run_gemm(c, PC_SI_APPLY, g, c->cp, DT::F64, DT::F64, bytes);
   const int chk = check_gemm(c, g, DT::F64, DT::F64, DT::F64);
@@ -913,10 +917,9 @@ int full_projectors(ctm_ctx* c, int keep) {
 }
 
 // Step 3: C_i' = P_r^(i-1) Ct_i P_l^(i);  T_j' = P_r^(j) (T_j a) P_l^(j).
-int renormalize(ctm_ctx* c, int keep) {
+int renormalize_corners(ctm_ctx* c, int keep) {
   const int x = c->chi_env, Dl = c->Dl, N1 = x * Dl, xp = keep;
   const int nxt = 1 - c->cur;
-  double* const* T = c->T[c->cur];
   {
     GemmBatch g = gemm_rowmajor(4, N1, xp, N1, N1, xp, xp);
     for (int i = 0; i < 4; ++i) {
@@ -936,6 +939,13 @@ int renormalize(ctm_ctx* c, int keep) {
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
   }
+  return 0;
+}
+
+int renormalize_edges(ctm_ctx* c, int keep) {
+  const int x = c->chi_env, Dl = c->Dl, xp = keep;
+  const int nxt = 1 - c->cur;
+  double* const* T = c->T[c->cur];
   // Z1[(b, g'), (r, u)] = sum_g T_j[(b, u), g] P_l[(g, r), g']   (batched over r).
   // u, the row leg of each product, is Z1's unit-stride leg, so that the rows
   // of a tile are stored contiguously; the next product contracts (r, u)
@@ -993,21 +1003,23 @@ int renormalize(ctm_ctx* c, int keep) {
   return 0;
 }
 
-// Normalises the 8 tensors of buffer `buf` (environment dimension x) and
-// raises the device flag on a zero or non-finite norm.
-int normalize_env(ctm_ctx* c, int buf, int x) {
+// Normalises tensors first .. first+count-1 of buffer `buf` (0..3 the
+// corners, 4..7 the edges; environment dimension x) and raises the device
+// flag on a zero or non-finite norm.  Each tensor has its own partial sums
+// and norm slot, so the corners and the edges can be normalised on two
+// streams at once with the same results.
+int normalize_env(ctm_ctx* c, int buf, int x, int first = 0, int count = 8) {
   NormArgs na{};
-  for (int i = 0; i < 4; ++i) {
-    na.x[i] = c->C[buf][i];
-    na.n[i] = (long)x * x;
-    na.x[4 + i] = c->T[buf][i];
-    na.n[4 + i] = (long)x * c->Dl * x;
+  for (int t = 0; t < count; ++t) {
+    const int i = first + t;
+    na.x[t] = i < 4 ? c->C[buf][i] : c->T[buf][i - 4];
+    na.n[t] = i < 4 ? (long)x * x : (long)x * c->Dl * x;
   }
-  na.out = c->scal;
+  na.out = c->scal + first;
   na.bad = c->bad;
-  na.part = c->dot_part;
+  na.part = c->dot_part + (long)first * kNormBlocks;
   static_assert(8 * kNormBlocks <= kMaxDots * kDotBlocks, "norm partial sums exceed dot_part");
-  ENQ(elem_normalize(na, 8, st));
+  ENQ(elem_normalize(na, count, st));
   return 0;
 }
 
@@ -1190,11 +1202,33 @@ int move_work(ctm_ctx* c, int mode, int keep, int nsi, bool measure) {
   } else {
     TRY(si_projectors(c, keep, nsi, measure));
   }
-  TRY(renormalize(c, keep));
   const int nxt = 1 - c->cur;
-  if (c->cfg.sym == CTM_SYM_C4V) TRY(c4v_finish(c, nxt, keep));
-  TRY(normalize_env(c, nxt, keep));
-  TRY(spectra(c, nxt, keep));
+  if (c->cfg.sym == CTM_SYM_C4V || c->rec || !c->side) {
+    TRY(renormalize_corners(c, keep));
+    TRY(renormalize_edges(c, keep));
+    if (c->cfg.sym == CTM_SYM_C4V) TRY(c4v_finish(c, nxt, keep));
+    TRY(normalize_env(c, nxt, keep));
+    TRY(spectra(c, nxt, keep));
+    return 0;
+  }
+  // the new corners' norms and spectra (the convergence measure) on the side
+  // stream while the edges are renormalised: the same operations on the same
+  // data, in a different schedule
+  TRY(renormalize_corners(c, keep));
+  CTM_HIP_TRY(hipEventRecord(c->ev_fork, c->st));
+  CTM_HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  {
+    hipStream_t main = c->st;
+    c->st = c->side;
+    int r = normalize_env(c, nxt, keep, 0, 4);
+    if (!r) r = spectra(c, nxt, keep);
+    c->st = main;
+    if (r) return r;
+  }
+  TRY(renormalize_edges(c, keep));
+  TRY(normalize_env(c, nxt, keep, 4, 4));
+  CTM_HIP_TRY(hipEventRecord(c->ev_join, c->side));
+  CTM_HIP_TRY(hipStreamWaitEvent(c->st, c->ev_join, 0));
   return 0;
 }
 
@@ -1963,7 +1997,10 @@ ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev
   c->ws_bytes = need;
   carve(c, (char*)c->ws);
   if (hipHostMalloc((void**)&c->hbuf, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
     std::string m = "pinned host buffer or event creation failed";
     ctm_destroy(c);
     return (ctm_status)fail(nullptr, CTM_E_NOMEM, m);
@@ -2039,6 +2076,12 @@ void ctm_destroy(ctm_ctx* c) {
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   drop_graphs(c);
   if (c->done_ev) (void)hipEventDestroy(c->done_ev);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->rb) rocblas_destroy_handle(c->rb);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);

@@ -372,6 +372,191 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
 }
 
 // ---------------------------------------------------------------------------
+// Float32 form of the double-buffered skinny tile, for the float32
+// contractions with long K (the site absorptions of the corners and of the
+// edges' renormalisation, 20736 x 1296 x 1296 per corner at D = 6, and
+// Zc = Ct P_l): operands of type TA / TB are rounded to float32 on their way
+// into LDS and multiplied on v_mfma_f32_16x16x4f32 with float32
+// accumulation (operand layout as the float64 instruction; result element r
+// of lane l in row 4 (l / 16) + r).
+// ---------------------------------------------------------------------------
+template <int BM, int BK>
+struct SkinnyAF {
+  static constexpr int LT = BM + 16;
+  static constexpr int LN = BK + 1;
+  static constexpr int SIZE = (BK * LT > BM * LN) ? BK * LT : BM * LN;
+};
+
+template <typename TA, typename TB, typename TC, int BM, int BN, int WGM, int WGN, bool TRANS>
+__device__ __forceinline__ void skinny_tile_f32(const GemmBatch& g, int tiles_m, int tiles_n,
+                                                int lin, float (*As)[SkinnyAF<BM, 16>::SIZE],
+                                                float (*Bs)[16][BN + 16]) {
+  constexpr int BK = 16;
+  using AL = SkinnyAF<BM, BK>;
+  using VA2 = TA __attribute__((ext_vector_type(2)));
+  using VB2 = TB __attribute__((ext_vector_type(2)));
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int MI = WTM / 16, NI = WTN / 16;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int NA = BM * BK / 2, NB = BN * BK / 2;
+  constexpr int VA = (NA + NT - 1) / NT, VB = (NB + NT - 1) / NT;
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile multiple of 16");
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int per_prob = tiles_m * tiles_n;
+  const int pb = lin / per_prob, tile = lin % per_prob;
+  const int prob = pb / g.nbatch, batch = pb % g.nbatch;
+  const int tn = tile % tiles_n, tm = tile / tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int M = g.M, N = g.N, K = g.K;
+  const TA* A = (const TA*)g.A[prob] + (long)batch * g.a_bs;
+  const TB* B = (const TB*)g.B[prob] + (long)batch * g.b_bs;
+  TC* C = (TC*)g.C[prob] + (long)batch * g.c_bs;
+  const long lda = g.lda, ldb = g.ldb;
+
+  VA2 ra[VA];
+  VB2 rb[VB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < VA; ++e) {
+      const int i = tid + e * NT;
+      VA2 v = {(TA)0, (TA)0};
+      if (i < NA) {
+        if (TRANS) {
+          const int gk = k0 + i / (BM / 2), gm = m0 + 2 * (i % (BM / 2));
+          if (gk < K) {
+            const TA* p = A + (long)gk * lda + gm;
+            if (gm + 1 < M) v = *(const VA2*)p;
+            else if (gm < M) v.x = p[0];
+          }
+        } else {
+          const int gm = m0 + i / (BK / 2), gk = k0 + 2 * (i % (BK / 2));
+          if (gm < M) {
+            const TA* p = A + (long)gm * lda + gk;
+            if (gk + 1 < K) v = *(const VA2*)p;
+            else if (gk < K) v.x = p[0];
+          }
+        }
+      }
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < VB; ++e) {
+      const int i = tid + e * NT;
+      const int gk = k0 + i / (BN / 2), gn = n0 + 2 * (i % (BN / 2));
+      VB2 v = {(TB)0, (TB)0};
+      if (i < NB && gk < K) {
+        const TB* p = B + (long)gk * ldb + gn;
+        if (gn + 1 < N) v = *(const VB2*)p;
+        else if (gn < N) v.x = p[0];
+      }
+      rb[e] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < VA; ++e) {
+      const int i = tid + e * NT;
+      if (i < NA) {
+        if (TRANS) {
+          const int kk = i / (BM / 2), m = 2 * (i % (BM / 2));
+          As[buf][kk * AL::LT + m] = (float)ra[e].x;
+          As[buf][kk * AL::LT + m + 1] = (float)ra[e].y;
+        } else {
+          const int m = i / (BK / 2), kk = 2 * (i % (BK / 2));
+          As[buf][m * AL::LN + kk] = (float)ra[e].x;
+          As[buf][m * AL::LN + kk + 1] = (float)ra[e].y;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VB; ++e) {
+      const int i = tid + e * NT;
+      if (i < NB) {
+        Bs[buf][i / (BN / 2)][2 * (i % (BN / 2))] = (float)rb[e].x;
+        Bs[buf][i / (BN / 2)][2 * (i % (BN / 2)) + 1] = (float)rb[e].y;
+      }
+    }
+  };
+
+  v4f acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      float a[MI], b[NI];
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const int m = wm * WTM + i * 16 + (lane & 15);
+        a[i] = TRANS ? As[buf][kr * AL::LT + m] : As[buf][m * AL::LN + kr];
+      }
+#pragma unroll
+      for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  long offn[NI];
+  bool okn[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int n = n0 + wn * WTN + j * 16 + (lane & 15);
+    okn[j] = n < N;
+    offn[j] = okn[j] ? map2(n, g.cdiv_n, g.cs_n1, g.cs_n0) : 0;
+  }
+  const double alpha = g.alpha;
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
+      if (m >= M) continue;
+      const long offm = map2(m, g.cdiv_m, g.cs_m1, g.cs_m0);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        if (!okn[j]) continue;
+        TC* p = C + offm + offn[j];
+        double v = alpha * (double)acc[i][j][r];
+        if (g.accumulate) v += (double)*p;
+        *p = cvt<TC>(v);
+      }
+    }
+  }
+}
+
+template <typename TA, typename TB, typename TC, int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_skinny_f32x(
+    GemmBatch g, int tiles_m, int tiles_n) {
+  __shared__ float As[2][SkinnyAF<BM, 16>::SIZE];
+  __shared__ float Bs[2][16][BN + 16];
+  const int per_prob = tiles_m * tiles_n;
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int prob = lin / per_prob / g.nbatch;
+  if (g.transA[prob])
+    skinny_tile_f32<TA, TB, TC, BM, BN, WGM, WGN, true>(g, tiles_m, tiles_n, lin, As, Bs);
+  else
+    skinny_tile_f32<TA, TB, TC, BM, BN, WGM, WGN, false>(g, tiles_m, tiles_n, lin, As, Bs);
+}
+
+// ---------------------------------------------------------------------------
 // Split form of the skinny tile for the SI applications (stream-K style).  A
 // launch of one tile per workgroup leaves CUs idle or half loaded when the
 // count x tiles_m tiles do not fill the chip evenly (432 tiles of 96 rows on
@@ -1141,6 +1326,34 @@ int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStr
 }
 
 namespace {
+// 8-byte aligned pairs of float32 / float64 operands for the float32 skinny tile.
+bool pairs_ok(const GemmBatch& g) {
+  if ((g.lda & 1) || (g.ldb & 1) || (g.a_bs & 1) || (g.b_bs & 1)) return false;
+  for (int i = 0; i < g.count; ++i)
+    if (((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & 15)) return false;
+  return true;
+}
+
+// float32 contractions long enough for the double-buffered float32 tile
+// (the same shape rule as the float64 one below).
+template <typename TA, typename TB, typename TC>
+bool launch_f32_db(const GemmBatch& g, hipStream_t s, int* rc) {
+  if (g.K < 512 || g.M < 256 || !pairs_ok(g)) return false;
+  auto go = [&](auto kern, int bm, int bn, int threads) {
+    const int tm = ceil_div(g.M, bm), tn = ceil_div(g.N, bn);
+    kern<<<dim3(tm * tn * g.count * g.nbatch), dim3(threads), 0, s>>>(g, tm, tn);
+    const hipError_t e = hipGetLastError();
+    *rc = e == hipSuccess ? 0 : hip_fail(e, "float32 skinny tile", __LINE__);
+  };
+  if (g.N <= 160)
+    go(gemm_skinny_f32x<TA, TB, TC, 96, 160, 2, 2>, 96, 160, 256);
+  else if ((long)g.M * g.count * g.nbatch >= 16384)
+    go(gemm_skinny_f32x<TA, TB, TC, 256, 144, 8, 1>, 256, 144, 512);
+  else
+    go(gemm_skinny_f32x<TA, TB, TC, 128, 144, 4, 1>, 128, 144, 256);
+  return true;
+}
+
 // float64 GEMMs long enough for the double-buffered tiles: N <= 160 takes
 // the 96 x 160 tile, wider N the 128 x 144 tile (144 divides the D^4 = 1296
 // columns of the double-layer absorptions at D = 6).
@@ -1181,6 +1394,19 @@ int launch_gemm(const GemmBatch& g, DT ta, DT tb, DT tc, hipStream_t s) {
     if (tc == DT::F64 && launch_f64_db(g, s, &rc)) return rc;
     if (tc == DT::F64) return launch_k4<double, double, double, double>(g, s);
     if (tc == DT::F32) return launch_k4<double, double, float, double>(g, s);
+  }
+  {
+    // the float32 contractions with long K on the double-buffered tile
+    int rc = 0;
+    if (ta == DT::F32 && tb == DT::F64 && tc == DT::F64 &&
+        launch_f32_db<float, double, double>(g, s, &rc))
+      return rc;
+    if (ta == DT::F64 && tb == DT::F32 && tc == DT::F32 &&
+        launch_f32_db<double, float, float>(g, s, &rc))
+      return rc;
+    if (ta == DT::F64 && tb == DT::F32 && tc == DT::F64 &&
+        launch_f32_db<double, float, double>(g, s, &rc))
+      return rc;
   }
   if (ta == DT::F32) {
     if (tb == DT::F64 && tc == DT::F64) return launch_k4<float, double, double, float>(g, s);

@@ -105,12 +105,12 @@ def test_full_size_si_move_matches_oracle(oracle_move):
 
 # Largest deviation of a unit-norm corner spectrum from the float64
 # oracle's after one move, per contraction precision: measured 3.2e-7
-# (float32) and 5.6e-4 (bfloat16) on MI355X; the bounds leave a factor of
-# about five above them.
-SPECTRUM_TOL = {"f32": 2e-6, "bf16": 3e-3, "bf16x3": 1e-4}
+# (float32), 5.6e-4 (bfloat16) and 1.9e-6 (split bfloat16) on MI355X; the
+# bounds leave a factor of about five above them.
+SPECTRUM_TOL = {"f32": 2e-6, "bf16": 3e-3, "bf16x3": 1e-5}
 
 
-@pytest.mark.parametrize("prec,pinv", [("f32", 1e-6), ("bf16", 1e-2), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("prec,pinv", [("f32", 1e-6), ("bf16", 1e-2), ("bf16x3", 1e-8)])
 def test_full_size_reduced_precision_move_matches_oracle_spectra(oracle_move, prec, pinv):
     """One SI move with float32 or bfloat16 contractions (float32
     accumulation) from the same state as the float64 oracle move: the corner
@@ -175,10 +175,12 @@ def test_full_size_triangular_energy_gradient_directional_differences():
 def test_full_size_precision_modes_converged_energy():
     """Config 3 (D=6, chi=144) converged in each contraction precision from
     one shared growth move (full SVD, float64): the float64 run to delta <
-    1e-10, the float32 run to delta < 1e-6, the bfloat16 run for a fixed 40
-    moves (its rounded corners reach a fixed point of the rounded map), the
-    split bfloat16 run (three bf16 products per contraction) to delta <
-    1e-5.  The relative errors of the energy per site (<h>_H + <h>_V) and of
+    1e-10; the float32 and the split bfloat16 run (three bf16 products per
+    contraction) until delta < 1e-9 or 60 moves (their delta stalls at the
+    precision's noise, so they run the 60 moves and end at the fixed point
+    of the rounded map, not at a convergence cut of their own); the
+    bfloat16 run for a fixed 40 moves (its rounded corners reach a fixed
+    point of the rounded map, delta = 0).  The relative errors of the energy per site (<h>_H + <h>_V) and of
     the norm per site against the float64 run are printed; float32 and split
     bfloat16 meet the 1e-5 bound of the precision mode, plain bfloat16
     (8 significant bits) does not.  (The float64 run is the reference: its
@@ -198,8 +200,8 @@ def test_full_size_precision_modes_converged_energy():
     ref.close()
     print(f"f64: {r['moves']} moves to delta {r['delta']:.2e}, e = {e64:.12f}, kappa = {k64:.12f}")
     errs = {}
-    for prec, pinv, tol, moves in (("f32", 1e-6, 1e-6, 200), ("bf16", 1e-2, 0.0, 40),
-                                   ("bf16x3", 1e-4, 1e-5, 200)):
+    for prec, pinv, tol, moves in (("f32", 1e-6, 1e-9, 60), ("bf16", 1e-2, 0.0, 40),
+                                   ("bf16x3", 1e-8, 1e-9, 60)):
         c2 = P.Config(d=2, D=D6, chi=CHI, p=P16, n_si=NSI, prec=prec, pinv_rtol=pinv)
         ctx = P.Ctm(c2, torch.from_numpy(A).to(dev))
         ctx.set_state(grown)
