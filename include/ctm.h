@@ -487,6 +487,21 @@ ctm_status ctm_gemm_f64_split(int count, const double* const* A, const double* c
  * step 1).  Zero columns get tau = 0 and no division by zero. */
 ctm_status ctm_qr_f64(int count, double* const* W, int N, int k, void* stream);
 
+/* ctm_qr_f64 without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  The same kernels and result as ctm_qr_f64 (bit for
+ * bit), with their workspace in a static device array of
+ * ctm_qr_f64_noalloc_max_bytes() bytes (96 MiB) that each device holds
+ * until the process ends; CTM_E_NOMEM when the workspace of (count, N, k)
+ * exceeds it (8 blocks of 5184 x 160 need 71 MiB), CTM_E_ARG for shapes
+ * without a QR leaf split.  Stream-ordered and asynchronous (no
+ * synchronisation; ctm_qr_f64 synchronises).  Every call on a device
+ * shares that device's array: calls that may overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller.  The
+ * array needs no initial contents, so nothing is cleared between calls. */
+size_t ctm_qr_f64_noalloc_max_bytes(void);
+ctm_status ctm_qr_f64_noalloc(int count, double* const* W, int N, int k, void* stream);
+
 /* Singular value decomposition of `count` n x n row-major matrices
  * (QR-based projector section, step 2): rho_i = u_i diag(s_i) v_i^T with
  * s descending.  u_i and v_i are n x n row-major (columns are the singular

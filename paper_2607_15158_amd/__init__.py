@@ -115,6 +115,9 @@ _sigs = {
                                           _vp, ctypes.c_size_t, ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int), _vp]),
     "ctm_qr_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),
+    "ctm_qr_f64_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int,
+                                          ctypes.c_int, _vp]),
+    "ctm_qr_f64_noalloc_max_bytes": (ctypes.c_size_t, []),
     "ctm_vjp_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ctm_config), ctypes.POINTER(ctypes.c_size_t)]),
     "ctm_move_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t]),
     "ctm_energy_vjp": (ctypes.c_int, [_vp, _vp, _dp, _dp, _vp, _vp, _vp, ctypes.c_size_t]),
@@ -750,6 +753,13 @@ def qr_f64(W: Sequence, stream=None):
     """In-place thin Householder QR (R_ii >= 0) of N x k device matrices."""
     N, k = W[0].shape
     _check(_lib.ctm_qr_f64(len(W), _ptr_array(W), N, k, _stream(stream)))
+
+
+def qr_f64_noalloc(W: Sequence, stream=None):
+    """As :func:`qr_f64`, with the library's static scratch (no allocation,
+    no synchronisation)."""
+    N, k = W[0].shape
+    _check(_lib.ctm_qr_f64_noalloc(len(W), _ptr_array(W), N, k, _stream(stream)))
 
 
 def svd_f64(rho: Sequence, u: Sequence, s: Sequence, v: Sequence, stream=None):

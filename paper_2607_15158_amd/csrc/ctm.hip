@@ -2453,6 +2453,69 @@ ctm_status ctm_qr_f64(int count, double* const* W, int N, int k, void* stream) {
   return r ? (ctm_status)(r == 1 ? CTM_E_ARG : r) : CTM_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free thin QR: the workspace of launch_qr lives in a file-scope
+// device array instead of a hipMalloc'd buffer.  Each device holds its own
+// copy of the array at its own address; the host-side name is only a symbol,
+// so the address used in kernel arguments is taken once per device with
+// hipGetSymbolAddress (with that device current) and kept.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)96 << 20;   // 96 MiB per device
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of this device's scratch array (resolved on first use).
+int scratch_address(void** out) {
+  int dev = 0;
+  CTM_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(nullptr, CTM_E_DEVICE, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, CTM_E_DEVICE,
+                  std::string("hipGetSymbolAddress of the QR scratch failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ctm_qr_f64_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+ctm_status ctm_qr_f64_noalloc(int count, double* const* W, int N, int k, void* stream) {
+  if (count < 0 || count > kMaxProb || !W || k < 1 || N < k)
+    return (ctm_status)fail(nullptr, CTM_E_ARG, "invalid qr arguments");
+  if (count == 0) return CTM_OK;
+  if (k > 192 || !qr_plan_ok(N, k))
+    return (ctm_status)fail(nullptr, CTM_E_ARG,
+                            "no QR leaf partition for these N, k (need k <= 192 and N/k not too large)");
+  const size_t need = qr_workspace_bytes(count, N, k);
+  if (need > kNoAllocScratchBytes)
+    return (ctm_status)fail(nullptr, CTM_E_NOMEM,
+                            "QR workspace of " + std::to_string(need) + " bytes exceeds the " +
+                                std::to_string(kNoAllocScratchBytes) + "-byte static scratch");
+  void* ws = nullptr;
+  const int rs = scratch_address(&ws);
+  if (rs) return (ctm_status)rs;
+  const int r = launch_qr(count, W, N, k, ws, (hipStream_t)stream);
+  return r ? (ctm_status)(r == 1 ? CTM_E_ARG : r) : CTM_OK;
+}
+
 ctm_status ctm_svd_f64(int count, const double* const* rho, double* const* u, double* const* s,
                        double* const* v, int n, void* stream) {
   if (count < 0 || count > kMaxProb || !rho || !s || n < 1)
