@@ -509,6 +509,108 @@ ctm_status ctm_qr_f64_noalloc(int count, double* const* W, int N, int k, void* s
 ctm_status ctm_svd_f64(int count, const double* const* rho, double* const* u,
                        double* const* s, double* const* v, int n, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Unit cells (End Matter, larger unit-cell CTMRG): an Lx x Ly cell of
+ * different site tensors, site (x, y) in column x and row y, periodic.
+ * Every site has its own environment C1..C4, T1..T4 (the single-site index
+ * conventions; the dimensions of each tensor are its own while the
+ * environment grows, chi after it).  One iteration is a left, a top, a right
+ * and a bottom move, the latter three being the left move of the cell turned
+ * by 90, 180 and 270 degrees.  A left move renormalises column by column:
+ * the left cut of every 2 x 2 cluster of a column gets its own projectors
+ * from M = Ct3 Ct4 Ct1 Ct2 of the cluster's four enlarged corners (each
+ * site's own), then the left environment (C1, T4, C4) of the column moves
+ * one column to the right: C1' = P_r (C1 T1), T4' = P_r (T4 a) P_l,
+ * C4' = (T3 C4) P_l, each normalised to unit Frobenius norm.
+ * Projector kinds per cut: identities while the cut is not larger than chi
+ * (CTM_CELL_GROW); randomized SVD: n_si subspace steps from the cut's fixed
+ * start blocks (their first rows while the environment grows), which stay
+ * unchanged (CTM_CELL_RSVD, the warm-up); subspace iteration on the cut's
+ * own blocks, recycled as X v, Y^T u (CTM_CELL_SI, QR-based projector
+ * section); the full SVD of M (CTM_CELL_SVD, Standard CTMRG section; also
+ * taken when a randomized or SI step cannot run: fewer block rows than k, or
+ * an environment still growing).  One stream per cell; every call is
+ * synchronous.
+ * ------------------------------------------------------------------------- */
+typedef struct ctm_cell ctm_cell;
+
+enum { CTM_CELL_RSVD = 0, CTM_CELL_SI = 1, CTM_CELL_SVD = 2, CTM_CELL_GROW = 3 };
+
+typedef struct {
+  int Lx, Ly;       /* columns and rows of the cell (1..16)                              */
+  int d;            /* physical dimension; 0 = network tensors a given directly          */
+  int D;            /* virtual bond dimension of A, or leg dimension of a when d == 0    */
+  int chi;          /* environment bond dimension; chi >= Dl (= D^2, or D when d == 0)   */
+  int p;            /* oversampling; k = min(chi + p, chi Dl) <= 192                     */
+  int n_si;         /* subspace steps per cut and move (>= 0)                            */
+  int stabilized;   /* 1: orthonormalise after M and after M^T; 0: only after M^T M      */
+  double pinv_rtol; /* s_i <= pinv_rtol * s_1 gives s_i^-1/2 := 0                        */
+} ctm_cell_config;
+
+/* Device bytes ctm_cell_create allocates for cfg. */
+ctm_status ctm_cell_workspace_bytes(const ctm_cell_config* cfg, size_t* bytes);
+
+/* Creates a cell.  sites_dev: Lx*Ly site tensors in device memory, site
+ * (x, y) at index y*Lx + x, each A[s, u, l, d, r] (d*D^4 doubles; the double
+ * layer a = sum_s A A is formed on the device, iPEPS section) or, when
+ * d == 0, the network tensor a[u, l, d, r] (D^4 doubles).  boundary_dev:
+ * Lx*Ly*4*Dl doubles in device memory, the vectors that close leg u, l, d, r
+ * (in that order) of each site when it forms part of a neighbour's initial
+ * environment (every tensor of site (x, y) is the neighbour in its direction
+ * with its outer legs closed), or NULL for the ket-bra delta vectors (d > 0)
+ * or all-ones vectors (d == 0).  The initial environment is normalised and
+ * its corner spectra recorded.  Inputs are copied; the caller keeps them.
+ * CTM_E_SHAPE / CTM_E_ARG for invalid configurations, CTM_E_NOMEM when the
+ * workspace (ctm_cell_workspace_bytes) cannot be allocated. */
+ctm_status ctm_cell_create(ctm_cell** out, const ctm_cell_config* cfg, const double* sites_dev,
+                           const double* boundary_dev);
+void ctm_cell_destroy(ctm_cell* cell);
+/* Last error message recorded on the cell, or "" if none. */
+const char* ctm_cell_last_error(const ctm_cell* cell);
+
+/* Start blocks of every cut (device memory, copied): X and Y^T, each
+ * [4 directions][Lx*Ly cuts][chi*Dl][k] row-major; cut (x', y') of direction
+ * d is the left cut of cluster (x', y') of the cell turned d times, at index
+ * y'*Lx' + x' with Lx' = Lx for d = 0, 2 and Ly for d = 1, 3 (one turn puts
+ * site (x, y) of a cell of width w at (y, w - 1 - x)). */
+ctm_status ctm_cell_set_blocks(ctm_cell* cell, const double* X_dev, const double* Yt_dev);
+
+/* One iteration (left, top, right, bottom moves) with projectors of the
+ * given kind (CTM_CELL_RSVD, CTM_CELL_SI or CTM_CELL_SVD; see above; an SI
+ * iteration after one of another kind starts from the start blocks).
+ * *delta (may be NULL): the largest over sites and corners of
+ * |s_new - s_old|_2 of the unit-norm corner spectra zero-padded to chi
+ * (QR-based projector section, step 4).  CTM_E_STATE without start blocks
+ * (RSVD, SI); CTM_E_NUMERIC on a zero or non-finite norm (the environment is
+ * then undefined). */
+ctm_status ctm_cell_iterate(ctm_cell* cell, int mode, double* delta);
+
+/* Iterations until convergence: warm-up iterations of kind warm_mode
+ * (CTM_CELL_RSVD or CTM_CELL_SVD) while fewer than `warmup` iterations were
+ * made or some site's C1 has fewer than chi rows, then CTM_CELL_SI
+ * iterations until delta < tol or max_iter iterations in all.  *iters: the
+ * iterations made; deltas[i] and kinds[i] (may be NULL, else max_iter
+ * entries): delta and kind of iteration i.  CTM_E_NOT_CONVERGED when the
+ * budget ran out (the environment stays valid). */
+ctm_status ctm_cell_run(ctm_cell* cell, int warmup, int warm_mode, double tol, int max_iter,
+                        int* iters, double* deltas, int* kinds);
+
+/* Doubles of the host environment layout: per site (index y*Lx + x) the
+ * corners C1..C4, each in a chi x chi slot, then the edges T1..T4, each in a
+ * chi x Dl x chi slot, every tensor row-major at the start of its slot with
+ * its own dimensions (zeros after it). */
+ctm_status ctm_cell_env_size(const ctm_cell* cell, size_t* n);
+/* Copies the environment to host memory (n doubles) and its dimensions to
+ * dims (16 ints per site: rows, cols of C1..C4, then in, out of T1..T4). */
+ctm_status ctm_cell_get_env(ctm_cell* cell, double* host, size_t n, int* dims);
+/* Replaces the environment (dimensions 1..chi and consistent around every
+ * corner), records its corner spectra; the next SI iteration starts from
+ * the start blocks. */
+ctm_status ctm_cell_set_env(ctm_cell* cell, const double* host, size_t n, const int* dims);
+/* Copies the current blocks of every cut (the recycled ones after SI
+ * iterations; layout of ctm_cell_set_blocks) to host memory. */
+ctm_status ctm_cell_get_blocks(ctm_cell* cell, double* X_host, double* Yt_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,7 +69,18 @@ class ctm_prof_entry(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class ctm_cell_config(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("d", ctypes.c_int),
+                ("D", ctypes.c_int), ("chi", ctypes.c_int), ("p", ctypes.c_int),
+                ("n_si", ctypes.c_int), ("stabilized", ctypes.c_int),
+                ("pinv_rtol", ctypes.c_double)]
+
+
+CELL_RSVD, CELL_SI, CELL_SVD, CELL_GROW = range(4)
+CELL_MODE = {"rsvd": CELL_RSVD, "si": CELL_SI, "svd": CELL_SVD}
+
 _vp, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
 _sigs = {
     "ctm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "ctm_last_error": (ctypes.c_char_p, [_vp]),
@@ -128,6 +139,20 @@ _sigs = {
                                            _dp]),
     "ctm_svd_f64": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _vp]),
+    "ctm_cell_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(ctm_cell_config),
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "ctm_cell_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(ctm_cell_config), _vp,
+                                       _vp]),
+    "ctm_cell_destroy": (None, [_vp]),
+    "ctm_cell_last_error": (ctypes.c_char_p, [_vp]),
+    "ctm_cell_set_blocks": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ctm_cell_iterate": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "ctm_cell_run": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                    _ip, _dp, _ip]),
+    "ctm_cell_env_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ctm_cell_get_env": (ctypes.c_int, [_vp, _dp, ctypes.c_size_t, _ip]),
+    "ctm_cell_set_env": (ctypes.c_int, [_vp, _dp, ctypes.c_size_t, _ip]),
+    "ctm_cell_get_blocks": (ctypes.c_int, [_vp, _dp, _dp]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -767,3 +792,160 @@ def svd_f64(rho: Sequence, u: Sequence, s: Sequence, v: Sequence, stream=None):
     _check(_lib.ctm_svd_f64(len(rho), _ptr_array(rho), None if u is None else _ptr_array(u),
                             _ptr_array(s), None if v is None else _ptr_array(v), n,
                             _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# unit cells (ctm_cell_* of include/ctm.h)
+# ---------------------------------------------------------------------------
+def _check_cell(status: int, h=None):
+    if status != CTM_OK:
+        raise CtmError(status, _lib.ctm_cell_last_error(h).decode())
+    return status
+
+
+@dataclass
+class CellConfig:
+    Lx: int
+    Ly: int
+    d: int
+    D: int
+    chi: int
+    p: int = 8
+    n_si: int = 2
+    stabilized: int = 1
+    pinv_rtol: float = 1e-12
+
+    @property
+    def Dl(self) -> int:
+        return self.D * self.D if self.d > 0 else self.D
+
+    @property
+    def N(self) -> int:
+        return self.chi * self.Dl
+
+    @property
+    def k(self) -> int:
+        return min(self.chi + self.p, self.N)
+
+    @property
+    def ns(self) -> int:
+        return self.Lx * self.Ly
+
+    def c(self) -> ctm_cell_config:
+        return ctm_cell_config(self.Lx, self.Ly, self.d, self.D, self.chi, self.p, self.n_si,
+                               self.stabilized, self.pinv_rtol)
+
+
+def cell_workspace_bytes(cfg: CellConfig) -> int:
+    n = ctypes.c_size_t(0)
+    _check_cell(_lib.ctm_cell_workspace_bytes(ctypes.byref(cfg.c()), ctypes.byref(n)))
+    return int(n.value)
+
+
+class Cell:
+    """CTMRG of an Lx x Ly unit cell on the GPU.
+
+    ``sites``: a float64 device tensor of the Lx*Ly site tensors, site
+    (x, y) at index y*Lx + x (A[s, u, l, d, r], or a[u, l, d, r] when
+    d == 0); ``boundary``: None or a device tensor [Lx*Ly, 4, Dl] of the
+    vectors that close legs u, l, d, r of each site in its neighbours'
+    initial environments."""
+
+    def __init__(self, cfg: CellConfig, sites, boundary=None):
+        self.cfg = cfg
+        self._h = _vp()
+        self._keep = (sites.contiguous(), None if boundary is None else boundary.contiguous())
+        torch.cuda.synchronize()   # the cell copies the inputs on its own stream
+        _check_cell(_lib.ctm_cell_create(ctypes.byref(self._h), ctypes.byref(cfg.c()),
+                                         self._keep[0].data_ptr(),
+                                         None if boundary is None else self._keep[1].data_ptr()))
+
+    def close(self):
+        if self._h:
+            _lib.ctm_cell_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        self.close()
+
+    def set_blocks(self, X, Yt):
+        """Start blocks [4, Lx*Ly, N, k] (device tensors) of every cut."""
+        X, Yt = X.contiguous(), Yt.contiguous()
+        torch.cuda.synchronize()
+        _check_cell(_lib.ctm_cell_set_blocks(self._h, X.data_ptr(), Yt.data_ptr()), self._h)
+
+    def iterate(self, mode: str = "si") -> float:
+        delta = ctypes.c_double(0.0)
+        _check_cell(_lib.ctm_cell_iterate(self._h, CELL_MODE[mode], ctypes.byref(delta)), self._h)
+        return float(delta.value)
+
+    def run(self, warmup: int, tol: float, max_iter: int, warm_mode: str = "rsvd") -> dict:
+        iters = ctypes.c_int(0)
+        deltas = (ctypes.c_double * max(1, max_iter))()
+        kinds = (ctypes.c_int * max(1, max_iter))()
+        st = _lib.ctm_cell_run(self._h, warmup, CELL_MODE[warm_mode], tol, max_iter,
+                               ctypes.byref(iters), deltas, kinds)
+        if st not in (CTM_OK, CTM_E_NOT_CONVERGED):
+            _check_cell(st, self._h)
+        n = iters.value
+        names = {CELL_RSVD: "rsvd", CELL_SI: "si", CELL_SVD: "svd"}
+        return {"iters": n, "converged": st == CTM_OK, "deltas": list(deltas[:n]),
+                "kinds": [names[k] for k in kinds[:n]]}
+
+    def _env_size(self) -> int:
+        n = ctypes.c_size_t(0)
+        _check_cell(_lib.ctm_cell_env_size(self._h, ctypes.byref(n)), self._h)
+        return int(n.value)
+
+    def get_env(self) -> dict:
+        """{(x, y): (C1..C4, T1..T4)} as numpy arrays of their own shapes."""
+        cfg = self.cfg
+        n = self._env_size()
+        buf = np.zeros(n)
+        dims = (ctypes.c_int * (16 * cfg.ns))()
+        _check_cell(_lib.ctm_cell_get_env(self._h, buf.ctypes.data_as(_dp), n, dims), self._h)
+        chi, Dl = cfg.chi, cfg.Dl
+        out, off = {}, 0
+        for s in range(cfg.ns):
+            C, T = [], []
+            for i in range(4):
+                r, c = dims[16 * s + 2 * i], dims[16 * s + 2 * i + 1]
+                C.append(buf[off:off + r * c].reshape(r, c).copy())
+                off += chi * chi
+            for i in range(4):
+                a, b = dims[16 * s + 8 + 2 * i], dims[16 * s + 9 + 2 * i]
+                T.append(buf[off:off + a * Dl * b].reshape(a, Dl, b).copy())
+                off += chi * Dl * chi
+            out[(s % cfg.Lx, s // cfg.Lx)] = (C, T)
+        return out
+
+    def set_env(self, env: dict):
+        cfg = self.cfg
+        chi, Dl = cfg.chi, cfg.Dl
+        buf = np.zeros(self._env_size())
+        dims = (ctypes.c_int * (16 * cfg.ns))()
+        off = 0
+        for s in range(cfg.ns):
+            C, T = env[(s % cfg.Lx, s // cfg.Lx)]
+            for i in range(4):
+                r, c = C[i].shape
+                buf[off:off + r * c] = np.ascontiguousarray(C[i]).ravel()
+                dims[16 * s + 2 * i], dims[16 * s + 2 * i + 1] = r, c
+                off += chi * chi
+            for i in range(4):
+                a, _, b = T[i].shape
+                buf[off:off + a * Dl * b] = np.ascontiguousarray(T[i]).ravel()
+                dims[16 * s + 8 + 2 * i], dims[16 * s + 9 + 2 * i] = a, b
+                off += chi * Dl * chi
+        _check_cell(_lib.ctm_cell_set_env(self._h, buf.ctypes.data_as(_dp), buf.size, dims),
+                    self._h)
+
+    def get_blocks(self):
+        cfg = self.cfg
+        X = np.zeros((4, cfg.ns, cfg.N, cfg.k))
+        Y = np.zeros_like(X)
+        _check_cell(_lib.ctm_cell_get_blocks(self._h, X.ctypes.data_as(_dp), Y.ctypes.data_as(_dp)),
+                    self._h)
+        return X, Y
