@@ -611,6 +611,75 @@ ctm_status ctm_cell_set_env(ctm_cell* cell, const double* host, size_t n, const 
  * iterations; layout of ctm_cell_set_blocks) to host memory. */
 ctm_status ctm_cell_get_blocks(ctm_cell* cell, double* X_host, double* Yt_host);
 
+/* State vector of a cell whose environment has dimension chi (device
+ * memory, float64): per site (index y*Lx + x) C1..C4 (chi x chi each) then
+ * T1..T4 (chi x Dl x chi each), then X and then Y^T of every cut in the
+ * layout of ctm_cell_set_blocks.  get: the environment and the blocks the
+ * next SI iteration starts from (CTM_E_STATE while the environment is still
+ * growing); set: replaces both, and the next SI iterations continue from
+ * these blocks.  Both synchronise. */
+ctm_status ctm_cell_state_size(const ctm_cell* cell, size_t* n);
+ctm_status ctm_cell_get_state_device(ctm_cell* cell, double* dev, size_t n);
+ctm_status ctm_cell_set_state_device(ctm_cell* cell, const double* dev, size_t n);
+
+/* Vector-Jacobian product of one SI iteration of the cell (Differentiable
+ * fixed point passage, eq. implicit: gradients are built from the VJPs of
+ * single iterations; unrolling them gives the gradient of an energy after a
+ * number of iterations).  The iteration is recomputed from state_in (device,
+ * ctm_cell_state_size doubles, every cut an SI cut with the state's own
+ * blocks), and state_out receives its result (may be NULL).  With
+ * state_out_bar (the cotangent of the output state, device) the cotangent
+ * of state_in is written to state_in_bar (device) and that of the site
+ * tensors added to site_bar (device, Lx*Ly*d*D^4 doubles, or the network
+ * tensors' Lx*Ly*D^4 when d == 0; may be NULL).  Discrete choices of the
+ * iteration (QR diagonal signs, the sign rule, the pseudo-inverse mask) are
+ * held fixed.  The intermediates live in device memory the cell allocates
+ * on the first call and keeps (about 40 x 4 chi^2 Dl^4 bytes per cut of an
+ * iteration for the corners and their cotangents); CTM_E_NOMEM if it cannot.
+ * Synchronises; the cell's own environment is not changed. */
+ctm_status ctm_cell_move_vjp(ctm_cell* cell, const double* state_in, const double* state_out_bar,
+                             double* state_in_bar, double* site_bar, double* state_out);
+
+/* Energy per site of the cell's state (device, as above; its blocks are not
+ * read): e = (1 / (Lx Ly)) sum over the sites (x, y) and over the bonds in
+ * the mask `bonds` (1: horizontal to (x+1, y), 2: vertical to (x, y+1),
+ * 4: diagonal to (x+1, y+1)) of <op_b> from the two-site reduced density
+ * matrix (iPEPS section, observables; the diagonal bond on the 2 x 2
+ * plaquette of the four enlarged corners).  ops_host: three d^2 x d^2
+ * operators op[(t1 t2), (s1 s2)] (bra, ket) for h, v, d in turn (host
+ * memory; those outside the mask are not read).  With state_bar and/or
+ * site_bar (device, may be NULL) the gradient: state_bar is written (the
+ * blocks' part zero), site_bar accumulated.  Needs d > 0.  Synchronises. */
+ctm_status ctm_cell_energy_vjp(ctm_cell* cell, const double* state, const double* ops_host,
+                               int bonds, double* e_out, double* state_bar, double* site_bar);
+
+/* ---------------------------------------------------------------------------
+ * Self-checks of the adjoint's building blocks (test infrastructure for the
+ * cell adjoint): each runs one operation of the reverse-mode tape on the
+ * default stream, seeds the cotangent of its output and returns the output
+ * and the input cotangents (device memory throughout, synchronous).
+ *
+ * GEMM with the library's descriptor: dims = {M, N, K, transA, cdiv_m,
+ * cdiv_n, nbatch}, strides = {lda, ldb, cs_m1, cs_m0, cs_n1, cs_n0, a_bs,
+ * b_bs, c_bs}; C (nC doubles, zero where the map writes nothing) = alpha
+ * op(A) B; Abar, Bbar receive the cotangents for the output cotangent Cbar.
+ * QR: Q_j = thin Householder QR of H_j (R_jj >= 0), count blocks n x k in a
+ * row; Hbar for Qbar.  Projector factors: rho (k x k) and the sign source
+ * Yt (nrows x k) give outs = [us, vs (k x k each), vsc, usc (k x keep
+ * each)] (see the QR-based projector section), bars in the same layout give
+ * rhobar.  Normalisation: count tensors of n[t] doubles in a row, y = x / |x|
+ * each; xbar for ybar. */
+ctm_status ctm_tape_check_gemm(const int* dims, const long* strides, double alpha, const double* A,
+                               long nA, const double* B, long nB, double* C, long nC,
+                               const double* Cbar, double* Abar, double* Bbar);
+ctm_status ctm_tape_check_qr(int count, int n, int k, const double* H, double* Q, const double* Qbar,
+                             double* Hbar);
+ctm_status ctm_tape_check_svdproj(int k, int keep, int nrows, double rtol, const double* rho,
+                                  const double* Yt, double* outs, const double* bars,
+                                  double* rhobar);
+ctm_status ctm_tape_check_normalize(int count, const long* n, const double* x, double* y,
+                                    const double* ybar, double* xbar);
+
 #ifdef __cplusplus
 }
 #endif

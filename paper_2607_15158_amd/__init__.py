@@ -153,6 +153,11 @@ _sigs = {
     "ctm_cell_get_env": (ctypes.c_int, [_vp, _dp, ctypes.c_size_t, _ip]),
     "ctm_cell_set_env": (ctypes.c_int, [_vp, _dp, ctypes.c_size_t, _ip]),
     "ctm_cell_get_blocks": (ctypes.c_int, [_vp, _dp, _dp]),
+    "ctm_cell_state_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ctm_cell_get_state_device": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "ctm_cell_set_state_device": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "ctm_cell_move_vjp": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "ctm_cell_energy_vjp": (ctypes.c_int, [_vp, _vp, _dp, ctypes.c_int, _dp, _vp, _vp]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -942,6 +947,73 @@ class Cell:
         _check_cell(_lib.ctm_cell_set_env(self._h, buf.ctypes.data_as(_dp), buf.size, dims),
                     self._h)
 
+    # --- state vector and adjoint ------------------------------------------
+    def state_size(self) -> int:
+        n = ctypes.c_size_t(0)
+        _check_cell(_lib.ctm_cell_state_size(self._h, ctypes.byref(n)), self._h)
+        return int(n.value)
+
+    def get_state_device(self):
+        """The state vector (environment of dimension chi and the blocks the
+        next SI iteration starts from) as a float64 device tensor."""
+        out = torch.empty(self.state_size(), dtype=torch.float64, device=self._keep[0].device)
+        torch.cuda.synchronize()
+        _check_cell(_lib.ctm_cell_get_state_device(self._h, out.data_ptr(), out.numel()), self._h)
+        return out
+
+    def set_state_device(self, state):
+        state = state.contiguous()
+        torch.cuda.synchronize()
+        _check_cell(_lib.ctm_cell_set_state_device(self._h, state.data_ptr(), state.numel()),
+                    self._h)
+
+    def site_size(self) -> int:
+        cfg = self.cfg
+        return cfg.ns * (cfg.d * cfg.D ** 4 if cfg.d > 0 else cfg.Dl ** 4)
+
+    def move_vjp(self, state, bar=None, site_bar=None, want_out=True):
+        """One SI iteration from ``state`` (device tensor): returns
+        (state_out or None, state_bar or None, site_bar); with ``bar`` the
+        cotangent of the output state, ``site_bar`` (created when None)
+        accumulates the site tensors' cotangent."""
+        state = state.contiguous()
+        dev = state.device
+        out = torch.empty_like(state) if want_out else None
+        sbar = None
+        if bar is not None:
+            bar = bar.contiguous()
+            sbar = torch.empty_like(state)
+            if site_bar is None:
+                site_bar = torch.zeros(self.site_size(), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        _check_cell(_lib.ctm_cell_move_vjp(
+            self._h, state.data_ptr(), None if bar is None else bar.data_ptr(),
+            None if sbar is None else sbar.data_ptr(),
+            None if site_bar is None else site_bar.data_ptr(),
+            None if out is None else out.data_ptr()), self._h)
+        return out, sbar, site_bar
+
+    def energy_vjp(self, state, ops: dict, grad: bool = True, site_bar=None):
+        """Energy per site sum over the bonds in ``ops`` ({'h'|'v'|'d':
+        operator d^2 x d^2}); with ``grad`` also (state_bar, site_bar)."""
+        d = self.cfg.d
+        mask, buf = 0, np.zeros((3, d * d, d * d))
+        for b, name in enumerate("hvd"):
+            if name in ops:
+                mask |= 1 << b
+                buf[b] = np.asarray(ops[name], dtype=np.float64)
+        state = state.contiguous()
+        e = ctypes.c_double(0.0)
+        sbar = torch.empty_like(state) if grad else None
+        if grad and site_bar is None:
+            site_bar = torch.zeros(self.site_size(), dtype=torch.float64, device=state.device)
+        torch.cuda.synchronize()
+        _check_cell(_lib.ctm_cell_energy_vjp(
+            self._h, state.data_ptr(), buf.ctypes.data_as(_dp), mask, ctypes.byref(e),
+            None if sbar is None else sbar.data_ptr(),
+            None if not grad else site_bar.data_ptr()), self._h)
+        return (float(e.value), sbar, site_bar) if grad else float(e.value)
+
     def get_blocks(self):
         cfg = self.cfg
         X = np.zeros((4, cfg.ns, cfg.N, cfg.k))
@@ -949,3 +1021,37 @@ class Cell:
         _check_cell(_lib.ctm_cell_get_blocks(self._h, X.ctypes.data_as(_dp), Y.ctypes.data_as(_dp)),
                     self._h)
         return X, Y
+
+
+def unrolled_cell_energy(sites, cfg: CellConfig, ops: dict, state0, moves: int):
+    """Energy per site of the cell (bonds and operators in ``ops``) after
+    ``moves`` SI iterations from ``state0`` (a float64 device state vector of
+    a cell environment of dimension chi), differentiable with respect to the
+    stacked site tensors ``sites`` ([Lx*Ly, d, D, D, D, D], site (x, y) at
+    y*Lx + x) by unrolling: the forward pass keeps the state at every
+    iteration boundary on the device (checkpoints), the backward pass takes
+    the energy's gradient and then the adjoint of every iteration from its
+    checkpoint in reverse order, recomputing each iteration there."""
+
+    class _Unrolled(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, site):
+            c = Cell(cfg, site.detach())
+            c.set_state_device(state0.detach())
+            states = [state0.detach().clone()]
+            for _ in range(moves):
+                c.iterate("si")
+                states.append(c.get_state_device())
+            e, bar, site_bar = c.energy_vjp(states[-1], ops)
+            for st in reversed(states[:-1]):
+                _, bar, site_bar = c.move_vjp(st, bar, site_bar, want_out=False)
+            ctx.save_for_backward(site_bar.reshape(site.shape))
+            c.close()
+            return torch.tensor(e, dtype=torch.float64, device=site.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            (grad,) = ctx.saved_tensors
+            return g * grad
+
+    return _Unrolled.apply(sites)

@@ -27,33 +27,20 @@
 // Cuts of a column with equal shapes run batched (the X and Y blocks of up
 // to four cuts per launch).  All launches are ordered on the cell's stream.
 
-#include "../../include/ctm.h"
+#include "cell.h"
 
-#include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <limits>
-#include <string>
-#include <vector>
 
-#include "common.h"
 #include "elem.h"
 
 using namespace sictm;
 
 namespace {
-
-constexpr int kCellMaxSide = 16;
-constexpr int kCutsPerLaunch = 4;   // X and Y blocks of 4 cuts = 8 problems
-
-inline int imod(int a, int m) { return ((a % m) + m) % m; }
-
-struct Span {
-  uintptr_t a, b;
-};
 
 struct CellCarver {
   char* base = nullptr;
@@ -69,15 +56,6 @@ struct CellCarver {
   void* take_bytes(size_t bytes) { return (void*)take((bytes + 7) / 8); }
 };
 
-// Environment of one site: tensor pointers and dimensions (rows, cols of the
-// corners; in, out of the edges, whose middle leg has the network's Dl).
-struct SiteEnv {
-  double* C[4];
-  double* T[4];
-  int Cd[4][2];
-  int Td[4][2];
-};
-
 // One cut of a column step: the four cluster corners and what the cut's
 // projectors need.
 struct Cut {
@@ -88,47 +66,6 @@ struct Cut {
   int keep;
   int cid;               // index of the cut's blocks in its direction
 };
-
-}  // namespace
-
-struct ctm_cell {
-  ctm_cell_config cfg;
-  int Lx = 0, Ly = 0, ns = 0, Dl = 0, chi = 0, k = 0, Nf = 0, Lmax = 0;
-  hipStream_t st = nullptr;
-  rocblas_handle rb = nullptr;
-  char* mem = nullptr;
-  std::vector<std::pair<uintptr_t, uintptr_t>> bufs;
-  std::string err;
-  // sites
-  std::vector<double*> A, a, ap, apr;   // ap, apr: [site * 4 + corner]
-  std::vector<SiteEnv> env;
-  std::vector<double*> spare;           // [Lmax * 3] targets of the new tensors of a column
-  // blocks [dir * ns + cut]
-  std::vector<double*> X0, Y0, X, Y;
-  bool blocks_set = false;
-  int last_mode = -1;
-  // per-cut work of a column step
-  std::vector<double*> Q, Wst, CT;      // [Lmax * 4]
-  std::vector<double*> B;               // [Lmax * 6] N x k blocks
-  std::vector<double*> rho, u, v, vs, s, sg, vsc, usc, Pl, Prt, Z1, Z2;   // [Lmax]
-  std::vector<double*> F;               // full SVD: R, L, M, Ut, Uv, U sorted, Vt sorted, Us, Vs
-  double *fs = nullptr, *fE = nullptr, *fsg = nullptr;
-  int *finfo = nullptr, *fperm = nullptr;
-  // spectra
-  std::vector<double*> cpad, csv;       // [ns * 4]
-  double* spec[2] = {nullptr, nullptr};
-  int spec_cur = 0;
-  double* bvec = nullptr;               // [ns][4][Dl] boundary vectors of the initial environment
-  double* scal = nullptr;               // [0..63] norms, [64..64+ns) per-site delta
-  int* bad = nullptr;
-  double* norm_part = nullptr;
-  void* qr_ws = nullptr;
-  void* svd_ws = nullptr;
-  double* sk_part = nullptr;
-  long iterations = 0;
-};
-
-namespace {
 
 int cfail(ctm_cell* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -184,28 +121,6 @@ int check_gemm(ctm_cell* c, const GemmBatch& g) {
   return 0;
 }
 
-GemmBatch gemm_of(int M, int N, int K, long lda, long ldb, long ldc) {
-  GemmBatch g{};
-  g.count = 0;
-  g.M = M;
-  g.N = N;
-  g.K = K;
-  g.lda = lda;
-  g.ldb = ldb;
-  gemm_set_rowmajor_c(g, ldc);
-  g.nbatch = 1;
-  g.alpha = 1.0;
-  return g;
-}
-
-void add(GemmBatch& g, const double* A, const double* B, double* C, int transA = 0) {
-  g.A[g.count] = A;
-  g.B[g.count] = B;
-  g.C[g.count] = C;
-  g.transA[g.count] = transA;
-  ++g.count;
-}
-
 // Launches a float64 GEMM (the subspace-iteration shape takes the kernels of
 // the single-site SI applications).
 int run(ctm_cell* c, const GemmBatch& g, bool si = false) {
@@ -217,25 +132,6 @@ int run(ctm_cell* c, const GemmBatch& g, bool si = false) {
     CTRY(launch_gemm(g, DT::F64, DT::F64, DT::F64, c->st));
   }
   return 0;
-}
-
-// ---------------------------------------------------------------------------
-// the turned cell
-// ---------------------------------------------------------------------------
-inline int width(const ctm_cell* c, int d) { return (d & 1) ? c->Ly : c->Lx; }
-inline int height(const ctm_cell* c, int d) { return (d & 1) ? c->Lx : c->Ly; }
-
-// Site of the cell at (x', y') of the cell turned d times (one turn maps
-// site (x, y) of a cell of width w to (y, w - 1 - x)).
-int site_of(const ctm_cell* c, int d, int xt, int yt) {
-  int x = imod(xt, width(c, d)), y = imod(yt, height(c, d));
-  for (int t = d; t >= 1; --t) {
-    const int w_prev = ((t - 1) & 1) ? c->Ly : c->Lx;
-    const int xp = w_prev - 1 - y, yp = x;
-    x = xp;
-    y = yp;
-  }
-  return y * c->Lx + x;
 }
 
 // ---------------------------------------------------------------------------
@@ -1134,8 +1030,9 @@ ctm_status ctm_cell_iterate(ctm_cell* cell, int mode, double* delta) {
   if (!cell) return (ctm_status)cfail(nullptr, CTM_E_ARG, "null cell");
   if (mode != CTM_CELL_RSVD && mode != CTM_CELL_SI && mode != CTM_CELL_SVD)
     return (ctm_status)cfail(cell, CTM_E_ARG, "mode must be CTM_CELL_RSVD, _SI or _SVD");
-  if (mode != CTM_CELL_SVD && !cell->blocks_set)
-    return (ctm_status)cfail(cell, CTM_E_STATE, "set the start blocks first");
+  const bool si_from_state = mode == CTM_CELL_SI && cell->cur_set && cell->last_mode == CTM_CELL_SI;
+  if (mode != CTM_CELL_SVD && !cell->blocks_set && !si_from_state)
+    return (ctm_status)cfail(cell, CTM_E_STATE, "set the start blocks (or a state) first");
   cell->err.clear();
   const int r = iteration(cell, mode, delta);
   return (ctm_status)r;

@@ -316,12 +316,14 @@ struct KmatArgs {
   int n;
 };
 
-// Inner matrix of the SVD adjoint; the inverse gaps carry a Lorentzian
-// broadening (1e-12 s_1^2)^2 that only matters for (near-)degenerate pairs.
+// Inner matrix of the SVD adjoint.  The inverse gaps 1 / (s_j^2 - s_i^2)
+// carry a Lorentzian broadening relative to the pair, (1e-14 (s_i^2 +
+// s_j^2))^2, which only changes pairs degenerate to rounding: the kept
+// singular values of rho span many orders of magnitude, so a broadening on
+// the scale of s_1^2 would suppress the gaps among the small ones.
 __global__ __launch_bounds__(256) void k_svd_kmat(KmatArgs a) {
   const int b = blockIdx.y, n = a.n;
   const double* s = a.s[b];
-  const double e2 = 1e-12 * s[0] * s[0], eps = e2 * e2;
   for (int idx = blockIdx.x * 256 + threadIdx.x; idx < n * n; idx += gridDim.x * 256) {
     const int i = idx / n, j = idx % n;
     double v;
@@ -329,7 +331,8 @@ __global__ __launch_bounds__(256) void k_svd_kmat(KmatArgs a) {
       v = a.sb[b][i];
     } else {
       const double dl = s[j] * s[j] - s[i] * s[i];
-      const double F = dl / (dl * dl + eps);
+      const double e2 = 1e-14 * (s[i] * s[i] + s[j] * s[j]);
+      const double F = dl / (dl * dl + e2 * e2);
       v = F * (a.Ju[b][idx] - a.Ju[b][j * n + i]) * s[j] +
           s[i] * F * (a.Jv[b][idx] - a.Jv[b][j * n + i]);
     }

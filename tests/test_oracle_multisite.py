@@ -281,3 +281,161 @@ def test_planted_cell_mistakes_are_caught(monkeypatch):
     monkeypatch.undo()
     monkeypatch.setattr(M, "_turn_a", lambda t: t)
     assert not ising_cell_errors(a, imp, e, 3, 3, beta)[0] <= 1e-6
+
+
+# --------------------------------------------------------------------------
+# the reverse-mode reference of the cell iteration and energy
+# --------------------------------------------------------------------------
+import torch  # noqa: E402
+
+import oracle.multisite_adjoint as MA  # noqa: E402
+
+HEIS = S.heisenberg_bond()
+
+
+def full_cell(Lx, Ly, D=2, chi=8, p=4, seed=5):
+    """A random PEPS cell whose environment has reached chi (two randomized
+    warm-up iterations, one SI iteration), with its recycled blocks."""
+    A = {(x, y): S.product_plus_noise_site(2, D, seed + 7 * x + 3 * y, noise=0.5)
+         for x in range(Lx) for y in range(Ly)}
+    a = {s: O.double_layer(t) for s, t in A.items()}
+    N, k = chi * D * D, chi + p
+    iso0 = blocks(Lx, Ly, N, k, 31)
+    cell = M.cell_initial_env(a, Lx, Ly, S.trace_boundary(D), A=A)
+    for _ in range(2):
+        cell, _, _ = M.ctm_iteration(cell, chi, "rsvd", iso0)
+    cell, cur, _ = M.ctm_iteration(cell, chi, "si", {d: dict(iso0[d]) for d in range(4)})
+    assert all(e.chi == chi for e in cell.env.values())
+    return cell, cur, A
+
+
+def as_env(cell):
+    return {s: ([c.copy() for c in e.C], [t.copy() for t in e.T]) for s, e in cell.env.items()}
+
+
+def test_torch_cell_iteration_equals_the_numpy_one():
+    cell, cur, A = full_cell(3, 2)
+    new, iso_n, _ = M.ctm_iteration(cell, 8, "si", cur)
+    tt = lambda v: torch.as_tensor(v)  # noqa: E731
+    env_t = {s: ([tt(c) for c in C], [tt(t) for t in T]) for s, (C, T) in as_env(cell).items()}
+    iso_t = {d: {k: (tt(X), tt(Y)) for k, (X, Y) in cur[d].items()} for d in range(4)}
+    env_o, iso_o = MA.cell_iteration_torch(env_t, iso_t, {s: tt(v) for s, v in A.items()}, 3, 2, 8)
+    for s, e in new.env.items():
+        for g, o in zip(env_o[s][0] + env_o[s][1], e.C + e.T):
+            assert np.abs(g.numpy() - o).max() <= 1e-12 * np.abs(o).max()
+    # the kept columns of the recycled blocks tightly; the oversampled ones
+    # (weak directions, set by rounding) loosely
+    for d in range(4):
+        for k, (X, Y) in iso_n[d].items():
+            for g, o in ((iso_o[d][k][0].numpy(), X), (iso_o[d][k][1].numpy(), Y)):
+                assert np.abs(g[:, :8] - o[:, :8]).max() <= 1e-11
+                assert np.abs(g - o).max() <= 1e-8
+
+
+def test_torch_cell_energy_equals_the_numpy_one():
+    cell, _, A = full_cell(2, 2)
+    ops = {"h": HEIS, "v": 0.5 * HEIS, "d": 0.25 * HEIS}
+    e_np = M.cell_energy(cell, ops)
+    tt = lambda v: torch.as_tensor(v)  # noqa: E731
+    env_t = {s: ([tt(c) for c in C], [tt(t) for t in T]) for s, (C, T) in as_env(cell).items()}
+    e_t = float(MA.cell_energy_torch(env_t, {s: tt(v) for s, v in A.items()}, 2, 2, ops))
+    assert abs(e_t - e_np) <= 1e-13 * abs(e_np)
+
+
+def _dot(a, b):
+    return float(np.sum(a * b))
+
+
+def test_cell_move_vjp_matches_central_differences_of_the_numpy_oracle():
+    """<bar, d(iteration)> along random directions of every site tensor and of
+    the environment, from central differences of the NumPy iteration."""
+    Lx, Ly, chi = 2, 2, 8
+    cell, cur, A = full_cell(Lx, Ly)
+    rng = np.random.default_rng(3)
+    new, iso_n, _ = M.ctm_iteration(cell, chi, "si", cur)
+    env_b = {s: ([rng.standard_normal(c.shape) for c in e.C], [rng.standard_normal(t.shape) for t in e.T])
+             for s, e in new.env.items()}
+    # cotangents on the kept columns of the recycled blocks only: the
+    # oversampled columns are weak directions set by rounding, whose finite
+    # differences are not in the linear regime
+    def kept(shape):
+        b = rng.standard_normal(shape)
+        b[:, chi:] = 0.0
+        return b
+
+    iso_b = {d: {k: (kept(X.shape), kept(Y.shape)) for k, (X, Y) in iso_n[d].items()}
+             for d in range(4)}
+    env_g, iso_g, A_g = MA.cell_move_vjp(as_env(cell), cur, A, Lx, Ly, chi, (env_b, iso_b))
+
+    def f(cell_, A_, cur_):
+        c2 = cell_.copy()
+        c2.a = {s: O.double_layer(t) for s, t in A_.items()}
+        out, iso_o, _ = M.ctm_iteration(c2, chi, "si", cur_)
+        v = 0.0
+        for s, e in out.env.items():
+            v += sum(_dot(o, w) for o, w in zip(e.C + e.T, env_b[s][0] + env_b[s][1]))
+        for d in range(4):
+            for k, (X, Y) in iso_o[d].items():
+                v += _dot(X, iso_b[d][k][0]) + _dot(Y, iso_b[d][k][1])
+        return v
+
+    h = 1e-6
+    dA = {s: rng.standard_normal(t.shape) for s, t in A.items()}
+    fd = (f(cell, {s: A[s] + h * dA[s] for s in A}, cur) -
+          f(cell, {s: A[s] - h * dA[s] for s in A}, cur)) / (2 * h)
+    an = sum(_dot(A_g[s], dA[s]) for s in A)
+    assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+def test_energy_after_an_iteration_matches_central_differences_along_the_environment():
+    """The environment direction through a gauge-invariant function: the
+    energy after one SI iteration (random environment perturbations break
+    the ket-bra symmetry that pairs entries of equal magnitude, so the sign
+    rule can pick other signs; closed networks do not see the signs)."""
+    Lx, Ly, chi = 2, 2, 8
+    cell, cur, A = full_cell(Lx, Ly)
+    ops = {"h": HEIS, "v": HEIS, "d": HEIS}
+    new, _, _ = M.ctm_iteration(cell, chi, "si", cur)
+    _, env_b, _ = MA.cell_energy_vjp(as_env(new), A, Lx, Ly, ops)
+    iso_b = {d: {k: (np.zeros_like(X), np.zeros_like(Y)) for k, (X, Y) in cur[d].items()}
+             for d in range(4)}
+    env_g, _, _ = MA.cell_move_vjp(as_env(cell), cur, A, Lx, Ly, chi, (env_b, iso_b))
+    rng = np.random.default_rng(5)
+    dE = {s: ([rng.standard_normal(c.shape) for c in e.C], [rng.standard_normal(t.shape) for t in e.T])
+          for s, e in cell.env.items()}
+    # the iteration carries rounding noise of ~1e-11 (weak directions of the
+    # blocks), so the step is 1e-4; the central difference then agrees with
+    # the adjoint to ~5e-6 relative (1e-6: noise-limited at ~1e-4)
+    h = 1e-4
+
+    def f(sign):
+        c2 = cell.copy()
+        for s, e in c2.env.items():
+            c2.env[s] = O.Env([c + sign * h * g for c, g in zip(e.C, dE[s][0])],
+                              [t + sign * h * g for t, g in zip(e.T, dE[s][1])])
+        out, _, _ = M.ctm_iteration(c2, chi, "si", cur)
+        return M.cell_energy(out, ops)
+
+    fd = (f(1) - f(-1)) / (2 * h)
+    an = sum(_dot(g, w) for s in env_g for g, w in zip(env_g[s][0] + env_g[s][1], dE[s][0] + dE[s][1]))
+    assert abs(fd - an) <= 2e-5 * max(1e-3, abs(an)), (fd, an)
+
+
+def test_cell_energy_vjp_matches_central_differences_of_the_numpy_oracle():
+    Lx, Ly = 2, 2
+    cell, _, A = full_cell(Lx, Ly)
+    ops = {"h": HEIS, "v": HEIS, "d": HEIS}
+    e, env_g, A_g = MA.cell_energy_vjp(as_env(cell), A, Lx, Ly, ops)
+    assert abs(e - M.cell_energy(cell, ops)) <= 1e-13
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    dA = {s: rng.standard_normal(t.shape) for s, t in A.items()}
+
+    def fa(sign):
+        c2 = cell.copy()
+        c2.A = {s: A[s] + sign * h * dA[s] for s in A}
+        c2.a = {s: O.double_layer(t) for s, t in c2.A.items()}   # closed layers of the diagonal bonds
+        return M.cell_energy(c2, ops)
+
+    fd = (fa(1) - fa(-1)) / (2 * h)
+    an = sum(_dot(A_g[s], dA[s]) for s in A)
+    assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (fd, an)
