@@ -196,6 +196,72 @@ def serving(args, n_requests):
     return out
 
 
+def unit_cell(args):
+    """The 3x3 unit cell of nine different site tensors at D=5, chi=100,
+    p=5 (the paper's variational optimisation workload, larger unit-cell
+    passage of the End Matter): randomized-SVD warm-up iterations, timed SI
+    iterations (left, top, right and bottom moves, column by column), and one
+    optimisation step: the triangular-lattice energy per site after
+    ``args.cell_moves`` SI iterations and its gradient with respect to the
+    nine site tensors through the unrolled iterations (checkpoints at every
+    iteration boundary, the adjoint of every iteration recomputed from its
+    checkpoint)."""
+    import torch
+    import paper_2607_15158_amd as P
+    import synth as S
+
+    dev = torch.device("cuda", 0)
+    Lx, Ly, D = 3, 3, 5
+    cfg = P.CellConfig(Lx, Ly, d=2, D=D, chi=100, p=5, n_si=2)
+    sites = np.stack([S.product_plus_noise_site(2, D, 40 + 7 * (s % Lx) + 3 * (s // Lx), noise=0.05)
+                      for s in range(cfg.ns)])
+    X = np.zeros((4, cfg.ns, cfg.N, cfg.k))
+    Y = np.zeros_like(X)
+    for d in range(4):
+        lx, ly = (Lx, Ly) if d % 2 == 0 else (Ly, Lx)
+        for y in range(ly):
+            for x in range(lx):
+                X[d, y * lx + x] = S.gaussian_block(cfg.N, cfg.k, 31 + 100 * d + 10 * x + y)
+                Y[d, y * lx + x] = S.gaussian_block(cfg.N, cfg.k, 1031 + 100 * d + 10 * x + y)
+    st_sites = torch.from_numpy(sites).to(dev)
+    c = P.Cell(cfg, st_sites)
+    c.set_blocks(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
+    del X, Y
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        c.iterate("rsvd")
+    t_warm = (time.perf_counter() - t) / 3
+    n_si = 10
+    t = time.perf_counter()
+    deltas = [c.iterate("si") for _ in range(n_si)]
+    t_si = (time.perf_counter() - t) / n_si
+    state = c.get_state_device()
+    c.close()
+    h = S.heisenberg_bond()
+    ops = {"h": h, "v": h, "d": h}
+    out = {"workload": f"{Lx}x{Ly} unit cell, nine d=2 D={D} site tensors, chi=100, p=5, n_si=2, "
+                       f"N={cfg.N}; iteration = left, top, right, bottom moves",
+           "warmup_iteration_s": round(t_warm, 4), "si_iteration_s": round(t_si, 4),
+           "si_deltas": [float(f"{d:.3e}") for d in deltas]}
+    if args.cell_moves > 0:
+        x = st_sites.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        e = P.unrolled_cell_energy(x, cfg, ops, state, args.cell_moves)
+        e.backward()
+        torch.cuda.synchronize()
+        t_opt = time.perf_counter() - t
+        out.update({"optimisation_step_iterations": args.cell_moves,
+                    "optimisation_step_s": round(t_opt, 3),
+                    "energy_per_site": e.item(),
+                    "gradient_norm": float(x.grad.norm())})
+        log(f"unit cell: SI iteration {t_si:.3f} s; energy {e.item():.10f} and its gradient "
+            f"through {args.cell_moves} iterations in {t_opt:.1f} s")
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +325,10 @@ def main():
     ap.add_argument("--serve-batch-n", type=int, default=1296,
                     help="requests with chi * D^2 up to this move together in grouped launches "
                          "(ctm_move_batch) in the batched serving mode")
+    ap.add_argument("--cell-moves", type=int, default=30,
+                    help="SI iterations of the unit-cell optimisation step (3x3 cell, D=5, "
+                         "chi=100; -1: skip the unit-cell sub-measurement, 0: time the "
+                         "iterations only)")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving sub-measurement of the default run (0: skip)")
     args = ap.parse_args()
@@ -518,6 +588,10 @@ def main():
     if args.serve_requests > 0 and args.prec == "f64":
         serve = serving(args, args.serve_requests)
 
+    cell = None
+    if args.cell_moves >= 0 and args.prec == "f64":
+        cell = unit_cell(args)
+
 
     value = args.steps / elapsed
     out = {
@@ -544,6 +618,7 @@ def main():
         "converged_environment": conv,
         "speedup_vs_full_svd": None if svd is None else round(value / svd["moves_per_s"], 2),
         "serving": serve,
+        "unit_cell": cell,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -160,8 +160,10 @@ struct ctm_ctx {
   // signalled by done_ev; the host-side state advances in finish_move
   double* hbuf = nullptr;    // [0..15] scal copy, [16] bad flag (as int)
   hipEvent_t done_ev = nullptr;
-  // second stream of a move: the new corners' norms and spectra run on it
-  // while the edges are renormalised (fork and join by events)
+  // second stream of an eager move: the new corners' norms and spectra run
+  // on it while the edges are renormalised (fork and join by events).
+  // Created on the first eager move that uses it; contexts that replay
+  // captured moves (ctm_use_graphs) keep the one-stream schedule.
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool pending = false;
@@ -1203,7 +1205,7 @@ int move_work(ctm_ctx* c, int mode, int keep, int nsi, bool measure) {
     TRY(si_projectors(c, keep, nsi, measure));
   }
   const int nxt = 1 - c->cur;
-  if (c->cfg.sym == CTM_SYM_C4V || c->rec || !c->side) {
+  if (c->cfg.sym == CTM_SYM_C4V || c->rec || c->use_graphs) {
     TRY(renormalize_corners(c, keep));
     TRY(renormalize_edges(c, keep));
     if (c->cfg.sym == CTM_SYM_C4V) TRY(c4v_finish(c, nxt, keep));
@@ -1215,6 +1217,17 @@ int move_work(ctm_ctx* c, int mode, int keep, int nsi, bool measure) {
   // stream while the edges are renormalised: the same operations on the same
   // data, in a different schedule
   TRY(renormalize_corners(c, keep));
+  if (!c->side) {
+    if ((!c->ev_fork &&
+         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) ||
+        (!c->ev_join &&
+         hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+      c->side = nullptr;
+      (void)hipGetLastError();
+      return fail(c, CTM_E_DEVICE, "creation of the second stream or its events failed");
+    }
+  }
   CTM_HIP_TRY(hipEventRecord(c->ev_fork, c->st));
   CTM_HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
   {
@@ -1997,10 +2010,7 @@ ctm_status ctm_init(ctm_ctx** out, const ctm_config* cfg, const double* site_dev
   c->ws_bytes = need;
   carve(c, (char*)c->ws);
   if (hipHostMalloc((void**)&c->hbuf, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+      hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming) != hipSuccess) {
     std::string m = "pinned host buffer or event creation failed";
     ctm_destroy(c);
     return (ctm_status)fail(nullptr, CTM_E_NOMEM, m);
