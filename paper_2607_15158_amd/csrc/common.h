@@ -47,6 +47,71 @@ __device__ __forceinline__ double wave_sum64(double x) {
   return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
 }
 
+// Exchange of two doubles between lanes L and L ^ 32 (gfx950 permlane32
+// swap: the upper half of `a` trades places with the lower half of `b`).
+// After the call a + b holds, in every lane, its own value of the half it
+// keeps (a for lanes < 32, b for lanes >= 32) plus the partner's value of
+// the same half.
+__device__ __forceinline__ void swap_halves32(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// The same between L and L ^ 16 (permlane16 swap: the odd 16-lane rows of
+// `a` trade places with the even rows of `b`).
+__device__ __forceinline__ void swap_halves16(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// One halving level through a DPP pattern whose partner differs from the
+// lane in bit `bit`: the lane keeps `lo` (bit clear) or `hi` (bit set) and
+// adds the partner's value of the same half.
+template <int CTRL>
+__device__ __forceinline__ double dpp_halve(double lo, double hi, bool bit) {
+  const double send = bit ? lo : hi;
+  return (bit ? hi : lo) + dpp_mov_f64<CTRL>(send);
+}
+
+// Transpose-reduction of 32 per-lane values p(0..31) over the wavefront:
+// lane L returns the sum over all 64 lanes of p(L >> 1).  Each level halves
+// the values a lane holds by trading half of them with a partner lane: L^32
+// and L^16 by the permlane swaps, then L^8 (row_ror:8), L^7 (row_half_mirror)
+// and L^3 (quad_perm 3,2,1,0) by DPP, the kept half chosen by bits 5..1 of
+// L; a last exchange with L^1 (quad_perm 1,0,3,2) completes the sum.  The
+// six partner masks are linearly independent over GF(2), so every lane's
+// contribution enters each result exactly once.  p(s) is evaluated in pairs
+// (s, s + 16) as the first level consumes them.
+template <typename PF>
+__device__ __forceinline__ double wave_xsum32(const PF& p, int lane) {
+  double q[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    double a = p(s), b = p(s + 16);
+    swap_halves32(a, b);
+    q[s] = a + b;
+  }
+  double r[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    double a = q[s], b = q[s + 8];
+    swap_halves16(a, b);
+    r[s] = a + b;
+  }
+  double t[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) t[s] = dpp_halve<0x128>(r[s], r[s + 4], (lane >> 3) & 1);
+  double u[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) u[s] = dpp_halve<0x141>(t[s], t[s + 2], (lane >> 2) & 1);
+  const double v = dpp_halve<0x1B>(u[0], u[1], (lane >> 1) & 1);
+  return v + dpp_mov_f64<0xB1>(v);
+}
+
 #define CTM_HIP_TRY(expr)                                              \
   do {                                                                 \
     hipError_t _e = (expr);                                            \

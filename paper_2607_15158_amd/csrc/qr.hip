@@ -47,6 +47,12 @@ __device__ __forceinline__ double wave_sum(double x) { return wave_sum64(x); }
 // cores (v_mfma_f64_16x16x4: operand lane l -> (row l%16, k l/16), result
 // element r -> (row l/16 + 4r, column l%16)).  16x16 blocks are dealt to the
 // four wavefronts; `store(m, n, value)` receives every result element once.
+// The operands of kMmStage k-steps are read into registers before their
+// products issue, so that one LDS latency covers kMmStage products, and the
+// products rotate over four accumulators.  Indices outside the operands are
+// clamped to element (0, 0) for the read and their values replaced by zero,
+// so every LDS read stays inside the caller's arrays.
+constexpr int kMmStage = 8;
 template <typename FA, typename FB, typename FS>
 __device__ __forceinline__ void lds_mm(int M, int N, int K, FA A, FB B, FS store, int wave,
                                        int lane) {
@@ -54,27 +60,28 @@ __device__ __forceinline__ void lds_mm(int M, int N, int K, FA A, FB B, FS store
   for (int blk = wave; blk < bm * bn; blk += 4) {
     const int i0 = (blk / bn) << 4, j0 = (blk % bn) << 4;
     const int ar = i0 + (lane & 15), bc = j0 + (lane & 15);
-    v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-    int k0 = 0;
-    for (; k0 + 8 <= K; k0 += 8) {
-      const int ka = k0 + (lane >> 4), kb = ka + 4;
-      const double a0 = ar < M ? A(ar, ka) : 0.0;
-      const double b0 = bc < N ? B(ka, bc) : 0.0;
-      const double a1 = ar < M ? A(ar, kb) : 0.0;
-      const double b1 = bc < N ? B(kb, bc) : 0.0;
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
-    }
-    for (; k0 < K; k0 += 4) {
-      const int ka = k0 + (lane >> 4);
-      const double a0 = (ar < M && ka < K) ? A(ar, ka) : 0.0;
-      const double b0 = (bc < N && ka < K) ? B(ka, bc) : 0.0;
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+    const bool ain = ar < M, bin = bc < N;
+    const int arc = ain ? ar : 0, bcc = bin ? bc : 0;
+    v4d acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    for (int k0 = 0; k0 < K; k0 += 4 * kMmStage) {
+      double a[kMmStage], b[kMmStage];
+#pragma unroll
+      for (int u = 0; u < kMmStage; ++u) {
+        const int ka = k0 + 4 * u + (lane >> 4);
+        const bool kin = ka < K;
+        const int kc = kin ? ka : 0;
+        const double av = A(arc, kc), bv = B(kc, bcc);
+        a[u] = (ain && kin) ? av : 0.0;
+        b[u] = (bin && kin) ? bv : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kMmStage; ++u)
+        acc[u & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u & 3], 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = i0 + (lane >> 4) + 4 * r, col = j0 + (lane & 15);
-      if (row < M && col < N) store(row, col, acc0[r] + acc1[r]);
+      if (row < M && col < N) store(row, col, (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]));
     }
   }
 }
@@ -136,22 +143,22 @@ __device__ __forceinline__ void build_T(double (*T)[kT], double (*G)[kT], const 
 }
 
 // ---------------------------------------------------------------------------
-// Householder factorisation of one panel by a single wavefront, with the
-// panel in registers: x[r][c] is row (lane + 64 r), column c.  The pivot of
-// column j is row j (lane j, r = 0); below(j, r) selects the rows that carry
-// reflector j under the pivot.  Per column the wavefront forms the reflector
-// (dlarfg convention); one reduction then gives both v_j^T x_s for the later
-// columns s > j (applied at once) and v_s^T v_j for the earlier ones (the
-// Gram column of the WY factor T).  The 32 per-lane partial sums of a step
-// are reduced through LDS: every lane writes its row of partials, lane l
-// adds column l % 32 over one half of the rows, and the halves meet in one
-// cross-lane exchange; the scaled sums are read back as LDS broadcasts.
-// The wavefront's LDS traffic is ordered by itself, so no barrier is needed.
+// Householder factorisation of one panel by the four wavefronts of a
+// workgroup, each holding 64 rows of the panel in registers: x[c] is column
+// c of the lane's row.  The pivot of column j is row j, held by lane j of
+// wavefront 0; on(j) says whether the lane's row carries reflector j (lies
+// below the pivot).  Rows and columns outside the panel are held as zeros,
+// so they take part in every sum without changing it.  Per column every
+// wavefront reduces its share of the squared norm and wavefront 0 publishes
+// the pivot; after a barrier all wavefronts form the same reflector (dlarfg
+// convention); one transpose-reduction per wavefront (wave_xsum32) of the
+// products v_j^T x_s, a barrier, and the four shares summed in a fixed
+// order give every wavefront the same v_j^T x_s for the later columns s > j
+// (applied at once from scalar registers) and v_s^T v_j for the earlier
+// ones (the Gram column of the WY factor T, written by wavefront 0).  The
+// shared sums are double-buffered by column parity, so two barriers per
+// column order all reads and writes.
 // ---------------------------------------------------------------------------
-struct PanelScratch {
-  double P[64][kT];   // per-lane partial sums
-  double F[kPanel];   // tau * v_j^T x_s
-};
 
 // 1/x to full double precision from the hardware estimate (two Newton
 // steps); x is never zero where it is used.
@@ -161,23 +168,28 @@ __device__ __forceinline__ double fast_rcp(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+struct PanelShare {
+  double ss[2][4];          // squared norms below the pivot, per wavefront
+  double alpha[2];          // pivot value
+  double dot[2][4][kPanel]; // v_j^T x_s per wavefront
+};
+
 // Step J of the panel factorisation (J is a template parameter so that every
-// register of the panel is addressed statically).  Branch-free when FULL
-// (w == 32), so consecutive steps form one block the scheduler can overlap.
-template <int J, bool FULL, int RPL, typename Below>
-__device__ __forceinline__ void panel_step(double (&x)[RPL][kPanel], int w, int lane,
-                                           const Below& below, double* tau_out, double (*G)[kT],
-                                           PanelScratch& ps) {
-  if (FULL || J < w) {
-    bool bl[RPL];
-    double ss = 0.0;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      bl[r] = below(J, r);
-      ss += bl[r] ? x[r][J] * x[r][J] : 0.0;
-    }
-    ss = wave_sum64(ss);
-    const double alpha = readlane_f64(x[0][J], J);
+// register of the panel is addressed statically); columns J >= w are absent.
+template <int J, typename On>
+__device__ __forceinline__ void panel_step(double (&x)[kPanel], int w, int lane, int wave,
+                                           const On& on, double* tau_out, double (*G)[kT],
+                                           PanelShare& sh) {
+  if (J < w) {
+    constexpr int b = J & 1;
+    const bool bj = on(J);
+    const bool piv = wave == 0 && lane == J;
+    const double ssw = wave_sum64(bj ? x[J] * x[J] : 0.0);
+    if (lane == 0) sh.ss[b][wave] = ssw;
+    if (piv) sh.alpha[b] = x[J];
+    __syncthreads();
+    const double ss = (sh.ss[b][0] + sh.ss[b][1]) + (sh.ss[b][2] + sh.ss[b][3]);
+    const double alpha = sh.alpha[b];
     // dlarfg: beta = -sign(alpha) |(alpha, x)|, tau = (beta - alpha) / beta,
     // v = x / (alpha - beta); H = I (tau = 0) when x is exactly zero
     const bool live = ss > 0.0;
@@ -185,60 +197,39 @@ __device__ __forceinline__ void panel_step(double (&x)[RPL][kPanel], int w, int 
     const double beta = live ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
     const double tau = live ? (beta - alpha) * fast_rcp(beta) : 0.0;
     const double scal = live ? fast_rcp(alpha - beta) : 0.0;
-    double vj[RPL];
+    const double vj = bj ? x[J] * scal : (piv ? 1.0 : 0.0);
+    x[J] = bj ? vj : (piv ? beta : x[J]);
+    if (wave == 0 && lane == 0) tau_out[J] = tau;
+    const double part = wave_xsum32([&](int s) { return s == J ? 0.0 : vj * x[s]; }, lane);
+    const int col = lane >> 1;
+    if (!(lane & 1)) sh.dot[b][wave][col] = part;
+    __syncthreads();
+    const double tot =
+        (sh.dot[b][0][col] + sh.dot[b][1][col]) + (sh.dot[b][2][col] + sh.dot[b][3][col]);
+    if (wave == 0 && !(lane & 1) && col < J) G[col][J] = tot;
+    const double f = tau * tot;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      vj[r] = bl[r] ? x[r][J] * scal : ((r == 0 && lane == J) ? 1.0 : 0.0);
-      if (bl[r]) x[r][J] = vj[r];
-    }
-    if (lane == J) x[0][J] = beta;
-    if (lane == 0) tau_out[J] = tau;
-#pragma unroll
-    for (int s = 0; s < kPanel; ++s) {
-      double acc = 0.0;
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) acc += vj[r] * x[r][s];
-      ps.P[lane][s] = acc;
-    }
-    const int col = lane & 31, h = (lane >> 5) * 32;
-    double tot = 0.0;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) tot += ps.P[h + i][col];
-    tot += __shfl_xor(tot, 32, 64);
-    if (lane < 32) {
-      ps.F[lane] = tau * tot;
-      if (lane < J) G[lane][J] = tot;
-    }
-#pragma unroll
-    for (int s = J + 1; s < kPanel; ++s) {
-      if (FULL || s < w) {
-        const double f = ps.F[s];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) x[r][s] -= f * vj[r];
-      }
-    }
+    for (int s = J + 1; s < kPanel; ++s) x[s] -= readlane_f64(f, 2 * s) * vj;
   }
-  if constexpr (J + 1 < kPanel) panel_step<J + 1, FULL>(x, w, lane, below, tau_out, G, ps);
+  if constexpr (J + 1 < kPanel) panel_step<J + 1>(x, w, lane, wave, on, tau_out, G, sh);
 }
 
-template <int RPL, typename Below>
-__device__ __forceinline__ void wave_panel_qr(double (&x)[RPL][kPanel], int w, int lane, Below below,
-                                              double* tau_out, double (*G)[kT], PanelScratch& ps) {
-  if (w == kPanel)
-    panel_step<0, true>(x, w, lane, below, tau_out, G, ps);
-  else
-    panel_step<0, false>(x, w, lane, below, tau_out, G, ps);
+// The whole panel; afterwards wavefront 0 forms T from the Gram columns.
+template <typename On>
+__device__ __forceinline__ void block_panel_qr(double (&x)[kPanel], int w, int lane, int wave,
+                                               On on, double* tau_s, double (*G)[kT],
+                                               double (*T)[kT], PanelShare& sh) {
+  panel_step<0>(x, w, lane, wave, on, tau_s, G, sh);
+  if (wave == 0) build_T(T, G, tau_s, w, lane);
 }
 
 // ---------------------------------------------------------------------------
-// leaf factorisation of panel p + WY update of its trailing columns
+// leaf factorisation of panel p (the trailing columns: qr_leaf_wy)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void qr_leaf_factor(QrArgs q, int p) {
-  __shared__ double V[kPanel][kLR];           // panel, column-major
-  __shared__ double Cc[kPanel][kLR];          // trailing chunk, column-major
-  __shared__ double T[kPanel][kT], G[kPanel][kT], W1[kPanel][kT];
+  __shared__ double T[kPanel][kT], G[kPanel][kT];
   __shared__ double tau_s[kPanel];
-  __shared__ PanelScratch ps;
+  __shared__ PanelShare sh;
   const int leaf = blockIdx.x, mat = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = q.N, k = q.k, nb = q.nb;
@@ -247,74 +238,27 @@ __global__ __launch_bounds__(256) void qr_leaf_factor(QrArgs q, int p) {
   const int a0 = (leaf == 0) ? c0 : s;
   const int m = e - a0;
   double* A = q.A[mat];
-
-  if (wave == 0) {
-    constexpr int RPL = kLeafRows / 64;
-    double x[RPL][kPanel];
+  // row (lane + 64 wave) of the leaf's active rows; rows at or beyond m are
+  // held as zeros
+  const int row = lane + 64 * wave;
+  double x[kPanel];
+  {
+    const double* src = A + (long)(a0 + (row < m ? row : 0)) * k + c0;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int row = lane + 64 * r;
-      const double* src = A + (long)(a0 + row) * k + c0;
+    for (int c = 0; c < kPanel; ++c) x[c] = (row < m && c < w) ? src[c] : 0.0;
+  }
+  block_panel_qr(x, w, lane, wave, [&](int j) { return row > j; }, tau_s, G, T, sh);
+  if (row < m) {
+    double* dst = A + (long)(a0 + row) * k + c0;
 #pragma unroll
-      for (int c = 0; c < kPanel; ++c) x[r][c] = (row < m && c < w) ? src[c] : 0.0;
-    }
-    wave_panel_qr<RPL>(
-        x, w, lane,
-        [&](int j, int r) {
-          const int row = lane + 64 * r;
-          return row > j && row < m;
-        },
-        tau_s, G, ps);
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int row = lane + 64 * r;
-      double* dst = A + (long)(a0 + row) * k + c0;
-#pragma unroll
-      for (int c = 0; c < kPanel; ++c) {
-        if (row < m && c < w) dst[c] = x[r][c];
-        if (row < kLR) V[c][row] = x[r][c];
-      }
-    }
-    build_T(T, G, tau_s, w, lane);
+    for (int c = 0; c < kPanel; ++c)
+      if (c < w) dst[c] = x[c];
   }
   __syncthreads();
   const long sl = slot(mat, p, leaf, nb, q.P);
   if (tid < w) q.tau[sl * kPanel + tid] = tau_s[tid];
   for (int idx = tid; idx < kPanel * kPanel; idx += 256)
     q.Tl[sl * kPanel * kPanel + idx] = T[idx / kPanel][idx % kPanel];
-
-  // unit lower-trapezoidal V (implicit ones, zeros above) of the WY factor
-  auto Veff = [&](int r, int a) -> double {
-    return r > a ? V[a][r] : (r == a ? 1.0 : 0.0);
-  };
-  for (int cb = c0 + w; cb < k; cb += kPanel) {
-    const int nc = min(kPanel, k - cb);
-    __syncthreads();
-    g2l(m * kPanel, tid,
-        [&](int idx) {
-          const int r = idx / kPanel, c = idx % kPanel;
-          return c < nc ? A[(long)(a0 + r) * k + cb + c] : 0.0;
-        },
-        [&](int idx, double v) { Cc[idx % kPanel][idx / kPanel] = v; });
-    __syncthreads();
-    // W1 = V^T C  (w x nc)
-    lds_mm(w, nc, m, [&](int a, int r) { return Veff(r, a); },
-           [&](int r, int c) { return Cc[c][r]; }, [&](int i, int j, double x) { W1[i][j] = x; },
-           wave, lane);
-    __syncthreads();
-    // G <- T^T W1   (G reused as scratch)
-    lds_mm(w, nc, w, [&](int i, int l) { return T[l][i]; }, [&](int l, int c) { return W1[l][c]; },
-           [&](int i, int j, double x) { G[i][j] = x; }, wave, lane);
-    __syncthreads();
-    // C -= V G
-    lds_mm(m, nc, w, Veff, [&](int l, int c) { return G[l][c]; },
-           [&](int r, int c, double x) { Cc[c][r] -= x; }, wave, lane);
-    __syncthreads();
-    for (int idx = tid; idx < m * kPanel; idx += 256) {
-      const int r = idx / kPanel, c = idx % kPanel;
-      if (c < nc) A[(long)(a0 + r) * k + cb + c] = Cc[c][r];
-    }
-  }
 }
 
 // Top row of the w x w triangle a leaf holds during panel p.
@@ -325,30 +269,27 @@ __device__ __forceinline__ int top_row(int leaf, int c0, int N, int nb) {
 // ---------------------------------------------------------------------------
 // Reduction tree: a node at stride s combines the triangles of the leaves
 // a, a + s, ..., a + (kArity - 1) s (those below nb), a = node * s * kArity;
-// the first child keeps R, the others receive the reflector parts.  Row
-// (lane + 64 r) of the node's wavefront is row (lane & 31) of child
-// (lane >> 5) + 2 r.  The node's WY factor is stored in the slot of child 1,
-// s (4 i + 1), which no other node at any stride shares.
+// the first child keeps R, the others receive the reflector parts.  Lane l
+// of wavefront v holds row (l & 31) of child 2 v + (l >> 5).  The node's WY
+// factor is stored in the slot of child 1, s (kArity i + 1), which no other
+// node at any stride shares (its odd part times a power of kArity).
 // ---------------------------------------------------------------------------
-constexpr int kArity = 4;
-constexpr int kNodeRPL = kArity / 2;
-constexpr int kTrailN = 32;   // trailing columns per LDS chunk in the tree kernels
+constexpr int kArity = 8;
+static_assert(kArity == 2 * 4, "two children per wavefront, four wavefronts");
+constexpr int kTrailN = 32;   // columns per workgroup in the block-reflector kernels
+static_assert(kTrailN == kPanel, "the leaf and tree block-reflector chunks share one launch width");
 
 __device__ __forceinline__ int node_children(int a, int s, int nb) {
   return min(kArity, (nb - a + s - 1) / s);
 }
 
-// Wavefront 0 factors the stacked triangles [R_0; R_1; ...]; the reflectors
-// are [e_j; v_j] with v_j in the upper triangles of the children after the
-// first.  Trailing columns [c0 + w, k) of the node's rows:
-// W1 = C_0 + sum_h V_h^T C_h; W2 = T^T W1; C_0 -= W2; C_h -= V_h W2.
+// The workgroup factors the stacked triangles [R_0; R_1; ...]; the
+// reflectors are [e_j; v_j] with v_j in the upper triangles of the children
+// after the first (the node's trailing columns: qr_tree_wy).
 __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int s) {
-  __shared__ double Vs[kArity - 1][kPanel][kT];
   __shared__ double T[kPanel][kT], G[kPanel][kT];
-  __shared__ double Cs[kArity][kPanel][kTrailN + 1];
-  __shared__ double W1[kPanel][kTrailN + 1], W2[kPanel][kTrailN + 1];
   __shared__ double tau_s[kPanel];
-  __shared__ PanelScratch ps;
+  __shared__ PanelShare sh;
   const int a = blockIdx.x * s * kArity;
   const int mat = blockIdx.y;
   const int N = q.N, k = q.k, nb = q.nb;
@@ -356,110 +297,43 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int s) {
   const int nch = node_children(a, s, nb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
-  // top rows of the children, computed once (leaf_start divides in 64 bits)
-  __shared__ int tops[kArity];
-  if (tid < kArity) tops[tid] = tid < nch ? top_row(a + tid * s, c0, N, nb) : 0;
-  __syncthreads();
-  auto top = [&](int h) { return tops[h]; };
   double* A = q.A[mat];
-  if (wave == 0) {
-    const int rr = lane & 31;
-    double x[kNodeRPL][kPanel];
+  const int rr = lane & 31, h = 2 * wave + (lane >> 5);
+  const bool live = h < nch;
+  const long rowoff = live ? (long)(top_row(a + h * s, c0, N, nb) + rr) * k + c0 : 0;
+  double x[kPanel];
 #pragma unroll
-    for (int r = 0; r < kNodeRPL; ++r) {
-      const int h = (lane >> 5) + 2 * r;
-      const bool live = h < nch;
-      const double* src = A + (long)(live ? top(h) + rr : 0) * k + c0;
+  for (int c = 0; c < kPanel; ++c) x[c] = (live && rr <= c && c < w) ? A[rowoff + c] : 0.0;
+  // the reflectors live in the children after the first; their rows below
+  // the triangles and absent children are held as zeros
+  block_panel_qr(x, w, lane, wave, [&](int) { return h > 0; }, tau_s, G, T, sh);
+  if (live) {
 #pragma unroll
-      for (int c = 0; c < kPanel; ++c) x[r][c] = (live && rr <= c && c < w) ? src[c] : 0.0;
-    }
-    wave_panel_qr<kNodeRPL>(
-        x, w, lane,
-        [&](int j, int r) {
-          const int h = (lane >> 5) + 2 * r;
-          return h > 0 && h < nch && rr <= j;
-        },
-        tau_s, G, ps);
-#pragma unroll
-    for (int r = 0; r < kNodeRPL; ++r) {
-      const int h = (lane >> 5) + 2 * r;
-      if (h < nch) {
-        double* dst = A + (long)(top(h) + rr) * k + c0;
-#pragma unroll
-        for (int c = 0; c < kPanel; ++c) {
-          const bool in = rr <= c && c < w;
-          if (in) dst[c] = x[r][c];
-          if (h > 0) Vs[h - 1][rr][c] = in ? x[r][c] : 0.0;
-        }
-      }
-    }
-    build_T(T, G, tau_s, w, lane);
+    for (int c = 0; c < kPanel; ++c)
+      if (rr <= c && c < w) A[rowoff + c] = x[c];
   }
   __syncthreads();
   const long sl = slot(mat, p, a + s, nb, q.P);
   for (int idx = tid; idx < kPanel * kPanel; idx += 256)
     q.Tn[sl * kPanel * kPanel + idx] = T[idx / kPanel][idx % kPanel];
-  // children after the first stacked along one index: u = (h - 1) * kPanel + r
-  const int nv = (nch - 1) * kPanel;
-  auto V = [&](int u, int c) -> double { return Vs[u >> 5][u & 31][c]; };
-  for (int cb = c0 + w; cb < k; cb += kTrailN) {
-    const int nc = min(kTrailN, k - cb);
-    __syncthreads();
-    // rows r >= w of every child are loaded as zeros, so that the stacked
-    // products may run over full kPanel-row blocks
-    g2l(nch * kPanel * kTrailN, tid,
-        [&](int idx) {
-          const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
-          const int r = rc / kTrailN, c = rc % kTrailN;
-          return (r < w && c < nc) ? A[(long)(top(h) + r) * k + cb + c] : 0.0;
-        },
-        [&](int idx, double v) {
-          const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
-          Cs[h][rc / kTrailN][rc % kTrailN] = v;
-        });
-    __syncthreads();
-    lds_mm(w, nc, nv, [&](int i, int u) { return V(u, i); },
-           [&](int u, int c) { return Cs[1 + (u >> 5)][u & 31][c]; },
-           [&](int i, int j, double x) { W1[i][j] = x + Cs[0][i][j]; }, wave, lane);
-    __syncthreads();
-    lds_mm(w, nc, w, [&](int i, int l) { return T[l][i]; }, [&](int l, int c) { return W1[l][c]; },
-           [&](int i, int j, double x) { W2[i][j] = x; }, wave, lane);
-    __syncthreads();
-    lds_mm(nv, nc, w, V, [&](int l, int c) { return W2[l][c]; },
-           [&](int u, int c, double x) { Cs[1 + (u >> 5)][u & 31][c] -= x; }, wave, lane);
-    for (int idx = tid; idx < w * kTrailN; idx += 256) {
-      const int r = idx / kTrailN, c = idx % kTrailN;
-      if (c < nc) Cs[0][r][c] -= W2[r][c];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nch * w * kTrailN; idx += 256) {
-      const int h = idx / (w * kTrailN), rc = idx % (w * kTrailN);
-      const int r = rc / kTrailN, c = rc % kTrailN;
-      if (c < nc) A[(long)(top(h) + r) * k + cb + c] = Cs[h][r][c];
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
-// Q formation
+// Block reflectors applied to 32-column chunks, one chunk per workgroup
+// (blockIdx.z), so that the chunks of a leaf or node run side by side.
+// FORM = false: the trailing update of the factorisation, A <- H^T A on the
+// columns [c0 + w, k) (H = I - V T V^T, so H^T uses T^T); FORM = true: the
+// Q formation, E <- H E on the columns [c0, k).
 // ---------------------------------------------------------------------------
-__global__ void qr_init_e(QrArgs q) {
-  const int mat = blockIdx.y;
-  const long total = (long)q.N * q.k;
-  double* E = q.E[mat];
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
-       i += (long)gridDim.x * blockDim.x) {
-    const long r = i / q.k, c = i % q.k;
-    E[i] = (r == c) ? 1.0 : 0.0;
-  }
-}
 
-// E rows of the node <- Q_node E on columns [c0, k):
-// W1 = E_0 + sum_h V_h^T E_h; W2 = T W1; E_0 -= W2; E_h -= V_h W2.
-__global__ __launch_bounds__(256) void qr_tree_apply(QrArgs q, int p, int s) {
+// Node rows: W1 = C_0 + sum_h V_h^T C_h; W2 = op(T) W1; C_0 -= W2;
+// C_h -= V_h W2.
+template <bool FORM>
+__global__ __launch_bounds__(256) void qr_tree_wy(QrArgs q, int p, int s) {
   __shared__ double Vs[kArity - 1][kPanel][kT], T[kPanel][kT];
   __shared__ double Cs[kArity][kPanel][kTrailN + 1];
   __shared__ double W1[kPanel][kTrailN + 1], W2[kPanel][kTrailN + 1];
+  __shared__ int tops[kArity];
   const int a = blockIdx.x * s * kArity;
   const int mat = blockIdx.y;
   const int N = q.N, k = q.k, nb = q.nb;
@@ -467,12 +341,14 @@ __global__ __launch_bounds__(256) void qr_tree_apply(QrArgs q, int p, int s) {
   const int nch = node_children(a, s, nb);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
-  __shared__ int tops[kArity];
+  const int cb = (FORM ? c0 : c0 + w) + blockIdx.z * kTrailN;
+  if (cb >= k) return;
+  const int nc = min(kTrailN, k - cb);
   if (tid < kArity) tops[tid] = tid < nch ? top_row(a + tid * s, c0, N, nb) : 0;
   __syncthreads();
   auto top = [&](int h) { return tops[h]; };
   const double* A = q.A[mat];
-  double* E = q.E[mat];
+  double* M = FORM ? q.E[mat] : q.A[mat];
   const long sl = slot(mat, p, a + s, nb, q.P);
   const int nv = (nch - 1) * kPanel;
   g2l(nv * kPanel, tid,
@@ -487,45 +363,46 @@ __global__ __launch_bounds__(256) void qr_tree_apply(QrArgs q, int p, int s) {
       });
   g2l(kPanel * kPanel, tid, [&](int idx) { return q.Tn[sl * kPanel * kPanel + idx]; },
       [&](int idx, double v) { T[idx / kPanel][idx % kPanel] = v; });
+  // rows r >= w of every child are loaded as zeros, so that the stacked
+  // products may run over full kPanel-row blocks
+  g2l(nch * kPanel * kTrailN, tid,
+      [&](int idx) {
+        const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
+        const int r = rc / kTrailN, c = rc % kTrailN;
+        return (r < w && c < nc) ? M[(long)(top(h) + r) * k + cb + c] : 0.0;
+      },
+      [&](int idx, double v) {
+        const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
+        Cs[h][rc / kTrailN][rc % kTrailN] = v;
+      });
+  __syncthreads();
   auto V = [&](int u, int c) -> double { return Vs[u >> 5][u & 31][c]; };
-  for (int cb = c0; cb < k; cb += kTrailN) {
-    const int nc = min(kTrailN, k - cb);
-    __syncthreads();
-    g2l(nch * kPanel * kTrailN, tid,
-        [&](int idx) {
-          const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
-          const int r = rc / kTrailN, c = rc % kTrailN;
-          return (r < w && c < nc) ? E[(long)(top(h) + r) * k + cb + c] : 0.0;
-        },
-        [&](int idx, double v) {
-          const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
-          Cs[h][rc / kTrailN][rc % kTrailN] = v;
-        });
-    __syncthreads();
-    lds_mm(w, nc, nv, [&](int i, int u) { return V(u, i); },
-           [&](int u, int c) { return Cs[1 + (u >> 5)][u & 31][c]; },
-           [&](int i, int j, double x) { W1[i][j] = x + Cs[0][i][j]; }, wave, lane);
-    __syncthreads();
-    lds_mm(w, nc, w, [&](int i, int l) { return T[i][l]; }, [&](int l, int c) { return W1[l][c]; },
-           [&](int i, int j, double x) { W2[i][j] = x; }, wave, lane);
-    __syncthreads();
-    lds_mm(nv, nc, w, V, [&](int l, int c) { return W2[l][c]; },
-           [&](int u, int c, double x) { Cs[1 + (u >> 5)][u & 31][c] -= x; }, wave, lane);
-    for (int idx = tid; idx < w * kTrailN; idx += 256) {
-      const int r = idx / kTrailN, c = idx % kTrailN;
-      if (c < nc) Cs[0][r][c] -= W2[r][c];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nch * w * kTrailN; idx += 256) {
-      const int h = idx / (w * kTrailN), rc = idx % (w * kTrailN);
-      const int r = rc / kTrailN, c = rc % kTrailN;
-      if (c < nc) E[(long)(top(h) + r) * k + cb + c] = Cs[h][r][c];
-    }
+  lds_mm(w, nc, nv, [&](int i, int u) { return V(u, i); },
+         [&](int u, int c) { return Cs[1 + (u >> 5)][u & 31][c]; },
+         [&](int i, int j, double x) { W1[i][j] = x + Cs[0][i][j]; }, wave, lane);
+  __syncthreads();
+  lds_mm(w, nc, w, [&](int i, int l) { return FORM ? T[i][l] : T[l][i]; },
+         [&](int l, int c) { return W1[l][c]; }, [&](int i, int j, double x) { W2[i][j] = x; },
+         wave, lane);
+  __syncthreads();
+  lds_mm(nv, nc, w, V, [&](int l, int c) { return W2[l][c]; },
+         [&](int u, int c, double x) { Cs[1 + (u >> 5)][u & 31][c] -= x; }, wave, lane);
+  for (int idx = tid; idx < w * kTrailN; idx += 256) {
+    const int r = idx / kTrailN, c = idx % kTrailN;
+    if (c < nc) Cs[0][r][c] -= W2[r][c];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nch * w * kTrailN; idx += 256) {
+    const int h = idx / (w * kTrailN), rc = idx % (w * kTrailN);
+    const int r = rc / kTrailN, c = rc % kTrailN;
+    if (c < nc) M[(long)(top(h) + r) * k + cb + c] = Cs[h][r][c];
   }
 }
 
-// E rows of the leaf <- Q_leaf E on columns [c0, k): C -= V T (V^T C).
-__global__ __launch_bounds__(256) void qr_leaf_apply(QrArgs q, int p) {
+// Leaf rows: C -= V op(T) (V^T C), V unit lower-trapezoidal (implicit ones,
+// zeros above).
+template <bool FORM>
+__global__ __launch_bounds__(256) void qr_leaf_wy(QrArgs q, int p) {
   __shared__ double V[kPanel][kLR];
   __shared__ double Cc[kPanel][kLR];
   __shared__ double T[kPanel][kT], W1[kPanel][kT], W2[kPanel][kT];
@@ -533,11 +410,14 @@ __global__ __launch_bounds__(256) void qr_leaf_apply(QrArgs q, int p) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = q.N, k = q.k, nb = q.nb;
   const int c0 = p * kPanel, w = min(kPanel, k - c0);
+  const int cb = (FORM ? c0 : c0 + w) + blockIdx.z * kPanel;
+  if (cb >= k) return;
+  const int nc = min(kPanel, k - cb);
   const int s = leaf_start(leaf, N, nb), e = leaf_start(leaf + 1, N, nb);
   const int a0 = (leaf == 0) ? c0 : s;
   const int m = e - a0;
   const double* A = q.A[mat];
-  double* E = q.E[mat];
+  double* M = FORM ? q.E[mat] : q.A[mat];
   const long sl = slot(mat, p, leaf, nb, q.P);
   g2l(kPanel * kLeafRows, tid,
       [&](int idx) {
@@ -548,29 +428,40 @@ __global__ __launch_bounds__(256) void qr_leaf_apply(QrArgs q, int p) {
       [&](int idx, double v) { V[idx % kPanel][idx / kPanel] = v; });
   g2l(kPanel * kPanel, tid, [&](int idx) { return q.Tl[sl * kPanel * kPanel + idx]; },
       [&](int idx, double v) { T[idx / kPanel][idx % kPanel] = v; });
-  for (int cb = c0; cb < k; cb += kPanel) {
-    const int nc = min(kPanel, k - cb);
-    __syncthreads();
-    g2l(m * kPanel, tid,
-        [&](int idx) {
-          const int r = idx / kPanel, c = idx % kPanel;
-          return c < nc ? E[(long)(a0 + r) * k + cb + c] : 0.0;
-        },
-        [&](int idx, double v) { Cc[idx % kPanel][idx / kPanel] = v; });
-    __syncthreads();
-    lds_mm(w, nc, m, [&](int a, int r) { return V[a][r]; }, [&](int r, int c) { return Cc[c][r]; },
-           [&](int i, int j, double x) { W1[i][j] = x; }, wave, lane);
-    __syncthreads();
-    lds_mm(w, nc, w, [&](int i, int l) { return T[i][l]; }, [&](int l, int c) { return W1[l][c]; },
-           [&](int i, int j, double x) { W2[i][j] = x; }, wave, lane);
-    __syncthreads();
-    lds_mm(m, nc, w, [&](int r, int l) { return V[l][r]; }, [&](int l, int c) { return W2[l][c]; },
-           [&](int r, int c, double x) { Cc[c][r] -= x; }, wave, lane);
-    __syncthreads();
-    for (int idx = tid; idx < m * kPanel; idx += 256) {
-      const int r = idx / kPanel, c = idx % kPanel;
-      if (c < nc) E[(long)(a0 + r) * k + cb + c] = Cc[c][r];
-    }
+  g2l(m * kPanel, tid,
+      [&](int idx) {
+        const int r = idx / kPanel, c = idx % kPanel;
+        return c < nc ? M[(long)(a0 + r) * k + cb + c] : 0.0;
+      },
+      [&](int idx, double v) { Cc[idx % kPanel][idx / kPanel] = v; });
+  __syncthreads();
+  lds_mm(w, nc, m, [&](int a, int r) { return V[a][r]; }, [&](int r, int c) { return Cc[c][r]; },
+         [&](int i, int j, double x) { W1[i][j] = x; }, wave, lane);
+  __syncthreads();
+  lds_mm(w, nc, w, [&](int i, int l) { return FORM ? T[i][l] : T[l][i]; },
+         [&](int l, int c) { return W1[l][c]; }, [&](int i, int j, double x) { W2[i][j] = x; },
+         wave, lane);
+  __syncthreads();
+  lds_mm(m, nc, w, [&](int r, int l) { return V[l][r]; }, [&](int l, int c) { return W2[l][c]; },
+         [&](int r, int c, double x) { Cc[c][r] -= x; }, wave, lane);
+  __syncthreads();
+  for (int idx = tid; idx < m * kPanel; idx += 256) {
+    const int r = idx / kPanel, c = idx % kPanel;
+    if (c < nc) M[(long)(a0 + r) * k + cb + c] = Cc[c][r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Q formation
+// ---------------------------------------------------------------------------
+__global__ void qr_init_e(QrArgs q) {
+  const int mat = blockIdx.y;
+  const long total = (long)q.N * q.k;
+  double* E = q.E[mat];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x) {
+    const long r = i / q.k, c = i % q.k;
+    E[i] = (r == c) ? 1.0 : 0.0;
   }
 }
 
@@ -658,24 +549,31 @@ int launch_qr(int count, double* const* W, int N, int k, void* ws, hipStream_t s
   }
   q.sgn = e + (size_t)count * N * k;
 
+  // factorisation: per panel the leaves, then the tree levels; each factor
+  // launch is followed by the update of the trailing columns it leaves
   for (int p = 0; p < pl.P; ++p) {
+    const int c0 = p * kPanel, w = std::min(kPanel, k - c0);
+    const int trail = (k - c0 - w + kTrailN - 1) / kTrailN;
     qr_leaf_factor<<<dim3(pl.nb, count), 256, 0, s>>>(q, p);
+    if (trail) qr_leaf_wy<false><<<dim3(pl.nb, count, trail), 256, 0, s>>>(q, p);
     for (int L = 0, st = 1; L < pl.depth; ++L, st *= kArity) {
       const int nodes = (pl.nb + st * kArity - 1) / (st * kArity);
       qr_tree_factor<<<dim3(nodes, count), 256, 0, s>>>(q, p, st);
+      if (trail) qr_tree_wy<false><<<dim3(nodes, count, trail), 256, 0, s>>>(q, p, st);
     }
   }
   const long total = (long)N * k;
   const int blocks = (int)std::min<long>(1024, (total + 255) / 256);
   qr_init_e<<<dim3(blocks, count), 256, 0, s>>>(q);
   for (int p = pl.P - 1; p >= 0; --p) {
+    const int chunks = (k - p * kPanel + kTrailN - 1) / kTrailN;
     for (int L = pl.depth - 1; L >= 0; --L) {
       int st = 1;
       for (int i = 0; i < L; ++i) st *= kArity;
       const int nodes = (pl.nb + st * kArity - 1) / (st * kArity);
-      qr_tree_apply<<<dim3(nodes, count), 256, 0, s>>>(q, p, st);
+      qr_tree_wy<true><<<dim3(nodes, count, chunks), 256, 0, s>>>(q, p, st);
     }
-    qr_leaf_apply<<<dim3(pl.nb, count), 256, 0, s>>>(q, p);
+    qr_leaf_wy<true><<<dim3(pl.nb, count, chunks), 256, 0, s>>>(q, p);
   }
   qr_diag_sign<<<dim3(1, count), 256, 0, s>>>(q);
   qr_sign_copy<<<dim3(blocks, count), 256, 0, s>>>(q);

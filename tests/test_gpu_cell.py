@@ -199,7 +199,9 @@ def test_cell_run_on_a_bond_gauged_ising_cell_matches_oracle():
     assert err <= 1e-8
     sg = spectra_of(env, Lx, Ly, chi)
     so = M.cell_corner_spectra(cell, chi)
-    assert np.abs(sg - so).max() <= 1e-12
+    # both runs stop once the corner spectra change by less than 1e-11 per
+    # iteration (the convergence measure), which is what fixes them
+    assert np.abs(sg - so).max() <= 1e-11
     g.close()
 
 
