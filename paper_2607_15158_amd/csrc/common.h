@@ -187,6 +187,11 @@ int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStr
 int launch_gemm_si_f32(const GemmBatch& g, hipStream_t s);
 // The same product in split bfloat16 (A float32, three bf16 products).
 int launch_gemm_si_bx3(const GemmBatch& g, hipStream_t s);
+// The float32 product split over ncu workgroups like launch_gemm_si_balanced
+// (partial tiles in the same float64 scratch); launch_gemm_si_f32 when the
+// split does not apply.
+bool gemm_si_f32_balanced_applies(const GemmBatch& g, const void* scratch, int ncu);
+int launch_gemm_si_f32_balanced(const GemmBatch& g, double* scratch, int ncu, hipStream_t s);
 
 // Grouped float64 GEMMs: one persistent launch over the products of several
 // descriptors of different shapes (see gemm.hip).  Each descriptor's work

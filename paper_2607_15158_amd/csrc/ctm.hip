@@ -371,7 +371,8 @@ size_t carve(ctm_ctx* c, char* base) {
     c->xi_out = cv.take<double>(8);
     c->xi_qr = qr_ok ? cv.take_bytes(qr_workspace_bytes(1, (int)nE, c->xi_m)) : nullptr;
   }
-  c->sk_part = c->cp == DT::F64 && gemm_si_balanced_useful(8, (int)N, (int)k, (int)N, kSplitMaxCus)
+  c->sk_part = (c->cp == DT::F64 || (c->cp == DT::F32 && !c->split)) &&
+                       gemm_si_balanced_useful(8, (int)N, (int)k, (int)N, kSplitMaxCus)
                    ? (double*)cv.take_bytes(gemm_si_scratch_bytes())
                    : nullptr;
   c->obs_y = cv.take<double>((size_t)dd * xm * Dl * xm);
@@ -587,7 +588,8 @@ int apply_step(ctm_ctx* c, int count, const int* ci, const int* trans, double* c
     const int chk = check_gemm(c, g, DT::F32, DT::F64, DT::F64);
     if (chk) return chk;
     ProfScope ps(c, PC_SI_APPLY, gemm_flops(g), bytes);
-    return c->split ? launch_gemm_si_bx3(g, c->st) : launch_gemm_si_f32(g, c->st);
+    if (c->split) return launch_gemm_si_bx3(g, c->st);
+    return launch_gemm_si_f32_balanced(g, c->sk_part, c->sk_cus, c->st);
   }
   if (c->cp != DT::F64) return run_gemm(c, PC_SI_APPLY, g, c->cp, DT::F64, DT::F64, bytes);
   const int chk = check_gemm(c, g, DT::F64, DT::F64, DT::F64);

@@ -764,6 +764,204 @@ __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_s
   }
 }
 
+// Float32 form of the split SI application (contraction precision f32): the
+// same ranges of (tile, K-slice) space as gemm_streamk_f64 over 192 x 160
+// tiles, with A (the enlarged corner) in float32, B (the float64 block)
+// rounded to float32 on its way into LDS, 32-wide slices (the bytes of the
+// float64 kernel's 16) and v_mfma_f32_16x16x4f32 with float32 accumulation.
+// Whole tiles are widened to float64 on store; cut tiles leave their partial
+// sums in float64 in the same scratch slots, summed by gemm_streamk_fixup.
+namespace skf32 {
+constexpr int BM = 192, BN = 160, BK = 32, WGM = 4, WGN = 2, NT = 64 * WGM * WGN;
+constexpr int WTM = BM / WGM, WTN = BN / WGN;   // 48 x 80 per wavefront
+constexpr int MI = WTM / 16, NI = WTN / 16;     // 3 x 5 accumulator blocks
+constexpr int LT = BM + 16;                     // transposed A in LDS: [k][m]
+constexpr int LN = BK + 1;                      // plain A in LDS: [m][k]
+constexpr int ASZ = (BK * LT > BM * LN) ? BK * LT : BM * LN;
+constexpr int LB = BN + 16;                     // B in LDS: [k][n]
+constexpr int NA = BM * BK / 4;                 // 16-byte loads of A per slice (4 floats)
+constexpr int NB = BK * BN / 2;                 // 16-byte loads of B per slice (2 doubles)
+constexpr int VA = (NA + NT - 1) / NT, VB = (NB + NT - 1) / NT;
+}  // namespace skf32
+
+template <bool TRANS>
+__device__ __forceinline__ void sk_segment_f32(const GemmBatch& g, int prob, int m0, int s0, int s1,
+                                               float (*As)[skf32::ASZ],
+                                               float (*Bs)[skf32::BK][skf32::LB],
+                                               v4f (&acc)[skf32::MI][skf32::NI]) {
+  using namespace skf32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int M = g.M, N = g.N, K = g.K;
+  const float* A = (const float*)g.A[prob];
+  const double* B = (const double*)g.B[prob];
+  const long lda = g.lda, ldb = g.ldb;
+  v4f ra[VA];
+  v2d rb[VB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < VA; ++e) {
+      const int i = tid + e * NT;
+      v4f v = {0.f, 0.f, 0.f, 0.f};
+      if (i < NA) {
+        if (TRANS) {
+          const int gk = k0 + i / (BM / 4), gm = m0 + 4 * (i % (BM / 4));
+          if (gk < K) {
+            const float* q = A + (long)gk * lda + gm;
+            if (gm + 3 < M) {
+              v = *(const v4f*)q;
+            } else {
+              if (gm < M) v.x = q[0];
+              if (gm + 1 < M) v.y = q[1];
+              if (gm + 2 < M) v.z = q[2];
+            }
+          }
+        } else {
+          const int gm = m0 + i / (BK / 4), gk = k0 + 4 * (i % (BK / 4));
+          if (gm < M) {
+            const float* q = A + (long)gm * lda + gk;
+            if (gk + 3 < K) {
+              v = *(const v4f*)q;
+            } else {
+              if (gk < K) v.x = q[0];
+              if (gk + 1 < K) v.y = q[1];
+              if (gk + 2 < K) v.z = q[2];
+            }
+          }
+        }
+      }
+      ra[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < VB; ++e) {
+      const int i = tid + e * NT;
+      const int gk = k0 + i / (BN / 2), gn = 2 * (i % (BN / 2));
+      v2d v = {0.0, 0.0};
+      if (i < NB && gk < K) {
+        const double* q = B + (long)gk * ldb + gn;
+        if (gn + 1 < N) v = *(const v2d*)q;
+        else if (gn < N) v.x = q[0];
+      }
+      rb[e] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < VA; ++e) {
+      const int i = tid + e * NT;
+      if (i < NA) {
+        if (TRANS) {
+          const int kk = i / (BM / 4), m = 4 * (i % (BM / 4));
+          *(v4f*)&As[buf][kk * LT + m] = ra[e];
+        } else {
+          const int m = i / (BK / 4), kk = 4 * (i % (BK / 4));
+          float* q = &As[buf][m * LN + kk];
+          q[0] = ra[e].x;
+          q[1] = ra[e].y;
+          q[2] = ra[e].z;
+          q[3] = ra[e].w;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < VB; ++e) {
+      const int i = tid + e * NT;
+      if (i < NB) {
+        float* q = &Bs[buf][i / (BN / 2)][2 * (i % (BN / 2))];
+        q[0] = (float)rb[e].x;
+        q[1] = (float)rb[e].y;
+      }
+    }
+  };
+  load(s0 * BK);
+  store(0);
+  __syncthreads();
+  for (int kt = s0; kt < s1; ++kt) {
+    const int buf = (kt - s0) & 1;
+    if (kt + 1 < s1) load((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      float a[MI], b[NI];
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const int m = wm * WTM + i * 16 + (lane & 15);
+        a[i] = TRANS ? As[buf][kr * LT + m] : As[buf][m * LN + kr];
+      }
+#pragma unroll
+      for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < s1) store(buf ^ 1);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(skf32::NT, 1) void gemm_streamk_f32(GemmBatch g, StreamK sk) {
+  using namespace skf32;
+  __shared__ float As[2][ASZ];
+  __shared__ float Bs[2][BK][LB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const long begin = sk_begin(w, sk), end = sk_begin(w + 1, sk);
+  const int M = g.M, N = g.N;
+  // segments last to first, as in the float64 kernel
+  long pend = end;
+  while (pend > begin) {
+    const long tile = (pend - 1) / sk.nslices;
+    const long pos = tile * sk.nslices > begin ? tile * sk.nslices : begin;
+    const int s0 = (int)(pos - tile * sk.nslices), s1 = (int)(pend - tile * sk.nslices);
+    const int prob = (int)(tile / sk.tiles_m), m0 = (int)(tile % sk.tiles_m) * BM;
+    v4f acc[MI][NI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    if (g.transA[prob])
+      sk_segment_f32<true>(g, prob, m0, s0, s1, As, Bs, acc);
+    else
+      sk_segment_f32<false>(g, prob, m0, s0, s1, As, Bs, acc);
+    // float32 MFMA result element r of lane l: row 4 (l / 16) + r, column l % 16
+    if (s0 == 0 && s1 == sk.nslices) {
+      double* C = (double*)g.C[prob];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
+          if (m >= M) continue;
+          double* row = C + (long)m * g.cs_m0;
+#pragma unroll
+          for (int j = 0; j < NI; ++j) {
+            const int n = wn * WTN + j * 16 + (lane & 15);
+            if (n >= N) continue;
+            double v = g.alpha * (double)acc[i][j][r];
+            if (g.accumulate) v += row[n];
+            row[n] = v;
+          }
+        }
+      }
+    } else {
+      double* P = sk.part + (long)(2 * w + (pos == begin ? 0 : 1)) * (BM * BN);
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ml = wm * WTM + i * 16 + 4 * (lane >> 4) + r;
+#pragma unroll
+          for (int j = 0; j < NI; ++j)
+            P[ml * BN + wn * WTN + j * 16 + (lane & 15)] = (double)acc[i][j][r];
+        }
+    }
+    pend = pos;
+  }
+}
+
 // Sums the partial tiles of every tile cut by range boundaries, in
 // workgroup order, and writes them (alpha and accumulate as in the main
 // kernel; the split runs only with a plain row-major C).  kFixRows-row strips of a tile per block of 256
@@ -1319,6 +1517,37 @@ int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStr
   sk.nwg = ncu;
   sk.part = scratch;
   gemm_streamk_f64<192, 160, 4, 2><<<ncu, 512, 0, s>>>(g, sk);
+  CTM_HIP_TRY(hipGetLastError());
+  gemm_streamk_fixup<192, 160><<<(int)((long)g.count * tm * (192 / kFixRows)), 256, 0, s>>>(g, sk);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+bool gemm_si_f32_balanced_applies(const GemmBatch& g, const void* scratch, int ncu) {
+  if (!scratch || ((uintptr_t)scratch & 15) || g.M <= 0 || g.N <= 0 || g.count <= 0 ||
+      g.nbatch != 1 || g.N > skf32::BN)
+    return false;
+  if ((g.lda & 3) || (g.ldb & 1)) return false;
+  for (int i = 0; i < g.count; ++i)
+    if (((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & 15)) return false;
+  const bool rowmajor_c = g.cdiv_m >= g.M && g.cdiv_n >= g.N && g.cs_n0 == 1;
+  // at least 8 slices per range, so that no range is empty
+  const long tiles = (long)g.count * ceil_div(g.M, skf32::BM);
+  return rowmajor_c && ncu >= 1 && ncu <= kSplitMaxCus && tiles >= ncu / 2 &&
+         tiles * ceil_div(g.K, skf32::BK) >= 8L * ncu && tiles * ceil_div(g.K, skf32::BK) <= (1L << 40);
+}
+
+int launch_gemm_si_f32_balanced(const GemmBatch& g, double* scratch, int ncu, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch <= 0) return 0;
+  if (!gemm_si_f32_balanced_applies(g, scratch, ncu)) return launch_gemm_si_f32(g, s);
+  const int tm = ceil_div(g.M, skf32::BM);
+  StreamK sk;
+  sk.nslices = ceil_div(g.K, skf32::BK);
+  sk.tiles_m = tm;
+  sk.total = (long)g.count * tm * sk.nslices;
+  sk.nwg = ncu;
+  sk.part = scratch;
+  gemm_streamk_f32<<<ncu, skf32::NT, 0, s>>>(g, sk);
   CTM_HIP_TRY(hipGetLastError());
   gemm_streamk_fixup<192, 160><<<(int)((long)g.count * tm * (192 / kFixRows)), 256, 0, s>>>(g, sk);
   CTM_HIP_TRY(hipGetLastError());

@@ -174,8 +174,21 @@ struct PanelShare {
   double dot[2][4][kPanel]; // v_j^T x_s per wavefront
 };
 
+// Squared norm below the pivot of column j (this wavefront's share) and the
+// pivot value, published for the step that factors column j.
+template <int J, typename On>
+__device__ __forceinline__ void publish_norm(const double (&x)[kPanel], int lane, int wave,
+                                             const On& on, PanelShare& sh) {
+  constexpr int b = J & 1;
+  const double ssw = wave_sum64(on(J) ? x[J] * x[J] : 0.0);
+  if (lane == 0) sh.ss[b][wave] = ssw;
+  if (wave == 0 && lane == J) sh.alpha[b] = x[J];
+}
+
 // Step J of the panel factorisation (J is a template parameter so that every
 // register of the panel is addressed statically); columns J >= w are absent.
+// Column J + 1 is updated first and its norm published before the other
+// columns are updated, so that its reduction overlaps their updates.
 template <int J, typename On>
 __device__ __forceinline__ void panel_step(double (&x)[kPanel], int w, int lane, int wave,
                                            const On& on, double* tau_out, double (*G)[kT],
@@ -184,9 +197,6 @@ __device__ __forceinline__ void panel_step(double (&x)[kPanel], int w, int lane,
     constexpr int b = J & 1;
     const bool bj = on(J);
     const bool piv = wave == 0 && lane == J;
-    const double ssw = wave_sum64(bj ? x[J] * x[J] : 0.0);
-    if (lane == 0) sh.ss[b][wave] = ssw;
-    if (piv) sh.alpha[b] = x[J];
     __syncthreads();
     const double ss = (sh.ss[b][0] + sh.ss[b][1]) + (sh.ss[b][2] + sh.ss[b][3]);
     const double alpha = sh.alpha[b];
@@ -208,8 +218,12 @@ __device__ __forceinline__ void panel_step(double (&x)[kPanel], int w, int lane,
         (sh.dot[b][0][col] + sh.dot[b][1][col]) + (sh.dot[b][2][col] + sh.dot[b][3][col]);
     if (wave == 0 && !(lane & 1) && col < J) G[col][J] = tot;
     const double f = tau * tot;
+    if constexpr (J + 1 < kPanel) {
+      x[J + 1] -= readlane_f64(f, 2 * (J + 1)) * vj;
+      publish_norm<J + 1>(x, lane, wave, on, sh);
+    }
 #pragma unroll
-    for (int s = J + 1; s < kPanel; ++s) x[s] -= readlane_f64(f, 2 * s) * vj;
+    for (int s = J + 2; s < kPanel; ++s) x[s] -= readlane_f64(f, 2 * s) * vj;
   }
   if constexpr (J + 1 < kPanel) panel_step<J + 1>(x, w, lane, wave, on, tau_out, G, sh);
 }
@@ -219,6 +233,7 @@ template <typename On>
 __device__ __forceinline__ void block_panel_qr(double (&x)[kPanel], int w, int lane, int wave,
                                                On on, double* tau_s, double (*G)[kT],
                                                double (*T)[kT], PanelShare& sh) {
+  publish_norm<0>(x, lane, wave, on, sh);
   panel_step<0>(x, w, lane, wave, on, tau_s, G, sh);
   if (wave == 0) build_T(T, G, tau_s, w, lane);
 }
