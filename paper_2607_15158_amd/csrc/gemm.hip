@@ -73,10 +73,14 @@ constexpr int kK4BK = 16, kK4Pad = 2;
 
 // One BM x BN output tile (tm, tn) of problem `prob`, inner batch `batch`.
 // The K loop runs in ascending 16-wide slices whatever the tile shape, so an
-// output element gets the same bits from every tile shape and grid.
+// output element gets the same bits from every tile shape and grid.  The
+// slices are double-buffered in LDS: the global loads of slice kt + 1 are in
+// flight while slice kt is multiplied, then stored into the other buffer,
+// one barrier per slice.
 template <typename TA, typename TB, typename TC, typename CT, int BM, int BN, int WGM, int WGN>
 __device__ __forceinline__ void k4_tile(const GemmBatch& g, int prob, int batch, int tm, int tn,
-                                        CT (*As)[BM + kK4Pad], CT (*Bs)[BN + kK4Pad]) {
+                                        CT (*As)[kK4BK][BM + kK4Pad],
+                                        CT (*Bs)[kK4BK][BN + kK4Pad]) {
   constexpr int BK = kK4BK;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int MI = WTM / 16, NI = WTN / 16;
@@ -118,18 +122,18 @@ __device__ __forceinline__ void k4_tile(const GemmBatch& g, int prob, int batch,
       rb[e] = v;
     }
   };
-  auto store_tiles = [&]() {
+  auto store_tiles = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int i = tid + e * 256;
       int m, kk;
       if (trans) { m = i % BM; kk = i / BM; } else { m = i / BK; kk = i % BK; }
-      As[kk][m] = ra[e];
+      As[buf][kk][m] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int i = tid + e * 256;
-      Bs[i / BN][i % BN] = rb[e];
+      Bs[buf][i / BN][i % BN] = rb[e];
     }
   };
 
@@ -141,23 +145,25 @@ __device__ __forceinline__ void k4_tile(const GemmBatch& g, int prob, int batch,
 
   const int nk = (K + BK - 1) / BK;
   load_tiles(0);
+  store_tiles(0);
+  __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    store_tiles();
-    __syncthreads();
+    const int buf = kt & 1;
     if (kt + 1 < nk) load_tiles((kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       CT a[MI], b[NI];
       const int kr = ks + (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < MI; ++i) a[i] = As[kr][wm * WTM + i * 16 + (lane & 15)];
+      for (int i = 0; i < MI; ++i) a[i] = As[buf][kr][wm * WTM + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < NI; ++j) b[j] = Bs[kr][wn * WTN + j * 16 + (lane & 15)];
+      for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kr][wn * WTN + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NI; ++j) acc[i][j] = Mfma4<CT>::op(a[i], b[j], acc[i][j]);
     }
+    if (kt + 1 < nk) store_tiles(buf ^ 1);
     __syncthreads();
   }
 
@@ -192,8 +198,8 @@ __device__ __forceinline__ void k4_tile(const GemmBatch& g, int prob, int batch,
 
 template <typename TA, typename TB, typename TC, typename CT, int BM, int BN, int WGM, int WGN>
 __global__ __launch_bounds__(256) void gemm_k4(GemmBatch g, int tiles_m, int tiles_n) {
-  __shared__ CT As[kK4BK][BM + kK4Pad];
-  __shared__ CT Bs[kK4BK][BN + kK4Pad];
+  __shared__ CT As[2][kK4BK][BM + kK4Pad];
+  __shared__ CT Bs[2][kK4BK][BN + kK4Pad];
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int prob = blockIdx.y / g.nbatch, batch = blockIdx.y % g.nbatch;
   k4_tile<TA, TB, TC, CT, BM, BN, WGM, WGN>(g, prob, batch, tile / tiles_n, tile % tiles_n, As, Bs);
@@ -1053,8 +1059,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_s
 template <int BM, int BN, int WGM, int WGN>
 __global__ __launch_bounds__(256) void gemm_k4_grouped(const GroupItem* items, int nitems,
                                                        long total) {
-  __shared__ double As[kK4BK][BM + kK4Pad];
-  __shared__ double Bs[kK4BK][BN + kK4Pad];
+  __shared__ double As[2][kK4BK][BM + kK4Pad];
+  __shared__ double Bs[2][kK4BK][BN + kK4Pad];
   for (long w = blockIdx.x; w < total; w += gridDim.x) {
     const GroupItem& it = items[group_of(items, nitems, w)];
     const int lin = (int)(w - it.first);
