@@ -339,46 +339,53 @@ __global__ __launch_bounds__(1024) void svd_finalize(SvdArgs a) {
       for (int r = lane; r < n; r += 64) Uc[(size_t)c * n + r] /= sn;
   }
   __syncthreads();
-  // orthonormal completion of numerically zero columns (sequential, wavefront
-  // 0); the cut is the one below which the rotations left a column alone
+  // orthonormal completion of numerically zero columns; the cut is the one
+  // below which the rotations left a column alone.  Zero columns are taken
+  // in order; for each, unit vectors e_cand (cand increasing) are projected
+  // on the complement of the other columns (the non-zero ones and the zero
+  // ones already completed) by classical Gram-Schmidt applied twice, with
+  // the dot products of a pass spread over the wavefronts and the update
+  // over the rows, until one keeps enough of its length.
   const double zero_cut = 1e-15 * sqrt(a.fro2[mat]);
-  if (a.U[mat] != nullptr && wave == 0) {
+  if (a.U[mat] != nullptr) {
+    __shared__ double xs[kSvdMaxN], ds[kSvdMaxN];
+    __shared__ double xnorm;
     int cand = 0;
     for (int c = 0; c < n; ++c) {
       if (snorm[c] > zero_cut) continue;
       for (; cand < n; ++cand) {
-        double x[kRPL];
-#pragma unroll
-        for (int t = 0; t < kRPL; ++t) x[t] = (lane + 64 * t == cand) ? 1.0 : 0.0;
+        for (int r = tid; r < n; r += 1024) xs[r] = r == cand ? 1.0 : 0.0;
+        __syncthreads();
         for (int pass = 0; pass < 2; ++pass) {
-          for (int o = 0; o < n; ++o) {
-            if (o == c || (snorm[o] <= zero_cut && o > c)) continue;
+          for (int o = wave; o < n; o += nwaves) {
+            const bool ref = o != c && !(snorm[o] <= zero_cut && o > c);
             double d = 0.0;
-#pragma unroll
-            for (int t = 0; t < kRPL; ++t) {
-              const int r = lane + 64 * t;
-              if (r < n) d += Uc[(size_t)o * n + r] * x[t];
-            }
+            if (ref)
+              for (int r = lane; r < n; r += 64) d += Uc[(size_t)o * n + r] * xs[r];
             d = wsum(d);
-#pragma unroll
-            for (int t = 0; t < kRPL; ++t) {
-              const int r = lane + 64 * t;
-              if (r < n) x[t] -= d * Uc[(size_t)o * n + r];
-            }
+            if (lane == 0) ds[o] = ref ? d : 0.0;
           }
+          __syncthreads();
+          for (int r = tid; r < n; r += 1024) {
+            double acc = 0.0;
+            for (int o = 0; o < n; ++o) acc += ds[o] * Uc[(size_t)o * n + r];
+            xs[r] -= acc;
+          }
+          __syncthreads();
         }
-        double nn = 0.0;
-#pragma unroll
-        for (int t = 0; t < kRPL; ++t) nn += x[t] * x[t];
-        nn = sqrt(wsum(nn));
+        if (wave == 0) {
+          double nn = 0.0;
+          for (int r = lane; r < n; r += 64) nn += xs[r] * xs[r];
+          nn = sqrt(wsum(nn));
+          if (lane == 0) xnorm = nn;
+        }
+        __syncthreads();
+        const double nn = xnorm;
         // the complement has dimension >= 1, so some unit vector keeps at
         // least 1/sqrt(n) of its length after the projection
         if (nn > 0.5 / sqrt((double)n)) {
-#pragma unroll
-          for (int t = 0; t < kRPL; ++t) {
-            const int r = lane + 64 * t;
-            if (r < n) Uc[(size_t)c * n + r] = x[t] / nn;
-          }
+          for (int r = tid; r < n; r += 1024) Uc[(size_t)c * n + r] = xs[r] / nn;
+          __syncthreads();
           ++cand;
           break;
         }
