@@ -461,21 +461,24 @@ ctm_status ctm_gemm_f64(int count, const double* const* A, const double* const* 
                         long ldb, long ldc, double alpha, int accumulate, void* stream);
 
 /* The product of ctm_gemm_f64 for the subspace-iteration applications
- * (QR-based projector section: M X and M^T Y^T with thin blocks, N <= 160),
- * with the (192-row tile, 16-wide K slice) space of all `count` problems
- * split into `ncu` equal contiguous ranges, one per workgroup of 8 wavefronts
- * (one workgroup per CU: 256 on MI355X; 1 <= ncu <= 256), so that no CU idles
- * while another finishes a tile.  Tiles cut by range boundaries are summed
- * from partial tiles in `scratch` (device memory of
- * ctm_gemm_f64_split_scratch_bytes() bytes, owned by the caller, contents not
- * preserved; calls sharing one scratch must be ordered on one stream) by a
- * second kernel in a fixed order: the result is the same on every call.
- * trans_a is a host array of `count` flags (0 or 1) as in ctm_gemm_f64; C is
- * row-major with leading dimension ldc.  When the split does not apply
- * (scratch NULL, N > 160, fewer than ncu/2 tiles, fewer than 16 K slices,
- * operands or scratch not 16-byte aligned, odd lda or ldb) the plain tile
- * kernel runs; if used_split is non-NULL it receives 1 when the split ran,
- * else 0. */
+ * (QR-based projector section: M X and M^T Y^T with thin blocks, N <= 160)
+ * and other thin products with long K, with the (192-row tile, 16-wide K
+ * slice) space of all `count` problems split into R equal contiguous ranges,
+ * R = min(ncu, pairs / 8) for `pairs` (tile, slice) pairs (every range holds
+ * at least 8 slices), one per workgroup of 8 wavefronts (one workgroup per
+ * CU: 256 on MI355X; 1 <= ncu <= 256), so that no CU idles while another
+ * finishes a tile.  Tiles cut by range boundaries are summed from partial
+ * tiles in `scratch` (device memory of ctm_gemm_f64_split_scratch_bytes()
+ * bytes, owned by the caller, contents not preserved; calls sharing one
+ * scratch must be ordered on one stream) by a second kernel in a fixed
+ * order: the result is the same on every call.  trans_a is a host array of
+ * `count` flags (0 or 1) as in ctm_gemm_f64; C is row-major with leading
+ * dimension ldc.  Problems with N <= 128 take 192 x 128 tiles.  The split
+ * applies when scratch is non-NULL and 16-byte aligned, N <= 160, K spans at
+ * least 16 slices (K > 240), lda is even, the A bases are 16-byte aligned and
+ * the B bases 16-byte aligned (even ldb) or 8-byte aligned (odd ldb);
+ * otherwise the plain tile kernel runs.  If used_split is non-NULL it
+ * receives 1 when the split ran, else 0. */
 size_t ctm_gemm_f64_split_scratch_bytes(void);
 ctm_status ctm_gemm_f64_split(int count, const double* const* A, const double* const* B,
                               double* const* C, int M, int N, int K, const int* trans_a, long lda,

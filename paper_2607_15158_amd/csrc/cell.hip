@@ -121,16 +121,13 @@ int check_gemm(ctm_cell* c, const GemmBatch& g) {
   return 0;
 }
 
-// Launches a float64 GEMM (the subspace-iteration shape takes the kernels of
-// the single-site SI applications).
-int run(ctm_cell* c, const GemmBatch& g, bool si = false) {
+// Launches a float64 GEMM: the split kernel of the SI applications wherever
+// it applies (thin products with long K: the SI applications, rho, the
+// corner and edge renormalisations), else the tile kernels.
+int run(ctm_cell* c, const GemmBatch& g) {
   if (g.count == 0) return 0;
   CTRY(check_gemm(c, g));
-  if (si) {
-    CTRY(launch_gemm_si_balanced(g, c->sk_part, kSplitMaxCus, c->st));
-  } else {
-    CTRY(launch_gemm(g, DT::F64, DT::F64, DT::F64, c->st));
-  }
+  CTRY(launch_gemm_f64_any(g, c->sk_part, kSplitMaxCus, c->st));
   return 0;
 }
 
@@ -223,14 +220,14 @@ int apply_pair(ctm_cell* c, const std::vector<const Cut*>& g, int qx, int tx, in
     GemmBatch gb = gemm_of(Mx, k, Kx, ldx, k, k);
     for (int i = 0; i < n; ++i) add(gb, c->Q[g[i]->j * 4 + qx], xin[i], xout[i], tx);
     for (int i = 0; i < n; ++i) add(gb, c->Q[g[i]->j * 4 + qy], yin[i], yout[i], ty_);
-    return run(c, gb, true);
+    return run(c, gb);
   }
   GemmBatch gx = gemm_of(Mx, k, Kx, ldx, k, k);
   for (int i = 0; i < n; ++i) add(gx, c->Q[g[i]->j * 4 + qx], xin[i], xout[i], tx);
-  CTRY(run(c, gx, true));
+  CTRY(run(c, gx));
   GemmBatch gy = gemm_of(My, k, Ky, ldy, k, k);
   for (int i = 0; i < n; ++i) add(gy, c->Q[g[i]->j * 4 + qy], yin[i], yout[i], ty_);
-  return run(c, gy, true);
+  return run(c, gy);
 }
 
 int qr_blocks(ctm_cell* c, std::vector<double*> w, int n) {

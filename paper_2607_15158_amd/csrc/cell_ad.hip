@@ -294,7 +294,7 @@ int taped_move(ctm_cell* c, Tape& t, const std::vector<const double*>& a, std::v
             add(g, Q[y0 + i][qy], yc[i], o, tyy);
             ny[i] = o;
           }
-          ATRY(t.gemm(g, true));
+          ATRY(t.gemm(g));
           xc = nx;
           yc = ny;
           return 0;

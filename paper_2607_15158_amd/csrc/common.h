@@ -181,6 +181,9 @@ size_t gemm_si_scratch_bytes();
 bool gemm_si_balanced_useful(int count, int M, int N, int K, int ncu);
 bool gemm_si_balanced_applies(const GemmBatch& g, const void* scratch, int ncu);
 int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStream_t s);
+// A float64 product on the split kernel where it applies (thin B, several
+// K slices per tile), else on the tile kernels.
+int launch_gemm_f64_any(const GemmBatch& g, double* scratch, int ncu, hipStream_t s);
 // float32 contractions of the same shape: A float32, B and C float64 (B
 // rounded to float32, float32 accumulation); other shapes fall back to
 // launch_gemm.

@@ -592,7 +592,7 @@ __device__ __forceinline__ int sk_owner(long p, const StreamK& sk) {
 }
 
 // acc += op(A)[m0 .. m0+BM) x B over the K slices [s0, s1) of problem prob.
-template <int BM, int BN, int WGM, int WGN, bool TRANS, int MI, int NI>
+template <int BM, int BN, int WGM, int WGN, bool TRANS, bool BODD, int MI, int NI>
 __device__ __forceinline__ void sk_segment(const GemmBatch& g, int prob, int m0, int s0, int s1,
                                            double (*As)[SkinnyA<BM, 16>::SIZE],
                                            double (*Bs)[16][BN + 16], v4d (&acc)[MI][NI]) {
@@ -640,8 +640,17 @@ __device__ __forceinline__ void sk_segment(const GemmBatch& g, int prob, int m0,
       v2d v = {0.0, 0.0};
       if (i < NB && gk < K) {
         const double* p = B + (long)gk * ldb + gn;
-        if (gn + 1 < N) v = *(const v2d*)p;
-        else if (gn < N) v.x = p[0];
+        if (gn + 1 < N) {
+          // an odd ldb leaves every other row 8-byte aligned only
+          if (BODD) {
+            v.x = p[0];
+            v.y = p[1];
+          } else {
+            v = *(const v2d*)p;
+          }
+        } else if (gn < N) {
+          v.x = p[0];
+        }
       }
       rb[e] = v;
     }
@@ -695,7 +704,7 @@ __device__ __forceinline__ void sk_segment(const GemmBatch& g, int prob, int m0,
   }
 }
 
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, bool BODD>
 __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_streamk_f64(
     GemmBatch g, StreamK sk) {
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
@@ -723,9 +732,9 @@ __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_s
 #pragma unroll
       for (int j = 0; j < NI; ++j) acc[i][j] = v4d{0, 0, 0, 0};
     if (g.transA[prob])
-      sk_segment<BM, BN, WGM, WGN, true, MI, NI>(g, prob, m0, s0, s1, As, Bs, acc);
+      sk_segment<BM, BN, WGM, WGN, true, BODD, MI, NI>(g, prob, m0, s0, s1, As, Bs, acc);
     else
-      sk_segment<BM, BN, WGM, WGN, false, MI, NI>(g, prob, m0, s0, s1, As, Bs, acc);
+      sk_segment<BM, BN, WGM, WGN, false, BODD, MI, NI>(g, prob, m0, s0, s1, As, Bs, acc);
     if (s0 == 0 && s1 == sk.nslices) {
       // the whole tile: written here
       double* C = (double*)g.C[prob];
@@ -969,9 +978,9 @@ __global__ __launch_bounds__(skf32::NT, 1) void gemm_streamk_f32(GemmBatch g, St
 }
 
 // Sums the partial tiles of every tile cut by range boundaries, in
-// workgroup order, and writes them (alpha and accumulate as in the main
-// kernel; the split runs only with a plain row-major C).  kFixRows-row strips of a tile per block of 256
-// threads, two adjacent columns per thread.  Ranges are never empty here (the
+// workgroup order, and writes them through C's index map (alpha and
+// accumulate as in the main kernel).  kFixRows-row strips of a tile per block
+// of 256 threads, two adjacent columns per thread.  Ranges are never empty here (the
 // split runs only with at least 8 slices per workgroup), so every workgroup
 // between the first and the last owner of a tile left a partial in slot 2w.
 constexpr int kFixRows = 24;
@@ -995,14 +1004,16 @@ __global__ __launch_bounds__(256) void gemm_streamk_fixup(GemmBatch g, StreamK s
     v2d v = *(const v2d*)&sk.part[(long)first_slot * (BM * BN) + e];
     for (int w = wf + 1; w <= wl; ++w) v += *(const v2d*)&sk.part[(long)(2 * w) * (BM * BN) + e];
     const bool two = n + 1 < g.N;
-    double* p = C + (long)m * g.cs_m0 + n;
+    const long offm = map2(m, g.cdiv_m, g.cs_m1, g.cs_m0);
+    double* p0 = C + offm + map2(n, g.cdiv_n, g.cs_n1, g.cs_n0);
+    double* p1 = two ? C + offm + map2(n + 1, g.cdiv_n, g.cs_n1, g.cs_n0) : p0;
     double o0 = g.alpha * v.x, o1 = g.alpha * v.y;
     if (g.accumulate) {
-      o0 += p[0];
-      if (two) o1 += p[1];
+      o0 += *p0;
+      if (two) o1 += *p1;
     }
-    p[0] = o0;
-    if (two) p[1] = o1;
+    *p0 = o0;
+    if (two) *p1 = o1;
   }
 }
 
@@ -1495,20 +1506,44 @@ int launch_gemm_si(const GemmBatch& g, hipStream_t s) {
 
 size_t gemm_si_scratch_bytes() { return (size_t)2 * kSplitMaxCus * 192 * 160 * sizeof(double); }
 
+// Ranges of the split: ncu, or fewer so that each holds at least 8 slices.
+static int sk_ranges(long pairs, int ncu) { return (int)std::min<long>(ncu, pairs / 8); }
+
 bool gemm_si_balanced_useful(int count, int M, int N, int K, int ncu) {
-  // ranges pay off once the tiles reach half the CUs and each tile holds
-  // several slices; below that the plain tile kernel.  With these bounds
-  // every range holds at least 8 slices, so none is empty.
-  return ncu >= 1 && ncu <= kSplitMaxCus && N <= 160 && (long)ceil_div(M, 192) * count >= ncu / 2 &&
-         ceil_div(K, 16) >= 16;
+  // the split pays whenever each tile holds several slices: its ranges keep
+  // every CU busy for the same time whatever the tile count, where the
+  // plain kernel leaves CUs idle through whole K walks once the tiles are
+  // fewer than the slots or do not divide them
+  if (ncu < 1 || ncu > kSplitMaxCus || N > 160 || M <= 0 || count <= 0 || K <= 0) return false;
+  const long tiles = (long)ceil_div(M, 192) * count, ns = ceil_div(K, 16);
+  return ns >= 16 && sk_ranges(tiles * ns, ncu) >= 1;
+}
+
+// The split kernel's operands: A as the skinny kernel's (even lda, 16-byte
+// aligned rows); B with an even ldb on 16-byte aligned bases, or with an odd
+// one on 8-byte aligned bases (loaded one element at a time).
+static bool streamk_ok(const GemmBatch& g) {
+  if ((g.lda & 1) || (g.a_bs & 1)) return false;
+  const uintptr_t balign = (g.ldb & 1) ? 7 : 15;
+  for (int i = 0; i < g.count; ++i)
+    if (((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & balign)) return false;
+  return true;
 }
 
 bool gemm_si_balanced_applies(const GemmBatch& g, const void* scratch, int ncu) {
   if (!scratch || ((uintptr_t)scratch & 15) || g.M <= 0 || g.N <= 0 || g.count <= 0 || g.nbatch != 1)
     return false;
-  const bool rowmajor_c = g.cdiv_m >= g.M && g.cdiv_n >= g.N && g.cs_n0 == 1;
-  return gemm_si_balanced_useful(g.count, g.M, g.N, g.K, ncu) && skinny_ok(g) && rowmajor_c &&
+  return gemm_si_balanced_useful(g.count, g.M, g.N, g.K, ncu) && streamk_ok(g) &&
          (long)g.count * ceil_div(g.M, 192) * ceil_div(g.K, 16) <= (1L << 40);
+}
+
+template <int BN, bool BODD>
+static int launch_streamk_f64(const GemmBatch& g, const StreamK& sk, hipStream_t s) {
+  gemm_streamk_f64<192, BN, 4, 2, BODD><<<sk.nwg, 512, 0, s>>>(g, sk);
+  CTM_HIP_TRY(hipGetLastError());
+  gemm_streamk_fixup<192, BN><<<(int)((long)g.count * sk.tiles_m * (192 / kFixRows)), 256, 0, s>>>(g, sk);
+  CTM_HIP_TRY(hipGetLastError());
+  return 0;
 }
 
 int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStream_t s) {
@@ -1520,13 +1555,18 @@ int launch_gemm_si_balanced(const GemmBatch& g, double* scratch, int ncu, hipStr
   sk.nslices = ns;
   sk.tiles_m = tm;
   sk.total = (long)g.count * tm * ns;
-  sk.nwg = ncu;
+  sk.nwg = sk_ranges(sk.total, ncu);
   sk.part = scratch;
-  gemm_streamk_f64<192, 160, 4, 2><<<ncu, 512, 0, s>>>(g, sk);
-  CTM_HIP_TRY(hipGetLastError());
-  gemm_streamk_fixup<192, 160><<<(int)((long)g.count * tm * (192 / kFixRows)), 256, 0, s>>>(g, sk);
-  CTM_HIP_TRY(hipGetLastError());
-  return 0;
+  // 128-wide tiles for N <= 128 (3 x 4 accumulator blocks of 16 x 16 per
+  // wavefront): less of the MFMA work is padding
+  const bool odd = g.ldb & 1;
+  if (g.N <= 128) return odd ? launch_streamk_f64<128, true>(g, sk, s) : launch_streamk_f64<128, false>(g, sk, s);
+  return odd ? launch_streamk_f64<160, true>(g, sk, s) : launch_streamk_f64<160, false>(g, sk, s);
+}
+
+int launch_gemm_f64_any(const GemmBatch& g, double* scratch, int ncu, hipStream_t s) {
+  if (gemm_si_balanced_applies(g, scratch, ncu)) return launch_gemm_si_balanced(g, scratch, ncu, s);
+  return launch_gemm(g, DT::F64, DT::F64, DT::F64, s);
 }
 
 bool gemm_si_f32_balanced_applies(const GemmBatch& g, const void* scratch, int ncu) {

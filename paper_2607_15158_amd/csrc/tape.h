@@ -49,8 +49,8 @@ class Tape {
 
   // --- operations (forward launch + backward record) ------------------------
   // Float64 GEMM with the library's descriptor (no accumulate); every output
-  // must be a fresh value.  si: the subspace-iteration kernels.
-  int gemm(const GemmBatch& g, bool si = false);
+  // must be a fresh value.  Thin products with long K take the split kernel.
+  int gemm(const GemmBatch& g);
   // dst (row-major over dims) = src[sum_i idx_i strides_i]; a bijection.
   int permute(const double* src, double* dst, int nd, const int* dims, const long* strides);
   // Q_i = the thin Householder QR of H_i (R_ii >= 0), n x k each.
@@ -99,7 +99,7 @@ class Tape {
   Region* find(const void* p, uintptr_t* base);
   bool inside(const void* p, size_t bytes) const;
   int check_gemm(const GemmBatch& g) const;
-  int launch(const GemmBatch& g, bool si);
+  int launch(const GemmBatch& g);
   double* tmp(long n);        // backward scratch, released by tmp_reset()
   void tmp_reset() { tmp_off_ = 0; }
   int fill(double* x, long n, double v);

@@ -568,14 +568,13 @@ int Tape::check_gemm(const GemmBatch& g) const {
   return 0;
 }
 
-int Tape::launch(const GemmBatch& g, bool si) {
+int Tape::launch(const GemmBatch& g) {
   if (dry_ || g.count == 0) return 0;
   if (check_gemm(g))
     return fail(CTM_E_SHAPE, "adjoint GEMM operand outside its buffers (M=" + std::to_string(g.M) +
                                  " N=" + std::to_string(g.N) + " K=" + std::to_string(g.K) +
                                  "); launch refused");
-  const int rc = si ? launch_gemm_si_balanced(g, sk_part_, kSplitMaxCus, st_)
-                    : launch_gemm(g, DT::F64, DT::F64, DT::F64, st_);
+  const int rc = launch_gemm_f64_any(g, sk_part_, kSplitMaxCus, st_);
   if (rc) return fail(rc == 1 ? CTM_E_ARG : rc, thread_error());
   return 0;
 }
@@ -583,9 +582,9 @@ int Tape::launch(const GemmBatch& g, bool si) {
 // ---------------------------------------------------------------------------
 // GEMM
 // ---------------------------------------------------------------------------
-int Tape::gemm(const GemmBatch& g, bool si) {
+int Tape::gemm(const GemmBatch& g) {
   if (g.accumulate) return fail(CTM_E_ARG, "taped GEMMs do not accumulate");
-  const int rc = launch(g, si);
+  const int rc = launch(g);
   if (rc) return rc;
   // scratch of the backward pass: per problem C_bar and one transposed operand
   const long MN = (long)g.M * g.N;
@@ -638,7 +637,7 @@ int Tape::gemm_bwd(const GemmBatch& g) {
       GemmBatch ga{};
       auto flush = [&]() -> int {
         if (ga.count == 0) return 0;
-        const int rc = launch(ga, false);
+        const int rc = launch(ga);
         ga.count = 0;
         return rc;
       };
@@ -700,7 +699,7 @@ int Tape::gemm_bwd(const GemmBatch& g) {
       GemmBatch gb{};
       auto flush = [&]() -> int {
         if (gb.count == 0) return 0;
-        const int rc = launch(gb, false);
+        const int rc = launch(gb);
         gb.count = 0;
         return rc;
       };
@@ -814,8 +813,8 @@ int Tape::qr(int count, const double* const* H, double* const* Q, int n, int k) 
       g2.A[i] = qb[j]; g2.transA[i] = 1; g2.B[i] = q[j]; g2.C[i] = Mm[i];
     }
     g1.count = g2.count = nl;
-    int rc = launch(g1, false);
-    if (!rc) rc = launch(g2, false);
+    int rc = launch(g1);
+    if (!rc) rc = launch(g2);
     if (rc) return rc;
     SmallArgs sa{};
     for (int i = 0; i < nl; ++i) {
@@ -848,8 +847,8 @@ int Tape::qr(int count, const double* const* H, double* const* Q, int n, int k) 
       g4.A[i] = Y[i]; g4.B[i] = RiT[i]; g4.C[i] = hg[j];
     }
     g3.count = g4.count = nl;
-    rc = launch(g3, false);
-    if (!rc) rc = launch(g4, false);
+    rc = launch(g3);
+    if (!rc) rc = launch(g4);
     return rc;
   });
   return 0;
@@ -891,7 +890,7 @@ int Tape::svdproj(int count, const double* const* rho, const double* const* Yt, 
       gy.C[j] = ytu[j];
     }
     gy.count = count;
-    rc = launch(gy, false);
+    rc = launch(gy);
     if (rc) return rc;
     SignArgs sa{};
     sa.N = nrows;
@@ -969,7 +968,7 @@ int Tape::svdproj(int count, const double* const* rho, const double* const* Yt, 
       g1.A[2 * j + 1] = VS[j]; g1.transA[2 * j + 1] = 1; g1.B[2 * j + 1] = vb[j]; g1.C[2 * j + 1] = Jv[j];
     }
     g1.count = 2 * cnt;
-    int rc = launch(g1, false);
+    int rc = launch(g1);
     if (rc) return rc;
     KmatArgs ka{};
     for (int j = 0; j < cnt; ++j) {
@@ -987,7 +986,7 @@ int Tape::svdproj(int count, const double* const* rho, const double* const* Yt, 
       if (rc) return rc;
     }
     g2.count = cnt;
-    rc = launch(g2, false);
+    rc = launch(g2);
     if (rc) return rc;
     GemmBatch g3 = rm(k, k, k);
     g3.accumulate = 1;
@@ -999,7 +998,7 @@ int Tape::svdproj(int count, const double* const* rho, const double* const* Yt, 
       ++nc;
     }
     g3.count = nc;
-    return launch(g3, false);
+    return launch(g3);
   });
   return 0;
 }

@@ -63,7 +63,10 @@ SPLIT_CASES = [
     (1, 400, 16, 300, [1], None, 2, 2.0, 1, True),            # two ranges of 1.5 tiles
     (2, 700, 100, 260, [0, 1], 700, 1, 1.0, 0, True),         # one range: every tile whole
     (2, 2000, 33, 4001, [0, 0], None, 256, 1.0, 0, False),    # odd lda: the plain tile kernel
-    (8, 500, 160, 500, [0] * 8, None, 256, 1.0, 0, False),    # 24 tiles: too few to split
+    (8, 500, 160, 500, [0] * 8, None, 256, 1.0, 0, True),     # 24 tiles in 96 ranges of 8 slices
+    (4, 3000, 64, 200, [0] * 4, None, 256, 1.0, 0, False),    # 13 K slices: the plain tile kernel
+    (6, 2500, 105, 2500, [0, 0, 0, 1, 1, 1], None, 256, 1.0, 0, True),  # odd ldb, 84 long tiles
+    (2, 1000, 127, 2100, [1, 0], 2100, 32, -1.0, 1, True),    # odd ldb, 128-wide tiles, ragged
 ]
 
 
