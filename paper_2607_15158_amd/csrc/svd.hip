@@ -36,6 +36,7 @@ namespace {
 
 constexpr int kSvdMaxN = 192;   // the preconditioning QR holds n <= 192 rows per leaf
 constexpr int kRPL = kSvdMaxN / 64;   // rows per lane in the finalisation
+constexpr int kCompChunk = 32;       // non-zero columns staged per LDS pass of the completion
 constexpr int kBlk = 16;              // columns per block
 constexpr int kMaxSweeps = 24;
 constexpr int kInner = 1;            // inner sweeps per block-pair visit
@@ -340,55 +341,132 @@ __global__ __launch_bounds__(1024) void svd_finalize(SvdArgs a) {
   }
   __syncthreads();
   // orthonormal completion of numerically zero columns; the cut is the one
-  // below which the rotations left a column alone.  Zero columns are taken
-  // in order; for each, unit vectors e_cand (cand increasing) are projected
-  // on the complement of the other columns (the non-zero ones and the zero
-  // ones already completed) by classical Gram-Schmidt applied twice, with
-  // the dot products of a pass spread over the wavefronts and the update
-  // over the rows, until one keeps enough of its length.
+  // below which the rotations left a column alone.  The unit vectors are
+  // projected on the complement of the non-zero columns at once
+  // (X = I - U U^T), and the complement's basis is drawn from X's columns
+  // in index order by Gram-Schmidt: the zero columns, in index order, take
+  // the unit vectors e_0, e_1, ... that keep enough of their length after
+  // the projection on the complement of the non-zero columns and of the
+  // zero columns completed before.  Wavefront w keeps columns w, w + 16, ...
+  // of X in registers, rows lane, lane + 64, lane + 128.
   const double zero_cut = 1e-15 * sqrt(a.fro2[mat]);
   if (a.U[mat] != nullptr) {
-    __shared__ double xs[kSvdMaxN], ds[kSvdMaxN];
-    __shared__ double xnorm;
-    int cand = 0;
-    for (int c = 0; c < n; ++c) {
-      if (snorm[c] > zero_cut) continue;
-      for (; cand < n; ++cand) {
-        for (int r = tid; r < n; r += 1024) xs[r] = r == cand ? 1.0 : 0.0;
+    __shared__ int nzl[kSvdMaxN], zl[kSvdMaxN];
+    __shared__ int cnt[2];
+    __shared__ double qs[kSvdMaxN];
+    __shared__ int took[2];
+    __shared__ double ust[kCompChunk][kSvdMaxN];
+    if (wave == 0) {
+      int nr = 0, nz = 0;
+      for (int base = 0; base < n; base += 64) {
+        const int c = base + lane;
+        const bool in = c < n;
+        const bool live = in && snorm[c] > zero_cut;
+        const unsigned long long ml = __ballot(live), mz = __ballot(in && !live);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        if (live) nzl[nr + __popcll(ml & below)] = c;
+        else if (in) zl[nz + __popcll(mz & below)] = c;
+        nr += __popcll(ml);
+        nz += __popcll(mz);
+      }
+      if (lane == 0) {
+        cnt[0] = nr;
+        cnt[1] = nz;
+      }
+    }
+    __syncthreads();
+    const int nr = cnt[0], nz = cnt[1];
+    if (nz > 0) {
+      constexpr int CPW = kSvdMaxN / nwaves;   // columns per wavefront
+      double x[CPW][kRPL];
+#pragma unroll
+      for (int q = 0; q < CPW; ++q)
+#pragma unroll
+        for (int e = 0; e < kRPL; ++e) {
+          const int j = wave + nwaves * q, i = lane + 64 * e;
+          x[q][e] = (i == j && j < n) ? 1.0 : 0.0;
+        }
+      // X -= U_nz U_nz^T, kCompChunk non-zero columns staged in LDS at a time
+      for (int o0 = 0; o0 < nr; o0 += kCompChunk) {
+        const int m = min(kCompChunk, nr - o0);
+        for (int t = tid; t < m * n; t += 1024) {
+          const int oo = t / n, i = t % n;
+          ust[oo][i] = Uc[(size_t)nzl[o0 + oo] * n + i];
+        }
         __syncthreads();
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int o = wave; o < n; o += nwaves) {
-            const bool ref = o != c && !(snorm[o] <= zero_cut && o > c);
-            double d = 0.0;
-            if (ref)
-              for (int r = lane; r < n; r += 64) d += Uc[(size_t)o * n + r] * xs[r];
-            d = wsum(d);
-            if (lane == 0) ds[o] = ref ? d : 0.0;
+        for (int oo = 0; oo < m; ++oo) {
+          double ui[kRPL];
+#pragma unroll
+          for (int e = 0; e < kRPL; ++e) {
+            const int i = lane + 64 * e;
+            ui[e] = i < n ? ust[oo][i] : 0.0;
           }
-          __syncthreads();
-          for (int r = tid; r < n; r += 1024) {
-            double acc = 0.0;
-            for (int o = 0; o < n; ++o) acc += ds[o] * Uc[(size_t)o * n + r];
-            xs[r] -= acc;
+#pragma unroll
+          for (int q = 0; q < CPW; ++q) {
+            const int j = wave + nwaves * q;
+            const double uj = j < n ? ust[oo][j] : 0.0;
+#pragma unroll
+            for (int e = 0; e < kRPL; ++e) x[q][e] -= uj * ui[e];
           }
-          __syncthreads();
-        }
-        if (wave == 0) {
-          double nn = 0.0;
-          for (int r = lane; r < n; r += 64) nn += xs[r] * xs[r];
-          nn = sqrt(wsum(nn));
-          if (lane == 0) xnorm = nn;
         }
         __syncthreads();
-        const double nn = xnorm;
-        // the complement has dimension >= 1, so some unit vector keeps at
-        // least 1/sqrt(n) of its length after the projection
-        if (nn > 0.5 / sqrt((double)n)) {
-          for (int r = tid; r < n; r += 1024) Uc[(size_t)c * n + r] = xs[r] / nn;
-          __syncthreads();
-          ++cand;
-          break;
+      }
+      // candidates in index order: a column of X that keeps more than
+      // 1/(2 sqrt(n)) of its length (some column of the complement's
+      // projector always does) becomes the next zero column and is removed
+      // from the later candidates
+      const double keep_min = 0.5 / sqrt((double)n);
+      int t = 0;
+      for (int cand = 0; cand < n && t < nz; ++cand) {
+        if (wave == cand % nwaves) {
+          const int qc = cand / nwaves;
+          double xc[kRPL] = {};
+#pragma unroll
+          for (int q = 0; q < CPW; ++q)
+            if (q == qc)
+#pragma unroll
+              for (int e = 0; e < kRPL; ++e) xc[e] = x[q][e];
+          double ss = 0.0;
+#pragma unroll
+          for (int e = 0; e < kRPL; ++e) ss += xc[e] * xc[e];
+          const double nn = sqrt(wsum(ss));
+          const bool take = nn > keep_min;
+          if (take) {
+            const double inv = 1.0 / nn;
+            const int c = zl[t];
+#pragma unroll
+            for (int e = 0; e < kRPL; ++e) {
+              const int i = lane + 64 * e;
+              if (i < n) {
+                qs[i] = xc[e] * inv;
+                Uc[(size_t)c * n + i] = xc[e] * inv;
+              }
+            }
+          }
+          if (lane == 0) took[cand & 1] = take ? 1 : 0;
         }
+        __syncthreads();
+        if (!took[cand & 1]) continue;
+        ++t;
+        if (t == nz) break;
+        double qv[kRPL];
+#pragma unroll
+        for (int e = 0; e < kRPL; ++e) {
+          const int i = lane + 64 * e;
+          qv[e] = i < n ? qs[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) {
+          const int j = wave + nwaves * q;
+          if (j <= cand || j >= n) continue;
+          double d = 0.0;
+#pragma unroll
+          for (int e = 0; e < kRPL; ++e) d += qv[e] * x[q][e];
+          d = wsum(d);
+#pragma unroll
+          for (int e = 0; e < kRPL; ++e) x[q][e] -= d * qv[e];
+        }
+        __syncthreads();
       }
     }
   }

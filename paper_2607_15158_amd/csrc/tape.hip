@@ -265,20 +265,32 @@ struct KmatArgs {
 // s_j^2))^2, which only changes pairs degenerate to rounding: the kept
 // singular values of rho span many orders of magnitude, so a broadening on
 // the scale of s_1^2 would suppress the gaps among the small ones.
+// Singular values at or below the forward SVD's zero cut (1e-15 of the
+// Frobenius norm) count as exact zeros: their vectors are a completion
+// chosen by the forward pass, a rotation among them changes no output, and
+// the terms of a pair of them vanish (both carry a factor s = 0).
 __global__ __launch_bounds__(256) void k_svd_kmat(KmatArgs a) {
   const int b = blockIdx.y, n = a.n;
   const double* s = a.s[b];
+  double f2 = 0.0;
+  for (int t = 0; t < n; ++t) f2 += s[t] * s[t];
+  const double cut = 1e-15 * sqrt(f2);
   for (int idx = blockIdx.x * 256 + threadIdx.x; idx < n * n; idx += gridDim.x * 256) {
     const int i = idx / n, j = idx % n;
     double v;
     if (i == j) {
       v = a.sb[b][i];
     } else {
-      const double dl = s[j] * s[j] - s[i] * s[i];
-      const double e2 = 1e-14 * (s[i] * s[i] + s[j] * s[j]);
-      const double F = dl / (dl * dl + e2 * e2);
-      v = F * (a.Ju[b][idx] - a.Ju[b][j * n + i]) * s[j] +
-          s[i] * F * (a.Jv[b][idx] - a.Jv[b][j * n + i]);
+      const double si = s[i] > cut ? s[i] : 0.0, sj = s[j] > cut ? s[j] : 0.0;
+      if (si == 0.0 && sj == 0.0) {
+        v = 0.0;
+      } else {
+        const double dl = sj * sj - si * si;
+        const double e2 = 1e-14 * (si * si + sj * sj);
+        const double F = dl / (dl * dl + e2 * e2);
+        v = F * (a.Ju[b][idx] - a.Ju[b][j * n + i]) * sj +
+            si * F * (a.Jv[b][idx] - a.Jv[b][j * n + i]);
+      }
     }
     a.K[b][idx] = v;
   }
