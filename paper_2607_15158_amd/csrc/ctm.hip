@@ -480,6 +480,22 @@ int run_gemm(ctm_ctx* c, int cls, const GemmBatch& g0, DT ta, DT tb, DT tc, doub
   // in the split bfloat16 mode every product with a float32-stored operand is
   // a contraction of the mode
   if (c->split && (ta == DT::F32 || tb == DT::F32)) g.split = 1;
+  // thin float64 products with long K on the split kernel of the SI
+  // applications (its own launch in a recorded batch: it sums cut tiles in
+  // a fixed order of its own, so the product keeps the bits of a solo move)
+  if (ta == DT::F64 && tb == DT::F64 && tc == DT::F64 && !g.split &&
+      gemm_si_balanced_applies(g, c->sk_part, c->sk_cus)) {
+    double* part = c->sk_part;
+    const int cus = c->sk_cus;
+    if (c->rec) {
+      c->rec->push_back(BatchOp{false, GemmBatch{}, [=](hipStream_t st) {
+                                  return launch_gemm_si_balanced(g, part, cus, st);
+                                }});
+      return 0;
+    }
+    ProfScope ps(c, cls, gemm_flops(g), bytes);
+    return launch_gemm_si_balanced(g, part, cus, c->st);
+  }
   if (c->rec) {
     if (ta == DT::F64 && tb == DT::F64 && tc == DT::F64)
       c->rec->push_back(BatchOp{true, g, nullptr});
