@@ -222,6 +222,19 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 // k-contiguous and are kept as [m][k] with rows of BK + 1 doubles, so that
 // both the 16-byte row loads and the fragment reads (16 consecutive m at
 // fixed k per lane group) avoid bank conflicts.
+// Two adjacent doubles: one 16-byte load, or two 8-byte ones where odd
+// leading dimensions leave every other row 8-byte aligned only.
+template <bool ODD>
+__device__ __forceinline__ v2d ld_pair(const double* p) {
+  if (ODD) {
+    v2d v;
+    v.x = p[0];
+    v.y = p[1];
+    return v;
+  }
+  return *(const v2d*)p;
+}
+
 template <int BM, int BK>
 struct SkinnyA {
   static constexpr int LT = BM + 16;          // [k][m] row length
@@ -229,7 +242,7 @@ struct SkinnyA {
   static constexpr int SIZE = (BK * LT > BM * LN) ? BK * LT : BM * LN;
 };
 
-template <int BM, int BN, int WGM, int WGN, bool TRANS>
+template <int BM, int BN, int WGM, int WGN, bool TRANS, bool ODD = false>
 __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int tiles_n, int lin,
                                             double (*As)[SkinnyA<BM, 16>::SIZE],
                                             double (*Bs)[16][BN + 16]) {
@@ -266,14 +279,14 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
           const int gk = k0 + i / (BM / 2), gm = m0 + 2 * (i % (BM / 2));
           if (gk < K) {
             const double* p = A + (long)gk * lda + gm;
-            if (gm + 1 < M) v = *(const v2d*)p;
+            if (gm + 1 < M) v = ld_pair<ODD>(p);
             else if (gm < M) v.x = p[0];
           }
         } else {
           const int gm = m0 + i / (BK / 2), gk = k0 + 2 * (i % (BK / 2));
           if (gm < M) {
             const double* p = A + (long)gm * lda + gk;
-            if (gk + 1 < K) v = *(const v2d*)p;
+            if (gk + 1 < K) v = ld_pair<ODD>(p);
             else if (gk < K) v.x = p[0];
           }
         }
@@ -287,7 +300,7 @@ __device__ __forceinline__ void skinny_tile(const GemmBatch& g, int tiles_m, int
       v2d v = {0.0, 0.0};
       if (i < NB && gk < K) {
         const double* p = B + (long)gk * ldb + gn;
-        if (gn + 1 < N) v = *(const v2d*)p;
+        if (gn + 1 < N) v = ld_pair<ODD>(p);
         else if (gn < N) v.x = p[0];
       }
       rb[e] = v;
@@ -1017,7 +1030,7 @@ __global__ __launch_bounds__(256) void gemm_streamk_fixup(GemmBatch g, StreamK s
   }
 }
 
-template <int BM, int BN, int WGM, int WGN, int ROLE>
+template <int BM, int BN, int WGM, int WGN, int ROLE, bool ODD = false>
 __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_skinny_f64(
     GemmBatch g, int tiles_m, int tiles_n) {
   __shared__ double As[2][SkinnyA<BM, 16>::SIZE];
@@ -1026,9 +1039,9 @@ __global__ __launch_bounds__(64 * WGM * WGN, 512 / (64 * WGM * WGN)) void gemm_s
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
   const int prob = lin / per_prob / g.nbatch;
   if (g.transA[prob])
-    skinny_tile<BM, BN, WGM, WGN, true>(g, tiles_m, tiles_n, lin, As, Bs);
+    skinny_tile<BM, BN, WGM, WGN, true, ODD>(g, tiles_m, tiles_n, lin, As, Bs);
   else
-    skinny_tile<BM, BN, WGM, WGN, false>(g, tiles_m, tiles_n, lin, As, Bs);
+    skinny_tile<BM, BN, WGM, WGN, false, ODD>(g, tiles_m, tiles_n, lin, As, Bs);
 }
 
 // ---------------------------------------------------------------------------
@@ -1441,11 +1454,11 @@ bool skinny_ok(const GemmBatch& g) {
   return true;
 }
 
-template <int BM, int BN, int WGM, int WGN, int ROLE>
+template <int BM, int BN, int WGM, int WGN, int ROLE, bool ODD = false>
 int launch_skinny(const GemmBatch& g, hipStream_t s) {
   const int tm = ceil_div(g.M, BM), tn = ceil_div(g.N, BN);
   dim3 grid(tm * tn * g.count * g.nbatch), block(64 * WGM * WGN);
-  gemm_skinny_f64<BM, BN, WGM, WGN, ROLE><<<grid, block, 0, s>>>(g, tm, tn);
+  gemm_skinny_f64<BM, BN, WGM, WGN, ROLE, ODD><<<grid, block, 0, s>>>(g, tm, tn);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }
@@ -1634,7 +1647,18 @@ bool launch_f32_db(const GemmBatch& g, hipStream_t s, int* rc) {
 // columns of the double-layer absorptions at D = 6).
 bool launch_f64_db(const GemmBatch& g, hipStream_t s, int* rc) {
   // short K (a few slices per tile) gains nothing from the double buffer
-  if (g.K < 512 || g.M < 256 || !skinny_ok(g)) return false;
+  if (g.K < 512 || g.M < 256) return false;
+  // odd leading dimensions or batch strides: the same tiles with operand
+  // pairs loaded one element at a time
+  if (!skinny_ok(g)) {
+    if (g.N <= 160)
+      *rc = launch_skinny<96, 160, 2, 2, 0, true>(g, s);
+    else if ((long)g.M * g.count * g.nbatch >= 16384)
+      *rc = launch_skinny<256, 144, 8, 1, 0, true>(g, s);
+    else
+      *rc = launch_skinny<128, 144, 4, 1, 0, true>(g, s);
+    return true;
+  }
   if (g.N <= 160)
     *rc = launch_skinny<96, 160, 2, 2, 0>(g, s);
   else if ((long)g.M * g.count * g.nbatch >= 16384)

@@ -2,7 +2,7 @@
 
 GEMM against float64 NumPy products (N <= 160 runs the skinny kernel of the
 enlarged-corner applications, wide N with long K the 256 x 144 double-
-buffered tiles, short K the general tiles; the split form of the skinny
+buffered tiles, also with odd leading dimensions, short K the general tiles; the split form of the skinny
 kernel with ranges shorter and longer than a tile, mixed transposes, padded
 rows, alpha and accumulation, and the cases where it hands over to the
 plain tiles); Householder QR against the oracle's
@@ -31,7 +31,11 @@ def dev(x):
                                          (1000, 144, 520, 0), (64, 1296, 1296, 0),
                                          (5184, 160, 5184, 0), (5184, 160, 5184, 1),
                                          (97, 159, 33, 1), (5600, 300, 600, 0),
-                                         (5600, 300, 600, 1)])
+                                         (5600, 300, 600, 1),
+                                         # odd leading dimensions: pairs loaded one
+                                         # element at a time
+                                         (1001, 625, 625, 0), (10001, 625, 625, 1),
+                                         (2001, 159, 777, 0)])
 def test_gemm_f64_matches_numpy(M, N, K, trans):
     rng = np.random.default_rng(M * 7 + N)
     A = [rng.standard_normal((K, M) if trans else (M, K)) for _ in range(3)]
