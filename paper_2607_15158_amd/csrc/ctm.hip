@@ -496,6 +496,12 @@ int run_gemm(ctm_ctx* c, int cls, const GemmBatch& g0, DT ta, DT tb, DT tc, doub
     ProfScope ps(c, cls, gemm_flops(g), bytes);
     return launch_gemm_si_balanced(g, part, cus, c->st);
   }
+  // the float32 contractions of that shape on the float32 split kernel
+  if (ta == DT::F32 && tb == DT::F64 && tc == DT::F64 && !g.split && !c->rec &&
+      gemm_si_f32_balanced_applies(g, c->sk_part, c->sk_cus)) {
+    ProfScope ps(c, cls, gemm_flops(g), bytes);
+    return launch_gemm_si_f32_balanced(g, c->sk_part, c->sk_cus, c->st);
+  }
   if (c->rec) {
     if (ta == DT::F64 && tb == DT::F64 && tc == DT::F64)
       c->rec->push_back(BatchOp{true, g, nullptr});

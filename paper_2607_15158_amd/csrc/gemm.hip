@@ -1590,10 +1590,10 @@ bool gemm_si_f32_balanced_applies(const GemmBatch& g, const void* scratch, int n
   for (int i = 0; i < g.count; ++i)
     if (((uintptr_t)g.A[i] & 15) || ((uintptr_t)g.B[i] & 15)) return false;
   const bool rowmajor_c = g.cdiv_m >= g.M && g.cdiv_n >= g.N && g.cs_n0 == 1;
-  // at least 8 slices per range, so that no range is empty
-  const long tiles = (long)g.count * ceil_div(g.M, skf32::BM);
-  return rowmajor_c && ncu >= 1 && ncu <= kSplitMaxCus && tiles >= ncu / 2 &&
-         tiles * ceil_div(g.K, skf32::BK) >= 8L * ncu && tiles * ceil_div(g.K, skf32::BK) <= (1L << 40);
+  // at least 8 slices per range, so that no range is empty, and 8 per tile
+  const long tiles = (long)g.count * ceil_div(g.M, skf32::BM), ns = ceil_div(g.K, skf32::BK);
+  return rowmajor_c && ncu >= 1 && ncu <= kSplitMaxCus && ns >= 8 && tiles * ns >= 8L * ncu &&
+         tiles * ns <= (1L << 40);
 }
 
 int launch_gemm_si_f32_balanced(const GemmBatch& g, double* scratch, int ncu, hipStream_t s) {
