@@ -162,6 +162,31 @@ def test_jacobi_svd(n):
         assert np.abs((U * Sv) @ V.T - m).max() <= 1e-13 * ref[0] * n
 
 
+@pytest.mark.parametrize("n,r", [(105, 40), (192, 70), (160, 1), (64, 0)])
+def test_jacobi_svd_rank_deficient(n, r):
+    """Rank-r matrices: the n - r numerically zero columns are completed to an
+    orthonormal basis (the staged non-zero columns span several LDS chunks
+    at r = 40 and 70; n = 192 gives three rows per lane) and the product still
+    reconstructs the input."""
+    rng = np.random.default_rng(1000 + n + r)
+    m = rng.standard_normal((n, r)) @ rng.standard_normal((r, n)) if r else np.zeros((n, n))
+    rd = [dev(m)]
+    ud = [torch.zeros(n, n, dtype=torch.float64, device="cuda")]
+    vd = [torch.zeros(n, n, dtype=torch.float64, device="cuda")]
+    sd = [torch.zeros(n, dtype=torch.float64, device="cuda")]
+    P.svd_f64(rd, ud, sd, vd)
+    torch.cuda.synchronize()
+    U, Sv, V = ud[0].cpu().numpy(), sd[0].cpu().numpy(), vd[0].cpu().numpy()
+    ref = np.linalg.svd(m, compute_uv=False)
+    scale = max(ref[0], 1.0)
+    assert np.all(np.isfinite(U)) and np.all(np.isfinite(V))
+    assert np.all(np.diff(Sv) <= 0)
+    assert np.abs(Sv - ref).max() <= 1e-13 * scale * n
+    assert np.abs(U.T @ U - np.eye(n)).max() <= 1e-12 * n
+    assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12 * n
+    assert np.abs((U * Sv) @ V.T - m).max() <= 1e-13 * scale * n
+
+
 def test_jacobi_svd_values_only():
     rng = np.random.default_rng(9)
     m = rng.standard_normal((50, 50))
