@@ -415,12 +415,22 @@ __global__ __launch_bounds__(256) void qr_tree_wy(QrArgs q, int p, int s) {
 }
 
 // Leaf rows: C -= V op(T) (V^T C), V unit lower-trapezoidal (implicit ones,
-// zeros above).
+// zeros above).  Wavefront w owns rows 48 w .. 48 w + 47 of the leaf and
+// reads its rows of V and C from global memory straight into the operand
+// layout of v_mfma_f64_16x16x4 (lane l: row l/16 of a 4-row k-step, column
+// l%16 of a 16-column block), so neither block is staged in LDS: the
+// wavefronts' partial products V_w^T C_w meet in LDS, every wavefront forms
+// one 16 x 16 block of W2 = op(T) W1 from their sum, and each then updates
+// its own rows, C_w -= V_w W2.  About 50 KB of LDS lets several workgroups
+// share a CU.
 template <bool FORM>
-__global__ __launch_bounds__(256) void qr_leaf_wy(QrArgs q, int p) {
-  __shared__ double V[kPanel][kLR];
-  __shared__ double Cc[kPanel][kLR];
-  __shared__ double T[kPanel][kT], W1[kPanel][kT], W2[kPanel][kT];
+__global__ __launch_bounds__(256, 2) void qr_leaf_wy(QrArgs q, int p) {
+  constexpr int RW = kLeafRows / 4;   // rows per wavefront
+  constexpr int KS = RW / 4;          // k-steps over a wavefront's rows
+  constexpr int RB = RW / 16;         // 16-row blocks of a wavefront's rows
+  static_assert(kPanel == 32 && kTrailN == kPanel && RW % 16 == 0, "fragment shapes");
+  __shared__ double Wp[4][kPanel][kT];
+  __shared__ double T[kPanel][kT], W2[kPanel][kT];
   const int leaf = blockIdx.x, mat = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = q.N, k = q.k, nb = q.nb;
@@ -434,35 +444,83 @@ __global__ __launch_bounds__(256) void qr_leaf_wy(QrArgs q, int p) {
   const double* A = q.A[mat];
   double* M = FORM ? q.E[mat] : q.A[mat];
   const long sl = slot(mat, p, leaf, nb, q.P);
-  g2l(kPanel * kLeafRows, tid,
-      [&](int idx) {
-        const int r = idx / kPanel, c = idx % kPanel;
-        if (r >= m || c >= w) return 0.0;
-        return r > c ? A[(long)(a0 + r) * k + c0 + c] : (r == c ? 1.0 : 0.0);
-      },
-      [&](int idx, double v) { V[idx % kPanel][idx / kPanel] = v; });
-  g2l(kPanel * kPanel, tid, [&](int idx) { return q.Tl[sl * kPanel * kPanel + idx]; },
-      [&](int idx, double v) { T[idx / kPanel][idx % kPanel] = v; });
-  g2l(m * kPanel, tid,
-      [&](int idx) {
-        const int r = idx / kPanel, c = idx % kPanel;
-        return c < nc ? M[(long)(a0 + r) * k + cb + c] : 0.0;
-      },
-      [&](int idx, double v) { Cc[idx % kPanel][idx / kPanel] = v; });
+  auto vval = [&](int r, int c) -> double {
+    if (r >= m || c >= w) return 0.0;
+    return r > c ? A[(long)(a0 + r) * k + c0 + c] : (r == c ? 1.0 : 0.0);
+  };
+  auto cval = [&](int r, int c) -> double {
+    return (r < m && c < nc) ? M[(long)(a0 + r) * k + cb + c] : 0.0;
+  };
+  // T (w x w; entries outside it are never read)
+  for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
+    const int i = idx / kPanel, l = idx % kPanel;
+    T[i][l] = (i < w && l < w) ? q.Tl[sl * kPanel * kPanel + idx] : 0.0;
+  }
+  const int r0 = RW * wave, li = lane & 15, lk = lane >> 4;
+  {
+    double vf[KS][2], cf[KS][2];
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      const int rr = r0 + 4 * t + lk;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        vf[t][i] = vval(rr, 16 * i + li);
+        cf[t][i] = cval(rr, 16 * i + li);
+      }
+    }
+    v4d acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+#pragma unroll
+    for (int t = 0; t < KS; ++t)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(vf[t][i], cf[t][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wp[wave][16 * i + lk + 4 * r][16 * j + li] = acc[i][j][r];
+  }
   __syncthreads();
-  lds_mm(w, nc, m, [&](int a, int r) { return V[a][r]; }, [&](int r, int c) { return Cc[c][r]; },
-         [&](int i, int j, double x) { W1[i][j] = x; }, wave, lane);
+  {
+    // W2 block (bi, bj) = op(T) W1 with W1 the sum of the partials in wave order
+    const int bi = wave >> 1, bj = wave & 1;
+    v4d a2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < kPanel / 4; ++t) {
+      const int l = 4 * t + lk, i = 16 * bi + li, c = 16 * bj + li;
+      const double tv = FORM ? T[i][l] : T[l][i];
+      const double w1 = (Wp[0][l][c] + Wp[1][l][c]) + (Wp[2][l][c] + Wp[3][l][c]);
+      a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(tv, w1, a2, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) W2[16 * bi + lk + 4 * r][16 * bj + li] = a2[r];
+  }
   __syncthreads();
-  lds_mm(w, nc, w, [&](int i, int l) { return FORM ? T[i][l] : T[l][i]; },
-         [&](int l, int c) { return W1[l][c]; }, [&](int i, int j, double x) { W2[i][j] = x; },
-         wave, lane);
-  __syncthreads();
-  lds_mm(m, nc, w, [&](int r, int l) { return V[l][r]; }, [&](int l, int c) { return W2[l][c]; },
-         [&](int r, int c, double x) { Cc[c][r] -= x; }, wave, lane);
-  __syncthreads();
-  for (int idx = tid; idx < m * kPanel; idx += 256) {
-    const int r = idx / kPanel, c = idx % kPanel;
-    if (c < nc) M[(long)(a0 + r) * k + cb + c] = Cc[c][r];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int rr0 = r0 + 16 * rb;
+    if (rr0 >= m) break;
+    v4d u[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int t = 0; t < kPanel / 4; ++t) {
+      const double av = vval(rr0 + li, 4 * t + lk);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        u[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W2[4 * t + lk][16 * j + li], u[j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rr0 + lk + 4 * r, col = 16 * j + li;
+        if (row < m && col < nc) {
+          double* pc = M + (long)(a0 + row) * k + cb + col;
+          *pc = *pc - u[j][r];
+        }
+      }
   }
 }
 
