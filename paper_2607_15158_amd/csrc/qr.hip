@@ -342,12 +342,18 @@ __global__ __launch_bounds__(256) void qr_tree_factor(QrArgs q, int p, int s) {
 // ---------------------------------------------------------------------------
 
 // Node rows: W1 = C_0 + sum_h V_h^T C_h; W2 = op(T) W1; C_0 -= W2;
-// C_h -= V_h W2.
+// C_h -= V_h W2.  The children are stacked with V_0 = I, so that the node is
+// one product of the leaf kernel's form over kArity x 32 rows: wavefront w
+// owns children 2w and 2w + 1 (64 rows) and reads their rows of V and C
+// straight into the MFMA operand layout; rows r >= w of a child are zero.
 template <bool FORM>
-__global__ __launch_bounds__(256) void qr_tree_wy(QrArgs q, int p, int s) {
-  __shared__ double Vs[kArity - 1][kPanel][kT], T[kPanel][kT];
-  __shared__ double Cs[kArity][kPanel][kTrailN + 1];
-  __shared__ double W1[kPanel][kTrailN + 1], W2[kPanel][kTrailN + 1];
+__global__ __launch_bounds__(256, 2) void qr_tree_wy(QrArgs q, int p, int s) {
+  constexpr int RW = kArity * kPanel / 4;   // rows per wavefront (two children)
+  constexpr int KS = RW / 4;
+  constexpr int RB = RW / 16;
+  static_assert(kPanel == 32 && kTrailN == kPanel && kArity == 8, "fragment shapes");
+  __shared__ double Wp[4][kPanel][kT];
+  __shared__ double T[kPanel][kT], W2[kPanel][kT];
   __shared__ int tops[kArity];
   const int a = blockIdx.x * s * kArity;
   const int mat = blockIdx.y;
@@ -360,57 +366,90 @@ __global__ __launch_bounds__(256) void qr_tree_wy(QrArgs q, int p, int s) {
   if (cb >= k) return;
   const int nc = min(kTrailN, k - cb);
   if (tid < kArity) tops[tid] = tid < nch ? top_row(a + tid * s, c0, N, nb) : 0;
-  __syncthreads();
-  auto top = [&](int h) { return tops[h]; };
   const double* A = q.A[mat];
   double* M = FORM ? q.E[mat] : q.A[mat];
   const long sl = slot(mat, p, a + s, nb, q.P);
-  const int nv = (nch - 1) * kPanel;
-  g2l(nv * kPanel, tid,
-      [&](int idx) {
-        const int u = idx / kPanel, c = idx % kPanel;
-        const int h = 1 + (u >> 5), r = u & 31;
-        return (r <= c && c < w) ? A[(long)(top(h) + r) * k + c0 + c] : 0.0;
-      },
-      [&](int idx, double v) {
-        const int u = idx / kPanel;
-        Vs[u >> 5][u & 31][idx % kPanel] = v;
-      });
-  g2l(kPanel * kPanel, tid, [&](int idx) { return q.Tn[sl * kPanel * kPanel + idx]; },
-      [&](int idx, double v) { T[idx / kPanel][idx % kPanel] = v; });
-  // rows r >= w of every child are loaded as zeros, so that the stacked
-  // products may run over full kPanel-row blocks
-  g2l(nch * kPanel * kTrailN, tid,
-      [&](int idx) {
-        const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
-        const int r = rc / kTrailN, c = rc % kTrailN;
-        return (r < w && c < nc) ? M[(long)(top(h) + r) * k + cb + c] : 0.0;
-      },
-      [&](int idx, double v) {
-        const int h = idx / (kPanel * kTrailN), rc = idx % (kPanel * kTrailN);
-        Cs[h][rc / kTrailN][rc % kTrailN] = v;
-      });
-  __syncthreads();
-  auto V = [&](int u, int c) -> double { return Vs[u >> 5][u & 31][c]; };
-  lds_mm(w, nc, nv, [&](int i, int u) { return V(u, i); },
-         [&](int u, int c) { return Cs[1 + (u >> 5)][u & 31][c]; },
-         [&](int i, int j, double x) { W1[i][j] = x + Cs[0][i][j]; }, wave, lane);
-  __syncthreads();
-  lds_mm(w, nc, w, [&](int i, int l) { return FORM ? T[i][l] : T[l][i]; },
-         [&](int l, int c) { return W1[l][c]; }, [&](int i, int j, double x) { W2[i][j] = x; },
-         wave, lane);
-  __syncthreads();
-  lds_mm(nv, nc, w, V, [&](int l, int c) { return W2[l][c]; },
-         [&](int u, int c, double x) { Cs[1 + (u >> 5)][u & 31][c] -= x; }, wave, lane);
-  for (int idx = tid; idx < w * kTrailN; idx += 256) {
-    const int r = idx / kTrailN, c = idx % kTrailN;
-    if (c < nc) Cs[0][r][c] -= W2[r][c];
+  for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
+    const int i = idx / kPanel, l = idx % kPanel;
+    T[i][l] = (i < w && l < w) ? q.Tn[sl * kPanel * kPanel + idx] : 0.0;
   }
   __syncthreads();
-  for (int idx = tid; idx < nch * w * kTrailN; idx += 256) {
-    const int h = idx / (w * kTrailN), rc = idx % (w * kTrailN);
-    const int r = rc / kTrailN, c = rc % kTrailN;
-    if (c < nc) M[(long)(top(h) + r) * k + cb + c] = Cs[h][r][c];
+  // stacked row u = 32 h + r of child h
+  auto vval = [&](int u, int c) -> double {
+    const int h = u >> 5, r = u & 31;
+    if (h >= nch || r >= w || c >= w) return 0.0;
+    if (h == 0) return r == c ? 1.0 : 0.0;
+    return r <= c ? A[(long)(tops[h] + r) * k + c0 + c] : 0.0;
+  };
+  auto cval = [&](int u, int c) -> double {
+    const int h = u >> 5, r = u & 31;
+    return (h < nch && r < w && c < nc) ? M[(long)(tops[h] + r) * k + cb + c] : 0.0;
+  };
+  const int r0 = RW * wave, li = lane & 15, lk = lane >> 4;
+  {
+    double vf[KS][2], cf[KS][2];
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      const int rr = r0 + 4 * t + lk;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        vf[t][i] = vval(rr, 16 * i + li);
+        cf[t][i] = cval(rr, 16 * i + li);
+      }
+    }
+    v4d acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+#pragma unroll
+    for (int t = 0; t < KS; ++t)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(vf[t][i], cf[t][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wp[wave][16 * i + lk + 4 * r][16 * j + li] = acc[i][j][r];
+  }
+  __syncthreads();
+  {
+    const int bi = wave >> 1, bj = wave & 1;
+    v4d a2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < kPanel / 4; ++t) {
+      const int l = 4 * t + lk, i = 16 * bi + li, c = 16 * bj + li;
+      const double tv = FORM ? T[i][l] : T[l][i];
+      const double w1 = (Wp[0][l][c] + Wp[1][l][c]) + (Wp[2][l][c] + Wp[3][l][c]);
+      a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(tv, w1, a2, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) W2[16 * bi + lk + 4 * r][16 * bj + li] = a2[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int rr0 = r0 + 16 * rb;
+    if ((rr0 >> 5) >= nch) break;
+    v4d u[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int t = 0; t < kPanel / 4; ++t) {
+      const double av = vval(rr0 + li, 4 * t + lk);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        u[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W2[4 * t + lk][16 * j + li], u[j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int uu = rr0 + lk + 4 * r, col = 16 * j + li;
+        const int h = uu >> 5, rw = uu & 31;
+        if (h < nch && rw < w && col < nc) {
+          double* pc = M + (long)(tops[h] + rw) * k + cb + col;
+          *pc = *pc - u[j][r];
+        }
+      }
   }
 }
 
