@@ -196,19 +196,20 @@ __global__ void k_col_sign(SignArgs sa) {
   }
 }
 
-// Projector factors for one bond (one block per bond):
+// Projector factors for one bond (blockIdx.y; the k x k elements spread
+// over the blocks of x):
 //   sinv_i = s_i^-1/2 if s_i > rtol * s_0 else 0    (i < keep)
 //   vs  = v diag(sg)            (k x k)   -> recycled X = X vs
 //   vsc = v[:, :keep] diag(sg * sinv)     -> P_l = A vsc
 //   usc = u[:, :keep] diag(sg * sinv)     -> P_r^T = B^T usc
 //   gap = s_keep / s_(keep+1) - 1 (or -1)
 __global__ void k_proj_prep(ProjPrepArgs pa) {
-  const int b = blockIdx.x;
+  const int b = blockIdx.y;
   const int k = pa.k, keep = pa.keep;
   const double* s = pa.s[b];
   const double* sg = pa.sg[b];
   const double s0 = s[0];
-  for (int i = threadIdx.x; i < k * k; i += blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k * k; i += gridDim.x * blockDim.x) {
     const int r = i / k, c = i % k;
     const double sgc = sg[c];
     if (pa.vs[b]) pa.vs[b][i] = pa.v[b][i] * sgc;
@@ -219,7 +220,7 @@ __global__ void k_proj_prep(ProjPrepArgs pa) {
       pa.usc[b][r * keep + c] = pa.u[b][i] * sgc * si;
     }
   }
-  if (threadIdx.x == 0 && pa.gap) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && pa.gap) {
     double g = -1.0;
     if (keep < k && s[keep] > 0.0) g = s[keep - 1] / s[keep] - 1.0;
     pa.gap[b] = g;
@@ -774,7 +775,8 @@ int elem_scale_cols(const SignArgs& sa, int count, hipStream_t s) {
 }
 
 int elem_proj_prep(const ProjPrepArgs& pa, int count, hipStream_t s) {
-  k_proj_prep<<<count, 256, 0, s>>>(pa);
+  const int blocks = std::max(1, std::min(64, (pa.k * pa.k + 255) / 256));
+  k_proj_prep<<<dim3(blocks, count), 256, 0, s>>>(pa);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }

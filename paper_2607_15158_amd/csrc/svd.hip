@@ -83,17 +83,27 @@ __global__ void svd_init(SvdArgs a) {
     for (int i = threadIdx.x; i < kMaxSweeps; i += blockDim.x) a.flags[mat * kMaxSweeps + i] = 0;
 }
 
-// Column norms, stable descending sort -> perm; Wp = Wc = A[:, perm].
+// Column norms, stable descending sort -> perm (the copy Wp = Wc = A[:, perm]
+// follows in svd_prep_copy).  Thread c sums column c down the rows, so
+// that each row is read by consecutive threads.
 __global__ __launch_bounds__(256) void svd_prep(SvdArgs a) {
   __shared__ double nrm[kSvdMaxN];
   __shared__ int perm[kSvdMaxN];
-  const int mat = blockIdx.x, n = a.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mat = blockIdx.x, n = a.n, tid = threadIdx.x;
   const double* A = a.Ain[mat];
-  for (int c = wave; c < n; c += 4) {
-    double ss = 0.0;
-    for (int r = lane; r < n; r += 64) ss += A[(size_t)r * n + c] * A[(size_t)r * n + c];
-    ss = wsum(ss);
-    if (lane == 0) nrm[c] = ss;
+  for (int c = tid; c < n; c += 256) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int r = 0;
+    for (; r + 3 < n; r += 4) {
+      const double x0 = A[(size_t)r * n + c], x1 = A[(size_t)(r + 1) * n + c];
+      const double x2 = A[(size_t)(r + 2) * n + c], x3 = A[(size_t)(r + 3) * n + c];
+      s0 += x0 * x0;
+      s1 += x1 * x1;
+      s2 += x2 * x2;
+      s3 += x3 * x3;
+    }
+    for (; r < n; ++r) s0 += A[(size_t)r * n + c] * A[(size_t)r * n + c];
+    nrm[c] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
   if (tid == 0) {
@@ -109,11 +119,18 @@ __global__ __launch_bounds__(256) void svd_prep(SvdArgs a) {
   __syncthreads();
   int* pg = a.perm + (size_t)mat * n;
   for (int c = tid; c < n; c += 256) pg[c] = perm[c];
+}
+
+// Wp = Wc = A[:, perm], over the blocks of x (matrix blockIdx.y).
+__global__ __launch_bounds__(256) void svd_prep_copy(SvdArgs a) {
+  const int mat = blockIdx.y, n = a.n;
+  const double* A = a.Ain[mat];
+  const int* pg = a.perm + (size_t)mat * n;
   double* Wp = a.Wp[mat];
   double* Wc = a.Wc[mat];
-  for (int i = tid; i < n * n; i += 256) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n * n; i += gridDim.x * 256) {
     const int r = i / n, j = i % n;
-    const double v = A[(size_t)r * n + perm[j]];
+    const double v = A[(size_t)r * n + pg[j]];
     Wp[i] = v;
     Wc[i] = v;
   }
@@ -544,6 +561,8 @@ int launch_svd(int count, const double* const* A, double* const* U, double* cons
     qptr[i] = a.Wp[i];
   }
   svd_prep<<<count, 256, 0, s>>>(a);
+  CTM_HIP_TRY(hipGetLastError());
+  svd_prep_copy<<<dim3(std::max(1, std::min(64, n * n / 256)), count), 256, 0, s>>>(a);
   CTM_HIP_TRY(hipGetLastError());
   int r = launch_qr(count, qptr, n, n, qws, s);
   if (r) return r;
