@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsictm.so")
-SOURCES = ["gemm.hip", "gemm_f32.hip", "qr.hip", "svd.hip", "elem.hip", "ctm.hip", "serve.hip",
+SOURCES = ["gemm.hip", "gemm_f32.hip", "qr.hip", "svd.hip", "elem.hip", "absorb.hip", "ctm.hip", "serve.hip",
            "vjp.hip", "cell.hip", "tape.hip", "cell_ad.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

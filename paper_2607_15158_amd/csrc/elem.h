@@ -82,6 +82,15 @@ int elem_norms(const NormArgs& na, int count, hipStream_t s);
 int elem_col_sign(const SignArgs& sa, int count, hipStream_t s);
 int elem_scale_cols(const SignArgs& sa, int count, hipStream_t s);
 int elem_proj_prep(const ProjPrepArgs& pa, int count, hipStream_t s);
+
+// Site absorption of the four enlarged corners through the single-layer
+// tensor A ([s][u][l][d][r], real): Ct_i[(x, o1), (y, o2)] =
+// sum_(p, q) W_i[(x, y), p, q] a_i[(p, q), (o1, o2)] with a_i the corner-i leg
+// permutation of the double layer, given per corner as the strides in A of
+// the legs (p, q, o1, o2).  float64; D^2 <= 36 and d D^2 <= 72.
+bool absorb_corner_fits(int D, int d);
+int launch_absorb_corners(const double* const* W, double* const* Ct, const double* A,
+                          const long (*legs)[4], int chi, int D, int d, hipStream_t s);
 // The first m singular triples of a dense SVD in descending order of the
 // singular value (stable): s_out[j], U_out[:, j], Vt_out[j, :] (row-major,
 // leading dimension n); perm holds n ints.
