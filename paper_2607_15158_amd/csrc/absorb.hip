@@ -35,11 +35,13 @@ constexpr int kAbsNB1 = (kAbsMaxN + 15) / 16;    // column blocks of the first p
 constexpr int kAbsNB2 = (kAbsMaxDl + 15) / 16;   // column blocks of the second
 
 struct AbsArgs {
-  const double* W[4];    // [chi^2][Dl][Dl] per corner
-  double* Ct[4];         // [(x, o1)][(y, o2)] per corner, N1 = chi Dl columns
+  const double* W[4];    // [nR][Dl][Dl] per problem
+  double* Ct[4];         // output per problem, element (R, o1, o2) at
+                         // (R / n2) sR1 + (R % n2) sR2 + o1 so1 + o2 so2
   const double* A;       // single-layer site tensor [s][u][l][d][r]
-  long sA[4][4];         // per corner: strides in A of the legs p, q, o1, o2
-  int chi, D, d, Dl;
+  long sA[4][4];         // per problem: strides in A of the legs p, q, o1, o2
+  long nR, sR1, sR2, so1, so2;
+  int n2, D, d, Dl;
 };
 
 __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
@@ -53,11 +55,10 @@ __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
   double* const Xs = Bx;
   const int corner = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int D = a.D, d = a.d, Dl = a.Dl, dDl = d * Dl, chi = a.chi;
-  const long nR = (long)chi * chi;
+  const int D = a.D, d = a.d, Dl = a.Dl, dDl = d * Dl;
+  const long nR = a.nR;
   const long R0 = (long)blockIdx.x * kAbsG;
   const int G = (int)min((long)kAbsG, nR - R0);
-  const long N1 = (long)chi * Dl;
   __shared__ int ko1[kAbsMaxDl], mo1[kAbsMaxDl], k1off[kAbsMaxDl], n1off[kAbsMaxN];
   __shared__ int ko2[kAbsMaxN], k2off[kAbsMaxN], n2off[kAbsMaxDl], mo2[kAbsMaxDl];
   const double* W = a.W[corner];
@@ -200,12 +201,13 @@ __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
         }
   }
   __syncthreads();
-  // Ct rows (x, o1) hold the D^2 columns (y, o2) of one pair contiguously
+  // for the corners, rows (x, o1) of Ct hold the D^2 columns (y, o2) of one
+  // pair contiguously
   double* Ct = a.Ct[corner];
   for (int i = tid; i < G * Dl * Dl; i += 256) {
     const int g = i / (Dl * Dl), rem = i % (Dl * Dl), o1 = rem / Dl, o2 = rem % Dl;
-    const long R = R0 + g, x = R / chi, y = R % chi;
-    Ct[(x * Dl + o1) * N1 + y * Dl + o2] = Ws[i];
+    const long R = R0 + g;
+    Ct[(R / a.n2) * a.sR1 + (R % a.n2) * a.sR2 + o1 * a.so1 + o2 * a.so2] = Ws[i];
   }
 }
 
@@ -215,28 +217,40 @@ bool absorb_corner_fits(int D, int d) {
   return d >= 1 && D >= 2 && D * D <= kAbsMaxDl && d * D * D <= kAbsMaxN;
 }
 
-int launch_absorb_corners(const double* const* W, double* const* Ct, const double* A,
-                          const long (*legs)[4], int chi, int D, int d, hipStream_t s) {
-  if (!absorb_corner_fits(D, d) || chi < 1) {
-    set_thread_error("single-layer corner absorption: D, d outside its LDS tiling");
+int launch_absorb(const double* const* W, double* const* out, const double* A,
+                  const long (*legs)[4], long nR, int n2, const long* ostr, int D, int d,
+                  hipStream_t s) {
+  if (!absorb_corner_fits(D, d) || nR < 1 || n2 < 1) {
+    set_thread_error("single-layer absorption: D, d outside its LDS tiling");
     return 1;
   }
   AbsArgs a{};
   for (int i = 0; i < 4; ++i) {
     a.W[i] = W[i];
-    a.Ct[i] = Ct[i];
+    a.Ct[i] = out[i];
     for (int j = 0; j < 4; ++j) a.sA[i][j] = legs[i][j];
   }
   a.A = A;
-  a.chi = chi;
+  a.nR = nR;
+  a.n2 = n2;
+  a.sR1 = ostr[0];
+  a.sR2 = ostr[1];
+  a.so1 = ostr[2];
+  a.so2 = ostr[3];
   a.D = D;
   a.d = d;
   a.Dl = D * D;
-  const long nR = (long)chi * chi;
   dim3 grid((unsigned)((nR + kAbsG - 1) / kAbsG), 4);
   k_absorb_corner<<<grid, 256, 0, s>>>(a);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
+}
+
+int launch_absorb_corners(const double* const* W, double* const* Ct, const double* A,
+                          const long (*legs)[4], int chi, int D, int d, hipStream_t s) {
+  const long Dl = (long)D * D, N1 = (long)chi * Dl;
+  const long ostr[4] = {Dl * N1, Dl, N1, 1};
+  return launch_absorb(W, Ct, A, legs, (long)chi * chi, chi, ostr, D, d, s);
 }
 
 }  // namespace sictm

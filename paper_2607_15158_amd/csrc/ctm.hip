@@ -1024,8 +1024,39 @@ int renormalize_edges(ctm_ctx* c, int keep) {
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
   }
-  // Z2[(b, l), d, g'] = Z1[(b, g'), (r, u)] apr_(j+1)[(r, u), (l, d)]
-  {
+  // Z2[(b, l), d, g'] = Z1[(b, g'), (r, u)] apr_(j+1)[(r, u), (l, d)], through
+  // the single-layer tensor where it applies (as the corners' absorption)
+  if (c->cp == DT::F64 && c->d > 0 && absorb_corner_fits(c->D, c->d)) {
+    const long Dd = c->D, su = Dd * Dd * Dd, sl = Dd * Dd, sd = Dd, sr = 1;
+    const long cl[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
+    struct Ptrs { const double* W[4]; double* out[4]; long legs[4][4]; long ostr[4]; } pp;
+    for (int j = 0; j < 4; ++j) {
+      const int i = (j + 1) % 4;
+      pp.legs[j][0] = cl[i][1];
+      pp.legs[j][1] = cl[i][0];
+      pp.legs[j][2] = cl[i][2];
+      pp.legs[j][3] = cl[i][3];
+      pp.W[j] = c->S1[j];
+      pp.out[j] = c->S2[j];
+    }
+    pp.ostr[0] = (long)Dl * Dl * xp;
+    pp.ostr[1] = 1;
+    pp.ostr[2] = (long)Dl * xp;
+    pp.ostr[3] = xp;
+    const long nR = (long)x * xp;
+    const double* A = c->A_site;
+    const int Di = c->D, d = c->d;
+    if (c->rec) {
+      c->rec->push_back(BatchOp{false, GemmBatch{}, [=](hipStream_t st) {
+                                  return launch_absorb(pp.W, pp.out, A, pp.legs, nR, xp, pp.ostr,
+                                                       Di, d, st);
+                                }});
+    } else {
+      ProfScope ps(c, PC_RENORM, 4.0 * 4.0 * (double)nR * Dl * Dl * Dl * d);
+      if (launch_absorb(pp.W, pp.out, A, pp.legs, nR, xp, pp.ostr, Di, d, c->st))
+        return fail(c, CTM_E_DEVICE, thread_error());
+    }
+  } else {
     GemmBatch g = gemm_rowmajor(4, x * xp, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
     g.cdiv_m = xp;
     g.cs_m1 = (long)Dl * Dl * xp;
