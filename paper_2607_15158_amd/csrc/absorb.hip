@@ -44,6 +44,9 @@ struct AbsArgs {
   int n2, D, d, Dl;
 };
 
+// DT: the bond dimension D as a compile-time constant (every index division
+// by D or D^2 becomes a multiply).
+template <int DT>
 __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
   // LDS: one buffer holds in turn the W rows [G][Dl][Dl], X [G * Dl][dDl]
   // and the corner block in Ct's order; A [s][p][q][o1][o2] (62 KB in all:
@@ -55,16 +58,22 @@ __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
   double* const Xs = Bx;
   const int corner = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int D = a.D, d = a.d, Dl = a.Dl, dDl = d * Dl;
+  constexpr int D = DT, Dl = DT * DT;
+  const int d = a.d, dDl = d * Dl;
   const long nR = a.nR;
   const long R0 = (long)blockIdx.x * kAbsG;
   const int G = (int)min((long)kAbsG, nR - R0);
+  __shared__ long rowoff[kAbsG];   // output offset of pair g
+  if (tid < G) {
+    const long R = R0 + tid;
+    rowoff[tid] = (R / a.n2) * a.sR1 + (R % a.n2) * a.sR2;
+  }
   __shared__ int ko1[kAbsMaxDl], mo1[kAbsMaxDl], k1off[kAbsMaxDl], n1off[kAbsMaxN];
   __shared__ int ko2[kAbsMaxN], k2off[kAbsMaxN], n2off[kAbsMaxDl], mo2[kAbsMaxDl];
   const double* W = a.W[corner];
   for (long i = tid; i < (long)G * Dl * Dl; i += 256) Ws[i] = W[R0 * Dl * Dl + i];
   const long* st = a.sA[corner];
-  const int D2 = D * D, D3 = D2 * D, D4 = D3 * D;
+  constexpr int D2 = D * D, D3 = D2 * D, D4 = D3 * D;
   for (int i = tid; i < d * D4; i += 256) {
     int rem = i;
     const int o2 = rem % D; rem /= D;
@@ -206,8 +215,7 @@ __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
   double* Ct = a.Ct[corner];
   for (int i = tid; i < G * Dl * Dl; i += 256) {
     const int g = i / (Dl * Dl), rem = i % (Dl * Dl), o1 = rem / Dl, o2 = rem % Dl;
-    const long R = R0 + g;
-    Ct[(R / a.n2) * a.sR1 + (R % a.n2) * a.sR2 + o1 * a.so1 + o2 * a.so2] = Ws[i];
+    Ct[rowoff[g] + o1 * a.so1 + o2 * a.so2] = Ws[i];
   }
 }
 
@@ -241,7 +249,13 @@ int launch_absorb(const double* const* W, double* const* out, const double* A,
   a.d = d;
   a.Dl = D * D;
   dim3 grid((unsigned)((nR + kAbsG - 1) / kAbsG), 4);
-  k_absorb_corner<<<grid, 256, 0, s>>>(a);
+  switch (D) {
+    case 2: k_absorb_corner<2><<<grid, 256, 0, s>>>(a); break;
+    case 3: k_absorb_corner<3><<<grid, 256, 0, s>>>(a); break;
+    case 4: k_absorb_corner<4><<<grid, 256, 0, s>>>(a); break;
+    case 5: k_absorb_corner<5><<<grid, 256, 0, s>>>(a); break;
+    default: k_absorb_corner<6><<<grid, 256, 0, s>>>(a); break;
+  }
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }
