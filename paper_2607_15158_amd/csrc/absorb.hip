@@ -34,12 +34,14 @@ constexpr int kAbsRB = ((kAbsG * kAbsMaxDl + 15) / 16 + 3) / 4;   // 16-row bloc
 constexpr int kAbsNB1 = (kAbsMaxN + 15) / 16;    // column blocks of the first product
 constexpr int kAbsNB2 = (kAbsMaxDl + 15) / 16;   // column blocks of the second
 
+constexpr int kAbsMaxProb = 8;
+
 struct AbsArgs {
-  const double* W[4];    // [nR][Dl][Dl] per problem
-  double* Ct[4];         // output per problem, element (R, o1, o2) at
-                         // (R / n2) sR1 + (R % n2) sR2 + o1 so1 + o2 so2
-  const double* A;       // single-layer site tensor [s][u][l][d][r]
-  long sA[4][4];         // per problem: strides in A of the legs p, q, o1, o2
+  const double* W[kAbsMaxProb];    // [nR][Dl][Dl] per problem
+  double* Ct[kAbsMaxProb];         // output per problem, element (R, o1, o2) at
+                                   // (R / n2) sR1 + (R % n2) sR2 + o1 so1 + o2 so2
+  const double* A[kAbsMaxProb];    // single-layer site tensor [s][u][l][d][r] per problem
+  long sA[kAbsMaxProb][4];         // per problem: strides in A of the legs p, q, o1, o2
   long nR, sR1, sR2, so1, so2;
   int n2, D, d, Dl;
 };
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
     const int q = rem % D; rem /= D;
     const int p = rem % D;
     const int s = rem / D;
-    As[i] = a.A[(long)s * D4 + p * st[0] + q * st[1] + o1 * st[2] + o2 * st[3]];
+    As[i] = a.A[corner][(long)s * D4 + p * st[0] + q * st[1] + o1 * st[2] + o2 * st[3]];
   }
   for (int i = tid; i < Dl; i += 256) {
     const int hi = i / D, lo = i % D;
@@ -225,20 +227,20 @@ bool absorb_corner_fits(int D, int d) {
   return d >= 1 && D >= 2 && D * D <= kAbsMaxDl && d * D * D <= kAbsMaxN;
 }
 
-int launch_absorb(const double* const* W, double* const* out, const double* A,
-                  const long (*legs)[4], long nR, int n2, const long* ostr, int D, int d,
-                  hipStream_t s) {
-  if (!absorb_corner_fits(D, d) || nR < 1 || n2 < 1) {
-    set_thread_error("single-layer absorption: D, d outside its LDS tiling");
+int launch_absorb(int count, const double* const* W, double* const* out,
+                  const double* const* A, const long (*legs)[4], long nR, int n2,
+                  const long* ostr, int D, int d, hipStream_t s) {
+  if (!absorb_corner_fits(D, d) || nR < 1 || n2 < 1 || count < 1 || count > kAbsMaxProb) {
+    set_thread_error("single-layer absorption: D, d or the problem count outside its tiling");
     return 1;
   }
   AbsArgs a{};
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < count; ++i) {
     a.W[i] = W[i];
     a.Ct[i] = out[i];
+    a.A[i] = A[i];
     for (int j = 0; j < 4; ++j) a.sA[i][j] = legs[i][j];
   }
-  a.A = A;
   a.nR = nR;
   a.n2 = n2;
   a.sR1 = ostr[0];
@@ -248,7 +250,7 @@ int launch_absorb(const double* const* W, double* const* out, const double* A,
   a.D = D;
   a.d = d;
   a.Dl = D * D;
-  dim3 grid((unsigned)((nR + kAbsG - 1) / kAbsG), 4);
+  dim3 grid((unsigned)((nR + kAbsG - 1) / kAbsG), count);
   switch (D) {
     case 2: k_absorb_corner<2><<<grid, 256, 0, s>>>(a); break;
     case 3: k_absorb_corner<3><<<grid, 256, 0, s>>>(a); break;
@@ -264,7 +266,8 @@ int launch_absorb_corners(const double* const* W, double* const* Ct, const doubl
                           const long (*legs)[4], int chi, int D, int d, hipStream_t s) {
   const long Dl = (long)D * D, N1 = (long)chi * Dl;
   const long ostr[4] = {Dl * N1, Dl, N1, 1};
-  return launch_absorb(W, Ct, A, legs, (long)chi * chi, chi, ostr, D, d, s);
+  const double* As[4] = {A, A, A, A};
+  return launch_absorb(4, W, Ct, As, legs, (long)chi * chi, chi, ostr, D, d, s);
 }
 
 }  // namespace sictm

@@ -1048,12 +1048,14 @@ int renormalize_edges(ctm_ctx* c, int keep) {
     const int Di = c->D, d = c->d;
     if (c->rec) {
       c->rec->push_back(BatchOp{false, GemmBatch{}, [=](hipStream_t st) {
-                                  return launch_absorb(pp.W, pp.out, A, pp.legs, nR, xp, pp.ostr,
-                                                       Di, d, st);
+                                  const double* As[4] = {A, A, A, A};
+                                  return launch_absorb(4, pp.W, pp.out, As, pp.legs, nR, xp,
+                                                       pp.ostr, Di, d, st);
                                 }});
     } else {
       ProfScope ps(c, PC_RENORM, 4.0 * 4.0 * (double)nR * Dl * Dl * Dl * d);
-      if (launch_absorb(pp.W, pp.out, A, pp.legs, nR, xp, pp.ostr, Di, d, c->st))
+      const double* As[4] = {A, A, A, A};
+      if (launch_absorb(4, pp.W, pp.out, As, pp.legs, nR, xp, pp.ostr, Di, d, c->st))
         return fail(c, CTM_E_DEVICE, thread_error());
     }
   } else {

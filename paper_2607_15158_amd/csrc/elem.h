@@ -91,12 +91,13 @@ int elem_proj_prep(const ProjPrepArgs& pa, int count, hipStream_t s);
 bool absorb_corner_fits(int D, int d);
 int launch_absorb_corners(const double* const* W, double* const* Ct, const double* A,
                           const long (*legs)[4], int chi, int D, int d, hipStream_t s);
-// The same absorption for four problems of nR rows (W_i [nR][Dl][Dl]) with
-// output element (R, o1, o2) at (R / n2) ostr[0] + (R % n2) ostr[1] +
-// o1 ostr[2] + o2 ostr[3] (the edges' Z2 = Z1 a of the renormalisation).
-int launch_absorb(const double* const* W, double* const* out, const double* A,
-                  const long (*legs)[4], long nR, int n2, const long* ostr, int D, int d,
-                  hipStream_t s);
+// The same absorption for 1..8 problems of nR rows (W_i [nR][Dl][Dl], site
+// tensor A_i) with output element (R, o1, o2) at (R / n2) ostr[0] +
+// (R % n2) ostr[1] + o1 ostr[2] + o2 ostr[3] (the edges' Z2 = Z1 a of the
+// renormalisation, the unit cell's corners).
+int launch_absorb(int count, const double* const* W, double* const* out,
+                  const double* const* A, const long (*legs)[4], long nR, int n2,
+                  const long* ostr, int D, int d, hipStream_t s);
 // The first m singular triples of a dense SVD in descending order of the
 // singular value (stable): s_out[j], U_out[:, j], Vt_out[j, :] (row-major,
 // leading dimension n); perm holds n ints.
