@@ -11,12 +11,13 @@
 //   Ct[(x, o1k o1b), (y, o2k o2b)]   = sum_(pb, qb, s) X[...] A[s, pb, qb, o1b, o2b]
 // the same tensor for 4 d chi^2 D^6 flops (9x less at D = 6, d = 2).
 //
-// One workgroup takes kAbsG = 2 consecutive (x, y) pairs of one corner: their W
-// rows and the corner's leg permutation of A are staged in LDS, the first
-// product (rows (g, pb, qb), K = D^2, N = d D^2) writes X to LDS, the second
-// (rows (g, o1k, o2k), K = d D^2, N = D^2) writes the corner straight to its
-// place in Ct (through LDS, so that each pair's D^2 columns of a row of Ct
-// are written contiguously).  Both run on v_mfma_f64_16x16x4; the index
+// One workgroup takes kAbsG = 2 consecutive (x, y) pairs of one problem:
+// their W rows and the problem's leg permutation of A are staged in LDS, the
+// first product (rows (g, pb, qb), K = D^2, N = d D^2) writes X to LDS, the
+// second (rows (g, o1k, o2k), K = d D^2, N = D^2) stages the output block in
+// LDS, from where it is written through the output's index map (for the
+// corners, each pair's D^2 columns of a row of Ct contiguously).  The edges'
+// absorption Z2 = Z1 a has the same form with rows (b, g').  Both run on v_mfma_f64_16x16x4; the index
 // groupings of every operand are additive, so per-dimension offset tables in
 // LDS turn each fragment into a per-lane base plus one table entry per
 // k-step.
@@ -100,8 +101,8 @@ __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
     k2off[i] = s * D4 + (r / D) * D3 + (r % D) * D2;          // k = (pb, qb, s) -> A
   }
   __syncthreads();
-  // Wavefront w takes the 16-row blocks w, w + 4, w + 8 of both products and
-  // every column block, so each k-step's fragments feed up to 15 (then 9)
+  // Wavefront w takes the 16-row blocks w and w + 4 of both products and
+  // every column block, so each k-step's fragments feed up to 10 (then 6)
   // independent accumulators.
   const int M = G * Dl;
   const int mb = (M + 15) >> 4, nb1 = (dDl + 15) >> 4, nb2 = (Dl + 15) >> 4;
