@@ -1646,8 +1646,11 @@ bool launch_f32_db(const GemmBatch& g, hipStream_t s, int* rc) {
 // the 96 x 160 tile, wider N the 128 x 144 tile (144 divides the D^4 = 1296
 // columns of the double-layer absorptions at D = 6).
 bool launch_f64_db(const GemmBatch& g, hipStream_t s, int* rc) {
-  // short K (a few slices per tile) gains nothing from the double buffer
-  if (g.K < 512 || g.M < 256) return false;
+  // short K (a few slices per tile) gains nothing from the double buffer,
+  // except on the wide products with many rows (the corner stems, K = chi),
+  // which the 256 x 144 tile covers with fewer, fuller workgroups
+  const bool wide = g.K >= 128 && g.N > 160 && (long)g.M * g.count * g.nbatch >= 16384;
+  if ((g.K < 512 && !wide) || g.M < 256) return false;
   // odd leading dimensions or batch strides: the same tiles with operand
   // pairs loaded one element at a time
   if (!skinny_ok(g)) {
