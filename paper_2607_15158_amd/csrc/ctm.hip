@@ -1001,22 +1001,19 @@ int renormalize_edges(ctm_ctx* c, int keep) {
   const int x = c->chi_env, Dl = c->Dl, xp = keep;
   const int nxt = 1 - c->cur;
   double* const* T = c->T[c->cur];
-  // Z1[(b, g'), (r, u)] = sum_g T_j[(b, u), g] P_l[(g, r), g']   (batched over r).
-  // u, the row leg of each product, is Z1's unit-stride leg, so that the rows
-  // of a tile are stored contiguously; the next product contracts (r, u)
-  // against the correspondingly swapped copy of the site tensor.
+  // Z1[(b, g'), (r, u)] = sum_g T_j[(b, u), g] P_l[(g, r), g'], one product
+  // per edge with columns (r, g') (P_l read as a x by Dl xp matrix), so that
+  // it has the wide shape of the corner stems.  u, the row leg, is Z1's
+  // unit-stride leg, so that the rows of a tile are stored contiguously; the
+  // next product contracts (r, u) against the site tensor.
   {
-    GemmBatch g = gemm_rowmajor(4, x * Dl, xp, x, x, (long)Dl * xp, 0);
+    GemmBatch g = gemm_rowmajor(4, x * Dl, Dl * xp, x, x, (long)Dl * xp, 0);
     g.cdiv_m = Dl;
     g.cs_m1 = (long)xp * Dl * Dl;
     g.cs_m0 = 1;
-    g.cdiv_n = 1 << 30;
-    g.cs_n1 = 0;
+    g.cdiv_n = xp;
+    g.cs_n1 = Dl;
     g.cs_n0 = (long)Dl * Dl;
-    g.nbatch = Dl;
-    g.a_bs = 0;
-    g.b_bs = xp;
-    g.c_bs = Dl;
     for (int j = 0; j < 4; ++j) {
       g.A[j] = T[j];
       g.B[j] = c->Pl[j];
