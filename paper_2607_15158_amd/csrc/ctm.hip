@@ -1021,8 +1021,11 @@ int renormalize_edges(ctm_ctx* c, int keep) {
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, DT::F64, DT::F64));
   }
-  // Z2[(b, l), d, g'] = Z1[(b, g'), (r, u)] apr_(j+1)[(r, u), (l, d)], through
-  // the single-layer tensor where it applies (as the corners' absorption)
+  // Z2[(b, l), g', d] = Z1[(b, g'), (r, u)] apr_(j+1)[(r, u), (l, d)], through
+  // the single-layer tensor where it applies (as the corners' absorption); d
+  // is Z2's unit-stride leg, so that each (b, g') row block is written in
+  // runs of D^2
+
   if (c->cp == DT::F64 && c->d > 0 && absorb_corner_fits(c->D, c->d)) {
     const long Dd = c->D, su = Dd * Dd * Dd, sl = Dd * Dd, sd = Dd, sr = 1;
     const long cl[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
@@ -1037,9 +1040,9 @@ int renormalize_edges(ctm_ctx* c, int keep) {
       pp.out[j] = c->S2[j];
     }
     pp.ostr[0] = (long)Dl * Dl * xp;
-    pp.ostr[1] = 1;
+    pp.ostr[1] = Dl;
     pp.ostr[2] = (long)Dl * xp;
-    pp.ostr[3] = xp;
+    pp.ostr[3] = 1;
     const long nR = (long)x * xp;
     const double* A = c->A_site;
     const int Di = c->D, d = c->d;
@@ -1059,10 +1062,10 @@ int renormalize_edges(ctm_ctx* c, int keep) {
     GemmBatch g = gemm_rowmajor(4, x * xp, Dl * Dl, Dl * Dl, (long)Dl * Dl, (long)Dl * Dl, 0);
     g.cdiv_m = xp;
     g.cs_m1 = (long)Dl * Dl * xp;
-    g.cs_m0 = 1;
+    g.cs_m0 = Dl;
     g.cdiv_n = Dl;
     g.cs_n1 = (long)Dl * xp;
-    g.cs_n0 = xp;
+    g.cs_n0 = 1;
     for (int j = 0; j < 4; ++j) {
       g.A[j] = c->S1[j];
       g.B[j] = c->apr[(j + 1) % 4];
@@ -1070,13 +1073,13 @@ int renormalize_edges(ctm_ctx* c, int keep) {
     }
     TRY(run_gemm(c, PC_RENORM, g, DT::F64, c->cp, DT::F64));
   }
-  // T'[b', (d, g')] = sum_(b,l) P_r^T[(b, l), b'] Z2[(b, l), (d, g')]: one
-  // GEMM per edge, computed as its transpose (rows (d, g'), N = xp columns b'),
-  // the tall-skinny shape of the double-buffered kernel; the output map
-  // writes it back in T' order
+  // T'[b', (d, g')] = sum_(b,l) P_r^T[(b, l), b'] Z2[(b, l), (g', d)]: one
+  // GEMM per edge, computed as its transpose (rows (g', d), N = xp columns
+  // b'), the tall-skinny shape of the split kernel; the output map writes it
+  // back in T' order
   {
     GemmBatch g = gemm_rowmajor(4, Dl * xp, xp, x * Dl, (long)Dl * xp, xp, 0);
-    set_map(g, 1 << 30, 0, 1, 1 << 30, 0, (long)Dl * xp);
+    set_map(g, Dl, 1, xp, 1 << 30, 0, (long)Dl * xp);
     for (int j = 0; j < 4; ++j) {
       g.A[j] = c->S2[j];
       g.transA[j] = 1;
