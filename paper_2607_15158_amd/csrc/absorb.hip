@@ -39,7 +39,7 @@ constexpr int kAbsMaxProb = 8;
 
 struct AbsArgs {
   const double* W[kAbsMaxProb];    // [nR][Dl][Dl] per problem
-  double* Ct[kAbsMaxProb];         // output per problem, element (R, o1, o2) at
+  void* Ct[kAbsMaxProb];           // output (TO) per problem, element (R, o1, o2) at
                                    // (R / n2) sR1 + (R % n2) sR2 + o1 so1 + o2 so2
   const double* A[kAbsMaxProb];    // single-layer site tensor [s][u][l][d][r] per problem
   long sA[kAbsMaxProb][4];         // per problem: strides in A of the legs p, q, o1, o2
@@ -49,7 +49,7 @@ struct AbsArgs {
 
 // DT: the bond dimension D as a compile-time constant (every index division
 // by D or D^2 becomes a multiply).
-template <int DT>
+template <int DT, typename TO>
 __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
   // LDS: one buffer holds in turn the W rows [G][Dl][Dl], X [G * Dl][dDl]
   // and the corner block in Ct's order; A [s][p][q][o1][o2] (62 KB in all:
@@ -215,10 +215,10 @@ __global__ __launch_bounds__(256) void k_absorb_corner(AbsArgs a) {
   __syncthreads();
   // for the corners, rows (x, o1) of Ct hold the D^2 columns (y, o2) of one
   // pair contiguously
-  double* Ct = a.Ct[corner];
+  TO* Ct = (TO*)a.Ct[corner];
   for (int i = tid; i < G * Dl * Dl; i += 256) {
     const int g = i / (Dl * Dl), rem = i % (Dl * Dl), o1 = rem / Dl, o2 = rem % Dl;
-    Ct[rowoff[g] + o1 * a.so1 + o2 * a.so2] = Ws[i];
+    Ct[rowoff[g] + o1 * a.so1 + o2 * a.so2] = (TO)Ws[i];
   }
 }
 
@@ -228,7 +228,18 @@ bool absorb_corner_fits(int D, int d) {
   return d >= 1 && D >= 2 && D * D <= kAbsMaxDl && d * D * D <= kAbsMaxN;
 }
 
-int launch_absorb(int count, const double* const* W, double* const* out,
+template <typename TO>
+static void launch_absorb_t(const AbsArgs& a, dim3 grid, int D, hipStream_t s) {
+  switch (D) {
+    case 2: k_absorb_corner<2, TO><<<grid, 256, 0, s>>>(a); break;
+    case 3: k_absorb_corner<3, TO><<<grid, 256, 0, s>>>(a); break;
+    case 4: k_absorb_corner<4, TO><<<grid, 256, 0, s>>>(a); break;
+    case 5: k_absorb_corner<5, TO><<<grid, 256, 0, s>>>(a); break;
+    default: k_absorb_corner<6, TO><<<grid, 256, 0, s>>>(a); break;
+  }
+}
+
+int launch_absorb(int count, const double* const* W, void* const* out, bool out_f32,
                   const double* const* A, const long (*legs)[4], long nR, int n2,
                   const long* ostr, int D, int d, hipStream_t s) {
   if (!absorb_corner_fits(D, d) || nR < 1 || n2 < 1 || count < 1 || count > kAbsMaxProb) {
@@ -252,23 +263,18 @@ int launch_absorb(int count, const double* const* W, double* const* out,
   a.d = d;
   a.Dl = D * D;
   dim3 grid((unsigned)((nR + kAbsG - 1) / kAbsG), count);
-  switch (D) {
-    case 2: k_absorb_corner<2><<<grid, 256, 0, s>>>(a); break;
-    case 3: k_absorb_corner<3><<<grid, 256, 0, s>>>(a); break;
-    case 4: k_absorb_corner<4><<<grid, 256, 0, s>>>(a); break;
-    case 5: k_absorb_corner<5><<<grid, 256, 0, s>>>(a); break;
-    default: k_absorb_corner<6><<<grid, 256, 0, s>>>(a); break;
-  }
+  if (out_f32) launch_absorb_t<float>(a, grid, D, s);
+  else launch_absorb_t<double>(a, grid, D, s);
   CTM_HIP_TRY(hipGetLastError());
   return 0;
 }
 
-int launch_absorb_corners(const double* const* W, double* const* Ct, const double* A,
+int launch_absorb_corners(const double* const* W, void* const* Ct, bool out_f32, const double* A,
                           const long (*legs)[4], int chi, int D, int d, hipStream_t s) {
   const long Dl = (long)D * D, N1 = (long)chi * Dl;
   const long ostr[4] = {Dl * N1, Dl, N1, 1};
   const double* As[4] = {A, A, A, A};
-  return launch_absorb(4, W, Ct, As, legs, (long)chi * chi, chi, ostr, D, d, s);
+  return launch_absorb(4, W, Ct, out_f32, As, legs, (long)chi * chi, chi, ostr, D, d, s);
 }
 
 }  // namespace sictm

@@ -566,32 +566,38 @@ GemmBatch corner_site_gemm(ctm_ctx* c, int count) {
 
 int build_corners(ctm_ctx* c) {
   TRY(corner_stems(c, PC_CORNER));
-  if (c->cp == DT::F64 && c->d > 0 && absorb_corner_fits(c->D, c->d)) {
+  if ((c->cp == DT::F64 || (c->cp == DT::F32 && !c->split)) && c->d > 0 &&
+      absorb_corner_fits(c->D, c->d)) {
     // the single-layer absorption (ket layer, then bra layer with the
-    // physical index): the same corners for a ninth of the flops at D = 6
+    // physical index): the same corners for a ninth of the flops at D = 6,
+    // in float64 arithmetic (also in the float32 mode, where it is faster
+    // than the float32 double-layer product; the corners are stored in the
+    // mode's type)
+    const bool f32 = c->cp == DT::F32;
     const long D = c->D, su = D * D * D, sl = D * D, sd = D, sr = 1;
     const long legs[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
     const double* W[4];
-    double* Ct[4];
+    void* Ct[4];
     for (int i = 0; i < 4; ++i) {
       W[i] = c->S1[i];
-      Ct[i] = (double*)c->Ct[i];
+      Ct[i] = c->Ct[i];
     }
     const double* A = c->A_site;
     const int x = c->chi_env, Dd = c->D, d = c->d;
     if (c->rec) {
-      struct Ptrs { const double* W[4]; double* Ct[4]; long legs[4][4]; } pp;
+      struct Ptrs { const double* W[4]; void* Ct[4]; long legs[4][4]; } pp;
       std::memcpy(pp.W, W, sizeof(W));
       std::memcpy(pp.Ct, Ct, sizeof(Ct));
       std::memcpy(pp.legs, legs, sizeof(legs));
       c->rec->push_back(BatchOp{false, GemmBatch{}, [=](hipStream_t st) {
-                                  return launch_absorb_corners(pp.W, pp.Ct, A, pp.legs, x, Dd, d, st);
+                                  return launch_absorb_corners(pp.W, pp.Ct, f32, A, pp.legs, x, Dd,
+                                                               d, st);
                                 }});
       return 0;
     }
     const double Dl = (double)c->Dl;
     ProfScope ps(c, PC_CORNER, 4.0 * 4.0 * x * x * Dl * Dl * Dl * d);
-    const int r = launch_absorb_corners(W, Ct, A, legs, x, Dd, d, c->st);
+    const int r = launch_absorb_corners(W, Ct, f32, A, legs, x, Dd, d, c->st);
     if (r) return fail(c, CTM_E_DEVICE, thread_error());
     return 0;
   }
@@ -1025,11 +1031,11 @@ int renormalize_edges(ctm_ctx* c, int keep) {
   // the single-layer tensor where it applies (as the corners' absorption); d
   // is Z2's unit-stride leg, so that each (b, g') row block is written in
   // runs of D^2
-
-  if (c->cp == DT::F64 && c->d > 0 && absorb_corner_fits(c->D, c->d)) {
+  if ((c->cp == DT::F64 || (c->cp == DT::F32 && !c->split)) && c->d > 0 &&
+      absorb_corner_fits(c->D, c->d)) {
     const long Dd = c->D, su = Dd * Dd * Dd, sl = Dd * Dd, sd = Dd, sr = 1;
     const long cl[4][4] = {{sl, su, sd, sr}, {su, sr, sl, sd}, {sr, sd, su, sl}, {sd, sl, sr, su}};
-    struct Ptrs { const double* W[4]; double* out[4]; long legs[4][4]; long ostr[4]; } pp;
+    struct Ptrs { const double* W[4]; void* out[4]; long legs[4][4]; long ostr[4]; } pp;
     for (int j = 0; j < 4; ++j) {
       const int i = (j + 1) % 4;
       pp.legs[j][0] = cl[i][1];
@@ -1049,13 +1055,13 @@ int renormalize_edges(ctm_ctx* c, int keep) {
     if (c->rec) {
       c->rec->push_back(BatchOp{false, GemmBatch{}, [=](hipStream_t st) {
                                   const double* As[4] = {A, A, A, A};
-                                  return launch_absorb(4, pp.W, pp.out, As, pp.legs, nR, xp,
+                                  return launch_absorb(4, pp.W, pp.out, false, As, pp.legs, nR, xp,
                                                        pp.ostr, Di, d, st);
                                 }});
     } else {
       ProfScope ps(c, PC_RENORM, 4.0 * 4.0 * (double)nR * Dl * Dl * Dl * d);
       const double* As[4] = {A, A, A, A};
-      if (launch_absorb(4, pp.W, pp.out, As, pp.legs, nR, xp, pp.ostr, Di, d, c->st))
+      if (launch_absorb(4, pp.W, pp.out, false, As, pp.legs, nR, xp, pp.ostr, Di, d, c->st))
         return fail(c, CTM_E_DEVICE, thread_error());
     }
   } else {

@@ -87,15 +87,16 @@ int elem_proj_prep(const ProjPrepArgs& pa, int count, hipStream_t s);
 // tensor A ([s][u][l][d][r], real): Ct_i[(x, o1), (y, o2)] =
 // sum_(p, q) W_i[(x, y), p, q] a_i[(p, q), (o1, o2)] with a_i the corner-i leg
 // permutation of the double layer, given per corner as the strides in A of
-// the legs (p, q, o1, o2).  float64; D^2 <= 36 and d D^2 <= 72.
+// the legs (p, q, o1, o2).  float64 arithmetic, output in float64 or (out_f32)
+// float32; D^2 <= 36 and d D^2 <= 72.
 bool absorb_corner_fits(int D, int d);
-int launch_absorb_corners(const double* const* W, double* const* Ct, const double* A,
+int launch_absorb_corners(const double* const* W, void* const* Ct, bool out_f32, const double* A,
                           const long (*legs)[4], int chi, int D, int d, hipStream_t s);
 // The same absorption for 1..8 problems of nR rows (W_i [nR][Dl][Dl], site
 // tensor A_i) with output element (R, o1, o2) at (R / n2) ostr[0] +
 // (R % n2) ostr[1] + o1 ostr[2] + o2 ostr[3] (the edges' Z2 = Z1 a of the
 // renormalisation, the unit cell's corners).
-int launch_absorb(int count, const double* const* W, double* const* out,
+int launch_absorb(int count, const double* const* W, void* const* out, bool out_f32,
                   const double* const* A, const long (*legs)[4], long nR, int n2,
                   const long* ostr, int D, int d, hipStream_t s);
 // The first m singular triples of a dense SVD in descending order of the
