@@ -15,12 +15,15 @@
 // Block-pair parallel ordering: the columns are cut into blocks of kBlk; an
 // outer sweep pairs the blocks in a round-robin tournament, one launch per
 // round, one workgroup per block pair and matrix.  The workgroup loads the
-// 2 kBlk columns of U into LDS and rotates all pairs among them once, in
-// 2 kBlk - 1 inner rounds of kBlk disjoint pairs, 16 lanes per pair (rows
-// spread over the lanes, dot products reduced by DPP row sums); the
+// 2 kBlk columns of U into LDS and rotates the pairs across the two blocks
+// in kBlk inner steps of kBlk disjoint pairs (in the sweep's first round,
+// where every block is visited once, the pairs within each block first, in
+// kBlk - 1 more steps), so that every column pair meets once per sweep;
+// 16 lanes per pair (rows spread over the lanes, dot products reduced by
+// DPP row sums); the
 // rotations of the visit are accumulated in a 2 kBlk x 2 kBlk matrix W and
 // applied to the right vectors once at the end (V_cols <- V_cols W).
-// Every column pair meets in every outer sweep; a per-matrix flag records
+// A per-matrix flag records
 // whether a sweep rotated anything, and later launches return at once after
 // a sweep without rotations.  Columns that end numerically zero
 // (rank-deficient input) are replaced by an orthonormal completion so that
@@ -225,10 +228,24 @@ __device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int rou
   // not change the result above roundoff; they are completed at the end
   const double negl = 1e-30 * a.fro2[mat];
   int my_rot = 0;
-  for (int rr = 0; rr < inner * (kC - 1); ++rr) {
-    const int r = rr % (kC - 1);
-    const int ca = tour(grp, r, kC), cb = tour(kC - 1 - grp, r, kC);
-    const int p = min(ca, cb), q = max(ca, cb);
+  // the sweep's first round (every block in exactly one pair) also pairs
+  // the columns within each block: kBlk - 1 steps of a round-robin per
+  // block, kBlk / 2 pairs of each block per step; then kBlk steps pair
+  // column i of the first block with column (i + step) mod kBlk of the
+  // second, so that a sweep meets every column pair exactly once
+  const int nintra = round == 0 ? kBlk - 1 : 0, nstep = nintra + kBlk;
+  for (int rr = 0; rr < inner * nstep; ++rr) {
+    const int r = rr % nstep;
+    int p, q;
+    if (r < nintra) {
+      const int blk = grp / (kBlk / 2), k = grp % (kBlk / 2);
+      const int ca = tour(k, r, kBlk), cb = tour(kBlk - 1 - k, r, kBlk);
+      p = blk * kBlk + min(ca, cb);
+      q = blk * kBlk + max(ca, cb);
+    } else {
+      p = grp;
+      q = kBlk + (grp + r - nintra) % kBlk;
+    }
     const bool live = gcol(p) < n && gcol(q) < n;
     if (live) {
       double up[RPL], uq[RPL];
