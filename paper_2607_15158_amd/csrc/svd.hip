@@ -196,25 +196,35 @@ __device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int rou
   double* Vc = Uc + (size_t)n * n;
   // local column j -> global column: j < kBlk from b0, else from b1
   auto gcol = [&](int j) { return (j < kBlk ? b0 : b1) * kBlk + (j % kBlk); };
-  // 8 independent loads in flight per thread (one workgroup per CU; 20
-  // measured the same)
-  constexpr int kLd = 8;
+  // the 2 kBlk columns of U (and of V) into LDS, one column per wave at a
+  // time, rows lane + 64 t: coalesced, with no index division; four columns
+  // per wave in flight
   const int nv = a.want_v ? 2 : 1;
-  for (int base = tid; base < nv * kC * n; base += 256 * kLd) {
-    double t[kLd];
+  const int wv = tid / 64, ln = tid % 64;
+  constexpr int kRW = (16 * RPL + 63) / 64;   // row chunks per lane (n <= 16 RPL)
+  const int ncol = nv * kC;
+  for (int c0 = wv; c0 < ncol; c0 += 16) {
+    double t[4][kRW];
 #pragma unroll
-    for (int u = 0; u < kLd; ++u) {
-      const int idx = base + u * 256;
-      const int h = idx / (kC * n), rem = idx % (kC * n);
-      const int g = gcol(rem / n);
-      t[u] = (idx < nv * kC * n && g < n) ? (h ? Vc : Uc)[(size_t)g * n + rem % n] : 0.0;
+    for (int u = 0; u < 4; ++u) {
+      const int cc = c0 + 4 * u, g = gcol(cc % kC);
+      const double* src = (cc < kC ? Uc : Vc) + (size_t)g * n;
+#pragma unroll
+      for (int r = 0; r < kRW; ++r) {
+        const int row = ln + 64 * r;
+        t[u][r] = (cc < ncol && g < n && row < n) ? src[row] : 0.0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < kLd; ++u) {
-      const int idx = base + u * 256;
-      if (idx < nv * kC * n) {
-        const int h = idx / (kC * n), rem = idx % (kC * n);
-        (h ? Vl : Ul)[rem / n][rem % n] = t[u];
+    for (int u = 0; u < 4; ++u) {
+      const int cc = c0 + 4 * u;
+      if (cc < ncol) {
+        double* dst = cc < kC ? Ul[cc] : Vl[cc - kC];
+#pragma unroll
+        for (int r = 0; r < kRW; ++r) {
+          const int row = ln + 64 * r;
+          if (row < n) dst[row] = t[u][r];
+        }
       }
     }
   }
@@ -295,10 +305,15 @@ __device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int rou
     __syncthreads();
   }
   if (li == 0 && my_rot) atomicAdd(&rot, my_rot);
-  for (int idx = tid; idx < kC * n; idx += 256) {
-    const int j = idx / n, rr = idx % n;
+  for (int j = wv; j < kC; j += 4) {
     const int g = gcol(j);
-    if (g < n) Uc[(size_t)g * n + rr] = Ul[j][rr];
+    if (g < n) {
+#pragma unroll
+      for (int r = 0; r < kRW; ++r) {
+        const int row = ln + 64 * r;
+        if (row < n) Uc[(size_t)g * n + row] = Ul[j][row];
+      }
+    }
   }
   if (a.want_v) {
     // V_cols <- V_cols W, register-blocked over the whole workgroup: thread
