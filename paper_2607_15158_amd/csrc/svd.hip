@@ -223,7 +223,10 @@ __device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int rou
 #pragma unroll
         for (int r = 0; r < kRW; ++r) {
           const int row = ln + 64 * r;
-          if (row < n) dst[row] = t[u][r];
+          if (row < n)
+            dst[row] = t[u][r];
+          else if (row < 16 * RPL)
+            dst[row] = 0.0;   // rows n .. 16 RPL - 1 hold exact zeros
         }
       }
     }
@@ -238,6 +241,21 @@ __device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int rou
   // not change the result above roundoff; they are completed at the end
   const double negl = 1e-30 * a.fro2[mat];
   int my_rot = 0;
+  // each step's rotation of W is applied at the start of the next step,
+  // beside that step's loads (every W column is still rotated in step
+  // order: a column belongs to one pair per step, and only that pair's
+  // group touches it until the next barrier)
+  int wpp = -1, wqq = 0;
+  double wc = 1.0, ws = 0.0;
+  auto rotate_w = [&]() {
+#pragma unroll
+    for (int tt = 0; tt < kC / kLanesPerPair; ++tt) {
+      const int row = li + kLanesPerPair * tt;
+      const double wp = Wl[row][wpp], wq = Wl[row][wqq];
+      Wl[row][wpp] = wc * wp - ws * wq;
+      Wl[row][wqq] = ws * wp + wc * wq;
+    }
+  };
   // the sweep's first round (every block in exactly one pair) also pairs
   // the columns within each block: kBlk - 1 steps of a round-robin per
   // block, kBlk / 2 pairs of each block per step; then kBlk steps pair
@@ -245,6 +263,10 @@ __device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int rou
   // second, so that a sweep meets every column pair exactly once
   const int nintra = round == 0 ? kBlk - 1 : 0, nstep = nintra + kBlk;
   for (int rr = 0; rr < inner * nstep; ++rr) {
+    if (wpp >= 0) {
+      rotate_w();
+      wpp = -1;
+    }
     const int r = rr % nstep;
     int p, q;
     if (r < nintra) {
@@ -262,9 +284,10 @@ __device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int rou
       double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
+        // rows n .. 16 RPL - 1 are zero: no guard
         const int row = li + kLanesPerPair * t;
-        up[t] = row < n ? Ul[p][row] : 0.0;
-        uq[t] = row < n ? Ul[q][row] : 0.0;
+        up[t] = Ul[p][row];
+        uq[t] = Ul[q][row];
         al += up[t] * up[t];
         be += uq[t] * uq[t];
         ga += up[t] * uq[t];
@@ -286,24 +309,21 @@ __device__ __forceinline__ void block_round(const SvdArgs& a, int sweep, int rou
 #pragma unroll
         for (int tt = 0; tt < RPL; ++tt) {
           const int row = li + kLanesPerPair * tt;
-          if (row < n) {
-            Ul[p][row] = c * up[tt] - s * uq[tt];
-            Ul[q][row] = s * up[tt] + c * uq[tt];
-          }
+          Ul[p][row] = c * up[tt] - s * uq[tt];
+          Ul[q][row] = s * up[tt] + c * uq[tt];
         }
-        if (a.want_v) {
-#pragma unroll
-          for (int tt = 0; tt < kC / kLanesPerPair; ++tt) {
-            const int row = li + kLanesPerPair * tt;
-            const double wp = Wl[row][p], wq = Wl[row][q];
-            Wl[row][p] = c * wp - s * wq;
-            Wl[row][q] = s * wp + c * wq;
-          }
+        if (a.want_v) {   // W's rotation waits for the next step
+          wpp = p;
+          wqq = q;
+          wc = c;
+          ws = s;
         }
       }
     }
     __syncthreads();
   }
+  if (wpp >= 0) rotate_w();
+  if (a.want_v) __syncthreads();   // W is complete before V_cols <- V_cols W
   if (li == 0 && my_rot) atomicAdd(&rot, my_rot);
   for (int j = wv; j < kC; j += 4) {
     const int g = gcol(j);
